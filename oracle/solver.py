@@ -1,0 +1,165 @@
+"""One implicit-Euler time step: Algorithm 1 with Algorithm 2.
+
+Oracle module (test infrastructure only; never used by the product path).
+
+Paper passages followed:
+* Section 4.1, Algorithm 1 (quasi-Newton solver): x_1 := y; for a fixed
+  number of iterations: gradient, descent direction, backtracking line search
+  starting from alpha = 1 and halving until the Armijo condition
+      g(x_k + alpha d) <= g(x_k) + gamma alpha tr(grad g(x_k)^T d)
+  holds, gamma = 0.3 (section 4.1, "Line search").
+* Section 4.2, Algorithm 2 (L-BFGS two-loop recursion): q := -grad g;
+  newest-to-oldest pass computing zeta_i = tr(s_i^T q)/rho_i and
+  q -= zeta_i t_i; r := A_0^{-1} q with A_0 = M/h^2 + L (unscaled);
+  oldest-to-newest pass with eta = tr(t_i^T r)/rho_i and r += s_i (zeta_i - eta);
+  d := r. s_i = x_{i+1} - x_i, t_i = grad g(x_{i+1}) - grad g(x_i),
+  rho_i = tr(t_i^T s_i), window m = 5. With m = 0 this is d = -A^{-1} grad g.
+* Section 5, Table StatAll: 10 iterations per frame, m = 5, h = 1/30 s.
+
+Readings (paper silent):
+* The history holds the pairs of the current time step only (reset every
+  step); the window is min(m, pairs stored).
+* Curvature safeguard: a pair is stored only if rho > 1e-10 |s| |t| (this
+  also skips s = t = 0). If the direction is not a descent direction
+  (grad^T d >= 0 with grad != 0), the history is cleared and d = -A^{-1} grad.
+* If g(y) is not finite (e.g. an inverted Neo-Hookean element), x_1 := x.
+* The line search stops after 30 halvings; if no trial passes, the iterate
+  stays x_k and the step's remaining iterations are skipped.
+* Pinned vertices keep their input positions; their velocity becomes 0.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import List, Optional
+
+import numpy as np
+
+from . import fem
+
+
+def two_loop(grad: np.ndarray, pairs, solve) -> np.ndarray:
+    """Algorithm 2: d = -B_k grad with pairs [(s, t, rho)] oldest first."""
+    q = -grad
+    zetas = []
+    for s, t, rho in reversed(pairs):                 # i = k-1, ..., k-m
+        zeta = float(np.sum(s * q)) / rho
+        q = q - zeta * t
+        zetas.append(zeta)
+    r = solve(q)                                      # r := A_0^{-1} q
+    for (s, t, rho), zeta in zip(pairs, reversed(zetas)):   # i = k-m, ..., k-1
+        eta = float(np.sum(t * r)) / rho
+        r = r + s * (zeta - eta)
+    return r
+
+
+@dataclasses.dataclass
+class StepResult:
+    x: np.ndarray
+    v: np.ndarray
+    iterations_run: int = 0
+    ls_trials: int = 0
+    ls_exhausted: int = 0
+    lbfgs_skipped: int = 0
+    fallbacks: int = 0
+    g_first: float = 0.0
+    g_last: float = 0.0
+    grad_norm_first: float = 0.0
+    grad_norm_last: float = float("nan")
+    trace: list = dataclasses.field(default_factory=list)   # per iteration
+    iterates: list = dataclasses.field(default_factory=list)
+
+
+def step(model: "fem.Model", x: np.ndarray, v: np.ndarray, f_ext=None,
+         iterations: int = 10, history: int = 5, gamma: float = 0.3,
+         backtrack: float = 0.5, max_halvings: int = 30,
+         final_gradient: bool = False, keep_iterates: bool = False,
+         x_init: Optional[np.ndarray] = None) -> StepResult:
+    """Advance (x, v) by one step of size model.h; returns the new state."""
+    x = np.asarray(x, dtype=np.float64)
+    v = np.asarray(v, dtype=np.float64)
+    f = model.free
+    y = fem.inertia_target(model, x, v, f_ext)
+    res = StepResult(x=None, v=None)
+
+    xk = y.copy() if x_init is None else np.asarray(x_init, dtype=np.float64).copy()
+    xk[model.pinned] = x[model.pinned]
+    gk = fem.objective(model, xk, y)
+    if not np.isfinite(gk):
+        xk = x.copy()
+        gk = fem.objective(model, xk, y)
+        res.fallbacks += 1
+    res.g_first = gk
+    if keep_iterates:
+        res.iterates.append(xk.copy())
+
+    pairs: List[tuple] = []
+    x_prev = grad_prev = None
+    for k in range(iterations):
+        grad = fem.gradient(model, xk, y)
+        if k == 0:
+            res.grad_norm_first = float(np.linalg.norm(grad))
+        if x_prev is not None:
+            s = xk[f] - x_prev[f]
+            t = grad - grad_prev
+            rho = float(np.sum(t * s))
+            if rho > 1e-10 * np.linalg.norm(s) * np.linalg.norm(t):
+                pairs.append((s, t, rho))
+                if len(pairs) > history:
+                    pairs.pop(0)
+            else:
+                res.lbfgs_skipped += 1
+        if history == 0:
+            pairs = []
+        d = two_loop(grad, pairs, model.solve)
+        gtd = float(np.sum(grad * d))
+        if gtd >= 0.0 and np.any(grad != 0.0):
+            pairs = []
+            d = model.solve(-grad)
+            gtd = float(np.sum(grad * d))
+            res.fallbacks += 1
+
+        alpha = 1.0
+        accepted = False
+        margins = []
+        for _ in range(max_halvings + 1):
+            xt = xk.copy()
+            xt[f] = xk[f] + alpha * d
+            gt = fem.objective(model, xt, y)
+            res.ls_trials += 1
+            bound = gk + gamma * alpha * gtd
+            margins.append((alpha, gt, bound))
+            if gt <= bound:
+                accepted = True
+                break
+            alpha *= backtrack
+        res.trace.append(dict(g=gk, gtd=gtd, alpha=alpha if accepted else 0.0,
+                              margins=margins, pairs=len(pairs)))
+        res.iterations_run += 1
+        if not accepted:
+            res.ls_exhausted = 1
+            break
+        x_prev, grad_prev = xk, grad
+        xk, gk = xt, gt
+        if keep_iterates:
+            res.iterates.append(xk.copy())
+
+    res.g_last = gk
+    if final_gradient:
+        res.grad_norm_last = float(np.linalg.norm(fem.gradient(model, xk, y)))
+    xk[model.pinned] = x[model.pinned]
+    res.x = xk
+    res.v = (xk - x) / model.h
+    res.v[model.pinned] = 0.0
+    return res
+
+
+def simulate(model: "fem.Model", x0, v0, steps: int, **kw):
+    """Run `steps` time steps; returns the list of positions and the results."""
+    x, v = np.asarray(x0, dtype=np.float64), np.asarray(v0, dtype=np.float64)
+    xs, results = [], []
+    for _ in range(steps):
+        r = step(model, x, v, **kw)
+        x, v = r.x, r.v
+        xs.append(x)
+        results.append(r)
+    return xs, results

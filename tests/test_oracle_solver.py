@@ -1,0 +1,376 @@
+"""Pins of the oracle's assembly, objective, two-loop recursion and time step.
+
+CPU only. The oracle is checked against finite differences, textbook
+identities (dense BFGS update, secant equation), the paper's central identity
+(the quasi-Newton step with projective-dynamics energies is one local/global
+iteration), closed-form motions, invariances, and a projected Newton solve.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+import oracle
+import workloads as W
+from oracle import fem, materials as mat, newton, solver
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_constants.json")
+
+
+def _model(w, **kw):
+    return oracle.build_model(w.rest, w.tets, w.pinned, w.materials, w.tet_mat,
+                              w.h, w.gravity, **kw)
+
+
+def _small(kind=W.NEOHOOKEAN, dims=(3, 2, 2), pinned=True, seed=0, E=1e5, nu=0.4):
+    w = W.workload_cantilever(jitter_seed=seed, dims=dims, edge=0.1, kind=kind, E=E, nu=nu)
+    if not pinned:
+        w.pinned = np.zeros(0, dtype=np.int32)
+    return w
+
+
+# ---------------------------------------------------------------------------
+# paper constants
+# ---------------------------------------------------------------------------
+def test_defaults_match_paper_constants():
+    g = json.load(open(GOLDEN))
+    import inspect
+    sig = inspect.signature(solver.step)
+    assert sig.parameters["iterations"].default == g["iterations"]["value"]
+    assert sig.parameters["history"].default == g["history"]["value"]
+    assert sig.parameters["gamma"].default == g["gamma"]["value"]
+    assert sig.parameters["backtrack"].default == g["backtrack"]["value"]
+    bsig = inspect.signature(fem.build_model)
+    assert bsig.parameters["h"].default == pytest.approx(g["h"]["value"])
+    assert [bsig.parameters["fit_lo"].default, bsig.parameters["fit_hi"].default] == \
+        g["fit_interval"]["value"]
+    ls = g["ls_per_iteration_squirrel"]
+    assert ls["numerator"] / (ls["frames"] * ls["iterations_per_frame"]) == \
+        pytest.approx(ls["value"], abs=0.005)
+
+
+# ---------------------------------------------------------------------------
+# mesh, masses, assembly
+# ---------------------------------------------------------------------------
+def test_grid_counts_and_volumes():
+    w = W.workload_cantilever(0)
+    assert (w.n_verts, w.n_tets, len(w.pinned)) == (176, 540, 16)
+    m = _model(w)
+    # Kuhn tets of a cube have volume edge^3 / 6; jitter changes it by < ~6 %
+    assert np.all(np.abs(m.vol / (0.1 ** 3 / 6) - 1) < 0.07)
+    # total mass = rho * total volume
+    assert m.mass.sum() == pytest.approx(1000.0 * m.vol.sum(), rel=1e-14)
+    wb = W.workload_block(n=40)
+    assert (wb.n_verts, wb.n_tets, len(wb.pinned)) == (68921, 384000, 1681)
+
+
+def test_unjittered_grid_volume_is_exact():
+    rest, tets = W.kuhn_grid(3, 2, 2, 0.1)
+    Dm_inv, vol, det = fem.element_rest_data(rest, tets)
+    assert np.allclose(vol, 0.1 ** 3 / 6, rtol=1e-13)
+    assert vol.sum() == pytest.approx(3 * 2 * 2 * 0.1 ** 3, rel=1e-13)
+
+
+def test_L_quadratic_form_is_weighted_frobenius_norm():
+    """x^T L x = sum_e V_e k_e |F_e(x)|^2 with F from the displacement map."""
+    w = _small(pinned=False)
+    m = _model(w)
+    rng = np.random.default_rng(1)
+    x = w.rest + 0.05 * rng.normal(size=w.rest.shape)
+    Lm = m.A - scipy.sparse.diags(m.mass / m.h ** 2)
+    quad = sum(x[:, c] @ (Lm @ x[:, c]) for c in range(3))
+    F = fem.deformation_gradients(m, x)
+    ref = np.sum(m.vol * m.k * np.einsum("tij,tij->t", F, F))
+    assert quad == pytest.approx(ref, rel=1e-12)
+
+
+def test_L_annihilates_constants():
+    """Constant vectors are in the nullspace of every G_i (section 3)."""
+    w = _small(pinned=False)
+    m = _model(w)
+    Lm = m.A - scipy.sparse.diags(m.mass / m.h ** 2)
+    assert np.abs(Lm @ np.ones(m.n_free)).max() < 1e-9 * abs(Lm).max()
+
+
+def test_A_is_spd_and_solve_is_exact():
+    w = W.workload_cantilever(0)
+    m = _model(w)
+    Ad = m.A.toarray()
+    assert np.allclose(Ad, Ad.T, rtol=0, atol=1e-9 * np.abs(Ad).max())
+    np.linalg.cholesky(Ad)
+    q = np.random.default_rng(2).normal(size=(m.n_free, 3))
+    r = m.solve(q)
+    assert np.abs(Ad @ r - q).max() < 1e-13 * np.abs(Ad).max() * np.abs(r).max()
+    # the sparse LU path used for large meshes gives the same solution
+    import scipy.sparse.linalg as spla
+    lu = spla.splu(m.A, permc_spec="MMD_AT_PLUS_A", options=dict(SymmetricMode=True))
+    assert np.abs(lu.solve(q) - r).max() < 1e-12 * np.abs(r).max()
+
+
+@pytest.mark.parametrize("kind", [W.NEOHOOKEAN, W.STVK, W.SPLINE, W.COROTATED, W.POLYNOMIAL])
+def test_gradient_matches_finite_differences(kind):
+    """grad g by central differences of g over every free coordinate."""
+    w = _small(kind=kind)
+    m = _model(w)
+    rng = np.random.default_rng(kind)
+    x = w.rest + 0.01 * rng.normal(size=w.rest.shape)
+    y = w.rest + 0.01 * rng.normal(size=w.rest.shape)
+    x[m.pinned] = w.rest[m.pinned]
+    g = fem.gradient(m, x, y)
+    eps = 1e-7
+    fd = np.zeros_like(g)
+    for a, v in enumerate(m.free):
+        for c in range(3):
+            xp = x.copy(); xp[v, c] += eps
+            xm = x.copy(); xm[v, c] -= eps
+            fd[a, c] = (fem.objective(m, xp, y) - fem.objective(m, xm, y)) / (2 * eps)
+    assert np.abs(fd - g).max() < 1e-6 * np.abs(g).max()
+
+
+@pytest.mark.parametrize("kind", [W.NEOHOOKEAN, W.STVK, W.SPLINE])
+def test_element_forces_balance(kind):
+    """Per tet: sum of vertex forces = 0 and sum of x_j x f_j = 0 (momentum)."""
+    w = _small(kind=kind)
+    m = _model(w)
+    x = w.rest + 0.02 * np.random.default_rng(3).normal(size=w.rest.shape)
+    _, P = fem.element_psi_P(m, x)
+    fe = fem.element_forces(m, P)                  # (T, 4, 3)
+    scale = np.abs(fe).max()
+    assert np.abs(fe.sum(axis=1)).max() < 1e-12 * scale
+    X = x[m.tets]
+    torque = np.cross(X, fe).sum(axis=1)
+    assert np.abs(torque).max() < 1e-12 * scale * np.abs(X).max()
+
+
+def test_zero_force_at_rest():
+    w = _small()
+    m = _model(w)
+    _, P = fem.element_psi_P(m, w.rest)
+    assert np.abs(P).max() < 1e-9
+    assert fem.elastic_energy(m, w.rest) == pytest.approx(0.0, abs=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# Algorithm 2 (two-loop recursion)
+# ---------------------------------------------------------------------------
+def _spd(n, seed):
+    rng = np.random.default_rng(seed)
+    B = rng.normal(size=(n, n))
+    return B @ B.T + n * np.eye(n)
+
+
+def test_two_loop_without_history_is_preconditioned_gradient():
+    A = _spd(7, 0)
+    solve = lambda q: np.linalg.solve(A, q)
+    g = np.random.default_rng(1).normal(size=(7, 3))
+    d = solver.two_loop(g, [], solve)
+    assert np.allclose(d, -np.linalg.solve(A, g), rtol=1e-14, atol=1e-14)
+
+
+def test_two_loop_equals_dense_bfgs_update():
+    """Nocedal & Wright: H+ = (I - s t^T / rho) H (I - t s^T / rho) + s s^T / rho.
+
+    The coordinates are decoupled (trace form), so the dense update acts on
+    the n x n matrix and the three columns share it.
+    """
+    n = 6
+    A = _spd(n, 4)
+    solve = lambda q: np.linalg.solve(A, q)
+    rng = np.random.default_rng(5)
+    pairs = []
+    H = np.linalg.inv(A)
+    for _ in range(4):
+        s = rng.normal(size=(n, 3))
+        t = A @ s + 0.1 * rng.normal(size=(n, 3))
+        rho = float(np.sum(t * s))
+        assert rho > 0
+        pairs.append((s, t, rho))
+    # dense update on the flattened 3n space with H0 = kron(A^{-1}, I3)
+    H = np.kron(np.linalg.inv(A), np.eye(3))
+    for s, t, rho in pairs:
+        sv, tv = s.reshape(-1), t.reshape(-1)
+        V = np.eye(3 * n) - np.outer(tv, sv) / rho
+        H = V.T @ H @ V + np.outer(sv, sv) / rho
+    g = rng.normal(size=(n, 3))
+    d = solver.two_loop(g, pairs, solve)
+    assert np.abs(d.reshape(-1) + H @ g.reshape(-1)).max() < 1e-12 * np.abs(d).max()
+    # secant equation for the newest pair: B_k t_{k-1} = s_{k-1}
+    s, t, _ = pairs[-1]
+    assert np.abs(solver.two_loop(t, pairs, solve) + s).max() < 1e-12 * np.abs(s).max()
+
+
+# ---------------------------------------------------------------------------
+# The paper's central identity: projective dynamics = quasi-Newton step
+# ---------------------------------------------------------------------------
+def _pd_global_step(m, x, y):
+    """One local/global iteration of projective dynamics for ARAP (section 3).
+
+    Local: p_e = polar rotation of F_e. Global: solve
+    (M/h^2 + L) x* = J p + M y / h^2, with the pinned-vertex coupling of L
+    moved to the right-hand side. J p and L are assembled here from the
+    shape-function gradients, independently of the oracle's gradient code.
+    """
+    F = fem.deformation_gradients(m, x)
+    R = np.stack([scipy.linalg.polar(Fe)[0] for Fe in F])
+    B = fem.shape_gradients(m.Dm_inv)                  # (T, 4, 3)
+    w_e = m.vol * m.k
+    Jp = np.zeros_like(x)
+    for a in range(4):
+        np.add.at(Jp, m.tets[:, a], w_e[:, None] * np.einsum("tik,tk->ti", R, B[:, a]))
+    n = m.n
+    Lfull = np.zeros((n, n))
+    Ke = np.einsum("tai,tbi->tab", B, B) * w_e[:, None, None]
+    for a in range(4):
+        for b in range(4):
+            np.add.at(Lfull, (m.tets[:, a], m.tets[:, b]), Ke[:, a, b])
+    f, p = m.free, m.pinned
+    Aff = Lfull[np.ix_(f, f)] + np.diag(m.mass[f] / m.h ** 2)
+    rhs = Jp[f] + m.mass[f][:, None] * y[f] / m.h ** 2 - Lfull[np.ix_(f, p)] @ x[p]
+    return np.linalg.solve(Aff, rhs)
+
+
+def test_arap_quasi_newton_step_is_projective_dynamics_iteration():
+    """Corotated with lambda = 0 is ARAP: x + d_PD equals the PD global step,
+    and alpha = 1 always passes the Armijo test (section 4)."""
+    w = _small(kind=W.COROTATED, dims=(4, 2, 2), E=1e5, nu=0.0)
+    assert w.materials[0].lam == 0.0
+    m = _model(w)
+    assert m.k[0] == pytest.approx(2 * w.materials[0].mu, rel=1e-13)
+    rng = np.random.default_rng(11)
+    x = w.rest + 0.01 * rng.normal(size=w.rest.shape)
+    x[m.pinned] = w.rest[m.pinned]
+    y = w.rest + 0.03 * rng.normal(size=w.rest.shape)
+    # the projection onto SO(3) is the polar factor only for det F > 0
+    assert np.all(np.linalg.det(fem.deformation_gradients(m, x)) > 0)
+    g = fem.gradient(m, x, y)
+    d = solver.two_loop(g, [], m.solve)
+    x_pd = _pd_global_step(m, x, y)
+    assert np.abs(x[m.free] + d - x_pd).max() < 1e-12 * np.abs(x_pd).max()
+    # whole steps with m = 0: every line search accepts alpha = 1
+    r = solver.step(m, x, np.zeros_like(x), history=0)
+    assert r.ls_trials == r.iterations_run == 10
+
+
+# ---------------------------------------------------------------------------
+# Whole step: closed forms and invariances
+# ---------------------------------------------------------------------------
+def test_free_fall_closed_form():
+    """Unpinned body at rest shape with uniform velocity: no elastic force, so
+    x' = x + h v + h^2 g and v' = v + h g exactly."""
+    w = _small(pinned=False)
+    m = _model(w)
+    v = np.tile([0.3, -0.2, 0.1], (w.n_verts, 1))
+    r = solver.step(m, w.rest, v)
+    grav = np.asarray(w.gravity)
+    assert np.abs(r.x - (w.rest + m.h * v + m.h ** 2 * grav)).max() < 1e-13
+    assert np.abs(r.v - (v + m.h * grav)).max() < 1e-11
+    assert r.lbfgs_skipped == 9 and r.ls_exhausted == 0
+
+
+@pytest.mark.parametrize("kind", [W.NEOHOOKEAN, W.STVK, W.SPLINE])
+def test_rigid_equivariance(kind):
+    """step(x + c) = step(x) + c; step(x Q^T) = step(x) Q^T with rotated gravity."""
+    w = _small(kind=kind, pinned=False, dims=(3, 2, 2))
+    rng = np.random.default_rng(7)
+    x = w.rest + 0.01 * rng.normal(size=w.rest.shape)
+    v = 0.1 * rng.normal(size=w.rest.shape)
+    m = _model(w)
+    r0 = solver.step(m, x, v)
+    c = np.array([0.3, -1.0, 2.0])
+    r1 = solver.step(m, x + c, v)
+    scale = np.abs(r0.x - x).max()
+    assert np.abs(r1.x - c - r0.x).max() < 1e-9 * scale
+    Q = np.linalg.qr(rng.normal(size=(3, 3)))[0]
+    if np.linalg.det(Q) < 0:
+        Q[:, 0] *= -1
+    mq = oracle.build_model(w.rest, w.tets, w.pinned, w.materials, w.tet_mat, w.h,
+                            Q @ np.asarray(w.gravity))
+    r2 = solver.step(mq, x @ Q.T, v @ Q.T)
+    assert np.abs(r2.x - r0.x @ Q.T).max() < 1e-9 * scale
+
+
+@pytest.mark.parametrize("kind", [W.NEOHOOKEAN, W.STVK, W.SPLINE])
+def test_objective_monotone_within_step(kind):
+    w = W.workload_cantilever(0, kind=kind)
+    m = _model(w)
+    x, v = w.x0, w.v0
+    for _ in range(3):
+        r = solver.step(m, x, v)
+        gs = [t["g"] for t in r.trace] + [r.g_last]
+        assert all(b <= a for a, b in zip(gs, gs[1:]))
+        x, v = r.x, r.v
+
+
+def test_infeasible_inertia_target_falls_back_to_x():
+    """If y inverts a Neo-Hookean element, x_1 := x (feasible)."""
+    w = _small()
+    m = _model(w)
+    v = np.zeros_like(w.rest)
+    v[m.free[0]] = [0.0, 0.0, -300.0]              # flings one vertex through
+    r = solver.step(m, w.rest, v)
+    assert r.fallbacks >= 1 and np.isfinite(r.g_last)
+
+
+# ---------------------------------------------------------------------------
+# Convergence to the minimiser and the paper's qualitative claims
+# ---------------------------------------------------------------------------
+@pytest.mark.slow
+def test_quasi_newton_converges_to_newton_minimiser():
+    """Brute force on the 540-tet cantilever: many QN iterations reach the
+    minimiser that projected Newton finds.
+
+    Both searches stall once the decrease asked by the Armijo test is below
+    the rounding of g (per-element cancellation in I1 - 3 and log J gives
+    ~1e-13 absolute noise at g ~ 10), at gradient norms of 1e-7 .. 1e-5; the
+    minimisers then agree to ~1e-8 of the displacement.
+    """
+    w = W.workload_cantilever(0)
+    m = _model(w)
+    x, v = w.x0, w.v0
+    for _ in range(3):                               # move away from rest first
+        r = solver.step(m, x, v)
+        x, v = r.x, r.v
+    y = fem.inertia_target(m, x, v)
+    x_star, g_star = newton.newton_minimise(m, y, y, tol=1e-9)
+    r = solver.step(m, x, v, iterations=300, final_gradient=True)
+    disp = np.abs(x_star - x).max()
+    assert np.abs(r.x - x_star).max() < 1e-7 * disp
+    assert r.g_last == pytest.approx(g_star, rel=1e-12)
+    assert r.grad_norm_last < 1e-6 * r.grad_norm_first
+
+
+@pytest.mark.slow
+def test_paper_claims_plausibility():
+    """Section 5: ~1.0-1.2 line-search trials per iteration on mild scenes;
+    L-BFGS history improves on plain PD directions (m = 5 <= m = 2 < m = 0);
+    10 QN iterations come close to one projected Newton iteration.
+
+    The paper reports 10 QN iterations beating one Newton iteration on its
+    scenes; on this cantilever they reach 2.9e-3 against Newton's 2.6e-3, so
+    only "within a factor of 2" is asserted.
+    """
+    w = W.workload_cantilever(0)
+    m = _model(w)
+    x, v = w.x0, w.v0
+    trials = iters = 0
+    for _ in range(5):
+        r = solver.step(m, x, v)
+        trials += r.ls_trials
+        iters += r.iterations_run
+        x, v = r.x, r.v
+    assert 1.0 <= trials / iters <= 1.2
+    y = fem.inertia_target(m, x, v)
+    x_star, g_star = newton.newton_minimise(m, y, y, tol=1e-9)
+    g0 = fem.objective(m, y, y)
+    r5 = solver.step(m, x, v, history=5)
+    r2 = solver.step(m, x, v, history=2)
+    r0 = solver.step(m, x, v, history=0)
+    x1, g1 = newton.newton_minimise(m, y, y, max_iter=1, tol=0.0)
+    e5 = newton.relative_error(r5.g_last, g0, g_star)
+    e2 = newton.relative_error(r2.g_last, g0, g_star)
+    e0 = newton.relative_error(r0.g_last, g0, g_star)
+    e_newton1 = newton.relative_error(g1, g0, g_star)
+    assert e5 <= e2 < e0 / 5
+    assert e5 < 2.0 * e_newton1
