@@ -1,0 +1,218 @@
+#!/usr/bin/env python3
+"""Throughput of the quasi-Newton / L-BFGS implicit-Euler step on one MI355X.
+
+Workload: a 40 x 40 x 40 grid of 0.025 m cubes split into 384,000 tets
+(68,921 vertices), bottom face pinned, released under gravity from a seeded
+10 % random affine pre-stretch; three runs with Neo-Hookean, St. Venant-
+Kirchhoff and spline materials (E = 1e5 Pa, nu = 0.4, rho = 1000 kg/m^3);
+h = 1/30 s, 10 quasi-Newton iterations per step, L-BFGS window m = 5,
+backtracking Armijo line search; all arithmetic in FP64.
+
+A "step" is one full implicit-Euler step of the hot path (element passes,
+gradient gather, two-loop recursion, prefactored solves, line search) with
+the state resident in HBM. `value` is steps per second over the three
+material runs (3 * steps / total time). Also reported: tet evaluations per
+second, per-kernel HIP-event timings against the HBM roofline, and the FP64
+NumPy oracle timed on the host on a bounded sample of the same workload.
+
+Prints one JSON line. Runs on one GPU only.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "timesteps/s and tet-evals/s at fixed L-BFGS residual; served p50/p99 step latency"
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def element_bytes(T, n, nf):
+    """Algorithmic HBM bytes of one FP64 line-search element pass.
+
+    Per tet: 4 int32 vertex ids (16 B), Dm^{-1} (72 B), rest volume (8 B);
+    per vertex once: x (24 B); per free vertex once: d (24 B), y (24 B) and
+    the lumped mass (8 B) for the inertia term.
+    """
+    return T * (16 + 72 + 8) + n * 24 + nf * (24 + 24 + 8)
+
+
+def solve_bytes(nnz_exact, nf):
+    """Algorithmic HBM bytes of one prefactored solve (3 right-hand sides):
+    the factor values read by the forward and by the backward sweep, plus the
+    right-hand side read and the solution written (intermediate vectors are
+    not algorithmic)."""
+    return 2 * 8 * nnz_exact + 2 * 24 * nf
+
+
+def run_material(kind, args, torch, W, qnsim):
+    w = W.workload_block(kind, n=args.n)
+    t0 = time.time()
+    sim = qnsim.sim_from_workload(w)
+    prep = time.time() - t0
+    info = sim.factor_info()
+    log(f"[bench] {w.name}: prepared in {prep:.2f}s, nnz(L)={info['nnz_L_exact']}, "
+        f"levels={info['n_levels']}")
+    x = torch.from_numpy(w.x0.copy()).cuda()
+    v = torch.from_numpy(w.v0.copy()).cuda()
+    if args.warmup:
+        sim.run_device(x, v, w.h, args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = sim.run_device(x, v, w.h, args.steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    log(f"[bench] {w.name}: {args.steps} steps in {dt:.3f}s ({args.steps / dt:.1f} steps/s), "
+        f"trials {st['ls_trials']}, iterations {st['iterations_run']}")
+    res = dict(material=W.MATERIAL_NAMES[kind], steps=args.steps, seconds=dt,
+               steps_per_s=args.steps / dt, ls_trials=st["ls_trials"],
+               iterations=st["iterations_run"], exhausted=st["ls_exhausted"],
+               element_passes=st["ls_trials"] + args.steps, T=w.n_tets, n=w.n_verts,
+               nf=info["n_free"], nnz_L=info["nnz_L_exact"], levels=info["n_levels"],
+               prepare_s=prep)
+    # per-kernel timings (HIP events on the library's stream)
+    reps = 20
+    el_ms = sim.time_kernel(qnsim.KERNEL_ELEMENT, reps)
+    ga_ms = sim.time_kernel(qnsim.KERNEL_GATHER, reps)
+    so_ms = sim.time_kernel(qnsim.KERNEL_SOLVE, reps)
+    res["kernel_ms"] = dict(element=el_ms, gather=ga_ms, solve=so_ms)
+    res["element_bytes"] = element_bytes(w.n_tets, w.n_verts, info["n_free"])
+    res["solve_bytes"] = solve_bytes(info["nnz_L_exact"], info["n_free"])
+    sim.close()
+    return res
+
+
+def cpu_baseline(args, W):
+    """The FP64 oracle on a bounded sample: one step of the Neo-Hookean block."""
+    import numpy as np  # noqa: F401
+    import oracle
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    w = W.workload_block(W.NEOHOOKEAN, n=args.n)
+    t0 = time.time()
+    m = oracle.build_model(w.rest, w.tets, w.pinned, w.materials, w.tet_mat, w.h, w.gravity)
+    build = time.time() - t0
+    t0 = time.perf_counter()
+    steps = args.cpu_sample_steps
+    x, v = w.x0, w.v0
+    for _ in range(steps):
+        r = oracle.step(m, x, v)
+        x, v = r.x, r.v
+    dt = time.perf_counter() - t0
+    log(f"[bench] oracle: build {build:.1f}s, {steps} step(s) in {dt:.1f}s")
+    return {"value": steps / dt, "unit": "timesteps/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"{steps} step(s) of the Neo-Hookean 40^3 block (384,000 tets) after an "
+                      f"untimed {build:.1f}s model build and banded Cholesky factorisation"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=40, help="cubes per axis of the block")
+    ap.add_argument("--materials", default="neohookean,stvk,spline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-steps", type=int, default=1)
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(independent simulations would be sharded by simulation, one process per GPU); "
+              "run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import workloads as W
+    from paper_1604_07378_amd import qnsim
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    names = {v: k for k, v in W.MATERIAL_NAMES.items()}
+    kinds = [names[s] for s in args.materials.split(",")]
+    runs = [run_material(k, args, torch, W, qnsim) for k in kinds]
+
+    total_steps = sum(r["steps"] for r in runs)
+    total_s = sum(r["seconds"] for r in runs)
+    tet_evals = sum(r["T"] * r["element_passes"] for r in runs)
+    value = total_steps / total_s
+
+    # dominant kernel: largest share of step time among the timed kernels
+    nh = runs[0]
+    per_step = {
+        "element": nh["kernel_ms"]["element"] * nh["element_passes"] / nh["steps"],
+        "gather": nh["kernel_ms"]["gather"] * nh["iterations"] / nh["steps"],
+        "solve": nh["kernel_ms"]["solve"] * nh["iterations"] / nh["steps"],
+    }
+    dom = max(per_step, key=per_step.get)
+    if dom == "solve":
+        bytes_, ms = nh["solve_bytes"], nh["kernel_ms"]["solve"]
+    else:
+        bytes_, ms = nh["element_bytes"], nh["kernel_ms"]["element"]
+        dom = "element"
+    achieved = bytes_ / (ms * 1e-3) / 1e9
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "timesteps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * total_s / total_steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"block {args.n}^3 cubes x 6 tets ({nh['T']} tets, {nh['n']} verts), "
+                        f"materials {args.materials}, FP64, h=1/30 s, 10 iterations, m=5",
+            "tets": nh["T"], "verts": nh["n"], "free_verts": nh["nf"],
+            "materials": args.materials.split(","),
+        },
+        "tet_evals_per_s": tet_evals / total_s,
+        "runs": [{k: r[k] for k in ("material", "steps_per_s", "ls_trials", "iterations",
+                                    "exhausted", "kernel_ms", "nnz_L", "levels", "prepare_s")}
+                 for r in runs],
+        "step_time_share_ms": per_step,
+        "roofline": {
+            "bound": "hbm",
+            "kernel": dom,
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+            "algorithmic_bytes_per_launch": bytes_,
+            "avg_launch_ms": ms,
+        },
+        "kernels": {
+            "element": {"ms": nh["kernel_ms"]["element"], "bytes": nh["element_bytes"],
+                        "GBs": nh["element_bytes"] / (nh["kernel_ms"]["element"] * 1e-3) / 1e9},
+            "solve": {"ms": nh["kernel_ms"]["solve"], "bytes": nh["solve_bytes"],
+                      "GBs": nh["solve_bytes"] / (nh["kernel_ms"]["solve"] * 1e-3) / 1e9},
+            "gather_ms": nh["kernel_ms"]["gather"],
+        },
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args, W)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

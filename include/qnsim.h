@@ -1,0 +1,251 @@
+/*
+ * qnsim.h -- C ABI of the MI355X (gfx950) quasi-Newton hyperelastic step.
+ *
+ * The library advances a tetrahedral mesh by implicit-Euler time steps. Each
+ * step minimises
+ *     g(x) = 1/(2 h^2) tr((x - y)^T M (x - y)) + E(x)                 (Eq. PD)
+ * with y = x_n + h v_n + h^2 M^{-1} f_ext (section 3), by a fixed number of
+ * quasi-Newton iterations (section 4.1, Algorithm 1): a descent direction from
+ * the L-BFGS two-loop recursion (section 4.2, Algorithm 2) whose initial
+ * Hessian is the constant, prefactored matrix A = M/h^2 + L with
+ * L = sum_e V_e k_e G_e^T G_e (section 3, Eqs. PDmatrixForm / PDsolution;
+ * section 4.1 for k_e), and a backtracking Armijo line search (section 4.1,
+ * "Line search"). Every step of the hot path runs in HIP kernels; the host
+ * only orders, factors and uploads A once per mesh (qnsim_prepare).
+ *
+ * Conventions (all entry points):
+ *  - Every function returns an int status: QNSIM_OK (0) or a negative
+ *    QNSIM_E_* code. No C++ exception crosses the ABI.
+ *  - On error, output buffers are left untouched and the context stays usable;
+ *    qnsim_last_error() returns a message describing the last failure.
+ *  - All pointers are owned by the caller. The library copies what it needs
+ *    and keeps no caller pointer after a call returns.
+ *  - Positions, velocities and forces are row-major n x 3 arrays of doubles in
+ *    the caller's vertex numbering; tetrahedra are row-major T x 4 int32
+ *    vertex indices (any orientation).
+ *  - Host entry points (qnsim_step) synchronise before returning. Device entry
+ *    points (qnsim_step_device) take device pointers and a hipStream_t passed
+ *    as void*, are stream-ordered and do not synchronise except where stated.
+ *  - Calls on one context must not overlap (a context is not thread-safe);
+ *    distinct contexts are independent.
+ */
+#ifndef QNSIM_H
+#define QNSIM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------- */
+#define QNSIM_OK 0
+#define QNSIM_E_INVALID -1     /* null pointer, size or index out of range     */
+#define QNSIM_E_NONFINITE -2   /* NaN or Inf in an input array                  */
+#define QNSIM_E_DEGENERATE -3  /* rest tetrahedron with (near) zero volume      */
+#define QNSIM_E_INVERTED -4    /* Neo-Hookean element with J <= 0 at input x    */
+#define QNSIM_E_STIFFNESS -5   /* stiffness fit k <= 0 for a material           */
+#define QNSIM_E_NOT_SPD -6     /* Cholesky factorisation of A failed            */
+#define QNSIM_E_H_MISMATCH -7  /* step h differs from the h A was factored for  */
+#define QNSIM_E_STATE -8       /* call out of order (e.g. step before prepare)  */
+#define QNSIM_E_NOMEM -9       /* host or device allocation failed              */
+#define QNSIM_E_DEVICE -10     /* HIP runtime error                             */
+
+/* ---- material types (section 4.1, Valanis-Landel materials; section 5) --- */
+#define QNSIM_NEOHOOKEAN 0  /* mu/2 (I1-3) - mu log J + lam/2 (log J)^2          */
+#define QNSIM_STVK 1        /* mu tr(E^2) + lam/2 tr(E)^2, E = (F^T F - I)/2     */
+#define QNSIM_SPLINE 2      /* sum a(s_i) + lam/2 (J-1)^2, a'' piecewise linear  */
+#define QNSIM_COROTATED 3   /* mu |F-R|^2 + lam/2 tr(R^T F - I)^2                */
+#define QNSIM_POLYNOMIAL 4  /* sum mu (s_i - 1)^4                                */
+
+/* ---- precision modes ---------------------------------------------------- */
+#define QNSIM_FP64 0   /* every kernel in FP64                                   */
+#define QNSIM_MIXED 1  /* FP32 element energies/stresses; FP64 solves, dot
+                          products, curvature pairs and line-search sums         */
+
+typedef struct qnsim qnsim_t; /* opaque; owns all its host and device memory */
+
+/* Solver options. qnsim_options_default() fills the paper's settings:
+ * 10 iterations per step and L-BFGS window m = 5 (section 5, Table StatAll),
+ * Armijo gamma = 0.3 and backtracking factor 0.5 (section 4.1), stiffness fit
+ * interval [0.5, 1.5] (section 5), at most 30 halvings per line search,
+ * gravity (0, 0, -9.81) m/s^2, FP64, device 0. */
+typedef struct {
+  int32_t iterations;   /* quasi-Newton iterations per step (>= 1)           */
+  int32_t history;      /* L-BFGS window m (0..16); 0 = plain PD direction   */
+  int32_t max_halvings; /* line-search trials per iteration = max_halvings+1 */
+  int32_t precision;    /* QNSIM_FP64 or QNSIM_MIXED                         */
+  int32_t device;       /* HIP device ordinal                                */
+  int32_t reserved;
+  double gamma;         /* Armijo constant in (0, 1)                         */
+  double backtrack;     /* step-length factor after a failed trial, (0, 1)   */
+  double fit_lo;        /* stiffness fit interval [fit_lo, fit_hi]           */
+  double fit_hi;
+  double gravity[3];    /* uniform body acceleration added to f_ext / m      */
+} qnsim_options;
+
+/* One material. mu, lambda in Pa; density in kg/m^3. For QNSIM_SPLINE,
+ * spline_d2[j] is a''(s) at the knot s_j = 0.2 + 0.4 j (j = 0..7); a'' is
+ * linear between knots and constant beyond the end knots, with
+ * a'(1) = a(1) = 0 (the paper's spline curves are not published; this is the
+ * spline family the library implements). Ignored for other types. */
+typedef struct {
+  int32_t type;
+  int32_t reserved;
+  double mu;
+  double lambda;
+  double density;
+  double spline_d2[8];
+} qnsim_material;
+
+/* Per-step counters (filled by qnsim_step / qnsim_step_device when non-null). */
+typedef struct {
+  int32_t iterations_run; /* quasi-Newton iterations executed                */
+  int32_t ls_trials;      /* objective evaluations in line searches          */
+  int32_t ls_exhausted;   /* 1 if a line search found no acceptable step     */
+  int32_t lbfgs_skipped;  /* curvature pairs rejected (rho <= 1e-10|s||t|)   */
+  int32_t fallbacks;      /* x_1 := x (infeasible y) or non-descent resets   */
+  int32_t reserved;
+  double g_first;         /* g(x_1)                                           */
+  double g_last;          /* g at the returned state                          */
+  double grad_norm_first; /* |grad g(x_1)|                                    */
+  double grad_norm_last;  /* |grad g(x_final)| (one extra gradient pass), or
+                             NaN unless requested with qnsim_set_diagnostics  */
+} qnsim_stats;
+
+/* Factor and schedule facts, for reports and tests. */
+typedef struct {
+  int32_t n_free;         /* free vertices = order of A                       */
+  int32_t n_supernodes;
+  int32_t n_levels;       /* supernode tree height + 1                        */
+  int32_t max_front;      /* largest supernode rows (columns + below-diag)    */
+  int64_t nnz_L;          /* stored factor entries (incl. explicit zeros)     */
+  int64_t nnz_L_exact;    /* structural nonzeros of the Cholesky factor       */
+  int64_t factor_bytes;   /* device bytes of the solve blocks                 */
+  double factor_flops;    /* host factorisation flops                         */
+  double prepare_seconds; /* wall time of the last qnsim_prepare              */
+} qnsim_factor_info;
+
+/* Fill *opts with the defaults listed above. */
+int qnsim_options_default(qnsim_options* opts);
+
+/* Create a context. opts may be NULL (defaults). Does not touch the GPU. */
+int qnsim_create(const qnsim_options* opts, qnsim_t** out);
+
+/* Destroy a context and free its host and device memory. NULL is a no-op. */
+void qnsim_destroy(qnsim_t* ctx);
+
+/* Rest mesh: n_verts rest positions (n x 3) and n_tets tetrahedra (T x 4).
+ * Rejects indices out of range, repeated vertices in a tet, non-finite
+ * coordinates and tets with |det Dm| <= 1e-12 * (longest edge)^3
+ * (QNSIM_E_DEGENERATE). Invalidates a previous prepare. */
+int qnsim_set_mesh(qnsim_t* ctx, int32_t n_verts, const double* rest_xyz,
+                   int32_t n_tets, const int32_t* tets);
+
+/* Pinned (Dirichlet) vertices: they keep their input positions, enter the
+ * element deformation gradients, and are eliminated from A and the solver
+ * vectors. n_pinned = 0 clears the set. Invalidates a previous prepare. */
+int qnsim_set_pinned(qnsim_t* ctx, int32_t n_pinned, const int32_t* idx);
+
+/* Materials: n_mat entries; tet_mat[T] gives each tet's material index, or
+ * NULL to use material 0 everywhere. Invalidates a previous prepare. */
+int qnsim_set_materials(qnsim_t* ctx, int32_t n_mat, const qnsim_material* mats,
+                        const int32_t* tet_mat);
+
+/* Host precompute for time step h (section 3; section 4.1): element rest data,
+ * lumped masses, per-material stiffness k by the least-squares fit of
+ * Eq. stiffness over [fit_lo, fit_hi], A = M/h^2 + L on the free vertices,
+ * nested-dissection ordering, supernodal Cholesky factorisation and the
+ * level-scheduled solve blocks; then uploads everything to the device. */
+int qnsim_prepare(qnsim_t* ctx, double h);
+
+/* Same host precompute as qnsim_prepare without any device work; used to
+ * inspect the factorisation on machines without a GPU. A later qnsim_prepare
+ * with the same h reuses it. */
+int qnsim_analyze(qnsim_t* ctx, double h);
+
+/* One time step from host arrays (n x 3): x, v in; x_out, v_out out (may alias
+ * x and v). f_ext may be NULL (gravity only). h must equal the prepared h.
+ * Returns QNSIM_E_INVERTED if a Neo-Hookean element has J <= 0 at x.
+ * Synchronises. stats may be NULL. */
+int qnsim_step(qnsim_t* ctx, const double* x, const double* v, double h,
+               const double* f_ext, double* x_out, double* v_out, qnsim_stats* stats);
+
+/* One time step from device arrays (n x 3 doubles, caller's numbering) on the
+ * given stream (hipStream_t as void*; NULL = default stream). x_out / v_out
+ * may alias x / v. The inverted-input check of qnsim_step is not made here:
+ * an infeasible x shows up as a non-finite g_first. If stats is non-null the
+ * call synchronises the stream to fill it; otherwise the step is fully
+ * stream-ordered once the line-search budget is not exceeded. */
+int qnsim_step_device(qnsim_t* ctx, const double* d_x, const double* d_v, double h,
+                      const double* d_fext, double* d_x_out, double* d_v_out,
+                      void* stream, qnsim_stats* stats);
+
+/* Run `steps` consecutive time steps on device arrays, advancing (d_x, d_v)
+ * in place, and accumulate counters into stats (if non-null). Used to time
+ * trajectories without host round trips between steps. */
+int qnsim_run_device(qnsim_t* ctx, double* d_x, double* d_v, double h,
+                     const double* d_fext, int32_t steps, void* stream,
+                     qnsim_stats* stats);
+
+/* Request the extra gradient pass that fills grad_norm_last (0 = off). */
+int qnsim_set_diagnostics(qnsim_t* ctx, int32_t final_gradient);
+
+/* Per-tet stiffness k (T doubles), available after qnsim_analyze/prepare. */
+int qnsim_get_stiffness(const qnsim_t* ctx, double* k);
+
+/* Lumped vertex masses (n doubles), available after qnsim_analyze/prepare. */
+int qnsim_get_masses(const qnsim_t* ctx, double* mass);
+
+/* Factor and schedule facts, available after qnsim_analyze/prepare. */
+int qnsim_get_factor_info(const qnsim_t* ctx, qnsim_factor_info* info);
+
+/* The Cholesky factor as CSC of the permuted free-vertex matrix, so that
+ * A[perm][:, perm] = L L^T. perm[i] = caller vertex id of the i-th free
+ * unknown (n_free int32). colptr (n_free+1 int64), rowidx / values (nnz_L_exact
+ * int32 / double). Any output pointer may be NULL to skip it. */
+int qnsim_export_factor(const qnsim_t* ctx, int32_t* perm, int64_t* colptr,
+                        int32_t* rowidx, double* values);
+
+/* ---- kernel-level entry points (device arrays, caller's numbering) ------ */
+
+/* Objective and gradient at positions d_x with inertia target d_y (n x 3):
+ * *g_out = g(x) (Eq. PD, free vertices), d_grad (n x 3) = grad g with zero
+ * rows at pinned vertices. Synchronises. */
+int qnsim_eval_device(qnsim_t* ctx, const double* d_x, const double* d_y,
+                      double* g_out, double* d_grad, void* stream);
+
+/* Per-element energy density Psi (T doubles) and first Piola stress P
+ * (T x 9, row-major 3x3 per tet) at positions d_x. Synchronises. */
+int qnsim_element_stress_device(qnsim_t* ctx, const double* d_x, double* d_psi,
+                                double* d_P, void* stream);
+
+/* r = A^{-1} q with the prefactored matrix (section 3, Eq. PDsolution): d_q and
+ * d_r are n x 3 in the caller's numbering; rows of pinned vertices are ignored
+ * in q and set to zero in r. Stream-ordered. */
+int qnsim_solve_device(qnsim_t* ctx, const double* d_q, double* d_r, void* stream);
+
+/* ---- measurement -------------------------------------------------------- */
+
+/* Kernels that qnsim_time_kernel can time in isolation. */
+#define QNSIM_KERNEL_ELEMENT 0  /* element pass of a line-search trial: energy and
+                                   gradient contributions at x_k + alpha d   */
+#define QNSIM_KERNEL_GATHER 1   /* gradient gather (inertia + element terms)     */
+#define QNSIM_KERNEL_SOLVE 2    /* r = A^{-1} q: all forward and backward levels */
+
+/* Time `reps` back-to-back launches of one kernel of the step on the
+ * context's stream with HIP events, on the device state left by the last step
+ * (call after at least one step). *avg_ms = mean time per launch (for
+ * QNSIM_KERNEL_SOLVE: per complete solve). Synchronises. The kernels' inputs
+ * are not changed; their outputs are scratch of the next step. */
+int qnsim_time_kernel(qnsim_t* ctx, int32_t kernel, int32_t reps, double* avg_ms);
+
+/* Descriptive text of a status code, and of the context's last failure. */
+const char* qnsim_strerror(int code);
+const char* qnsim_last_error(const qnsim_t* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QNSIM_H */

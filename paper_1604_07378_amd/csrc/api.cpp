@@ -1,0 +1,740 @@
+// C ABI of the library: argument checks, host precompute orchestration
+// (element rest data, lumped masses, stiffness, assembly of A, ordering,
+// factorisation), upload of the device data, and the step entry points.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/qnsim.h"
+#include "ctx.hpp"
+
+using namespace qn;
+
+namespace {
+
+int fail(qnsim_t* c, int code, const std::string& msg) {
+  if (c) c->last_error = msg;
+  return code;
+}
+
+bool finite_all(const double* p, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+void invalidate(qnsim_t* c) {
+  c->analyzed = false;
+  c->prepared = false;
+  dev_free(c->dev);
+}
+
+// ---------------------------------------------------------------------------
+// Host precompute
+// ---------------------------------------------------------------------------
+int analyze_impl(qnsim_t* c, double h) {
+  auto t0 = std::chrono::steady_clock::now();
+  if (!c->have_mesh) return fail(c, QNSIM_E_STATE, "qnsim_set_mesh has not been called");
+  if (!c->have_mats) return fail(c, QNSIM_E_STATE, "qnsim_set_materials has not been called");
+  if (!(h > 0.0) || !std::isfinite(h)) return fail(c, QNSIM_E_INVALID, "h must be positive");
+  const int n = c->n, T = c->T;
+  const qnsim_options& o = c->opt;
+  // materials: spline tables and stiffness (section 4.1, Eq. stiffness)
+  for (size_t mi = 0; mi < c->mats.size(); ++mi) {
+    Material& m = c->mats[mi];
+    if (m.type == SPLINE) spline_tables(m);
+    m.k = stiffness_fit(m, o.fit_lo, o.fit_hi);
+    if (!(m.k > 0.0) || !std::isfinite(m.k))
+      return fail(c, QNSIM_E_STIFFNESS,
+                  "material " + std::to_string(mi) + " has a non-positive stiffness fit");
+  }
+  // element rest data: Dm = [X1-X0, X2-X0, X3-X0], V = |det Dm|/6, Dm^{-1}
+  c->vol.assign(T, 0.0);
+  c->Dminv.assign(9 * (size_t)T, 0.0);
+  c->kstiff.assign(T, 0.0);
+  c->mass.assign(n, 0.0);
+  for (int t = 0; t < T; ++t) {
+    const int* tv = &c->tets[4 * (size_t)t];
+    double D[3][3];
+    double emax = 0.0;
+    for (int j = 0; j < 3; ++j)
+      for (int i = 0; i < 3; ++i) D[i][j] = c->rest[3 * (size_t)tv[j + 1] + i] - c->rest[3 * (size_t)tv[0] + i];
+    for (int a = 0; a < 4; ++a)
+      for (int b = a + 1; b < 4; ++b) {
+        double e2 = 0.0;
+        for (int i = 0; i < 3; ++i) {
+          double dd = c->rest[3 * (size_t)tv[a] + i] - c->rest[3 * (size_t)tv[b] + i];
+          e2 += dd * dd;
+        }
+        emax = std::max(emax, e2);
+      }
+    const double det = D[0][0] * (D[1][1] * D[2][2] - D[1][2] * D[2][1]) -
+                       D[0][1] * (D[1][0] * D[2][2] - D[1][2] * D[2][0]) +
+                       D[0][2] * (D[1][0] * D[2][1] - D[1][1] * D[2][0]);
+    const double el = std::sqrt(emax);
+    if (!(std::fabs(det) > 1e-12 * el * el * el))
+      return fail(c, QNSIM_E_DEGENERATE, "tet " + std::to_string(t) + " is degenerate at rest");
+    const double id = 1.0 / det;
+    double* Mi = &c->Dminv[9 * (size_t)t];
+    Mi[0] = (D[1][1] * D[2][2] - D[1][2] * D[2][1]) * id;
+    Mi[1] = (D[0][2] * D[2][1] - D[0][1] * D[2][2]) * id;
+    Mi[2] = (D[0][1] * D[1][2] - D[0][2] * D[1][1]) * id;
+    Mi[3] = (D[1][2] * D[2][0] - D[1][0] * D[2][2]) * id;
+    Mi[4] = (D[0][0] * D[2][2] - D[0][2] * D[2][0]) * id;
+    Mi[5] = (D[0][2] * D[1][0] - D[0][0] * D[1][2]) * id;
+    Mi[6] = (D[1][0] * D[2][1] - D[1][1] * D[2][0]) * id;
+    Mi[7] = (D[0][1] * D[2][0] - D[0][0] * D[2][1]) * id;
+    Mi[8] = (D[0][0] * D[1][1] - D[0][1] * D[1][0]) * id;
+    const double V = std::fabs(det) / 6.0;
+    c->vol[t] = V;
+    const Material& m = c->mats[c->tet_mat[t]];
+    c->kstiff[t] = m.k;
+    for (int a = 0; a < 4; ++a) c->mass[tv[a]] += 0.25 * m.rho * V;  // lumped mass
+  }
+  // free vertices
+  std::vector<int> free_ids;
+  std::vector<int> free_of(n, -1);
+  for (int v = 0; v < n; ++v)
+    if (!c->pinned[v]) {
+      if (!(c->mass[v] > 0.0))
+        return fail(c, QNSIM_E_INVALID,
+                    "free vertex " + std::to_string(v) + " belongs to no tetrahedron");
+      free_of[v] = (int)free_ids.size();
+      free_ids.push_back(v);
+    }
+  const int nf = (int)free_ids.size();
+  if (nf == 0) return fail(c, QNSIM_E_INVALID, "every vertex is pinned");
+  // free-vertex graph and geometric nested dissection (rest coordinates)
+  std::vector<std::vector<int>> nb(nf);
+  for (int t = 0; t < T; ++t) {
+    const int* tv = &c->tets[4 * (size_t)t];
+    for (int a = 0; a < 4; ++a)
+      for (int b = 0; b < 4; ++b) {
+        int fa = free_of[tv[a]], fb = free_of[tv[b]];
+        if (a != b && fa >= 0 && fb >= 0) nb[fa].push_back(fb);
+      }
+  }
+  std::vector<int64_t> adjptr(nf + 1, 0);
+  std::vector<int> adj;
+  for (int i = 0; i < nf; ++i) {
+    auto& l = nb[i];
+    std::sort(l.begin(), l.end());
+    l.erase(std::unique(l.begin(), l.end()), l.end());
+    adjptr[i + 1] = adjptr[i] + (int64_t)l.size();
+  }
+  adj.reserve(adjptr[nf]);
+  for (int i = 0; i < nf; ++i) adj.insert(adj.end(), nb[i].begin(), nb[i].end());
+  std::vector<std::vector<int>>().swap(nb);
+  std::vector<double> fxyz(3 * (size_t)nf);
+  for (int i = 0; i < nf; ++i)
+    for (int k = 0; k < 3; ++k) fxyz[3 * (size_t)i + k] = c->rest[3 * (size_t)free_ids[i] + k];
+  std::vector<int> nd = nested_dissection(nf, adjptr, adj, fxyz.data(), 32);
+  std::vector<int> ind(nf);
+  for (int p = 0; p < nf; ++p) ind[nd[p]] = p;
+  // A = M/h^2 + sum_e V_e k_e G_e^T G_e (lower triangle, nested-dissection order)
+  struct Ent { int col, row; double v; };
+  std::vector<Ent> ents;
+  ents.reserve((size_t)T * 10 + nf);
+  for (int i = 0; i < nf; ++i) ents.push_back({ind[i], ind[i], c->mass[free_ids[i]] / (h * h)});
+  for (int t = 0; t < T; ++t) {
+    const int* tv = &c->tets[4 * (size_t)t];
+    const double* Mi = &c->Dminv[9 * (size_t)t];
+    double g[4][3];
+    for (int k = 0; k < 3; ++k) {
+      g[1][k] = Mi[0 * 3 + k];
+      g[2][k] = Mi[1 * 3 + k];
+      g[3][k] = Mi[2 * 3 + k];
+      g[0][k] = -(g[1][k] + g[2][k] + g[3][k]);
+    }
+    const double w = c->vol[t] * c->kstiff[t];
+    for (int a = 0; a < 4; ++a) {
+      int fa = free_of[tv[a]];
+      if (fa < 0) continue;
+      for (int b = 0; b < 4; ++b) {
+        int fb = free_of[tv[b]];
+        if (fb < 0) continue;
+        int ra = ind[fa], rb = ind[fb];
+        if (ra < rb) continue;
+        ents.push_back({rb, ra, w * (g[a][0] * g[b][0] + g[a][1] * g[b][1] + g[a][2] * g[b][2])});
+      }
+    }
+  }
+  std::stable_sort(ents.begin(), ents.end(), [](const Ent& x, const Ent& y) {
+    return x.col < y.col || (x.col == y.col && x.row < y.row);
+  });
+  std::vector<int64_t> colptr(nf + 1, 0);
+  std::vector<int> rowidx;
+  std::vector<double> val;
+  rowidx.reserve(ents.size());
+  val.reserve(ents.size());
+  for (size_t e = 0; e < ents.size();) {
+    size_t f = e;
+    double s = 0.0;
+    while (f < ents.size() && ents[f].col == ents[e].col && ents[f].row == ents[e].row) s += ents[f++].v;
+    rowidx.push_back(ents[e].row);
+    val.push_back(s);
+    colptr[ents[e].col + 1]++;
+    e = f;
+  }
+  std::vector<Ent>().swap(ents);
+  for (int j = 0; j < nf; ++j) colptr[j + 1] += colptr[j];
+  std::string err;
+  int rc = factorize(nf, colptr, rowidx, val, c->factor, err);
+  if (rc == -1) return fail(c, QNSIM_E_NOT_SPD, err);
+  if (rc != 0) return fail(c, QNSIM_E_DEVICE, err);
+  // internal vertex order: free unknowns in factor order, then pinned vertices
+  c->nf = nf;
+  c->vperm.assign(n, -1);
+  c->viperm.assign(n, -1);
+  for (int i = 0; i < nf; ++i) c->vperm[i] = free_ids[nd[c->factor.order[i]]];
+  int p = nf;
+  for (int v = 0; v < n; ++v)
+    if (c->pinned[v]) c->vperm[p++] = v;
+  for (int i = 0; i < n; ++i) c->viperm[c->vperm[i]] = i;
+  // tets sorted by their smallest internal vertex id (spatial locality)
+  std::vector<int> key(T);
+  for (int t = 0; t < T; ++t) {
+    const int* tv = &c->tets[4 * (size_t)t];
+    key[t] = std::min(std::min(c->viperm[tv[0]], c->viperm[tv[1]]),
+                      std::min(c->viperm[tv[2]], c->viperm[tv[3]]));
+  }
+  c->tperm.resize(T);
+  std::iota(c->tperm.begin(), c->tperm.end(), 0);
+  std::stable_sort(c->tperm.begin(), c->tperm.end(), [&](int a, int b) { return key[a] < key[b]; });
+  c->single_type = c->mats[c->tet_mat[0]].type;
+  for (int t = 1; t < T; ++t)
+    if (c->mats[c->tet_mat[t]].type != c->single_type) { c->single_type = -1; break; }
+  c->h = h;
+  c->analyzed = true;
+  c->analyze_seconds =
+      std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return QNSIM_OK;
+}
+
+template <class T>
+int upload(qnsim_t* c, T** dst, const T* src, size_t count) {
+  hipError_t e = hipMalloc((void**)dst, std::max<size_t>(count * sizeof(T), 8));
+  if (e != hipSuccess) return fail(c, QNSIM_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  c->dev.bytes += count * sizeof(T);
+  if (count) {
+    e = hipMemcpy(*dst, src, count * sizeof(T), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return fail(c, QNSIM_E_DEVICE, std::string("hipMemcpy: ") + hipGetErrorString(e));
+  }
+  return QNSIM_OK;
+}
+
+#define UP(dst, vec)                                                    \
+  do {                                                                  \
+    int rc_ = upload(c, &(dst), (vec).data(), (vec).size());            \
+    if (rc_) return rc_;                                                \
+  } while (0)
+
+int upload_impl(qnsim_t* c) {
+  dev_free(c->dev);
+  DeviceMesh& D = c->dev;
+  const Factor& F = c->factor;
+  const int n = c->n, T = c->T, nf = c->nf;
+  D.device = c->opt.device;
+  if (hipSetDevice(D.device) != hipSuccess)
+    return fail(c, QNSIM_E_DEVICE, "hipSetDevice failed (no GPU?)");
+  D.n = n; D.nf = nf; D.T = T; D.h = c->h;
+  D.nmat = (int)c->mats.size();
+  D.single_type = c->single_type;
+  D.m = c->opt.history;
+  D.slots = D.m + 1;
+  // element data in internal tet order
+  std::vector<int> tv(4 * (size_t)T), tm(T);
+  std::vector<double> Bm(9 * (size_t)T), vol(T);
+  for (int t = 0; t < T; ++t) {
+    const int o = c->tperm[t];
+    for (int a = 0; a < 4; ++a) tv[4 * (size_t)t + a] = c->viperm[c->tets[4 * (size_t)o + a]];
+    for (int e = 0; e < 9; ++e) Bm[(size_t)e * T + t] = c->Dminv[9 * (size_t)o + e];
+    vol[t] = c->vol[o];
+    tm[t] = c->tet_mat[o];
+  }
+  std::vector<DevMat> dm(c->mats.size());
+  for (size_t i = 0; i < dm.size(); ++i) {
+    const Material& m = c->mats[i];
+    DevMat& d = dm[i];
+    std::memset(&d, 0, sizeof(d));
+    d.type = m.type; d.mu = m.mu; d.lam = m.lam;
+    for (int j = 0; j < 8; ++j) { d.d2[j] = m.d2[j]; d.a0[j] = m.a0[j]; d.a1[j] = m.a1[j]; }
+  }
+  std::vector<double> mass(n);
+  for (int i = 0; i < n; ++i) mass[i] = c->mass[c->vperm[i]];
+  // incidences of free vertices, ordered by (internal tet, slot)
+  std::vector<int> inc_ptr(nf + 1, 0), inc_idx;
+  for (int t = 0; t < T; ++t)
+    for (int a = 0; a < 4; ++a)
+      if (tv[4 * (size_t)t + a] < nf) inc_ptr[tv[4 * (size_t)t + a] + 1]++;
+  for (int i = 0; i < nf; ++i) inc_ptr[i + 1] += inc_ptr[i];
+  inc_idx.resize(inc_ptr[nf]);
+  {
+    std::vector<int> fill(inc_ptr.begin(), inc_ptr.end() - 1);
+    for (int t = 0; t < T; ++t)
+      for (int a = 0; a < 4; ++a) {
+        int v = tv[4 * (size_t)t + a];
+        if (v < nf) inc_idx[fill[v]++] = 4 * t + a;
+      }
+  }
+  UP(D.tv, tv);
+  UP(D.Bm, Bm);
+  UP(D.vol, vol);
+  if (D.nmat > 1) UP(D.tmat, tm);
+  UP(D.mats, dm);
+  UP(D.mass, mass);
+  UP(D.inc_ptr, inc_ptr);
+  UP(D.inc_idx, inc_idx);
+  UP(D.vperm, c->vperm);
+  UP(D.tperm, c->tperm);
+  // supernodal solve data and level work lists
+  const int ns = (int)F.sn.size();
+  std::vector<int> sfirst(ns), sncol(ns), snb(ns);
+  std::vector<int64_t> sval(ns), srows(ns), supd(ns);
+  for (int s = 0; s < ns; ++s) {
+    const Supernode& S = F.sn[s];
+    sfirst[s] = S.first; sncol[s] = S.ncol; snb[s] = S.nbelow;
+    sval[s] = S.val_off; srows[s] = S.rows_off; supd[s] = S.upd_off;
+    D.max_m = std::max(D.max_m, S.m());
+    D.max_nc = std::max(D.max_nc, S.ncol);
+  }
+  std::vector<int2> fw, bw;
+  D.levels.assign(F.nlevels, Level{0, 0, 0, 0});
+  for (int l = 0; l < F.nlevels; ++l) {
+    D.levels[l].fw_begin = (int)fw.size();
+    D.levels[l].bw_begin = (int)bw.size();
+    for (int s = 0; s < ns; ++s) {
+      if (F.sn[s].level != l) continue;
+      const int m = F.sn[s].m(), nc = F.sn[s].ncol;
+      for (int r = 0; r < (m + 63) / 64; ++r) fw.push_back(make_int2(s, r));
+      for (int cb = 0; cb < (nc + 15) / 16; ++cb) bw.push_back(make_int2(s, cb));
+    }
+    D.levels[l].fw_end = (int)fw.size();
+    D.levels[l].bw_end = (int)bw.size();
+  }
+  UP(D.blk, F.Binv);
+  UP(D.sn_first, sfirst);
+  UP(D.sn_ncol, sncol);
+  UP(D.sn_nbelow, snb);
+  UP(D.sn_val, sval);
+  UP(D.sn_rows, srows);
+  UP(D.sn_upd, supd);
+  UP(D.sn_cptr, F.child_ptr);
+  UP(D.sn_child, F.children);
+  UP(D.rows, F.rows);
+  UP(D.rel, F.rel);
+  UP(D.fw_items, fw);
+  UP(D.bw_items, bw);
+  {
+    std::vector<double> z(3 * (size_t)F.upd_total + 1, 0.0);
+    UP(D.upd, z);
+  }
+  std::string err;
+  int rc = dev_alloc(D, err);
+  if (rc) return fail(c, rc, err);
+  c->prepared = true;
+  return QNSIM_OK;
+}
+
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+int qnsim_options_default(qnsim_options* o) {
+  if (!o) return QNSIM_E_INVALID;
+  std::memset(o, 0, sizeof(*o));
+  o->iterations = 10;
+  o->history = 5;
+  o->max_halvings = 30;
+  o->precision = QNSIM_FP64;
+  o->device = 0;
+  o->gamma = 0.3;
+  o->backtrack = 0.5;
+  o->fit_lo = 0.5;
+  o->fit_hi = 1.5;
+  o->gravity[0] = 0.0;
+  o->gravity[1] = 0.0;
+  o->gravity[2] = -9.81;
+  return QNSIM_OK;
+}
+
+int qnsim_create(const qnsim_options* opts, qnsim_t** out) {
+  if (!out) return QNSIM_E_INVALID;
+  qnsim_options o;
+  if (opts) o = *opts;
+  else qnsim_options_default(&o);
+  if (o.iterations < 1 || o.history < 0 || o.history > kMaxHistory || o.max_halvings < 0 ||
+      o.max_halvings > 200 || !(o.gamma > 0 && o.gamma < 1) || !(o.backtrack > 0 && o.backtrack < 1) ||
+      !(o.fit_hi > o.fit_lo) || !(o.fit_lo > 0) ||
+      (o.precision != QNSIM_FP64 && o.precision != QNSIM_MIXED) ||
+      !finite_all(o.gravity, 3))
+    return QNSIM_E_INVALID;
+  qnsim_t* c = new (std::nothrow) qnsim();
+  if (!c) return QNSIM_E_NOMEM;
+  c->opt = o;
+  *out = c;
+  return QNSIM_OK;
+}
+
+void qnsim_destroy(qnsim_t* c) {
+  if (!c) return;
+  dev_free(c->dev);
+  delete c;
+}
+
+int qnsim_set_mesh(qnsim_t* c, int32_t n_verts, const double* rest, int32_t n_tets,
+                   const int32_t* tets) {
+  if (!c) return QNSIM_E_INVALID;
+  if (n_verts <= 0 || n_tets <= 0 || !rest || !tets)
+    return fail(c, QNSIM_E_INVALID, "mesh needs vertices and tetrahedra");
+  if (!finite_all(rest, 3 * (size_t)n_verts))
+    return fail(c, QNSIM_E_NONFINITE, "non-finite rest coordinate");
+  for (int64_t t = 0; t < n_tets; ++t) {
+    const int32_t* tv = tets + 4 * t;
+    for (int a = 0; a < 4; ++a) {
+      if (tv[a] < 0 || tv[a] >= n_verts)
+        return fail(c, QNSIM_E_INVALID, "tet " + std::to_string(t) + " has a vertex out of range");
+      for (int b = 0; b < a; ++b)
+        if (tv[a] == tv[b])
+          return fail(c, QNSIM_E_INVALID, "tet " + std::to_string(t) + " repeats a vertex");
+    }
+  }
+  invalidate(c);
+  c->n = n_verts;
+  c->T = n_tets;
+  c->rest.assign(rest, rest + 3 * (size_t)n_verts);
+  c->tets.assign(tets, tets + 4 * (size_t)n_tets);
+  c->pinned.assign(n_verts, 0);
+  c->tet_mat.assign(n_tets, 0);
+  c->have_mesh = true;
+  c->have_mats = false;
+  return QNSIM_OK;
+}
+
+int qnsim_set_pinned(qnsim_t* c, int32_t n_pinned, const int32_t* idx) {
+  if (!c) return QNSIM_E_INVALID;
+  if (!c->have_mesh) return fail(c, QNSIM_E_STATE, "qnsim_set_mesh has not been called");
+  if (n_pinned < 0 || (n_pinned > 0 && !idx)) return fail(c, QNSIM_E_INVALID, "bad pinned list");
+  for (int i = 0; i < n_pinned; ++i)
+    if (idx[i] < 0 || idx[i] >= c->n) return fail(c, QNSIM_E_INVALID, "pinned index out of range");
+  invalidate(c);
+  std::fill(c->pinned.begin(), c->pinned.end(), 0);
+  for (int i = 0; i < n_pinned; ++i) c->pinned[idx[i]] = 1;
+  return QNSIM_OK;
+}
+
+int qnsim_set_materials(qnsim_t* c, int32_t n_mat, const qnsim_material* mats,
+                        const int32_t* tet_mat) {
+  if (!c) return QNSIM_E_INVALID;
+  if (!c->have_mesh) return fail(c, QNSIM_E_STATE, "qnsim_set_mesh has not been called");
+  if (n_mat <= 0 || !mats) return fail(c, QNSIM_E_INVALID, "need at least one material");
+  std::vector<Material> ms(n_mat);
+  for (int i = 0; i < n_mat; ++i) {
+    const qnsim_material& q = mats[i];
+    if (q.type < QNSIM_NEOHOOKEAN || q.type > QNSIM_POLYNOMIAL)
+      return fail(c, QNSIM_E_INVALID, "unknown material type");
+    if (!std::isfinite(q.mu) || !std::isfinite(q.lambda) || !std::isfinite(q.density) ||
+        !finite_all(q.spline_d2, 8))
+      return fail(c, QNSIM_E_NONFINITE, "non-finite material parameter");
+    if (!(q.density > 0.0)) return fail(c, QNSIM_E_INVALID, "density must be positive");
+    ms[i].type = q.type;
+    ms[i].mu = q.mu;
+    ms[i].lam = q.lambda;
+    ms[i].rho = q.density;
+    for (int j = 0; j < 8; ++j) ms[i].d2[j] = (q.type == QNSIM_SPLINE) ? q.spline_d2[j] : 0.0;
+  }
+  std::vector<int> tm(c->T, 0);
+  if (tet_mat) {
+    for (int t = 0; t < c->T; ++t) {
+      if (tet_mat[t] < 0 || tet_mat[t] >= n_mat)
+        return fail(c, QNSIM_E_INVALID, "tet material index out of range");
+      tm[t] = tet_mat[t];
+    }
+  }
+  invalidate(c);
+  c->mats = std::move(ms);
+  c->tet_mat = std::move(tm);
+  c->have_mats = true;
+  return QNSIM_OK;
+}
+
+int qnsim_analyze(qnsim_t* c, double h) {
+  if (!c) return QNSIM_E_INVALID;
+  if (c->analyzed && c->h == h) return QNSIM_OK;
+  invalidate(c);
+  try {
+    return analyze_impl(c, h);
+  } catch (const std::bad_alloc&) {
+    return fail(c, QNSIM_E_NOMEM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(c, QNSIM_E_INVALID, e.what());
+  }
+}
+
+int qnsim_prepare(qnsim_t* c, double h) {
+  if (!c) return QNSIM_E_INVALID;
+  auto t0 = std::chrono::steady_clock::now();
+  int rc = qnsim_analyze(c, h);
+  if (rc) return rc;
+  try {
+    rc = upload_impl(c);
+  } catch (const std::bad_alloc&) {
+    rc = fail(c, QNSIM_E_NOMEM, "host allocation failed");
+  }
+  if (rc) {
+    dev_free(c->dev);
+    c->prepared = false;
+    return rc;
+  }
+  c->analyze_seconds +=
+      std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return QNSIM_OK;
+}
+
+static StepParams params_of(const qnsim_t* c, double h) {
+  StepParams p;
+  p.iterations = c->opt.iterations;
+  p.history = c->opt.history;
+  p.max_halvings = c->opt.max_halvings;
+  p.budget = 2;
+  p.gamma = c->opt.gamma;
+  p.backtrack = c->opt.backtrack;
+  for (int i = 0; i < 3; ++i) p.grav[i] = c->opt.gravity[i];
+  p.h = h;
+  return p;
+}
+
+static void fill_stats(const Ctl& t, double gnorm_last, qnsim_stats* s) {
+  s->iterations_run = t.iters;
+  s->ls_trials = t.trials;
+  s->ls_exhausted = t.exhausted;
+  s->lbfgs_skipped = t.skipped;
+  s->fallbacks = t.fallbacks;
+  s->reserved = 0;
+  s->g_first = t.g_first;
+  s->g_last = t.g_k;
+  s->grad_norm_first = std::sqrt(t.gnorm2_first);
+  s->grad_norm_last = gnorm_last;
+}
+
+static int check_step(qnsim_t* c, double h) {
+  if (!c->prepared) return fail(c, QNSIM_E_STATE, "qnsim_prepare has not been called");
+  if (!(std::fabs(h - c->h) <= 1e-12 * c->h))
+    return fail(c, QNSIM_E_H_MISMATCH, "h differs from the prepared h");
+  return QNSIM_OK;
+}
+
+int qnsim_step_device(qnsim_t* c, const double* d_x, const double* d_v, double h,
+                      const double* d_fext, double* d_xo, double* d_vo, void* stream,
+                      qnsim_stats* stats) {
+  if (!c) return QNSIM_E_INVALID;
+  if (!d_x || !d_v || !d_xo || !d_vo) return fail(c, QNSIM_E_INVALID, "null device pointer");
+  int rc = check_step(c, h);
+  if (rc) return rc;
+  std::string err;
+  Ctl t;
+  double gl = NAN;
+  rc = dev_step(c->dev, params_of(c, h), d_x, d_v, d_fext, d_xo, d_vo,
+                stream ? stream : c->dev.stream, stats != nullptr, &t,
+                c->diag_final_gradient != 0, &gl, err);
+  if (rc) return fail(c, rc, err);
+  if (stats) fill_stats(t, gl, stats);
+  return QNSIM_OK;
+}
+
+int qnsim_run_device(qnsim_t* c, double* d_x, double* d_v, double h, const double* d_fext,
+                     int32_t steps, void* stream, qnsim_stats* stats) {
+  if (!c) return QNSIM_E_INVALID;
+  if (!d_x || !d_v || steps < 0) return fail(c, QNSIM_E_INVALID, "bad arguments");
+  int rc = check_step(c, h);
+  if (rc) return rc;
+  qnsim_stats acc;
+  std::memset(&acc, 0, sizeof(acc));
+  for (int s = 0; s < steps; ++s) {
+    std::string err;
+    Ctl t;
+    double gl = NAN;
+    rc = dev_step(c->dev, params_of(c, h), d_x, d_v, d_fext, d_x, d_v,
+                  stream ? stream : c->dev.stream, true, &t, c->diag_final_gradient != 0, &gl, err);
+    if (rc) return fail(c, rc, err);
+    qnsim_stats one;
+    fill_stats(t, gl, &one);
+    acc.iterations_run += one.iterations_run;
+    acc.ls_trials += one.ls_trials;
+    acc.ls_exhausted += one.ls_exhausted;
+    acc.lbfgs_skipped += one.lbfgs_skipped;
+    acc.fallbacks += one.fallbacks;
+    if (s == 0) { acc.g_first = one.g_first; acc.grad_norm_first = one.grad_norm_first; }
+    acc.g_last = one.g_last;
+    acc.grad_norm_last = one.grad_norm_last;
+  }
+  if (stats) *stats = acc;
+  return QNSIM_OK;
+}
+
+int qnsim_step(qnsim_t* c, const double* x, const double* v, double h, const double* f_ext,
+               double* x_out, double* v_out, qnsim_stats* stats) {
+  if (!c) return QNSIM_E_INVALID;
+  if (!x || !v || !x_out || !v_out) return fail(c, QNSIM_E_INVALID, "null pointer");
+  int rc = check_step(c, h);
+  if (rc) return rc;
+  const size_t n3 = 3 * (size_t)c->n;
+  if (!finite_all(x, n3) || !finite_all(v, n3) || (f_ext && !finite_all(f_ext, n3)))
+    return fail(c, QNSIM_E_NONFINITE, "non-finite input state");
+  hipStream_t st = (hipStream_t)c->dev.stream;
+  double* buf = nullptr;
+  if (hipMalloc(&buf, 5 * n3 * sizeof(double)) != hipSuccess)
+    return fail(c, QNSIM_E_NOMEM, "staging allocation failed");
+  double *dx = buf, *dv = buf + n3, *df = buf + 2 * n3, *dxo = buf + 3 * n3, *dvo = buf + 4 * n3;
+  auto cleanup = [&]() { (void)hipFree(buf); };
+  if (hipMemcpyAsync(dx, x, n3 * 8, hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(dv, v, n3 * 8, hipMemcpyHostToDevice, st) != hipSuccess ||
+      (f_ext && hipMemcpyAsync(df, f_ext, n3 * 8, hipMemcpyHostToDevice, st) != hipSuccess)) {
+    cleanup();
+    return fail(c, QNSIM_E_DEVICE, "host-to-device copy failed");
+  }
+  std::string err;
+  bool has_nh = false;
+  for (const Material& m : c->mats) has_nh |= (m.type == NEOHOOKEAN);
+  if (has_nh) {
+    int inv = 0;
+    rc = dev_check_inverted(c->dev, dx, st, &inv, err);
+    if (rc) { cleanup(); return fail(c, rc, err); }
+    if (inv) { cleanup(); return fail(c, QNSIM_E_INVERTED, "Neo-Hookean element with J <= 0 at x"); }
+  }
+  Ctl t;
+  double gl = NAN;
+  rc = dev_step(c->dev, params_of(c, h), dx, dv, f_ext ? df : nullptr, dxo, dvo, st, true, &t,
+                c->diag_final_gradient != 0, &gl, err);
+  if (rc) { cleanup(); return fail(c, rc, err); }
+  if (hipMemcpyAsync(x_out, dxo, n3 * 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipMemcpyAsync(v_out, dvo, n3 * 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess) {
+    cleanup();
+    return fail(c, QNSIM_E_DEVICE, "device-to-host copy failed");
+  }
+  cleanup();
+  if (stats) fill_stats(t, gl, stats);
+  return QNSIM_OK;
+}
+
+int qnsim_set_diagnostics(qnsim_t* c, int32_t final_gradient) {
+  if (!c) return QNSIM_E_INVALID;
+  c->diag_final_gradient = final_gradient ? 1 : 0;
+  return QNSIM_OK;
+}
+
+int qnsim_get_stiffness(const qnsim_t* c, double* k) {
+  if (!c || !k) return QNSIM_E_INVALID;
+  if (!c->analyzed) return QNSIM_E_STATE;
+  std::copy(c->kstiff.begin(), c->kstiff.end(), k);
+  return QNSIM_OK;
+}
+
+int qnsim_get_masses(const qnsim_t* c, double* m) {
+  if (!c || !m) return QNSIM_E_INVALID;
+  if (!c->analyzed) return QNSIM_E_STATE;
+  std::copy(c->mass.begin(), c->mass.end(), m);
+  return QNSIM_OK;
+}
+
+int qnsim_get_factor_info(const qnsim_t* c, qnsim_factor_info* info) {
+  if (!c || !info) return QNSIM_E_INVALID;
+  if (!c->analyzed) return QNSIM_E_STATE;
+  const Factor& F = c->factor;
+  info->n_free = c->nf;
+  info->n_supernodes = (int)F.sn.size();
+  info->n_levels = F.nlevels;
+  info->max_front = F.max_front;
+  info->nnz_L = F.nnz_stored;
+  info->nnz_L_exact = F.nnz_exact;
+  info->factor_bytes = (int64_t)F.Binv.size() * 8;
+  info->factor_flops = F.flops;
+  info->prepare_seconds = c->analyze_seconds;
+  return QNSIM_OK;
+}
+
+int qnsim_export_factor(const qnsim_t* c, int32_t* perm, int64_t* colptr, int32_t* rowidx,
+                        double* values) {
+  if (!c) return QNSIM_E_INVALID;
+  if (!c->analyzed) return QNSIM_E_STATE;
+  if (perm)
+    for (int i = 0; i < c->nf; ++i) perm[i] = c->vperm[i];
+  if (colptr || rowidx || values) {
+    std::vector<int64_t> cp;
+    std::vector<int> ri;
+    std::vector<double> va;
+    factor_to_csc(c->factor, cp, ri, va);
+    if (colptr) std::copy(cp.begin(), cp.end(), colptr);
+    if (rowidx) std::copy(ri.begin(), ri.end(), rowidx);
+    if (values) std::copy(va.begin(), va.end(), values);
+  }
+  return QNSIM_OK;
+}
+
+int qnsim_eval_device(qnsim_t* c, const double* d_x, const double* d_y, double* g_out,
+                      double* d_grad, void* stream) {
+  if (!c || !d_x || !d_y || !g_out || !d_grad) return QNSIM_E_INVALID;
+  if (!c->prepared) return fail(c, QNSIM_E_STATE, "qnsim_prepare has not been called");
+  std::string err;
+  int rc = dev_eval(c->dev, d_x, d_y, g_out, d_grad, stream ? stream : c->dev.stream, err);
+  return rc ? fail(c, rc, err) : QNSIM_OK;
+}
+
+int qnsim_element_stress_device(qnsim_t* c, const double* d_x, double* d_psi, double* d_P,
+                                void* stream) {
+  if (!c || !d_x || !d_psi || !d_P) return QNSIM_E_INVALID;
+  if (!c->prepared) return fail(c, QNSIM_E_STATE, "qnsim_prepare has not been called");
+  std::string err;
+  int rc = dev_element_stress(c->dev, d_x, d_psi, d_P, stream ? stream : c->dev.stream, err);
+  return rc ? fail(c, rc, err) : QNSIM_OK;
+}
+
+int qnsim_solve_device(qnsim_t* c, const double* d_q, double* d_r, void* stream) {
+  if (!c || !d_q || !d_r) return QNSIM_E_INVALID;
+  if (!c->prepared) return fail(c, QNSIM_E_STATE, "qnsim_prepare has not been called");
+  std::string err;
+  int rc = dev_solve(c->dev, d_q, d_r, stream ? stream : c->dev.stream, err);
+  return rc ? fail(c, rc, err) : QNSIM_OK;
+}
+
+int qnsim_time_kernel(qnsim_t* c, int32_t kernel, int32_t reps, double* avg_ms) {
+  if (!c || !avg_ms || reps < 1 || kernel < QNSIM_KERNEL_ELEMENT || kernel > QNSIM_KERNEL_SOLVE)
+    return QNSIM_E_INVALID;
+  if (!c->prepared) return fail(c, QNSIM_E_STATE, "qnsim_prepare has not been called");
+  std::string err;
+  int rc = dev_time_kernel(c->dev, kernel, reps, avg_ms, err);
+  return rc ? fail(c, rc, err) : QNSIM_OK;
+}
+
+const char* qnsim_strerror(int code) {
+  switch (code) {
+    case QNSIM_OK: return "ok";
+    case QNSIM_E_INVALID: return "invalid argument";
+    case QNSIM_E_NONFINITE: return "non-finite input";
+    case QNSIM_E_DEGENERATE: return "degenerate rest tetrahedron";
+    case QNSIM_E_INVERTED: return "inverted Neo-Hookean element at input";
+    case QNSIM_E_STIFFNESS: return "non-positive stiffness fit";
+    case QNSIM_E_NOT_SPD: return "matrix not positive definite";
+    case QNSIM_E_H_MISMATCH: return "time step differs from the prepared one";
+    case QNSIM_E_STATE: return "call out of order";
+    case QNSIM_E_NOMEM: return "out of memory";
+    case QNSIM_E_DEVICE: return "HIP runtime error";
+  }
+  return "unknown status";
+}
+
+const char* qnsim_last_error(const qnsim_t* c) { return c ? c->last_error.c_str() : ""; }
+
+}  // extern "C"

@@ -1,0 +1,45 @@
+// Context of one simulated mesh: caller inputs, host precompute, and the
+// device-resident state of the solver.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/qnsim.h"
+#include "host.hpp"
+#include "kernels.hpp"
+
+struct qnsim {
+  qnsim_options opt;
+  std::string last_error;
+  int diag_final_gradient = 0;
+
+  // ---- caller inputs (caller numbering) ----
+  int n = 0, T = 0;
+  std::vector<double> rest;       // n x 3
+  std::vector<int> tets;          // T x 4
+  std::vector<char> pinned;       // n flags
+  std::vector<qn::Material> mats;
+  std::vector<int> tet_mat;       // T
+  bool have_mesh = false, have_mats = false;
+
+  // ---- host precompute ----
+  bool analyzed = false;
+  double h = 0.0;
+  double analyze_seconds = 0.0;
+  std::vector<double> vol;        // T (caller order)
+  std::vector<double> Dminv;      // T x 9 (caller order), row-major 3x3
+  std::vector<double> mass;       // n (caller order)
+  std::vector<double> kstiff;     // T (caller order)
+  int nf = 0;                     // free vertices
+  std::vector<int> vperm;         // internal vertex -> caller vertex
+  std::vector<int> viperm;        // caller vertex -> internal vertex
+  std::vector<int> tperm;         // internal tet -> caller tet
+  qn::Factor factor;
+  int single_type = -1;           // material type shared by all tets, or -1
+
+  // ---- device state ----
+  bool prepared = false;
+  qn::DeviceMesh dev;
+};

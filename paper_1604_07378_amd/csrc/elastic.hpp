@@ -1,0 +1,266 @@
+// Element energy densities and first Piola stresses on the device (FP64 and
+// FP32 instantiations). Materials follow section 4.1 (Valanis-Landel form) and
+// section 5 (Neo-Hookean, St. Venant-Kirchhoff, corotated, spline-based, and
+// the polynomial material a(x) = mu (x-1)^4).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+
+namespace qn {
+
+template <typename R>
+struct M3 {
+  R a[3][3];
+};
+
+template <typename R>
+__device__ __forceinline__ R det3(const M3<R>& F) {
+  return F.a[0][0] * (F.a[1][1] * F.a[2][2] - F.a[1][2] * F.a[2][1]) -
+         F.a[0][1] * (F.a[1][0] * F.a[2][2] - F.a[1][2] * F.a[2][0]) +
+         F.a[0][2] * (F.a[1][0] * F.a[2][1] - F.a[1][1] * F.a[2][0]);
+}
+
+// Cofactor matrix: dJ/dF (= J F^{-T} when J != 0).
+template <typename R>
+__device__ __forceinline__ M3<R> cofactor(const M3<R>& F) {
+  M3<R> C;
+  C.a[0][0] = F.a[1][1] * F.a[2][2] - F.a[1][2] * F.a[2][1];
+  C.a[0][1] = F.a[1][2] * F.a[2][0] - F.a[1][0] * F.a[2][2];
+  C.a[0][2] = F.a[1][0] * F.a[2][1] - F.a[1][1] * F.a[2][0];
+  C.a[1][0] = F.a[0][2] * F.a[2][1] - F.a[0][1] * F.a[2][2];
+  C.a[1][1] = F.a[0][0] * F.a[2][2] - F.a[0][2] * F.a[2][0];
+  C.a[1][2] = F.a[0][1] * F.a[2][0] - F.a[0][0] * F.a[2][1];
+  C.a[2][0] = F.a[0][1] * F.a[1][2] - F.a[0][2] * F.a[1][1];
+  C.a[2][1] = F.a[0][2] * F.a[1][0] - F.a[0][0] * F.a[1][2];
+  C.a[2][2] = F.a[0][0] * F.a[1][1] - F.a[0][1] * F.a[1][0];
+  return C;
+}
+
+// ---------------------------------------------------------------------------
+// Signed 3x3 SVD, F = U diag(s) V^T with det U = det V = +1 and s3 carrying
+// the sign of det F. Method of McAdams et al. 2011 ("Computing the singular
+// value decomposition of 3x3 matrices with minimal branching and elementary
+// floating point operations"): Jacobi eigenanalysis of F^T F for V, columns
+// of F V sorted by decreasing norm, then a Givens QR of F V whose R diagonal
+// gives the signed singular values. Exact Jacobi and Givens angles are used
+// (not the quaternion approximations of the paper cited).
+// ---------------------------------------------------------------------------
+template <typename R>
+__device__ __forceinline__ void jacobi_rotate(R S[3][3], R V[3][3], int p, int q) {
+  R spq = S[p][q];
+  if (spq == R(0)) return;
+  R tau = (S[q][q] - S[p][p]) / (R(2) * spq);
+  R t = (tau >= R(0) ? R(1) : R(-1)) / (fabs(tau) + sqrt(R(1) + tau * tau));
+  R c = R(1) / sqrt(R(1) + t * t);
+  R s = t * c;
+  // S <- J^T S J with J the rotation in the (p, q) plane
+  for (int k = 0; k < 3; ++k) {
+    R skp = S[k][p], skq = S[k][q];
+    S[k][p] = c * skp - s * skq;
+    S[k][q] = s * skp + c * skq;
+  }
+  for (int k = 0; k < 3; ++k) {
+    R spk = S[p][k], sqk = S[q][k];
+    S[p][k] = c * spk - s * sqk;
+    S[q][k] = s * spk + c * sqk;
+  }
+  for (int k = 0; k < 3; ++k) {
+    R vkp = V[k][p], vkq = V[k][q];
+    V[k][p] = c * vkp - s * vkq;
+    V[k][q] = s * vkp + c * vkq;
+  }
+}
+
+template <typename R>
+__device__ __forceinline__ void swap_cols(R A[3][3], int i, int j, bool negate) {
+  for (int k = 0; k < 3; ++k) {
+    R t = A[k][i];
+    A[k][i] = negate ? -A[k][j] : A[k][j];
+    A[k][j] = t;
+  }
+}
+
+// Givens rotation zeroing B[j][col] against B[i][col]; accumulates U.
+template <typename R>
+__device__ __forceinline__ void givens_qr(R B[3][3], R U[3][3], int i, int j, int col) {
+  R a = B[i][col], b = B[j][col];
+  R r = sqrt(a * a + b * b);
+  R c = R(1), s = R(0);
+  if (r > R(0)) { c = a / r; s = b / r; }
+  for (int k = 0; k < 3; ++k) {
+    R bi = B[i][k], bj = B[j][k];
+    B[i][k] = c * bi + s * bj;
+    B[j][k] = -s * bi + c * bj;
+  }
+  for (int k = 0; k < 3; ++k) {
+    R ui = U[k][i], uj = U[k][j];
+    U[k][i] = c * ui + s * uj;
+    U[k][j] = -s * ui + c * uj;
+  }
+}
+
+template <typename R>
+__device__ __forceinline__ void svd3(const M3<R>& F, R U[3][3], R sig[3], R V[3][3]) {
+  R S[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j)
+      S[i][j] = F.a[0][i] * F.a[0][j] + F.a[1][i] * F.a[1][j] + F.a[2][i] * F.a[2][j];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) V[i][j] = (i == j) ? R(1) : R(0);
+  const int sweeps = sizeof(R) == 8 ? 6 : 4;
+  for (int sw = 0; sw < sweeps; ++sw) {
+    jacobi_rotate(S, V, 0, 1);
+    jacobi_rotate(S, V, 0, 2);
+    jacobi_rotate(S, V, 1, 2);
+  }
+  R B[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j)
+      B[i][j] = F.a[i][0] * V[0][j] + F.a[i][1] * V[1][j] + F.a[i][2] * V[2][j];
+  R n0 = B[0][0] * B[0][0] + B[1][0] * B[1][0] + B[2][0] * B[2][0];
+  R n1 = B[0][1] * B[0][1] + B[1][1] * B[1][1] + B[2][1] * B[2][1];
+  R n2 = B[0][2] * B[0][2] + B[1][2] * B[1][2] + B[2][2] * B[2][2];
+  // sort columns by decreasing norm; each swap negates one column to keep det V = +1
+  if (n0 < n1) { swap_cols(B, 0, 1, true); swap_cols(V, 0, 1, true); R t = n0; n0 = n1; n1 = t; }
+  if (n0 < n2) { swap_cols(B, 0, 2, true); swap_cols(V, 0, 2, true); R t = n0; n0 = n2; n2 = t; }
+  if (n1 < n2) { swap_cols(B, 1, 2, true); swap_cols(V, 1, 2, true); R t = n1; n1 = n2; n2 = t; }
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) U[i][j] = (i == j) ? R(1) : R(0);
+  givens_qr(B, U, 0, 1, 0);
+  givens_qr(B, U, 0, 2, 0);
+  givens_qr(B, U, 1, 2, 1);
+  sig[0] = B[0][0];
+  sig[1] = B[1][1];
+  sig[2] = B[2][2];
+  // B[0][0] >= 0 by construction; make s2 >= 0 too (flip U columns 1 and 2)
+  if (sig[1] < R(0)) {
+    sig[1] = -sig[1];
+    sig[2] = -sig[2];
+    for (int k = 0; k < 3; ++k) { U[k][1] = -U[k][1]; U[k][2] = -U[k][2]; }
+  }
+}
+
+// Spline stretch term: a(s), a'(s) from the knot tables (knots 0.2 + 0.4 j).
+template <typename R>
+__device__ __forceinline__ void spline_eval(const DevMat& m, R s, R& a, R& da) {
+  const R k0 = R(0.2), dk = R(0.4);
+  int j;
+  R x;
+  if (s < k0) {
+    x = s - k0;
+    a = R(m.a0[0]) + R(m.a1[0]) * x + R(m.d2[0]) * x * x * R(0.5);
+    da = R(m.a1[0]) + R(m.d2[0]) * x;
+    return;
+  }
+  if (s > R(3.0)) {
+    x = s - R(3.0);
+    a = R(m.a0[7]) + R(m.a1[7]) * x + R(m.d2[7]) * x * x * R(0.5);
+    da = R(m.a1[7]) + R(m.d2[7]) * x;
+    return;
+  }
+  j = (int)((s - k0) / dk);
+  j = j < 0 ? 0 : (j > 6 ? 6 : j);
+  x = s - (k0 + dk * R(j));
+  R c0 = R(m.d2[j]), slope = (R(m.d2[j + 1]) - c0) / dk;
+  a = R(m.a0[j]) + R(m.a1[j]) * x + c0 * x * x * R(0.5) + slope * x * x * x * (R(1) / R(6));
+  da = R(m.a1[j]) + c0 * x + slope * x * x * R(0.5);
+}
+
+// Psi (energy per unit rest volume) and P for one material. Returns false if
+// the state is infeasible (Neo-Hookean with J <= 0): Psi = +inf, P = 0.
+template <typename R, int TYPE>
+__device__ __forceinline__ bool material_eval(const DevMat& mat, const M3<R>& F, R& psi, M3<R>& P) {
+  const R mu = R(mat.mu), lam = R(mat.lam);
+  if (TYPE == 0) {  // Neo-Hookean
+    R J = det3(F);
+    if (!(J > R(0))) {
+      psi = R(INFINITY);
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) P.a[i][j] = R(0);
+      return false;
+    }
+    M3<R> C = cofactor(F);
+    R invJ = R(1) / J;
+    R lj = log(J);
+    R I1 = R(0);
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) I1 += F.a[i][j] * F.a[i][j];
+    psi = R(0.5) * mu * (I1 - R(3)) - mu * lj + R(0.5) * lam * lj * lj;
+    R cf = (lam * lj - mu) * invJ;
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) P.a[i][j] = mu * F.a[i][j] + cf * C.a[i][j];
+    return true;
+  } else if (TYPE == 1) {  // St. Venant-Kirchhoff
+    R E[3][3];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j)
+        E[i][j] = R(0.5) * (F.a[0][i] * F.a[0][j] + F.a[1][i] * F.a[1][j] + F.a[2][i] * F.a[2][j] -
+                            (i == j ? R(1) : R(0)));
+    R tr = E[0][0] + E[1][1] + E[2][2];
+    R ee = R(0);
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) ee += E[i][j] * E[i][j];
+    psi = mu * ee + R(0.5) * lam * tr * tr;
+    R Sst[3][3];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) Sst[i][j] = R(2) * mu * E[i][j] + (i == j ? lam * tr : R(0));
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j)
+        P.a[i][j] = F.a[i][0] * Sst[0][j] + F.a[i][1] * Sst[1][j] + F.a[i][2] * Sst[2][j];
+    return true;
+  } else {  // stretch-based: spline (2), corotated (3), polynomial (4)
+    R U[3][3], V[3][3], s[3];
+    svd3(F, U, s, V);
+    R g[3];
+    if (TYPE == 2) {
+      R J = det3(F);
+      psi = R(0.5) * lam * (J - R(1)) * (J - R(1));
+      for (int i = 0; i < 3; ++i) {
+        R a, da;
+        spline_eval(mat, s[i], a, da);
+        psi += a;
+        g[i] = da;
+      }
+      M3<R> C = cofactor(F);
+      R cf = lam * (J - R(1));
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+          P.a[i][j] = U[i][0] * g[0] * V[j][0] + U[i][1] * g[1] * V[j][1] + U[i][2] * g[2] * V[j][2] +
+                      cf * C.a[i][j];
+      return true;
+    } else if (TYPE == 3) {
+      R tr = s[0] + s[1] + s[2] - R(3);
+      psi = mu * ((s[0] - R(1)) * (s[0] - R(1)) + (s[1] - R(1)) * (s[1] - R(1)) +
+                  (s[2] - R(1)) * (s[2] - R(1))) +
+            R(0.5) * lam * tr * tr;
+      for (int i = 0; i < 3; ++i) g[i] = R(2) * mu * (s[i] - R(1)) + lam * tr;
+    } else {
+      psi = R(0);
+      for (int i = 0; i < 3; ++i) {
+        R e = s[i] - R(1);
+        psi += mu * e * e * e * e;
+        g[i] = R(4) * mu * e * e * e;
+      }
+    }
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j)
+        P.a[i][j] = U[i][0] * g[0] * V[j][0] + U[i][1] * g[1] * V[j][1] + U[i][2] * g[2] * V[j][2];
+    return true;
+  }
+}
+
+template <typename R>
+__device__ __forceinline__ bool material_eval_any(const DevMat& mat, const M3<R>& F, R& psi,
+                                                  M3<R>& P) {
+  switch (mat.type) {
+    case 0: return material_eval<R, 0>(mat, F, psi, P);
+    case 1: return material_eval<R, 1>(mat, F, psi, P);
+    case 2: return material_eval<R, 2>(mat, F, psi, P);
+    case 3: return material_eval<R, 3>(mat, F, psi, P);
+    default: return material_eval<R, 4>(mat, F, psi, P);
+  }
+}
+
+}  // namespace qn

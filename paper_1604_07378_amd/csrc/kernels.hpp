@@ -1,0 +1,127 @@
+// Device state of one mesh and the host-side launchers of the step kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace qn {
+
+constexpr int kMaxHistory = 16;
+
+// Material parameters as the element kernels read them.
+struct DevMat {
+  int type;
+  int pad;
+  double mu, lam;
+  double d2[8], a0[8], a1[8];
+};
+
+// Control block of one step, resident in device memory. Only single-block
+// "decide" kernels write it; every other kernel reads it to predicate itself.
+struct Ctl {
+  double g_k;          // objective at the current iterate
+  double gtd;          // grad g(x_k) . d_k
+  double alpha;        // current trial step length
+  double g_first, gnorm2_first;
+  double gnorm2_cur;   // |grad g(x_k)|^2 of the current iterate
+  double rho[kMaxHistory + 1];
+  double zeta[kMaxHistory + 1];
+  int active;          // step still iterating
+  int need_host;       // a rare event needs the host (budget, non-descent, infeasible y)
+  int host_reason;     // 1 = line-search budget, 2 = non-descent, 3 = infeasible y
+  int ls_done;         // current iteration's line search accepted
+  int npairs;          // stored curvature pairs (<= m)
+  int newest;          // ring slot of the newest pair
+  int cand;            // ring slot written by this iteration's gather
+  int trials_iter;     // trials in the current line search
+  int trials, skipped, fallbacks, exhausted, iters;
+  int final_k;         // iteration whose iterate is returned when exhausted
+  int inverted;        // inverted-input check result
+  int pad;
+};
+
+struct Level {
+  int fw_begin, fw_end;  // forward work items
+  int bw_begin, bw_end;  // backward work items
+};
+
+struct DeviceMesh {
+  int device = 0;
+  int n = 0, nf = 0, T = 0, nmat = 0, single_type = -1, m = 5, slots = 6;
+  double h = 0.0;
+  // element data (internal tet order)
+  int* tv = nullptr;          // T x 4 internal vertex ids
+  double* Bm = nullptr;       // 9 x T (SoA) entries of Dm^{-1}, row-major per tet
+  double* vol = nullptr;      // T
+  int* tmat = nullptr;        // T material ids (nullptr if nmat == 1)
+  DevMat* mats = nullptr;     // nmat
+  // vertices (internal order: free in factor order, then pinned)
+  double* mass = nullptr;     // n
+  int* inc_ptr = nullptr;     // nf + 1
+  int* inc_idx = nullptr;     // (tet * 4 + slot) per incidence
+  int* vperm = nullptr;       // n: internal -> caller vertex
+  int* tperm = nullptr;       // T: internal -> caller tet
+  // supernodal solve
+  double* blk = nullptr;
+  int* sn_first = nullptr; int* sn_ncol = nullptr; int* sn_nbelow = nullptr;
+  int64_t* sn_val = nullptr; int64_t* sn_rows = nullptr; int64_t* sn_upd = nullptr;
+  int* sn_cptr = nullptr; int* sn_child = nullptr;
+  int* rows = nullptr; int* rel = nullptr;
+  int2* fw_items = nullptr; int2* bw_items = nullptr;
+  std::vector<Level> levels;
+  double* upd = nullptr;
+  int max_m = 0, max_nc = 0;
+  // solver vectors (internal order, 3 doubles per vertex)
+  double* x0 = nullptr;       // n x 3 input positions
+  double* v0 = nullptr;       // n x 3 input velocities
+  double* y = nullptr;        // n x 3 inertial target
+  double* X[2] = {nullptr, nullptr};   // n x 3 iterates (double buffer)
+  double* G[2] = {nullptr, nullptr};   // nf x 3 gradients (double buffer)
+  double* d = nullptr;        // nf x 3 direction (solve output, loop 2 in place)
+  double* q = nullptr;        // nf x 3 loop-1 output / solve input
+  double* z = nullptr;        // nf x 3 forward-solve intermediate
+  double* Sv = nullptr;       // slots x nf x 3
+  double* Tv = nullptr;       // slots x nf x 3
+  double* fel = nullptr;      // T x 4 x 3 element gradient contributions
+  double* part = nullptr;     // reduction partials
+  double* psi = nullptr;      // T per-element energies (probe entry point)
+  int vec_blocks = 1;         // blocks of the vector kernels (fixed -> deterministic)
+  int elem_blocks = 1;
+  Ctl* ctl = nullptr;
+  Ctl* ctl_host = nullptr;    // pinned mirror
+  void* stream = nullptr;     // internal stream (hipStream_t)
+  void* ev[2] = {nullptr, nullptr};
+  size_t bytes = 0;
+};
+
+struct StepParams {
+  int iterations, history, max_halvings, budget;
+  double gamma, backtrack;
+  double grav[3];
+  double h;
+};
+
+// All launchers return 0 or a negative QNSIM_E_* code; err receives a message.
+int dev_alloc(DeviceMesh& d, std::string& err);
+void dev_free(DeviceMesh& d);
+int dev_sync(DeviceMesh& d, void* stream, std::string& err);
+
+// One full time step on the device. x/v/fext/xo/vo: caller numbering n x 3.
+int dev_step(DeviceMesh& d, const StepParams& p, const double* x, const double* v,
+             const double* fext, double* xo, double* vo, void* stream, bool want_ctl,
+             Ctl* ctl_out, bool final_gradient, double* gnorm_last, std::string& err);
+
+// Probes.
+int dev_eval(DeviceMesh& d, const double* x, const double* y, double* g_out, double* grad,
+             void* stream, std::string& err);
+int dev_element_stress(DeviceMesh& d, const double* x, double* psi, double* P, void* stream,
+                       std::string& err);
+int dev_solve(DeviceMesh& d, const double* q, double* r, void* stream, std::string& err);
+int dev_time_kernel(DeviceMesh& d, int kernel, int reps, double* avg_ms, std::string& err);
+int dev_check_inverted(DeviceMesh& d, const double* x, void* stream, int* inverted,
+                       std::string& err);
+
+}  // namespace qn

@@ -1,0 +1,1068 @@
+// HIP kernels and the device driver of one implicit-Euler step:
+// Algorithm 1 (quasi-Newton iterations with backtracking Armijo line search,
+// section 4.1) with Algorithm 2 (L-BFGS two-loop recursion, section 4.2)
+// for the descent direction, whose initial Hessian A = M/h^2 + L is applied
+// through the prefactored supernodal Cholesky factor (section 3).
+//
+// Every decision of the step (accept/reject a trial, store/skip a curvature
+// pair) is taken on the device in single-block "decide" kernels that write a
+// control block; all other kernels read the control block and skip their
+// work when it says so. The host therefore enqueues a fixed kernel sequence
+// per step and synchronises once at the end; only rare events (a line search
+// longer than the enqueued trial budget, a non-descent direction, an
+// infeasible inertial target) hand control back to the host, which continues
+// the same step from where the device stopped.
+//
+// All reductions are deterministic: fixed grids, fixed per-thread element
+// assignment, fixed shuffle/LDS trees, and partial sums combined in block
+// order. No atomics.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "../../include/qnsim.h"
+#include "elastic.hpp"
+#include "kernels.hpp"
+
+namespace qn {
+
+namespace {
+
+constexpr int BS = 256;          // threads per block of every kernel
+constexpr int FW_ROWS = 64;      // rows of a forward-solve work item
+constexpr int BW_COLS = 16;      // columns of a backward-solve work item
+constexpr int CHUNK = 1024;      // LDS staging chunk (entries x 3 doubles)
+
+#define HIP_OK(expr)                                                              \
+  do {                                                                            \
+    hipError_t e_ = (expr);                                                       \
+    if (e_ != hipSuccess) {                                                       \
+      err = std::string(#expr) + ": " + hipGetErrorString(e_);                    \
+      return QNSIM_E_DEVICE;                                                      \
+    }                                                                             \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// Deterministic reductions
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+// Sum over the 256 threads of a block; result valid in thread 0.
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0) r = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+  return r;
+}
+
+// Sum of n partials in a fixed order; result valid in every thread.
+__device__ __forceinline__ double sum_partials(const double* p, int n, double* sh) {
+  double v = 0.0;
+  for (int i = threadIdx.x; i < n; i += BS) v += p[i];
+  v = block_sum(v, sh);
+  __syncthreads();
+  if (threadIdx.x == 0) sh[8] = v;
+  __syncthreads();
+  double r = sh[8];
+  __syncthreads();
+  return r;
+}
+
+__device__ __forceinline__ bool ctl_run(const Ctl* c) { return c->active && !c->need_host; }
+
+// ---------------------------------------------------------------------------
+// Step setup: inertial target y = x + h v + h^2 (a + f_ext / m) (section 3)
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(BS)
+k_step_init(int n, int nf, const int* __restrict__ vperm, const double* __restrict__ mass,
+            const double* __restrict__ x, const double* __restrict__ v,
+            const double* __restrict__ fext, double h, double ax, double ay, double az,
+            double* __restrict__ x0, double* __restrict__ y, double* __restrict__ X0,
+            double* __restrict__ X1, Ctl* ctl, int slots) {
+  int i = blockIdx.x * BS + threadIdx.x;
+  if (i == 0) {
+    ctl->active = 1; ctl->need_host = 0; ctl->host_reason = 0; ctl->ls_done = 0;
+    ctl->npairs = 0; ctl->newest = 0; ctl->cand = slots > 1 ? 1 : 0; ctl->trials_iter = 0;
+    ctl->trials = 0; ctl->skipped = 0; ctl->fallbacks = 0; ctl->exhausted = 0; ctl->iters = 0;
+    ctl->final_k = -1; ctl->alpha = 0.0; ctl->gtd = 0.0; ctl->inverted = 0;
+  }
+  if (i >= n) return;
+  const int o = vperm[i];
+  const double acc[3] = {ax, ay, az};
+  for (int c = 0; c < 3; ++c) {
+    double xi = x[3 * (size_t)o + c];
+    x0[3 * (size_t)i + c] = xi;
+    if (i < nf) {
+      double a = acc[c];
+      if (fext) a += fext[3 * (size_t)o + c] / mass[i];
+      double yi = xi + h * v[3 * (size_t)o + c] + h * h * a;
+      y[3 * (size_t)i + c] = yi;
+      X0[3 * (size_t)i + c] = yi;
+    } else {
+      y[3 * (size_t)i + c] = xi;
+      X0[3 * (size_t)i + c] = xi;
+      X1[3 * (size_t)i + c] = xi;
+    }
+  }
+}
+
+// x_1 := x on the free vertices (fallback when g(y) is not finite).
+__global__ void __launch_bounds__(BS)
+k_copy_free(int nf, const double* __restrict__ src, double* __restrict__ dst) {
+  int i = blockIdx.x * BS + threadIdx.x;
+  if (i < 3 * nf) dst[i] = src[i];
+}
+
+// ---------------------------------------------------------------------------
+// Element pass (section 3, Eq. PD; section 4, Eq. PDgrad2): per tet
+// F = Ds Dm^{-1}, Psi, P, energy V Psi and gradient contributions
+// V P Dm^{-T} (vertex 0 gets minus their sum); thread i also adds the inertia
+// term of free vertex i. Positions are x_k + alpha d on the free vertices
+// (alpha from the control block in a trial, 0 otherwise).
+// mode 0: evaluate at x_k (always runs); mode 1: line-search trial
+// (predicated on an active, unfinished line search); mode 2: probe.
+// ---------------------------------------------------------------------------
+template <int TYPE>
+__global__ void __launch_bounds__(BS)
+k_elem(int mode, int T, int nf, const int* __restrict__ tv, const double* __restrict__ Bm,
+       const double* __restrict__ vol, const int* __restrict__ tmat,
+       const DevMat* __restrict__ mats, const double* __restrict__ mass,
+       const double* __restrict__ X, const double* __restrict__ d,
+       const double* __restrict__ y, double inv2h2, const Ctl* __restrict__ ctl,
+       double* __restrict__ fel, double* __restrict__ part, double* __restrict__ psi_out) {
+  __shared__ double sh[16];
+  double alpha = 0.0;
+  if (mode == 1) {
+    if (!(ctl_run(ctl) && !ctl->ls_done)) return;
+    alpha = ctl->alpha;
+  }
+  const int t = blockIdx.x * BS + threadIdx.x;
+  double e = 0.0;
+  if (t < T) {
+    const int4 iv = reinterpret_cast<const int4*>(tv)[t];
+    const int vid[4] = {iv.x, iv.y, iv.z, iv.w};
+    double p[4][3];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const int v = vid[a];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        double xv = X[3 * (size_t)v + c];
+        if (mode == 1 && v < nf) xv = __fma_rn(alpha, d[3 * (size_t)v + c], xv);
+        p[a][c] = xv;
+      }
+    }
+    double B[3][3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) B[r][c] = Bm[(size_t)(3 * r + c) * T + t];
+    M3<double> F;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      double ds0 = p[1][i] - p[0][i], ds1 = p[2][i] - p[0][i], ds2 = p[3][i] - p[0][i];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) F.a[i][k] = ds0 * B[0][k] + ds1 * B[1][k] + ds2 * B[2][k];
+    }
+    const DevMat& mt = mats[tmat ? tmat[t] : 0];
+    double psi;
+    M3<double> P;
+    if (TYPE >= 0)
+      material_eval<double, (TYPE < 0 ? 0 : TYPE)>(mt, F, psi, P);
+    else
+      material_eval_any<double>(mt, F, psi, P);
+    const double V = vol[t];
+    e = V * psi;
+    if (psi_out) psi_out[t] = psi;
+    double g[4][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      double s = 0.0;
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        double hij = V * (P.a[i][0] * B[j][0] + P.a[i][1] * B[j][1] + P.a[i][2] * B[j][2]);
+        g[j + 1][i] = hij;
+        s += hij;
+      }
+      g[0][i] = -s;
+    }
+    double* o = fel + (size_t)t * 12;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) o[3 * a + c] = g[a][c];
+  }
+  if (t < nf) {
+    double s = 0.0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      double xv = X[3 * (size_t)t + c];
+      if (mode == 1) xv = __fma_rn(alpha, d[3 * (size_t)t + c], xv);
+      double dx = xv - y[3 * (size_t)t + c];
+      s += dx * dx;
+    }
+    e += mass[t] * s * inv2h2;
+  }
+  double b = block_sum(e, sh);
+  if (threadIdx.x == 0 && part) part[blockIdx.x] = b;
+}
+
+// g(x_1): start of the step.
+__global__ void __launch_bounds__(BS)
+k_init_decide(const double* __restrict__ part, int nparts, Ctl* ctl) {
+  __shared__ double sh[16];
+  double g = sum_partials(part, nparts, sh);
+  if (threadIdx.x == 0) {
+    if (!ctl_run(ctl)) return;
+    if (!isfinite(g)) {
+      ctl->need_host = 1;
+      ctl->host_reason = 3;
+      return;
+    }
+    ctl->g_k = g;
+    ctl->g_first = g;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Gradient gather (section 4, Eq. PDgrad2): grad_i = m_i (x_i - y_i)/h^2 +
+// sum of the element contributions of vertex i in a fixed (CSR) order. For
+// k >= 1 it first materialises x_k = x_{k-1} + alpha d of the accepted trial
+// and forms the curvature pair s = x_k - x_{k-1}, t = grad_k - grad_{k-1}
+// (Algorithm 2) in the candidate ring slot, with the partial sums of t.s,
+// s.s, t.t and grad.grad.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(BS)
+k_gather(int k, int nf, const int* __restrict__ inc_ptr, const int* __restrict__ inc_idx,
+         const double* __restrict__ fel, const double* __restrict__ mass,
+         const double* __restrict__ y, double inv_h2, const double* __restrict__ Xp,
+         double* __restrict__ Xc, const double* __restrict__ d, const double* __restrict__ Gp,
+         double* __restrict__ Gc, double* __restrict__ Sall, double* __restrict__ Tall,
+         const Ctl* __restrict__ ctl, double* __restrict__ part) {
+  __shared__ double sh[16];
+  if (!ctl_run(ctl)) return;
+  const double alpha = ctl->alpha;
+  const size_t slot_off = (size_t)ctl->cand * 3 * nf;
+  double* __restrict__ S = Sall + slot_off;
+  double* __restrict__ Tt = Tall + slot_off;
+  double a_ts = 0.0, a_ss = 0.0, a_tt = 0.0, a_gg = 0.0;
+  for (int i = blockIdx.x * BS + threadIdx.x; i < nf; i += gridDim.x * BS) {
+    double xn[3], gr[3];
+    const double mi = mass[i] * inv_h2;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      double xc;
+      if (k > 0) {
+        double xp = Xp[3 * (size_t)i + c];
+        xc = __fma_rn(alpha, d[3 * (size_t)i + c], xp);
+        Xc[3 * (size_t)i + c] = xc;
+        double s = xc - xp;
+        S[3 * (size_t)i + c] = s;
+        a_ss += s * s;
+      } else {
+        xc = Xc[3 * (size_t)i + c];
+      }
+      xn[c] = xc;
+      gr[c] = mi * (xc - y[3 * (size_t)i + c]);
+    }
+    const int e0 = inc_ptr[i], e1 = inc_ptr[i + 1];
+    double f0 = 0.0, f1 = 0.0, f2 = 0.0;
+    for (int e = e0; e < e1; ++e) {
+      const double* f = fel + 3 * (size_t)inc_idx[e];
+      f0 += f[0];
+      f1 += f[1];
+      f2 += f[2];
+    }
+    gr[0] += f0;
+    gr[1] += f1;
+    gr[2] += f2;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      Gc[3 * (size_t)i + c] = gr[c];
+      a_gg += gr[c] * gr[c];
+      if (k > 0) {
+        double tt = gr[c] - Gp[3 * (size_t)i + c];
+        Tt[3 * (size_t)i + c] = tt;
+        a_tt += tt * tt;
+        a_ts += tt * S[3 * (size_t)i + c];
+      }
+    }
+    (void)xn;
+  }
+  const int nb = gridDim.x;
+  double r;
+  r = block_sum(a_ts, sh); if (threadIdx.x == 0) part[0 * nb + blockIdx.x] = r;
+  r = block_sum(a_ss, sh); if (threadIdx.x == 0) part[1 * nb + blockIdx.x] = r;
+  r = block_sum(a_tt, sh); if (threadIdx.x == 0) part[2 * nb + blockIdx.x] = r;
+  r = block_sum(a_gg, sh); if (threadIdx.x == 0) part[3 * nb + blockIdx.x] = r;
+}
+
+// Curvature safeguard and ring bookkeeping; resets the line search.
+__global__ void __launch_bounds__(BS)
+k_pair_decide(int k, int m, int slots, const double* __restrict__ part, int nb, Ctl* ctl) {
+  __shared__ double sh[16];
+  double ts = sum_partials(part + 0 * nb, nb, sh);
+  double ss = sum_partials(part + 1 * nb, nb, sh);
+  double tt = sum_partials(part + 2 * nb, nb, sh);
+  double gg = sum_partials(part + 3 * nb, nb, sh);
+  if (threadIdx.x != 0 || !ctl_run(ctl)) return;
+  if (k == 0) {
+    ctl->gnorm2_first = gg;
+  } else if (m > 0 && ts > 1e-10 * sqrt(ss) * sqrt(tt)) {
+    ctl->newest = ctl->cand;
+    ctl->rho[ctl->cand] = ts;
+    ctl->npairs = ctl->npairs < m ? ctl->npairs + 1 : m;
+  } else {
+    ctl->skipped += 1;
+  }
+  ctl->cand = (ctl->newest + 1) % slots;
+  ctl->ls_done = 0;
+  ctl->alpha = 1.0;
+  ctl->trials_iter = 0;
+  ctl->iters = k + 1;
+  ctl->gnorm2_cur = gg;
+}
+
+// ---------------------------------------------------------------------------
+// L-BFGS two-loop recursion (Algorithm 2). Launch j of loop 1 (j = 0..m):
+// applies q -= zeta t for the (j-1)-th newest pair, then forms the partial
+// sums of s.q for the j-th newest pair. Launch 0 sets q := -grad.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(BS)
+k_loop1(int j, int nf, int slots, const double* __restrict__ grad, double* __restrict__ q,
+        const double* __restrict__ Sall, const double* __restrict__ Tall,
+        const double* __restrict__ pin, double* __restrict__ pout, int nb, Ctl* ctl) {
+  __shared__ double sh[16];
+  if (!ctl_run(ctl)) return;
+  const int np = ctl->npairs, newest = ctl->newest;
+  const bool apply = j >= 1 && (j - 1) < np;
+  const bool dot = j < np;
+  if (j >= 1 && !apply) return;
+  const size_t n3 = 3 * (size_t)nf;
+  double zeta = 0.0;
+  const double* tp = nullptr;
+  if (apply) {
+    int sp = (newest - (j - 1) + slots) % slots;
+    zeta = sum_partials(pin, nb, sh) / ctl->rho[sp];
+    if (blockIdx.x == 0 && threadIdx.x == 0) ctl->zeta[sp] = zeta;
+    tp = Tall + (size_t)sp * n3;
+  }
+  const double* sc = dot ? Sall + (size_t)((newest - j + slots) % slots) * n3 : nullptr;
+  double acc = 0.0;
+  for (size_t i = blockIdx.x * BS + threadIdx.x; i < n3; i += (size_t)gridDim.x * BS) {
+    double qi = (j == 0) ? -grad[i] : q[i];
+    if (apply) qi = qi - zeta * tp[i];
+    q[i] = qi;
+    if (dot) acc += sc[i] * qi;
+  }
+  if (dot) {
+    double b = block_sum(acc, sh);
+    if (threadIdx.x == 0) pout[blockIdx.x] = b;
+  }
+}
+
+// Launch j of loop 2 (j = 0..m), on r (in place): applies
+// r += s (zeta - eta) for the (j-1)-th oldest pair, eta = t.r / rho, then forms
+// the partial sums of t.r for the j-th oldest pair. Launch m also forms the
+// partial sums of grad.d for the Armijo test.
+__global__ void __launch_bounds__(BS)
+k_loop2(int j, int m, int nf, int slots, double* __restrict__ r, const double* __restrict__ grad,
+        const double* __restrict__ Sall, const double* __restrict__ Tall,
+        const double* __restrict__ pin, double* __restrict__ pout, double* __restrict__ pgtd,
+        int nb, const Ctl* __restrict__ ctl) {
+  __shared__ double sh[16];
+  if (!ctl_run(ctl)) return;
+  const int np = ctl->npairs, newest = ctl->newest;
+  const bool apply = j >= 1 && (j - 1) < np;
+  const bool dot = j < np;
+  const bool last = (j == m);
+  if (!apply && !dot && !last) return;
+  const size_t n3 = 3 * (size_t)nf;
+  double coef = 0.0;
+  const double* sp_vec = nullptr;
+  if (apply) {
+    int sp = (newest - (np - 1 - (j - 1)) + slots) % slots;
+    double eta = sum_partials(pin, nb, sh) / ctl->rho[sp];
+    coef = ctl->zeta[sp] - eta;
+    sp_vec = Sall + (size_t)sp * n3;
+  }
+  const double* tc = dot ? Tall + (size_t)((newest - (np - 1 - j) + slots) % slots) * n3 : nullptr;
+  double acc = 0.0, agtd = 0.0;
+  for (size_t i = blockIdx.x * BS + threadIdx.x; i < n3; i += (size_t)gridDim.x * BS) {
+    double ri = r[i];
+    if (apply) {
+      ri = ri + sp_vec[i] * coef;
+      r[i] = ri;
+    }
+    if (dot) acc += tc[i] * ri;
+    if (last) agtd += grad[i] * ri;
+  }
+  if (dot) {
+    double b = block_sum(acc, sh);
+    if (threadIdx.x == 0) pout[blockIdx.x] = b;
+  }
+  if (last) {
+    double b = block_sum(agtd, sh);
+    if (threadIdx.x == 0) pgtd[blockIdx.x] = b;
+  }
+}
+
+// Descent check: grad.d < 0 unless grad = 0.
+__global__ void __launch_bounds__(BS)
+k_dir_decide(const double* __restrict__ pgtd, int nb, Ctl* ctl) {
+  __shared__ double sh[16];
+  double gtd = sum_partials(pgtd, nb, sh);
+  if (threadIdx.x != 0 || !ctl_run(ctl)) return;
+  double gg = ctl->gnorm2_cur;
+  if (!(gtd < 0.0) && gg > 0.0) {
+    ctl->need_host = 1;
+    ctl->host_reason = 2;
+    return;
+  }
+  ctl->gtd = gtd;
+}
+
+// Armijo test of one line-search trial (section 4.1, Algorithm 1).
+__global__ void __launch_bounds__(BS)
+k_ls_decide(int k, int last_in_budget, int max_halvings, double gamma, double backtrack,
+            const double* __restrict__ part, int nparts, Ctl* ctl) {
+  __shared__ double sh[16];
+  if (!(ctl_run(ctl) && !ctl->ls_done)) return;
+  double g = sum_partials(part, nparts, sh);
+  if (threadIdx.x != 0) return;
+  ctl->trials += 1;
+  ctl->trials_iter += 1;
+  if (g <= ctl->g_k + gamma * ctl->alpha * ctl->gtd) {
+    ctl->ls_done = 1;
+    ctl->g_k = g;
+  } else if (ctl->trials_iter > max_halvings) {
+    ctl->exhausted = 1;
+    ctl->active = 0;
+    ctl->final_k = k;
+  } else {
+    ctl->alpha *= backtrack;
+    if (last_in_budget) {
+      ctl->need_host = 1;
+      ctl->host_reason = 1;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Triangular solves with the partitioned-inverse supernodal factor.
+// Forward (leaves to root): for supernode S with children C,
+//   t_S = q_S - sum_C v_C|_S,   z_S = L11^{-1} t_S,
+//   v_S = (L21 L11^{-1}) t_S + sum_C v_C|_{rows below S}.
+// Backward (root to leaves): w_S = L11^{-T} z_S - (L21 L11^{-1})^T w_{rows below S}.
+// One launch per tree level; a forward work item is (S, 64-row block), a
+// backward work item is (S, 16-column block).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(BS)
+k_fwd(const int2* __restrict__ items, const int* __restrict__ sn_first,
+      const int* __restrict__ sn_ncol, const int* __restrict__ sn_nbelow,
+      const int64_t* __restrict__ sn_val, const int64_t* __restrict__ sn_rows,
+      const int64_t* __restrict__ sn_upd, const int* __restrict__ cptr,
+      const int* __restrict__ child, const int* __restrict__ rel,
+      const double* __restrict__ blk, const double* __restrict__ q, double* __restrict__ z,
+      double* __restrict__ upd, const Ctl* __restrict__ ctl) {
+  __shared__ double t3[3][CHUNK];
+  __shared__ double pt[3][FW_ROWS];
+  __shared__ double red[3][4][FW_ROWS];
+  if (ctl && !ctl_run(ctl)) return;
+  const int2 it = items[blockIdx.x];
+  const int s = it.x;
+  const int first = sn_first[s], nc = sn_ncol[s], nb = sn_nbelow[s];
+  const int m = nc + nb;
+  const int r0 = it.y * FW_ROWS;
+  const int r1 = min(m, r0 + FW_ROWS);
+  const double* __restrict__ B = blk + sn_val[s];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, w = tid >> 6;
+  const int row = r0 + lane;
+  if (tid < FW_ROWS) { pt[0][tid] = 0.0; pt[1][tid] = 0.0; pt[2][tid] = 0.0; }
+  double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
+  // columns are processed in chunks that fit in LDS
+  const int cmax = min(nc, r1);  // rows < nc only need columns <= row
+  for (int c0 = 0; c0 < nc; c0 += CHUNK) {
+    const int c1 = min(nc, c0 + CHUNK);
+    __syncthreads();
+    for (int c = c0 + tid; c < c1; c += BS) {
+      t3[0][c - c0] = q[3 * (size_t)(first + c) + 0];
+      t3[1][c - c0] = q[3 * (size_t)(first + c) + 1];
+      t3[2][c - c0] = q[3 * (size_t)(first + c) + 2];
+    }
+    __syncthreads();
+    // subtract the children's update vectors (children in fixed order; rows of
+    // one child are distinct, so threads never collide)
+    for (int e = cptr[s]; e < cptr[s + 1]; ++e) {
+      const int ch = child[e];
+      const int cnb = sn_nbelow[ch];
+      const int* __restrict__ rl = rel + sn_rows[ch];
+      const double* __restrict__ u = upd + sn_upd[ch];
+      for (int a = tid; a < cnb; a += BS) {
+        const int pos = rl[a];
+        if (pos >= c0 && pos < c1) {
+          t3[0][pos - c0] -= u[3 * a + 0];
+          t3[1][pos - c0] -= u[3 * a + 1];
+          t3[2][pos - c0] -= u[3 * a + 2];
+        } else if (c0 == 0 && pos >= nc && pos >= r0 && pos < r1) {
+          pt[0][pos - r0] += u[3 * a + 0];
+          pt[1][pos - r0] += u[3 * a + 1];
+          pt[2][pos - r0] += u[3 * a + 2];
+        }
+      }
+      __syncthreads();
+    }
+    // out[row] += sum_c B[row, c] t[c], wave w takes columns c = c0 + w (mod 4)
+    if (row < r1) {
+      const int cend = (row < nc) ? min(c1, row + 1) : c1;
+      for (int c = c0 + w; c < cend; c += 4) {
+        const double b = B[(size_t)c * m + row];
+        acc0 += b * t3[0][c - c0];
+        acc1 += b * t3[1][c - c0];
+        acc2 += b * t3[2][c - c0];
+      }
+    }
+    (void)cmax;
+  }
+  red[0][w][lane] = acc0;
+  red[1][w][lane] = acc1;
+  red[2][w][lane] = acc2;
+  __syncthreads();
+  if (tid < FW_ROWS && row < r1) {
+    double o[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) o[c] = (red[c][0][tid] + red[c][1][tid]) + (red[c][2][tid] + red[c][3][tid]);
+    if (row < nc) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) z[3 * (size_t)(first + row) + c] = o[c];
+    } else {
+      double* __restrict__ u = upd + sn_upd[s] + 3 * (size_t)(row - nc);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) u[c] = o[c] + pt[c][tid];
+    }
+  }
+}
+
+__global__ void __launch_bounds__(BS)
+k_bwd(const int2* __restrict__ items, const int* __restrict__ sn_first,
+      const int* __restrict__ sn_ncol, const int* __restrict__ sn_nbelow,
+      const int64_t* __restrict__ sn_val, const int64_t* __restrict__ sn_rows,
+      const int* __restrict__ rows, const double* __restrict__ blk,
+      const double* __restrict__ z, double* __restrict__ wv, const Ctl* __restrict__ ctl) {
+  __shared__ double u3[3][CHUNK];
+  if (ctl && !ctl_run(ctl)) return;
+  const int2 it = items[blockIdx.x];
+  const int s = it.x;
+  const int first = sn_first[s], nc = sn_ncol[s], nb = sn_nbelow[s];
+  const int m = nc + nb;
+  const int cb0 = it.y * BW_COLS;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const double* __restrict__ B = blk + sn_val[s];
+  const int* __restrict__ rw = rows + sn_rows[s];
+  // wave w owns columns cb0 + w*4 .. cb0 + w*4 + 3
+  double acc[4][3];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) acc[a][0] = acc[a][1] = acc[a][2] = 0.0;
+  for (int i0 = cb0; i0 < m; i0 += CHUNK) {  // rows < cb0 never contribute
+    const int i1 = min(m, i0 + CHUNK);
+    __syncthreads();
+    for (int i = i0 + tid; i < i1; i += BS) {
+      if (i < nc) {
+        u3[0][i - i0] = z[3 * (size_t)(first + i) + 0];
+        u3[1][i - i0] = z[3 * (size_t)(first + i) + 1];
+        u3[2][i - i0] = z[3 * (size_t)(first + i) + 2];
+      } else {
+        const int g = rw[i - nc];
+        u3[0][i - i0] = -wv[3 * (size_t)g + 0];
+        u3[1][i - i0] = -wv[3 * (size_t)g + 1];
+        u3[2][i - i0] = -wv[3 * (size_t)g + 2];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const int c = cb0 + w * 4 + a;
+      if (c >= nc) break;
+      const double* __restrict__ col = B + (size_t)c * m;
+      for (int i = max(i0, c) + lane; i < i1; i += 64) {
+        const double b = col[i];
+        acc[a][0] += b * u3[0][i - i0];
+        acc[a][1] += b * u3[1][i - i0];
+        acc[a][2] += b * u3[2][i - i0];
+      }
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const int c = cb0 + w * 4 + a;
+    double r0 = wave_sum(acc[a][0]), r1 = wave_sum(acc[a][1]), r2 = wave_sum(acc[a][2]);
+    if (lane == 0 && c < nc) {
+      wv[3 * (size_t)(first + c) + 0] = r0;
+      wv[3 * (size_t)(first + c) + 1] = r1;
+      wv[3 * (size_t)(first + c) + 2] = r2;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// End of step: x' = final iterate, v' = (x' - x)/h; pinned: x' = x, v' = 0.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(BS)
+k_finalize(int n, int nf, int K, const int* __restrict__ vperm, const double* __restrict__ x0,
+           const double* __restrict__ X0, const double* __restrict__ X1,
+           const double* __restrict__ d, double inv_h, const Ctl* __restrict__ ctl,
+           double* __restrict__ xo, double* __restrict__ vo) {
+  if (ctl->need_host) return;
+  const int i = blockIdx.x * BS + threadIdx.x;
+  if (i >= n) return;
+  int kf;
+  bool add;
+  if (ctl->exhausted) { kf = ctl->final_k; add = false; }
+  else { kf = K - 1; add = ctl->ls_done != 0; }
+  const double* Xc = (kf & 1) ? X1 : X0;
+  const double alpha = ctl->alpha;
+  const int o = vperm[i];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    double xin = x0[3 * (size_t)i + c];
+    double xf = xin, vf = 0.0;
+    if (i < nf) {
+      xf = Xc[3 * (size_t)i + c];
+      if (add) xf = __fma_rn(alpha, d[3 * (size_t)i + c], xf);
+      vf = (xf - xin) * inv_h;
+    }
+    xo[3 * (size_t)o + c] = xf;
+    vo[3 * (size_t)o + c] = vf;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Probe helpers
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(BS)
+k_load_perm(int n, const int* __restrict__ vperm, const double* __restrict__ src,
+            double* __restrict__ dst) {
+  const int i = blockIdx.x * BS + threadIdx.x;
+  if (i >= n) return;
+  const int o = vperm[i];
+  for (int c = 0; c < 3; ++c) dst[3 * (size_t)i + c] = src[3 * (size_t)o + c];
+}
+
+__global__ void __launch_bounds__(BS)
+k_store_perm(int n, int nf, const int* __restrict__ vperm, const double* __restrict__ src,
+             double* __restrict__ dst) {
+  const int i = blockIdx.x * BS + threadIdx.x;
+  if (i >= n) return;
+  const int o = vperm[i];
+  for (int c = 0; c < 3; ++c) dst[3 * (size_t)o + c] = (i < nf) ? src[3 * (size_t)i + c] : 0.0;
+}
+
+__global__ void k_ctl_probe(Ctl* ctl) {
+  ctl->active = 1; ctl->need_host = 0; ctl->ls_done = 0; ctl->cand = 0; ctl->alpha = 0.0;
+  ctl->npairs = 0; ctl->newest = 0; ctl->inverted = 0;
+}
+
+__global__ void __launch_bounds__(BS)
+k_sum_to_ctl(const double* __restrict__ part, int nparts, Ctl* ctl) {
+  __shared__ double sh[16];
+  double g = sum_partials(part, nparts, sh);
+  if (threadIdx.x == 0) ctl->g_k = g;
+}
+
+__global__ void __launch_bounds__(BS)
+k_store_stress(int T, const int* __restrict__ tperm, const double* __restrict__ psi_int,
+               const int* __restrict__ tv, const double* __restrict__ Bm,
+               const int* __restrict__ tmat, const DevMat* __restrict__ mats,
+               const double* __restrict__ X, double* __restrict__ psi, double* __restrict__ Pout) {
+  const int t = blockIdx.x * BS + threadIdx.x;
+  if (t >= T) return;
+  const int4 iv = reinterpret_cast<const int4*>(tv)[t];
+  const int vid[4] = {iv.x, iv.y, iv.z, iv.w};
+  double p[4][3];
+  for (int a = 0; a < 4; ++a)
+    for (int c = 0; c < 3; ++c) p[a][c] = X[3 * (size_t)vid[a] + c];
+  M3<double> F;
+  for (int i = 0; i < 3; ++i)
+    for (int k = 0; k < 3; ++k) {
+      double s = 0.0;
+      for (int j = 0; j < 3; ++j) s += (p[j + 1][i] - p[0][i]) * Bm[(size_t)(3 * j + k) * T + t];
+      F.a[i][k] = s;
+    }
+  double ps;
+  M3<double> P;
+  material_eval_any<double>(mats[tmat ? tmat[t] : 0], F, ps, P);
+  const int o = tperm[t];
+  psi[o] = ps;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) Pout[9 * (size_t)o + 3 * i + j] = P.a[i][j];
+  (void)psi_int;
+}
+
+// Neo-Hookean inverted-input check: flags any NH tet with J <= 0 at X.
+__global__ void __launch_bounds__(BS)
+k_check_inverted(int T, const int* __restrict__ tv, const double* __restrict__ Bm,
+                 const int* __restrict__ tmat, const DevMat* __restrict__ mats,
+                 const double* __restrict__ X, Ctl* ctl) {
+  const int t = blockIdx.x * BS + threadIdx.x;
+  if (t >= T) return;
+  if (mats[tmat ? tmat[t] : 0].type != 0) return;
+  const int4 iv = reinterpret_cast<const int4*>(tv)[t];
+  const int vid[4] = {iv.x, iv.y, iv.z, iv.w};
+  M3<double> F;
+  for (int i = 0; i < 3; ++i)
+    for (int k = 0; k < 3; ++k) {
+      double s = 0.0;
+      for (int j = 0; j < 3; ++j)
+        s += (X[3 * (size_t)vid[j + 1] + i] - X[3 * (size_t)vid[0] + i]) * Bm[(size_t)(3 * j + k) * T + t];
+      F.a[i][k] = s;
+    }
+  if (!(det3(F) > 0.0)) ctl->inverted = 1;  // every writer stores the same value
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launch helpers
+// ---------------------------------------------------------------------------
+inline int nblk(int64_t n) { return (int)std::max<int64_t>(1, (n + BS - 1) / BS); }
+
+void launch_elem(DeviceMesh& D, hipStream_t st, int mode, const double* X, double* part,
+                 double* psi_out) {
+  const double inv2h2 = 0.5 / (D.h * D.h);
+  const int grid = D.elem_blocks;
+#define QN_ELEM(TY)                                                                         \
+  hipLaunchKernelGGL(k_elem<TY>, dim3(grid), dim3(BS), 0, st, mode, D.T, D.nf, D.tv, D.Bm, \
+                     D.vol, D.tmat, D.mats, D.mass, X, D.d, D.y, inv2h2, D.ctl, D.fel, part, \
+                     psi_out)
+  switch (D.single_type) {
+    case 0: QN_ELEM(0); break;
+    case 1: QN_ELEM(1); break;
+    case 2: QN_ELEM(2); break;
+    case 3: QN_ELEM(3); break;
+    case 4: QN_ELEM(4); break;
+    default: QN_ELEM(-1); break;
+  }
+#undef QN_ELEM
+}
+
+void launch_solve(DeviceMesh& D, hipStream_t st, const double* q, double* r, const Ctl* ctl) {
+  const int L = (int)D.levels.size();
+  for (int l = 0; l < L; ++l) {
+    const Level& lv = D.levels[l];
+    int n = lv.fw_end - lv.fw_begin;
+    if (n > 0)
+      hipLaunchKernelGGL(k_fwd, dim3(n), dim3(BS), 0, st, D.fw_items + lv.fw_begin, D.sn_first,
+                         D.sn_ncol, D.sn_nbelow, D.sn_val, D.sn_rows, D.sn_upd, D.sn_cptr,
+                         D.sn_child, D.rel, D.blk, q, D.z, D.upd, ctl);
+  }
+  for (int l = L - 1; l >= 0; --l) {
+    const Level& lv = D.levels[l];
+    int n = lv.bw_end - lv.bw_begin;
+    if (n > 0)
+      hipLaunchKernelGGL(k_bwd, dim3(n), dim3(BS), 0, st, D.bw_items + lv.bw_begin, D.sn_first,
+                         D.sn_ncol, D.sn_nbelow, D.sn_val, D.sn_rows, D.rows, D.blk, D.z, r, ctl);
+  }
+}
+
+// Partials layout: [0, 4*vb) gather values; two ping-pong dot buffers of vb;
+// gtd buffer of vb; element partials of elem_blocks.
+struct Parts {
+  double *gather, *dotA, *dotB, *gtd, *elem;
+};
+Parts parts_of(DeviceMesh& D) {
+  const int vb = D.vec_blocks;
+  Parts p;
+  p.gather = D.part;
+  p.dotA = D.part + 4 * vb;
+  p.dotB = D.part + 5 * vb;
+  p.gtd = D.part + 6 * vb;
+  p.elem = D.part + 7 * vb;
+  return p;
+}
+
+enum Stage { ST_GATHER = 0, ST_DIRECTION = 1, ST_LINESEARCH = 2 };
+
+void launch_iteration(DeviceMesh& D, const StepParams& P, hipStream_t st, int k, int stage,
+                      int budget) {
+  Parts pp = parts_of(D);
+  const int vb = D.vec_blocks;
+  const int m = P.history;
+  double* Xc = D.X[k & 1];
+  const double* Xp = D.X[(k + 1) & 1];
+  double* Gc = D.G[k & 1];
+  const double* Gp = D.G[(k + 1) & 1];
+  if (stage <= ST_GATHER) {
+    hipLaunchKernelGGL(k_gather, dim3(vb), dim3(BS), 0, st, k, D.nf, D.inc_ptr, D.inc_idx, D.fel,
+                       D.mass, D.y, 1.0 / (D.h * D.h), Xp, Xc, D.d, Gp, Gc, D.Sv, D.Tv, D.ctl,
+                       pp.gather);
+    hipLaunchKernelGGL(k_pair_decide, dim3(1), dim3(BS), 0, st, k, m, D.slots, pp.gather, vb,
+                       D.ctl);
+  }
+  if (stage <= ST_DIRECTION) {
+    for (int j = 0; j <= m; ++j) {
+      double* pin = (j & 1) ? pp.dotA : pp.dotB;
+      double* pout = (j & 1) ? pp.dotB : pp.dotA;
+      hipLaunchKernelGGL(k_loop1, dim3(vb), dim3(BS), 0, st, j, D.nf, D.slots, Gc, D.q, D.Sv,
+                         D.Tv, pin, pout, vb, D.ctl);
+    }
+    launch_solve(D, st, D.q, D.d, D.ctl);
+    for (int j = 0; j <= m; ++j) {
+      double* pin = (j & 1) ? pp.dotA : pp.dotB;
+      double* pout = (j & 1) ? pp.dotB : pp.dotA;
+      hipLaunchKernelGGL(k_loop2, dim3(vb), dim3(BS), 0, st, j, m, D.nf, D.slots, D.d, Gc, D.Sv,
+                         D.Tv, pin, pout, pp.gtd, vb, D.ctl);
+    }
+    hipLaunchKernelGGL(k_dir_decide, dim3(1), dim3(BS), 0, st, pp.gtd, vb, D.ctl);
+  }
+  for (int b = 0; b < budget; ++b) {
+    launch_elem(D, st, 1, Xc, pp.elem, nullptr);
+    hipLaunchKernelGGL(k_ls_decide, dim3(1), dim3(BS), 0, st, k, (b == budget - 1) ? 1 : 0,
+                       P.max_halvings, P.gamma, P.backtrack, pp.elem, D.elem_blocks, D.ctl);
+  }
+}
+
+__global__ void k_host_resume(Ctl* ctl, int clear_pairs) {
+  ctl->need_host = 0;
+  ctl->host_reason = 0;
+  if (clear_pairs) { ctl->npairs = 0; ctl->fallbacks += 1; }
+}
+
+__global__ void k_fallback_x(Ctl* ctl) {
+  ctl->need_host = 0;
+  ctl->host_reason = 0;
+  ctl->fallbacks += 1;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Device memory
+// ---------------------------------------------------------------------------
+int dev_sync(DeviceMesh& D, void* stream, std::string& err) {
+  HIP_OK(hipStreamSynchronize((hipStream_t)(stream ? stream : D.stream)));
+  return 0;
+}
+
+void dev_free(DeviceMesh& D) {
+  void* ptrs[] = {D.tv, D.Bm, D.vol, D.tmat, D.mats, D.mass, D.inc_ptr, D.inc_idx, D.vperm,
+                  D.blk, D.sn_first, D.sn_ncol, D.sn_nbelow, D.sn_val, D.sn_rows, D.sn_upd,
+                  D.sn_cptr, D.sn_child, D.rows, D.rel, D.fw_items, D.bw_items, D.upd, D.x0,
+                  D.v0, D.y, D.X[0], D.X[1], D.G[0], D.G[1], D.d, D.q, D.z, D.Sv, D.Tv, D.fel,
+                  D.part, D.psi, D.ctl, D.tperm};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  if (D.ctl_host) (void)hipHostFree(D.ctl_host);
+  if (D.stream) (void)hipStreamDestroy((hipStream_t)D.stream);
+  D = DeviceMesh();
+}
+
+int dev_alloc(DeviceMesh& D, std::string& err) {
+  HIP_OK(hipSetDevice(D.device));
+  const size_t n3 = 3 * (size_t)D.n, f3 = 3 * (size_t)std::max(D.nf, 1);
+  auto A = [&](void** p, size_t bytes) -> hipError_t {
+    D.bytes += bytes;
+    return hipMalloc(p, std::max<size_t>(bytes, 8));
+  };
+  HIP_OK(A((void**)&D.x0, n3 * 8));
+  HIP_OK(A((void**)&D.v0, n3 * 8));
+  HIP_OK(A((void**)&D.y, n3 * 8));
+  HIP_OK(A((void**)&D.X[0], n3 * 8));
+  HIP_OK(A((void**)&D.X[1], n3 * 8));
+  HIP_OK(A((void**)&D.G[0], f3 * 8));
+  HIP_OK(A((void**)&D.G[1], f3 * 8));
+  HIP_OK(A((void**)&D.d, f3 * 8));
+  HIP_OK(A((void**)&D.q, f3 * 8));
+  HIP_OK(A((void**)&D.z, f3 * 8));
+  HIP_OK(A((void**)&D.Sv, f3 * 8 * D.slots));
+  HIP_OK(A((void**)&D.Tv, f3 * 8 * D.slots));
+  HIP_OK(A((void**)&D.fel, (size_t)D.T * 12 * 8));
+  HIP_OK(A((void**)&D.psi, (size_t)D.T * 8));
+  D.vec_blocks = std::max(1, std::min(256, nblk(D.nf)));
+  D.elem_blocks = nblk(std::max(D.T, D.nf));
+  HIP_OK(A((void**)&D.part, (size_t)(7 * D.vec_blocks + D.elem_blocks) * 8));
+  HIP_OK(A((void**)&D.ctl, sizeof(Ctl)));
+  HIP_OK(hipHostMalloc((void**)&D.ctl_host, sizeof(Ctl), hipHostMallocDefault));
+  hipStream_t st;
+  HIP_OK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+  D.stream = st;
+  HIP_OK(hipMemset(D.X[1], 0, n3 * 8));
+  HIP_OK(hipMemset(D.ctl, 0, sizeof(Ctl)));
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// One time step
+// ---------------------------------------------------------------------------
+int dev_step(DeviceMesh& D, const StepParams& P, const double* x, const double* v,
+             const double* fext, double* xo, double* vo, void* stream, bool want_ctl,
+             Ctl* ctl_out, bool final_gradient, double* gnorm_last, std::string& err) {
+  hipStream_t st = (hipStream_t)stream;
+  Parts pp = parts_of(D);
+  const int K = P.iterations;
+  hipLaunchKernelGGL(k_step_init, dim3(nblk(D.n)), dim3(BS), 0, st, D.n, D.nf, D.vperm, D.mass,
+                     x, v, fext, P.h, P.grav[0], P.grav[1], P.grav[2], D.x0, D.y, D.X[0], D.X[1],
+                     D.ctl, D.slots);
+  launch_elem(D, st, 0, D.X[0], pp.elem, nullptr);
+  hipLaunchKernelGGL(k_init_decide, dim3(1), dim3(BS), 0, st, pp.elem, D.elem_blocks, D.ctl);
+  for (int k = 0; k < K; ++k) launch_iteration(D, P, st, k, ST_GATHER, P.budget);
+  hipLaunchKernelGGL(k_finalize, dim3(nblk(D.n)), dim3(BS), 0, st, D.n, D.nf, K, D.vperm, D.x0,
+                     D.X[0], D.X[1], D.d, 1.0 / P.h, D.ctl, xo, vo);
+  HIP_OK(hipGetLastError());
+  HIP_OK(hipMemcpyAsync(D.ctl_host, D.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+  HIP_OK(hipStreamSynchronize(st));
+  // Rare events: continue the step from where the device stopped.
+  int guard = 0;
+  while (D.ctl_host->need_host) {
+    if (++guard > 4 * K + 8) {
+      err = "step did not settle after host continuation";
+      return QNSIM_E_DEVICE;
+    }
+    const int reason = D.ctl_host->host_reason;
+    int k = D.ctl_host->iters - 1;
+    if (reason == 3) {
+      // infeasible y: x_1 := x, evaluate again
+      hipLaunchKernelGGL(k_fallback_x, dim3(1), dim3(1), 0, st, D.ctl);
+      hipLaunchKernelGGL(k_copy_free, dim3(nblk(3 * (int64_t)D.nf)), dim3(BS), 0, st, D.nf, D.x0,
+                         D.X[0]);
+      launch_elem(D, st, 0, D.X[0], pp.elem, nullptr);
+      hipLaunchKernelGGL(k_init_decide, dim3(1), dim3(BS), 0, st, pp.elem, D.elem_blocks, D.ctl);
+      k = -1;
+    } else if (reason == 2) {
+      hipLaunchKernelGGL(k_host_resume, dim3(1), dim3(1), 0, st, D.ctl, 1);
+      launch_iteration(D, P, st, k, ST_DIRECTION, P.max_halvings + 1);
+    } else {
+      hipLaunchKernelGGL(k_host_resume, dim3(1), dim3(1), 0, st, D.ctl, 0);
+      launch_iteration(D, P, st, k, ST_LINESEARCH, P.max_halvings + 1);
+    }
+    for (int kk = k + 1; kk < K; ++kk) launch_iteration(D, P, st, kk, ST_GATHER, P.budget);
+    hipLaunchKernelGGL(k_finalize, dim3(nblk(D.n)), dim3(BS), 0, st, D.n, D.nf, K, D.vperm, D.x0,
+                       D.X[0], D.X[1], D.d, 1.0 / P.h, D.ctl, xo, vo);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipMemcpyAsync(D.ctl_host, D.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+  }
+  if (final_gradient && gnorm_last) {
+    // gradient at the returned state (diagnostic): element pass + gather at x'
+    hipLaunchKernelGGL(k_load_perm, dim3(nblk(D.n)), dim3(BS), 0, st, D.n, D.vperm, xo, D.X[0]);
+    hipLaunchKernelGGL(k_ctl_probe, dim3(1), dim3(1), 0, st, D.ctl);
+    launch_elem(D, st, 2, D.X[0], pp.elem, nullptr);
+    hipLaunchKernelGGL(k_gather, dim3(D.vec_blocks), dim3(BS), 0, st, 0, D.nf, D.inc_ptr,
+                       D.inc_idx, D.fel, D.mass, D.y, 1.0 / (D.h * D.h), D.X[1], D.X[0], D.d,
+                       D.G[1], D.G[0], D.Sv, D.Tv, D.ctl, pp.gather);
+    hipLaunchKernelGGL(k_sum_to_ctl, dim3(1), dim3(BS), 0, st, pp.gather + 3 * D.vec_blocks,
+                       D.vec_blocks, D.ctl);
+    Ctl tmp;
+    HIP_OK(hipMemcpyAsync(&tmp, D.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    *gnorm_last = std::sqrt(tmp.g_k);
+  }
+  if (want_ctl && ctl_out) *ctl_out = *D.ctl_host;
+  return 0;
+}
+
+int dev_eval(DeviceMesh& D, const double* x, const double* y, double* g_out, double* grad,
+             void* stream, std::string& err) {
+  hipStream_t st = (hipStream_t)stream;
+  Parts pp = parts_of(D);
+  hipLaunchKernelGGL(k_load_perm, dim3(nblk(D.n)), dim3(BS), 0, st, D.n, D.vperm, x, D.X[0]);
+  hipLaunchKernelGGL(k_load_perm, dim3(nblk(D.n)), dim3(BS), 0, st, D.n, D.vperm, y, D.y);
+  hipLaunchKernelGGL(k_ctl_probe, dim3(1), dim3(1), 0, st, D.ctl);
+  launch_elem(D, st, 2, D.X[0], pp.elem, nullptr);
+  hipLaunchKernelGGL(k_sum_to_ctl, dim3(1), dim3(BS), 0, st, pp.elem, D.elem_blocks, D.ctl);
+  hipLaunchKernelGGL(k_gather, dim3(D.vec_blocks), dim3(BS), 0, st, 0, D.nf, D.inc_ptr, D.inc_idx,
+                     D.fel, D.mass, D.y, 1.0 / (D.h * D.h), D.X[1], D.X[0], D.d, D.G[1], D.G[0],
+                     D.Sv, D.Tv, D.ctl, pp.gather);
+  hipLaunchKernelGGL(k_store_perm, dim3(nblk(D.n)), dim3(BS), 0, st, D.n, D.nf, D.vperm, D.G[0],
+                     grad);
+  HIP_OK(hipGetLastError());
+  Ctl tmp;
+  HIP_OK(hipMemcpyAsync(&tmp, D.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+  HIP_OK(hipStreamSynchronize(st));
+  *g_out = tmp.g_k;
+  return 0;
+}
+
+int dev_element_stress(DeviceMesh& D, const double* x, double* psi, double* P, void* stream,
+                       std::string& err) {
+  hipStream_t st = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_load_perm, dim3(nblk(D.n)), dim3(BS), 0, st, D.n, D.vperm, x, D.X[0]);
+  hipLaunchKernelGGL(k_store_stress, dim3(nblk(D.T)), dim3(BS), 0, st, D.T, D.tperm, D.psi, D.tv,
+                     D.Bm, D.tmat, D.mats, D.X[0], psi, P);
+  HIP_OK(hipGetLastError());
+  HIP_OK(hipStreamSynchronize(st));
+  return 0;
+}
+
+int dev_solve(DeviceMesh& D, const double* q, double* r, void* stream, std::string& err) {
+  hipStream_t st = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_load_perm, dim3(nblk(D.nf)), dim3(BS), 0, st, D.nf, D.vperm, q, D.q);
+  launch_solve(D, st, D.q, D.d, nullptr);
+  hipLaunchKernelGGL(k_store_perm, dim3(nblk(D.n)), dim3(BS), 0, st, D.n, D.nf, D.vperm, D.d, r);
+  HIP_OK(hipGetLastError());
+  return 0;
+}
+
+namespace {
+__global__ void k_ctl_timing(Ctl* ctl) {
+  ctl->active = 1; ctl->need_host = 0; ctl->ls_done = 0; ctl->alpha = 0.5; ctl->cand = 0;
+}
+}  // namespace
+
+int dev_time_kernel(DeviceMesh& D, int kernel, int reps, double* avg_ms, std::string& err) {
+  hipStream_t st = (hipStream_t)D.stream;
+  Parts pp = parts_of(D);
+  hipEvent_t e0, e1;
+  HIP_OK(hipEventCreate(&e0));
+  HIP_OK(hipEventCreate(&e1));
+  hipLaunchKernelGGL(k_ctl_timing, dim3(1), dim3(1), 0, st, D.ctl);
+  // one untimed launch to warm caches and code objects
+  for (int pass = 0; pass < 2; ++pass) {
+    const int n = pass == 0 ? 1 : reps;
+    if (pass == 1) HIP_OK(hipEventRecord(e0, st));
+    for (int r = 0; r < n; ++r) {
+      if (kernel == 0) {
+        launch_elem(D, st, 1, D.X[0], pp.elem, nullptr);
+      } else if (kernel == 1) {
+        hipLaunchKernelGGL(k_gather, dim3(D.vec_blocks), dim3(BS), 0, st, 0, D.nf, D.inc_ptr,
+                           D.inc_idx, D.fel, D.mass, D.y, 1.0 / (D.h * D.h), D.X[1], D.X[0], D.d,
+                           D.G[1], D.G[0], D.Sv, D.Tv, D.ctl, pp.gather);
+      } else {
+        launch_solve(D, st, D.q, D.G[1], nullptr);
+      }
+    }
+  }
+  HIP_OK(hipEventRecord(e1, st));
+  HIP_OK(hipEventSynchronize(e1));
+  float ms = 0.f;
+  HIP_OK(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *avg_ms = (double)ms / std::max(1, reps);
+  return 0;
+}
+
+int dev_check_inverted(DeviceMesh& D, const double* x, void* stream, int* inverted,
+                       std::string& err) {
+  hipStream_t st = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_load_perm, dim3(nblk(D.n)), dim3(BS), 0, st, D.n, D.vperm, x, D.X[1]);
+  hipLaunchKernelGGL(k_ctl_probe, dim3(1), dim3(1), 0, st, D.ctl);
+  hipLaunchKernelGGL(k_check_inverted, dim3(nblk(D.T)), dim3(BS), 0, st, D.T, D.tv, D.Bm, D.tmat,
+                     D.mats, D.X[1], D.ctl);
+  HIP_OK(hipGetLastError());
+  Ctl tmp;
+  HIP_OK(hipMemcpyAsync(&tmp, D.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+  HIP_OK(hipStreamSynchronize(st));
+  *inverted = tmp.inverted;
+  return 0;
+}
+
+}  // namespace qn

@@ -1,0 +1,326 @@
+"""Python binding of libqnsim (argument marshalling only).
+
+Every computation of the time step runs in the HIP library; this module only
+converts NumPy arrays / torch tensors into the plain pointers and sizes of
+the C ABI declared in include/qnsim.h. There is no fallback: if the compiled
+library is missing the import of the binding fails.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqnsim.so")
+
+KERNEL_ELEMENT, KERNEL_GATHER, KERNEL_SOLVE = 0, 1, 2
+QNSIM_FP64 = 0
+QNSIM_MIXED = 1
+NEOHOOKEAN, STVK, SPLINE, COROTATED, POLYNOMIAL = 0, 1, 2, 3, 4
+
+ERRORS = {
+    -1: "QNSIM_E_INVALID", -2: "QNSIM_E_NONFINITE", -3: "QNSIM_E_DEGENERATE",
+    -4: "QNSIM_E_INVERTED", -5: "QNSIM_E_STIFFNESS", -6: "QNSIM_E_NOT_SPD",
+    -7: "QNSIM_E_H_MISMATCH", -8: "QNSIM_E_STATE", -9: "QNSIM_E_NOMEM",
+    -10: "QNSIM_E_DEVICE",
+}
+
+
+class QnsimError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("history", ctypes.c_int32),
+                ("max_halvings", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("device", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("gamma", ctypes.c_double), ("backtrack", ctypes.c_double),
+                ("fit_lo", ctypes.c_double), ("fit_hi", ctypes.c_double),
+                ("gravity", ctypes.c_double * 3)]
+
+
+class MaterialC(ctypes.Structure):
+    _fields_ = [("type", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("mu", ctypes.c_double), ("lambda_", ctypes.c_double),
+                ("density", ctypes.c_double), ("spline_d2", ctypes.c_double * 8)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("iterations_run", ctypes.c_int32), ("ls_trials", ctypes.c_int32),
+                ("ls_exhausted", ctypes.c_int32), ("lbfgs_skipped", ctypes.c_int32),
+                ("fallbacks", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("g_first", ctypes.c_double), ("g_last", ctypes.c_double),
+                ("grad_norm_first", ctypes.c_double), ("grad_norm_last", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+class FactorInfo(ctypes.Structure):
+    _fields_ = [("n_free", ctypes.c_int32), ("n_supernodes", ctypes.c_int32),
+                ("n_levels", ctypes.c_int32), ("max_front", ctypes.c_int32),
+                ("nnz_L", ctypes.c_int64), ("nnz_L_exact", ctypes.c_int64),
+                ("factor_bytes", ctypes.c_int64), ("factor_flops", ctypes.c_double),
+                ("prepare_seconds", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_P = ctypes.c_void_p
+_D = ctypes.c_double
+_I = ctypes.c_int32
+
+# name -> (restype, argtypes); every entry point of include/qnsim.h
+SIGNATURES = {
+    "qnsim_options_default": (ctypes.c_int, [ctypes.POINTER(Options)]),
+    "qnsim_create": (ctypes.c_int, [ctypes.POINTER(Options), ctypes.POINTER(_P)]),
+    "qnsim_destroy": (None, [_P]),
+    "qnsim_set_mesh": (ctypes.c_int, [_P, _I, _P, _I, _P]),
+    "qnsim_set_pinned": (ctypes.c_int, [_P, _I, _P]),
+    "qnsim_set_materials": (ctypes.c_int, [_P, _I, ctypes.POINTER(MaterialC), _P]),
+    "qnsim_prepare": (ctypes.c_int, [_P, _D]),
+    "qnsim_analyze": (ctypes.c_int, [_P, _D]),
+    "qnsim_step": (ctypes.c_int, [_P, _P, _P, _D, _P, _P, _P, ctypes.POINTER(Stats)]),
+    "qnsim_step_device": (ctypes.c_int, [_P, _P, _P, _D, _P, _P, _P, _P, ctypes.POINTER(Stats)]),
+    "qnsim_run_device": (ctypes.c_int, [_P, _P, _P, _D, _P, _I, _P, ctypes.POINTER(Stats)]),
+    "qnsim_set_diagnostics": (ctypes.c_int, [_P, _I]),
+    "qnsim_get_stiffness": (ctypes.c_int, [_P, _P]),
+    "qnsim_get_masses": (ctypes.c_int, [_P, _P]),
+    "qnsim_get_factor_info": (ctypes.c_int, [_P, ctypes.POINTER(FactorInfo)]),
+    "qnsim_export_factor": (ctypes.c_int, [_P, _P, _P, _P, _P]),
+    "qnsim_eval_device": (ctypes.c_int, [_P, _P, _P, ctypes.POINTER(_D), _P, _P]),
+    "qnsim_element_stress_device": (ctypes.c_int, [_P, _P, _P, _P, _P]),
+    "qnsim_solve_device": (ctypes.c_int, [_P, _P, _P, _P]),
+    "qnsim_time_kernel": (ctypes.c_int, [_P, _I, _I, ctypes.POINTER(_D)]),
+    "qnsim_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "qnsim_last_error": (ctypes.c_char_p, [_P]),
+}
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libqnsim.so (built in-tree by build_lib.build()); no fallback."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with "
+                          "paper_1604_07378_amd.build_lib.build() (hipcc, gfx950)")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def default_options() -> Options:
+    o = Options()
+    load_library().qnsim_options_default(ctypes.byref(o))
+    return o
+
+
+def _f64(a, shape=None) -> np.ndarray:
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if shape is not None and a.shape != shape:
+        raise ValueError(f"expected shape {shape}, got {a.shape}")
+    return a
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _tptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    if not t.is_cuda or t.dtype.__str__() != "torch.float64" or not t.is_contiguous():
+        raise ValueError("device arrays must be contiguous float64 CUDA (HIP) tensors")
+    return t.data_ptr()
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return getattr(stream, "cuda_stream", stream)
+
+
+class Sim:
+    """One simulated mesh (a qnsim_t context)."""
+
+    def __init__(self, options: Optional[Options] = None, **overrides):
+        self._lib = load_library()
+        o = options if options is not None else default_options()
+        for k, v in overrides.items():
+            if k == "gravity":
+                o.gravity = (ctypes.c_double * 3)(*v)
+            else:
+                setattr(o, k, v)
+        self.options = o
+        h = ctypes.c_void_p()
+        self._check(self._lib.qnsim_create(ctypes.byref(o), ctypes.byref(h)), None)
+        self._h = h
+        self.n = self.T = 0
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.qnsim_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc, ctx="self"):
+        if rc != 0:
+            msg = ""
+            if ctx is not None and getattr(self, "_h", None):
+                msg = self._lib.qnsim_last_error(self._h).decode()
+            raise QnsimError(rc, msg or self._lib.qnsim_strerror(rc).decode())
+
+    # ---- setup ------------------------------------------------------------
+    def set_mesh(self, rest, tets):
+        rest = _f64(rest)
+        tets = np.ascontiguousarray(tets, dtype=np.int32)
+        self.n, self.T = rest.shape[0], tets.shape[0]
+        self._check(self._lib.qnsim_set_mesh(self._h, self.n, _ptr(rest), self.T, _ptr(tets)))
+
+    def set_pinned(self, idx):
+        idx = np.ascontiguousarray(idx, dtype=np.int32)
+        self._check(self._lib.qnsim_set_pinned(self._h, idx.size, _ptr(idx) if idx.size else None))
+
+    def set_materials(self, materials: Sequence, tet_mat=None):
+        arr = (MaterialC * len(materials))()
+        for i, m in enumerate(materials):
+            get = (lambda k: m[k]) if isinstance(m, dict) else (lambda k: getattr(m, k))
+            arr[i].type = int(get("type"))
+            arr[i].mu = float(get("mu"))
+            arr[i].lambda_ = float(get("lam"))
+            arr[i].density = float(get("density"))
+            d2 = get("spline_d2") if not isinstance(m, dict) else m.get("spline_d2")
+            if d2 is not None:
+                for j, val in enumerate(np.asarray(d2, dtype=np.float64)):
+                    arr[i].spline_d2[j] = float(val)
+        tm = None
+        if tet_mat is not None:
+            tm = np.ascontiguousarray(tet_mat, dtype=np.int32)
+        self._check(self._lib.qnsim_set_materials(self._h, len(materials), arr,
+                                                  _ptr(tm) if tm is not None else None))
+
+    def analyze(self, h: float):
+        self._check(self._lib.qnsim_analyze(self._h, float(h)))
+
+    def prepare(self, h: float):
+        self._check(self._lib.qnsim_prepare(self._h, float(h)))
+
+    def set_diagnostics(self, final_gradient: bool):
+        self._check(self._lib.qnsim_set_diagnostics(self._h, 1 if final_gradient else 0))
+
+    # ---- queries ----------------------------------------------------------
+    def stiffness(self) -> np.ndarray:
+        k = np.empty(self.T)
+        self._check(self._lib.qnsim_get_stiffness(self._h, _ptr(k)))
+        return k
+
+    def masses(self) -> np.ndarray:
+        m = np.empty(self.n)
+        self._check(self._lib.qnsim_get_masses(self._h, _ptr(m)))
+        return m
+
+    def factor_info(self) -> dict:
+        fi = FactorInfo()
+        self._check(self._lib.qnsim_get_factor_info(self._h, ctypes.byref(fi)))
+        return fi.as_dict()
+
+    def export_factor(self):
+        info = self.factor_info()
+        nf, nnz = info["n_free"], info["nnz_L"]
+        perm = np.empty(nf, dtype=np.int32)
+        cp = np.empty(nf + 1, dtype=np.int64)
+        ri = np.empty(nnz, dtype=np.int32)
+        va = np.empty(nnz)
+        self._check(self._lib.qnsim_export_factor(self._h, _ptr(perm), _ptr(cp), _ptr(ri), _ptr(va)))
+        return perm, cp, ri, va
+
+    # ---- steps --------------------------------------------------------------
+    def step(self, x, v, h: float, f_ext=None):
+        """One step from host arrays; returns (x', v', stats dict)."""
+        x = _f64(x, (self.n, 3))
+        v = _f64(v, (self.n, 3))
+        f = _f64(f_ext, (self.n, 3)) if f_ext is not None else None
+        xo = np.empty_like(x)
+        vo = np.empty_like(v)
+        st = Stats()
+        self._check(self._lib.qnsim_step(self._h, _ptr(x), _ptr(v), float(h),
+                                         _ptr(f) if f is not None else None,
+                                         _ptr(xo), _ptr(vo), ctypes.byref(st)))
+        return xo, vo, st.as_dict()
+
+    def step_device(self, x, v, h: float, f_ext=None, x_out=None, v_out=None,
+                    stream=None, stats: bool = True):
+        """One step on torch device tensors (n x 3 float64); in place by default."""
+        x_out = x if x_out is None else x_out
+        v_out = v if v_out is None else v_out
+        st = Stats()
+        self._check(self._lib.qnsim_step_device(
+            self._h, _tptr(x), _tptr(v), float(h), _tptr(f_ext), _tptr(x_out), _tptr(v_out),
+            _stream_ptr(stream), ctypes.byref(st) if stats else None))
+        return st.as_dict() if stats else None
+
+    def run_device(self, x, v, h: float, steps: int, f_ext=None, stream=None):
+        st = Stats()
+        self._check(self._lib.qnsim_run_device(self._h, _tptr(x), _tptr(v), float(h),
+                                               _tptr(f_ext), int(steps), _stream_ptr(stream),
+                                               ctypes.byref(st)))
+        return st.as_dict()
+
+    def time_kernel(self, kernel: int, reps: int) -> float:
+        """Mean milliseconds per launch of one step kernel (HIP events)."""
+        ms = ctypes.c_double()
+        self._check(self._lib.qnsim_time_kernel(self._h, int(kernel), int(reps), ctypes.byref(ms)))
+        return ms.value
+
+    # ---- kernel-level probes ------------------------------------------------
+    def eval_device(self, x, y, grad_out, stream=None) -> float:
+        g = ctypes.c_double()
+        self._check(self._lib.qnsim_eval_device(self._h, _tptr(x), _tptr(y), ctypes.byref(g),
+                                                _tptr(grad_out), _stream_ptr(stream)))
+        return g.value
+
+    def element_stress_device(self, x, psi_out, P_out, stream=None):
+        self._check(self._lib.qnsim_element_stress_device(self._h, _tptr(x), _tptr(psi_out),
+                                                          _tptr(P_out), _stream_ptr(stream)))
+
+    def solve_device(self, q, r_out, stream=None):
+        self._check(self._lib.qnsim_solve_device(self._h, _tptr(q), _tptr(r_out),
+                                                 _stream_ptr(stream)))
+
+
+def sim_from_workload(w, options: Optional[Options] = None, prepare: bool = True, **overrides):
+    """Build a Sim from a workload description (rest, tets, pinned, materials...)."""
+    if "gravity" not in overrides:
+        overrides["gravity"] = tuple(w.gravity)
+    s = Sim(options, **overrides)
+    s.set_mesh(w.rest, w.tets)
+    s.set_pinned(w.pinned)
+    mats = []
+    for m in w.materials:
+        mats.append(dict(type=m.type, mu=m.mu, lam=m.lam, density=m.density,
+                         spline_d2=m.d2() if hasattr(m, "d2") else None))
+    s.set_materials(mats, w.tet_mat)
+    if prepare:
+        s.prepare(w.h)
+    else:
+        s.analyze(w.h)
+    return s

@@ -1,0 +1,226 @@
+"""GPU parity: the HIP path against the FP64 oracle, through the C ABI.
+
+Tolerances (FP64 everywhere on this path):
+* per-element Psi and P: 1e-11 of the largest magnitude (the spline material
+  goes through two different SVD algorithms);
+* objective g: 1e-12 relative; gradient: 1e-11 of its largest entry;
+* prefactored solve r = A^{-1} q: 1e-12 of the largest |r|;
+* trajectories: eps(N) = |x_gpu(N) - x_ora(N)|_2 / |x_ora(N) - X|_2 <= 1e-9
+  after every step (displacement-normalised, all vertices).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from oracle import fem
+
+torch = pytest.importorskip("torch")
+from paper_1604_07378_amd import qnsim  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+KINDS = [W.NEOHOOKEAN, W.STVK, W.SPLINE, W.COROTATED, W.POLYNOMIAL]
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def _model(w):
+    return oracle.build_model(w.rest, w.tets, w.pinned, w.materials, w.tet_mat, w.h, w.gravity)
+
+
+def _perturbed(w, amp, seed):
+    rng = np.random.default_rng(seed)
+    x = w.rest + amp * w.edge * rng.uniform(-1, 1, size=w.rest.shape)
+    x[w.pinned] = w.rest[w.pinned]
+    return x
+
+
+def _eps(x_gpu, x_ora, rest):
+    return np.linalg.norm(x_gpu - x_ora) / max(np.linalg.norm(x_ora - rest), 1e-300)
+
+
+def test_device_visible():
+    assert torch.cuda.is_available(), "no HIP device visible"
+    print("device:", torch.cuda.get_device_name(0), flush=True)
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_element_energy_and_stress(kind):
+    w = W.workload_cantilever(0, kind=kind)
+    s = qnsim.sim_from_workload(w)
+    m = _model(w)
+    x = _perturbed(w, 0.15, 1)
+    psi_ref, P_ref = fem.element_psi_P(m, x)
+    psi = torch.empty(w.n_tets, dtype=torch.float64, device="cuda")
+    P = torch.empty(w.n_tets, 9, dtype=torch.float64, device="cuda")
+    s.element_stress_device(_dev(x), psi, P)
+    torch.cuda.synchronize()
+    psi, P = psi.cpu().numpy(), P.cpu().numpy().reshape(-1, 3, 3)
+    assert np.abs(psi - psi_ref).max() <= 1e-11 * np.abs(psi_ref).max()
+    assert np.abs(P - P_ref).max() <= 1e-11 * np.abs(P_ref).max()
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_objective_and_gradient(kind):
+    w = W.workload_cantilever(0, kind=kind)
+    s = qnsim.sim_from_workload(w)
+    m = _model(w)
+    x = _perturbed(w, 0.1, 2)
+    y = _perturbed(w, 0.1, 3)
+    g_ref = fem.objective(m, x, y)
+    grad_ref = np.zeros_like(x)
+    grad_ref[m.free] = fem.gradient(m, x, y)
+    grad = torch.empty(w.n_verts, 3, dtype=torch.float64, device="cuda")
+    g = s.eval_device(_dev(x), _dev(y), grad)
+    grad = grad.cpu().numpy()
+    assert g == pytest.approx(g_ref, rel=1e-12)
+    assert np.abs(grad - grad_ref).max() <= 1e-11 * np.abs(grad_ref).max()
+
+
+@pytest.mark.parametrize("dims", [(10, 3, 3), (7, 5, 3), (1, 1, 1), (16, 14, 12)])
+def test_prefactored_solve(dims):
+    w = W.workload_cantilever(0, dims=dims)
+    s = qnsim.sim_from_workload(w)
+    m = _model(w)
+    q = np.random.default_rng(4).normal(size=(w.n_verts, 3))
+    r_ref = np.zeros_like(q)
+    r_ref[m.free] = m.solve(q[m.free])
+    r = torch.empty(w.n_verts, 3, dtype=torch.float64, device="cuda")
+    s.solve_device(_dev(q), r)
+    torch.cuda.synchronize()
+    r = r.cpu().numpy()
+    assert np.abs(r - r_ref).max() <= 1e-12 * np.abs(r_ref).max()
+
+
+def _trajectory_parity(w, steps, tol=1e-9, history=5, check_stats=True):
+    m = _model(w)
+    s = qnsim.sim_from_workload(w, history=history)
+    x_o, v_o = w.x0.copy(), w.v0.copy()
+    x_g, v_g = w.x0.copy(), w.v0.copy()
+    worst = 0.0
+    for k in range(steps):
+        r = oracle.step(m, x_o, v_o, history=history)
+        x_o, v_o = r.x, r.v
+        x_g, v_g, st = s.step(x_g, v_g, w.h)
+        e = _eps(x_g, x_o, w.rest)
+        worst = max(worst, e)
+        assert e <= tol, f"step {k}: eps {e:.3e}"
+        if check_stats:
+            assert st["iterations_run"] == r.iterations_run
+            assert st["ls_trials"] == r.ls_trials, f"step {k}"
+            assert st["lbfgs_skipped"] == r.lbfgs_skipped
+            assert st["g_last"] == pytest.approx(r.g_last, rel=1e-9)
+    return worst
+
+
+def test_cantilever_neohookean_100_steps():
+    """540-tet cantilever, Neo-Hookean E = 1e5, nu = 0.4, 100 steps from rest."""
+    w = W.workload_cantilever(0)
+    worst = _trajectory_parity(w, 100)
+    print(f"cantilever NH 100 steps: max eps {worst:.3e}", flush=True)
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_cantilever_other_jitter_seeds(seed):
+    _trajectory_parity(W.workload_cantilever(seed), 30)
+
+
+@pytest.mark.parametrize("kind", [W.STVK, W.SPLINE, W.COROTATED, W.POLYNOMIAL])
+def test_cantilever_materials(kind):
+    _trajectory_parity(W.workload_cantilever(0, kind=kind), 30)
+
+
+@pytest.mark.parametrize("history", [0, 1, 2, 8])
+def test_history_window(history):
+    _trajectory_parity(W.workload_cantilever(0), 20, history=history)
+
+
+def test_ragged_small_meshes():
+    for dims in [(1, 1, 1), (2, 1, 1), (5, 2, 1)]:
+        _trajectory_parity(W.workload_cantilever(0, dims=dims), 10)
+
+
+def test_per_element_young_modulus():
+    w = W.workload_mixed_cantilever(0)
+    _trajectory_parity(w, 20)
+
+
+def test_determinism():
+    w = W.workload_cantilever(0)
+    s = qnsim.sim_from_workload(w)
+    outs = []
+    for _ in range(2):
+        x, v = w.x0.copy(), w.v0.copy()
+        for _ in range(5):
+            x, v, _st = s.step(x, v, w.h)
+        outs.append(x)
+    assert np.array_equal(outs[0], outs[1])
+
+
+def test_device_entry_points_agree_with_host_entry_point():
+    w = W.workload_cantilever(0)
+    s = qnsim.sim_from_workload(w)
+    x, v = w.x0.copy(), w.v0.copy()
+    for _ in range(3):
+        x, v, _ = s.step(x, v, w.h)
+    xd, vd = _dev(w.x0), _dev(w.v0)
+    for _ in range(3):
+        s.step_device(xd, vd, w.h)
+    torch.cuda.synchronize()
+    assert np.array_equal(xd.cpu().numpy(), x)
+    xr, vr = _dev(w.x0), _dev(w.v0)
+    s.run_device(xr, vr, w.h, 3)
+    torch.cuda.synchronize()
+    assert np.array_equal(xr.cpu().numpy(), x)
+
+
+def test_step_errors():
+    w = W.workload_cantilever(0)
+    s = qnsim.sim_from_workload(w)
+    with pytest.raises(qnsim.QnsimError) as e:
+        s.step(w.x0, w.v0, w.h * 2)
+    assert e.value.code == -7
+    bad = w.x0.copy()
+    bad[100] = bad[100] + np.array([0.0, 0.0, -0.5])   # flips tets through each other
+    with pytest.raises(qnsim.QnsimError) as e:
+        s.step(bad, w.v0, w.h)
+    assert e.value.code == -4
+    nanx = w.x0.copy()
+    nanx[3, 1] = np.nan
+    with pytest.raises(qnsim.QnsimError) as e:
+        s.step(nanx, w.v0, w.h)
+    assert e.value.code == -2
+    x, v, st = s.step(w.x0, w.v0, w.h)           # context still usable
+    assert st["iterations_run"] == 10
+
+
+def test_infeasible_inertial_target_falls_back():
+    """A fast vertex makes y invert a Neo-Hookean tet: x_1 := x (host path)."""
+    w = W.workload_cantilever(0, dims=(3, 2, 2))
+    m = _model(w)
+    v = np.zeros_like(w.rest)
+    v[m.free[0]] = [0.0, 0.0, -300.0]
+    r = oracle.step(m, w.rest, v)
+    s = qnsim.sim_from_workload(w)
+    x, vv, st = s.step(w.rest, v, w.h)
+    assert st["fallbacks"] == r.fallbacks >= 1
+    assert _eps(x, r.x, w.rest) <= 1e-9
+
+
+@pytest.mark.parametrize("kind", [W.NEOHOOKEAN, W.STVK, W.SPLINE])
+def test_block_first_step_full_size(kind):
+    """The 40^3 block (384,000 tets) at full size, in the benchmark's launch
+    configuration: one time step against the oracle (banded LAPACK solve)."""
+    w = W.workload_block(kind, n=40)
+    s = qnsim.sim_from_workload(w)
+    m = _model(w)
+    r = oracle.step(m, w.x0, w.v0)
+    x, v, st = s.step(w.x0, w.v0, w.h)
+    e = _eps(x, r.x, w.rest)
+    print(f"block {W.MATERIAL_NAMES[kind]}: eps {e:.3e} trials {st['ls_trials']} / {r.ls_trials}",
+          flush=True)
+    assert e <= 1e-9
+    assert st["ls_trials"] == r.ls_trials
