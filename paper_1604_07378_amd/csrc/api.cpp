@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cstdlib>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -242,8 +243,6 @@ int upload_impl(qnsim_t* c) {
   const Factor& F = c->factor;
   const int n = c->n, T = c->T, nf = c->nf;
   D.device = c->opt.device;
-  if (hipSetDevice(D.device) != hipSuccess)
-    return fail(c, QNSIM_E_DEVICE, "hipSetDevice failed (no GPU?)");
   D.n = n; D.nf = nf; D.T = T; D.h = c->h;
   D.nmat = (int)c->mats.size();
   D.single_type = c->single_type;
@@ -284,6 +283,149 @@ int upload_impl(qnsim_t* c) {
         if (v < nf) inc_idx[fill[v]++] = 4 * t + a;
       }
   }
+  // supernodal solve: packed blocks (row-major forward copy, column-major
+  // backward copy), work items in topological order, assembly lists
+  const int ns = (int)F.sn.size();
+  auto pow2ceil = [](int v) { int p = 1; while (p < v) p <<= 1; return p; };
+  auto clampi = [](int v, int lo, int hi) { return std::max(lo, std::min(hi, v)); };
+  std::vector<SnInfo> sinfo(ns);
+  std::vector<int64_t> poff(ns + 1, 0);
+  for (int s = 0; s < ns; ++s) {
+    const Supernode& S = F.sn[s];
+    poff[s + 1] = poff[s] + (int64_t)S.ncol * (S.ncol + 1) / 2 + (int64_t)S.nbelow * S.ncol;
+  }
+  std::vector<double> Bf(poff[ns]), Bb(poff[ns]);
+  std::vector<int4> fwl, bwl;
+  std::vector<std::vector<int4>> fw_by_level(F.nlevels), bw_by_level(F.nlevels);
+  for (int s = 0; s < ns; ++s) {
+    const Supernode& S = F.sn[s];
+    const int nc = S.ncol, m = S.m();
+    const double* blk = F.Binv.data() + S.val_off;
+    double* bf = Bf.data() + poff[s];
+    double* bb = Bb.data() + poff[s];
+    for (int r = 0; r < m; ++r) {
+      const int len = r < nc ? r + 1 : nc;
+      const int64_t ro = r < nc ? (int64_t)r * (r + 1) / 2
+                                : (int64_t)nc * (nc + 1) / 2 + (int64_t)(r - nc) * nc;
+      for (int c = 0; c < len; ++c) bf[ro + c] = blk[r + (size_t)c * m];
+    }
+    for (int c = 0; c < nc; ++c) {
+      const int64_t co = (int64_t)c * m - (int64_t)c * (c - 1) / 2;
+      for (int i = c; i < m; ++i) bb[co + (i - c)] = blk[i + (size_t)c * m];
+    }
+    SnInfo& I = sinfo[s];
+    I.first = S.first; I.ncol = nc; I.nbelow = S.nbelow; I.parent = S.parent;
+    I.nchild = F.child_ptr[s + 1] - F.child_ptr[s];
+    I.fw_off = poff[s]; I.bw_off = poff[s];
+    I.rows_off = S.rows_off; I.vp_in = 0; I.vp_out = -1;
+    // forward items: groups of Lf lanes per row, up to 4 rows per group
+    const int Lf = clampi(pow2ceil((nc + 3) / 4), 4, 64), sf = 4 * (64 / Lf);
+    const int rpg_f = clampi(((16384 + nc - 1) / nc + sf - 1) / sf, 1, 4);
+    const int rows_item = sf * rpg_f;
+    for (int r0 = 0; r0 < m; r0 += rows_item)
+      fw_by_level[S.level].push_back(make_int4(s, r0, std::min(m, r0 + rows_item), Lf));
+    I.fw_items = (m + rows_item - 1) / rows_item;
+    // backward items: groups of Lb lanes per column, up to 4 columns per group
+    const int Lb = clampi(pow2ceil((m + 3) / 4), 4, 64), sb = 4 * (64 / Lb);
+    const int rpg_b = clampi(((16384 + m - 1) / m + sb - 1) / sb, 1, 4);
+    const int cols_item = sb * rpg_b;
+    for (int c0 = 0; c0 < nc; c0 += cols_item)
+      bw_by_level[S.level].push_back(
+          make_int4((int)(0x80000000u | (unsigned)s), c0, std::min(nc, c0 + cols_item), Lb));
+    I.bw_items = (nc + cols_item - 1) / cols_item;
+  }
+  // child slots: supernode P owns nchild(P) slots of m(P) x 3 doubles; the
+  // j-th child writes its update rows into slot j at its relative positions
+  int64_t vp_total = 0;
+  for (int s = 0; s < ns; ++s) {
+    SnInfo& I = sinfo[s];
+    I.vp_in = vp_total;
+    vp_total += (int64_t)I.nchild * 3 * (I.ncol + I.nbelow);
+  }
+  for (int s = 0; s < ns; ++s)
+    for (int e = F.child_ptr[s]; e < F.child_ptr[s + 1]; ++e)
+      sinfo[F.children[e]].vp_out =
+          sinfo[s].vp_in + (int64_t)(e - F.child_ptr[s]) * 3 * (sinfo[s].ncol + sinfo[s].nbelow);
+  for (int s = 0; s < ns; ++s) {
+    SnInfo& I = sinfo[s];
+    I.child_items = 0;
+    for (int e = F.child_ptr[s]; e < F.child_ptr[s + 1]; ++e) I.child_items += sinfo[F.children[e]].fw_items;
+  }
+  D.levels.assign(F.nlevels, Level{0, 0, 0, 0});
+  for (int l = 0; l < F.nlevels; ++l) {
+    D.levels[l].fw_begin = (int)fwl.size();
+    fwl.insert(fwl.end(), fw_by_level[l].begin(), fw_by_level[l].end());
+    D.levels[l].fw_end = (int)fwl.size();
+  }
+  for (int l = F.nlevels - 1; l >= 0; --l) {
+    D.levels[l].bw_begin = (int)fwl.size();
+    fwl.insert(fwl.end(), bw_by_level[l].begin(), bw_by_level[l].end());
+    D.levels[l].bw_end = (int)fwl.size();
+  }
+  // Self-check of the solve schedule before anything reaches the device:
+  // item ranges inside their supernode and within the 4 rows/columns per lane
+  // group the kernel handles, every row and column covered exactly once,
+  // packed offsets, row lists and assembly indices inside their arrays.
+  {
+    std::vector<int> cover_r(ns, 0), cover_c(ns, 0);
+    for (const int4& it : fwl) {
+      const bool bwd = it.x < 0;
+      const int s = it.x & 0x7fffffff;
+      if (s < 0 || s >= ns) return fail(c, QNSIM_E_DEVICE, "schedule: bad supernode");
+      const SnInfo& I = sinfo[s];
+      const int lim = bwd ? I.ncol : I.ncol + I.nbelow;
+      if (it.y < 0 || it.z > lim || it.y >= it.z || it.w < 4 || it.w > 64 || (64 % it.w) != 0 ||
+          it.z - it.y > 4 * 4 * (64 / it.w))
+        return fail(c, QNSIM_E_DEVICE, "schedule: bad item range");
+      (bwd ? cover_c : cover_r)[s] += it.z - it.y;
+    }
+    for (int s = 0; s < ns; ++s) {
+      const SnInfo& I = sinfo[s];
+      if (cover_r[s] != I.ncol + I.nbelow || cover_c[s] != I.ncol)
+        return fail(c, QNSIM_E_DEVICE, "schedule: rows or columns not covered once");
+      if (I.fw_off + (int64_t)I.ncol * (I.ncol + 1) / 2 + (int64_t)I.nbelow * I.ncol > (int64_t)Bf.size())
+        return fail(c, QNSIM_E_DEVICE, "schedule: block offset out of range");
+      if (I.rows_off + I.nbelow > (int64_t)F.rows.size() || I.first < 0 || I.first + I.ncol > nf ||
+          I.vp_in < 0 || I.vp_in + (int64_t)I.nchild * 3 * (I.ncol + I.nbelow) > vp_total ||
+          (I.parent >= 0) != (I.vp_out >= 0) ||
+          (I.parent >= 0 && (I.vp_out < sinfo[I.parent].vp_in ||
+                             I.vp_out + 3 * (int64_t)(sinfo[I.parent].ncol + sinfo[I.parent].nbelow) >
+                                 sinfo[I.parent].vp_in + (int64_t)sinfo[I.parent].nchild * 3 *
+                                     (sinfo[I.parent].ncol + sinfo[I.parent].nbelow))) ||
+          (I.parent < 0 && I.nbelow != 0))
+        return fail(c, QNSIM_E_DEVICE, "schedule: row list or update offset out of range");
+      for (int r = 0; r < I.nbelow; ++r) {
+        int g = F.rows[I.rows_off + r];
+        if (g < I.first + I.ncol || g >= nf) return fail(c, QNSIM_E_DEVICE, "schedule: bad row");
+      }
+      if (I.parent >= 0) {
+        const SnInfo& P = sinfo[I.parent];
+        for (int r = 0; r < I.nbelow; ++r) {
+          const int pos = F.rel[I.rows_off + r];
+          if (pos < 0 || pos >= P.ncol + P.nbelow || (r > 0 && pos <= F.rel[I.rows_off + r - 1]))
+            return fail(c, QNSIM_E_DEVICE, "schedule: bad relative row");
+        }
+      }
+      if (I.parent >= ns) return fail(c, QNSIM_E_DEVICE, "schedule: bad parent");
+    }
+    // topological order: forward items of a supernode come after those of its
+    // children, backward items after those of its parent and after all forward items
+    std::vector<int> last_fw(ns, -1), first_fw(ns, 1 << 30), first_bw(ns, 1 << 30), last_bw(ns, -1);
+    for (int i = 0; i < (int)fwl.size(); ++i) {
+      const int s = fwl[i].x & 0x7fffffff;
+      if (fwl[i].x < 0) { first_bw[s] = std::min(first_bw[s], i); last_bw[s] = i; }
+      else { first_fw[s] = std::min(first_fw[s], i); last_fw[s] = i; }
+    }
+    for (int s = 0; s < ns; ++s) {
+      const int p = sinfo[s].parent;
+      if (p >= 0 && !(last_fw[s] < first_fw[p] && last_bw[p] < first_bw[s]))
+        return fail(c, QNSIM_E_DEVICE, "schedule: items not in topological order");
+      if (p < 0 && !(last_fw[s] < first_bw[s])) return fail(c, QNSIM_E_DEVICE, "schedule: root order");
+    }
+  }
+  // host-side construction done: select the device and upload
+  if (hipSetDevice(D.device) != hipSuccess)
+    return fail(c, QNSIM_E_DEVICE, "hipSetDevice failed (no GPU?)");
   UP(D.tv, tv);
   UP(D.Bm, Bm);
   UP(D.vol, vol);
@@ -294,47 +436,18 @@ int upload_impl(qnsim_t* c) {
   UP(D.inc_idx, inc_idx);
   UP(D.vperm, c->vperm);
   UP(D.tperm, c->tperm);
-  // supernodal solve data and level work lists
-  const int ns = (int)F.sn.size();
-  std::vector<int> sfirst(ns), sncol(ns), snb(ns);
-  std::vector<int64_t> sval(ns), srows(ns), supd(ns);
-  for (int s = 0; s < ns; ++s) {
-    const Supernode& S = F.sn[s];
-    sfirst[s] = S.first; sncol[s] = S.ncol; snb[s] = S.nbelow;
-    sval[s] = S.val_off; srows[s] = S.rows_off; supd[s] = S.upd_off;
-    D.max_m = std::max(D.max_m, S.m());
-    D.max_nc = std::max(D.max_nc, S.ncol);
-  }
-  std::vector<int2> fw, bw;
-  D.levels.assign(F.nlevels, Level{0, 0, 0, 0});
-  for (int l = 0; l < F.nlevels; ++l) {
-    D.levels[l].fw_begin = (int)fw.size();
-    D.levels[l].bw_begin = (int)bw.size();
-    for (int s = 0; s < ns; ++s) {
-      if (F.sn[s].level != l) continue;
-      const int m = F.sn[s].m(), nc = F.sn[s].ncol;
-      for (int r = 0; r < (m + 63) / 64; ++r) fw.push_back(make_int2(s, r));
-      for (int cb = 0; cb < (nc + 15) / 16; ++cb) bw.push_back(make_int2(s, cb));
-    }
-    D.levels[l].fw_end = (int)fw.size();
-    D.levels[l].bw_end = (int)bw.size();
-  }
-  UP(D.blk, F.Binv);
-  UP(D.sn_first, sfirst);
-  UP(D.sn_ncol, sncol);
-  UP(D.sn_nbelow, snb);
-  UP(D.sn_val, sval);
-  UP(D.sn_rows, srows);
-  UP(D.sn_upd, supd);
-  UP(D.sn_cptr, F.child_ptr);
-  UP(D.sn_child, F.children);
+  D.nsn = ns;
+  D.n_items = (int)fwl.size();
+  UP(D.sn, sinfo);
+  UP(D.items, fwl);
+  UP(D.Bf, Bf);
+  UP(D.Bb, Bb);
   UP(D.rows, F.rows);
   UP(D.rel, F.rel);
-  UP(D.fw_items, fw);
-  UP(D.bw_items, bw);
+
   {
-    std::vector<double> z(3 * (size_t)F.upd_total + 1, 0.0);
-    UP(D.upd, z);
+    std::vector<double> zv((size_t)vp_total + 3, 0.0);  // zero once: see child slots
+    UP(D.vp, zv);
   }
   std::string err;
   int rc = dev_alloc(D, err);

@@ -44,8 +44,19 @@ struct Ctl {
 };
 
 struct Level {
-  int fw_begin, fw_end;  // forward work items
-  int bw_begin, bw_end;  // backward work items
+  int fw_begin, fw_end;  // forward work items of this level
+  int bw_begin, bw_end;  // backward work items of this level
+};
+
+// Per-supernode data of the device triangular solves.
+struct SnInfo {
+  int first, ncol, nbelow, parent;
+  int nchild, fw_items, bw_items, child_items;  // child_items: forward items of all children
+  long long fw_off;    // row-major packed [L11^{-1}; L21 L11^{-1}] (forward sweep)
+  long long bw_off;    // column-major packed, same blocks (backward sweep)
+  long long rows_off;  // below-diagonal row list (and positions in the parent)
+  long long vp_in;     // this supernode's child slots: nchild x (m x 3) doubles
+  long long vp_out;    // where this supernode writes its update rows (parent slot)
 };
 
 struct DeviceMesh {
@@ -64,16 +75,16 @@ struct DeviceMesh {
   int* inc_idx = nullptr;     // (tet * 4 + slot) per incidence
   int* vperm = nullptr;       // n: internal -> caller vertex
   int* tperm = nullptr;       // T: internal -> caller tet
-  // supernodal solve
-  double* blk = nullptr;
-  int* sn_first = nullptr; int* sn_ncol = nullptr; int* sn_nbelow = nullptr;
-  int64_t* sn_val = nullptr; int64_t* sn_rows = nullptr; int64_t* sn_upd = nullptr;
-  int* sn_cptr = nullptr; int* sn_child = nullptr;
-  int* rows = nullptr; int* rel = nullptr;
-  int2* fw_items = nullptr; int2* bw_items = nullptr;
-  std::vector<Level> levels;
-  double* upd = nullptr;
-  int max_m = 0, max_nc = 0;
+  // supernodal solve (one launch per tree level and sweep)
+  int nsn = 0, n_items = 0;
+  SnInfo* sn = nullptr;
+  int4* items = nullptr;      // (supernode | bwd flag, begin, end, lanes per row/column)
+  double* Bf = nullptr;       // forward blocks, row-major packed
+  double* Bb = nullptr;       // backward blocks, column-major packed
+  int* rows = nullptr;        // below-diagonal rows of each supernode
+  int* rel = nullptr;         // position of each below row in the parent's rows
+  double* vp = nullptr;       // children's update vectors in their parents' row space
+  std::vector<Level> levels;  // item ranges per tree level
   // solver vectors (internal order, 3 doubles per vertex)
   double* x0 = nullptr;       // n x 3 input positions
   double* v0 = nullptr;       // n x 3 input velocities
@@ -103,6 +114,9 @@ struct StepParams {
   double grav[3];
   double h;
 };
+
+// Prefactored solve r = A^{-1} q on the stream (internal order, nf x 3).
+void launch_solve(DeviceMesh& D, hipStream_t st, const double* q, double* r, const Ctl* ctl);
 
 // All launchers return 0 or a negative QNSIM_E_* code; err receives a message.
 int dev_alloc(DeviceMesh& d, std::string& err);

@@ -32,9 +32,6 @@ namespace qn {
 namespace {
 
 constexpr int BS = 256;          // threads per block of every kernel
-constexpr int FW_ROWS = 64;      // rows of a forward-solve work item
-constexpr int BW_COLS = 16;      // columns of a backward-solve work item
-constexpr int CHUNK = 1024;      // LDS staging chunk (entries x 3 doubles)
 
 #define HIP_OK(expr)                                                              \
   do {                                                                            \
@@ -318,7 +315,9 @@ k_pair_decide(int k, int m, int slots, const double* __restrict__ part, int nb, 
   if (threadIdx.x != 0 || !ctl_run(ctl)) return;
   if (k == 0) {
     ctl->gnorm2_first = gg;
-  } else if (m > 0 && ts > 1e-10 * sqrt(ss) * sqrt(tt)) {
+  } else if (m == 0) {
+    // no history window: pairs are never stored, nor counted as skipped
+  } else if (ts > 1e-10 * sqrt(ss) * sqrt(tt)) {
     ctl->newest = ctl->cand;
     ctl->rho[ctl->cand] = ts;
     ctl->npairs = ctl->npairs < m ? ctl->npairs + 1 : m;
@@ -454,163 +453,6 @@ k_ls_decide(int k, int last_in_budget, int max_halvings, double gamma, double ba
     if (last_in_budget) {
       ctl->need_host = 1;
       ctl->host_reason = 1;
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Triangular solves with the partitioned-inverse supernodal factor.
-// Forward (leaves to root): for supernode S with children C,
-//   t_S = q_S - sum_C v_C|_S,   z_S = L11^{-1} t_S,
-//   v_S = (L21 L11^{-1}) t_S + sum_C v_C|_{rows below S}.
-// Backward (root to leaves): w_S = L11^{-T} z_S - (L21 L11^{-1})^T w_{rows below S}.
-// One launch per tree level; a forward work item is (S, 64-row block), a
-// backward work item is (S, 16-column block).
-// ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(BS)
-k_fwd(const int2* __restrict__ items, const int* __restrict__ sn_first,
-      const int* __restrict__ sn_ncol, const int* __restrict__ sn_nbelow,
-      const int64_t* __restrict__ sn_val, const int64_t* __restrict__ sn_rows,
-      const int64_t* __restrict__ sn_upd, const int* __restrict__ cptr,
-      const int* __restrict__ child, const int* __restrict__ rel,
-      const double* __restrict__ blk, const double* __restrict__ q, double* __restrict__ z,
-      double* __restrict__ upd, const Ctl* __restrict__ ctl) {
-  __shared__ double t3[3][CHUNK];
-  __shared__ double pt[3][FW_ROWS];
-  __shared__ double red[3][4][FW_ROWS];
-  if (ctl && !ctl_run(ctl)) return;
-  const int2 it = items[blockIdx.x];
-  const int s = it.x;
-  const int first = sn_first[s], nc = sn_ncol[s], nb = sn_nbelow[s];
-  const int m = nc + nb;
-  const int r0 = it.y * FW_ROWS;
-  const int r1 = min(m, r0 + FW_ROWS);
-  const double* __restrict__ B = blk + sn_val[s];
-  const int tid = threadIdx.x;
-  const int lane = tid & 63, w = tid >> 6;
-  const int row = r0 + lane;
-  if (tid < FW_ROWS) { pt[0][tid] = 0.0; pt[1][tid] = 0.0; pt[2][tid] = 0.0; }
-  double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
-  // columns are processed in chunks that fit in LDS
-  const int cmax = min(nc, r1);  // rows < nc only need columns <= row
-  for (int c0 = 0; c0 < nc; c0 += CHUNK) {
-    const int c1 = min(nc, c0 + CHUNK);
-    __syncthreads();
-    for (int c = c0 + tid; c < c1; c += BS) {
-      t3[0][c - c0] = q[3 * (size_t)(first + c) + 0];
-      t3[1][c - c0] = q[3 * (size_t)(first + c) + 1];
-      t3[2][c - c0] = q[3 * (size_t)(first + c) + 2];
-    }
-    __syncthreads();
-    // subtract the children's update vectors (children in fixed order; rows of
-    // one child are distinct, so threads never collide)
-    for (int e = cptr[s]; e < cptr[s + 1]; ++e) {
-      const int ch = child[e];
-      const int cnb = sn_nbelow[ch];
-      const int* __restrict__ rl = rel + sn_rows[ch];
-      const double* __restrict__ u = upd + sn_upd[ch];
-      for (int a = tid; a < cnb; a += BS) {
-        const int pos = rl[a];
-        if (pos >= c0 && pos < c1) {
-          t3[0][pos - c0] -= u[3 * a + 0];
-          t3[1][pos - c0] -= u[3 * a + 1];
-          t3[2][pos - c0] -= u[3 * a + 2];
-        } else if (c0 == 0 && pos >= nc && pos >= r0 && pos < r1) {
-          pt[0][pos - r0] += u[3 * a + 0];
-          pt[1][pos - r0] += u[3 * a + 1];
-          pt[2][pos - r0] += u[3 * a + 2];
-        }
-      }
-      __syncthreads();
-    }
-    // out[row] += sum_c B[row, c] t[c], wave w takes columns c = c0 + w (mod 4)
-    if (row < r1) {
-      const int cend = (row < nc) ? min(c1, row + 1) : c1;
-      for (int c = c0 + w; c < cend; c += 4) {
-        const double b = B[(size_t)c * m + row];
-        acc0 += b * t3[0][c - c0];
-        acc1 += b * t3[1][c - c0];
-        acc2 += b * t3[2][c - c0];
-      }
-    }
-    (void)cmax;
-  }
-  red[0][w][lane] = acc0;
-  red[1][w][lane] = acc1;
-  red[2][w][lane] = acc2;
-  __syncthreads();
-  if (tid < FW_ROWS && row < r1) {
-    double o[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) o[c] = (red[c][0][tid] + red[c][1][tid]) + (red[c][2][tid] + red[c][3][tid]);
-    if (row < nc) {
-#pragma unroll
-      for (int c = 0; c < 3; ++c) z[3 * (size_t)(first + row) + c] = o[c];
-    } else {
-      double* __restrict__ u = upd + sn_upd[s] + 3 * (size_t)(row - nc);
-#pragma unroll
-      for (int c = 0; c < 3; ++c) u[c] = o[c] + pt[c][tid];
-    }
-  }
-}
-
-__global__ void __launch_bounds__(BS)
-k_bwd(const int2* __restrict__ items, const int* __restrict__ sn_first,
-      const int* __restrict__ sn_ncol, const int* __restrict__ sn_nbelow,
-      const int64_t* __restrict__ sn_val, const int64_t* __restrict__ sn_rows,
-      const int* __restrict__ rows, const double* __restrict__ blk,
-      const double* __restrict__ z, double* __restrict__ wv, const Ctl* __restrict__ ctl) {
-  __shared__ double u3[3][CHUNK];
-  if (ctl && !ctl_run(ctl)) return;
-  const int2 it = items[blockIdx.x];
-  const int s = it.x;
-  const int first = sn_first[s], nc = sn_ncol[s], nb = sn_nbelow[s];
-  const int m = nc + nb;
-  const int cb0 = it.y * BW_COLS;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const double* __restrict__ B = blk + sn_val[s];
-  const int* __restrict__ rw = rows + sn_rows[s];
-  // wave w owns columns cb0 + w*4 .. cb0 + w*4 + 3
-  double acc[4][3];
-#pragma unroll
-  for (int a = 0; a < 4; ++a) acc[a][0] = acc[a][1] = acc[a][2] = 0.0;
-  for (int i0 = cb0; i0 < m; i0 += CHUNK) {  // rows < cb0 never contribute
-    const int i1 = min(m, i0 + CHUNK);
-    __syncthreads();
-    for (int i = i0 + tid; i < i1; i += BS) {
-      if (i < nc) {
-        u3[0][i - i0] = z[3 * (size_t)(first + i) + 0];
-        u3[1][i - i0] = z[3 * (size_t)(first + i) + 1];
-        u3[2][i - i0] = z[3 * (size_t)(first + i) + 2];
-      } else {
-        const int g = rw[i - nc];
-        u3[0][i - i0] = -wv[3 * (size_t)g + 0];
-        u3[1][i - i0] = -wv[3 * (size_t)g + 1];
-        u3[2][i - i0] = -wv[3 * (size_t)g + 2];
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      const int c = cb0 + w * 4 + a;
-      if (c >= nc) break;
-      const double* __restrict__ col = B + (size_t)c * m;
-      for (int i = max(i0, c) + lane; i < i1; i += 64) {
-        const double b = col[i];
-        acc[a][0] += b * u3[0][i - i0];
-        acc[a][1] += b * u3[1][i - i0];
-        acc[a][2] += b * u3[2][i - i0];
-      }
-    }
-  }
-#pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    const int c = cb0 + w * 4 + a;
-    double r0 = wave_sum(acc[a][0]), r1 = wave_sum(acc[a][1]), r2 = wave_sum(acc[a][2]);
-    if (lane == 0 && c < nc) {
-      wv[3 * (size_t)(first + c) + 0] = r0;
-      wv[3 * (size_t)(first + c) + 1] = r1;
-      wv[3 * (size_t)(first + c) + 2] = r2;
     }
   }
 }
@@ -754,25 +596,6 @@ void launch_elem(DeviceMesh& D, hipStream_t st, int mode, const double* X, doubl
 #undef QN_ELEM
 }
 
-void launch_solve(DeviceMesh& D, hipStream_t st, const double* q, double* r, const Ctl* ctl) {
-  const int L = (int)D.levels.size();
-  for (int l = 0; l < L; ++l) {
-    const Level& lv = D.levels[l];
-    int n = lv.fw_end - lv.fw_begin;
-    if (n > 0)
-      hipLaunchKernelGGL(k_fwd, dim3(n), dim3(BS), 0, st, D.fw_items + lv.fw_begin, D.sn_first,
-                         D.sn_ncol, D.sn_nbelow, D.sn_val, D.sn_rows, D.sn_upd, D.sn_cptr,
-                         D.sn_child, D.rel, D.blk, q, D.z, D.upd, ctl);
-  }
-  for (int l = L - 1; l >= 0; --l) {
-    const Level& lv = D.levels[l];
-    int n = lv.bw_end - lv.bw_begin;
-    if (n > 0)
-      hipLaunchKernelGGL(k_bwd, dim3(n), dim3(BS), 0, st, D.bw_items + lv.bw_begin, D.sn_first,
-                         D.sn_ncol, D.sn_nbelow, D.sn_val, D.sn_rows, D.rows, D.blk, D.z, r, ctl);
-  }
-}
-
 // Partials layout: [0, 4*vb) gather values; two ping-pong dot buffers of vb;
 // gtd buffer of vb; element partials of elem_blocks.
 struct Parts {
@@ -854,8 +677,7 @@ int dev_sync(DeviceMesh& D, void* stream, std::string& err) {
 
 void dev_free(DeviceMesh& D) {
   void* ptrs[] = {D.tv, D.Bm, D.vol, D.tmat, D.mats, D.mass, D.inc_ptr, D.inc_idx, D.vperm,
-                  D.blk, D.sn_first, D.sn_ncol, D.sn_nbelow, D.sn_val, D.sn_rows, D.sn_upd,
-                  D.sn_cptr, D.sn_child, D.rows, D.rel, D.fw_items, D.bw_items, D.upd, D.x0,
+                  D.sn, D.items, D.Bf, D.Bb, D.rows, D.rel, D.vp, D.x0,
                   D.v0, D.y, D.X[0], D.X[1], D.G[0], D.G[1], D.d, D.q, D.z, D.Sv, D.Tv, D.fel,
                   D.part, D.psi, D.ctl, D.tperm};
   for (void* p : ptrs)

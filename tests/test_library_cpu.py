@@ -117,3 +117,18 @@ def test_errors_are_reported_not_raised_across_the_abi():
     s.set_pinned([0])
     s.analyze(1 / 30)
     assert s.factor_info()["n_free"] == 3
+
+
+@pytest.mark.parametrize("w", [W.workload_cantilever(0), W.workload_cantilever(0, dims=(1, 1, 1)),
+                               W.workload_block(W.SPLINE, n=12)],
+                         ids=["cantilever", "one-cube", "block12"])
+def test_solve_schedule_self_check_passes_on_host(w):
+    """qnsim_prepare builds the solve schedule and checks it on the host before
+    selecting a device; without a GPU it must get as far as hipSetDevice."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("GPU present: prepare succeeds instead")
+    s = qnsim.sim_from_workload(w, prepare=False)
+    with pytest.raises(qnsim.QnsimError) as e:
+        s.prepare(w.h)
+    assert "hipSetDevice" in str(e.value), str(e.value)
