@@ -69,19 +69,28 @@ typedef struct qnsim qnsim_t; /* opaque; owns all its host and device memory */
  * 10 iterations per step and L-BFGS window m = 5 (section 5, Table StatAll),
  * Armijo gamma = 0.3 and backtracking factor 0.5 (section 4.1), stiffness fit
  * interval [0.5, 1.5] (section 5), at most 30 halvings per line search,
- * gravity (0, 0, -9.81) m/s^2, FP64, device 0. */
+ * gravity (0, 0, -9.81) m/s^2, FP64, device 0, dense_top 6144,
+ * subtree_cap 384. */
 typedef struct {
   int32_t iterations;   /* quasi-Newton iterations per step (>= 1)           */
   int32_t history;      /* L-BFGS window m (0..16); 0 = plain PD direction   */
   int32_t max_halvings; /* line-search trials per iteration = max_halvings+1 */
   int32_t precision;    /* QNSIM_FP64 or QNSIM_MIXED                         */
   int32_t device;       /* HIP device ordinal                                */
-  int32_t reserved;
+  int32_t dense_top;    /* largest column count of the dense top block of the
+                           prefactored solve (0 = off, at most 6144); the
+                           top levels of the supernode tree are merged into
+                           it when a latency/bandwidth cost model favours it */
   double gamma;         /* Armijo constant in (0, 1)                         */
   double backtrack;     /* step-length factor after a failed trial, (0, 1)   */
   double fit_lo;        /* stiffness fit interval [fit_lo, fit_hi]           */
   double fit_hi;
   double gravity[3];    /* uniform body acceleration added to f_ext / m      */
+  int32_t subtree_cap;  /* the lowest levels of the supernode tree whose
+                           supernodes all have at most subtree_cap rows are
+                           solved one subtree per workgroup (0 = off, at
+                           most 384)                                        */
+  int32_t reserved;
 } qnsim_options;
 
 /* One material. mu, lambda in Pa; density in kg/m^3. For QNSIM_SPLINE,
@@ -119,6 +128,8 @@ typedef struct {
   int32_t n_supernodes;
   int32_t n_levels;       /* supernode tree height + 1                        */
   int32_t max_front;      /* largest supernode rows (columns + below-diag)    */
+  int32_t dense_top_cols; /* columns of the dense top block (0 if none)      */
+  int32_t subtree_levels; /* lowest levels solved one subtree per workgroup   */
   int64_t nnz_L;          /* stored factor entries (incl. explicit zeros)     */
   int64_t nnz_L_exact;    /* structural nonzeros of the Cholesky factor       */
   int64_t factor_bytes;   /* device bytes of the solve blocks                 */

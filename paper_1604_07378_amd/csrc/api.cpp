@@ -187,7 +187,7 @@ int analyze_impl(qnsim_t* c, double h) {
   std::vector<Ent>().swap(ents);
   for (int j = 0; j < nf; ++j) colptr[j + 1] += colptr[j];
   std::string err;
-  int rc = factorize(nf, colptr, rowidx, val, c->factor, err);
+  int rc = factorize(nf, colptr, rowidx, val, c->factor, err, c->opt.dense_top);
   if (rc == -1) return fail(c, QNSIM_E_NOT_SPD, err);
   if (rc != 0) return fail(c, QNSIM_E_DEVICE, err);
   // internal vertex order: free unknowns in factor order, then pinned vertices
@@ -289,20 +289,48 @@ int upload_impl(qnsim_t* c) {
   auto pow2ceil = [](int v) { int p = 1; while (p < v) p <<= 1; return p; };
   auto clampi = [](int v, int lo, int hi) { return std::max(lo, std::min(hi, v)); };
   std::vector<SnInfo> sinfo(ns);
-  std::vector<int64_t> poff(ns + 1, 0);
+  // packed offsets: the dense top block (if any) is stored in full in the
+  // forward array only; every other block is packed in both arrays
+  const int top = F.top;
+  std::vector<int64_t> pf(ns + 1, 0), pb(ns + 1, 0);
   for (int s = 0; s < ns; ++s) {
     const Supernode& S = F.sn[s];
-    poff[s + 1] = poff[s] + (int64_t)S.ncol * (S.ncol + 1) / 2 + (int64_t)S.nbelow * S.ncol;
+    const int64_t packed = (int64_t)S.ncol * (S.ncol + 1) / 2 + (int64_t)S.nbelow * S.ncol;
+    pf[s + 1] = pf[s] + (s == top ? (int64_t)S.ncol * S.ncol : packed);
+    pb[s + 1] = pb[s] + (s == top ? 0 : packed);
   }
-  std::vector<double> Bf(poff[ns]), Bb(poff[ns]);
+  std::vector<double> Bf(pf[ns]), Bb(pb[ns]);
   std::vector<int4> fwl, bwl;
   std::vector<std::vector<int4>> fw_by_level(F.nlevels), bw_by_level(F.nlevels);
+  // bottom subtrees: the lowest levels whose supernodes all have at most
+  // subtree_cap rows are solved by one workgroup per subtree
+  const int sparse_levels = top >= 0 ? F.sn[top].level : F.nlevels;
+  int Lsub = 0;
+  {
+    std::vector<int> maxm(F.nlevels, 0);
+    for (int s = 0; s < ns; ++s)
+      if (s != top) maxm[F.sn[s].level] = std::max(maxm[F.sn[s].level], F.sn[s].m());
+    const int cap = std::min(c->opt.subtree_cap, kSubCap);
+    while (Lsub < sparse_levels && maxm[Lsub] <= cap) ++Lsub;
+    if (Lsub < 2) Lsub = 0;
+  }
   for (int s = 0; s < ns; ++s) {
     const Supernode& S = F.sn[s];
     const int nc = S.ncol, m = S.m();
     const double* blk = F.Binv.data() + S.val_off;
-    double* bf = Bf.data() + poff[s];
-    double* bb = Bb.data() + poff[s];
+    SnInfo& I = sinfo[s];
+    I.first = S.first; I.ncol = nc; I.nbelow = S.nbelow; I.parent = S.parent;
+    I.nchild = F.child_ptr[s + 1] - F.child_ptr[s];
+    I.fw_off = pf[s]; I.bw_off = pb[s];
+    I.rows_off = S.rows_off; I.vp_in = 0; I.vp_out = -1;
+    if (s == top) {
+      // symmetric: the column-major block is also its row-major copy
+      std::copy(blk, blk + (size_t)nc * nc, Bf.data() + pf[s]);
+      I.fw_items = I.bw_items = 0;
+      continue;
+    }
+    double* bf = Bf.data() + pf[s];
+    double* bb = Bb.data() + pb[s];
     for (int r = 0; r < m; ++r) {
       const int len = r < nc ? r + 1 : nc;
       const int64_t ro = r < nc ? (int64_t)r * (r + 1) / 2
@@ -313,11 +341,10 @@ int upload_impl(qnsim_t* c) {
       const int64_t co = (int64_t)c * m - (int64_t)c * (c - 1) / 2;
       for (int i = c; i < m; ++i) bb[co + (i - c)] = blk[i + (size_t)c * m];
     }
-    SnInfo& I = sinfo[s];
-    I.first = S.first; I.ncol = nc; I.nbelow = S.nbelow; I.parent = S.parent;
-    I.nchild = F.child_ptr[s + 1] - F.child_ptr[s];
-    I.fw_off = poff[s]; I.bw_off = poff[s];
-    I.rows_off = S.rows_off; I.vp_in = 0; I.vp_out = -1;
+    if (S.level < Lsub) {
+      I.fw_items = I.bw_items = 0;  // one-wave items, built per subtree below
+      continue;
+    }
     // forward items: groups of Lf lanes per row, up to 4 rows per group
     const int Lf = clampi(pow2ceil((nc + 3) / 4), 4, 64), sf = 4 * (64 / Lf);
     const int rpg_f = clampi(((16384 + nc - 1) / nc + sf - 1) / sf, 1, 4);
@@ -351,6 +378,46 @@ int upload_impl(qnsim_t* c) {
     I.child_items = 0;
     for (int e = F.child_ptr[s]; e < F.child_ptr[s + 1]; ++e) I.child_items += sinfo[F.children[e]].fw_items;
   }
+  // subtree tasks: roots are bottom supernodes whose parent is not a bottom
+  // supernode; a subtree is a contiguous range of the postordered supernodes
+  std::vector<int4> sub_fw, sub_bw;
+  std::vector<int> sub_fw_ptr, sub_bw_ptr, task_of(ns, -1);
+  int n_tasks = 0;
+  if (Lsub > 0) {
+    std::vector<int> start(ns);
+    for (int s = 0; s < ns; ++s) {
+      start[s] = s;
+      for (int e = F.child_ptr[s]; e < F.child_ptr[s + 1]; ++e)
+        start[s] = std::min(start[s], start[F.children[e]]);
+    }
+    for (int R = 0; R < ns; ++R) {
+      const Supernode& SR = F.sn[R];
+      if (R == top || SR.level >= Lsub) continue;
+      if (SR.parent >= 0 && SR.parent != top && F.sn[SR.parent].level < Lsub) continue;
+      std::vector<std::vector<int4>> fw(Lsub), bw(Lsub);
+      for (int s = start[R]; s <= R; ++s) {
+        const Supernode& S = F.sn[s];
+        task_of[s] = n_tasks;
+        const int nc = S.ncol, m = S.m();
+        const int Lf = clampi(pow2ceil((nc + 3) / 4), 4, 64), rf = 4 * (64 / Lf);
+        for (int r0 = 0; r0 < m; r0 += rf)
+          fw[S.level].push_back(make_int4(s, r0, std::min(m, r0 + rf), Lf));
+        const int Lb = clampi(pow2ceil((m + 3) / 4), 4, 64), cb = 4 * (64 / Lb);
+        for (int c0 = 0; c0 < nc; c0 += cb)
+          bw[S.level].push_back(
+              make_int4((int)(0x80000000u | (unsigned)s), c0, std::min(nc, c0 + cb), Lb));
+      }
+      for (int l = 0; l < Lsub; ++l) {
+        sub_fw_ptr.push_back((int)sub_fw.size());
+        sub_fw.insert(sub_fw.end(), fw[l].begin(), fw[l].end());
+        sub_bw_ptr.push_back((int)sub_bw.size());
+        sub_bw.insert(sub_bw.end(), bw[l].begin(), bw[l].end());
+      }
+      sub_fw_ptr.push_back((int)sub_fw.size());
+      sub_bw_ptr.push_back((int)sub_bw.size());
+      ++n_tasks;
+    }
+  }
   D.levels.assign(F.nlevels, Level{0, 0, 0, 0});
   for (int l = 0; l < F.nlevels; ++l) {
     D.levels[l].fw_begin = (int)fwl.size();
@@ -379,11 +446,49 @@ int upload_impl(qnsim_t* c) {
         return fail(c, QNSIM_E_DEVICE, "schedule: bad item range");
       (bwd ? cover_c : cover_r)[s] += it.z - it.y;
     }
+    for (int t = 0; t < n_tasks; ++t) {
+      for (int pass = 0; pass < 2; ++pass) {
+        const std::vector<int>& ptr = pass ? sub_bw_ptr : sub_fw_ptr;
+        const std::vector<int4>& its = pass ? sub_bw : sub_fw;
+        for (int l = 0; l < Lsub; ++l) {
+          const int b = ptr[(size_t)t * (Lsub + 1) + l], e = ptr[(size_t)t * (Lsub + 1) + l + 1];
+          if (b > e || e > (int)its.size()) return fail(c, QNSIM_E_DEVICE, "schedule: bad subtree offsets");
+          for (int i = b; i < e; ++i) {
+            const int4 it = its[i];
+            const int s = it.x & 0x7fffffff;
+            if ((it.x < 0) != (pass == 1) || s < 0 || s >= ns || task_of[s] != t ||
+                F.sn[s].level != l)
+              return fail(c, QNSIM_E_DEVICE, "schedule: subtree item outside its task or level");
+            const SnInfo& I = sinfo[s];
+            const int lim = pass ? I.ncol : I.ncol + I.nbelow;
+            if (I.ncol + I.nbelow > kSubCap || it.y < 0 || it.z > lim || it.y >= it.z ||
+                it.w < 4 || it.w > 64 || (64 % it.w) != 0 || it.z - it.y > 4 * (64 / it.w))
+              return fail(c, QNSIM_E_DEVICE, "schedule: bad subtree item range");
+            (pass ? cover_c : cover_r)[s] += it.z - it.y;
+          }
+        }
+      }
+    }
+    for (int s = 0; s < ns; ++s) {
+      if (task_of[s] < 0) continue;
+      const int p = sinfo[s].parent;
+      // the parent is in the same subtree at a higher level, or outside every subtree
+      if (p >= 0 && !((task_of[p] == task_of[s] && F.sn[p].level > F.sn[s].level) ||
+                      (task_of[p] < 0 && (p == top || F.sn[p].level >= Lsub))))
+        return fail(c, QNSIM_E_DEVICE, "schedule: subtree parent order");
+    }
     for (int s = 0; s < ns; ++s) {
       const SnInfo& I = sinfo[s];
-      if (cover_r[s] != I.ncol + I.nbelow || cover_c[s] != I.ncol)
+      const bool is_top = s == top;
+      if (is_top ? (cover_r[s] != 0 || cover_c[s] != 0 || I.nbelow != 0 || I.parent >= 0 ||
+                    s != ns - 1 || I.ncol > kMaxDenseTop || I.first + I.ncol != nf)
+                 : (cover_r[s] != I.ncol + I.nbelow || cover_c[s] != I.ncol))
         return fail(c, QNSIM_E_DEVICE, "schedule: rows or columns not covered once");
-      if (I.fw_off + (int64_t)I.ncol * (I.ncol + 1) / 2 + (int64_t)I.nbelow * I.ncol > (int64_t)Bf.size())
+      if (I.fw_off + (is_top ? (int64_t)I.ncol * I.ncol
+                             : (int64_t)I.ncol * (I.ncol + 1) / 2 + (int64_t)I.nbelow * I.ncol) >
+              (int64_t)Bf.size() ||
+          (!is_top && I.bw_off + (int64_t)I.ncol * (I.ncol + 1) / 2 + (int64_t)I.nbelow * I.ncol >
+                          (int64_t)Bb.size()))
         return fail(c, QNSIM_E_DEVICE, "schedule: block offset out of range");
       if (I.rows_off + I.nbelow > (int64_t)F.rows.size() || I.first < 0 || I.first + I.ncol > nf ||
           I.vp_in < 0 || I.vp_in + (int64_t)I.nchild * 3 * (I.ncol + I.nbelow) > vp_total ||
@@ -416,8 +521,12 @@ int upload_impl(qnsim_t* c) {
       if (fwl[i].x < 0) { first_bw[s] = std::min(first_bw[s], i); last_bw[s] = i; }
       else { first_fw[s] = std::min(first_fw[s], i); last_fw[s] = i; }
     }
+    // the dense top block runs between the two sweeps: after every forward
+    // item and before every backward item
     for (int s = 0; s < ns; ++s) {
+      if (s == top) continue;
       const int p = sinfo[s].parent;
+      if (p == top) continue;
       if (p >= 0 && !(last_fw[s] < first_fw[p] && last_bw[p] < first_bw[s]))
         return fail(c, QNSIM_E_DEVICE, "schedule: items not in topological order");
       if (p < 0 && !(last_fw[s] < first_bw[s])) return fail(c, QNSIM_E_DEVICE, "schedule: root order");
@@ -438,8 +547,38 @@ int upload_impl(qnsim_t* c) {
   UP(D.tperm, c->tperm);
   D.nsn = ns;
   D.n_items = (int)fwl.size();
+  auto to_desc = [&](const std::vector<int4>& in) {
+    std::vector<ItemDesc> out(in.size());
+    for (size_t i = 0; i < in.size(); ++i) {
+      const int4 it = in[i];
+      const bool bwd = it.x < 0;
+      const SnInfo& I = sinfo[it.x & 0x7fffffff];
+      ItemDesc& d = out[i];
+      d.begin = it.y; d.end = it.z; d.L = it.w; d.nchild = I.nchild;
+      d.first = I.first; d.ncol = I.ncol; d.nbelow = I.nbelow; d.pad = 0;
+      d.blk = bwd ? I.bw_off : I.fw_off;
+      d.rows_off = I.rows_off; d.vp_in = I.vp_in; d.vp_out = I.vp_out;
+    }
+    return out;
+  };
+  D.sub_levels = n_tasks > 0 ? Lsub : 0;
+  D.sub_tasks = n_tasks;
+  if (n_tasks > 0) {
+    UP(D.sub_fw, to_desc(sub_fw));
+    UP(D.sub_bw, to_desc(sub_bw));
+    UP(D.sub_fw_ptr, sub_fw_ptr);
+    UP(D.sub_bw_ptr, sub_bw_ptr);
+  }
+  D.top_n = 0;
+  if (top >= 0) {
+    D.top_first = sinfo[top].first;
+    D.top_n = sinfo[top].ncol;
+    D.top_nch = sinfo[top].nchild;
+    D.top_vp = sinfo[top].vp_in;
+    D.top_off = sinfo[top].fw_off;
+  }
   UP(D.sn, sinfo);
-  UP(D.items, fwl);
+  UP(D.items, to_desc(fwl));
   UP(D.Bf, Bf);
   UP(D.Bb, Bb);
   UP(D.rows, F.rows);
@@ -472,6 +611,8 @@ int qnsim_options_default(qnsim_options* o) {
   o->max_halvings = 30;
   o->precision = QNSIM_FP64;
   o->device = 0;
+  o->dense_top = 6144;
+  o->subtree_cap = 384;
   o->gamma = 0.3;
   o->backtrack = 0.5;
   o->fit_lo = 0.5;
@@ -491,6 +632,8 @@ int qnsim_create(const qnsim_options* opts, qnsim_t** out) {
       o.max_halvings > 200 || !(o.gamma > 0 && o.gamma < 1) || !(o.backtrack > 0 && o.backtrack < 1) ||
       !(o.fit_hi > o.fit_lo) || !(o.fit_lo > 0) ||
       (o.precision != QNSIM_FP64 && o.precision != QNSIM_MIXED) ||
+      o.dense_top < 0 || o.dense_top > kMaxDenseTop || o.subtree_cap < 0 ||
+      o.subtree_cap > kSubCap ||
       !finite_all(o.gravity, 3))
     return QNSIM_E_INVALID;
   qnsim_t* c = new (std::nothrow) qnsim();
@@ -770,6 +913,8 @@ int qnsim_get_factor_info(const qnsim_t* c, qnsim_factor_info* info) {
   info->n_supernodes = (int)F.sn.size();
   info->n_levels = F.nlevels;
   info->max_front = F.max_front;
+  info->dense_top_cols = F.top >= 0 ? F.sn[F.top].ncol : 0;
+  info->subtree_levels = c->prepared ? c->dev.sub_levels : 0;
   info->nnz_L = F.nnz_stored;
   info->nnz_L_exact = F.nnz_exact;
   info->factor_bytes = (int64_t)F.Binv.size() * 8;

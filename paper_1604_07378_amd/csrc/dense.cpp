@@ -212,4 +212,78 @@ void gemm_nt_sub(int ma, int nb, int kk, const double* A, int lda, const double*
   parallel_for(ntiles, grain, &g, gemm_tiles);
 }
 
+namespace {
+struct GramArgs {
+  int n, nt;
+  const double* LT;  // transpose of Linv: LT[a + k n] = Linv[k, a]
+  double* S;
+};
+constexpr int TG = 64;
+
+void gram_tiles(const void* vctx, int64_t lo, int64_t hi) {
+  const GramArgs& g = *static_cast<const GramArgs*>(vctx);
+  const int n = g.n;
+  for (int64_t t = lo; t < hi; ++t) {
+    const int ta = (int)(t / g.nt), tb = (int)(t % g.nt);
+    if (tb > ta) continue;
+    const int a0 = ta * TG, b0 = tb * TG;
+    const int ma = std::min(TG, n - a0), nb = std::min(TG, n - b0);
+    const int k0 = a0;  // Linv[k, a] = 0 for k < a, and a >= a0 >= b0
+    const int kk = n - k0;
+    for (int bb = 0; bb < nb; bb += 4) {
+      const int nbb = std::min(4, nb - bb);
+      for (int aa = 0; aa < ma; aa += 8) {
+        const int maa = std::min(8, ma - aa);
+        const int ga = a0 + aa, gb = b0 + bb;
+        const double* Ap = g.LT + ga + (int64_t)k0 * n;
+        const double* Bp = g.LT + gb + (int64_t)k0 * n;
+        double* Cp = g.S + ga + (int64_t)gb * n;
+        if (maa == 8 && nbb == 4)
+          tile8x4(kk, Ap, n, Bp, n, Cp, n);
+        else
+          tile_generic(maa, nbb, kk, Ap, n, Bp, n, Cp, n, ga, gb, false);
+      }
+    }
+  }
+}
+
+struct TransArgs {
+  int n;
+  const double* src;
+  double* dst;
+};
+void transpose_cols(const void* vctx, int64_t lo, int64_t hi) {
+  const TransArgs& a = *static_cast<const TransArgs*>(vctx);
+  for (int64_t c = lo; c < hi; ++c)
+    for (int i = 0; i < a.n; ++i) a.dst[c + (int64_t)i * a.n] = a.src[i + c * a.n];
+}
+
+void mirror_cols(const void* vctx, int64_t lo, int64_t hi) {
+  const TransArgs& a = *static_cast<const TransArgs*>(vctx);
+  double* S = a.dst;
+  // lower part holds -S; write S to both triangles (column c: rows >= c)
+  for (int64_t c = lo; c < hi; ++c)
+    for (int i = (int)c; i < a.n; ++i) S[i + c * a.n] = -S[i + c * a.n];
+}
+void mirror_upper(const void* vctx, int64_t lo, int64_t hi) {
+  const TransArgs& a = *static_cast<const TransArgs*>(vctx);
+  double* S = a.dst;
+  for (int64_t c = lo; c < hi; ++c)
+    for (int i = 0; i < (int)c; ++i) S[i + c * a.n] = S[c + (int64_t)i * a.n];
+}
+}  // namespace
+
+void gram_of_lower_inverse(int n, const double* Linv, double* S) {
+  if (n <= 0) return;
+  std::vector<double> LT((size_t)n * n);
+  TransArgs tr{n, Linv, LT.data()};
+  parallel_for(n, 16, &tr, transpose_cols);
+  std::fill(S, S + (size_t)n * n, 0.0);
+  GramArgs g{n, (n + TG - 1) / TG, LT.data(), S};
+  parallel_for((int64_t)g.nt * g.nt, 1, &g, gram_tiles);
+  TransArgs m{n, nullptr, S};
+  parallel_for(n, 16, &m, mirror_cols);
+  parallel_for(n, 16, &m, mirror_upper);
+}
+
 }  // namespace qn

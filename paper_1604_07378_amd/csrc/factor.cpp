@@ -89,7 +89,7 @@ void inv_cols(const void* vctx, int64_t lo, int64_t hi) {
 }  // namespace
 
 int factorize(int n, const std::vector<int64_t>& colptr, const std::vector<int>& rowidx,
-              const std::vector<double>& val, Factor& f, std::string& err) {
+              const std::vector<double>& val, Factor& f, std::string& err, int dense_top_max) {
   f = Factor();
   f.n = n;
   if (n == 0) return 0;
@@ -242,6 +242,107 @@ int factorize(int n, const std::vector<int64_t>& colptr, const std::vector<int>&
     S.rep = p;
     std::vector<int>().swap(S.below);
   }
+  // ---- dense top block -------------------------------------------------------
+  // The highest levels of the supernode tree hold a few large separators, and
+  // each level costs the triangular solves two dependent phases. The
+  // supernodes at levels >= cut are merged into one dense root block T whose
+  // columns are renumbered to the end; that order is still a topological order
+  // of the elimination tree, so the fill of every other column is unchanged.
+  // For the root block the forward and backward sweeps combine into one
+  // product with the dense inverse of its Schur complement,
+  //     w_T = (L_TT L_TT^T)^{-1} t_T,
+  // which replaces 2 (levels above cut) dependent phases by two launches at
+  // the price of storing n_T^2 entries. The cut minimises a cost model of the
+  // solve: a fixed latency per phase plus streamed bytes at HBM bandwidth.
+  int top_rep = -1;
+  if (dense_top_max > 0) {
+    std::vector<int> kept;
+    for (int s = 0; s < nfund; ++s)
+      if (nodes[s].rep == -1) kept.push_back(s);
+    std::sort(kept.begin(), kept.end(), [&](int a2, int b2) { return nodes[a2].first < nodes[b2].first; });
+    std::vector<int> lev(nfund, 0);
+    int maxlev = 0;
+    for (int s : kept) {                        // children precede parents
+      if (nodes[s].parent < 0) continue;
+      const int p2 = find(nodes[s].parent);
+      lev[p2] = std::max(lev[p2], lev[s] + 1);
+    }
+    for (int s : kept) maxlev = std::max(maxlev, lev[s]);
+    std::vector<double> cols_at(maxlev + 1, 0.0), ent_at(maxlev + 1, 0.0);
+    for (int s : kept) {
+      cols_at[lev[s]] += nodes[s].ncol;
+      ent_at[lev[s]] += block_entries(nodes[s].ncol, (double)nodes[s].below.size());
+    }
+    constexpr double kPhaseUs = 12.0;        // one level of one sweep
+    constexpr double kTopUs = 10.0;          // the two launches of the top block
+    constexpr double kEntryUs = 8.0 / 6e6;   // one FP64 entry at ~6 TB/s
+    double best_gain = 0.0, ncT = 0.0, sparse = 0.0;
+    int cut = -1;
+    for (int c = maxlev; c >= 0; --c) {
+      ncT += cols_at[c];
+      if (ncT > dense_top_max) break;
+      sparse += 2.0 * kPhaseUs + 2.0 * ent_at[c] * kEntryUs;
+      const double gain = sparse - (kTopUs + ncT * ncT * kEntryUs);
+      if (gain > best_gain) { best_gain = gain; cut = c; }
+    }
+    if (cut >= 0) {
+      // renumber: other columns keep their order, top columns move to the end
+      std::vector<char> top_col(n, 0);
+      int nT = 0;
+      for (int s : kept)
+        if (lev[s] >= cut) {
+          for (int c = 0; c < nodes[s].ncol; ++c) top_col[nodes[s].first + c] = 1;
+          nT += nodes[s].ncol;
+        }
+      std::vector<int> newcol(n);
+      {
+        int lo = 0, hi = n - nT;
+        for (int j = 0; j < n; ++j) newcol[j] = top_col[j] ? hi++ : lo++;
+      }
+      top_rep = kept.back();                   // the last root is a top node
+      for (int s : kept) {
+        SymNode& S = nodes[s];
+        if (lev[s] >= cut) {
+          if (s != top_rep) { S.rep = top_rep; std::vector<int>().swap(S.below); }
+          continue;
+        }
+        S.first = newcol[S.first];
+        for (int& r : S.below) r = newcol[r];
+        if (!std::is_sorted(S.below.begin(), S.below.end())) {
+          err = "internal: top renumbering broke a row list";
+          return -2;
+        }
+      }
+      SymNode& T = nodes[top_rep];
+      T.first = n - nT;
+      T.ncol = nT;
+      T.parent = -1;
+      std::vector<int>().swap(T.below);
+      // permuted matrix and the combined ordering follow the new numbering
+      std::vector<int64_t> cp2(n + 1, 0);
+      for (int j = 0; j < n; ++j) cp2[newcol[j] + 1] = cp[j + 1] - cp[j];
+      for (int j = 0; j < n; ++j) cp2[j + 1] += cp2[j];
+      std::vector<int> ri2(cp[n]);
+      std::vector<double> rv2(cp[n]);
+      std::vector<int> order2(n);
+      for (int j = 0; j < n; ++j) {
+        const int nj = newcol[j];
+        int64_t o = cp2[nj];
+        for (int64_t e = cp[j]; e < cp[j + 1]; ++e) {
+          const int ni = newcol[ri[e]];
+          if (ni < nj) { err = "internal: top renumbering broke lower triangle"; return -2; }
+          ri2[o] = ni;
+          rv2[o] = rv[e];
+          ++o;
+        }
+        order2[nj] = f.order[j];
+      }
+      cp.swap(cp2);
+      ri.swap(ri2);
+      rv.swap(rv2);
+      f.order.swap(order2);
+    }
+  }
   // final supernodes in column order
   std::vector<int> keep;
   for (int s = 0; s < nfund; ++s)
@@ -267,6 +368,7 @@ int factorize(int n, const std::vector<int64_t>& colptr, const std::vector<int>&
     SymNode& nd = nodes[keep[k]];
     std::copy(nd.below.begin(), nd.below.end(), f.rows.begin() + f.sn[k].rows_off);
   }
+  f.top = top_rep < 0 ? -1 : newid[top_rep];
   std::vector<SymNode>().swap(nodes);
   // children, levels, offsets
   f.child_ptr.assign(ns + 1, 0);
@@ -379,6 +481,12 @@ int factorize(int n, const std::vector<int64_t>& colptr, const std::vector<int>&
     std::vector<double> inv((size_t)nc * nc);
     InvArgs ia{Lb, m, nc, inv.data()};
     parallel_for(nc, std::max<int64_t>(1, 4096 / std::max(1, nc)), &ia, inv_cols);
+    if (k == f.top) {
+      // (L11 L11^T)^{-1} = L11^{-T} L11^{-1}, stored in full (symmetric)
+      gram_of_lower_inverse(nc, inv.data(), Bb);
+      flops += (double)nc * nc * nc / 3.0;
+      continue;
+    }
     for (int c = 0; c < nc; ++c)
       for (int i = 0; i < nc; ++i) Bb[i + (size_t)c * m] = inv[i + (size_t)c * nc];
     if (nb > 0) {

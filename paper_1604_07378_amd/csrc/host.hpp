@@ -46,6 +46,10 @@ int host_threads();
 void gemm_nt_sub(int ma, int nb, int kk, const double* A, int lda, const double* B,
                  int ldb, double* C, int ldc, bool lower_only);
 
+// S = Linv^T Linv for a lower-triangular n x n Linv (column-major, ld n);
+// S (n x n, column-major) is written in full.
+void gram_of_lower_inverse(int n, const double* Linv, double* S);
+
 // ---------------------------------------------------------------------------
 // Ordering
 // ---------------------------------------------------------------------------
@@ -80,7 +84,9 @@ struct Factor {
   std::vector<int> child_ptr;       // children of each node (CSR)
   std::vector<int> children;
   std::vector<double> L;            // Cholesky blocks [L11; L21], column-major
-  std::vector<double> Binv;         // partitioned-inverse blocks [L11^{-1}; L21 L11^{-1}]
+  std::vector<double> Binv;         // partitioned-inverse blocks [L11^{-1}; L21 L11^{-1}];
+                                    // for the dense top block: (L11 L11^T)^{-1} in full
+  int top = -1;                     // dense top supernode (the last one), or -1
   int nlevels = 0;
   int max_front = 0;
   int64_t nnz_stored = 0;           // sum over nodes of stored block entries (lower part)
@@ -93,8 +99,10 @@ struct Factor {
 // triangle (including the diagonal) in CSC, already permuted into the final
 // order except for the etree postorder, which is applied here (the combined
 // permutation is returned in f.order). Returns 0, or -1 if not SPD.
+// The top levels of the supernode tree may be merged into one dense root block
+// of at most dense_top_max columns (0 disables), see Factor::top.
 int factorize(int n, const std::vector<int64_t>& colptr, const std::vector<int>& rowidx,
-              const std::vector<double>& val, Factor& f, std::string& err);
+              const std::vector<double>& val, Factor& f, std::string& err, int dense_top_max);
 
 // Exact CSC of L (for export and tests): column j's nonzeros.
 void factor_to_csc(const Factor& f, std::vector<int64_t>& colptr, std::vector<int>& rowidx,

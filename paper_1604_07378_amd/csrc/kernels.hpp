@@ -10,6 +10,11 @@
 namespace qn {
 
 constexpr int kMaxHistory = 16;
+// columns of the dense top block of the solve: 16 waves x 64 lanes x 6 columns
+constexpr int kMaxDenseTop = 6144;
+// largest staged right-hand side (forward: columns, backward: rows) of a
+// supernode in the bottom subtrees, per wave: 6 entries per lane
+constexpr int kSubCap = 384;
 
 // Material parameters as the element kernels read them.
 struct DevMat {
@@ -59,6 +64,20 @@ struct SnInfo {
   long long vp_out;    // where this supernode writes its update rows (parent slot)
 };
 
+// One work item of the solve, with the fields of its supernode it needs:
+// rows (forward) or columns (backward) [begin, end) of the supernode, L lanes
+// per row or column.
+struct ItemDesc {
+  int begin, end, L, nchild;
+  int first, ncol, nbelow, pad;
+  long long blk;       // the supernode's block in this sweep's packed copy
+  long long rows_off;  // its below-diagonal rows and their positions in the parent
+  long long vp_in;     // its children's update slots
+  long long vp_out;    // its own slot in its parent
+};
+// rows of a forward work item staged in LDS (pass-through sums)
+constexpr int kMaxItemRows = 256;  // == threads of a level-kernel workgroup
+
 struct DeviceMesh {
   int device = 0;
   int n = 0, nf = 0, T = 0, nmat = 0, single_type = -1, m = 5, slots = 6;
@@ -78,13 +97,25 @@ struct DeviceMesh {
   // supernodal solve (one launch per tree level and sweep)
   int nsn = 0, n_items = 0;
   SnInfo* sn = nullptr;
-  int4* items = nullptr;      // (supernode | bwd flag, begin, end, lanes per row/column)
+  ItemDesc* items = nullptr;  // per-level items: forward levels, then backward levels
   double* Bf = nullptr;       // forward blocks, row-major packed
   double* Bb = nullptr;       // backward blocks, column-major packed
   int* rows = nullptr;        // below-diagonal rows of each supernode
   int* rel = nullptr;         // position of each below row in the parent's rows
   double* vp = nullptr;       // children's update vectors in their parents' row space
-  std::vector<Level> levels;  // item ranges per tree level
+  std::vector<Level> levels;  // item ranges per tree level (levels >= sub_levels)
+  // bottom subtrees: levels < sub_levels, one workgroup per subtree
+  int sub_levels = 0, sub_tasks = 0;
+  ItemDesc* sub_fw = nullptr; // one-wave forward items, grouped by (task, level)
+  ItemDesc* sub_bw = nullptr; // one-wave backward items, grouped by (task, level)
+  int* sub_fw_ptr = nullptr;  // sub_tasks x (sub_levels + 1) item offsets
+  int* sub_bw_ptr = nullptr;
+  // dense top block (root supernode of the merged top levels), if top_n > 0:
+  // columns [top_first, top_first + top_n), full n x n inverse of its Schur
+  // complement at Bf + top_off, top_nch children's update slots at vp + top_vp
+  int top_first = 0, top_n = 0, top_nch = 0;
+  long long top_vp = 0, top_off = 0;
+  double* top_t = nullptr;    // top_n x 3 assembled right-hand side
   // solver vectors (internal order, 3 doubles per vertex)
   double* x0 = nullptr;       // n x 3 input positions
   double* v0 = nullptr;       // n x 3 input velocities
@@ -117,6 +148,16 @@ struct StepParams {
 
 // Prefactored solve r = A^{-1} q on the stream (internal order, nf x 3).
 void launch_solve(DeviceMesh& D, hipStream_t st, const double* q, double* r, const Ctl* ctl);
+
+// Workgroups of the dense top product for an n-column block: rows are split
+// evenly, at most 32 per workgroup, at most 256 workgroups unless more are
+// needed for the row limit.
+inline int top_workgroups(int n) {
+  int g = n / 8 < 1 ? 1 : n / 8;
+  if (g > 256) g = 256;
+  while ((n + g - 1) / g > 32) ++g;
+  return g;
+}
 
 // All launchers return 0 or a negative QNSIM_E_* code; err receives a message.
 int dev_alloc(DeviceMesh& d, std::string& err);

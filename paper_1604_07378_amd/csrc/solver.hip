@@ -679,7 +679,8 @@ void dev_free(DeviceMesh& D) {
   void* ptrs[] = {D.tv, D.Bm, D.vol, D.tmat, D.mats, D.mass, D.inc_ptr, D.inc_idx, D.vperm,
                   D.sn, D.items, D.Bf, D.Bb, D.rows, D.rel, D.vp, D.x0,
                   D.v0, D.y, D.X[0], D.X[1], D.G[0], D.G[1], D.d, D.q, D.z, D.Sv, D.Tv, D.fel,
-                  D.part, D.psi, D.ctl, D.tperm};
+                  D.part, D.psi, D.ctl, D.tperm, D.top_t,
+                  D.sub_fw, D.sub_bw, D.sub_fw_ptr, D.sub_bw_ptr};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (D.ctl_host) (void)hipHostFree(D.ctl_host);
@@ -704,6 +705,7 @@ int dev_alloc(DeviceMesh& D, std::string& err) {
   HIP_OK(A((void**)&D.d, f3 * 8));
   HIP_OK(A((void**)&D.q, f3 * 8));
   HIP_OK(A((void**)&D.z, f3 * 8));
+  HIP_OK(A((void**)&D.top_t, 3 * (size_t)std::max(D.top_n, 1) * 8));
   HIP_OK(A((void**)&D.Sv, f3 * 8 * D.slots));
   HIP_OK(A((void**)&D.Tv, f3 * 8 * D.slots));
   HIP_OK(A((void**)&D.fel, (size_t)D.T * 12 * 8));

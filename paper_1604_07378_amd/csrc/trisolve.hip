@@ -12,12 +12,16 @@
 //     w_S = (L11^{-1})^T z_S - (L21 L11^{-1})^T w_{rows below S}
 // Work items are a supernode and a block of its rows (forward) or columns
 // (backward); a lane group of 4..64 lanes computes one row or column, so a
-// large separator spreads over hundreds of workgroups. Each sweep launches
-// one kernel per level of the supernode tree (kernel boundaries order the
-// levels; workgroups never communicate within a launch). A forward item
-// assembles the right-hand side of its supernode itself from its children's
-// update vectors (complete since an earlier launch). Every value is computed by one fixed group of lanes in a
-// fixed order, so results are bitwise reproducible.
+// large separator spreads over hundreds of workgroups. Levels of the tree are
+// ordered by kernel boundaries (one launch per level and sweep), except for
+// the lowest levels, where one workgroup walks a whole subtree, and the
+// highest levels, merged into one dense block (see the dense top block
+// below). A forward item assembles the right-hand side of its supernode
+// itself from its children's update vectors. Each item's descriptor is one
+// 64-byte record, and its first block loads are issued before the loads of
+// the right-hand side, so both are in flight together. Every value is
+// computed by one fixed group of lanes in a fixed order, so results are
+// bitwise reproducible.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -29,7 +33,7 @@ namespace qn {
 namespace {
 
 constexpr int TS = 256;       // threads per workgroup
-constexpr int TCHUNK = 1024;  // entries of t / u staged in LDS at a time
+constexpr int TCHUNK = 512;   // entries of t / u staged in LDS at a time
 
 __device__ __forceinline__ double group_sum(double v, int L) {
   for (int off = L >> 1; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -55,47 +59,62 @@ __device__ __forceinline__ long long bw_col_off(int c, int m) {
 // zero); the item reads q and the children's slots with independent
 // contiguous loads, and adds the slots' entries below S's columns to its own
 // update rows (pass-through), which it writes into S's slot of its parent.
-__device__ __forceinline__ void fwd_item(const int4 d, const SnInfo& info,
-                                         const double* __restrict__ Bf,
+__device__ __forceinline__ void fwd_item(const ItemDesc& d, const double* __restrict__ Bf,
                                          const int* __restrict__ rel,
                                          const double* __restrict__ q, double* __restrict__ z,
                                          double* __restrict__ vp, double* s0, double* s1,
-                                         double* s2) {
+                                         double* s2, double* sp, int* srel) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int nc = info.ncol, first = info.first, m = info.ncol + info.nbelow;
-  const int L = d.w, G = 64 / L, grp = lane / L, gl = lane % L;
+  const int nc = d.ncol, first = d.first, m = d.ncol + d.nbelow;
+  const int L = d.L, G = 64 / L, grp = lane / L, gl = lane % L;
   const int slot0 = wave * G + grp;  // this group's first row in the item
   const int stride = 4 * G;
-  const int nch = info.nchild;
-  const double* __restrict__ vin = vp + info.vp_in;   // nch slots of m x 3
-  const size_t slot_stride = 3 * (size_t)m;
-  // pass-through sums of this group's rows below the columns (loads first)
-  double pass[4][3];
-  int relr[4];
+  const int nch = d.nchild;
+  const double* __restrict__ vin = vp + d.vp_in;   // nch slots of m x 3
+  const size_t ss = 3 * (size_t)m;
+  int cend[4];
+  const double* rp[4];
+  int cmax = 0;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    pass[k][0] = pass[k][1] = pass[k][2] = 0.0;
-    const int r = d.y + slot0 + k * stride;
-    relr[k] = (gl == 0 && r < d.z && r >= nc) ? rel[info.rows_off + (r - nc)] : 0;
-    if (gl == 0 && r < d.z && r >= nc) {
-      for (int j0 = 0; j0 < nch; j0 += 4) {
-        double u[4][3];
+    const int r = d.begin + slot0 + k * stride;
+    cend[k] = (r < d.end) ? (r < nc ? r + 1 : nc) : 0;
+    rp[k] = Bf + d.blk + fw_row_off(r < d.end ? r : 0, nc);
+    cmax = max(cmax, cend[k]);
+  }
+  // first block iteration (columns gl + u L of the first chunk)
+  double b[4][4];
+  {
+    const int c1 = min(nc, TCHUNK);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const double* up = vin + (j0 + j) * slot_stride + 3 * (size_t)r;
-          const bool ok = j0 + j < nch;
-          u[j][0] = ok ? up[0] : 0.0;
-          u[j][1] = ok ? up[1] : 0.0;
-          u[j][2] = ok ? up[2] : 0.0;
-        }
+    for (int k = 0; k < 4; ++k)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          pass[k][0] += u[j][0];
-          pass[k][1] += u[j][1];
-          pass[k][2] += u[j][2];
-        }
+      for (int u = 0; u < 4; ++u) {
+        const int cc = gl + u * L;
+        b[k][u] = (cc < min(cend[k], c1)) ? rp[k][cc] : 0.0;
       }
+  }
+  // output positions and pass-through sums of the item's rows below the
+  // columns, staged in LDS (one row per thread)
+  const int nrows = d.end - d.begin;
+  if (tid < nrows) {  // nrows <= kMaxItemRows == TS
+    const int r = d.begin + tid;
+    srel[tid] = r >= nc ? rel[d.rows_off + (r - nc)] : 0;
+    double p0 = 0.0, p1 = 0.0, p2 = 0.0;
+    for (int j0 = 0; r >= nc && j0 < nch; j0 += 2) {
+      double u[2][3];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const bool ok = j0 + j < nch;
+        const double* up = vin + (ok ? j0 + j : 0) * ss + 3 * (size_t)r;
+        u[j][0] = ok ? up[0] : 0.0;
+        u[j][1] = ok ? up[1] : 0.0;
+        u[j][2] = ok ? up[2] : 0.0;
+      }
+      p0 += u[0][0]; p1 += u[0][1]; p2 += u[0][2];
+      p0 += u[1][0]; p1 += u[1][1]; p2 += u[1][2];
     }
+    sp[3 * tid + 0] = p0; sp[3 * tid + 1] = p1; sp[3 * tid + 2] = p2;
   }
   double a[4][3];
 #pragma unroll
@@ -104,8 +123,7 @@ __device__ __forceinline__ void fwd_item(const int4 d, const SnInfo& info,
     const int c1 = min(nc, c0 + TCHUNK);
     if (c0 > 0) __syncthreads();
     {
-      // all loads of this thread's entries (q and up to 4 children per pass)
-      // are issued before any of them is used
+      // q and the children's slots on this chunk, all loads before use
       double v[TCHUNK / TS][3];
 #pragma unroll
       for (int jj = 0; jj < TCHUNK / TS; ++jj) {
@@ -115,15 +133,15 @@ __device__ __forceinline__ void fwd_item(const int4 d, const SnInfo& info,
         v[jj][1] = p[1];
         v[jj][2] = p[2];
       }
-      for (int j0 = 0; j0 < nch; j0 += 4) {
-        double u[TCHUNK / TS][4][3];
+      for (int j0 = 0; j0 < nch; j0 += 2) {
+        double u[TCHUNK / TS][2][3];
 #pragma unroll
         for (int jj = 0; jj < TCHUNK / TS; ++jj) {
           const int c = c0 + tid + jj * TS;
 #pragma unroll
-          for (int j = 0; j < 4; ++j) {
+          for (int j = 0; j < 2; ++j) {
             const bool ok = (j0 + j < nch) && c < c1;
-            const double* up = vin + (j0 + j) * slot_stride + 3 * (size_t)(ok ? c : 0);
+            const double* up = vin + (j0 + j) * ss + 3 * (size_t)(ok ? c : 0);
             u[jj][j][0] = ok ? up[0] : 0.0;
             u[jj][j][1] = ok ? up[1] : 0.0;
             u[jj][j][2] = ok ? up[2] : 0.0;
@@ -132,7 +150,7 @@ __device__ __forceinline__ void fwd_item(const int4 d, const SnInfo& info,
 #pragma unroll
         for (int jj = 0; jj < TCHUNK / TS; ++jj)
 #pragma unroll
-          for (int j = 0; j < 4; ++j) {
+          for (int j = 0; j < 2; ++j) {
             v[jj][0] -= u[jj][j][0];
             v[jj][1] -= u[jj][j][1];
             v[jj][2] -= u[jj][j][2];
@@ -151,25 +169,17 @@ __device__ __forceinline__ void fwd_item(const int4 d, const SnInfo& info,
     __syncthreads();
     // the group's (up to) 4 rows advance together: 4 rows x 4 unrolled
     // columns = 16 independent loads in flight per lane
-    int cend[4];
-    const double* rp[4];
-    int cmax = c0;
+    const int cm = min(cmax, c1);
+    for (int c = c0 + gl; c < cm; c += 4 * L) {
+      if (c0 > 0 || c != gl) {
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int r = d.y + slot0 + k * stride;
-      cend[k] = (r < d.z) ? min(c1, r < nc ? r + 1 : nc) : c0;
-      rp[k] = Bf + info.fw_off + fw_row_off(r < d.z ? r : 0, nc);
-      cmax = max(cmax, cend[k]);
-    }
-    for (int c = c0 + gl; c < cmax; c += 4 * L) {
-      double b[4][4];
+        for (int k = 0; k < 4; ++k)
 #pragma unroll
-      for (int k = 0; k < 4; ++k)
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int cc = c + u * L;
-          b[k][u] = (cc < cend[k]) ? rp[k][cc] : 0.0;
-        }
+          for (int u = 0; u < 4; ++u) {
+            const int cc = c + u * L;
+            b[k][u] = (cc < min(cend[k], c1)) ? rp[k][cc] : 0.0;
+          }
+      }
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int o = c + u * L - c0;
@@ -187,53 +197,78 @@ __device__ __forceinline__ void fwd_item(const int4 d, const SnInfo& info,
   }
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    const int r = d.y + slot0 + k * stride;
-    double o0 = group_sum(a[k][0], L), o1 = group_sum(a[k][1], L), o2 = group_sum(a[k][2], L);
-    if (gl == 0 && r < d.z) {
+    const int r = d.begin + slot0 + k * stride;
+    const double o0 = group_sum(a[k][0], L), o1 = group_sum(a[k][1], L),
+                 o2 = group_sum(a[k][2], L);
+    if (gl == 0 && r < d.end) {
       if (r < nc) {
         double* o = z + 3 * (size_t)(first + r);
         o[0] = o0; o[1] = o1; o[2] = o2;
       } else {
-        double* o = vp + info.vp_out + 3 * (size_t)relr[k];
-        o[0] = o0 + pass[k][0];
-        o[1] = o1 + pass[k][1];
-        o[2] = o2 + pass[k][2];
+        const int i = r - d.begin;
+        double* o = vp + d.vp_out + 3 * (size_t)srel[i];
+        o[0] = o0 + sp[3 * i + 0];
+        o[1] = o1 + sp[3 * i + 1];
+        o[2] = o2 + sp[3 * i + 2];
       }
     }
   }
 }
 
-__global__ void __launch_bounds__(TS)
-k_solve_fwd(const int4* __restrict__ items, const SnInfo* __restrict__ sn,
-            const double* __restrict__ Bf, const int* __restrict__ rel,
-            const double* __restrict__ q, double* __restrict__ z, double* __restrict__ vp,
-            const Ctl* __restrict__ ctl) {
-  __shared__ double s0[TCHUNK], s1[TCHUNK], s2[TCHUNK];
+__global__ void __launch_bounds__(TS, 4)
+k_solve_fwd(const ItemDesc* __restrict__ items, const double* __restrict__ Bf,
+            const int* __restrict__ rel, const double* __restrict__ q, double* __restrict__ z,
+            double* __restrict__ vp, const Ctl* __restrict__ ctl) {
+  static_assert(kMaxItemRows == TS, "one staged row per thread");
+  __shared__ double s0[TCHUNK], s1[TCHUNK], s2[TCHUNK], sp[3 * kMaxItemRows];
+  __shared__ int srel[kMaxItemRows];
   if (ctl && !(ctl->active && !ctl->need_host)) return;
-  const int4 d = items[blockIdx.x];
-  const SnInfo info = sn[d.x];
-  fwd_item(d, info, Bf, rel, q, z, vp, s0, s1, s2);
+  const ItemDesc d = items[blockIdx.x];
+  fwd_item(d, Bf, rel, q, z, vp, s0, s1, s2, sp, srel);
 }
 
 // Backward sweep, one tree level: one work item per workgroup. A lane group
 // of L lanes computes up to 4 columns of [L11^{-1}; L21 L11^{-1}]^T [z_S; -w_R].
-__device__ __forceinline__ void bwd_item(const int4 d, const SnInfo& info,
-                                         const double* __restrict__ Bb,
+__device__ __forceinline__ void bwd_item(const ItemDesc& d, const double* __restrict__ Bb,
                                          const int* __restrict__ rows,
                                          const double* __restrict__ z, double* __restrict__ w,
                                          double* s0, double* s1, double* s2) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int nc = info.ncol, m = info.ncol + info.nbelow, first = info.first;
-  const int L = d.w, G = 64 / L, grp = lane / L, gl = lane % L;
+  const int nc = d.ncol, m = d.ncol + d.nbelow, first = d.first;
+  const int L = d.L, G = 64 / L, grp = lane / L, gl = lane % L;
   const int slot0 = wave * G + grp;
   const int stride = 4 * G;
-  const int* __restrict__ rw = rows + info.rows_off;
+  const int* __restrict__ rw = rows + d.rows_off;
+  int cst[4];
+  const double* cp[4];
+  bool any = false;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int c = d.begin + slot0 + k * stride;
+    const bool ok = c < d.end;
+    cst[k] = ok ? c : m;                  // rows i >= c contribute to column c
+    cp[k] = Bb + d.blk + bw_col_off(ok ? c : 0, m) - (ok ? c : 0);
+    any |= ok;
+  }
+  // first block iteration of the first chunk
+  double b[4][4];
+  {
+    const int i0 = d.begin, i1 = min(m, i0 + TCHUNK);
+    const int i = max(i0, cst[0]) + gl;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int ii = i + u * L;
+        b[k][u] = (any && ii >= cst[k] && ii < i1) ? cp[k][ii] : 0.0;
+      }
+  }
   double a[4][3];
 #pragma unroll
   for (int k = 0; k < 4; ++k) a[k][0] = a[k][1] = a[k][2] = 0.0;
-  for (int i0 = d.y; i0 < m; i0 += TCHUNK) {  // rows above the item's columns never contribute
+  for (int i0 = d.begin; i0 < m; i0 += TCHUNK) {  // rows above the item's columns never contribute
     const int i1 = min(m, i0 + TCHUNK);
-    if (i0 > d.y) __syncthreads();
+    if (i0 > d.begin) __syncthreads();
     int g[TCHUNK / TS];
 #pragma unroll
     for (int j = 0; j < TCHUNK / TS; ++j) {
@@ -255,27 +290,17 @@ __device__ __forceinline__ void bwd_item(const int4 d, const SnInfo& info,
     }
     __syncthreads();
     // the group's (up to) 4 columns advance together: 16 loads in flight per lane
-    int cst[4];
-    const double* cp[4];
-    bool any = false;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int c = d.y + slot0 + k * stride;
-      const bool ok = c < d.z;
-      cst[k] = ok ? c : m;                  // rows i >= c contribute to column c
-      cp[k] = Bb + info.bw_off + bw_col_off(ok ? c : 0, m) - (ok ? c : 0);
-      any |= ok;
-    }
     if (any) {
       for (int i = max(i0, cst[0]) + gl; i < i1; i += 4 * L) {
-        double b[4][4];
+        if (i0 > d.begin || i != max(i0, cst[0]) + gl) {
 #pragma unroll
-        for (int k = 0; k < 4; ++k)
+          for (int k = 0; k < 4; ++k)
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const int ii = i + u * L;
-            b[k][u] = (ii >= cst[k] && ii < i1) ? cp[k][ii] : 0.0;
-          }
+            for (int u = 0; u < 4; ++u) {
+              const int ii = i + u * L;
+              b[k][u] = (ii >= cst[k] && ii < i1) ? cp[k][ii] : 0.0;
+            }
+        }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           const int o = i + u * L - i0;
@@ -294,10 +319,10 @@ __device__ __forceinline__ void bwd_item(const int4 d, const SnInfo& info,
   }
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    const int c = d.y + slot0 + k * stride;
+    const int c = d.begin + slot0 + k * stride;
     const double o0 = group_sum(a[k][0], L), o1 = group_sum(a[k][1], L),
                  o2 = group_sum(a[k][2], L);
-    if (gl == 0 && c < d.z) {
+    if (gl == 0 && c < d.end) {
       double* o = w + 3 * (size_t)(first + c);
       o[0] = o0; o[1] = o1; o[2] = o2;
     }
@@ -305,31 +330,417 @@ __device__ __forceinline__ void bwd_item(const int4 d, const SnInfo& info,
 }
 
 __global__ void __launch_bounds__(TS)
-k_solve_bwd(const int4* __restrict__ items, const SnInfo* __restrict__ sn,
-            const double* __restrict__ Bb, const int* __restrict__ rows,
-            const double* __restrict__ z, double* __restrict__ w,
+k_solve_bwd(const ItemDesc* __restrict__ items, const double* __restrict__ Bb,
+            const int* __restrict__ rows, const double* __restrict__ z, double* __restrict__ w,
             const Ctl* __restrict__ ctl) {
   __shared__ double s0[TCHUNK], s1[TCHUNK], s2[TCHUNK];
   if (ctl && !(ctl->active && !ctl->need_host)) return;
-  const int4 d = items[blockIdx.x];
-  const SnInfo info = sn[d.x & 0x7fffffff];
-  bwd_item(d, info, Bb, rows, z, w, s0, s1, s2);
+  const ItemDesc d = items[blockIdx.x];
+  bwd_item(d, Bb, rows, z, w, s0, s1, s2);
+}
+
+// ---------------------------------------------------------------------------
+// Bottom subtrees. The lowest levels of the tree hold many small supernodes;
+// instead of one launch per level, one workgroup takes a whole subtree of
+// those levels and walks its levels in order, with a workgroup barrier
+// between levels (children's update slots and the solution entries are
+// written and read by the same workgroup). Within a level every wave takes
+// its own work items, staging the supernode's right-hand side in its own
+// LDS region, so no barrier is needed inside a level.
+// ---------------------------------------------------------------------------
+constexpr int kSubThreads = 1024, kSubWaves = kSubThreads / 64;
+
+__device__ __forceinline__ void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Forward item of one wave: rows [begin, end) of the supernode with lane
+// groups of L lanes, rows begin + grp + k G (k < 4) per group. The wave
+// stages, for every row i < m of the supernode, ts[i] = q_i - (children's
+// updates)_i for i < nc (the right-hand side t_S) and ts[i] = (children's
+// updates)_i for i >= nc (the pass-through sums), in its LDS region
+// ts[3][kSubCap].
+__device__ __forceinline__ void fwd_wave_item(const ItemDesc& d, const double* __restrict__ Bf,
+                                              const int* __restrict__ rel,
+                                              const double* __restrict__ q,
+                                              double* __restrict__ z, double* __restrict__ vp,
+                                              double* ts, int lane) {
+  const int nc = d.ncol, first = d.first, m = d.ncol + d.nbelow;
+  const int L = d.L, G = 64 / L, grp = lane / L, gl = lane % L;
+  const int nch = d.nchild;
+  const double* __restrict__ vin = vp + d.vp_in;
+  const size_t ss = 3 * (size_t)m;
+  int cend[4];
+  const double* rp[4];
+  int cmax = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int r = d.begin + grp + k * G;
+    cend[k] = (r < d.end) ? (r < nc ? r + 1 : nc) : 0;
+    rp[k] = Bf + d.blk + fw_row_off(r < d.end ? r : 0, nc);
+    cmax = max(cmax, cend[k]);
+  }
+  double b[4][4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+#pragma unroll
+    for (int uu = 0; uu < 4; ++uu) {
+      const int cc = gl + uu * L;
+      b[k][uu] = (cc < cend[k]) ? rp[k][cc] : 0.0;
+    }
+  int relr[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int r = d.begin + grp + k * G;
+    relr[k] = (gl == 0 && r < d.end && r >= nc) ? rel[d.rows_off + (r - nc)] : 0;
+  }
+  for (int i0 = 0; i0 < m; i0 += 128) {
+    double v[2][3];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int i = i0 + lane + 64 * k;
+      const double* p = q + 3 * (size_t)(first + (i < nc ? i : 0));
+      v[k][0] = i < nc ? p[0] : 0.0;
+      v[k][1] = i < nc ? p[1] : 0.0;
+      v[k][2] = i < nc ? p[2] : 0.0;
+    }
+    for (int j0 = 0; j0 < nch; j0 += 2) {
+      double u[2][2][3];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const double* sl = vin + (size_t)(j0 + j < nch ? j0 + j : 0) * ss;
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+          const int i = i0 + lane + 64 * k;
+          const bool ok = j0 + j < nch && i < m;
+          u[j][k][0] = ok ? sl[3 * (size_t)i + 0] : 0.0;
+          u[j][k][1] = ok ? sl[3 * (size_t)i + 1] : 0.0;
+          u[j][k][2] = ok ? sl[3 * (size_t)i + 2] : 0.0;
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+          const bool rhs = i0 + lane + 64 * k < nc;
+          v[k][0] = rhs ? v[k][0] - u[j][k][0] : v[k][0] + u[j][k][0];
+          v[k][1] = rhs ? v[k][1] - u[j][k][1] : v[k][1] + u[j][k][1];
+          v[k][2] = rhs ? v[k][2] - u[j][k][2] : v[k][2] + u[j][k][2];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int i = i0 + lane + 64 * k;
+      if (i < m) {
+        ts[i] = v[k][0];
+        ts[kSubCap + i] = v[k][1];
+        ts[2 * kSubCap + i] = v[k][2];
+      }
+    }
+  }
+  wave_sync_lds();
+  double a[4][3];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) a[k][0] = a[k][1] = a[k][2] = 0.0;
+  for (int c = gl; c < cmax; c += 4 * L) {
+    if (c != gl) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int uu = 0; uu < 4; ++uu) {
+          const int cc = c + uu * L;
+          b[k][uu] = (cc < cend[k]) ? rp[k][cc] : 0.0;
+        }
+    }
+#pragma unroll
+    for (int uu = 0; uu < 4; ++uu) {
+      const int cc = c + uu * L;
+      if (cc < nc) {
+        const double t0 = ts[cc], t1 = ts[kSubCap + cc], t2 = ts[2 * kSubCap + cc];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          a[k][0] += b[k][uu] * t0;
+          a[k][1] += b[k][uu] * t1;
+          a[k][2] += b[k][uu] * t2;
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int r = d.begin + grp + k * G;
+    const double o0 = group_sum(a[k][0], L), o1 = group_sum(a[k][1], L),
+                 o2 = group_sum(a[k][2], L);
+    if (gl == 0 && r < d.end) {
+      if (r < nc) {
+        double* o = z + 3 * (size_t)(first + r);
+        o[0] = o0; o[1] = o1; o[2] = o2;
+      } else {
+        double* o = vp + d.vp_out + 3 * (size_t)relr[k];
+        o[0] = o0 + ts[r];
+        o[1] = o1 + ts[kSubCap + r];
+        o[2] = o2 + ts[2 * kSubCap + r];
+      }
+    }
+  }
+  wave_sync_lds();  // the region is restaged by the wave's next item
+}
+
+// Backward item of one wave: columns [begin, end) of the supernode, lane
+// groups of L lanes, columns begin + grp + k G (k < 4) per group. The entries
+// u_i = [z_S; -w_rows]_i for i in [begin, m) are staged in the wave's LDS
+// region (m - begin <= kSubCap).
+__device__ __forceinline__ void bwd_wave_item(const ItemDesc& d, const double* __restrict__ Bb,
+                                              const int* __restrict__ rows,
+                                              const double* __restrict__ z,
+                                              double* __restrict__ w, double* us, int lane) {
+  const int nc = d.ncol, m = d.ncol + d.nbelow, first = d.first;
+  const int L = d.L, G = 64 / L, grp = lane / L, gl = lane % L;
+  const int* __restrict__ rw = rows + d.rows_off;
+  constexpr int KC = kSubCap / 64;
+  int cst[4];
+  const double* cp[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int c = d.begin + grp + k * G;
+    const bool ok = c < d.end;
+    cst[k] = ok ? c : m;
+    cp[k] = Bb + d.blk + bw_col_off(ok ? c : 0, m) - (ok ? c : 0);
+  }
+  double b[4][4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+#pragma unroll
+    for (int uu = 0; uu < 4; ++uu) {
+      const int ii = cst[0] + gl + uu * L;
+      b[k][uu] = (ii >= cst[k] && ii < m) ? cp[k][ii] : 0.0;
+    }
+  int g[KC];
+#pragma unroll
+  for (int k = 0; k < KC; ++k) {
+    const int i = d.begin + lane + 64 * k;
+    g[k] = (i < m && i >= nc) ? rw[i - nc] : -1;
+  }
+  double v[KC][3];
+#pragma unroll
+  for (int k = 0; k < KC; ++k) {
+    const int i = d.begin + lane + 64 * k;
+    const double* p = (i < nc) ? z + 3 * (size_t)(first + i) : w + 3 * (size_t)(g[k] >= 0 ? g[k] : 0);
+    const bool ok = i < m;
+    const double sg = (i < nc) ? 1.0 : -1.0;
+    v[k][0] = ok ? sg * p[0] : 0.0;
+    v[k][1] = ok ? sg * p[1] : 0.0;
+    v[k][2] = ok ? sg * p[2] : 0.0;
+  }
+#pragma unroll
+  for (int k = 0; k < KC; ++k) {
+    const int i = d.begin + lane + 64 * k;
+    if (i < m) {
+      us[i - d.begin] = v[k][0];
+      us[kSubCap + i - d.begin] = v[k][1];
+      us[2 * kSubCap + i - d.begin] = v[k][2];
+    }
+  }
+  wave_sync_lds();
+  double a[4][3];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) a[k][0] = a[k][1] = a[k][2] = 0.0;
+  for (int i = cst[0] + gl; i < m; i += 4 * L) {
+    if (i != cst[0] + gl) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int uu = 0; uu < 4; ++uu) {
+          const int ii = i + uu * L;
+          b[k][uu] = (ii >= cst[k] && ii < m) ? cp[k][ii] : 0.0;
+        }
+    }
+#pragma unroll
+    for (int uu = 0; uu < 4; ++uu) {
+      const int ii = i + uu * L;
+      if (ii < m) {
+        const int o = ii - d.begin;
+        const double t0 = us[o], t1 = us[kSubCap + o], t2 = us[2 * kSubCap + o];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          a[k][0] += b[k][uu] * t0;
+          a[k][1] += b[k][uu] * t1;
+          a[k][2] += b[k][uu] * t2;
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int c = d.begin + grp + k * G;
+    const double o0 = group_sum(a[k][0], L), o1 = group_sum(a[k][1], L),
+                 o2 = group_sum(a[k][2], L);
+    if (gl == 0 && c < d.end) {
+      double* o = w + 3 * (size_t)(first + c);
+      o[0] = o0; o[1] = o1; o[2] = o2;
+    }
+  }
+  wave_sync_lds();
+}
+
+// Forward sweep over the bottom subtrees: workgroup = subtree, levels in
+// ascending order; ptr[task * (nl + 1) + l] delimits the level-l items.
+__global__ void __launch_bounds__(kSubThreads)
+k_solve_fwd_sub(const ItemDesc* __restrict__ items, const int* __restrict__ ptr, int nl,
+                const double* __restrict__ Bf, const int* __restrict__ rel,
+                const double* __restrict__ q, double* __restrict__ z, double* __restrict__ vp,
+                const Ctl* __restrict__ ctl) {
+  __shared__ double stage[kSubWaves][3 * kSubCap];
+  if (ctl && !(ctl->active && !ctl->need_host)) return;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int* p = ptr + (size_t)blockIdx.x * (nl + 1);
+  for (int l = 0; l < nl; ++l) {
+    if (l > 0) __syncthreads();
+    for (int i = p[l] + wv; i < p[l + 1]; i += kSubWaves) {
+      const ItemDesc d = items[i];
+      fwd_wave_item(d, Bf, rel, q, z, vp, stage[wv], lane);
+    }
+  }
+}
+
+// Backward sweep over the bottom subtrees: levels in descending order.
+__global__ void __launch_bounds__(kSubThreads)
+k_solve_bwd_sub(const ItemDesc* __restrict__ items, const int* __restrict__ ptr, int nl,
+                const double* __restrict__ Bb, const int* __restrict__ rows,
+                const double* __restrict__ z, double* __restrict__ w,
+                const Ctl* __restrict__ ctl) {
+  __shared__ double stage[kSubWaves][3 * kSubCap];
+  if (ctl && !(ctl->active && !ctl->need_host)) return;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int* p = ptr + (size_t)blockIdx.x * (nl + 1);
+  for (int l = nl - 1; l >= 0; --l) {
+    if (l < nl - 1) __syncthreads();
+    for (int i = p[l] + wv; i < p[l + 1]; i += kSubWaves) {
+      const ItemDesc d = items[i];
+      bwd_wave_item(d, Bb, rows, z, w, stage[wv], lane);
+    }
+  }
+}
+
+// Dense top block, step 1: its right-hand side t_T = q_T - (children's update
+// vectors), summed in a fixed order.
+__global__ void __launch_bounds__(TS)
+k_top_assemble(const double* __restrict__ q, const double* __restrict__ slots, int nch,
+               int n3, double* __restrict__ t, const Ctl* __restrict__ ctl) {
+  if (ctl && !(ctl->active && !ctl->need_host)) return;
+  const int i = blockIdx.x * TS + threadIdx.x;
+  if (i >= n3) return;
+  double v = q[i];
+  for (int j = 0; j < nch; ++j) v -= slots[(size_t)j * n3 + i];
+  t[i] = v;
+}
+
+// Dense top block, step 2: w_T = S^{-1} t_T with S^{-1} symmetric, n x n,
+// row-major. A workgroup owns a contiguous range of at most kTopRows rows and
+// stages t_T in LDS. Its tasks are (row, one of kTopParts column ranges);
+// wave wv takes tasks wv, wv + 16, ... A lane loads up to kTopU entries of
+// the task (all in flight at once), the next task's loads are issued before
+// the current task's sums are reduced over the wave, and the parts of a row
+// are added in LDS in a fixed order.
+constexpr int kTopThreads = 1024, kTopWaves = kTopThreads / 64, kTopRows = 32, kTopParts = 8;
+constexpr int kTopU = (kMaxDenseTop / kTopParts + 63) / 64;  // entries per lane and task
+
+__global__ void __launch_bounds__(kTopThreads)
+k_top_gemv(const double* __restrict__ Sinv, const double* __restrict__ t, int n, int nwg,
+           double* __restrict__ w, const Ctl* __restrict__ ctl) {
+  __shared__ double ts[3][kMaxDenseTop];
+  __shared__ double red[kTopRows][kTopParts][3];
+  if (ctl && !(ctl->active && !ctl->need_host)) return;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int rb = (int)(((long long)blockIdx.x * n) / nwg);
+  const int re = (int)(((long long)(blockIdx.x + 1) * n) / nwg);
+  const int ntask = kTopParts * (re - rb);
+  const int qw = (n + kTopParts - 1) / kTopParts;  // columns per part
+  const int U = (qw + 63) / 64;            // entries per lane and task (uniform)
+  double b[kTopU];
+  auto load_task = [&](int task) {
+    const int r = rb + task / kTopParts, q = task % kTopParts;
+    const int c0 = q * qw, c1 = min(n, c0 + qw);
+    const double* rowp = Sinv + (size_t)r * n;
+#pragma unroll
+    for (int u = 0; u < kTopU; ++u) {
+      const int c = c0 + lane + 64 * u;
+      b[u] = (u < U && c < c1) ? rowp[c] : 0.0;
+    }
+  };
+  int task = wv;
+  if (task < ntask) load_task(task);
+  for (int i = threadIdx.x; i < n; i += kTopThreads) {
+    ts[0][i] = t[3 * (size_t)i + 0];
+    ts[1][i] = t[3 * (size_t)i + 1];
+    ts[2][i] = t[3 * (size_t)i + 2];
+  }
+  __syncthreads();
+  for (; task < ntask; task += kTopWaves) {
+    const int q = task % kTopParts, c0 = q * qw, c1 = min(n, c0 + qw);
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+#pragma unroll
+    for (int u = 0; u < kTopU; ++u) {
+      const int c = c0 + lane + 64 * u;
+      if (u < U && c < c1) {
+        a0 += b[u] * ts[0][c];
+        a1 += b[u] * ts[1][c];
+        a2 += b[u] * ts[2][c];
+      }
+    }
+    if (task + kTopWaves < ntask) load_task(task + kTopWaves);
+    a0 = group_sum(a0, 64);
+    a1 = group_sum(a1, 64);
+    a2 = group_sum(a2, 64);
+    if (lane == 0) {
+      red[task / kTopParts][q][0] = a0;
+      red[task / kTopParts][q][1] = a1;
+      red[task / kTopParts][q][2] = a2;
+    }
+  }
+  __syncthreads();
+  const int i = threadIdx.x;
+  if (i < 3 * (re - rb)) {
+    const int r = i / 3, comp = i % 3;
+    double v = 0.0;
+#pragma unroll
+    for (int k = 0; k < kTopParts; ++k) v += red[r][k][comp];
+    w[3 * (size_t)rb + i] = v;
+  }
 }
 
 void launch_solve(DeviceMesh& D, hipStream_t st, const double* q, double* r, const Ctl* ctl) {
   const int L = (int)D.levels.size();
-  for (int l = 0; l < L; ++l) {
+  if (D.sub_tasks > 0)
+    hipLaunchKernelGGL(k_solve_fwd_sub, dim3(D.sub_tasks), dim3(kSubThreads), 0, st, D.sub_fw,
+                       D.sub_fw_ptr, D.sub_levels, D.Bf, D.rel, q, D.z, D.vp, ctl);
+  for (int l = D.sub_levels; l < L; ++l) {
     const int n = D.levels[l].fw_end - D.levels[l].fw_begin;
     if (n > 0)
       hipLaunchKernelGGL(k_solve_fwd, dim3(n), dim3(TS), 0, st, D.items + D.levels[l].fw_begin,
-                         D.sn, D.Bf, D.rel, q, D.z, D.vp, ctl);
+                         D.Bf, D.rel, q, D.z, D.vp, ctl);
   }
-  for (int l = L - 1; l >= 0; --l) {
+  if (D.top_n > 0) {
+    const int n = D.top_n, n3 = 3 * n;
+    hipLaunchKernelGGL(k_top_assemble, dim3((n3 + TS - 1) / TS), dim3(TS), 0, st,
+                       q + 3 * (size_t)D.top_first, D.vp + D.top_vp, D.top_nch, n3, D.top_t, ctl);
+    const int nwg = top_workgroups(n);
+    hipLaunchKernelGGL(k_top_gemv, dim3(nwg), dim3(kTopThreads), 0, st, D.Bf + D.top_off,
+                       D.top_t, n, nwg, r + 3 * (size_t)D.top_first, ctl);
+  }
+  for (int l = L - 1; l >= D.sub_levels; --l) {
     const int n = D.levels[l].bw_end - D.levels[l].bw_begin;
     if (n > 0)
       hipLaunchKernelGGL(k_solve_bwd, dim3(n), dim3(TS), 0, st, D.items + D.levels[l].bw_begin,
-                         D.sn, D.Bb, D.rows, D.z, r, ctl);
+                         D.Bb, D.rows, D.z, r, ctl);
   }
+  if (D.sub_tasks > 0)
+    hipLaunchKernelGGL(k_solve_bwd_sub, dim3(D.sub_tasks), dim3(kSubThreads), 0, st, D.sub_bw,
+                       D.sub_bw_ptr, D.sub_levels, D.Bb, D.rows, D.z, r, ctl);
 }
 
 }  // namespace qn

@@ -38,10 +38,11 @@ class QnsimError(RuntimeError):
 class Options(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("history", ctypes.c_int32),
                 ("max_halvings", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("device", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("device", ctypes.c_int32), ("dense_top", ctypes.c_int32),
                 ("gamma", ctypes.c_double), ("backtrack", ctypes.c_double),
                 ("fit_lo", ctypes.c_double), ("fit_hi", ctypes.c_double),
-                ("gravity", ctypes.c_double * 3)]
+                ("gravity", ctypes.c_double * 3),
+                ("subtree_cap", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class MaterialC(ctypes.Structure):
@@ -64,12 +65,13 @@ class Stats(ctypes.Structure):
 class FactorInfo(ctypes.Structure):
     _fields_ = [("n_free", ctypes.c_int32), ("n_supernodes", ctypes.c_int32),
                 ("n_levels", ctypes.c_int32), ("max_front", ctypes.c_int32),
+                ("dense_top_cols", ctypes.c_int32), ("subtree_levels", ctypes.c_int32),
                 ("nnz_L", ctypes.c_int64), ("nnz_L_exact", ctypes.c_int64),
                 ("factor_bytes", ctypes.c_int64), ("factor_flops", ctypes.c_double),
                 ("prepare_seconds", ctypes.c_double)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
 
 
 _P = ctypes.c_void_p

@@ -80,10 +80,20 @@ def test_objective_and_gradient(kind):
     assert np.abs(grad - grad_ref).max() <= 1e-11 * np.abs(grad_ref).max()
 
 
+# Solve schedules: every level through the per-level kernels; the bottom
+# subtrees in one workgroup each; a small dense top block above them; the
+# defaults (small meshes: one dense block).
+SCHEDULES = {"levels": dict(dense_top=0, subtree_cap=0),
+             "subtrees": dict(dense_top=0, subtree_cap=384),
+             "subtrees+top": dict(dense_top=64, subtree_cap=384),
+             "default": dict(dense_top=6144, subtree_cap=384)}
+
+
+@pytest.mark.parametrize("sched", list(SCHEDULES))
 @pytest.mark.parametrize("dims", [(10, 3, 3), (7, 5, 3), (1, 1, 1), (16, 14, 12)])
-def test_prefactored_solve(dims):
+def test_prefactored_solve(dims, sched):
     w = W.workload_cantilever(0, dims=dims)
-    s = qnsim.sim_from_workload(w)
+    s = qnsim.sim_from_workload(w, **SCHEDULES[sched])
     m = _model(w)
     q = np.random.default_rng(4).normal(size=(w.n_verts, 3))
     r_ref = np.zeros_like(q)
@@ -95,9 +105,9 @@ def test_prefactored_solve(dims):
     assert np.abs(r - r_ref).max() <= 1e-12 * np.abs(r_ref).max()
 
 
-def _trajectory_parity(w, steps, tol=1e-9, history=5, check_stats=True):
+def _trajectory_parity(w, steps, tol=1e-9, history=5, check_stats=True, sched="default"):
     m = _model(w)
-    s = qnsim.sim_from_workload(w, history=history)
+    s = qnsim.sim_from_workload(w, history=history, **SCHEDULES[sched])
     x_o, v_o = w.x0.copy(), w.v0.copy()
     x_g, v_g = w.x0.copy(), w.v0.copy()
     worst = 0.0
@@ -116,11 +126,13 @@ def _trajectory_parity(w, steps, tol=1e-9, history=5, check_stats=True):
     return worst
 
 
-def test_cantilever_neohookean_100_steps():
-    """540-tet cantilever, Neo-Hookean E = 1e5, nu = 0.4, 100 steps from rest."""
+@pytest.mark.parametrize("sched", list(SCHEDULES))
+def test_cantilever_neohookean_100_steps(sched):
+    """540-tet cantilever, Neo-Hookean E = 1e5, nu = 0.4, 100 steps from rest,
+    under every solve schedule."""
     w = W.workload_cantilever(0)
-    worst = _trajectory_parity(w, 100)
-    print(f"cantilever NH 100 steps: max eps {worst:.3e}", flush=True)
+    worst = _trajectory_parity(w, 100, sched=sched)
+    print(f"cantilever NH 100 steps ({sched}): max eps {worst:.3e}", flush=True)
 
 
 @pytest.mark.parametrize("seed", [1, 2])
@@ -136,6 +148,8 @@ def test_cantilever_materials(kind):
 @pytest.mark.parametrize("history", [0, 1, 2, 8])
 def test_history_window(history):
     _trajectory_parity(W.workload_cantilever(0), 20, history=history)
+    _trajectory_parity(W.workload_cantilever(0), 10, history=history, sched="levels")
+    _trajectory_parity(W.workload_cantilever(0), 10, history=history, sched="subtrees")
 
 
 def test_ragged_small_meshes():
@@ -208,6 +222,29 @@ def test_infeasible_inertial_target_falls_back():
     x, vv, st = s.step(w.rest, v, w.h)
     assert st["fallbacks"] == r.fallbacks >= 1
     assert _eps(x, r.x, w.rest) <= 1e-9
+
+
+@pytest.mark.parametrize("sched", ["levels", "subtrees", "default"])
+def test_block_solve_full_size(sched):
+    """r = A^{-1} q on the 40^3 block (67,240 unknowns x 3) under the solve
+    schedules, against the oracle's banded solve."""
+    w = W.workload_block(W.NEOHOOKEAN, n=40)
+    s = qnsim.sim_from_workload(w, **SCHEDULES[sched])
+    info = s.factor_info()
+    assert (info["dense_top_cols"] > 0) == (SCHEDULES[sched]["dense_top"] > 0)
+    assert (info["subtree_levels"] > 0) == (SCHEDULES[sched]["subtree_cap"] > 0)
+    m = _model(w)
+    q = np.random.default_rng(5).normal(size=(w.n_verts, 3))
+    r_ref = np.zeros_like(q)
+    r_ref[m.free] = m.solve(q[m.free])
+    r = torch.empty(w.n_verts, 3, dtype=torch.float64, device="cuda")
+    s.solve_device(_dev(q), r)
+    torch.cuda.synchronize()
+    r = r.cpu().numpy()
+    err = np.abs(r - r_ref).max() / np.abs(r_ref).max()
+    print(f"block solve {sched} (top {info['dense_top_cols']} cols, subtree levels "
+          f"{info['subtree_levels']}, {info['n_levels']} levels): rel err {err:.3e}", flush=True)
+    assert err <= 1e-12
 
 
 @pytest.mark.parametrize("kind", [W.NEOHOOKEAN, W.STVK, W.SPLINE])

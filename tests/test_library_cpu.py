@@ -60,12 +60,14 @@ def test_host_stiffness_per_element_materials():
     assert np.abs(s.stiffness() - m.k).max() <= 1e-13 * np.abs(m.k).max()
 
 
+@pytest.mark.parametrize("dense_top", [0, 64, 6144])
 @pytest.mark.parametrize("dims", [(10, 3, 3), (7, 5, 3), (1, 1, 1), (12, 10, 9)])
-def test_host_factor_reproduces_A(dims):
+def test_host_factor_reproduces_A(dims, dense_top):
     """L L^T equals the oracle's A (permuted) to rounding: the ordering,
-    symbolic structure, amalgamation and numeric factorisation together."""
+    symbolic structure, amalgamation, dense top block renumbering and numeric
+    factorisation together."""
     w = W.workload_cantilever(0, dims=dims)
-    s = qnsim.sim_from_workload(w, prepare=False)
+    s = qnsim.sim_from_workload(w, prepare=False, dense_top=dense_top)
     m = _model(w)
     perm, cp, ri, va = s.export_factor()
     nf = len(perm)
@@ -89,6 +91,8 @@ def test_block_factor_statistics():
     assert info["n_free"] == 67240
     assert info["nnz_L_exact"] < 40e6
     assert info["n_levels"] <= 20
+    # the top separators are merged into one dense block of bounded size
+    assert 0 < info["dense_top_cols"] <= 6144
 
 
 def test_errors_are_reported_not_raised_across_the_abi():
@@ -119,16 +123,20 @@ def test_errors_are_reported_not_raised_across_the_abi():
     assert s.factor_info()["n_free"] == 3
 
 
+@pytest.mark.parametrize("sched", [dict(dense_top=0, subtree_cap=0), dict(dense_top=0, subtree_cap=384),
+                                   dict(dense_top=64, subtree_cap=384), dict()],
+                         ids=["levels", "subtrees", "subtrees+top", "default"])
 @pytest.mark.parametrize("w", [W.workload_cantilever(0), W.workload_cantilever(0, dims=(1, 1, 1)),
-                               W.workload_block(W.SPLINE, n=12)],
-                         ids=["cantilever", "one-cube", "block12"])
-def test_solve_schedule_self_check_passes_on_host(w):
-    """qnsim_prepare builds the solve schedule and checks it on the host before
-    selecting a device; without a GPU it must get as far as hipSetDevice."""
+                               W.workload_block(W.SPLINE, n=12), W.workload_block(W.SPLINE, n=20)],
+                         ids=["cantilever", "one-cube", "block12", "block20"])
+def test_solve_schedule_self_check_passes_on_host(w, sched):
+    """qnsim_prepare builds the solve schedule (per-level items, bottom
+    subtrees, dense top block) and checks it on the host before selecting a
+    device; without a GPU it must get as far as hipSetDevice."""
     import torch
     if torch.cuda.is_available():
         pytest.skip("GPU present: prepare succeeds instead")
-    s = qnsim.sim_from_workload(w, prepare=False)
+    s = qnsim.sim_from_workload(w, prepare=False, **sched)
     with pytest.raises(qnsim.QnsimError) as e:
         s.prepare(w.h)
     assert "hipSetDevice" in str(e.value), str(e.value)
