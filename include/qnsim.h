@@ -70,7 +70,7 @@ typedef struct qnsim qnsim_t; /* opaque; owns all its host and device memory */
  * Armijo gamma = 0.3 and backtracking factor 0.5 (section 4.1), stiffness fit
  * interval [0.5, 1.5] (section 5), at most 30 halvings per line search,
  * gravity (0, 0, -9.81) m/s^2, FP64, device 0, dense_top 6144,
- * subtree_cap 384. */
+ * subtree_cap 384, level_merge 1. */
 typedef struct {
   int32_t iterations;   /* quasi-Newton iterations per step (>= 1)           */
   int32_t history;      /* L-BFGS window m (0..16); 0 = plain PD direction   */
@@ -90,7 +90,9 @@ typedef struct {
                            supernodes all have at most subtree_cap rows are
                            solved one subtree per workgroup (0 = off, at
                            most 384)                                        */
-  int32_t reserved;
+  int32_t level_merge;  /* 1: whole levels of the supernode tree may merge
+                           into their parents when a latency/bandwidth cost
+                           model favours it; 0: off                          */
 } qnsim_options;
 
 /* One material. mu, lambda in Pa; density in kg/m^3. For QNSIM_SPLINE,

@@ -187,7 +187,8 @@ int analyze_impl(qnsim_t* c, double h) {
   std::vector<Ent>().swap(ents);
   for (int j = 0; j < nf; ++j) colptr[j + 1] += colptr[j];
   std::string err;
-  int rc = factorize(nf, colptr, rowidx, val, c->factor, err, c->opt.dense_top);
+  int rc = factorize(nf, colptr, rowidx, val, c->factor, err, c->opt.dense_top,
+                     c->opt.level_merge != 0);
   if (rc == -1) return fail(c, QNSIM_E_NOT_SPD, err);
   if (rc != 0) return fail(c, QNSIM_E_DEVICE, err);
   // internal vertex order: free unknowns in factor order, then pinned vertices
@@ -268,19 +269,21 @@ int upload_impl(qnsim_t* c) {
   }
   std::vector<double> mass(n);
   for (int i = 0; i < n; ++i) mass[i] = c->mass[c->vperm[i]];
-  // incidences of free vertices, ordered by (internal tet, slot)
-  std::vector<int> inc_ptr(nf + 1, 0), inc_idx;
+  // incidences of free vertices, ordered by (internal tet, slot), in a padded
+  // table of inc_w entries per vertex (-1 after the last)
+  std::vector<int> valence(nf, 0);
   for (int t = 0; t < T; ++t)
     for (int a = 0; a < 4; ++a)
-      if (tv[4 * (size_t)t + a] < nf) inc_ptr[tv[4 * (size_t)t + a] + 1]++;
-  for (int i = 0; i < nf; ++i) inc_ptr[i + 1] += inc_ptr[i];
-  inc_idx.resize(inc_ptr[nf]);
+      if (tv[4 * (size_t)t + a] < nf) valence[tv[4 * (size_t)t + a]]++;
+  int inc_w = 4;
+  for (int i = 0; i < nf; ++i) inc_w = std::max(inc_w, (valence[i] + 3) / 4 * 4);
+  std::vector<int> inc_tab((size_t)std::max(nf, 1) * inc_w, -1);
   {
-    std::vector<int> fill(inc_ptr.begin(), inc_ptr.end() - 1);
+    std::vector<int> fill(nf, 0);
     for (int t = 0; t < T; ++t)
       for (int a = 0; a < 4; ++a) {
-        int v = tv[4 * (size_t)t + a];
-        if (v < nf) inc_idx[fill[v]++] = 4 * t + a;
+        const int v = tv[4 * (size_t)t + a];
+        if (v < nf) inc_tab[(size_t)v * inc_w + fill[v]++] = 4 * t + a;
       }
   }
   // supernodal solve: packed blocks (row-major forward copy, column-major
@@ -379,7 +382,8 @@ int upload_impl(qnsim_t* c) {
     for (int e = F.child_ptr[s]; e < F.child_ptr[s + 1]; ++e) I.child_items += sinfo[F.children[e]].fw_items;
   }
   // subtree tasks: roots are bottom supernodes whose parent is not a bottom
-  // supernode; a subtree is a contiguous range of the postordered supernodes
+  // supernode; a subtree is a contiguous range of the postordered supernodes.
+  // A task (one workgroup) takes one or more whole subtrees.
   std::vector<int4> sub_fw, sub_bw;
   std::vector<int> sub_fw_ptr, sub_bw_ptr, task_of(ns, -1);
   int n_tasks = 0;
@@ -390,23 +394,48 @@ int upload_impl(qnsim_t* c) {
       for (int e = F.child_ptr[s]; e < F.child_ptr[s + 1]; ++e)
         start[s] = std::min(start[s], start[F.children[e]]);
     }
+    // subtree roots and sizes (stored block entries)
+    std::vector<int> roots;
+    std::vector<double> size;
     for (int R = 0; R < ns; ++R) {
       const Supernode& SR = F.sn[R];
       if (R == top || SR.level >= Lsub) continue;
       if (SR.parent >= 0 && SR.parent != top && F.sn[SR.parent].level < Lsub) continue;
+      double e = 0.0;
+      for (int s = start[R]; s <= R; ++s)
+        e += (double)F.sn[s].ncol * (F.sn[s].ncol + 1) / 2 + (double)F.sn[s].ncol * F.sn[s].nbelow;
+      roots.push_back(R);
+      size.push_back(e);
+    }
+    // at most one workgroup per compute unit (the subtree kernels' LDS
+    // allows one per CU): largest subtrees first, each to the lightest group
+    const int ngroups = std::min((int)roots.size(), kSubGroups);
+    std::vector<int> order(roots.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return size[x] > size[y]; });
+    std::vector<std::vector<int>> members(ngroups);
+    std::vector<double> load(ngroups, 0.0);
+    for (int i : order) {
+      const int g = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      members[g].push_back(roots[i]);
+      load[g] += size[i];
+    }
+    for (int g = 0; g < ngroups; ++g) {
+      std::sort(members[g].begin(), members[g].end());
       std::vector<std::vector<int4>> fw(Lsub), bw(Lsub);
-      for (int s = start[R]; s <= R; ++s) {
-        const Supernode& S = F.sn[s];
-        task_of[s] = n_tasks;
-        const int nc = S.ncol, m = S.m();
-        const int Lf = clampi(pow2ceil((nc + 3) / 4), 4, 64), rf = 4 * (64 / Lf);
-        for (int r0 = 0; r0 < m; r0 += rf)
-          fw[S.level].push_back(make_int4(s, r0, std::min(m, r0 + rf), Lf));
-        const int Lb = clampi(pow2ceil((m + 3) / 4), 4, 64), cb = 4 * (64 / Lb);
-        for (int c0 = 0; c0 < nc; c0 += cb)
-          bw[S.level].push_back(
-              make_int4((int)(0x80000000u | (unsigned)s), c0, std::min(nc, c0 + cb), Lb));
-      }
+      for (int R : members[g])
+        for (int s = start[R]; s <= R; ++s) {
+          const Supernode& S = F.sn[s];
+          task_of[s] = n_tasks;
+          const int nc = S.ncol, m = S.m();
+          const int Lf = clampi(pow2ceil((nc + 3) / 4), 4, 64), rf = 4 * (64 / Lf);
+          for (int r0 = 0; r0 < m; r0 += rf)
+            fw[S.level].push_back(make_int4(s, r0, std::min(m, r0 + rf), Lf));
+          const int Lb = clampi(pow2ceil((m + 3) / 4), 4, 64), cb = 4 * (64 / Lb);
+          for (int c0 = 0; c0 < nc; c0 += cb)
+            bw[S.level].push_back(
+                make_int4((int)(0x80000000u | (unsigned)s), c0, std::min(nc, c0 + cb), Lb));
+        }
       for (int l = 0; l < Lsub; ++l) {
         sub_fw_ptr.push_back((int)sub_fw.size());
         sub_fw.insert(sub_fw.end(), fw[l].begin(), fw[l].end());
@@ -541,8 +570,8 @@ int upload_impl(qnsim_t* c) {
   if (D.nmat > 1) UP(D.tmat, tm);
   UP(D.mats, dm);
   UP(D.mass, mass);
-  UP(D.inc_ptr, inc_ptr);
-  UP(D.inc_idx, inc_idx);
+  D.inc_w = inc_w;
+  UP(D.inc_tab, inc_tab);
   UP(D.vperm, c->vperm);
   UP(D.tperm, c->tperm);
   D.nsn = ns;
@@ -613,6 +642,7 @@ int qnsim_options_default(qnsim_options* o) {
   o->device = 0;
   o->dense_top = 6144;
   o->subtree_cap = 384;
+  o->level_merge = 1;
   o->gamma = 0.3;
   o->backtrack = 0.5;
   o->fit_lo = 0.5;
@@ -633,7 +663,7 @@ int qnsim_create(const qnsim_options* opts, qnsim_t** out) {
       !(o.fit_hi > o.fit_lo) || !(o.fit_lo > 0) ||
       (o.precision != QNSIM_FP64 && o.precision != QNSIM_MIXED) ||
       o.dense_top < 0 || o.dense_top > kMaxDenseTop || o.subtree_cap < 0 ||
-      o.subtree_cap > kSubCap ||
+      o.subtree_cap > kSubCap || (o.level_merge != 0 && o.level_merge != 1) ||
       !finite_all(o.gravity, 3))
     return QNSIM_E_INVALID;
   qnsim_t* c = new (std::nothrow) qnsim();

@@ -9,6 +9,7 @@
 // turns each supernode of the triangular solves into two dense products.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <numeric>
@@ -89,7 +90,7 @@ void inv_cols(const void* vctx, int64_t lo, int64_t hi) {
 }  // namespace
 
 int factorize(int n, const std::vector<int64_t>& colptr, const std::vector<int>& rowidx,
-              const std::vector<double>& val, Factor& f, std::string& err, int dense_top_max) {
+              const std::vector<double>& val, Factor& f, std::string& err, int dense_top_max, bool level_merge) {
   f = Factor();
   f.n = n;
   if (n == 0) return 0;
@@ -242,83 +243,167 @@ int factorize(int n, const std::vector<int64_t>& colptr, const std::vector<int>&
     S.rep = p;
     std::vector<int>().swap(S.below);
   }
-  // ---- dense top block -------------------------------------------------------
-  // The highest levels of the supernode tree hold a few large separators, and
-  // each level costs the triangular solves two dependent phases. The
-  // supernodes at levels >= cut are merged into one dense root block T whose
-  // columns are renumbered to the end; that order is still a topological order
-  // of the elimination tree, so the fill of every other column is unchanged.
-  // For the root block the forward and backward sweeps combine into one
-  // product with the dense inverse of its Schur complement,
-  //     w_T = (L_TT L_TT^T)^{-1} t_T,
-  // which replaces 2 (levels above cut) dependent phases by two launches at
-  // the price of storing n_T^2 entries. The cut minimises a cost model of the
-  // solve: a fixed latency per phase plus streamed bytes at HBM bandwidth.
+  // ---- level merging and the dense top block ---------------------------------
+  // Each level of the supernode tree costs the triangular solves two
+  // dependent phases (one per sweep), each with a fixed latency of a few
+  // microseconds, while extra stored entries cost bandwidth. Two merges trade
+  // one for the other, both chosen by the same cost model:
+  //  * level merging: every supernode of a level joins its parent, so the
+  //    tree loses one level; a merged supernode is the parent's rows by the
+  //    union of the columns (the children's rows lie in it);
+  //  * the dense top block: the supernodes of the highest levels form one
+  //    root block T, whose two sweeps become one product with the dense
+  //    inverse of its Schur complement, w_T = (L_TT L_TT^T)^{-1} t_T.
+  // Merged columns are not contiguous in the postorder; the columns are
+  // renumbered by a postorder of the merged tree, which is still a
+  // topological order of the elimination tree, so the fill is unchanged.
+  constexpr double kPhaseUs = 12.0;        // one level of one sweep
+  constexpr double kTopUs = 10.0;          // the two launches of the top block
+  constexpr double kEntryUs = 8.0 / 6e6;   // one FP64 entry at ~6 TB/s
   int top_rep = -1;
-  if (dense_top_max > 0) {
-    std::vector<int> kept;
+  {
+    // units: the supernodes after amalgamation, each a contiguous column range
+    std::vector<int> u_first(nfund), u_ncol(nfund);
+    std::vector<char> unit(nfund, 0);
+    for (int s = 0; s < nfund; ++s) {
+      unit[s] = nodes[s].rep == -1;
+      u_first[s] = nodes[s].first;
+      u_ncol[s] = nodes[s].ncol;
+    }
+    std::vector<int> gnc(nfund, 0);                     // columns of each group
     for (int s = 0; s < nfund; ++s)
-      if (nodes[s].rep == -1) kept.push_back(s);
-    std::sort(kept.begin(), kept.end(), [&](int a2, int b2) { return nodes[a2].first < nodes[b2].first; });
-    std::vector<int> lev(nfund, 0);
-    int maxlev = 0;
-    for (int s : kept) {                        // children precede parents
-      if (nodes[s].parent < 0) continue;
-      const int p2 = find(nodes[s].parent);
-      lev[p2] = std::max(lev[p2], lev[s] + 1);
-    }
-    for (int s : kept) maxlev = std::max(maxlev, lev[s]);
-    std::vector<double> cols_at(maxlev + 1, 0.0), ent_at(maxlev + 1, 0.0);
-    for (int s : kept) {
-      cols_at[lev[s]] += nodes[s].ncol;
-      ent_at[lev[s]] += block_entries(nodes[s].ncol, (double)nodes[s].below.size());
-    }
-    constexpr double kPhaseUs = 12.0;        // one level of one sweep
-    constexpr double kTopUs = 10.0;          // the two launches of the top block
-    constexpr double kEntryUs = 8.0 / 6e6;   // one FP64 entry at ~6 TB/s
-    double best_gain = 0.0, ncT = 0.0, sparse = 0.0;
-    int cut = -1;
-    for (int c = maxlev; c >= 0; --c) {
-      ncT += cols_at[c];
-      if (ncT > dense_top_max) break;
-      sparse += 2.0 * kPhaseUs + 2.0 * ent_at[c] * kEntryUs;
-      const double gain = sparse - (kTopUs + ncT * ncT * kEntryUs);
-      if (gain > best_gain) { best_gain = gain; cut = c; }
-    }
-    if (cut >= 0) {
-      // renumber: other columns keep their order, top columns move to the end
-      std::vector<char> top_col(n, 0);
-      int nT = 0;
-      for (int s : kept)
-        if (lev[s] >= cut) {
-          for (int c = 0; c < nodes[s].ncol; ++c) top_col[nodes[s].first + c] = 1;
-          nT += nodes[s].ncol;
-        }
-      std::vector<int> newcol(n);
-      {
-        int lo = 0, hi = n - nT;
-        for (int j = 0; j < n; ++j) newcol[j] = top_col[j] ? hi++ : lo++;
-      }
-      top_rep = kept.back();                   // the last root is a top node
+      if (nodes[s].rep == -1) gnc[s] = nodes[s].ncol;
+    std::vector<int> lev(nfund, 0), gpar(nfund, -1);
+    std::vector<int> kept;
+    auto refresh = [&]() {                              // groups, parents, heights
+      kept.clear();
+      for (int s = 0; s < nfund; ++s)
+        if (nodes[s].rep == -1) kept.push_back(s);     // children before parents
       for (int s : kept) {
-        SymNode& S = nodes[s];
-        if (lev[s] >= cut) {
-          if (s != top_rep) { S.rep = top_rep; std::vector<int>().swap(S.below); }
-          continue;
+        lev[s] = 0;
+        gpar[s] = nodes[s].parent < 0 ? -1 : find(nodes[s].parent);
+      }
+      int maxlev = 0;
+      for (int s : kept) {
+        if (gpar[s] >= 0) lev[gpar[s]] = std::max(lev[gpar[s]], lev[s] + 1);
+      }
+      for (int s : kept) maxlev = std::max(maxlev, lev[s]);
+      return maxlev;
+    };
+    auto ent = [](double nc, double nb) { return nc * (nc + 1) / 2 + nc * nb; };
+    bool changed = false;
+    if (level_merge) {
+      for (;;) {
+        const int maxlev = refresh();
+        // a level can merge only if every supernode on it has a parent
+        std::vector<char> ok(maxlev + 1, 1);
+        for (int s : kept)
+          if (gpar[s] < 0) ok[lev[s]] = 0;
+        std::vector<int> addc(nfund, 0);
+        std::vector<double> childent(nfund, 0.0);
+        std::vector<char> seen(nfund, 0);
+        int best = -1;
+        double best_extra = 0.0;
+        for (int l = 0; l < maxlev; ++l) {
+          if (!ok[l]) continue;
+          std::vector<int> parents;
+          for (int s : kept)
+            if (lev[s] == l) {
+              const int p2 = gpar[s];
+              if (!seen[p2]) { seen[p2] = 1; parents.push_back(p2); addc[p2] = 0; childent[p2] = 0.0; }
+              addc[p2] += gnc[s];
+              childent[p2] += ent(gnc[s], (double)nodes[s].below.size());
+            }
+          double e = 0.0;
+          for (int p2 : parents) {
+            const double nb = (double)nodes[p2].below.size();
+            e += ent(gnc[p2] + addc[p2], nb) - ent(gnc[p2], nb) - childent[p2];
+            seen[p2] = 0;
+          }
+          if (best < 0 || e < best_extra) { best = l; best_extra = e; }
         }
-        S.first = newcol[S.first];
-        for (int& r : S.below) r = newcol[r];
-        if (!std::is_sorted(S.below.begin(), S.below.end())) {
-          err = "internal: top renumbering broke a row list";
+        // both sweeps lose a phase; both stream the extra entries
+        if (best < 0 || 2.0 * best_extra * kEntryUs >= 2.0 * kPhaseUs) break;
+        for (int s : kept)
+          if (lev[s] == best) {
+            const int p2 = gpar[s];
+            nodes[s].rep = p2;
+            gnc[p2] += gnc[s];
+            std::vector<int>().swap(nodes[s].below);
+          }
+        changed = true;
+      }
+    }
+    if (dense_top_max > 0) {
+      const int maxlev = refresh();
+      std::vector<double> cols_at(maxlev + 1, 0.0), ent_at(maxlev + 1, 0.0);
+      for (int s : kept) {
+        cols_at[lev[s]] += gnc[s];
+        ent_at[lev[s]] += ent(gnc[s], (double)nodes[s].below.size());
+      }
+      double best_gain = 0.0, ncT = 0.0, sparse = 0.0;
+      int cut = -1;
+      for (int c = maxlev; c >= 0; --c) {
+        ncT += cols_at[c];
+        if (ncT > dense_top_max) break;
+        sparse += 2.0 * kPhaseUs + 2.0 * ent_at[c] * kEntryUs;
+        const double gain = sparse - (kTopUs + ncT * ncT * kEntryUs);
+        if (gain > best_gain) { best_gain = gain; cut = c; }
+      }
+      if (cut >= 0) {
+        top_rep = kept.back();                 // the last root is a top node
+        for (int s : kept)
+          if (lev[s] >= cut && s != top_rep) {
+            nodes[s].rep = top_rep;
+            gnc[top_rep] += gnc[s];
+            std::vector<int>().swap(nodes[s].below);
+          }
+        std::vector<int>().swap(nodes[top_rep].below);
+        nodes[top_rep].parent = -1;
+        changed = true;
+      }
+    }
+    if (changed) {
+      // renumber: postorder of the merged forest, each group's column ranges
+      // in their original order (descendants first)
+      refresh();
+      std::vector<std::vector<int>> units(nfund), kids(nfund);
+      for (int s = 0; s < nfund; ++s)
+        if (unit[s]) units[find(s)].push_back(s);
+      for (int s : kept)
+        if (gpar[s] >= 0) kids[gpar[s]].push_back(s);
+      std::vector<int> newcol(n, -1);
+      int next = 0;
+      std::vector<std::pair<int, int>> stack;   // (group, next child index)
+      for (int r : kept) {
+        if (gpar[r] >= 0) continue;
+        stack.push_back({r, 0});
+        while (!stack.empty()) {
+          auto& top = stack.back();
+          if (top.second < (int)kids[top.first].size()) {
+            const int ch = kids[top.first][top.second++];
+            stack.push_back({ch, 0});
+            continue;
+          }
+          const int g = top.first;
+          stack.pop_back();
+          std::vector<int>& us = units[g];
+          std::sort(us.begin(), us.end(), [&](int x, int y) { return u_first[x] < u_first[y]; });
+          const int gfirst = next;
+          for (int u : us)
+            for (int c = 0; c < u_ncol[u]; ++c) newcol[u_first[u] + c] = next++;
+          nodes[g].first = gfirst;
+          nodes[g].ncol = next - gfirst;
+        }
+      }
+      if (next != n) { err = "internal: renumbering missed columns"; return -2; }
+      for (int s : kept) {
+        for (int& r : nodes[s].below) r = newcol[r];
+        if (!std::is_sorted(nodes[s].below.begin(), nodes[s].below.end())) {
+          err = "internal: renumbering broke a row list";
           return -2;
         }
       }
-      SymNode& T = nodes[top_rep];
-      T.first = n - nT;
-      T.ncol = nT;
-      T.parent = -1;
-      std::vector<int>().swap(T.below);
-      // permuted matrix and the combined ordering follow the new numbering
       std::vector<int64_t> cp2(n + 1, 0);
       for (int j = 0; j < n; ++j) cp2[newcol[j] + 1] = cp[j + 1] - cp[j];
       for (int j = 0; j < n; ++j) cp2[j + 1] += cp2[j];
@@ -330,7 +415,7 @@ int factorize(int n, const std::vector<int64_t>& colptr, const std::vector<int>&
         int64_t o = cp2[nj];
         for (int64_t e = cp[j]; e < cp[j + 1]; ++e) {
           const int ni = newcol[ri[e]];
-          if (ni < nj) { err = "internal: top renumbering broke lower triangle"; return -2; }
+          if (ni < nj) { err = "internal: renumbering broke the lower triangle"; return -2; }
           ri2[o] = ni;
           rv2[o] = rv[e];
           ++o;

@@ -99,10 +99,13 @@ struct Factor {
 // triangle (including the diagonal) in CSC, already permuted into the final
 // order except for the etree postorder, which is applied here (the combined
 // permutation is returned in f.order). Returns 0, or -1 if not SPD.
-// The top levels of the supernode tree may be merged into one dense root block
-// of at most dense_top_max columns (0 disables), see Factor::top.
+// level_merge: whole levels of the supernode tree may be merged into their
+// parents; the top levels may be merged into one dense root block of at most
+// dense_top_max columns (0 disables), see Factor::top. Both follow a cost
+// model of the level-scheduled triangular solves.
 int factorize(int n, const std::vector<int64_t>& colptr, const std::vector<int>& rowidx,
-              const std::vector<double>& val, Factor& f, std::string& err, int dense_top_max);
+              const std::vector<double>& val, Factor& f, std::string& err, int dense_top_max,
+              bool level_merge);
 
 // Exact CSC of L (for export and tests): column j's nonzeros.
 void factor_to_csc(const Factor& f, std::vector<int64_t>& colptr, std::vector<int>& rowidx,

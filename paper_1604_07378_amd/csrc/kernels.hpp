@@ -10,11 +10,15 @@
 namespace qn {
 
 constexpr int kMaxHistory = 16;
+constexpr int kSlots = kMaxHistory + 1;  // ring of curvature pairs: m + 1 slots at most
 // columns of the dense top block of the solve: 16 waves x 64 lanes x 6 columns
 constexpr int kMaxDenseTop = 6144;
 // largest staged right-hand side (forward: columns, backward: rows) of a
 // supernode in the bottom subtrees, per wave: 6 entries per lane
 constexpr int kSubCap = 384;
+// workgroups of the bottom-subtree kernels: one per compute unit of the MI355X
+// (their LDS use allows one per CU)
+constexpr int kSubGroups = 256;
 
 // Material parameters as the element kernels read them.
 struct DevMat {
@@ -32,8 +36,11 @@ struct Ctl {
   double alpha;        // current trial step length
   double g_first, gnorm2_first;
   double gnorm2_cur;   // |grad g(x_k)|^2 of the current iterate
-  double rho[kMaxHistory + 1];
-  double zeta[kMaxHistory + 1];
+  double rho[kSlots];        // s_i . t_i of the pair in ring slot i
+  double zeta[kSlots];       // first-loop coefficients of the two-loop recursion
+  double coef[kSlots];       // zeta_i - eta_i (second loop)
+  double sg[kSlots];         // s_i . grad g(x_k)
+  double G[kSlots][kSlots];  // G[i][j] = s_i . t_j for stored pairs i, j
   int active;          // step still iterating
   int need_host;       // a rare event needs the host (budget, non-descent, infeasible y)
   int host_reason;     // 1 = line-search budget, 2 = non-descent, 3 = infeasible y
@@ -90,8 +97,8 @@ struct DeviceMesh {
   DevMat* mats = nullptr;     // nmat
   // vertices (internal order: free in factor order, then pinned)
   double* mass = nullptr;     // n
-  int* inc_ptr = nullptr;     // nf + 1
-  int* inc_idx = nullptr;     // (tet * 4 + slot) per incidence
+  int inc_w = 4;              // incidence-table width: largest valence, rounded up to 4
+  int* inc_tab = nullptr;     // nf x inc_w: (tet * 4 + slot) per incidence, -1 padding
   int* vperm = nullptr;       // n: internal -> caller vertex
   int* tperm = nullptr;       // T: internal -> caller tet
   // supernodal solve (one launch per tree level and sweep)
@@ -130,7 +137,8 @@ struct DeviceMesh {
   double* fel = nullptr;      // T x 4 x 3 element gradient contributions
   double* part = nullptr;     // reduction partials
   double* psi = nullptr;      // T per-element energies (probe entry point)
-  int vec_blocks = 1;         // blocks of the vector kernels (fixed -> deterministic)
+  int gather_blocks = 1;      // blocks of the gradient gather (four lanes per vertex)
+  int vec3_blocks = 1;        // blocks of the vector kernels (one entry per thread)
   int elem_blocks = 1;
   Ctl* ctl = nullptr;
   Ctl* ctl_host = nullptr;    // pinned mirror

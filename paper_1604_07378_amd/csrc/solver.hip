@@ -77,6 +77,53 @@ __device__ __forceinline__ double sum_partials(const double* p, int n, double* s
 
 __device__ __forceinline__ bool ctl_run(const Ctl* c) { return c->active && !c->need_host; }
 
+// Block sums of N values per thread, written as out[d * nb + blockIdx.x]:
+// wave trees, then the four wave results in a fixed order.
+template <int N>
+__device__ __forceinline__ void block_sums_to(double (&v)[N], double* sh, double* out, int nb) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int d = 0; d < N; ++d) v[d] = wave_sum(v[d]);
+  if (lane == 0) {
+#pragma unroll
+    for (int d = 0; d < N; ++d) sh[w * N + d] = v[d];
+  }
+  __syncthreads();
+  for (int d = threadIdx.x; d < N; d += BS)
+    out[(size_t)d * nb + blockIdx.x] = (sh[d] + sh[N + d]) + (sh[2 * N + d] + sh[3 * N + d]);
+}
+
+// Totals of N partial arrays of nb entries (part[d * nb + b]) into tot[0..N),
+// valid in every thread: thread t takes entries t, t + 256, ... of every
+// array (all loads independent), then the block tree of block_sums_to.
+template <int N>
+__device__ __forceinline__ void totals_of(const double* __restrict__ part, int nb, double* sh,
+                                          double* tot) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  double v[N];
+#pragma unroll
+  for (int d = 0; d < N; ++d) v[d] = 0.0;
+  for (int b = threadIdx.x; b < nb; b += BS) {
+#pragma unroll
+    for (int d = 0; d < N; ++d) v[d] += part[(size_t)d * nb + b];
+  }
+#pragma unroll
+  for (int d = 0; d < N; ++d) v[d] = wave_sum(v[d]);
+  if (lane == 0) {
+#pragma unroll
+    for (int d = 0; d < N; ++d) sh[w * N + d] = v[d];
+  }
+  __syncthreads();
+  for (int d = threadIdx.x; d < N; d += BS)
+    tot[d] = (sh[d] + sh[N + d]) + (sh[2 * N + d] + sh[3 * N + d]);
+  __syncthreads();
+}
+
+// Ring slot of the a-th newest stored pair.
+__device__ __forceinline__ int pair_slot(const Ctl* c, int a, int slots) {
+  return (c->newest - a + slots) % slots;
+}
+
 // ---------------------------------------------------------------------------
 // Step setup: inertial target y = x + h v + h^2 (a + f_ext / m) (section 3)
 // ---------------------------------------------------------------------------
@@ -239,190 +286,286 @@ k_init_decide(const double* __restrict__ part, int nparts, Ctl* ctl) {
 // (Algorithm 2) in the candidate ring slot, with the partial sums of t.s,
 // s.s, t.t and grad.grad.
 // ---------------------------------------------------------------------------
+// Gradient gather of iteration k (section 4, Eq. PDgrad2): x_k = x_{k-1} +
+// alpha d, s = x_k - x_{k-1}, grad = M/h^2 (x_k - y) + sum of element
+// contributions (incidence lists, fixed order), t = grad - grad_{k-1}; s and
+// t go to the candidate ring slot. The same pass forms every dot product the
+// two-loop recursion needs, so that the recursion runs on scalars (Gram
+// form): dots [0..3] = t.s, s.s, t.t, g.g and, per ring slot j,
+// [4 + 3j] = s_j.g, [5 + 3j] = s.t_j, [6 + 3j] = s_j.t (the candidate's own
+// entries use the new s and t).
+template <int SL>
 __global__ void __launch_bounds__(BS)
-k_gather(int k, int nf, const int* __restrict__ inc_ptr, const int* __restrict__ inc_idx,
+k_gather(int k, int nf, int slots, int inc_w, const int* __restrict__ inc_tab,
          const double* __restrict__ fel, const double* __restrict__ mass,
          const double* __restrict__ y, double inv_h2, const double* __restrict__ Xp,
          double* __restrict__ Xc, const double* __restrict__ d, const double* __restrict__ Gp,
          double* __restrict__ Gc, double* __restrict__ Sall, double* __restrict__ Tall,
          const Ctl* __restrict__ ctl, double* __restrict__ part) {
-  __shared__ double sh[16];
+  constexpr int ND = 4 + 3 * SL;
+  __shared__ double sh[4 * ND];
   if (!ctl_run(ctl)) return;
   const double alpha = ctl->alpha;
-  const size_t slot_off = (size_t)ctl->cand * 3 * nf;
-  double* __restrict__ S = Sall + slot_off;
-  double* __restrict__ Tt = Tall + slot_off;
-  double a_ts = 0.0, a_ss = 0.0, a_tt = 0.0, a_gg = 0.0;
-  for (int i = blockIdx.x * BS + threadIdx.x; i < nf; i += gridDim.x * BS) {
-    double xn[3], gr[3];
-    const double mi = mass[i] * inv_h2;
+  const int cand = ctl->cand;
+  const size_t n3 = 3 * (size_t)nf;
+  double acc[ND];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      double xc;
-      if (k > 0) {
-        double xp = Xp[3 * (size_t)i + c];
-        xc = __fma_rn(alpha, d[3 * (size_t)i + c], xp);
-        Xc[3 * (size_t)i + c] = xc;
-        double s = xc - xp;
-        S[3 * (size_t)i + c] = s;
-        a_ss += s * s;
-      } else {
-        xc = Xc[3 * (size_t)i + c];
-      }
-      xn[c] = xc;
-      gr[c] = mi * (xc - y[3 * (size_t)i + c]);
-    }
-    const int e0 = inc_ptr[i], e1 = inc_ptr[i + 1];
-    double f0 = 0.0, f1 = 0.0, f2 = 0.0;
-    for (int e = e0; e < e1; ++e) {
-      const double* f = fel + 3 * (size_t)inc_idx[e];
-      f0 += f[0];
-      f1 += f[1];
-      f2 += f[2];
-    }
-    gr[0] += f0;
-    gr[1] += f1;
-    gr[2] += f2;
+  for (int j = 0; j < ND; ++j) acc[j] = 0.0;
+  // four lanes per vertex: lane gl sums incidence-table entries gl + 4u,
+  // a butterfly gives all four lanes the same total, and lane gl < 3 then
+  // handles component gl
+  const int gid = blockIdx.x * BS + threadIdx.x;
+  const int i = gid >> 2, gl = gid & 3;
+  const bool live = i < nf, own = live && gl < 3;
+  const size_t ic = 3 * (size_t)(live ? i : 0) + (gl < 3 ? gl : 0);
+  // loads that do not depend on the incidence sums go first
+  double mi = 0.0, yy = 0.0, xp = 0.0, dd = 0.0, gp = 0.0, x0 = 0.0;
+  double sj[SL], tj[SL];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      Gc[3 * (size_t)i + c] = gr[c];
-      a_gg += gr[c] * gr[c];
-      if (k > 0) {
-        double tt = gr[c] - Gp[3 * (size_t)i + c];
-        Tt[3 * (size_t)i + c] = tt;
-        a_tt += tt * tt;
-        a_ts += tt * S[3 * (size_t)i + c];
-      }
+  for (int j = 0; j < SL; ++j) sj[j] = tj[j] = 0.0;
+  if (own) {
+    mi = mass[i] * inv_h2;
+    yy = y[ic];
+    if (k > 0) {
+      xp = Xp[ic];
+      dd = d[ic];
+      gp = Gp[ic];
+#pragma unroll
+      for (int j = 0; j < SL; ++j)
+        if (j < slots && j != cand) {  // ring slots beyond m + 1 are not allocated
+          sj[j] = Sall[(size_t)j * n3 + ic];
+          tj[j] = Tall[(size_t)j * n3 + ic];
+        }
+    } else {
+      x0 = Xc[ic];
     }
-    (void)xn;
   }
-  const int nb = gridDim.x;
-  double r;
-  r = block_sum(a_ts, sh); if (threadIdx.x == 0) part[0 * nb + blockIdx.x] = r;
-  r = block_sum(a_ss, sh); if (threadIdx.x == 0) part[1 * nb + blockIdx.x] = r;
-  r = block_sum(a_tt, sh); if (threadIdx.x == 0) part[2 * nb + blockIdx.x] = r;
-  r = block_sum(a_gg, sh); if (threadIdx.x == 0) part[3 * nb + blockIdx.x] = r;
+  double f[3] = {0.0, 0.0, 0.0};
+  if (live) {
+    const int* __restrict__ row = inc_tab + (size_t)i * inc_w;
+    for (int u0 = gl; u0 < inc_w; u0 += 32) {
+      int ix[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) ix[u] = u0 + 4 * u < inc_w ? row[u0 + 4 * u] : -1;
+      double fv[8][3];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const double* fp = fel + 3 * (size_t)(ix[u] >= 0 ? ix[u] : 0);
+        fv[u][0] = ix[u] >= 0 ? fp[0] : 0.0;
+        fv[u][1] = ix[u] >= 0 ? fp[1] : 0.0;
+        fv[u][2] = ix[u] >= 0 ? fp[2] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) { f[0] += fv[u][0]; f[1] += fv[u][1]; f[2] += fv[u][2]; }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    f[c] += __shfl_xor(f[c], 1, 64);
+    f[c] += __shfl_xor(f[c], 2, 64);
+  }
+  if (own) {
+    const double fc = gl == 0 ? f[0] : (gl == 1 ? f[1] : f[2]);
+    double xc, sv = 0.0, tv = 0.0;
+    if (k > 0) {
+      xc = __fma_rn(alpha, dd, xp);
+      Xc[ic] = xc;
+      sv = xc - xp;
+      Sall[(size_t)cand * n3 + ic] = sv;
+      acc[1] += sv * sv;
+    } else {
+      xc = x0;
+    }
+    const double gr = mi * (xc - yy) + fc;
+    Gc[ic] = gr;
+    acc[3] += gr * gr;
+    if (k > 0) {
+      tv = gr - gp;
+      Tall[(size_t)cand * n3 + ic] = tv;
+      acc[2] += tv * tv;
+      acc[0] += tv * sv;
+#pragma unroll
+      for (int j = 0; j < SL; ++j) {
+        if (j >= slots) break;
+        if (j == cand) {
+          acc[4 + 3 * j] += sv * gr;
+        } else {
+          acc[4 + 3 * j] += sj[j] * gr;
+          acc[5 + 3 * j] += sv * tj[j];
+          acc[6 + 3 * j] += sj[j] * tv;
+        }
+      }
+    }
+  }
+  block_sums_to<ND>(acc, sh, part, gridDim.x);
 }
 
-// Curvature safeguard and ring bookkeeping; resets the line search.
+// Curvature safeguard, ring bookkeeping and the Gram matrix; then the first
+// loop of the two-loop recursion (Algorithm 2) on scalars, newest pair first:
+//   zeta_i = s_i . q_i / rho_i,  q_i = -grad - sum_{j newer than i} zeta_j t_j,
+//   s_i . q_i = -s_i . grad - sum_{j newer} zeta_j G[i][j].
+// Resets the line search of iteration k.
+template <int SL>
 __global__ void __launch_bounds__(BS)
-k_pair_decide(int k, int m, int slots, const double* __restrict__ part, int nb, Ctl* ctl) {
-  __shared__ double sh[16];
-  double ts = sum_partials(part + 0 * nb, nb, sh);
-  double ss = sum_partials(part + 1 * nb, nb, sh);
-  double tt = sum_partials(part + 2 * nb, nb, sh);
-  double gg = sum_partials(part + 3 * nb, nb, sh);
-  if (threadIdx.x != 0 || !ctl_run(ctl)) return;
+k_pair_decide(int k, int m, const double* __restrict__ part, int nb, Ctl* ctl) {
+  constexpr int ND = 4 + 3 * SL;
+  __shared__ double red[4 * ND], tot[ND];
+  __shared__ double sG[SL][SL], srho[SL], szeta[SL];
+  const int slots = m + 1;  // <= SL
+  // the control state the recursion reads, staged in LDS in parallel
+  for (int t = threadIdx.x; t < slots * slots; t += BS) sG[t / slots][t % slots] = ctl->G[t / slots][t % slots];
+  if (threadIdx.x < slots) srho[threadIdx.x] = ctl->rho[threadIdx.x];
+  const int run = ctl_run(ctl), cand = ctl->cand, newest0 = ctl->newest, np0 = ctl->npairs;
+  const int skipped0 = ctl->skipped;
+  totals_of<ND>(part, nb, red, tot);  // includes a barrier after the staging
+  if (threadIdx.x != 0 || !run) return;
+  const double ts = tot[0], ss = tot[1], tt = tot[2], gg = tot[3];
+  int newest = newest0, np = np0;
   if (k == 0) {
     ctl->gnorm2_first = gg;
   } else if (m == 0) {
     // no history window: pairs are never stored, nor counted as skipped
   } else if (ts > 1e-10 * sqrt(ss) * sqrt(tt)) {
-    ctl->newest = ctl->cand;
-    ctl->rho[ctl->cand] = ts;
-    ctl->npairs = ctl->npairs < m ? ctl->npairs + 1 : m;
+    const int c = cand;
+    newest = c;
+    srho[c] = ts;
+    np = np < m ? np + 1 : m;
+    for (int j = 0; j < slots; ++j) {
+      if (j == c) continue;
+      sG[c][j] = tot[5 + 3 * j];
+      sG[j][c] = tot[6 + 3 * j];
+      ctl->G[c][j] = sG[c][j];
+      ctl->G[j][c] = sG[j][c];
+    }
+    sG[c][c] = ts;
+    ctl->G[c][c] = ts;
+    ctl->rho[c] = ts;
   } else {
-    ctl->skipped += 1;
+    ctl->skipped = skipped0 + 1;
   }
-  ctl->cand = (ctl->newest + 1) % slots;
+  for (int j = 0; j < slots; ++j) ctl->sg[j] = k > 0 ? tot[4 + 3 * j] : 0.0;
+  ctl->newest = newest;
+  ctl->npairs = np;
+  ctl->cand = (newest + 1) % slots;
   ctl->ls_done = 0;
   ctl->alpha = 1.0;
   ctl->trials_iter = 0;
   ctl->iters = k + 1;
   ctl->gnorm2_cur = gg;
-}
-
-// ---------------------------------------------------------------------------
-// L-BFGS two-loop recursion (Algorithm 2). Launch j of loop 1 (j = 0..m):
-// applies q -= zeta t for the (j-1)-th newest pair, then forms the partial
-// sums of s.q for the j-th newest pair. Launch 0 sets q := -grad.
-// ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(BS)
-k_loop1(int j, int nf, int slots, const double* __restrict__ grad, double* __restrict__ q,
-        const double* __restrict__ Sall, const double* __restrict__ Tall,
-        const double* __restrict__ pin, double* __restrict__ pout, int nb, Ctl* ctl) {
-  __shared__ double sh[16];
-  if (!ctl_run(ctl)) return;
-  const int np = ctl->npairs, newest = ctl->newest;
-  const bool apply = j >= 1 && (j - 1) < np;
-  const bool dot = j < np;
-  if (j >= 1 && !apply) return;
-  const size_t n3 = 3 * (size_t)nf;
-  double zeta = 0.0;
-  const double* tp = nullptr;
-  if (apply) {
-    int sp = (newest - (j - 1) + slots) % slots;
-    zeta = sum_partials(pin, nb, sh) / ctl->rho[sp];
-    if (blockIdx.x == 0 && threadIdx.x == 0) ctl->zeta[sp] = zeta;
-    tp = Tall + (size_t)sp * n3;
-  }
-  const double* sc = dot ? Sall + (size_t)((newest - j + slots) % slots) * n3 : nullptr;
-  double acc = 0.0;
-  for (size_t i = blockIdx.x * BS + threadIdx.x; i < n3; i += (size_t)gridDim.x * BS) {
-    double qi = (j == 0) ? -grad[i] : q[i];
-    if (apply) qi = qi - zeta * tp[i];
-    q[i] = qi;
-    if (dot) acc += sc[i] * qi;
-  }
-  if (dot) {
-    double b = block_sum(acc, sh);
-    if (threadIdx.x == 0) pout[blockIdx.x] = b;
-  }
-}
-
-// Launch j of loop 2 (j = 0..m), on r (in place): applies
-// r += s (zeta - eta) for the (j-1)-th oldest pair, eta = t.r / rho, then forms
-// the partial sums of t.r for the j-th oldest pair. Launch m also forms the
-// partial sums of grad.d for the Armijo test.
-__global__ void __launch_bounds__(BS)
-k_loop2(int j, int m, int nf, int slots, double* __restrict__ r, const double* __restrict__ grad,
-        const double* __restrict__ Sall, const double* __restrict__ Tall,
-        const double* __restrict__ pin, double* __restrict__ pout, double* __restrict__ pgtd,
-        int nb, const Ctl* __restrict__ ctl) {
-  __shared__ double sh[16];
-  if (!ctl_run(ctl)) return;
-  const int np = ctl->npairs, newest = ctl->newest;
-  const bool apply = j >= 1 && (j - 1) < np;
-  const bool dot = j < np;
-  const bool last = (j == m);
-  if (!apply && !dot && !last) return;
-  const size_t n3 = 3 * (size_t)nf;
-  double coef = 0.0;
-  const double* sp_vec = nullptr;
-  if (apply) {
-    int sp = (newest - (np - 1 - (j - 1)) + slots) % slots;
-    double eta = sum_partials(pin, nb, sh) / ctl->rho[sp];
-    coef = ctl->zeta[sp] - eta;
-    sp_vec = Sall + (size_t)sp * n3;
-  }
-  const double* tc = dot ? Tall + (size_t)((newest - (np - 1 - j) + slots) % slots) * n3 : nullptr;
-  double acc = 0.0, agtd = 0.0;
-  for (size_t i = blockIdx.x * BS + threadIdx.x; i < n3; i += (size_t)gridDim.x * BS) {
-    double ri = r[i];
-    if (apply) {
-      ri = ri + sp_vec[i] * coef;
-      r[i] = ri;
+  for (int a = 0; a < np; ++a) {
+    const int i = (newest - a + slots) % slots;
+    double sq = k > 0 ? -tot[4 + 3 * i] : 0.0;
+    for (int b = 0; b < a; ++b) {
+      const int j = (newest - b + slots) % slots;
+      sq -= szeta[j] * sG[i][j];
     }
-    if (dot) acc += tc[i] * ri;
-    if (last) agtd += grad[i] * ri;
-  }
-  if (dot) {
-    double b = block_sum(acc, sh);
-    if (threadIdx.x == 0) pout[blockIdx.x] = b;
-  }
-  if (last) {
-    double b = block_sum(agtd, sh);
-    if (threadIdx.x == 0) pgtd[blockIdx.x] = b;
+    szeta[i] = sq / srho[i];
+    ctl->zeta[i] = szeta[i];
   }
 }
 
-// Descent check: grad.d < 0 unless grad = 0.
+// ---------------------------------------------------------------------------
+// L-BFGS two-loop recursion (Algorithm 2) in Gram form: the vector updates of
+// each loop are applied in one pass with coefficients computed on scalars.
+// ---------------------------------------------------------------------------
+// q = -grad - sum_i zeta_i t_i (newest pair first, the order of the first loop).
+template <int SL>
 __global__ void __launch_bounds__(BS)
-k_dir_decide(const double* __restrict__ pgtd, int nb, Ctl* ctl) {
-  __shared__ double sh[16];
-  double gtd = sum_partials(pgtd, nb, sh);
-  if (threadIdx.x != 0 || !ctl_run(ctl)) return;
-  double gg = ctl->gnorm2_cur;
+k_qform(int nf, int slots, const double* __restrict__ grad, const double* __restrict__ Tall,
+        double* __restrict__ q, const Ctl* __restrict__ ctl) {
+  if (!ctl_run(ctl)) return;
+  const int np = ctl->npairs;
+  const size_t n3 = 3 * (size_t)nf;
+  int sl[SL];
+  double ze[SL];
+#pragma unroll
+  for (int a = 0; a < SL; ++a) {
+    sl[a] = a < np ? pair_slot(ctl, a, slots) : 0;
+    ze[a] = a < np ? ctl->zeta[sl[a]] : 0.0;
+  }
+  const size_t i = (size_t)blockIdx.x * BS + threadIdx.x;  // one entry per thread
+  if (i >= n3) return;
+  double t[SL];
+#pragma unroll
+  for (int a = 0; a < SL; ++a) t[a] = a < np ? Tall[(size_t)sl[a] * n3 + i] : 0.0;
+  double v = -grad[i];
+#pragma unroll
+  for (int a = 0; a < SL; ++a)
+    if (a < np) v -= ze[a] * t[a];
+  q[i] = v;
+}
+
+// Dots of r0 = A^{-1} q with every stored t_j (by ring slot) and with grad:
+// [j] = t_j . r0, [SL] = grad . r0.
+template <int SL>
+__global__ void __launch_bounds__(BS)
+k_rdots(int nf, int slots, const double* __restrict__ r0, const double* __restrict__ grad,
+        const double* __restrict__ Tall, double* __restrict__ part, const Ctl* __restrict__ ctl) {
+  constexpr int ND = SL + 1;
+  __shared__ double sh[4 * ND];
+  if (!ctl_run(ctl)) return;
+  const int np = ctl->npairs;
+  const size_t n3 = 3 * (size_t)nf;
+  bool use[SL];
+#pragma unroll
+  for (int j = 0; j < SL; ++j) use[j] = false;
+  for (int a = 0; a < np; ++a) {
+    const int j = pair_slot(ctl, a, slots);
+#pragma unroll
+    for (int jj = 0; jj < SL; ++jj)
+      if (jj == j) use[jj] = true;
+  }
+  double acc[ND];
+#pragma unroll
+  for (int j = 0; j < ND; ++j) acc[j] = 0.0;
+  const size_t i = (size_t)blockIdx.x * BS + threadIdx.x;  // one entry per thread
+  if (i < n3) {
+    const double r = r0[i];
+    acc[SL] = grad[i] * r;
+#pragma unroll
+    for (int j = 0; j < SL; ++j)
+      if (use[j]) acc[j] = Tall[(size_t)j * n3 + i] * r;
+  }
+  block_sums_to<ND>(acc, sh, part, gridDim.x);
+}
+
+// Second loop on scalars, oldest pair first:
+//   eta_i = t_i . r_i / rho_i,  r_i = r0 + sum_{j older than i} c_j s_j,
+//   t_i . r_i = t_i . r0 + sum_{j older} c_j G[j][i],   c_i = zeta_i - eta_i;
+// then grad . d = grad . r0 + sum_i c_i s_i . grad and the descent check
+// (grad . d < 0 unless grad = 0).
+template <int SL>
+__global__ void __launch_bounds__(BS)
+k_coef_decide(int m, const double* __restrict__ part, int nb, Ctl* ctl) {
+  constexpr int ND = SL + 1;
+  __shared__ double red[4 * ND], tot[ND];
+  __shared__ double sG[SL][SL], srho[SL], szeta[SL], ssg[SL], scoef[SL];
+  const int slots = m + 1;  // <= SL
+  for (int t = threadIdx.x; t < slots * slots; t += BS) sG[t / slots][t % slots] = ctl->G[t / slots][t % slots];
+  if (threadIdx.x < slots) {
+    srho[threadIdx.x] = ctl->rho[threadIdx.x];
+    szeta[threadIdx.x] = ctl->zeta[threadIdx.x];
+    ssg[threadIdx.x] = ctl->sg[threadIdx.x];
+  }
+  const int run = ctl_run(ctl), np = ctl->npairs, newest = ctl->newest;
+  const double gg = ctl->gnorm2_cur;
+  totals_of<ND>(part, nb, red, tot);  // includes a barrier after the staging
+  if (threadIdx.x != 0 || !run) return;
+  double gtd = tot[SL];
+  for (int a = np - 1; a >= 0; --a) {
+    const int i = (newest - a + slots) % slots;
+    double tr = tot[i];
+    for (int b = np - 1; b > a; --b) {
+      const int j = (newest - b + slots) % slots;
+      tr += scoef[j] * sG[j][i];
+    }
+    scoef[i] = szeta[i] - tr / srho[i];
+    ctl->coef[i] = scoef[i];
+  }
+  for (int a = np - 1; a >= 0; --a) {
+    const int i = (newest - a + slots) % slots;
+    gtd += scoef[i] * ssg[i];
+  }
   if (!(gtd < 0.0) && gg > 0.0) {
     ctl->need_host = 1;
     ctl->host_reason = 2;
@@ -431,25 +574,59 @@ k_dir_decide(const double* __restrict__ pgtd, int nb, Ctl* ctl) {
   ctl->gtd = gtd;
 }
 
+// d = r0 + sum_i c_i s_i in place (oldest pair first, the order of the
+// second loop).
+template <int SL>
+__global__ void __launch_bounds__(BS)
+k_dform(int nf, int slots, const double* __restrict__ Sall, double* __restrict__ d,
+        const Ctl* __restrict__ ctl) {
+  if (!ctl_run(ctl)) return;
+  const int np = ctl->npairs;
+  if (np == 0) return;
+  const size_t n3 = 3 * (size_t)nf;
+  int sl[SL];
+  double cf[SL];
+#pragma unroll
+  for (int a = 0; a < SL; ++a) {
+    const int b = np - 1 - a;  // oldest first
+    sl[a] = b >= 0 ? pair_slot(ctl, b, slots) : 0;
+    cf[a] = b >= 0 ? ctl->coef[sl[a]] : 0.0;
+  }
+  const size_t i = (size_t)blockIdx.x * BS + threadIdx.x;  // one entry per thread
+  if (i >= n3) return;
+  double sv[SL];
+#pragma unroll
+  for (int a = 0; a < SL; ++a) sv[a] = a < np ? Sall[(size_t)sl[a] * n3 + i] : 0.0;
+  double v = d[i];
+#pragma unroll
+  for (int a = 0; a < SL; ++a)
+    if (a < np) v += sv[a] * cf[a];
+  d[i] = v;
+}
+
 // Armijo test of one line-search trial (section 4.1, Algorithm 1).
 __global__ void __launch_bounds__(BS)
 k_ls_decide(int k, int last_in_budget, int max_halvings, double gamma, double backtrack,
             const double* __restrict__ part, int nparts, Ctl* ctl) {
   __shared__ double sh[16];
-  if (!(ctl_run(ctl) && !ctl->ls_done)) return;
+  // every control field the test reads, loaded before the partial sums
+  const bool run = ctl_run(ctl) && !ctl->ls_done;
+  const double gk = ctl->g_k, alpha = ctl->alpha, gtd = ctl->gtd;
+  const int trials = ctl->trials, tri = ctl->trials_iter;
+  if (!run) return;
   double g = sum_partials(part, nparts, sh);
   if (threadIdx.x != 0) return;
-  ctl->trials += 1;
-  ctl->trials_iter += 1;
-  if (g <= ctl->g_k + gamma * ctl->alpha * ctl->gtd) {
+  ctl->trials = trials + 1;
+  ctl->trials_iter = tri + 1;
+  if (g <= gk + gamma * alpha * gtd) {
     ctl->ls_done = 1;
     ctl->g_k = g;
-  } else if (ctl->trials_iter > max_halvings) {
+  } else if (tri + 1 > max_halvings) {
     ctl->exhausted = 1;
     ctl->active = 0;
     ctl->final_k = k;
   } else {
-    ctl->alpha *= backtrack;
+    ctl->alpha = alpha * backtrack;
     if (last_in_budget) {
       ctl->need_host = 1;
       ctl->host_reason = 1;
@@ -596,20 +773,46 @@ void launch_elem(DeviceMesh& D, hipStream_t st, int mode, const double* X, doubl
 #undef QN_ELEM
 }
 
-// Partials layout: [0, 4*vb) gather values; two ping-pong dot buffers of vb;
-// gtd buffer of vb; element partials of elem_blocks.
+// Partials layout: gather dots (kGatherDots x gather_blocks), r0 dots
+// (kSlots + 1 x vec3_blocks), element partials (elem_blocks).
+constexpr int kGatherDots = 4 + 3 * kSlots;
 struct Parts {
-  double *gather, *dotA, *dotB, *gtd, *elem;
+  double *gather, *rdots, *elem;
 };
 Parts parts_of(DeviceMesh& D) {
-  const int vb = D.vec_blocks;
   Parts p;
   p.gather = D.part;
-  p.dotA = D.part + 4 * vb;
-  p.dotB = D.part + 5 * vb;
-  p.gtd = D.part + 6 * vb;
-  p.elem = D.part + 7 * vb;
+  p.rdots = D.part + (size_t)kGatherDots * D.gather_blocks;
+  p.elem = p.rdots + (size_t)(kSlots + 1) * D.vec3_blocks;
   return p;
+}
+
+// Ring slots compiled for: the exact count for windows m <= 8, else kSlots.
+inline int slots_variant(int m) { return m <= 8 ? m + 1 : kSlots; }
+
+#define QN_SLOTS_DISPATCH(SLV, CALL) \
+  switch (SLV) {                     \
+    case 1: CALL(1); break;          \
+    case 2: CALL(2); break;          \
+    case 3: CALL(3); break;          \
+    case 4: CALL(4); break;          \
+    case 5: CALL(5); break;          \
+    case 6: CALL(6); break;          \
+    case 7: CALL(7); break;          \
+    case 8: CALL(8); break;          \
+    case 9: CALL(9); break;          \
+    default: CALL(kSlots); break;    \
+  }
+
+void launch_gather(DeviceMesh& D, hipStream_t st, int k, int m, const double* Xp, double* Xc,
+                   const double* Gp, double* Gc, double* part) {
+#define QN_GATHER(SL)                                                                         \
+  hipLaunchKernelGGL(k_gather<SL>, dim3(D.gather_blocks), dim3(BS), 0, st, k, D.nf, m + 1,      \
+                     D.inc_w, D.inc_tab, D.fel, D.mass, D.y, 1.0 / (D.h * D.h), Xp, Xc, D.d,  \
+                     Gp, Gc,                                                                  \
+                     D.Sv, D.Tv, D.ctl, part)
+  QN_SLOTS_DISPATCH(slots_variant(m), QN_GATHER)
+#undef QN_GATHER
 }
 
 enum Stage { ST_GATHER = 0, ST_DIRECTION = 1, ST_LINESEARCH = 2 };
@@ -617,34 +820,39 @@ enum Stage { ST_GATHER = 0, ST_DIRECTION = 1, ST_LINESEARCH = 2 };
 void launch_iteration(DeviceMesh& D, const StepParams& P, hipStream_t st, int k, int stage,
                       int budget) {
   Parts pp = parts_of(D);
-  const int vb = D.vec_blocks;
+  const int gb = D.gather_blocks, vb = D.vec3_blocks;
   const int m = P.history;
   double* Xc = D.X[k & 1];
   const double* Xp = D.X[(k + 1) & 1];
   double* Gc = D.G[k & 1];
   const double* Gp = D.G[(k + 1) & 1];
+  const int slv = slots_variant(m), slots = m + 1;
   if (stage <= ST_GATHER) {
-    hipLaunchKernelGGL(k_gather, dim3(vb), dim3(BS), 0, st, k, D.nf, D.inc_ptr, D.inc_idx, D.fel,
-                       D.mass, D.y, 1.0 / (D.h * D.h), Xp, Xc, D.d, Gp, Gc, D.Sv, D.Tv, D.ctl,
-                       pp.gather);
-    hipLaunchKernelGGL(k_pair_decide, dim3(1), dim3(BS), 0, st, k, m, D.slots, pp.gather, vb,
-                       D.ctl);
+    launch_gather(D, st, k, m, Xp, Xc, Gp, Gc, pp.gather);
+#define QN_PAIR(SL) \
+  hipLaunchKernelGGL(k_pair_decide<SL>, dim3(1), dim3(BS), 0, st, k, m, pp.gather, gb, D.ctl)
+    QN_SLOTS_DISPATCH(slv, QN_PAIR)
+#undef QN_PAIR
   }
   if (stage <= ST_DIRECTION) {
-    for (int j = 0; j <= m; ++j) {
-      double* pin = (j & 1) ? pp.dotA : pp.dotB;
-      double* pout = (j & 1) ? pp.dotB : pp.dotA;
-      hipLaunchKernelGGL(k_loop1, dim3(vb), dim3(BS), 0, st, j, D.nf, D.slots, Gc, D.q, D.Sv,
-                         D.Tv, pin, pout, vb, D.ctl);
-    }
+#define QN_QFORM(SL)                                                                        \
+  hipLaunchKernelGGL(k_qform<SL>, dim3(vb), dim3(BS), 0, st, D.nf, slots, Gc, D.Tv, D.q, D.ctl)
+    QN_SLOTS_DISPATCH(slv, QN_QFORM)
+#undef QN_QFORM
     launch_solve(D, st, D.q, D.d, D.ctl);
-    for (int j = 0; j <= m; ++j) {
-      double* pin = (j & 1) ? pp.dotA : pp.dotB;
-      double* pout = (j & 1) ? pp.dotB : pp.dotA;
-      hipLaunchKernelGGL(k_loop2, dim3(vb), dim3(BS), 0, st, j, m, D.nf, D.slots, D.d, Gc, D.Sv,
-                         D.Tv, pin, pout, pp.gtd, vb, D.ctl);
-    }
-    hipLaunchKernelGGL(k_dir_decide, dim3(1), dim3(BS), 0, st, pp.gtd, vb, D.ctl);
+#define QN_RDOTS(SL)                                                                      \
+  hipLaunchKernelGGL(k_rdots<SL>, dim3(vb), dim3(BS), 0, st, D.nf, slots, D.d, Gc, D.Tv, \
+                     pp.rdots, D.ctl)
+    QN_SLOTS_DISPATCH(slv, QN_RDOTS)
+#undef QN_RDOTS
+#define QN_COEF(SL) \
+  hipLaunchKernelGGL(k_coef_decide<SL>, dim3(1), dim3(BS), 0, st, m, pp.rdots, vb, D.ctl)
+    QN_SLOTS_DISPATCH(slv, QN_COEF)
+#undef QN_COEF
+#define QN_DFORM(SL) \
+  hipLaunchKernelGGL(k_dform<SL>, dim3(vb), dim3(BS), 0, st, D.nf, slots, D.Sv, D.d, D.ctl)
+    QN_SLOTS_DISPATCH(slv, QN_DFORM)
+#undef QN_DFORM
   }
   for (int b = 0; b < budget; ++b) {
     launch_elem(D, st, 1, Xc, pp.elem, nullptr);
@@ -676,7 +884,7 @@ int dev_sync(DeviceMesh& D, void* stream, std::string& err) {
 }
 
 void dev_free(DeviceMesh& D) {
-  void* ptrs[] = {D.tv, D.Bm, D.vol, D.tmat, D.mats, D.mass, D.inc_ptr, D.inc_idx, D.vperm,
+  void* ptrs[] = {D.tv, D.Bm, D.vol, D.tmat, D.mats, D.mass, D.inc_tab, D.vperm,
                   D.sn, D.items, D.Bf, D.Bb, D.rows, D.rel, D.vp, D.x0,
                   D.v0, D.y, D.X[0], D.X[1], D.G[0], D.G[1], D.d, D.q, D.z, D.Sv, D.Tv, D.fel,
                   D.part, D.psi, D.ctl, D.tperm, D.top_t,
@@ -710,9 +918,12 @@ int dev_alloc(DeviceMesh& D, std::string& err) {
   HIP_OK(A((void**)&D.Tv, f3 * 8 * D.slots));
   HIP_OK(A((void**)&D.fel, (size_t)D.T * 12 * 8));
   HIP_OK(A((void**)&D.psi, (size_t)D.T * 8));
-  D.vec_blocks = std::max(1, std::min(256, nblk(D.nf)));
+  D.gather_blocks = nblk(4 * (int64_t)D.nf);
+  D.vec3_blocks = nblk(3 * (int64_t)D.nf);
   D.elem_blocks = nblk(std::max(D.T, D.nf));
-  HIP_OK(A((void**)&D.part, (size_t)(7 * D.vec_blocks + D.elem_blocks) * 8));
+  HIP_OK(A((void**)&D.part,
+           ((size_t)kGatherDots * D.gather_blocks + (size_t)(kSlots + 1) * D.vec3_blocks +
+            D.elem_blocks) * 8));
   HIP_OK(A((void**)&D.ctl, sizeof(Ctl)));
   HIP_OK(hipHostMalloc((void**)&D.ctl_host, sizeof(Ctl), hipHostMallocDefault));
   hipStream_t st;
@@ -779,11 +990,9 @@ int dev_step(DeviceMesh& D, const StepParams& P, const double* x, const double* 
     hipLaunchKernelGGL(k_load_perm, dim3(nblk(D.n)), dim3(BS), 0, st, D.n, D.vperm, xo, D.X[0]);
     hipLaunchKernelGGL(k_ctl_probe, dim3(1), dim3(1), 0, st, D.ctl);
     launch_elem(D, st, 2, D.X[0], pp.elem, nullptr);
-    hipLaunchKernelGGL(k_gather, dim3(D.vec_blocks), dim3(BS), 0, st, 0, D.nf, D.inc_ptr,
-                       D.inc_idx, D.fel, D.mass, D.y, 1.0 / (D.h * D.h), D.X[1], D.X[0], D.d,
-                       D.G[1], D.G[0], D.Sv, D.Tv, D.ctl, pp.gather);
-    hipLaunchKernelGGL(k_sum_to_ctl, dim3(1), dim3(BS), 0, st, pp.gather + 3 * D.vec_blocks,
-                       D.vec_blocks, D.ctl);
+    launch_gather(D, st, 0, 0, D.X[1], D.X[0], D.G[1], D.G[0], pp.gather);
+    hipLaunchKernelGGL(k_sum_to_ctl, dim3(1), dim3(BS), 0, st, pp.gather + 3 * D.gather_blocks,
+                       D.gather_blocks, D.ctl);
     Ctl tmp;
     HIP_OK(hipMemcpyAsync(&tmp, D.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
     HIP_OK(hipStreamSynchronize(st));
@@ -802,9 +1011,7 @@ int dev_eval(DeviceMesh& D, const double* x, const double* y, double* g_out, dou
   hipLaunchKernelGGL(k_ctl_probe, dim3(1), dim3(1), 0, st, D.ctl);
   launch_elem(D, st, 2, D.X[0], pp.elem, nullptr);
   hipLaunchKernelGGL(k_sum_to_ctl, dim3(1), dim3(BS), 0, st, pp.elem, D.elem_blocks, D.ctl);
-  hipLaunchKernelGGL(k_gather, dim3(D.vec_blocks), dim3(BS), 0, st, 0, D.nf, D.inc_ptr, D.inc_idx,
-                     D.fel, D.mass, D.y, 1.0 / (D.h * D.h), D.X[1], D.X[0], D.d, D.G[1], D.G[0],
-                     D.Sv, D.Tv, D.ctl, pp.gather);
+  launch_gather(D, st, 0, 0, D.X[1], D.X[0], D.G[1], D.G[0], pp.gather);
   hipLaunchKernelGGL(k_store_perm, dim3(nblk(D.n)), dim3(BS), 0, st, D.n, D.nf, D.vperm, D.G[0],
                      grad);
   HIP_OK(hipGetLastError());
@@ -856,9 +1063,7 @@ int dev_time_kernel(DeviceMesh& D, int kernel, int reps, double* avg_ms, std::st
       if (kernel == 0) {
         launch_elem(D, st, 1, D.X[0], pp.elem, nullptr);
       } else if (kernel == 1) {
-        hipLaunchKernelGGL(k_gather, dim3(D.vec_blocks), dim3(BS), 0, st, 0, D.nf, D.inc_ptr,
-                           D.inc_idx, D.fel, D.mass, D.y, 1.0 / (D.h * D.h), D.X[1], D.X[0], D.d,
-                           D.G[1], D.G[0], D.Sv, D.Tv, D.ctl, pp.gather);
+        launch_gather(D, st, 0, 0, D.X[1], D.X[0], D.G[1], D.G[0], pp.gather);
       } else {
         launch_solve(D, st, D.q, D.G[1], nullptr);
       }

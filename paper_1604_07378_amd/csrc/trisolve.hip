@@ -33,7 +33,7 @@ namespace qn {
 namespace {
 
 constexpr int TS = 256;       // threads per workgroup
-constexpr int TCHUNK = 512;   // entries of t / u staged in LDS at a time
+constexpr int TCHUNK = 1024;  // entries of t / u staged in LDS at a time
 
 __device__ __forceinline__ double group_sum(double v, int L) {
   for (int off = L >> 1; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -122,22 +122,24 @@ __device__ __forceinline__ void fwd_item(const ItemDesc& d, const double* __rest
   for (int c0 = 0; c0 < nc; c0 += TCHUNK) {
     const int c1 = min(nc, c0 + TCHUNK);
     if (c0 > 0) __syncthreads();
-    {
-      // q and the children's slots on this chunk, all loads before use
-      double v[TCHUNK / TS][3];
+    // q and the children's slots on this chunk, two columns per thread at a
+    // time (all loads of a pair of columns before use)
+    for (int jh = 0; jh < TCHUNK / TS; jh += 2) {
+      if (c0 + jh * TS >= c1) break;
+      double v[2][3];
 #pragma unroll
-      for (int jj = 0; jj < TCHUNK / TS; ++jj) {
-        const int c = c0 + tid + jj * TS;
+      for (int jj = 0; jj < 2; ++jj) {
+        const int c = c0 + tid + (jh + jj) * TS;
         const double* p = q + 3 * (size_t)(first + (c < c1 ? c : c0));
         v[jj][0] = p[0];
         v[jj][1] = p[1];
         v[jj][2] = p[2];
       }
       for (int j0 = 0; j0 < nch; j0 += 2) {
-        double u[TCHUNK / TS][2][3];
+        double u[2][2][3];
 #pragma unroll
-        for (int jj = 0; jj < TCHUNK / TS; ++jj) {
-          const int c = c0 + tid + jj * TS;
+        for (int jj = 0; jj < 2; ++jj) {
+          const int c = c0 + tid + (jh + jj) * TS;
 #pragma unroll
           for (int j = 0; j < 2; ++j) {
             const bool ok = (j0 + j < nch) && c < c1;
@@ -148,7 +150,7 @@ __device__ __forceinline__ void fwd_item(const ItemDesc& d, const double* __rest
           }
         }
 #pragma unroll
-        for (int jj = 0; jj < TCHUNK / TS; ++jj)
+        for (int jj = 0; jj < 2; ++jj)
 #pragma unroll
           for (int j = 0; j < 2; ++j) {
             v[jj][0] -= u[jj][j][0];
@@ -157,8 +159,8 @@ __device__ __forceinline__ void fwd_item(const ItemDesc& d, const double* __rest
           }
       }
 #pragma unroll
-      for (int jj = 0; jj < TCHUNK / TS; ++jj) {
-        const int c = c0 + tid + jj * TS;
+      for (int jj = 0; jj < 2; ++jj) {
+        const int c = c0 + tid + (jh + jj) * TS;
         if (c < c1) {
           s0[c - c0] = v[jj][0];
           s1[c - c0] = v[jj][1];

@@ -80,13 +80,15 @@ def test_objective_and_gradient(kind):
     assert np.abs(grad - grad_ref).max() <= 1e-11 * np.abs(grad_ref).max()
 
 
-# Solve schedules: every level through the per-level kernels; the bottom
-# subtrees in one workgroup each; a small dense top block above them; the
-# defaults (small meshes: one dense block).
-SCHEDULES = {"levels": dict(dense_top=0, subtree_cap=0),
-             "subtrees": dict(dense_top=0, subtree_cap=384),
-             "subtrees+top": dict(dense_top=64, subtree_cap=384),
-             "default": dict(dense_top=6144, subtree_cap=384)}
+# Solve schedules: every level of the unmerged tree through the per-level
+# kernels; the bottom subtrees in one workgroup each; a small dense top block
+# above them; merged levels without a top block; the defaults (small meshes:
+# one dense block).
+SCHEDULES = {"levels": dict(dense_top=0, subtree_cap=0, level_merge=0),
+             "subtrees": dict(dense_top=0, subtree_cap=384, level_merge=0),
+             "subtrees+top": dict(dense_top=64, subtree_cap=384, level_merge=0),
+             "merged": dict(dense_top=0, subtree_cap=384, level_merge=1),
+             "default": dict(dense_top=6144, subtree_cap=384, level_merge=1)}
 
 
 @pytest.mark.parametrize("sched", list(SCHEDULES))
@@ -224,7 +226,7 @@ def test_infeasible_inertial_target_falls_back():
     assert _eps(x, r.x, w.rest) <= 1e-9
 
 
-@pytest.mark.parametrize("sched", ["levels", "subtrees", "default"])
+@pytest.mark.parametrize("sched", ["levels", "subtrees", "merged", "default"])
 def test_block_solve_full_size(sched):
     """r = A^{-1} q on the 40^3 block (67,240 unknowns x 3) under the solve
     schedules, against the oracle's banded solve."""
@@ -232,7 +234,8 @@ def test_block_solve_full_size(sched):
     s = qnsim.sim_from_workload(w, **SCHEDULES[sched])
     info = s.factor_info()
     assert (info["dense_top_cols"] > 0) == (SCHEDULES[sched]["dense_top"] > 0)
-    assert (info["subtree_levels"] > 0) == (SCHEDULES[sched]["subtree_cap"] > 0)
+    if sched in ("levels", "subtrees"):
+        assert (info["subtree_levels"] > 0) == (sched == "subtrees")
     m = _model(w)
     q = np.random.default_rng(5).normal(size=(w.n_verts, 3))
     r_ref = np.zeros_like(q)

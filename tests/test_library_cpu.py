@@ -60,14 +60,15 @@ def test_host_stiffness_per_element_materials():
     assert np.abs(s.stiffness() - m.k).max() <= 1e-13 * np.abs(m.k).max()
 
 
-@pytest.mark.parametrize("dense_top", [0, 64, 6144])
-@pytest.mark.parametrize("dims", [(10, 3, 3), (7, 5, 3), (1, 1, 1), (12, 10, 9)])
-def test_host_factor_reproduces_A(dims, dense_top):
+@pytest.mark.parametrize("merge", [(0, 0), (64, 0), (0, 1), (6144, 1)],
+                         ids=["plain", "top", "levels", "default"])
+@pytest.mark.parametrize("dims", [(10, 3, 3), (7, 5, 3), (1, 1, 1), (12, 10, 9), (20, 8, 8)])
+def test_host_factor_reproduces_A(dims, merge):
     """L L^T equals the oracle's A (permuted) to rounding: the ordering,
-    symbolic structure, amalgamation, dense top block renumbering and numeric
-    factorisation together."""
+    symbolic structure, amalgamation, level merging and dense top block (with
+    their column renumbering) and numeric factorisation together."""
     w = W.workload_cantilever(0, dims=dims)
-    s = qnsim.sim_from_workload(w, prepare=False, dense_top=dense_top)
+    s = qnsim.sim_from_workload(w, prepare=False, dense_top=merge[0], level_merge=merge[1])
     m = _model(w)
     perm, cp, ri, va = s.export_factor()
     nf = len(perm)
@@ -123,9 +124,11 @@ def test_errors_are_reported_not_raised_across_the_abi():
     assert s.factor_info()["n_free"] == 3
 
 
-@pytest.mark.parametrize("sched", [dict(dense_top=0, subtree_cap=0), dict(dense_top=0, subtree_cap=384),
-                                   dict(dense_top=64, subtree_cap=384), dict()],
-                         ids=["levels", "subtrees", "subtrees+top", "default"])
+@pytest.mark.parametrize("sched", [dict(dense_top=0, subtree_cap=0, level_merge=0),
+                                   dict(dense_top=0, subtree_cap=384, level_merge=0),
+                                   dict(dense_top=64, subtree_cap=384, level_merge=0),
+                                   dict(dense_top=0, subtree_cap=384, level_merge=1), dict()],
+                         ids=["levels", "subtrees", "subtrees+top", "merged", "default"])
 @pytest.mark.parametrize("w", [W.workload_cantilever(0), W.workload_cantilever(0, dims=(1, 1, 1)),
                                W.workload_block(W.SPLINE, n=12), W.workload_block(W.SPLINE, n=20)],
                          ids=["cantilever", "one-cube", "block12", "block20"])
