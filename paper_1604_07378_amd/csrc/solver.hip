@@ -26,6 +26,7 @@
 #include "../../include/qnsim.h"
 #include "elastic.hpp"
 #include "kernels.hpp"
+#include "wave.hpp"
 
 namespace qn {
 
@@ -45,10 +46,7 @@ constexpr int BS = 256;          // threads per block of every kernel
 // ---------------------------------------------------------------------------
 // Deterministic reductions
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double wave_sum(double v) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-  return v;
-}
+__device__ __forceinline__ double wave_sum(double v) { return wave_total(v); }
 
 // Sum over the 256 threads of a block; result valid in thread 0.
 __device__ __forceinline__ double block_sum(double v, double* sh) {
@@ -360,10 +358,7 @@ k_gather(int k, int nf, int slots, int inc_w, const int* __restrict__ inc_tab,
     }
   }
 #pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    f[c] += __shfl_xor(f[c], 1, 64);
-    f[c] += __shfl_xor(f[c], 2, 64);
-  }
+  for (int c = 0; c < 3; ++c) f[c] = group_sum(f[c], 4);
   if (own) {
     const double fc = gl == 0 ? f[0] : (gl == 1 ? f[1] : f[2]);
     double xc, sv = 0.0, tv = 0.0;

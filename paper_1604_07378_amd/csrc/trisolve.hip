@@ -27,6 +27,7 @@
 #include <algorithm>
 
 #include "kernels.hpp"
+#include "wave.hpp"
 
 namespace qn {
 
@@ -34,11 +35,6 @@ namespace {
 
 constexpr int TS = 256;       // threads per workgroup
 constexpr int TCHUNK = 1024;  // entries of t / u staged in LDS at a time
-
-__device__ __forceinline__ double group_sum(double v, int L) {
-  for (int off = L >> 1; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
 
 __device__ __forceinline__ long long fw_row_off(int r, int nc) {
   return r < nc ? (long long)r * (r + 1) / 2
