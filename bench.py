@@ -58,7 +58,7 @@ def solve_bytes(nnz_exact, nf):
 def run_material(kind, args, torch, W, qnsim):
     w = W.workload_block(kind, n=args.n)
     t0 = time.time()
-    sim = qnsim.sim_from_workload(w)
+    sim = qnsim.sim_from_workload(w, **args.overrides)
     prep = time.time() - t0
     info = sim.factor_info()
     log(f"[bench] {w.name}: prepared in {prep:.2f}s, nnz(L)={info['nnz_L_exact']}, "
@@ -127,7 +127,13 @@ def main():
     ap.add_argument("--materials", default="neohookean,stvk,spline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=1)
+    ap.add_argument("--set", action="append", default=[], metavar="OPTION=INT",
+                    help="override an integer solver option (e.g. level_merge=0, dense_top=0)")
     args = ap.parse_args()
+    args.overrides = {}
+    for item in args.set:
+        key, _, val = item.partition("=")
+        args.overrides[key.strip()] = int(val)
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -184,6 +190,7 @@ def main():
                         f"materials {args.materials}, FP64, h=1/30 s, 10 iterations, m=5",
             "tets": nh["T"], "verts": nh["n"], "free_verts": nh["nf"],
             "materials": args.materials.split(","),
+            **({"options": args.overrides} if args.overrides else {}),
         },
         "tet_evals_per_s": tet_evals / total_s,
         "runs": [{k: r[k] for k in ("material", "steps_per_s", "ls_trials", "iterations",

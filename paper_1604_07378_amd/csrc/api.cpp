@@ -364,8 +364,31 @@ int upload_impl(qnsim_t* c) {
           make_int4((int)(0x80000000u | (unsigned)s), c0, std::min(nc, c0 + cols_item), Lb));
     I.bw_items = (nc + cols_item - 1) / cols_item;
   }
-  // child slots: supernode P owns nchild(P) slots of m(P) x 3 doubles; the
-  // j-th child writes its update rows into slot j at its relative positions
+  // Update slots: supernode P owns K(P) layers of m(P) x 3 doubles in its own
+  // row space, K(P) = the largest number of children that update one row of
+  // P. The children updating a row take its layers in child order, so every
+  // entry is written by one child at the same place every solve and the
+  // entries nobody writes stay zero; P sums K(P) layers instead of one slot
+  // per child. relL holds each below row's layered position (layer m(P) + row).
+  std::vector<int> relL(F.rel.size(), 0);
+  {
+    std::vector<int> cnt;
+    for (int s = 0; s < ns; ++s) {
+      const int mP = F.sn[s].m();
+      cnt.assign(mP, 0);
+      int K = 0;
+      for (int e = F.child_ptr[s]; e < F.child_ptr[s + 1]; ++e) {
+        const Supernode& C = F.sn[F.children[e]];
+        for (int r = 0; r < C.nbelow; ++r) {
+          const int pos = F.rel[C.rows_off + r];
+          const int layer = cnt[pos]++;
+          K = std::max(K, layer + 1);
+          relL[C.rows_off + r] = layer * mP + pos;
+        }
+      }
+      sinfo[s].nchild = K;
+    }
+  }
   int64_t vp_total = 0;
   for (int s = 0; s < ns; ++s) {
     SnInfo& I = sinfo[s];
@@ -374,8 +397,7 @@ int upload_impl(qnsim_t* c) {
   }
   for (int s = 0; s < ns; ++s)
     for (int e = F.child_ptr[s]; e < F.child_ptr[s + 1]; ++e)
-      sinfo[F.children[e]].vp_out =
-          sinfo[s].vp_in + (int64_t)(e - F.child_ptr[s]) * 3 * (sinfo[s].ncol + sinfo[s].nbelow);
+      sinfo[F.children[e]].vp_out = sinfo[s].vp_in;
   for (int s = 0; s < ns; ++s) {
     SnInfo& I = sinfo[s];
     I.child_items = 0;
@@ -522,25 +544,25 @@ int upload_impl(qnsim_t* c) {
       if (I.rows_off + I.nbelow > (int64_t)F.rows.size() || I.first < 0 || I.first + I.ncol > nf ||
           I.vp_in < 0 || I.vp_in + (int64_t)I.nchild * 3 * (I.ncol + I.nbelow) > vp_total ||
           (I.parent >= 0) != (I.vp_out >= 0) ||
-          (I.parent >= 0 && (I.vp_out < sinfo[I.parent].vp_in ||
-                             I.vp_out + 3 * (int64_t)(sinfo[I.parent].ncol + sinfo[I.parent].nbelow) >
-                                 sinfo[I.parent].vp_in + (int64_t)sinfo[I.parent].nchild * 3 *
-                                     (sinfo[I.parent].ncol + sinfo[I.parent].nbelow))) ||
+          I.parent >= ns || (I.parent >= 0 && I.vp_out != sinfo[I.parent].vp_in) ||
           (I.parent < 0 && I.nbelow != 0))
         return fail(c, QNSIM_E_DEVICE, "schedule: row list or update offset out of range");
       for (int r = 0; r < I.nbelow; ++r) {
         int g = F.rows[I.rows_off + r];
         if (g < I.first + I.ncol || g >= nf) return fail(c, QNSIM_E_DEVICE, "schedule: bad row");
       }
+      if (I.parent >= ns) return fail(c, QNSIM_E_DEVICE, "schedule: bad parent");
       if (I.parent >= 0) {
         const SnInfo& P = sinfo[I.parent];
+        const int mP = P.ncol + P.nbelow;
         for (int r = 0; r < I.nbelow; ++r) {
           const int pos = F.rel[I.rows_off + r];
-          if (pos < 0 || pos >= P.ncol + P.nbelow || (r > 0 && pos <= F.rel[I.rows_off + r - 1]))
+          const int lp = relL[I.rows_off + r];
+          if (pos < 0 || pos >= mP || (r > 0 && pos <= F.rel[I.rows_off + r - 1]) ||
+              lp % mP != pos || lp / mP >= P.nchild)
             return fail(c, QNSIM_E_DEVICE, "schedule: bad relative row");
         }
       }
-      if (I.parent >= ns) return fail(c, QNSIM_E_DEVICE, "schedule: bad parent");
     }
     // topological order: forward items of a supernode come after those of its
     // children, backward items after those of its parent and after all forward items
@@ -611,7 +633,7 @@ int upload_impl(qnsim_t* c) {
   UP(D.Bf, Bf);
   UP(D.Bb, Bb);
   UP(D.rows, F.rows);
-  UP(D.rel, F.rel);
+  UP(D.rel, relL);
 
   {
     std::vector<double> zv((size_t)vp_total + 3, 0.0);  // zero once: see child slots

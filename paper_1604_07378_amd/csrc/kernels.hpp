@@ -63,24 +63,25 @@ struct Level {
 // Per-supernode data of the device triangular solves.
 struct SnInfo {
   int first, ncol, nbelow, parent;
-  int nchild, fw_items, bw_items, child_items;  // child_items: forward items of all children
+  int nchild;          // layers of this supernode's update slots (see vp_in)
+  int fw_items, bw_items, child_items;  // child_items: forward items of all children
   long long fw_off;    // row-major packed [L11^{-1}; L21 L11^{-1}] (forward sweep)
   long long bw_off;    // column-major packed, same blocks (backward sweep)
   long long rows_off;  // below-diagonal row list (and positions in the parent)
-  long long vp_in;     // this supernode's child slots: nchild x (m x 3) doubles
-  long long vp_out;    // where this supernode writes its update rows (parent slot)
+  long long vp_in;     // this supernode's update layers: nchild x (m x 3) doubles
+  long long vp_out;    // its parent's layers (rows written at 3 * layered position)
 };
 
 // One work item of the solve, with the fields of its supernode it needs:
 // rows (forward) or columns (backward) [begin, end) of the supernode, L lanes
 // per row or column.
 struct ItemDesc {
-  int begin, end, L, nchild;
+  int begin, end, L, nchild;  // nchild: layers of the supernode's update slots
   int first, ncol, nbelow, pad;
   long long blk;       // the supernode's block in this sweep's packed copy
   long long rows_off;  // its below-diagonal rows and their positions in the parent
-  long long vp_in;     // its children's update slots
-  long long vp_out;    // its own slot in its parent
+  long long vp_in;     // its update layers (written by its children)
+  long long vp_out;    // its parent's update layers
 };
 // rows of a forward work item staged in LDS (pass-through sums)
 constexpr int kMaxItemRows = 256;  // == threads of a level-kernel workgroup
@@ -108,8 +109,8 @@ struct DeviceMesh {
   double* Bf = nullptr;       // forward blocks, row-major packed
   double* Bb = nullptr;       // backward blocks, column-major packed
   int* rows = nullptr;        // below-diagonal rows of each supernode
-  int* rel = nullptr;         // position of each below row in the parent's rows
-  double* vp = nullptr;       // children's update vectors in their parents' row space
+  int* rel = nullptr;         // layered position of each below row in the parent's layers
+  double* vp = nullptr;       // update layers of every supernode (children's updates)
   std::vector<Level> levels;  // item ranges per tree level (levels >= sub_levels)
   // bottom subtrees: levels < sub_levels, one workgroup per subtree
   int sub_levels = 0, sub_tasks = 0;

@@ -49,12 +49,13 @@ __device__ __forceinline__ long long bw_col_off(int c, int m) {
 
 // Forward sweep, one tree level: one work item per workgroup. A lane group
 // of L lanes computes up to 4 rows of [L11^{-1}; L21 L11^{-1}] t_S, where
-// t_S = q_S - (children's update vectors on S's columns). Every child of S
-// writes its update vector into its own zero-initialised slot laid out in
-// S's row space (same positions every solve, so the other entries stay
-// zero); the item reads q and the children's slots with independent
-// contiguous loads, and adds the slots' entries below S's columns to its own
-// update rows (pass-through), which it writes into S's slot of its parent.
+// t_S = q_S - (children's update vectors on S's columns). S owns K
+// zero-initialised layers laid out in its own row space; each child writes
+// each of its update rows into one layer (the same place every solve, at
+// most one writer per entry, so unwritten entries stay zero). The item reads
+// q and the K layers with independent contiguous loads, and adds the layers'
+// entries below S's columns to its own update rows (pass-through), which it
+// writes into its parent's layers.
 __device__ __forceinline__ void fwd_item(const ItemDesc& d, const double* __restrict__ Bf,
                                          const int* __restrict__ rel,
                                          const double* __restrict__ q, double* __restrict__ z,
@@ -66,7 +67,7 @@ __device__ __forceinline__ void fwd_item(const ItemDesc& d, const double* __rest
   const int slot0 = wave * G + grp;  // this group's first row in the item
   const int stride = 4 * G;
   const int nch = d.nchild;
-  const double* __restrict__ vin = vp + d.vp_in;   // nch slots of m x 3
+  const double* __restrict__ vin = vp + d.vp_in;   // nch layers of m x 3
   const size_t ss = 3 * (size_t)m;
   int cend[4];
   const double* rp[4];
@@ -624,8 +625,8 @@ k_solve_bwd_sub(const ItemDesc* __restrict__ items, const int* __restrict__ ptr,
   }
 }
 
-// Dense top block, step 1: its right-hand side t_T = q_T - (children's update
-// vectors), summed in a fixed order.
+// Dense top block, step 1: its right-hand side t_T = q_T - (its update layers),
+// summed in a fixed order.
 __global__ void __launch_bounds__(TS)
 k_top_assemble(const double* __restrict__ q, const double* __restrict__ slots, int nch,
                int n3, double* __restrict__ t, const Ctl* __restrict__ ctl) {

@@ -162,7 +162,10 @@ class Sim:
     def __init__(self, options: Optional[Options] = None, **overrides):
         self._lib = load_library()
         o = options if options is not None else default_options()
+        known = {f for f, _ in Options._fields_}
         for k, v in overrides.items():
+            if k not in known:
+                raise TypeError(f"unknown solver option {k!r}")
             if k == "gravity":
                 o.gravity = (ctypes.c_double * 3)(*v)
             else:
