@@ -140,6 +140,7 @@ struct DeviceMesh {
   double* psi = nullptr;      // T per-element energies (probe entry point)
   int gather_blocks = 1;      // blocks of the gradient gather (four lanes per vertex)
   int vec3_blocks = 1;        // blocks of the vector kernels (one entry per thread)
+  int rdots_blocks = 1;       // blocks of the r0 dot products (1024 threads)
   int elem_blocks = 1;
   Ctl* ctl = nullptr;
   Ctl* ctl_host = nullptr;    // pinned mirror

@@ -76,8 +76,8 @@ __device__ __forceinline__ double sum_partials(const double* p, int n, double* s
 __device__ __forceinline__ bool ctl_run(const Ctl* c) { return c->active && !c->need_host; }
 
 // Block sums of N values per thread, written as out[d * nb + blockIdx.x]:
-// wave trees, then the four wave results in a fixed order.
-template <int N>
+// wave sums, then the NW wave results added in wave order (sh: NW * N).
+template <int N, int NW = BS / 64>
 __device__ __forceinline__ void block_sums_to(double (&v)[N], double* sh, double* out, int nb) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
@@ -87,8 +87,11 @@ __device__ __forceinline__ void block_sums_to(double (&v)[N], double* sh, double
     for (int d = 0; d < N; ++d) sh[w * N + d] = v[d];
   }
   __syncthreads();
-  for (int d = threadIdx.x; d < N; d += BS)
-    out[(size_t)d * nb + blockIdx.x] = (sh[d] + sh[N + d]) + (sh[2 * N + d] + sh[3 * N + d]);
+  for (int d = threadIdx.x; d < N; d += NW * 64) {
+    double t = sh[d];
+    for (int k = 1; k < NW; ++k) t += sh[k * N + d];
+    out[(size_t)d * nb + blockIdx.x] = t;
+  }
 }
 
 // Totals of N partial arrays of nb entries (part[d * nb + b]) into tot[0..N),
@@ -292,6 +295,8 @@ k_init_decide(const double* __restrict__ part, int nparts, Ctl* ctl) {
 // form): dots [0..3] = t.s, s.s, t.t, g.g and, per ring slot j,
 // [4 + 3j] = s_j.g, [5 + 3j] = s.t_j, [6 + 3j] = s_j.t (the candidate's own
 // entries use the new s and t).
+constexpr int kWideBS = 1024;  // threads per block of the r0 dots
+
 template <int SL>
 __global__ void __launch_bounds__(BS)
 k_gather(int k, int nf, int slots, int inc_w, const int* __restrict__ inc_tab,
@@ -301,7 +306,7 @@ k_gather(int k, int nf, int slots, int inc_w, const int* __restrict__ inc_tab,
          double* __restrict__ Gc, double* __restrict__ Sall, double* __restrict__ Tall,
          const Ctl* __restrict__ ctl, double* __restrict__ part) {
   constexpr int ND = 4 + 3 * SL;
-  __shared__ double sh[4 * ND];
+  __shared__ double sh[(BS / 64) * ND];
   if (!ctl_run(ctl)) return;
   const double alpha = ctl->alpha;
   const int cand = ctl->cand;
@@ -493,11 +498,11 @@ k_qform(int nf, int slots, const double* __restrict__ grad, const double* __rest
 // Dots of r0 = A^{-1} q with every stored t_j (by ring slot) and with grad:
 // [j] = t_j . r0, [SL] = grad . r0.
 template <int SL>
-__global__ void __launch_bounds__(BS)
+__global__ void __launch_bounds__(kWideBS)
 k_rdots(int nf, int slots, const double* __restrict__ r0, const double* __restrict__ grad,
         const double* __restrict__ Tall, double* __restrict__ part, const Ctl* __restrict__ ctl) {
   constexpr int ND = SL + 1;
-  __shared__ double sh[4 * ND];
+  __shared__ double sh[(kWideBS / 64) * ND];
   if (!ctl_run(ctl)) return;
   const int np = ctl->npairs;
   const size_t n3 = 3 * (size_t)nf;
@@ -513,7 +518,7 @@ k_rdots(int nf, int slots, const double* __restrict__ r0, const double* __restri
   double acc[ND];
 #pragma unroll
   for (int j = 0; j < ND; ++j) acc[j] = 0.0;
-  const size_t i = (size_t)blockIdx.x * BS + threadIdx.x;  // one entry per thread
+  const size_t i = (size_t)blockIdx.x * kWideBS + threadIdx.x;  // one entry per thread
   if (i < n3) {
     const double r = r0[i];
     acc[SL] = grad[i] * r;
@@ -521,7 +526,7 @@ k_rdots(int nf, int slots, const double* __restrict__ r0, const double* __restri
     for (int j = 0; j < SL; ++j)
       if (use[j]) acc[j] = Tall[(size_t)j * n3 + i] * r;
   }
-  block_sums_to<ND>(acc, sh, part, gridDim.x);
+  block_sums_to<ND, kWideBS / 64>(acc, sh, part, gridDim.x);
 }
 
 // Second loop on scalars, oldest pair first:
@@ -769,7 +774,7 @@ void launch_elem(DeviceMesh& D, hipStream_t st, int mode, const double* X, doubl
 }
 
 // Partials layout: gather dots (kGatherDots x gather_blocks), r0 dots
-// (kSlots + 1 x vec3_blocks), element partials (elem_blocks).
+// (kSlots + 1 x rdots_blocks), element partials (elem_blocks).
 constexpr int kGatherDots = 4 + 3 * kSlots;
 struct Parts {
   double *gather, *rdots, *elem;
@@ -778,7 +783,7 @@ Parts parts_of(DeviceMesh& D) {
   Parts p;
   p.gather = D.part;
   p.rdots = D.part + (size_t)kGatherDots * D.gather_blocks;
-  p.elem = p.rdots + (size_t)(kSlots + 1) * D.vec3_blocks;
+  p.elem = p.rdots + (size_t)(kSlots + 1) * D.rdots_blocks;
   return p;
 }
 
@@ -836,12 +841,13 @@ void launch_iteration(DeviceMesh& D, const StepParams& P, hipStream_t st, int k,
 #undef QN_QFORM
     launch_solve(D, st, D.q, D.d, D.ctl);
 #define QN_RDOTS(SL)                                                                      \
-  hipLaunchKernelGGL(k_rdots<SL>, dim3(vb), dim3(BS), 0, st, D.nf, slots, D.d, Gc, D.Tv, \
-                     pp.rdots, D.ctl)
+  hipLaunchKernelGGL(k_rdots<SL>, dim3(D.rdots_blocks), dim3(kWideBS), 0, st, D.nf, slots, D.d, \
+                     Gc, D.Tv, pp.rdots, D.ctl)
     QN_SLOTS_DISPATCH(slv, QN_RDOTS)
 #undef QN_RDOTS
 #define QN_COEF(SL) \
-  hipLaunchKernelGGL(k_coef_decide<SL>, dim3(1), dim3(BS), 0, st, m, pp.rdots, vb, D.ctl)
+  hipLaunchKernelGGL(k_coef_decide<SL>, dim3(1), dim3(BS), 0, st, m, pp.rdots, D.rdots_blocks, \
+                     D.ctl)
     QN_SLOTS_DISPATCH(slv, QN_COEF)
 #undef QN_COEF
 #define QN_DFORM(SL) \
@@ -914,10 +920,11 @@ int dev_alloc(DeviceMesh& D, std::string& err) {
   HIP_OK(A((void**)&D.fel, (size_t)D.T * 12 * 8));
   HIP_OK(A((void**)&D.psi, (size_t)D.T * 8));
   D.gather_blocks = nblk(4 * (int64_t)D.nf);
+  D.rdots_blocks = (int)std::max<int64_t>(1, (3 * (int64_t)D.nf + kWideBS - 1) / kWideBS);
   D.vec3_blocks = nblk(3 * (int64_t)D.nf);
   D.elem_blocks = nblk(std::max(D.T, D.nf));
   HIP_OK(A((void**)&D.part,
-           ((size_t)kGatherDots * D.gather_blocks + (size_t)(kSlots + 1) * D.vec3_blocks +
+           ((size_t)kGatherDots * D.gather_blocks + (size_t)(kSlots + 1) * D.rdots_blocks +
             D.elem_blocks) * 8));
   HIP_OK(A((void**)&D.ctl, sizeof(Ctl)));
   HIP_OK(hipHostMalloc((void**)&D.ctl_host, sizeof(Ctl), hipHostMallocDefault));
