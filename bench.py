@@ -37,6 +37,30 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "solve_traffic_block40_neohookean.md")
+SOLVE_SOURCES = ["trisolve.hip", "factor.cpp", "api.cpp", "kernels.hpp", "wave.hpp"]
+
+
+def solve_traffic(n):
+    """HBM bytes of one solve measured with FETCH_SIZE / WRITE_SIZE (scaled by a copy
+    kernel) for the 40^3 block, or None when the workload differs or the solve's
+    sources changed since the counters were taken."""
+    import hashlib
+    if n != 40 or not os.path.exists(TRAFFIC_PROFILE):
+        return None
+    h = hashlib.sha256()
+    for f in SOLVE_SOURCES:
+        with open(os.path.join(ROOT, "paper_1604_07378_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    fields = {}
+    for line in open(TRAFFIC_PROFILE):
+        key, _, val = line.partition(":")
+        fields[key.strip()] = val.strip()
+    if fields.get("solve_source_sha256_16") != h.hexdigest()[:16]:
+        return None
+    return int(fields["traffic_bytes_per_solve"])
+
+
 def element_bytes(T, n, nf):
     """Algorithmic HBM bytes of one FP64 line-search element pass.
 
@@ -127,6 +151,9 @@ def main():
     ap.add_argument("--materials", default="neohookean,stvk,spline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=1)
+    ap.add_argument("--copy-calibration-mb", type=int, default=0,
+                    help="run one plain device copy of this many MB first (a reference kernel of "
+                         "known traffic for hardware-counter runs)")
     ap.add_argument("--set", action="append", default=[], metavar="OPTION=INT",
                     help="override an integer solver option (e.g. level_merge=0, dense_top=0)")
     args = ap.parse_args()
@@ -149,6 +176,14 @@ def main():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
+    if args.copy_calibration_mb > 0:
+        n = args.copy_calibration_mb * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy of {args.copy_calibration_mb} MB done")
+        del src, dst
     names = {v: k for k, v in W.MATERIAL_NAMES.items()}
     kinds = [names[s] for s in args.materials.split(",")]
     runs = [run_material(k, args, torch, W, qnsim) for k in kinds]
@@ -204,7 +239,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": solve_traffic(args.n) if dom == "solve" else None,
             "algorithmic_bytes_per_launch": bytes_,
             "avg_launch_ms": ms,
         },
