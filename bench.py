@@ -79,10 +79,10 @@ def solve_bytes(nnz_exact, nf):
     return 2 * 8 * nnz_exact + 2 * 24 * nf
 
 
-def run_material(kind, args, torch, W, qnsim):
+def run_material(kind, args, torch, W, qnsim, extra=None):
     w = W.workload_block(kind, n=args.n)
     t0 = time.time()
-    sim = qnsim.sim_from_workload(w, **args.overrides)
+    sim = qnsim.sim_from_workload(w, **{**args.overrides, **(extra or {})})
     prep = time.time() - t0
     info = sim.factor_info()
     log(f"[bench] {w.name}: prepared in {prep:.2f}s, nnz(L)={info['nnz_L_exact']}, "
@@ -151,6 +151,8 @@ def main():
     ap.add_argument("--materials", default="neohookean,stvk,spline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=1)
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip the extra mixed-precision Neo-Hookean run")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="run one plain device copy of this many MB first (a reference kernel of "
                          "known traffic for hardware-counter runs)")
@@ -187,6 +189,10 @@ def main():
     names = {v: k for k, v in W.MATERIAL_NAMES.items()}
     kinds = [names[s] for s in args.materials.split(",")]
     runs = [run_material(k, args, torch, W, qnsim) for k in kinds]
+    mixed = None
+    if not args.no_mixed and W.NEOHOOKEAN in kinds:
+        # informational: the mixed path (FP32 stresses) on the same workload
+        mixed = run_material(W.NEOHOOKEAN, args, torch, W, qnsim, {"precision": qnsim.QNSIM_MIXED})
 
     total_steps = sum(r["steps"] for r in runs)
     total_s = sum(r["seconds"] for r in runs)
@@ -232,6 +238,9 @@ def main():
                                     "exhausted", "kernel_ms", "nnz_L", "levels", "prepare_s")}
                  for r in runs],
         "step_time_share_ms": per_step,
+        **({"mixed_precision_run": {k: mixed[k] for k in ("material", "steps_per_s", "ls_trials",
+                                                         "iterations", "kernel_ms")}}
+           if mixed else {}),
         "roofline": {
             "bound": "hbm",
             "kernel": dom,

@@ -588,6 +588,7 @@ int upload_impl(qnsim_t* c) {
     return fail(c, QNSIM_E_DEVICE, "hipSetDevice failed (no GPU?)");
   UP(D.tv, tv);
   UP(D.Bm, Bm);
+  D.mixed = c->opt.precision == QNSIM_MIXED;
   UP(D.vol, vol);
   if (D.nmat > 1) UP(D.tmat, tm);
   UP(D.mats, dm);

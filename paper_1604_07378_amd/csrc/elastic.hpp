@@ -1,5 +1,5 @@
-// Element energy densities and first Piola stresses on the device (FP64 and
-// FP32 instantiations). Materials follow section 4.1 (Valanis-Landel form) and
+// Element energy densities and first Piola stresses on the device (FP64, and
+// the mixed FP32 evaluation below). Materials follow section 4.1 (Valanis-Landel form) and
 // section 5 (Neo-Hookean, St. Venant-Kirchhoff, corotated, spline-based, and
 // the polynomial material a(x) = mu (x-1)^4).
 #pragma once
@@ -260,6 +260,85 @@ __device__ __forceinline__ bool material_eval_any(const DevMat& mat, const M3<R>
     case 2: return material_eval<R, 2>(mat, F, psi, P);
     case 3: return material_eval<R, 3>(mat, F, psi, P);
     default: return material_eval<R, 4>(mat, F, psi, P);
+  }
+}
+
+// Mixed precision (FP32 stresses) without losing the small strains: near
+// rest, F - F^{-T} cancels at leading order, so a stress evaluated in FP32 on
+// F would carry a relative error of about 1e-7 / strain. Here F, J and the
+// Green strain E = (F^T F - I) / 2 = (H + H^T + H^T H) / 2 (H = F - I) are
+// formed in FP64 and the first Piola stress is evaluated in FP32 from terms
+// that are each accurate relative to themselves:
+//   Neo-Hookean  P = F S,  S = C^{-1} (2 mu E + lam log J I),  C = I + 2E,
+//   StVK         P = F (2 mu E + lam tr E I).
+// The energy density is formed in FP64 from the same invariants (a handful of
+// flops): FP32 energies put noise of ~1e-7 g into the Armijo test, which flips
+// line-search decisions and moves the trajectory by more than the mixed
+// path's tolerance. The stretch-based materials (SVD) are evaluated in FP64 in
+// this mode.
+template <int TYPE>
+__device__ __forceinline__ void material_eval_mixed(const DevMat& mat, const M3<double>& F,
+                                                    double& psi, M3<float>& P) {
+  const int ty = TYPE >= 0 ? TYPE : mat.type;
+  if (ty == 0 || ty == 1) {
+    double Ed[3][3];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        const double hij = F.a[i][j] - (i == j ? 1.0 : 0.0);
+        const double hji = F.a[j][i] - (i == j ? 1.0 : 0.0);
+        double hth = 0.0;
+        for (int k = 0; k < 3; ++k)
+          hth += (F.a[k][i] - (k == i ? 1.0 : 0.0)) * (F.a[k][j] - (k == j ? 1.0 : 0.0));
+        Ed[i][j] = 0.5 * (hij + hji + hth);
+      }
+    M3<float> Ff, E;
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        Ff.a[i][j] = (float)F.a[i][j];
+        E.a[i][j] = (float)Ed[i][j];
+      }
+    const double trEd = Ed[0][0] + Ed[1][1] + Ed[2][2];
+    const float mu = (float)mat.mu, lam = (float)mat.lam;
+    float S[3][3];
+    if (ty == 0) {
+      const double J = det3(F);
+      if (!(J > 0.0)) {
+        psi = INFINITY;
+        for (int i = 0; i < 3; ++i)
+          for (int j = 0; j < 3; ++j) P.a[i][j] = 0.0f;
+        return;
+      }
+      const double ljd = log(J);
+      const float lj = (float)ljd;
+      psi = mat.mu * (trEd - ljd) + 0.5 * mat.lam * ljd * ljd;
+      M3<float> C;
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) C.a[i][j] = (i == j ? 1.0f : 0.0f) + 2.0f * E.a[i][j];
+      const M3<float> Cc = cofactor(C);  // C symmetric: cofactor = adjugate
+      const float invC = (float)(1.0 / (J * J));
+      float T[3][3];
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) T[i][j] = 2.0f * mu * E.a[i][j] + (i == j ? lam * lj : 0.0f);
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+          S[i][j] = invC * (Cc.a[i][0] * T[0][j] + Cc.a[i][1] * T[1][j] + Cc.a[i][2] * T[2][j]);
+    } else {
+      const float tr = (float)trEd;
+      double ee = 0.0;
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) ee += Ed[i][j] * Ed[i][j];
+      psi = mat.mu * ee + 0.5 * mat.lam * trEd * trEd;
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) S[i][j] = 2.0f * mu * E.a[i][j] + (i == j ? lam * tr : 0.0f);
+    }
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j)
+        P.a[i][j] = Ff.a[i][0] * S[0][j] + Ff.a[i][1] * S[1][j] + Ff.a[i][2] * S[2][j];
+  } else {
+    M3<double> Pd;
+    material_eval_any<double>(mat, F, psi, Pd);
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) P.a[i][j] = (float)Pd.a[i][j];
   }
 }
 

@@ -93,6 +93,7 @@ struct DeviceMesh {
   // element data (internal tet order)
   int* tv = nullptr;          // T x 4 internal vertex ids
   double* Bm = nullptr;       // 9 x T (SoA) entries of Dm^{-1}, row-major per tet
+  int mixed = 0;              // FP32 element energies/stresses (QNSIM_MIXED)
   double* vol = nullptr;      // T
   int* tmat = nullptr;        // T material ids (nullptr if nmat == 1)
   DevMat* mats = nullptr;     // nmat
@@ -135,7 +136,7 @@ struct DeviceMesh {
   double* z = nullptr;        // nf x 3 forward-solve intermediate
   double* Sv = nullptr;       // slots x nf x 3
   double* Tv = nullptr;       // slots x nf x 3
-  double* fel = nullptr;      // T x 4 x 3 element gradient contributions
+  double* fel = nullptr;      // T x 4 x 3 element gradient contributions (FP32 in mixed mode)
   double* part = nullptr;     // reduction partials
   double* psi = nullptr;      // T per-element energies (probe entry point)
   int gather_blocks = 1;      // blocks of the gradient gather (four lanes per vertex)

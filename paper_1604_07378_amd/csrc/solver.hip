@@ -177,14 +177,15 @@ k_copy_free(int nf, const double* __restrict__ src, double* __restrict__ dst) {
 // mode 0: evaluate at x_k (always runs); mode 1: line-search trial
 // (predicated on an active, unfinished line search); mode 2: probe.
 // ---------------------------------------------------------------------------
-template <int TYPE>
+template <int TYPE, typename R>
 __global__ void __launch_bounds__(BS)
 k_elem(int mode, int T, int nf, const int* __restrict__ tv, const double* __restrict__ Bm,
-       const double* __restrict__ vol, const int* __restrict__ tmat,
-       const DevMat* __restrict__ mats, const double* __restrict__ mass,
-       const double* __restrict__ X, const double* __restrict__ d,
-       const double* __restrict__ y, double inv2h2, const Ctl* __restrict__ ctl,
-       double* __restrict__ fel, double* __restrict__ part, double* __restrict__ psi_out) {
+       const double* __restrict__ vol,
+       const int* __restrict__ tmat, const DevMat* __restrict__ mats,
+       const double* __restrict__ mass, const double* __restrict__ X,
+       const double* __restrict__ d, const double* __restrict__ y, double inv2h2,
+       const Ctl* __restrict__ ctl, R* __restrict__ fel, double* __restrict__ part,
+       double* __restrict__ psi_out) {
   __shared__ double sh[16];
   double alpha = 0.0;
   if (mode == 1) {
@@ -215,33 +216,38 @@ k_elem(int mode, int T, int nf, const int* __restrict__ tv, const double* __rest
     M3<double> F;
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-      double ds0 = p[1][i] - p[0][i], ds1 = p[2][i] - p[0][i], ds2 = p[3][i] - p[0][i];
+      const double ds0 = p[1][i] - p[0][i], ds1 = p[2][i] - p[0][i], ds2 = p[3][i] - p[0][i];
 #pragma unroll
       for (int k = 0; k < 3; ++k) F.a[i][k] = ds0 * B[0][k] + ds1 * B[1][k] + ds2 * B[2][k];
     }
     const DevMat& mt = mats[tmat ? tmat[t] : 0];
     double psi;
-    M3<double> P;
-    if (TYPE >= 0)
-      material_eval<double, (TYPE < 0 ? 0 : TYPE)>(mt, F, psi, P);
-    else
-      material_eval_any<double>(mt, F, psi, P);
+    M3<R> P;
+    if constexpr (sizeof(R) == 8) {
+      if (TYPE >= 0)
+        material_eval<double, (TYPE < 0 ? 0 : TYPE)>(mt, F, psi, P);
+      else
+        material_eval_any<double>(mt, F, psi, P);
+    } else {
+      material_eval_mixed<TYPE>(mt, F, psi, P);  // FP32 stress
+    }
     const double V = vol[t];
-    e = V * psi;
+    e = V * psi;  // energies and their sum are FP64 in every mode
     if (psi_out) psi_out[t] = psi;
-    double g[4][3];
+    const R VR = (R)V;
+    R g[4][3];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-      double s = 0.0;
+      R s = R(0);
 #pragma unroll
       for (int j = 0; j < 3; ++j) {
-        double hij = V * (P.a[i][0] * B[j][0] + P.a[i][1] * B[j][1] + P.a[i][2] * B[j][2]);
+        R hij = VR * (P.a[i][0] * (R)B[j][0] + P.a[i][1] * (R)B[j][1] + P.a[i][2] * (R)B[j][2]);
         g[j + 1][i] = hij;
         s += hij;
       }
       g[0][i] = -s;
     }
-    double* o = fel + (size_t)t * 12;
+    R* o = fel + (size_t)t * 12;
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -280,13 +286,6 @@ k_init_decide(const double* __restrict__ part, int nparts, Ctl* ctl) {
 }
 
 // ---------------------------------------------------------------------------
-// Gradient gather (section 4, Eq. PDgrad2): grad_i = m_i (x_i - y_i)/h^2 +
-// sum of the element contributions of vertex i in a fixed (CSR) order. For
-// k >= 1 it first materialises x_k = x_{k-1} + alpha d of the accepted trial
-// and forms the curvature pair s = x_k - x_{k-1}, t = grad_k - grad_{k-1}
-// (Algorithm 2) in the candidate ring slot, with the partial sums of t.s,
-// s.s, t.t and grad.grad.
-// ---------------------------------------------------------------------------
 // Gradient gather of iteration k (section 4, Eq. PDgrad2): x_k = x_{k-1} +
 // alpha d, s = x_k - x_{k-1}, grad = M/h^2 (x_k - y) + sum of element
 // contributions (incidence lists, fixed order), t = grad - grad_{k-1}; s and
@@ -297,10 +296,10 @@ k_init_decide(const double* __restrict__ part, int nparts, Ctl* ctl) {
 // entries use the new s and t).
 constexpr int kWideBS = 1024;  // threads per block of the r0 dots
 
-template <int SL>
+template <int SL, typename FT>
 __global__ void __launch_bounds__(BS)
 k_gather(int k, int nf, int slots, int inc_w, const int* __restrict__ inc_tab,
-         const double* __restrict__ fel, const double* __restrict__ mass,
+         const FT* __restrict__ fel, const double* __restrict__ mass,
          const double* __restrict__ y, double inv_h2, const double* __restrict__ Xp,
          double* __restrict__ Xc, const double* __restrict__ d, const double* __restrict__ Gp,
          double* __restrict__ Gc, double* __restrict__ Sall, double* __restrict__ Tall,
@@ -353,10 +352,10 @@ k_gather(int k, int nf, int slots, int inc_w, const int* __restrict__ inc_tab,
       double fv[8][3];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        const double* fp = fel + 3 * (size_t)(ix[u] >= 0 ? ix[u] : 0);
-        fv[u][0] = ix[u] >= 0 ? fp[0] : 0.0;
-        fv[u][1] = ix[u] >= 0 ? fp[1] : 0.0;
-        fv[u][2] = ix[u] >= 0 ? fp[2] : 0.0;
+        const FT* fp = fel + 3 * (size_t)(ix[u] >= 0 ? ix[u] : 0);
+        fv[u][0] = ix[u] >= 0 ? (double)fp[0] : 0.0;  // summed in FP64 in every mode
+        fv[u][1] = ix[u] >= 0 ? (double)fp[1] : 0.0;
+        fv[u][2] = ix[u] >= 0 ? (double)fp[2] : 0.0;
       }
 #pragma unroll
       for (int u = 0; u < 8; ++u) { f[0] += fv[u][0]; f[1] += fv[u][1]; f[2] += fv[u][2]; }
@@ -758,10 +757,17 @@ void launch_elem(DeviceMesh& D, hipStream_t st, int mode, const double* X, doubl
                  double* psi_out) {
   const double inv2h2 = 0.5 / (D.h * D.h);
   const int grid = D.elem_blocks;
-#define QN_ELEM(TY)                                                                         \
-  hipLaunchKernelGGL(k_elem<TY>, dim3(grid), dim3(BS), 0, st, mode, D.T, D.nf, D.tv, D.Bm, \
-                     D.vol, D.tmat, D.mats, D.mass, X, D.d, D.y, inv2h2, D.ctl, D.fel, part, \
-                     psi_out)
+#define QN_ELEM(TY)                                                                          \
+  do {                                                                                      \
+    if (D.mixed)                                                                            \
+      hipLaunchKernelGGL((k_elem<TY, float>), dim3(grid), dim3(BS), 0, st, mode, D.T, D.nf,  \
+                         D.tv, D.Bm, D.vol, D.tmat, D.mats, D.mass, X, D.d, D.y,     \
+                         inv2h2, D.ctl, reinterpret_cast<float*>(D.fel), part, psi_out);     \
+    else                                                                                    \
+      hipLaunchKernelGGL((k_elem<TY, double>), dim3(grid), dim3(BS), 0, st, mode, D.T, D.nf, \
+                         D.tv, D.Bm, D.vol, D.tmat, D.mats, D.mass, X, D.d, D.y,     \
+                         inv2h2, D.ctl, D.fel, part, psi_out);                               \
+  } while (0)
   switch (D.single_type) {
     case 0: QN_ELEM(0); break;
     case 1: QN_ELEM(1); break;
@@ -806,11 +812,18 @@ inline int slots_variant(int m) { return m <= 8 ? m + 1 : kSlots; }
 
 void launch_gather(DeviceMesh& D, hipStream_t st, int k, int m, const double* Xp, double* Xc,
                    const double* Gp, double* Gc, double* part) {
-#define QN_GATHER(SL)                                                                         \
-  hipLaunchKernelGGL(k_gather<SL>, dim3(D.gather_blocks), dim3(BS), 0, st, k, D.nf, m + 1,      \
-                     D.inc_w, D.inc_tab, D.fel, D.mass, D.y, 1.0 / (D.h * D.h), Xp, Xc, D.d,  \
-                     Gp, Gc,                                                                  \
-                     D.Sv, D.Tv, D.ctl, part)
+#define QN_GATHER(SL)                                                                          \
+  do {                                                                                        \
+    if (D.mixed)                                                                              \
+      hipLaunchKernelGGL((k_gather<SL, float>), dim3(D.gather_blocks), dim3(BS), 0, st, k,     \
+                         D.nf, m + 1, D.inc_w, D.inc_tab, reinterpret_cast<const float*>(D.fel), \
+                         D.mass, D.y, 1.0 / (D.h * D.h), Xp, Xc, D.d, Gp, Gc, D.Sv, D.Tv,      \
+                         D.ctl, part);                                                         \
+    else                                                                                      \
+      hipLaunchKernelGGL((k_gather<SL, double>), dim3(D.gather_blocks), dim3(BS), 0, st, k,    \
+                         D.nf, m + 1, D.inc_w, D.inc_tab, D.fel, D.mass, D.y,                  \
+                         1.0 / (D.h * D.h), Xp, Xc, D.d, Gp, Gc, D.Sv, D.Tv, D.ctl, part);     \
+  } while (0)
   QN_SLOTS_DISPATCH(slots_variant(m), QN_GATHER)
 #undef QN_GATHER
 }

@@ -264,3 +264,76 @@ def test_block_first_step_full_size(kind):
           flush=True)
     assert e <= 1e-9
     assert st["ls_trials"] == r.ls_trials
+
+
+# ---------------------------------------------------------------------------
+# Mixed precision (QNSIM_MIXED): FP32 element energies, stresses and force
+# contributions; FP64 positions differences, energy sums, gradient gather,
+# curvature dot products and solves. Stated tolerance against the FP64
+# oracle: eps <= 1e-4 per step.
+# ---------------------------------------------------------------------------
+def _mixed_vs_oracle(w, steps, tol=1e-4, free_steps=0):
+    """Per-step error of the mixed path: every step starts from the oracle's
+    state, and the mixed and FP64 GPU results of that one step are compared
+    with the oracle's. Also runs the first `free_steps` steps free (each
+    implementation from its own state)."""
+    m = _model(w)
+    s64 = qnsim.sim_from_workload(w)
+    s32 = qnsim.sim_from_workload(w, precision=qnsim.QNSIM_MIXED)
+    x_o, v_o = w.x0.copy(), w.v0.copy()
+    x_f, v_f = w.x0.copy(), w.v0.copy()
+    worst_o, worst_g, worst_free = 0.0, 0.0, 0.0
+    for k in range(steps):
+        r = oracle.step(m, x_o, v_o)
+        x_m, _, _ = s32.step(x_o, v_o, w.h)
+        x_g, _, _ = s64.step(x_o, v_o, w.h)
+        e_o = _eps(x_m, r.x, w.rest)
+        e_g = _eps(x_m, x_g, w.rest)
+        worst_o, worst_g = max(worst_o, e_o), max(worst_g, e_g)
+        assert e_o <= tol, f"step {k}: mixed vs oracle eps {e_o:.3e}"
+        if k < free_steps:
+            x_f, v_f, _ = s32.step(x_f, v_f, w.h)
+            e_f = _eps(x_f, r.x, w.rest)
+            worst_free = max(worst_free, e_f)
+            assert e_f <= tol, f"free-running step {k}: eps {e_f:.3e}"
+        x_o, v_o = r.x, r.v
+    return worst_o, worst_g, worst_free
+
+
+def test_mixed_precision_cantilever_300_steps():
+    """Per-element E log-uniform in [1e4, 1e7] Pa on the 540-tet cantilever,
+    300 steps: the mixed path's per-step error against the FP64 oracle and the
+    FP64 GPU path, and 60 free-running steps. (Beyond about 60 steps this
+    floppy bar's motion is chaotic: even the FP64 GPU path and the FP64
+    oracle separate by a factor ~10 every 8 steps from rounding differences,
+    so free-running trajectories are compared only before that.)"""
+    w = W.workload_mixed_cantilever(0)
+    wo, wg, wf = _mixed_vs_oracle(w, 300, free_steps=60)
+    print(f"mixed cantilever: per-step eps vs oracle max {wo:.3e}, vs FP64 GPU path {wg:.3e}; "
+          f"free-running 60 steps {wf:.3e}", flush=True)
+
+
+@pytest.mark.parametrize("kind", [W.NEOHOOKEAN, W.STVK, W.SPLINE])
+def test_mixed_precision_block_first_step(kind):
+    w = W.workload_block(kind, n=40)
+    wo, wg, _ = _mixed_vs_oracle(w, 1)
+    print(f"mixed block {W.MATERIAL_NAMES[kind]}: eps vs oracle {wo:.3e}, vs FP64 GPU {wg:.3e}",
+          flush=True)
+
+
+def test_mixed_precision_objective_and_gradient():
+    """The mixed evaluation of g and its gradient against the FP64 oracle at a
+    perturbed state (FP32 element terms: relative error ~1e-6 expected)."""
+    w = W.workload_mixed_cantilever(0)
+    m = _model(w)
+    s = qnsim.sim_from_workload(w, precision=qnsim.QNSIM_MIXED)
+    x = _perturbed(w, 0.05, 3)
+    y = _perturbed(w, 0.02, 4)
+    g_ref = fem.objective(m, x, y)
+    grad_ref = np.zeros_like(x)
+    grad_ref[m.free] = fem.gradient(m, x, y)
+    grad = torch.empty(w.n_verts, 3, dtype=torch.float64, device="cuda")
+    g = s.eval_device(_dev(x), _dev(y), grad)
+    grad = grad.cpu().numpy()
+    assert abs(g - g_ref) <= 1e-5 * abs(g_ref)
+    assert np.abs(grad - grad_ref).max() <= 1e-4 * np.abs(grad_ref).max()
