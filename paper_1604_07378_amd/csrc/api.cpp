@@ -220,434 +220,6 @@ int analyze_impl(qnsim_t* c, double h) {
   return QNSIM_OK;
 }
 
-template <class T>
-int upload(qnsim_t* c, T** dst, const T* src, size_t count) {
-  hipError_t e = hipMalloc((void**)dst, std::max<size_t>(count * sizeof(T), 8));
-  if (e != hipSuccess) return fail(c, QNSIM_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
-  c->dev.bytes += count * sizeof(T);
-  if (count) {
-    e = hipMemcpy(*dst, src, count * sizeof(T), hipMemcpyHostToDevice);
-    if (e != hipSuccess) return fail(c, QNSIM_E_DEVICE, std::string("hipMemcpy: ") + hipGetErrorString(e));
-  }
-  return QNSIM_OK;
-}
-
-#define UP(dst, vec)                                                    \
-  do {                                                                  \
-    int rc_ = upload(c, &(dst), (vec).data(), (vec).size());            \
-    if (rc_) return rc_;                                                \
-  } while (0)
-
-int upload_impl(qnsim_t* c) {
-  dev_free(c->dev);
-  DeviceMesh& D = c->dev;
-  const Factor& F = c->factor;
-  const int n = c->n, T = c->T, nf = c->nf;
-  D.device = c->opt.device;
-  D.n = n; D.nf = nf; D.T = T; D.h = c->h;
-  D.nmat = (int)c->mats.size();
-  D.single_type = c->single_type;
-  D.m = c->opt.history;
-  D.slots = D.m + 1;
-  // element data in internal tet order
-  std::vector<int> tv(4 * (size_t)T), tm(T);
-  std::vector<double> Bm(9 * (size_t)T), vol(T);
-  for (int t = 0; t < T; ++t) {
-    const int o = c->tperm[t];
-    for (int a = 0; a < 4; ++a) tv[4 * (size_t)t + a] = c->viperm[c->tets[4 * (size_t)o + a]];
-    for (int e = 0; e < 9; ++e) Bm[(size_t)e * T + t] = c->Dminv[9 * (size_t)o + e];
-    vol[t] = c->vol[o];
-    tm[t] = c->tet_mat[o];
-  }
-  std::vector<DevMat> dm(c->mats.size());
-  for (size_t i = 0; i < dm.size(); ++i) {
-    const Material& m = c->mats[i];
-    DevMat& d = dm[i];
-    std::memset(&d, 0, sizeof(d));
-    d.type = m.type; d.mu = m.mu; d.lam = m.lam;
-    for (int j = 0; j < 8; ++j) { d.d2[j] = m.d2[j]; d.a0[j] = m.a0[j]; d.a1[j] = m.a1[j]; }
-  }
-  std::vector<double> mass(n);
-  for (int i = 0; i < n; ++i) mass[i] = c->mass[c->vperm[i]];
-  // incidences of free vertices, ordered by (internal tet, slot), in a padded
-  // table of inc_w entries per vertex (-1 after the last)
-  std::vector<int> valence(nf, 0);
-  for (int t = 0; t < T; ++t)
-    for (int a = 0; a < 4; ++a)
-      if (tv[4 * (size_t)t + a] < nf) valence[tv[4 * (size_t)t + a]]++;
-  int inc_w = 4;
-  for (int i = 0; i < nf; ++i) inc_w = std::max(inc_w, (valence[i] + 3) / 4 * 4);
-  std::vector<int> inc_tab((size_t)std::max(nf, 1) * inc_w, -1);
-  {
-    std::vector<int> fill(nf, 0);
-    for (int t = 0; t < T; ++t)
-      for (int a = 0; a < 4; ++a) {
-        const int v = tv[4 * (size_t)t + a];
-        if (v < nf) inc_tab[(size_t)v * inc_w + fill[v]++] = 4 * t + a;
-      }
-  }
-  // supernodal solve: packed blocks (row-major forward copy, column-major
-  // backward copy), work items in topological order, assembly lists
-  const int ns = (int)F.sn.size();
-  auto pow2ceil = [](int v) { int p = 1; while (p < v) p <<= 1; return p; };
-  auto clampi = [](int v, int lo, int hi) { return std::max(lo, std::min(hi, v)); };
-  std::vector<SnInfo> sinfo(ns);
-  // packed offsets: the dense top block (if any) is stored in full in the
-  // forward array only; every other block is packed in both arrays
-  const int top = F.top;
-  std::vector<int64_t> pf(ns + 1, 0), pb(ns + 1, 0);
-  for (int s = 0; s < ns; ++s) {
-    const Supernode& S = F.sn[s];
-    const int64_t packed = (int64_t)S.ncol * (S.ncol + 1) / 2 + (int64_t)S.nbelow * S.ncol;
-    pf[s + 1] = pf[s] + (s == top ? (int64_t)S.ncol * S.ncol : packed);
-    pb[s + 1] = pb[s] + (s == top ? 0 : packed);
-  }
-  std::vector<double> Bf(pf[ns]), Bb(pb[ns]);
-  std::vector<int4> fwl, bwl;
-  std::vector<std::vector<int4>> fw_by_level(F.nlevels), bw_by_level(F.nlevels);
-  // bottom subtrees: the lowest levels whose supernodes all have at most
-  // subtree_cap rows are solved by one workgroup per subtree
-  const int sparse_levels = top >= 0 ? F.sn[top].level : F.nlevels;
-  int Lsub = 0;
-  {
-    std::vector<int> maxm(F.nlevels, 0);
-    for (int s = 0; s < ns; ++s)
-      if (s != top) maxm[F.sn[s].level] = std::max(maxm[F.sn[s].level], F.sn[s].m());
-    const int cap = std::min(c->opt.subtree_cap, kSubCap);
-    while (Lsub < sparse_levels && maxm[Lsub] <= cap) ++Lsub;
-    if (Lsub < 2) Lsub = 0;
-  }
-  for (int s = 0; s < ns; ++s) {
-    const Supernode& S = F.sn[s];
-    const int nc = S.ncol, m = S.m();
-    const double* blk = F.Binv.data() + S.val_off;
-    SnInfo& I = sinfo[s];
-    I.first = S.first; I.ncol = nc; I.nbelow = S.nbelow; I.parent = S.parent;
-    I.nchild = F.child_ptr[s + 1] - F.child_ptr[s];
-    I.fw_off = pf[s]; I.bw_off = pb[s];
-    I.rows_off = S.rows_off; I.vp_in = 0; I.vp_out = -1;
-    if (s == top) {
-      // symmetric: the column-major block is also its row-major copy
-      std::copy(blk, blk + (size_t)nc * nc, Bf.data() + pf[s]);
-      I.fw_items = I.bw_items = 0;
-      continue;
-    }
-    double* bf = Bf.data() + pf[s];
-    double* bb = Bb.data() + pb[s];
-    for (int r = 0; r < m; ++r) {
-      const int len = r < nc ? r + 1 : nc;
-      const int64_t ro = r < nc ? (int64_t)r * (r + 1) / 2
-                                : (int64_t)nc * (nc + 1) / 2 + (int64_t)(r - nc) * nc;
-      for (int c = 0; c < len; ++c) bf[ro + c] = blk[r + (size_t)c * m];
-    }
-    for (int c = 0; c < nc; ++c) {
-      const int64_t co = (int64_t)c * m - (int64_t)c * (c - 1) / 2;
-      for (int i = c; i < m; ++i) bb[co + (i - c)] = blk[i + (size_t)c * m];
-    }
-    if (S.level < Lsub) {
-      I.fw_items = I.bw_items = 0;  // one-wave items, built per subtree below
-      continue;
-    }
-    // forward items: groups of Lf lanes per row, up to 4 rows per group
-    const int Lf = clampi(pow2ceil((nc + 3) / 4), 4, 64), sf = 4 * (64 / Lf);
-    const int rpg_f = clampi(((16384 + nc - 1) / nc + sf - 1) / sf, 1, 4);
-    const int rows_item = sf * rpg_f;
-    for (int r0 = 0; r0 < m; r0 += rows_item)
-      fw_by_level[S.level].push_back(make_int4(s, r0, std::min(m, r0 + rows_item), Lf));
-    I.fw_items = (m + rows_item - 1) / rows_item;
-    // backward items: groups of Lb lanes per column, up to 4 columns per group
-    const int Lb = clampi(pow2ceil((m + 3) / 4), 4, 64), sb = 4 * (64 / Lb);
-    const int rpg_b = clampi(((16384 + m - 1) / m + sb - 1) / sb, 1, 4);
-    const int cols_item = sb * rpg_b;
-    for (int c0 = 0; c0 < nc; c0 += cols_item)
-      bw_by_level[S.level].push_back(
-          make_int4((int)(0x80000000u | (unsigned)s), c0, std::min(nc, c0 + cols_item), Lb));
-    I.bw_items = (nc + cols_item - 1) / cols_item;
-  }
-  // Update slots: supernode P owns K(P) layers of m(P) x 3 doubles in its own
-  // row space, K(P) = the largest number of children that update one row of
-  // P. The children updating a row take its layers in child order, so every
-  // entry is written by one child at the same place every solve and the
-  // entries nobody writes stay zero; P sums K(P) layers instead of one slot
-  // per child. relL holds each below row's layered position (layer m(P) + row).
-  std::vector<int> relL(F.rel.size(), 0);
-  {
-    std::vector<int> cnt;
-    for (int s = 0; s < ns; ++s) {
-      const int mP = F.sn[s].m();
-      cnt.assign(mP, 0);
-      int K = 0;
-      for (int e = F.child_ptr[s]; e < F.child_ptr[s + 1]; ++e) {
-        const Supernode& C = F.sn[F.children[e]];
-        for (int r = 0; r < C.nbelow; ++r) {
-          const int pos = F.rel[C.rows_off + r];
-          const int layer = cnt[pos]++;
-          K = std::max(K, layer + 1);
-          relL[C.rows_off + r] = layer * mP + pos;
-        }
-      }
-      sinfo[s].nchild = K;
-    }
-  }
-  int64_t vp_total = 0;
-  for (int s = 0; s < ns; ++s) {
-    SnInfo& I = sinfo[s];
-    I.vp_in = vp_total;
-    vp_total += (int64_t)I.nchild * 3 * (I.ncol + I.nbelow);
-  }
-  for (int s = 0; s < ns; ++s)
-    for (int e = F.child_ptr[s]; e < F.child_ptr[s + 1]; ++e)
-      sinfo[F.children[e]].vp_out = sinfo[s].vp_in;
-  for (int s = 0; s < ns; ++s) {
-    SnInfo& I = sinfo[s];
-    I.child_items = 0;
-    for (int e = F.child_ptr[s]; e < F.child_ptr[s + 1]; ++e) I.child_items += sinfo[F.children[e]].fw_items;
-  }
-  // subtree tasks: roots are bottom supernodes whose parent is not a bottom
-  // supernode; a subtree is a contiguous range of the postordered supernodes.
-  // A task (one workgroup) takes one or more whole subtrees.
-  std::vector<int4> sub_fw, sub_bw;
-  std::vector<int> sub_fw_ptr, sub_bw_ptr, task_of(ns, -1);
-  int n_tasks = 0;
-  if (Lsub > 0) {
-    std::vector<int> start(ns);
-    for (int s = 0; s < ns; ++s) {
-      start[s] = s;
-      for (int e = F.child_ptr[s]; e < F.child_ptr[s + 1]; ++e)
-        start[s] = std::min(start[s], start[F.children[e]]);
-    }
-    // subtree roots and sizes (stored block entries)
-    std::vector<int> roots;
-    std::vector<double> size;
-    for (int R = 0; R < ns; ++R) {
-      const Supernode& SR = F.sn[R];
-      if (R == top || SR.level >= Lsub) continue;
-      if (SR.parent >= 0 && SR.parent != top && F.sn[SR.parent].level < Lsub) continue;
-      double e = 0.0;
-      for (int s = start[R]; s <= R; ++s)
-        e += (double)F.sn[s].ncol * (F.sn[s].ncol + 1) / 2 + (double)F.sn[s].ncol * F.sn[s].nbelow;
-      roots.push_back(R);
-      size.push_back(e);
-    }
-    // at most one workgroup per compute unit (the subtree kernels' LDS
-    // allows one per CU): largest subtrees first, each to the lightest group
-    const int ngroups = std::min((int)roots.size(), kSubGroups);
-    std::vector<int> order(roots.size());
-    for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
-    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return size[x] > size[y]; });
-    std::vector<std::vector<int>> members(ngroups);
-    std::vector<double> load(ngroups, 0.0);
-    for (int i : order) {
-      const int g = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-      members[g].push_back(roots[i]);
-      load[g] += size[i];
-    }
-    for (int g = 0; g < ngroups; ++g) {
-      std::sort(members[g].begin(), members[g].end());
-      std::vector<std::vector<int4>> fw(Lsub), bw(Lsub);
-      for (int R : members[g])
-        for (int s = start[R]; s <= R; ++s) {
-          const Supernode& S = F.sn[s];
-          task_of[s] = n_tasks;
-          const int nc = S.ncol, m = S.m();
-          const int Lf = clampi(pow2ceil((nc + 3) / 4), 4, 64), rf = 4 * (64 / Lf);
-          for (int r0 = 0; r0 < m; r0 += rf)
-            fw[S.level].push_back(make_int4(s, r0, std::min(m, r0 + rf), Lf));
-          const int Lb = clampi(pow2ceil((m + 3) / 4), 4, 64), cb = 4 * (64 / Lb);
-          for (int c0 = 0; c0 < nc; c0 += cb)
-            bw[S.level].push_back(
-                make_int4((int)(0x80000000u | (unsigned)s), c0, std::min(nc, c0 + cb), Lb));
-        }
-      for (int l = 0; l < Lsub; ++l) {
-        sub_fw_ptr.push_back((int)sub_fw.size());
-        sub_fw.insert(sub_fw.end(), fw[l].begin(), fw[l].end());
-        sub_bw_ptr.push_back((int)sub_bw.size());
-        sub_bw.insert(sub_bw.end(), bw[l].begin(), bw[l].end());
-      }
-      sub_fw_ptr.push_back((int)sub_fw.size());
-      sub_bw_ptr.push_back((int)sub_bw.size());
-      ++n_tasks;
-    }
-  }
-  D.levels.assign(F.nlevels, Level{0, 0, 0, 0});
-  for (int l = 0; l < F.nlevels; ++l) {
-    D.levels[l].fw_begin = (int)fwl.size();
-    fwl.insert(fwl.end(), fw_by_level[l].begin(), fw_by_level[l].end());
-    D.levels[l].fw_end = (int)fwl.size();
-  }
-  for (int l = F.nlevels - 1; l >= 0; --l) {
-    D.levels[l].bw_begin = (int)fwl.size();
-    fwl.insert(fwl.end(), bw_by_level[l].begin(), bw_by_level[l].end());
-    D.levels[l].bw_end = (int)fwl.size();
-  }
-  // Self-check of the solve schedule before anything reaches the device:
-  // item ranges inside their supernode and within the 4 rows/columns per lane
-  // group the kernel handles, every row and column covered exactly once,
-  // packed offsets, row lists and assembly indices inside their arrays.
-  {
-    std::vector<int> cover_r(ns, 0), cover_c(ns, 0);
-    for (const int4& it : fwl) {
-      const bool bwd = it.x < 0;
-      const int s = it.x & 0x7fffffff;
-      if (s < 0 || s >= ns) return fail(c, QNSIM_E_DEVICE, "schedule: bad supernode");
-      const SnInfo& I = sinfo[s];
-      const int lim = bwd ? I.ncol : I.ncol + I.nbelow;
-      if (it.y < 0 || it.z > lim || it.y >= it.z || it.w < 4 || it.w > 64 || (64 % it.w) != 0 ||
-          it.z - it.y > 4 * 4 * (64 / it.w))
-        return fail(c, QNSIM_E_DEVICE, "schedule: bad item range");
-      (bwd ? cover_c : cover_r)[s] += it.z - it.y;
-    }
-    for (int t = 0; t < n_tasks; ++t) {
-      for (int pass = 0; pass < 2; ++pass) {
-        const std::vector<int>& ptr = pass ? sub_bw_ptr : sub_fw_ptr;
-        const std::vector<int4>& its = pass ? sub_bw : sub_fw;
-        for (int l = 0; l < Lsub; ++l) {
-          const int b = ptr[(size_t)t * (Lsub + 1) + l], e = ptr[(size_t)t * (Lsub + 1) + l + 1];
-          if (b > e || e > (int)its.size()) return fail(c, QNSIM_E_DEVICE, "schedule: bad subtree offsets");
-          for (int i = b; i < e; ++i) {
-            const int4 it = its[i];
-            const int s = it.x & 0x7fffffff;
-            if ((it.x < 0) != (pass == 1) || s < 0 || s >= ns || task_of[s] != t ||
-                F.sn[s].level != l)
-              return fail(c, QNSIM_E_DEVICE, "schedule: subtree item outside its task or level");
-            const SnInfo& I = sinfo[s];
-            const int lim = pass ? I.ncol : I.ncol + I.nbelow;
-            if (I.ncol + I.nbelow > kSubCap || it.y < 0 || it.z > lim || it.y >= it.z ||
-                it.w < 4 || it.w > 64 || (64 % it.w) != 0 || it.z - it.y > 4 * (64 / it.w))
-              return fail(c, QNSIM_E_DEVICE, "schedule: bad subtree item range");
-            (pass ? cover_c : cover_r)[s] += it.z - it.y;
-          }
-        }
-      }
-    }
-    for (int s = 0; s < ns; ++s) {
-      if (task_of[s] < 0) continue;
-      const int p = sinfo[s].parent;
-      // the parent is in the same subtree at a higher level, or outside every subtree
-      if (p >= 0 && !((task_of[p] == task_of[s] && F.sn[p].level > F.sn[s].level) ||
-                      (task_of[p] < 0 && (p == top || F.sn[p].level >= Lsub))))
-        return fail(c, QNSIM_E_DEVICE, "schedule: subtree parent order");
-    }
-    for (int s = 0; s < ns; ++s) {
-      const SnInfo& I = sinfo[s];
-      const bool is_top = s == top;
-      if (is_top ? (cover_r[s] != 0 || cover_c[s] != 0 || I.nbelow != 0 || I.parent >= 0 ||
-                    s != ns - 1 || I.ncol > kMaxDenseTop || I.first + I.ncol != nf)
-                 : (cover_r[s] != I.ncol + I.nbelow || cover_c[s] != I.ncol))
-        return fail(c, QNSIM_E_DEVICE, "schedule: rows or columns not covered once");
-      if (I.fw_off + (is_top ? (int64_t)I.ncol * I.ncol
-                             : (int64_t)I.ncol * (I.ncol + 1) / 2 + (int64_t)I.nbelow * I.ncol) >
-              (int64_t)Bf.size() ||
-          (!is_top && I.bw_off + (int64_t)I.ncol * (I.ncol + 1) / 2 + (int64_t)I.nbelow * I.ncol >
-                          (int64_t)Bb.size()))
-        return fail(c, QNSIM_E_DEVICE, "schedule: block offset out of range");
-      if (I.rows_off + I.nbelow > (int64_t)F.rows.size() || I.first < 0 || I.first + I.ncol > nf ||
-          I.vp_in < 0 || I.vp_in + (int64_t)I.nchild * 3 * (I.ncol + I.nbelow) > vp_total ||
-          (I.parent >= 0) != (I.vp_out >= 0) ||
-          I.parent >= ns || (I.parent >= 0 && I.vp_out != sinfo[I.parent].vp_in) ||
-          (I.parent < 0 && I.nbelow != 0))
-        return fail(c, QNSIM_E_DEVICE, "schedule: row list or update offset out of range");
-      for (int r = 0; r < I.nbelow; ++r) {
-        int g = F.rows[I.rows_off + r];
-        if (g < I.first + I.ncol || g >= nf) return fail(c, QNSIM_E_DEVICE, "schedule: bad row");
-      }
-      if (I.parent >= ns) return fail(c, QNSIM_E_DEVICE, "schedule: bad parent");
-      if (I.parent >= 0) {
-        const SnInfo& P = sinfo[I.parent];
-        const int mP = P.ncol + P.nbelow;
-        for (int r = 0; r < I.nbelow; ++r) {
-          const int pos = F.rel[I.rows_off + r];
-          const int lp = relL[I.rows_off + r];
-          if (pos < 0 || pos >= mP || (r > 0 && pos <= F.rel[I.rows_off + r - 1]) ||
-              lp % mP != pos || lp / mP >= P.nchild)
-            return fail(c, QNSIM_E_DEVICE, "schedule: bad relative row");
-        }
-      }
-    }
-    // topological order: forward items of a supernode come after those of its
-    // children, backward items after those of its parent and after all forward items
-    std::vector<int> last_fw(ns, -1), first_fw(ns, 1 << 30), first_bw(ns, 1 << 30), last_bw(ns, -1);
-    for (int i = 0; i < (int)fwl.size(); ++i) {
-      const int s = fwl[i].x & 0x7fffffff;
-      if (fwl[i].x < 0) { first_bw[s] = std::min(first_bw[s], i); last_bw[s] = i; }
-      else { first_fw[s] = std::min(first_fw[s], i); last_fw[s] = i; }
-    }
-    // the dense top block runs between the two sweeps: after every forward
-    // item and before every backward item
-    for (int s = 0; s < ns; ++s) {
-      if (s == top) continue;
-      const int p = sinfo[s].parent;
-      if (p == top) continue;
-      if (p >= 0 && !(last_fw[s] < first_fw[p] && last_bw[p] < first_bw[s]))
-        return fail(c, QNSIM_E_DEVICE, "schedule: items not in topological order");
-      if (p < 0 && !(last_fw[s] < first_bw[s])) return fail(c, QNSIM_E_DEVICE, "schedule: root order");
-    }
-  }
-  // host-side construction done: select the device and upload
-  if (hipSetDevice(D.device) != hipSuccess)
-    return fail(c, QNSIM_E_DEVICE, "hipSetDevice failed (no GPU?)");
-  UP(D.tv, tv);
-  UP(D.Bm, Bm);
-  D.mixed = c->opt.precision == QNSIM_MIXED;
-  UP(D.vol, vol);
-  if (D.nmat > 1) UP(D.tmat, tm);
-  UP(D.mats, dm);
-  UP(D.mass, mass);
-  D.inc_w = inc_w;
-  UP(D.inc_tab, inc_tab);
-  UP(D.vperm, c->vperm);
-  UP(D.tperm, c->tperm);
-  D.nsn = ns;
-  D.n_items = (int)fwl.size();
-  auto to_desc = [&](const std::vector<int4>& in) {
-    std::vector<ItemDesc> out(in.size());
-    for (size_t i = 0; i < in.size(); ++i) {
-      const int4 it = in[i];
-      const bool bwd = it.x < 0;
-      const SnInfo& I = sinfo[it.x & 0x7fffffff];
-      ItemDesc& d = out[i];
-      d.begin = it.y; d.end = it.z; d.L = it.w; d.nchild = I.nchild;
-      d.first = I.first; d.ncol = I.ncol; d.nbelow = I.nbelow; d.pad = 0;
-      d.blk = bwd ? I.bw_off : I.fw_off;
-      d.rows_off = I.rows_off; d.vp_in = I.vp_in; d.vp_out = I.vp_out;
-    }
-    return out;
-  };
-  D.sub_levels = n_tasks > 0 ? Lsub : 0;
-  D.sub_tasks = n_tasks;
-  if (n_tasks > 0) {
-    UP(D.sub_fw, to_desc(sub_fw));
-    UP(D.sub_bw, to_desc(sub_bw));
-    UP(D.sub_fw_ptr, sub_fw_ptr);
-    UP(D.sub_bw_ptr, sub_bw_ptr);
-  }
-  D.top_n = 0;
-  if (top >= 0) {
-    D.top_first = sinfo[top].first;
-    D.top_n = sinfo[top].ncol;
-    D.top_nch = sinfo[top].nchild;
-    D.top_vp = sinfo[top].vp_in;
-    D.top_off = sinfo[top].fw_off;
-  }
-  UP(D.sn, sinfo);
-  UP(D.items, to_desc(fwl));
-  UP(D.Bf, Bf);
-  UP(D.Bb, Bb);
-  UP(D.rows, F.rows);
-  UP(D.rel, relL);
-
-  {
-    std::vector<double> zv((size_t)vp_total + 3, 0.0);  // zero once: see child slots
-    UP(D.vp, zv);
-  }
-  std::string err;
-  int rc = dev_alloc(D, err);
-  if (rc) return fail(c, rc, err);
-  c->prepared = true;
-  return QNSIM_OK;
-}
-
-
 }  // namespace
 
 // ===========================================================================
@@ -797,7 +369,10 @@ int qnsim_prepare(qnsim_t* c, double h) {
   int rc = qnsim_analyze(c, h);
   if (rc) return rc;
   try {
-    rc = upload_impl(c);
+    std::string err;
+    rc = upload_sims({c}, c->opt, c->h, c->dev, err);
+    if (rc) fail(c, rc, err);
+    else c->prepared = true;
   } catch (const std::bad_alloc&) {
     rc = fail(c, QNSIM_E_NOMEM, "host allocation failed");
   }
@@ -824,7 +399,7 @@ static StepParams params_of(const qnsim_t* c, double h) {
   return p;
 }
 
-static void fill_stats(const Ctl& t, double gnorm_last, qnsim_stats* s) {
+static void fill_stats(const SimStat& t, bool have_last, qnsim_stats* s) {
   s->iterations_run = t.iters;
   s->ls_trials = t.trials;
   s->ls_exhausted = t.exhausted;
@@ -832,9 +407,9 @@ static void fill_stats(const Ctl& t, double gnorm_last, qnsim_stats* s) {
   s->fallbacks = t.fallbacks;
   s->reserved = 0;
   s->g_first = t.g_first;
-  s->g_last = t.g_k;
+  s->g_last = t.g_last;
   s->grad_norm_first = std::sqrt(t.gnorm2_first);
-  s->grad_norm_last = gnorm_last;
+  s->grad_norm_last = have_last ? std::sqrt(t.gnorm2_last) : NAN;
 }
 
 static int check_step(qnsim_t* c, double h) {
@@ -852,13 +427,10 @@ int qnsim_step_device(qnsim_t* c, const double* d_x, const double* d_v, double h
   int rc = check_step(c, h);
   if (rc) return rc;
   std::string err;
-  Ctl t;
-  double gl = NAN;
   rc = dev_step(c->dev, params_of(c, h), d_x, d_v, d_fext, d_xo, d_vo,
-                stream ? stream : c->dev.stream, stats != nullptr, &t,
-                c->diag_final_gradient != 0, &gl, err);
+                stream ? stream : c->dev.stream, c->diag_final_gradient != 0, err);
   if (rc) return fail(c, rc, err);
-  if (stats) fill_stats(t, gl, stats);
+  if (stats) fill_stats(c->dev.stat_host[0], c->diag_final_gradient != 0, stats);
   return QNSIM_OK;
 }
 
@@ -872,13 +444,11 @@ int qnsim_run_device(qnsim_t* c, double* d_x, double* d_v, double h, const doubl
   std::memset(&acc, 0, sizeof(acc));
   for (int s = 0; s < steps; ++s) {
     std::string err;
-    Ctl t;
-    double gl = NAN;
     rc = dev_step(c->dev, params_of(c, h), d_x, d_v, d_fext, d_x, d_v,
-                  stream ? stream : c->dev.stream, true, &t, c->diag_final_gradient != 0, &gl, err);
+                  stream ? stream : c->dev.stream, c->diag_final_gradient != 0, err);
     if (rc) return fail(c, rc, err);
     qnsim_stats one;
-    fill_stats(t, gl, &one);
+    fill_stats(c->dev.stat_host[0], c->diag_final_gradient != 0, &one);
     acc.iterations_run += one.iterations_run;
     acc.ls_trials += one.ls_trials;
     acc.ls_exhausted += one.ls_exhausted;
@@ -922,11 +492,10 @@ int qnsim_step(qnsim_t* c, const double* x, const double* v, double h, const dou
     if (rc) { cleanup(); return fail(c, rc, err); }
     if (inv) { cleanup(); return fail(c, QNSIM_E_INVERTED, "Neo-Hookean element with J <= 0 at x"); }
   }
-  Ctl t;
-  double gl = NAN;
-  rc = dev_step(c->dev, params_of(c, h), dx, dv, f_ext ? df : nullptr, dxo, dvo, st, true, &t,
-                c->diag_final_gradient != 0, &gl, err);
+  rc = dev_step(c->dev, params_of(c, h), dx, dv, f_ext ? df : nullptr, dxo, dvo, st,
+                c->diag_final_gradient != 0, err);
   if (rc) { cleanup(); return fail(c, rc, err); }
+  const SimStat t = c->dev.stat_host[0];
   if (hipMemcpyAsync(x_out, dxo, n3 * 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
       hipMemcpyAsync(v_out, dvo, n3 * 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
       hipStreamSynchronize(st) != hipSuccess) {
@@ -934,7 +503,7 @@ int qnsim_step(qnsim_t* c, const double* x, const double* v, double h, const dou
     return fail(c, QNSIM_E_DEVICE, "device-to-host copy failed");
   }
   cleanup();
-  if (stats) fill_stats(t, gl, stats);
+  if (stats) fill_stats(t, c->diag_final_gradient != 0, stats);
   return QNSIM_OK;
 }
 

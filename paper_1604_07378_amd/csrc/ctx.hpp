@@ -43,3 +43,10 @@ struct qnsim {
   bool prepared = false;
   qn::DeviceMesh dev;
 };
+
+namespace qn {
+// Device mesh of one or more analyzed simulations (all analyzed for h),
+// concatenated; returns 0 or a negative QNSIM_E_* code with err set.
+int upload_sims(const std::vector<const qnsim*>& sims, const qnsim_options& opt, double h,
+                DeviceMesh& D, std::string& err);
+}  // namespace qn

@@ -28,31 +28,66 @@ struct DevMat {
   double d2[8], a0[8], a1[8];
 };
 
-// Control block of one step, resident in device memory. Only single-block
-// "decide" kernels write it; every other kernel reads it to predicate itself.
+// Phase of one simulation within a step (each simulation of a batch moves
+// through Algorithm 1 on its own; every kernel works only on the simulations
+// in the phase it serves).
+enum Phase {
+  PH_IDLE = 0,    // not stepping
+  PH_INIT = 1,    // evaluate g(x_1), x_1 = y
+  PH_RETRY = 2,   // g(y) was not finite: evaluate again at x_1 = x
+  PH_GATHER = 3,  // form x_k and grad g(x_k), store the curvature pair
+  PH_DIR = 4,     // two-loop recursion and the prefactored solve
+  PH_LS = 5,      // backtracking line search along d
+  PH_DONE = 6,    // final iterate known
+  PH_FAILED = 7   // g not finite at the input state either
+};
+
+// Control block of one simulation in one step, resident in device memory.
+// Only the single-block "decide" kernels and the step set-up write it; every
+// other kernel reads it to select its simulations.
 struct Ctl {
   double g_k;          // objective at the current iterate
   double gtd;          // grad g(x_k) . d_k
   double alpha;        // current trial step length
-  double g_first, gnorm2_first;
   double gnorm2_cur;   // |grad g(x_k)|^2 of the current iterate
   double rho[kSlots];        // s_i . t_i of the pair in ring slot i
   double zeta[kSlots];       // first-loop coefficients of the two-loop recursion
   double coef[kSlots];       // zeta_i - eta_i (second loop)
   double sg[kSlots];         // s_i . grad g(x_k)
   double G[kSlots][kSlots];  // G[i][j] = s_i . t_j for stored pairs i, j
-  int active;          // step still iterating
-  int need_host;       // a rare event needs the host (budget, non-descent, infeasible y)
-  int host_reason;     // 1 = line-search budget, 2 = non-descent, 3 = infeasible y
-  int ls_done;         // current iteration's line search accepted
+  int phase;           // Phase
+  int k;               // current iteration (0-based)
+  int dir_cycle;       // cycle whose direction pass formed d (the d update runs then)
+  int final_add;       // x' = x_k + alpha d (last line search accepted) rather than x_k
   int npairs;          // stored curvature pairs (<= m)
   int newest;          // ring slot of the newest pair
   int cand;            // ring slot written by this iteration's gather
   int trials_iter;     // trials in the current line search
-  int trials, skipped, fallbacks, exhausted, iters;
-  int final_k;         // iteration whose iterate is returned when exhausted
-  int inverted;        // inverted-input check result
-  int pad;
+};
+
+// Per-simulation statistics of the last step (64 bytes), written by the
+// decide kernels and copied to the host once per step.
+struct SimStat {
+  double g_first, g_last, gnorm2_first, gnorm2_last;
+  int phase, iters, trials, skipped, fallbacks, exhausted, inverted, pad;
+};
+
+// One simulation of a batch: its ranges in the concatenated arrays.
+struct SimSeg {
+  int vf0, nf;         // free vertices [vf0, vf0 + nf) (internal order)
+  int t0, T;           // tetrahedra [t0, t0 + T)
+  int eb0, eb1;        // element-pass blocks
+  int gb0, gb1;        // gather blocks
+  int rb0, rb1;        // r0-dot blocks
+  int vb0, vb1;        // vector blocks
+};
+
+// Work of one block of a segmented kernel: simulation and index ranges.
+// Element pass: tets [a0, a1) and the inertia terms of free vertices
+// [b0, b1); gather: free vertices [a0, a1); vector passes: entries [a0, a1)
+// of the 3-component free-vertex vectors.
+struct BlockSeg {
+  int sim, a0, a1, b0, b1, pad0, pad1, pad2;
 };
 
 struct Level {
@@ -90,6 +125,18 @@ struct DeviceMesh {
   int device = 0;
   int n = 0, nf = 0, T = 0, nmat = 0, single_type = -1, m = 5, slots = 6;
   double h = 0.0;
+  // simulations of the batch (one for a single mesh); vertices, tets and the
+  // factor are the concatenation of theirs (A is block diagonal)
+  int S = 1;
+  std::vector<SimSeg> seg_h;  // host copy of seg
+  SimSeg* seg = nullptr;      // S
+  int* vsim = nullptr;        // n: simulation of each internal vertex
+  int* run = nullptr;         // S: simulation takes part in the current step
+  BlockSeg* eblk = nullptr;   // element-pass blocks
+  BlockSeg* gblk = nullptr;   // gather blocks (64 vertices each)
+  BlockSeg* vblk = nullptr;   // vector-pass blocks (256 entries each)
+  BlockSeg* rblk = nullptr;   // r0-dot blocks (1024 entries each)
+  int* dir_count = nullptr;   // simulations whose direction is being formed (solve gate)
   // element data (internal tet order)
   int* tv = nullptr;          // T x 4 internal vertex ids
   double* Bm = nullptr;       // 9 x T (SoA) entries of Dm^{-1}, row-major per tet
@@ -129,9 +176,10 @@ struct DeviceMesh {
   double* x0 = nullptr;       // n x 3 input positions
   double* v0 = nullptr;       // n x 3 input velocities
   double* y = nullptr;        // n x 3 inertial target
-  double* X[2] = {nullptr, nullptr};   // n x 3 iterates (double buffer)
-  double* G[2] = {nullptr, nullptr};   // nf x 3 gradients (double buffer)
-  double* d = nullptr;        // nf x 3 direction (solve output, loop 2 in place)
+  double* X = nullptr;        // n x 3 current iterate x_k (pinned rows: input positions)
+  double* G = nullptr;        // nf x 3 gradient at x_k
+  double* d = nullptr;        // nf x 3 direction
+  double* r = nullptr;        // nf x 3 solve output r0 = A^{-1} q
   double* q = nullptr;        // nf x 3 loop-1 output / solve input
   double* z = nullptr;        // nf x 3 forward-solve intermediate
   double* Sv = nullptr;       // slots x nf x 3
@@ -143,8 +191,10 @@ struct DeviceMesh {
   int vec3_blocks = 1;        // blocks of the vector kernels (one entry per thread)
   int rdots_blocks = 1;       // blocks of the r0 dot products (1024 threads)
   int elem_blocks = 1;
-  Ctl* ctl = nullptr;
-  Ctl* ctl_host = nullptr;    // pinned mirror
+  Ctl* ctl = nullptr;         // S
+  SimStat* stat = nullptr;    // S
+  SimStat* stat_host = nullptr;  // pinned mirror
+  int* run_host = nullptr;    // pinned staging of the participation mask
   void* stream = nullptr;     // internal stream (hipStream_t)
   void* ev[2] = {nullptr, nullptr};
   size_t bytes = 0;
@@ -158,7 +208,8 @@ struct StepParams {
 };
 
 // Prefactored solve r = A^{-1} q on the stream (internal order, nf x 3).
-void launch_solve(DeviceMesh& D, hipStream_t st, const double* q, double* r, const Ctl* ctl);
+// gate: if not null, the launches do nothing while *gate <= 0.
+void launch_solve(DeviceMesh& D, hipStream_t st, const double* q, double* r, const int* gate);
 
 // Workgroups of the dense top product for an n-column block: rows are split
 // evenly, at most 32 per workgroup, at most 256 workgroups unless more are
@@ -175,10 +226,15 @@ int dev_alloc(DeviceMesh& d, std::string& err);
 void dev_free(DeviceMesh& d);
 int dev_sync(DeviceMesh& d, void* stream, std::string& err);
 
-// One full time step on the device. x/v/fext/xo/vo: caller numbering n x 3.
+// One full time step of every simulation whose run flag is set (set_run
+// uploads the flags; a single mesh runs always). x/v/fext/xo/vo: caller
+// numbering, n x 3 (the simulations' vertices concatenated). On return the
+// per-simulation statistics are in D.stat_host; final_gradient adds
+// |grad g(x')|^2 (gnorm2_last) with one more element pass and gather.
 int dev_step(DeviceMesh& d, const StepParams& p, const double* x, const double* v,
-             const double* fext, double* xo, double* vo, void* stream, bool want_ctl,
-             Ctl* ctl_out, bool final_gradient, double* gnorm_last, std::string& err);
+             const double* fext, double* xo, double* vo, void* stream, bool final_gradient,
+             std::string& err);
+int dev_set_run(DeviceMesh& d, const int* run_flags, void* stream, std::string& err);
 
 // Probes.
 int dev_eval(DeviceMesh& d, const double* x, const double* y, double* g_out, double* grad,

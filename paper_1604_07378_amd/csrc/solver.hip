@@ -4,18 +4,24 @@
 // for the descent direction, whose initial Hessian A = M/h^2 + L is applied
 // through the prefactored supernodal Cholesky factor (section 3).
 //
-// Every decision of the step (accept/reject a trial, store/skip a curvature
-// pair) is taken on the device in single-block "decide" kernels that write a
-// control block; all other kernels read the control block and skip their
-// work when it says so. The host therefore enqueues a fixed kernel sequence
-// per step and synchronises once at the end; only rare events (a line search
-// longer than the enqueued trial budget, a non-descent direction, an
-// infeasible inertial target) hand control back to the host, which continues
-// the same step from where the device stopped.
+// A device mesh holds one simulation or a batch of independent ones: their
+// vertices, tets and factors are concatenated (A is block diagonal), and
+// every scalar of the method (objective, step length, curvature pairs,
+// two-loop coefficients) is kept per simulation in its control block. Each
+// kernel covers the whole batch in one launch; every block of a segmented
+// kernel belongs to one simulation and first checks that simulation's phase.
+// Decisions (accept/reject a trial, store/skip a curvature pair) are taken
+// on the device by "decide" kernels with one block per simulation, so each
+// simulation moves through Algorithm 1 at its own pace while the host
+// enqueues a fixed sequence of cycles (line-search trials, gradient gather,
+// direction) and synchronises once per step; simulations that need more
+// cycles (long line searches, a non-descent direction, an infeasible
+// inertial target) get them in a short continuation.
 //
 // All reductions are deterministic: fixed grids, fixed per-thread element
 // assignment, fixed shuffle/LDS trees, and partial sums combined in block
-// order. No atomics.
+// order. A simulation's blocks are laid out exactly as when it runs alone,
+// so its results do not depend on the rest of the batch.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -73,8 +79,6 @@ __device__ __forceinline__ double sum_partials(const double* p, int n, double* s
   return r;
 }
 
-__device__ __forceinline__ bool ctl_run(const Ctl* c) { return c->active && !c->need_host; }
-
 // Block sums of N values per thread, written as out[d * nb + blockIdx.x]:
 // wave sums, then the NW wave results added in wave order (sh: NW * N).
 template <int N, int NW = BS / 64>
@@ -94,19 +98,19 @@ __device__ __forceinline__ void block_sums_to(double (&v)[N], double* sh, double
   }
 }
 
-// Totals of N partial arrays of nb entries (part[d * nb + b]) into tot[0..N),
-// valid in every thread: thread t takes entries t, t + 256, ... of every
-// array (all loads independent), then the block tree of block_sums_to.
+// Totals of N partial arrays (part[d * stride + b], b in [0, nb)) into
+// tot[0..N), valid in every thread: thread t takes entries t, t + 256, ... of
+// every array (all loads independent), then the block tree of block_sums_to.
 template <int N>
-__device__ __forceinline__ void totals_of(const double* __restrict__ part, int nb, double* sh,
-                                          double* tot) {
+__device__ __forceinline__ void totals_of(const double* __restrict__ part, int stride, int nb,
+                                          double* sh, double* tot) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   double v[N];
 #pragma unroll
   for (int d = 0; d < N; ++d) v[d] = 0.0;
   for (int b = threadIdx.x; b < nb; b += BS) {
 #pragma unroll
-    for (int d = 0; d < N; ++d) v[d] += part[(size_t)d * nb + b];
+    for (int d = 0; d < N; ++d) v[d] += part[(size_t)d * stride + b];
   }
 #pragma unroll
   for (int d = 0; d < N; ++d) v[d] = wave_sum(v[d]);
@@ -126,22 +130,36 @@ __device__ __forceinline__ int pair_slot(const Ctl* c, int a, int slots) {
 }
 
 // ---------------------------------------------------------------------------
-// Step setup: inertial target y = x + h v + h^2 (a + f_ext / m) (section 3)
+// Step setup: inertial target y = x + h v + h^2 (a + f_ext / m) (section 3),
+// x_1 = y; pinned vertices keep their input positions. The thread of a
+// simulation's first free vertex resets its control block and statistics.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(BS)
-k_step_init(int n, int nf, const int* __restrict__ vperm, const double* __restrict__ mass,
-            const double* __restrict__ x, const double* __restrict__ v,
-            const double* __restrict__ fext, double h, double ax, double ay, double az,
-            double* __restrict__ x0, double* __restrict__ y, double* __restrict__ X0,
-            double* __restrict__ X1, Ctl* ctl, int slots) {
-  int i = blockIdx.x * BS + threadIdx.x;
-  if (i == 0) {
-    ctl->active = 1; ctl->need_host = 0; ctl->host_reason = 0; ctl->ls_done = 0;
-    ctl->npairs = 0; ctl->newest = 0; ctl->cand = slots > 1 ? 1 : 0; ctl->trials_iter = 0;
-    ctl->trials = 0; ctl->skipped = 0; ctl->fallbacks = 0; ctl->exhausted = 0; ctl->iters = 0;
-    ctl->final_k = -1; ctl->alpha = 0.0; ctl->gtd = 0.0; ctl->inverted = 0;
-  }
+k_step_init(int n, int nf, const int* __restrict__ vsim, const int* __restrict__ run,
+            const SimSeg* __restrict__ seg, const int* __restrict__ vperm,
+            const double* __restrict__ mass, const double* __restrict__ x,
+            const double* __restrict__ v, const double* __restrict__ fext, double h, double ax,
+            double ay, double az, double* __restrict__ x0, double* __restrict__ y,
+            double* __restrict__ X, Ctl* __restrict__ ctl, SimStat* __restrict__ stat, int slots,
+            int* __restrict__ dir_count) {
+  const int i = blockIdx.x * BS + threadIdx.x;
+  if (i == 0) *dir_count = 0;
   if (i >= n) return;
+  const int s = vsim[i];
+  const int on = run[s];
+  if (i == seg[s].vf0) {
+    Ctl* c = ctl + s;
+    c->phase = on ? PH_INIT : PH_IDLE;
+    c->k = 0; c->dir_cycle = -1; c->final_add = 0; c->npairs = 0; c->newest = 0;
+    c->cand = slots > 1 ? 1 : 0; c->trials_iter = 0; c->alpha = 0.0; c->gtd = 0.0;
+    if (on) {
+      SimStat* t = stat + s;
+      t->g_first = 0.0; t->g_last = 0.0; t->gnorm2_first = 0.0; t->gnorm2_last = 0.0;
+      t->phase = PH_INIT; t->iters = 0; t->trials = 0; t->skipped = 0; t->fallbacks = 0;
+      t->exhausted = 0; t->inverted = 0; t->pad = 0;
+    }
+  }
+  if (!on) return;
   const int o = vperm[i];
   const double acc[3] = {ax, ay, az};
   for (int c = 0; c < 3; ++c) {
@@ -152,49 +170,53 @@ k_step_init(int n, int nf, const int* __restrict__ vperm, const double* __restri
       if (fext) a += fext[3 * (size_t)o + c] / mass[i];
       double yi = xi + h * v[3 * (size_t)o + c] + h * h * a;
       y[3 * (size_t)i + c] = yi;
-      X0[3 * (size_t)i + c] = yi;
+      X[3 * (size_t)i + c] = yi;
     } else {
       y[3 * (size_t)i + c] = xi;
-      X0[3 * (size_t)i + c] = xi;
-      X1[3 * (size_t)i + c] = xi;
+      X[3 * (size_t)i + c] = xi;
     }
   }
 }
 
-// x_1 := x on the free vertices (fallback when g(y) is not finite).
+// x_1 := x on the free vertices of simulations whose g(y) was not finite.
 __global__ void __launch_bounds__(BS)
-k_copy_free(int nf, const double* __restrict__ src, double* __restrict__ dst) {
-  int i = blockIdx.x * BS + threadIdx.x;
-  if (i < 3 * nf) dst[i] = src[i];
+k_copy_retry(int nf, const int* __restrict__ vsim, const Ctl* __restrict__ ctl,
+             const double* __restrict__ src, double* __restrict__ dst) {
+  const int i = blockIdx.x * BS + threadIdx.x;
+  if (i >= 3 * nf) return;
+  if (ctl[vsim[i / 3]].phase != PH_RETRY) return;
+  dst[i] = src[i];
 }
 
 // ---------------------------------------------------------------------------
 // Element pass (section 3, Eq. PD; section 4, Eq. PDgrad2): per tet
 // F = Ds Dm^{-1}, Psi, P, energy V Psi and gradient contributions
-// V P Dm^{-T} (vertex 0 gets minus their sum); thread i also adds the inertia
-// term of free vertex i. Positions are x_k + alpha d on the free vertices
-// (alpha from the control block in a trial, 0 otherwise).
-// mode 0: evaluate at x_k (always runs); mode 1: line-search trial
-// (predicated on an active, unfinished line search); mode 2: probe.
+// V P Dm^{-T} (vertex 0 gets minus their sum); a block also adds the inertia
+// terms of its range of free vertices. Positions are x_k + alpha d on the
+// free vertices in a line-search trial (alpha from the control block), x_k
+// otherwise. want: the phase the block's simulation must be in (-1: always;
+// probes).
 // ---------------------------------------------------------------------------
 template <int TYPE, typename R>
 __global__ void __launch_bounds__(BS)
-k_elem(int mode, int T, int nf, const int* __restrict__ tv, const double* __restrict__ Bm,
-       const double* __restrict__ vol,
-       const int* __restrict__ tmat, const DevMat* __restrict__ mats,
-       const double* __restrict__ mass, const double* __restrict__ X,
-       const double* __restrict__ d, const double* __restrict__ y, double inv2h2,
-       const Ctl* __restrict__ ctl, R* __restrict__ fel, double* __restrict__ part,
-       double* __restrict__ psi_out) {
+k_elem(int want, int trial, const BlockSeg* __restrict__ blk, int T, int nf,
+       const int* __restrict__ tv, const double* __restrict__ Bm,
+       const double* __restrict__ vol, const int* __restrict__ tmat,
+       const DevMat* __restrict__ mats, const double* __restrict__ mass,
+       const double* __restrict__ X, const double* __restrict__ d,
+       const double* __restrict__ y, double inv2h2, const Ctl* __restrict__ ctl,
+       R* __restrict__ fel, double* __restrict__ part, double* __restrict__ psi_out) {
   __shared__ double sh[16];
+  const BlockSeg sg = blk[blockIdx.x];
   double alpha = 0.0;
-  if (mode == 1) {
-    if (!(ctl_run(ctl) && !ctl->ls_done)) return;
-    alpha = ctl->alpha;
+  if (want >= 0) {
+    const Ctl* c = ctl + sg.sim;
+    if (c->phase != want) return;
+    if (trial) alpha = c->alpha;
   }
-  const int t = blockIdx.x * BS + threadIdx.x;
+  const int t = sg.a0 + threadIdx.x;
   double e = 0.0;
-  if (t < T) {
+  if (t < sg.a1) {
     const int4 iv = reinterpret_cast<const int4*>(tv)[t];
     const int vid[4] = {iv.x, iv.y, iv.z, iv.w};
     double p[4][3];
@@ -204,7 +226,7 @@ k_elem(int mode, int T, int nf, const int* __restrict__ tv, const double* __rest
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         double xv = X[3 * (size_t)v + c];
-        if (mode == 1 && v < nf) xv = __fma_rn(alpha, d[3 * (size_t)v + c], xv);
+        if (trial && v < nf) xv = __fma_rn(alpha, d[3 * (size_t)v + c], xv);
         p[a][c] = xv;
       }
     }
@@ -253,93 +275,104 @@ k_elem(int mode, int T, int nf, const int* __restrict__ tv, const double* __rest
 #pragma unroll
       for (int c = 0; c < 3; ++c) o[3 * a + c] = g[a][c];
   }
-  if (t < nf) {
+  const int vi = sg.b0 + threadIdx.x;
+  if (vi < sg.b1) {
     double s = 0.0;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      double xv = X[3 * (size_t)t + c];
-      if (mode == 1) xv = __fma_rn(alpha, d[3 * (size_t)t + c], xv);
-      double dx = xv - y[3 * (size_t)t + c];
+      double xv = X[3 * (size_t)vi + c];
+      if (trial) xv = __fma_rn(alpha, d[3 * (size_t)vi + c], xv);
+      double dx = xv - y[3 * (size_t)vi + c];
       s += dx * dx;
     }
-    e += mass[t] * s * inv2h2;
+    e += mass[vi] * s * inv2h2;
   }
   double b = block_sum(e, sh);
   if (threadIdx.x == 0 && part) part[blockIdx.x] = b;
 }
 
-// g(x_1): start of the step.
+// g(x_1) of each simulation in phase `want` (PH_INIT, or PH_RETRY after
+// x_1 := x): one block per simulation.
 __global__ void __launch_bounds__(BS)
-k_init_decide(const double* __restrict__ part, int nparts, Ctl* ctl) {
+k_init_decide(int want, const SimSeg* __restrict__ seg, const double* __restrict__ part,
+              Ctl* __restrict__ ctl, SimStat* __restrict__ stat) {
   __shared__ double sh[16];
-  double g = sum_partials(part, nparts, sh);
-  if (threadIdx.x == 0) {
-    if (!ctl_run(ctl)) return;
-    if (!isfinite(g)) {
-      ctl->need_host = 1;
-      ctl->host_reason = 3;
-      return;
-    }
-    ctl->g_k = g;
-    ctl->g_first = g;
+  const int s = blockIdx.x;
+  Ctl* c = ctl + s;
+  if (c->phase != want) return;
+  const SimSeg sg = seg[s];
+  double g = sum_partials(part + sg.eb0, sg.eb1 - sg.eb0, sh);
+  if (threadIdx.x != 0) return;
+  SimStat* t = stat + s;
+  if (!isfinite(g)) {
+    c->phase = want == PH_INIT ? PH_RETRY : PH_FAILED;
+    if (want == PH_INIT) t->fallbacks += 1;
+  } else {
+    c->g_k = g;
+    c->k = 0;
+    c->phase = PH_GATHER;
+    t->g_first = g;
+    t->g_last = g;
   }
+  t->phase = c->phase;
 }
 
 // ---------------------------------------------------------------------------
 // Gradient gather of iteration k (section 4, Eq. PDgrad2): x_k = x_{k-1} +
-// alpha d, s = x_k - x_{k-1}, grad = M/h^2 (x_k - y) + sum of element
-// contributions (incidence lists, fixed order), t = grad - grad_{k-1}; s and
-// t go to the candidate ring slot. The same pass forms every dot product the
-// two-loop recursion needs, so that the recursion runs on scalars (Gram
-// form): dots [0..3] = t.s, s.s, t.t, g.g and, per ring slot j,
-// [4 + 3j] = s_j.g, [5 + 3j] = s.t_j, [6 + 3j] = s_j.t (the candidate's own
-// entries use the new s and t).
+// alpha d (in place), s = x_k - x_{k-1}, grad = M/h^2 (x_k - y) + sum of
+// element contributions (incidence lists, fixed order), t = grad -
+// grad_{k-1} (in place); s and t go to the candidate ring slot. The same pass
+// forms every dot product the two-loop recursion needs, so that the
+// recursion runs on scalars (Gram form): dots [0..3] = t.s, s.s, t.t, g.g
+// and, per ring slot j, [4 + 3j] = s_j.g, [5 + 3j] = s.t_j, [6 + 3j] = s_j.t
+// (the candidate's own entries use the new s and t). probe: every
+// simulation, gradient at X (k = 0).
+// ---------------------------------------------------------------------------
 constexpr int kWideBS = 1024;  // threads per block of the r0 dots
 
 template <int SL, typename FT>
 __global__ void __launch_bounds__(BS)
-k_gather(int k, int nf, int slots, int inc_w, const int* __restrict__ inc_tab,
-         const FT* __restrict__ fel, const double* __restrict__ mass,
-         const double* __restrict__ y, double inv_h2, const double* __restrict__ Xp,
-         double* __restrict__ Xc, const double* __restrict__ d, const double* __restrict__ Gp,
-         double* __restrict__ Gc, double* __restrict__ Sall, double* __restrict__ Tall,
-         const Ctl* __restrict__ ctl, double* __restrict__ part) {
+k_gather(int probe, const BlockSeg* __restrict__ blk, size_t n3, int slots, int inc_w,
+         const int* __restrict__ inc_tab, const FT* __restrict__ fel,
+         const double* __restrict__ mass, const double* __restrict__ y, double inv_h2,
+         double* __restrict__ X, const double* __restrict__ d, double* __restrict__ Gr,
+         double* __restrict__ Sall, double* __restrict__ Tall, const Ctl* __restrict__ ctl,
+         double* __restrict__ part) {
   constexpr int ND = 4 + 3 * SL;
   __shared__ double sh[(BS / 64) * ND];
-  if (!ctl_run(ctl)) return;
-  const double alpha = ctl->alpha;
-  const int cand = ctl->cand;
-  const size_t n3 = 3 * (size_t)nf;
+  const BlockSeg sg = blk[blockIdx.x];
+  const Ctl* cs = ctl + sg.sim;
+  if (!probe && cs->phase != PH_GATHER) return;
+  const int k = probe ? 0 : cs->k;
+  const double alpha = cs->alpha;
+  const int cand = cs->cand;
   double acc[ND];
 #pragma unroll
   for (int j = 0; j < ND; ++j) acc[j] = 0.0;
   // four lanes per vertex: lane gl sums incidence-table entries gl + 4u,
   // a butterfly gives all four lanes the same total, and lane gl < 3 then
   // handles component gl
-  const int gid = blockIdx.x * BS + threadIdx.x;
-  const int i = gid >> 2, gl = gid & 3;
-  const bool live = i < nf, own = live && gl < 3;
-  const size_t ic = 3 * (size_t)(live ? i : 0) + (gl < 3 ? gl : 0);
+  const int i = sg.a0 + (threadIdx.x >> 2), gl = threadIdx.x & 3;
+  const bool live = i < sg.a1, own = live && gl < 3;
+  const size_t ic = 3 * (size_t)(live ? i : sg.a0) + (gl < 3 ? gl : 0);
   // loads that do not depend on the incidence sums go first
-  double mi = 0.0, yy = 0.0, xp = 0.0, dd = 0.0, gp = 0.0, x0 = 0.0;
+  double mi = 0.0, yy = 0.0, xp = 0.0, dd = 0.0, gp = 0.0;
   double sj[SL], tj[SL];
 #pragma unroll
   for (int j = 0; j < SL; ++j) sj[j] = tj[j] = 0.0;
   if (own) {
     mi = mass[i] * inv_h2;
     yy = y[ic];
+    xp = X[ic];
     if (k > 0) {
-      xp = Xp[ic];
       dd = d[ic];
-      gp = Gp[ic];
+      gp = Gr[ic];
 #pragma unroll
       for (int j = 0; j < SL; ++j)
         if (j < slots && j != cand) {  // ring slots beyond m + 1 are not allocated
           sj[j] = Sall[(size_t)j * n3 + ic];
           tj[j] = Tall[(size_t)j * n3 + ic];
         }
-    } else {
-      x0 = Xc[ic];
     }
   }
   double f[3] = {0.0, 0.0, 0.0};
@@ -365,18 +398,16 @@ k_gather(int k, int nf, int slots, int inc_w, const int* __restrict__ inc_tab,
   for (int c = 0; c < 3; ++c) f[c] = group_sum(f[c], 4);
   if (own) {
     const double fc = gl == 0 ? f[0] : (gl == 1 ? f[1] : f[2]);
-    double xc, sv = 0.0, tv = 0.0;
+    double xc = xp, sv = 0.0, tv = 0.0;
     if (k > 0) {
       xc = __fma_rn(alpha, dd, xp);
-      Xc[ic] = xc;
+      X[ic] = xc;
       sv = xc - xp;
       Sall[(size_t)cand * n3 + ic] = sv;
       acc[1] += sv * sv;
-    } else {
-      xc = x0;
     }
     const double gr = mi * (xc - yy) + fc;
-    Gc[ic] = gr;
+    Gr[ic] = gr;
     acc[3] += gr * gr;
     if (k > 0) {
       tv = gr - gp;
@@ -403,25 +434,31 @@ k_gather(int k, int nf, int slots, int inc_w, const int* __restrict__ inc_tab,
 // loop of the two-loop recursion (Algorithm 2) on scalars, newest pair first:
 //   zeta_i = s_i . q_i / rho_i,  q_i = -grad - sum_{j newer than i} zeta_j t_j,
 //   s_i . q_i = -s_i . grad - sum_{j newer} zeta_j G[i][j].
-// Resets the line search of iteration k.
+// One block per simulation.
 template <int SL>
 __global__ void __launch_bounds__(BS)
-k_pair_decide(int k, int m, const double* __restrict__ part, int nb, Ctl* ctl) {
+k_pair_decide(int m, const SimSeg* __restrict__ seg, const double* __restrict__ part, int nb,
+              Ctl* __restrict__ ctl, SimStat* __restrict__ stat, int* __restrict__ dir_count) {
   constexpr int ND = 4 + 3 * SL;
   __shared__ double red[4 * ND], tot[ND];
   __shared__ double sG[SL][SL], srho[SL], szeta[SL];
+  const int sim = blockIdx.x;
+  Ctl* ctl_s = ctl + sim;
+  if (ctl_s->phase != PH_GATHER) return;
   const int slots = m + 1;  // <= SL
   // the control state the recursion reads, staged in LDS in parallel
-  for (int t = threadIdx.x; t < slots * slots; t += BS) sG[t / slots][t % slots] = ctl->G[t / slots][t % slots];
-  if (threadIdx.x < slots) srho[threadIdx.x] = ctl->rho[threadIdx.x];
-  const int run = ctl_run(ctl), cand = ctl->cand, newest0 = ctl->newest, np0 = ctl->npairs;
-  const int skipped0 = ctl->skipped;
-  totals_of<ND>(part, nb, red, tot);  // includes a barrier after the staging
-  if (threadIdx.x != 0 || !run) return;
+  for (int t = threadIdx.x; t < slots * slots; t += BS)
+    sG[t / slots][t % slots] = ctl_s->G[t / slots][t % slots];
+  if (threadIdx.x < slots) srho[threadIdx.x] = ctl_s->rho[threadIdx.x];
+  const int k = ctl_s->k, cand = ctl_s->cand, newest0 = ctl_s->newest, np0 = ctl_s->npairs;
+  const SimSeg sg = seg[sim];
+  totals_of<ND>(part + sg.gb0, nb, sg.gb1 - sg.gb0, red, tot);  // barrier after the staging
+  if (threadIdx.x != 0) return;
+  SimStat* st = stat + sim;
   const double ts = tot[0], ss = tot[1], tt = tot[2], gg = tot[3];
   int newest = newest0, np = np0;
   if (k == 0) {
-    ctl->gnorm2_first = gg;
+    st->gnorm2_first = gg;
   } else if (m == 0) {
     // no history window: pairs are never stored, nor counted as skipped
   } else if (ts > 1e-10 * sqrt(ss) * sqrt(tt)) {
@@ -433,24 +470,20 @@ k_pair_decide(int k, int m, const double* __restrict__ part, int nb, Ctl* ctl) {
       if (j == c) continue;
       sG[c][j] = tot[5 + 3 * j];
       sG[j][c] = tot[6 + 3 * j];
-      ctl->G[c][j] = sG[c][j];
-      ctl->G[j][c] = sG[j][c];
+      ctl_s->G[c][j] = sG[c][j];
+      ctl_s->G[j][c] = sG[j][c];
     }
     sG[c][c] = ts;
-    ctl->G[c][c] = ts;
-    ctl->rho[c] = ts;
+    ctl_s->G[c][c] = ts;
+    ctl_s->rho[c] = ts;
   } else {
-    ctl->skipped = skipped0 + 1;
+    st->skipped += 1;
   }
-  for (int j = 0; j < slots; ++j) ctl->sg[j] = k > 0 ? tot[4 + 3 * j] : 0.0;
-  ctl->newest = newest;
-  ctl->npairs = np;
-  ctl->cand = (newest + 1) % slots;
-  ctl->ls_done = 0;
-  ctl->alpha = 1.0;
-  ctl->trials_iter = 0;
-  ctl->iters = k + 1;
-  ctl->gnorm2_cur = gg;
+  for (int j = 0; j < slots; ++j) ctl_s->sg[j] = k > 0 ? tot[4 + 3 * j] : 0.0;
+  ctl_s->newest = newest;
+  ctl_s->npairs = np;
+  ctl_s->cand = (newest + 1) % slots;
+  ctl_s->gnorm2_cur = gg;
   for (int a = 0; a < np; ++a) {
     const int i = (newest - a + slots) % slots;
     double sq = k > 0 ? -tot[4 + 3 * i] : 0.0;
@@ -459,8 +492,12 @@ k_pair_decide(int k, int m, const double* __restrict__ part, int nb, Ctl* ctl) {
       sq -= szeta[j] * sG[i][j];
     }
     szeta[i] = sq / srho[i];
-    ctl->zeta[i] = szeta[i];
+    ctl_s->zeta[i] = szeta[i];
   }
+  ctl_s->phase = PH_DIR;
+  st->phase = PH_DIR;
+  st->iters = k + 1;
+  atomicAdd(dir_count, 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -470,20 +507,21 @@ k_pair_decide(int k, int m, const double* __restrict__ part, int nb, Ctl* ctl) {
 // q = -grad - sum_i zeta_i t_i (newest pair first, the order of the first loop).
 template <int SL>
 __global__ void __launch_bounds__(BS)
-k_qform(int nf, int slots, const double* __restrict__ grad, const double* __restrict__ Tall,
-        double* __restrict__ q, const Ctl* __restrict__ ctl) {
-  if (!ctl_run(ctl)) return;
-  const int np = ctl->npairs;
-  const size_t n3 = 3 * (size_t)nf;
+k_qform(const BlockSeg* __restrict__ blk, size_t n3, int slots, const double* __restrict__ grad,
+        const double* __restrict__ Tall, double* __restrict__ q, const Ctl* __restrict__ ctl) {
+  const BlockSeg sg = blk[blockIdx.x];
+  const Ctl* c = ctl + sg.sim;
+  if (c->phase != PH_DIR) return;
+  const int np = c->npairs;
   int sl[SL];
   double ze[SL];
 #pragma unroll
   for (int a = 0; a < SL; ++a) {
-    sl[a] = a < np ? pair_slot(ctl, a, slots) : 0;
-    ze[a] = a < np ? ctl->zeta[sl[a]] : 0.0;
+    sl[a] = a < np ? pair_slot(c, a, slots) : 0;
+    ze[a] = a < np ? c->zeta[sl[a]] : 0.0;
   }
-  const size_t i = (size_t)blockIdx.x * BS + threadIdx.x;  // one entry per thread
-  if (i >= n3) return;
+  const size_t i = (size_t)sg.a0 + threadIdx.x;  // one entry per thread
+  if (i >= (size_t)sg.a1) return;
   double t[SL];
 #pragma unroll
   for (int a = 0; a < SL; ++a) t[a] = a < np ? Tall[(size_t)sl[a] * n3 + i] : 0.0;
@@ -498,18 +536,20 @@ k_qform(int nf, int slots, const double* __restrict__ grad, const double* __rest
 // [j] = t_j . r0, [SL] = grad . r0.
 template <int SL>
 __global__ void __launch_bounds__(kWideBS)
-k_rdots(int nf, int slots, const double* __restrict__ r0, const double* __restrict__ grad,
-        const double* __restrict__ Tall, double* __restrict__ part, const Ctl* __restrict__ ctl) {
+k_rdots(const BlockSeg* __restrict__ blk, size_t n3, int slots, const double* __restrict__ r0,
+        const double* __restrict__ grad, const double* __restrict__ Tall,
+        double* __restrict__ part, const Ctl* __restrict__ ctl) {
   constexpr int ND = SL + 1;
   __shared__ double sh[(kWideBS / 64) * ND];
-  if (!ctl_run(ctl)) return;
-  const int np = ctl->npairs;
-  const size_t n3 = 3 * (size_t)nf;
+  const BlockSeg sg = blk[blockIdx.x];
+  const Ctl* c = ctl + sg.sim;
+  if (c->phase != PH_DIR) return;
+  const int np = c->npairs;
   bool use[SL];
 #pragma unroll
   for (int j = 0; j < SL; ++j) use[j] = false;
   for (int a = 0; a < np; ++a) {
-    const int j = pair_slot(ctl, a, slots);
+    const int j = pair_slot(c, a, slots);
 #pragma unroll
     for (int jj = 0; jj < SL; ++jj)
       if (jj == j) use[jj] = true;
@@ -517,8 +557,8 @@ k_rdots(int nf, int slots, const double* __restrict__ r0, const double* __restri
   double acc[ND];
 #pragma unroll
   for (int j = 0; j < ND; ++j) acc[j] = 0.0;
-  const size_t i = (size_t)blockIdx.x * kWideBS + threadIdx.x;  // one entry per thread
-  if (i < n3) {
+  const size_t i = (size_t)sg.a0 + threadIdx.x;  // one entry per thread
+  if (i < (size_t)sg.a1) {
     const double r = r0[i];
     acc[SL] = grad[i] * r;
 #pragma unroll
@@ -532,24 +572,33 @@ k_rdots(int nf, int slots, const double* __restrict__ r0, const double* __restri
 //   eta_i = t_i . r_i / rho_i,  r_i = r0 + sum_{j older than i} c_j s_j,
 //   t_i . r_i = t_i . r0 + sum_{j older} c_j G[j][i],   c_i = zeta_i - eta_i;
 // then grad . d = grad . r0 + sum_i c_i s_i . grad and the descent check
-// (grad . d < 0 unless grad = 0).
+// (grad . d < 0 unless grad = 0). A non-descent direction clears the history
+// and the direction is formed again in the next cycle (d = -A^{-1} grad).
+// On success the line search of the iteration starts at alpha = 1.
 template <int SL>
 __global__ void __launch_bounds__(BS)
-k_coef_decide(int m, const double* __restrict__ part, int nb, Ctl* ctl) {
+k_coef_decide(int m, int cyc, const SimSeg* __restrict__ seg, const double* __restrict__ part,
+              int nb, Ctl* __restrict__ ctl, SimStat* __restrict__ stat,
+              int* __restrict__ dir_count) {
   constexpr int ND = SL + 1;
   __shared__ double red[4 * ND], tot[ND];
   __shared__ double sG[SL][SL], srho[SL], szeta[SL], ssg[SL], scoef[SL];
+  const int sim = blockIdx.x;
+  Ctl* ctl_s = ctl + sim;
+  if (ctl_s->phase != PH_DIR) return;
   const int slots = m + 1;  // <= SL
-  for (int t = threadIdx.x; t < slots * slots; t += BS) sG[t / slots][t % slots] = ctl->G[t / slots][t % slots];
+  for (int t = threadIdx.x; t < slots * slots; t += BS)
+    sG[t / slots][t % slots] = ctl_s->G[t / slots][t % slots];
   if (threadIdx.x < slots) {
-    srho[threadIdx.x] = ctl->rho[threadIdx.x];
-    szeta[threadIdx.x] = ctl->zeta[threadIdx.x];
-    ssg[threadIdx.x] = ctl->sg[threadIdx.x];
+    srho[threadIdx.x] = ctl_s->rho[threadIdx.x];
+    szeta[threadIdx.x] = ctl_s->zeta[threadIdx.x];
+    ssg[threadIdx.x] = ctl_s->sg[threadIdx.x];
   }
-  const int run = ctl_run(ctl), np = ctl->npairs, newest = ctl->newest;
-  const double gg = ctl->gnorm2_cur;
-  totals_of<ND>(part, nb, red, tot);  // includes a barrier after the staging
-  if (threadIdx.x != 0 || !run) return;
+  const int np = ctl_s->npairs, newest = ctl_s->newest;
+  const double gg = ctl_s->gnorm2_cur;
+  const SimSeg sg = seg[sim];
+  totals_of<ND>(part + sg.rb0, nb, sg.rb1 - sg.rb0, red, tot);  // barrier after the staging
+  if (threadIdx.x != 0) return;
   double gtd = tot[SL];
   for (int a = np - 1; a >= 0; --a) {
     const int i = (newest - a + slots) % slots;
@@ -559,109 +608,126 @@ k_coef_decide(int m, const double* __restrict__ part, int nb, Ctl* ctl) {
       tr += scoef[j] * sG[j][i];
     }
     scoef[i] = szeta[i] - tr / srho[i];
-    ctl->coef[i] = scoef[i];
+    ctl_s->coef[i] = scoef[i];
   }
   for (int a = np - 1; a >= 0; --a) {
     const int i = (newest - a + slots) % slots;
     gtd += scoef[i] * ssg[i];
   }
   if (!(gtd < 0.0) && gg > 0.0) {
-    ctl->need_host = 1;
-    ctl->host_reason = 2;
+    ctl_s->npairs = 0;
+    ctl_s->dir_cycle = -1;
+    stat[sim].fallbacks += 1;
     return;
   }
-  ctl->gtd = gtd;
+  ctl_s->gtd = gtd;
+  ctl_s->alpha = 1.0;
+  ctl_s->trials_iter = 0;
+  ctl_s->dir_cycle = cyc;
+  ctl_s->phase = PH_LS;
+  stat[sim].phase = PH_LS;
+  atomicSub(dir_count, 1);
 }
 
-// d = r0 + sum_i c_i s_i in place (oldest pair first, the order of the
-// second loop).
+// d = r0 + sum_i c_i s_i (oldest pair first, the order of the second loop),
+// for the simulations whose direction was formed in this cycle.
 template <int SL>
 __global__ void __launch_bounds__(BS)
-k_dform(int nf, int slots, const double* __restrict__ Sall, double* __restrict__ d,
+k_dform(const BlockSeg* __restrict__ blk, size_t n3, int slots, int cyc,
+        const double* __restrict__ Sall, const double* __restrict__ r0, double* __restrict__ d,
         const Ctl* __restrict__ ctl) {
-  if (!ctl_run(ctl)) return;
-  const int np = ctl->npairs;
-  if (np == 0) return;
-  const size_t n3 = 3 * (size_t)nf;
+  const BlockSeg sg = blk[blockIdx.x];
+  const Ctl* c = ctl + sg.sim;
+  if (c->phase != PH_LS || c->dir_cycle != cyc) return;
+  const int np = c->npairs;
   int sl[SL];
   double cf[SL];
 #pragma unroll
   for (int a = 0; a < SL; ++a) {
     const int b = np - 1 - a;  // oldest first
-    sl[a] = b >= 0 ? pair_slot(ctl, b, slots) : 0;
-    cf[a] = b >= 0 ? ctl->coef[sl[a]] : 0.0;
+    sl[a] = b >= 0 ? pair_slot(c, b, slots) : 0;
+    cf[a] = b >= 0 ? c->coef[sl[a]] : 0.0;
   }
-  const size_t i = (size_t)blockIdx.x * BS + threadIdx.x;  // one entry per thread
-  if (i >= n3) return;
+  const size_t i = (size_t)sg.a0 + threadIdx.x;  // one entry per thread
+  if (i >= (size_t)sg.a1) return;
   double sv[SL];
 #pragma unroll
   for (int a = 0; a < SL; ++a) sv[a] = a < np ? Sall[(size_t)sl[a] * n3 + i] : 0.0;
-  double v = d[i];
+  double v = r0[i];
 #pragma unroll
   for (int a = 0; a < SL; ++a)
     if (a < np) v += sv[a] * cf[a];
   d[i] = v;
 }
 
-// Armijo test of one line-search trial (section 4.1, Algorithm 1).
+// Armijo test of one line-search trial (section 4.1, Algorithm 1), one block
+// per simulation. Accepting the trial of the last iteration ends the step
+// (x' = x_k + alpha d); otherwise the next iteration's gather forms x_{k+1}.
 __global__ void __launch_bounds__(BS)
-k_ls_decide(int k, int last_in_budget, int max_halvings, double gamma, double backtrack,
-            const double* __restrict__ part, int nparts, Ctl* ctl) {
+k_ls_decide(int K, int max_halvings, double gamma, double backtrack,
+            const SimSeg* __restrict__ seg, const double* __restrict__ part,
+            Ctl* __restrict__ ctl, SimStat* __restrict__ stat) {
   __shared__ double sh[16];
+  const int sim = blockIdx.x;
+  Ctl* c = ctl + sim;
+  if (c->phase != PH_LS) return;
   // every control field the test reads, loaded before the partial sums
-  const bool run = ctl_run(ctl) && !ctl->ls_done;
-  const double gk = ctl->g_k, alpha = ctl->alpha, gtd = ctl->gtd;
-  const int trials = ctl->trials, tri = ctl->trials_iter;
-  if (!run) return;
-  double g = sum_partials(part, nparts, sh);
+  const double gk = c->g_k, alpha = c->alpha, gtd = c->gtd;
+  const int tri = c->trials_iter, k = c->k;
+  const SimSeg sg = seg[sim];
+  double g = sum_partials(part + sg.eb0, sg.eb1 - sg.eb0, sh);
   if (threadIdx.x != 0) return;
-  ctl->trials = trials + 1;
-  ctl->trials_iter = tri + 1;
+  SimStat* st = stat + sim;
+  st->trials += 1;
+  c->trials_iter = tri + 1;
   if (g <= gk + gamma * alpha * gtd) {
-    ctl->ls_done = 1;
-    ctl->g_k = g;
-  } else if (tri + 1 > max_halvings) {
-    ctl->exhausted = 1;
-    ctl->active = 0;
-    ctl->final_k = k;
-  } else {
-    ctl->alpha = alpha * backtrack;
-    if (last_in_budget) {
-      ctl->need_host = 1;
-      ctl->host_reason = 1;
+    c->g_k = g;
+    st->g_last = g;
+    if (k == K - 1) {
+      c->final_add = 1;
+      c->phase = PH_DONE;
+    } else {
+      c->k = k + 1;
+      c->phase = PH_GATHER;
     }
+  } else if (tri + 1 > max_halvings) {
+    st->exhausted = 1;
+    c->final_add = 0;
+    c->phase = PH_DONE;
+  } else {
+    c->alpha = alpha * backtrack;
   }
+  st->phase = c->phase;
 }
 
 // ---------------------------------------------------------------------------
 // End of step: x' = final iterate, v' = (x' - x)/h; pinned: x' = x, v' = 0.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(BS)
-k_finalize(int n, int nf, int K, const int* __restrict__ vperm, const double* __restrict__ x0,
-           const double* __restrict__ X0, const double* __restrict__ X1,
-           const double* __restrict__ d, double inv_h, const Ctl* __restrict__ ctl,
-           double* __restrict__ xo, double* __restrict__ vo) {
-  if (ctl->need_host) return;
+k_finalize(int n, int nf, const int* __restrict__ vsim, const int* __restrict__ run,
+           const int* __restrict__ vperm, const double* __restrict__ x0,
+           const double* __restrict__ X, const double* __restrict__ d, double inv_h,
+           const Ctl* __restrict__ ctl, double* __restrict__ xo, double* __restrict__ vo) {
   const int i = blockIdx.x * BS + threadIdx.x;
   if (i >= n) return;
-  int kf;
-  bool add;
-  if (ctl->exhausted) { kf = ctl->final_k; add = false; }
-  else { kf = K - 1; add = ctl->ls_done != 0; }
-  const double* Xc = (kf & 1) ? X1 : X0;
-  const double alpha = ctl->alpha;
+  const int s = vsim[i];
+  if (!run[s]) return;
+  const Ctl* c = ctl + s;
+  if (c->phase != PH_DONE) return;
+  const bool add = c->final_add != 0;
+  const double alpha = c->alpha;
   const int o = vperm[i];
 #pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    double xin = x0[3 * (size_t)i + c];
+  for (int comp = 0; comp < 3; ++comp) {
+    double xin = x0[3 * (size_t)i + comp];
     double xf = xin, vf = 0.0;
     if (i < nf) {
-      xf = Xc[3 * (size_t)i + c];
-      if (add) xf = __fma_rn(alpha, d[3 * (size_t)i + c], xf);
+      xf = X[3 * (size_t)i + comp];
+      if (add) xf = __fma_rn(alpha, d[3 * (size_t)i + comp], xf);
       vf = (xf - xin) * inv_h;
     }
-    xo[3 * (size_t)o + c] = xf;
-    vo[3 * (size_t)o + c] = vf;
+    xo[3 * (size_t)o + comp] = xf;
+    vo[3 * (size_t)o + comp] = vf;
   }
 }
 
@@ -686,23 +752,32 @@ k_store_perm(int n, int nf, const int* __restrict__ vperm, const double* __restr
   for (int c = 0; c < 3; ++c) dst[3 * (size_t)o + c] = (i < nf) ? src[3 * (size_t)i + c] : 0.0;
 }
 
-__global__ void k_ctl_probe(Ctl* ctl) {
-  ctl->active = 1; ctl->need_host = 0; ctl->ls_done = 0; ctl->cand = 0; ctl->alpha = 0.0;
-  ctl->npairs = 0; ctl->newest = 0; ctl->inverted = 0;
-}
-
+// Sum of every partial (one simulation) into *out.
 __global__ void __launch_bounds__(BS)
-k_sum_to_ctl(const double* __restrict__ part, int nparts, Ctl* ctl) {
+k_sum_to(const double* __restrict__ part, int nparts, double* __restrict__ out) {
   __shared__ double sh[16];
   double g = sum_partials(part, nparts, sh);
-  if (threadIdx.x == 0) ctl->g_k = g;
+  if (threadIdx.x == 0) *out = g;
+}
+
+// |grad g|^2 of each running simulation from the gather partials of a probe
+// pass (dot 3 of every block), one block per simulation.
+__global__ void __launch_bounds__(BS)
+k_gnorm_last(const SimSeg* __restrict__ seg, const int* __restrict__ run,
+             const double* __restrict__ part, int nb, SimStat* __restrict__ stat) {
+  __shared__ double sh[16];
+  const int s = blockIdx.x;
+  if (!run[s]) return;
+  const SimSeg sg = seg[s];
+  double g = sum_partials(part + 3 * (size_t)nb + sg.gb0, sg.gb1 - sg.gb0, sh);
+  if (threadIdx.x == 0) stat[s].gnorm2_last = g;
 }
 
 __global__ void __launch_bounds__(BS)
-k_store_stress(int T, const int* __restrict__ tperm, const double* __restrict__ psi_int,
-               const int* __restrict__ tv, const double* __restrict__ Bm,
-               const int* __restrict__ tmat, const DevMat* __restrict__ mats,
-               const double* __restrict__ X, double* __restrict__ psi, double* __restrict__ Pout) {
+k_store_stress(int T, const int* __restrict__ tperm, const int* __restrict__ tv,
+               const double* __restrict__ Bm, const int* __restrict__ tmat,
+               const DevMat* __restrict__ mats, const double* __restrict__ X,
+               double* __restrict__ psi, double* __restrict__ Pout) {
   const int t = blockIdx.x * BS + threadIdx.x;
   if (t >= T) return;
   const int4 iv = reinterpret_cast<const int4*>(tv)[t];
@@ -724,16 +799,24 @@ k_store_stress(int T, const int* __restrict__ tperm, const double* __restrict__ 
   psi[o] = ps;
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j) Pout[9 * (size_t)o + 3 * i + j] = P.a[i][j];
-  (void)psi_int;
 }
 
-// Neo-Hookean inverted-input check: flags any NH tet with J <= 0 at X.
+__global__ void __launch_bounds__(BS) k_clear_inverted(int S, SimStat* __restrict__ stat) {
+  const int s = blockIdx.x * BS + threadIdx.x;
+  if (s < S) stat[s].inverted = 0;
+}
+
+// Neo-Hookean inverted-input check: flags each simulation with a Neo-Hookean
+// tet of J <= 0 at X (running simulations only).
 __global__ void __launch_bounds__(BS)
-k_check_inverted(int T, const int* __restrict__ tv, const double* __restrict__ Bm,
+k_check_inverted(const BlockSeg* __restrict__ blk, const int* __restrict__ run, int T,
+                 const int* __restrict__ tv, const double* __restrict__ Bm,
                  const int* __restrict__ tmat, const DevMat* __restrict__ mats,
-                 const double* __restrict__ X, Ctl* ctl) {
-  const int t = blockIdx.x * BS + threadIdx.x;
-  if (t >= T) return;
+                 const double* __restrict__ X, SimStat* __restrict__ stat) {
+  const BlockSeg sg = blk[blockIdx.x];
+  if (!run[sg.sim]) return;
+  const int t = sg.a0 + threadIdx.x;
+  if (t >= sg.a1) return;
   if (mats[tmat ? tmat[t] : 0].type != 0) return;
   const int4 iv = reinterpret_cast<const int4*>(tv)[t];
   const int vid[4] = {iv.x, iv.y, iv.z, iv.w};
@@ -745,7 +828,15 @@ k_check_inverted(int T, const int* __restrict__ tv, const double* __restrict__ B
         s += (X[3 * (size_t)vid[j + 1] + i] - X[3 * (size_t)vid[0] + i]) * Bm[(size_t)(3 * j + k) * T + t];
       F.a[i][k] = s;
     }
-  if (!(det3(F) > 0.0)) ctl->inverted = 1;  // every writer stores the same value
+  if (!(det3(F) > 0.0)) stat[sg.sim].inverted = 1;  // every writer stores the same value
+}
+
+// Control state for timing the kernels in isolation: every simulation in a
+// line search with alpha = 0.5.
+__global__ void __launch_bounds__(BS) k_ctl_timing(int S, Ctl* __restrict__ ctl) {
+  const int s = blockIdx.x * BS + threadIdx.x;
+  if (s >= S) return;
+  ctl[s].phase = PH_LS; ctl[s].alpha = 0.5; ctl[s].cand = 0; ctl[s].k = 0; ctl[s].npairs = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -753,20 +844,22 @@ k_check_inverted(int T, const int* __restrict__ tv, const double* __restrict__ B
 // ---------------------------------------------------------------------------
 inline int nblk(int64_t n) { return (int)std::max<int64_t>(1, (n + BS - 1) / BS); }
 
-void launch_elem(DeviceMesh& D, hipStream_t st, int mode, const double* X, double* part,
+// want: phase the simulations must be in (-1: all); trial: positions x_k + alpha d.
+void launch_elem(DeviceMesh& D, hipStream_t st, int want, int trial, double* part,
                  double* psi_out) {
   const double inv2h2 = 0.5 / (D.h * D.h);
   const int grid = D.elem_blocks;
-#define QN_ELEM(TY)                                                                          \
-  do {                                                                                      \
-    if (D.mixed)                                                                            \
-      hipLaunchKernelGGL((k_elem<TY, float>), dim3(grid), dim3(BS), 0, st, mode, D.T, D.nf,  \
-                         D.tv, D.Bm, D.vol, D.tmat, D.mats, D.mass, X, D.d, D.y,     \
-                         inv2h2, D.ctl, reinterpret_cast<float*>(D.fel), part, psi_out);     \
-    else                                                                                    \
-      hipLaunchKernelGGL((k_elem<TY, double>), dim3(grid), dim3(BS), 0, st, mode, D.T, D.nf, \
-                         D.tv, D.Bm, D.vol, D.tmat, D.mats, D.mass, X, D.d, D.y,     \
-                         inv2h2, D.ctl, D.fel, part, psi_out);                               \
+#define QN_ELEM(TY)                                                                           \
+  do {                                                                                       \
+    if (D.mixed)                                                                             \
+      hipLaunchKernelGGL((k_elem<TY, float>), dim3(grid), dim3(BS), 0, st, want, trial,       \
+                         D.eblk, D.T, D.nf, D.tv, D.Bm, D.vol, D.tmat, D.mats, D.mass, D.X,   \
+                         D.d, D.y, inv2h2, D.ctl, reinterpret_cast<float*>(D.fel), part,      \
+                         psi_out);                                                           \
+    else                                                                                     \
+      hipLaunchKernelGGL((k_elem<TY, double>), dim3(grid), dim3(BS), 0, st, want, trial,      \
+                         D.eblk, D.T, D.nf, D.tv, D.Bm, D.vol, D.tmat, D.mats, D.mass, D.X,   \
+                         D.d, D.y, inv2h2, D.ctl, D.fel, part, psi_out);                      \
   } while (0)
   switch (D.single_type) {
     case 0: QN_ELEM(0); break;
@@ -810,81 +903,80 @@ inline int slots_variant(int m) { return m <= 8 ? m + 1 : kSlots; }
     default: CALL(kSlots); break;    \
   }
 
-void launch_gather(DeviceMesh& D, hipStream_t st, int k, int m, const double* Xp, double* Xc,
-                   const double* Gp, double* Gc, double* part) {
+void launch_gather(DeviceMesh& D, hipStream_t st, int probe, int m, double* part) {
+  const size_t n3 = 3 * (size_t)D.nf;
 #define QN_GATHER(SL)                                                                          \
   do {                                                                                        \
     if (D.mixed)                                                                              \
-      hipLaunchKernelGGL((k_gather<SL, float>), dim3(D.gather_blocks), dim3(BS), 0, st, k,     \
-                         D.nf, m + 1, D.inc_w, D.inc_tab, reinterpret_cast<const float*>(D.fel), \
-                         D.mass, D.y, 1.0 / (D.h * D.h), Xp, Xc, D.d, Gp, Gc, D.Sv, D.Tv,      \
-                         D.ctl, part);                                                         \
+      hipLaunchKernelGGL((k_gather<SL, float>), dim3(D.gather_blocks), dim3(BS), 0, st, probe, \
+                         D.gblk, n3, m + 1, D.inc_w, D.inc_tab,                                \
+                         reinterpret_cast<const float*>(D.fel), D.mass, D.y,                   \
+                         1.0 / (D.h * D.h), D.X, D.d, D.G, D.Sv, D.Tv, D.ctl, part);           \
     else                                                                                      \
-      hipLaunchKernelGGL((k_gather<SL, double>), dim3(D.gather_blocks), dim3(BS), 0, st, k,    \
-                         D.nf, m + 1, D.inc_w, D.inc_tab, D.fel, D.mass, D.y,                  \
-                         1.0 / (D.h * D.h), Xp, Xc, D.d, Gp, Gc, D.Sv, D.Tv, D.ctl, part);     \
+      hipLaunchKernelGGL((k_gather<SL, double>), dim3(D.gather_blocks), dim3(BS), 0, st,       \
+                         probe, D.gblk, n3, m + 1, D.inc_w, D.inc_tab, D.fel, D.mass, D.y,     \
+                         1.0 / (D.h * D.h), D.X, D.d, D.G, D.Sv, D.Tv, D.ctl, part);           \
   } while (0)
   QN_SLOTS_DISPATCH(slots_variant(m), QN_GATHER)
 #undef QN_GATHER
 }
 
-enum Stage { ST_GATHER = 0, ST_DIRECTION = 1, ST_LINESEARCH = 2 };
-
-void launch_iteration(DeviceMesh& D, const StepParams& P, hipStream_t st, int k, int stage,
-                      int budget) {
+// Gather of the current iterate and the curvature-pair bookkeeping
+// (simulations in PH_GATHER).
+void launch_gather_stage(DeviceMesh& D, const StepParams& P, hipStream_t st) {
   Parts pp = parts_of(D);
-  const int gb = D.gather_blocks, vb = D.vec3_blocks;
   const int m = P.history;
-  double* Xc = D.X[k & 1];
-  const double* Xp = D.X[(k + 1) & 1];
-  double* Gc = D.G[k & 1];
-  const double* Gp = D.G[(k + 1) & 1];
-  const int slv = slots_variant(m), slots = m + 1;
-  if (stage <= ST_GATHER) {
-    launch_gather(D, st, k, m, Xp, Xc, Gp, Gc, pp.gather);
-#define QN_PAIR(SL) \
-  hipLaunchKernelGGL(k_pair_decide<SL>, dim3(1), dim3(BS), 0, st, k, m, pp.gather, gb, D.ctl)
-    QN_SLOTS_DISPATCH(slv, QN_PAIR)
+  launch_gather(D, st, 0, m, pp.gather);
+#define QN_PAIR(SL)                                                                            \
+  hipLaunchKernelGGL(k_pair_decide<SL>, dim3(D.S), dim3(BS), 0, st, m, D.seg, pp.gather,        \
+                     D.gather_blocks, D.ctl, D.stat, D.dir_count)
+  QN_SLOTS_DISPATCH(slots_variant(m), QN_PAIR)
 #undef QN_PAIR
-  }
-  if (stage <= ST_DIRECTION) {
-#define QN_QFORM(SL)                                                                        \
-  hipLaunchKernelGGL(k_qform<SL>, dim3(vb), dim3(BS), 0, st, D.nf, slots, Gc, D.Tv, D.q, D.ctl)
-    QN_SLOTS_DISPATCH(slv, QN_QFORM)
+}
+
+// Two-loop recursion with the prefactored solve (simulations in PH_DIR);
+// cyc tags the d update of this pass.
+void launch_direction(DeviceMesh& D, const StepParams& P, hipStream_t st, int cyc) {
+  Parts pp = parts_of(D);
+  const int m = P.history, slots = m + 1, slv = slots_variant(m);
+  const size_t n3 = 3 * (size_t)D.nf;
+#define QN_QFORM(SL)                                                                           \
+  hipLaunchKernelGGL(k_qform<SL>, dim3(D.vec3_blocks), dim3(BS), 0, st, D.vblk, n3, slots, D.G, \
+                     D.Tv, D.q, D.ctl)
+  QN_SLOTS_DISPATCH(slv, QN_QFORM)
 #undef QN_QFORM
-    launch_solve(D, st, D.q, D.d, D.ctl);
-#define QN_RDOTS(SL)                                                                      \
-  hipLaunchKernelGGL(k_rdots<SL>, dim3(D.rdots_blocks), dim3(kWideBS), 0, st, D.nf, slots, D.d, \
-                     Gc, D.Tv, pp.rdots, D.ctl)
-    QN_SLOTS_DISPATCH(slv, QN_RDOTS)
+  launch_solve(D, st, D.q, D.r, D.dir_count);
+#define QN_RDOTS(SL)                                                                           \
+  hipLaunchKernelGGL(k_rdots<SL>, dim3(D.rdots_blocks), dim3(kWideBS), 0, st, D.rblk, n3,       \
+                     slots, D.r, D.G, D.Tv, pp.rdots, D.ctl)
+  QN_SLOTS_DISPATCH(slv, QN_RDOTS)
 #undef QN_RDOTS
-#define QN_COEF(SL) \
-  hipLaunchKernelGGL(k_coef_decide<SL>, dim3(1), dim3(BS), 0, st, m, pp.rdots, D.rdots_blocks, \
-                     D.ctl)
-    QN_SLOTS_DISPATCH(slv, QN_COEF)
+#define QN_COEF(SL)                                                                            \
+  hipLaunchKernelGGL(k_coef_decide<SL>, dim3(D.S), dim3(BS), 0, st, m, cyc, D.seg, pp.rdots,    \
+                     D.rdots_blocks, D.ctl, D.stat, D.dir_count)
+  QN_SLOTS_DISPATCH(slv, QN_COEF)
 #undef QN_COEF
-#define QN_DFORM(SL) \
-  hipLaunchKernelGGL(k_dform<SL>, dim3(vb), dim3(BS), 0, st, D.nf, slots, D.Sv, D.d, D.ctl)
-    QN_SLOTS_DISPATCH(slv, QN_DFORM)
+#define QN_DFORM(SL)                                                                           \
+  hipLaunchKernelGGL(k_dform<SL>, dim3(D.vec3_blocks), dim3(BS), 0, st, D.vblk, n3, slots, cyc, \
+                     D.Sv, D.r, D.d, D.ctl)
+  QN_SLOTS_DISPATCH(slv, QN_DFORM)
 #undef QN_DFORM
-  }
-  for (int b = 0; b < budget; ++b) {
-    launch_elem(D, st, 1, Xc, pp.elem, nullptr);
-    hipLaunchKernelGGL(k_ls_decide, dim3(1), dim3(BS), 0, st, k, (b == budget - 1) ? 1 : 0,
-                       P.max_halvings, P.gamma, P.backtrack, pp.elem, D.elem_blocks, D.ctl);
+}
+
+// `trials` line-search trials (simulations in PH_LS).
+void launch_trials(DeviceMesh& D, const StepParams& P, hipStream_t st, int trials) {
+  Parts pp = parts_of(D);
+  for (int b = 0; b < trials; ++b) {
+    launch_elem(D, st, PH_LS, 1, pp.elem, nullptr);
+    hipLaunchKernelGGL(k_ls_decide, dim3(D.S), dim3(BS), 0, st, P.iterations, P.max_halvings,
+                       P.gamma, P.backtrack, D.seg, pp.elem, D.ctl, D.stat);
   }
 }
 
-__global__ void k_host_resume(Ctl* ctl, int clear_pairs) {
-  ctl->need_host = 0;
-  ctl->host_reason = 0;
-  if (clear_pairs) { ctl->npairs = 0; ctl->fallbacks += 1; }
-}
-
-__global__ void k_fallback_x(Ctl* ctl) {
-  ctl->need_host = 0;
-  ctl->host_reason = 0;
-  ctl->fallbacks += 1;
+void launch_finalize(DeviceMesh& D, const StepParams& P, hipStream_t st, double* xo,
+                     double* vo) {
+  hipLaunchKernelGGL(k_finalize, dim3(nblk(D.n)), dim3(BS), 0, st, D.n, D.nf, D.vsim, D.run,
+                     D.vperm, D.x0, D.X, D.d, 1.0 / P.h, D.ctl, xo, vo);
 }
 
 }  // namespace
@@ -900,16 +992,21 @@ int dev_sync(DeviceMesh& D, void* stream, std::string& err) {
 void dev_free(DeviceMesh& D) {
   void* ptrs[] = {D.tv, D.Bm, D.vol, D.tmat, D.mats, D.mass, D.inc_tab, D.vperm,
                   D.sn, D.items, D.Bf, D.Bb, D.rows, D.rel, D.vp, D.x0,
-                  D.v0, D.y, D.X[0], D.X[1], D.G[0], D.G[1], D.d, D.q, D.z, D.Sv, D.Tv, D.fel,
-                  D.part, D.psi, D.ctl, D.tperm, D.top_t,
-                  D.sub_fw, D.sub_bw, D.sub_fw_ptr, D.sub_bw_ptr};
+                  D.v0, D.y, D.X, D.G, D.d, D.r, D.q, D.z, D.Sv, D.Tv, D.fel,
+                  D.part, D.psi, D.ctl, D.stat, D.tperm, D.top_t,
+                  D.sub_fw, D.sub_bw, D.sub_fw_ptr, D.sub_bw_ptr,
+                  D.seg, D.vsim, D.run, D.eblk, D.gblk, D.vblk, D.rblk, D.dir_count};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
-  if (D.ctl_host) (void)hipHostFree(D.ctl_host);
+  if (D.stat_host) (void)hipHostFree(D.stat_host);
+  if (D.run_host) (void)hipHostFree(D.run_host);
   if (D.stream) (void)hipStreamDestroy((hipStream_t)D.stream);
   D = DeviceMesh();
 }
 
+// Allocates the solver vectors and control state; the block tables, seg and
+// vsim are uploaded by the caller beforehand (elem/gather/vec3/rdots block
+// counts set). Every simulation starts with its run flag set.
 int dev_alloc(DeviceMesh& D, std::string& err) {
   HIP_OK(hipSetDevice(D.device));
   const size_t n3 = 3 * (size_t)D.n, f3 = 3 * (size_t)std::max(D.nf, 1);
@@ -920,11 +1017,10 @@ int dev_alloc(DeviceMesh& D, std::string& err) {
   HIP_OK(A((void**)&D.x0, n3 * 8));
   HIP_OK(A((void**)&D.v0, n3 * 8));
   HIP_OK(A((void**)&D.y, n3 * 8));
-  HIP_OK(A((void**)&D.X[0], n3 * 8));
-  HIP_OK(A((void**)&D.X[1], n3 * 8));
-  HIP_OK(A((void**)&D.G[0], f3 * 8));
-  HIP_OK(A((void**)&D.G[1], f3 * 8));
+  HIP_OK(A((void**)&D.X, n3 * 8));
+  HIP_OK(A((void**)&D.G, f3 * 8));
   HIP_OK(A((void**)&D.d, f3 * 8));
+  HIP_OK(A((void**)&D.r, f3 * 8));
   HIP_OK(A((void**)&D.q, f3 * 8));
   HIP_OK(A((void**)&D.z, f3 * 8));
   HIP_OK(A((void**)&D.top_t, 3 * (size_t)std::max(D.top_n, 1) * 8));
@@ -932,20 +1028,34 @@ int dev_alloc(DeviceMesh& D, std::string& err) {
   HIP_OK(A((void**)&D.Tv, f3 * 8 * D.slots));
   HIP_OK(A((void**)&D.fel, (size_t)D.T * 12 * 8));
   HIP_OK(A((void**)&D.psi, (size_t)D.T * 8));
-  D.gather_blocks = nblk(4 * (int64_t)D.nf);
-  D.rdots_blocks = (int)std::max<int64_t>(1, (3 * (int64_t)D.nf + kWideBS - 1) / kWideBS);
-  D.vec3_blocks = nblk(3 * (int64_t)D.nf);
-  D.elem_blocks = nblk(std::max(D.T, D.nf));
   HIP_OK(A((void**)&D.part,
            ((size_t)kGatherDots * D.gather_blocks + (size_t)(kSlots + 1) * D.rdots_blocks +
             D.elem_blocks) * 8));
-  HIP_OK(A((void**)&D.ctl, sizeof(Ctl)));
-  HIP_OK(hipHostMalloc((void**)&D.ctl_host, sizeof(Ctl), hipHostMallocDefault));
+  HIP_OK(A((void**)&D.ctl, sizeof(Ctl) * D.S));
+  HIP_OK(A((void**)&D.stat, sizeof(SimStat) * D.S));
+  HIP_OK(A((void**)&D.run, sizeof(int) * D.S));
+  HIP_OK(A((void**)&D.dir_count, sizeof(int)));
+  HIP_OK(hipHostMalloc((void**)&D.stat_host, sizeof(SimStat) * D.S, hipHostMallocDefault));
+  HIP_OK(hipHostMalloc((void**)&D.run_host, sizeof(int) * D.S, hipHostMallocDefault));
   hipStream_t st;
   HIP_OK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
   D.stream = st;
-  HIP_OK(hipMemset(D.X[1], 0, n3 * 8));
-  HIP_OK(hipMemset(D.ctl, 0, sizeof(Ctl)));
+  HIP_OK(hipMemset(D.X, 0, n3 * 8));
+  HIP_OK(hipMemset(D.d, 0, f3 * 8));
+  HIP_OK(hipMemset(D.ctl, 0, sizeof(Ctl) * D.S));
+  HIP_OK(hipMemset(D.stat, 0, sizeof(SimStat) * D.S));
+  HIP_OK(hipMemset(D.dir_count, 0, sizeof(int)));
+  for (int s = 0; s < D.S; ++s) D.run_host[s] = 1;
+  HIP_OK(hipMemcpy(D.run, D.run_host, sizeof(int) * D.S, hipMemcpyHostToDevice));
+  return 0;
+}
+
+int dev_set_run(DeviceMesh& D, const int* run_flags, void* stream, std::string& err) {
+  hipStream_t st = (hipStream_t)(stream ? stream : D.stream);
+  // the previous copy out of run_host must be done before it is rewritten
+  HIP_OK(hipStreamSynchronize(st));
+  for (int s = 0; s < D.S; ++s) D.run_host[s] = run_flags[s] ? 1 : 0;
+  HIP_OK(hipMemcpyAsync(D.run, D.run_host, sizeof(int) * D.S, hipMemcpyHostToDevice, st));
   return 0;
 }
 
@@ -953,96 +1063,116 @@ int dev_alloc(DeviceMesh& D, std::string& err) {
 // One time step
 // ---------------------------------------------------------------------------
 int dev_step(DeviceMesh& D, const StepParams& P, const double* x, const double* v,
-             const double* fext, double* xo, double* vo, void* stream, bool want_ctl,
-             Ctl* ctl_out, bool final_gradient, double* gnorm_last, std::string& err) {
+             const double* fext, double* xo, double* vo, void* stream, bool final_gradient,
+             std::string& err) {
   hipStream_t st = (hipStream_t)stream;
   Parts pp = parts_of(D);
   const int K = P.iterations;
-  hipLaunchKernelGGL(k_step_init, dim3(nblk(D.n)), dim3(BS), 0, st, D.n, D.nf, D.vperm, D.mass,
-                     x, v, fext, P.h, P.grav[0], P.grav[1], P.grav[2], D.x0, D.y, D.X[0], D.X[1],
-                     D.ctl, D.slots);
-  launch_elem(D, st, 0, D.X[0], pp.elem, nullptr);
-  hipLaunchKernelGGL(k_init_decide, dim3(1), dim3(BS), 0, st, pp.elem, D.elem_blocks, D.ctl);
-  for (int k = 0; k < K; ++k) launch_iteration(D, P, st, k, ST_GATHER, P.budget);
-  hipLaunchKernelGGL(k_finalize, dim3(nblk(D.n)), dim3(BS), 0, st, D.n, D.nf, K, D.vperm, D.x0,
-                     D.X[0], D.X[1], D.d, 1.0 / P.h, D.ctl, xo, vo);
+  hipLaunchKernelGGL(k_step_init, dim3(nblk(D.n)), dim3(BS), 0, st, D.n, D.nf, D.vsim, D.run,
+                     D.seg, D.vperm, D.mass, x, v, fext, P.h, P.grav[0], P.grav[1], P.grav[2],
+                     D.x0, D.y, D.X, D.ctl, D.stat, D.slots, D.dir_count);
+  launch_elem(D, st, PH_INIT, 0, pp.elem, nullptr);
+  hipLaunchKernelGGL(k_init_decide, dim3(D.S), dim3(BS), 0, st, (int)PH_INIT, D.seg, pp.elem,
+                     D.ctl, D.stat);
+  // iteration k: line search of k, then (k + 1 < K) the gather and direction
+  // of k + 1; a simulation whose line search needs more than P.budget trials
+  // falls one cycle behind
+  int cyc = 0;
+  launch_gather_stage(D, P, st);
+  launch_direction(D, P, st, cyc);
+  for (int k = 0; k < K; ++k) {
+    launch_trials(D, P, st, P.budget);
+    if (k + 1 < K) {
+      launch_gather_stage(D, P, st);
+      launch_direction(D, P, st, ++cyc);
+    }
+  }
+  launch_finalize(D, P, st, xo, vo);
   HIP_OK(hipGetLastError());
-  HIP_OK(hipMemcpyAsync(D.ctl_host, D.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+  HIP_OK(hipMemcpyAsync(D.stat_host, D.stat, sizeof(SimStat) * D.S, hipMemcpyDeviceToHost, st));
   HIP_OK(hipStreamSynchronize(st));
-  // Rare events: continue the step from where the device stopped.
-  int guard = 0;
-  while (D.ctl_host->need_host) {
-    if (++guard > 4 * K + 8) {
-      err = "step did not settle after host continuation";
+  // Continuation: more cycles for the simulations that are not done.
+  const int extra_trials = std::max(P.budget, 4);
+  for (int round = 0;; ++round) {
+    int pending = 0, retry = 0, kmin = K;
+    for (int s = 0; s < D.S; ++s) {
+      if (!D.run_host[s]) continue;
+      const SimStat& t = D.stat_host[s];
+      if (t.phase == PH_DONE || t.phase == PH_FAILED) continue;
+      ++pending;
+      if (t.phase == PH_RETRY) retry = 1;
+      kmin = std::min(kmin, std::max(0, t.iters - 1));
+    }
+    if (!pending) break;
+    if (round > 4 * (K + P.max_halvings) + 8) {
+      err = "step did not settle after " + std::to_string(round) + " continuation rounds";
       return QNSIM_E_DEVICE;
     }
-    const int reason = D.ctl_host->host_reason;
-    int k = D.ctl_host->iters - 1;
-    if (reason == 3) {
-      // infeasible y: x_1 := x, evaluate again
-      hipLaunchKernelGGL(k_fallback_x, dim3(1), dim3(1), 0, st, D.ctl);
-      hipLaunchKernelGGL(k_copy_free, dim3(nblk(3 * (int64_t)D.nf)), dim3(BS), 0, st, D.nf, D.x0,
-                         D.X[0]);
-      launch_elem(D, st, 0, D.X[0], pp.elem, nullptr);
-      hipLaunchKernelGGL(k_init_decide, dim3(1), dim3(BS), 0, st, pp.elem, D.elem_blocks, D.ctl);
-      k = -1;
-    } else if (reason == 2) {
-      hipLaunchKernelGGL(k_host_resume, dim3(1), dim3(1), 0, st, D.ctl, 1);
-      launch_iteration(D, P, st, k, ST_DIRECTION, P.max_halvings + 1);
-    } else {
-      hipLaunchKernelGGL(k_host_resume, dim3(1), dim3(1), 0, st, D.ctl, 0);
-      launch_iteration(D, P, st, k, ST_LINESEARCH, P.max_halvings + 1);
+    if (retry) {
+      hipLaunchKernelGGL(k_copy_retry, dim3(nblk(3 * (int64_t)D.nf)), dim3(BS), 0, st, D.nf,
+                         D.vsim, D.ctl, D.x0, D.X);
+      launch_elem(D, st, PH_RETRY, 0, pp.elem, nullptr);
+      hipLaunchKernelGGL(k_init_decide, dim3(D.S), dim3(BS), 0, st, (int)PH_RETRY, D.seg,
+                         pp.elem, D.ctl, D.stat);
+      kmin = 0;
     }
-    for (int kk = k + 1; kk < K; ++kk) launch_iteration(D, P, st, kk, ST_GATHER, P.budget);
-    hipLaunchKernelGGL(k_finalize, dim3(nblk(D.n)), dim3(BS), 0, st, D.n, D.nf, K, D.vperm, D.x0,
-                       D.X[0], D.X[1], D.d, 1.0 / P.h, D.ctl, xo, vo);
+    const int ncyc = std::max(1, K - kmin);
+    for (int c = 0; c < ncyc; ++c) {
+      launch_gather_stage(D, P, st);
+      launch_direction(D, P, st, ++cyc);
+      launch_trials(D, P, st, extra_trials);
+    }
+    launch_finalize(D, P, st, xo, vo);
     HIP_OK(hipGetLastError());
-    HIP_OK(hipMemcpyAsync(D.ctl_host, D.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+    HIP_OK(hipMemcpyAsync(D.stat_host, D.stat, sizeof(SimStat) * D.S, hipMemcpyDeviceToHost, st));
     HIP_OK(hipStreamSynchronize(st));
   }
-  if (final_gradient && gnorm_last) {
+  for (int s = 0; s < D.S; ++s)
+    if (D.run_host[s] && D.stat_host[s].phase == PH_FAILED) {
+      err = "simulation " + std::to_string(s) + ": objective not finite at the input state";
+      return QNSIM_E_NONFINITE;
+    }
+  if (final_gradient) {
     // gradient at the returned state (diagnostic): element pass + gather at x'
-    hipLaunchKernelGGL(k_load_perm, dim3(nblk(D.n)), dim3(BS), 0, st, D.n, D.vperm, xo, D.X[0]);
-    hipLaunchKernelGGL(k_ctl_probe, dim3(1), dim3(1), 0, st, D.ctl);
-    launch_elem(D, st, 2, D.X[0], pp.elem, nullptr);
-    launch_gather(D, st, 0, 0, D.X[1], D.X[0], D.G[1], D.G[0], pp.gather);
-    hipLaunchKernelGGL(k_sum_to_ctl, dim3(1), dim3(BS), 0, st, pp.gather + 3 * D.gather_blocks,
-                       D.gather_blocks, D.ctl);
-    Ctl tmp;
-    HIP_OK(hipMemcpyAsync(&tmp, D.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+    hipLaunchKernelGGL(k_load_perm, dim3(nblk(D.n)), dim3(BS), 0, st, D.n, D.vperm, xo, D.X);
+    launch_elem(D, st, -1, 0, pp.elem, nullptr);
+    launch_gather(D, st, 1, 0, pp.gather);
+    hipLaunchKernelGGL(k_gnorm_last, dim3(D.S), dim3(BS), 0, st, D.seg, D.run, pp.gather,
+                       D.gather_blocks, D.stat);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipMemcpyAsync(D.stat_host, D.stat, sizeof(SimStat) * D.S, hipMemcpyDeviceToHost, st));
     HIP_OK(hipStreamSynchronize(st));
-    *gnorm_last = std::sqrt(tmp.g_k);
   }
-  if (want_ctl && ctl_out) *ctl_out = *D.ctl_host;
   return 0;
 }
 
+// Probes (single simulation).
 int dev_eval(DeviceMesh& D, const double* x, const double* y, double* g_out, double* grad,
              void* stream, std::string& err) {
   hipStream_t st = (hipStream_t)stream;
   Parts pp = parts_of(D);
-  hipLaunchKernelGGL(k_load_perm, dim3(nblk(D.n)), dim3(BS), 0, st, D.n, D.vperm, x, D.X[0]);
+  hipLaunchKernelGGL(k_load_perm, dim3(nblk(D.n)), dim3(BS), 0, st, D.n, D.vperm, x, D.X);
   hipLaunchKernelGGL(k_load_perm, dim3(nblk(D.n)), dim3(BS), 0, st, D.n, D.vperm, y, D.y);
-  hipLaunchKernelGGL(k_ctl_probe, dim3(1), dim3(1), 0, st, D.ctl);
-  launch_elem(D, st, 2, D.X[0], pp.elem, nullptr);
-  hipLaunchKernelGGL(k_sum_to_ctl, dim3(1), dim3(BS), 0, st, pp.elem, D.elem_blocks, D.ctl);
-  launch_gather(D, st, 0, 0, D.X[1], D.X[0], D.G[1], D.G[0], pp.gather);
-  hipLaunchKernelGGL(k_store_perm, dim3(nblk(D.n)), dim3(BS), 0, st, D.n, D.nf, D.vperm, D.G[0],
+  launch_elem(D, st, -1, 0, pp.elem, nullptr);
+  hipLaunchKernelGGL(k_sum_to, dim3(1), dim3(BS), 0, st, pp.elem, D.elem_blocks,
+                     &D.stat[0].g_last);
+  launch_gather(D, st, 1, 0, pp.gather);
+  hipLaunchKernelGGL(k_store_perm, dim3(nblk(D.n)), dim3(BS), 0, st, D.n, D.nf, D.vperm, D.G,
                      grad);
   HIP_OK(hipGetLastError());
-  Ctl tmp;
-  HIP_OK(hipMemcpyAsync(&tmp, D.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+  SimStat tmp;
+  HIP_OK(hipMemcpyAsync(&tmp, D.stat, sizeof(SimStat), hipMemcpyDeviceToHost, st));
   HIP_OK(hipStreamSynchronize(st));
-  *g_out = tmp.g_k;
+  *g_out = tmp.g_last;
   return 0;
 }
 
 int dev_element_stress(DeviceMesh& D, const double* x, double* psi, double* P, void* stream,
                        std::string& err) {
   hipStream_t st = (hipStream_t)stream;
-  hipLaunchKernelGGL(k_load_perm, dim3(nblk(D.n)), dim3(BS), 0, st, D.n, D.vperm, x, D.X[0]);
-  hipLaunchKernelGGL(k_store_stress, dim3(nblk(D.T)), dim3(BS), 0, st, D.T, D.tperm, D.psi, D.tv,
-                     D.Bm, D.tmat, D.mats, D.X[0], psi, P);
+  hipLaunchKernelGGL(k_load_perm, dim3(nblk(D.n)), dim3(BS), 0, st, D.n, D.vperm, x, D.X);
+  hipLaunchKernelGGL(k_store_stress, dim3(nblk(D.T)), dim3(BS), 0, st, D.T, D.tperm, D.tv, D.Bm,
+                     D.tmat, D.mats, D.X, psi, P);
   HIP_OK(hipGetLastError());
   HIP_OK(hipStreamSynchronize(st));
   return 0;
@@ -1051,17 +1181,11 @@ int dev_element_stress(DeviceMesh& D, const double* x, double* psi, double* P, v
 int dev_solve(DeviceMesh& D, const double* q, double* r, void* stream, std::string& err) {
   hipStream_t st = (hipStream_t)stream;
   hipLaunchKernelGGL(k_load_perm, dim3(nblk(D.nf)), dim3(BS), 0, st, D.nf, D.vperm, q, D.q);
-  launch_solve(D, st, D.q, D.d, nullptr);
-  hipLaunchKernelGGL(k_store_perm, dim3(nblk(D.n)), dim3(BS), 0, st, D.n, D.nf, D.vperm, D.d, r);
+  launch_solve(D, st, D.q, D.r, nullptr);
+  hipLaunchKernelGGL(k_store_perm, dim3(nblk(D.n)), dim3(BS), 0, st, D.n, D.nf, D.vperm, D.r, r);
   HIP_OK(hipGetLastError());
   return 0;
 }
-
-namespace {
-__global__ void k_ctl_timing(Ctl* ctl) {
-  ctl->active = 1; ctl->need_host = 0; ctl->ls_done = 0; ctl->alpha = 0.5; ctl->cand = 0;
-}
-}  // namespace
 
 int dev_time_kernel(DeviceMesh& D, int kernel, int reps, double* avg_ms, std::string& err) {
   hipStream_t st = (hipStream_t)D.stream;
@@ -1069,18 +1193,18 @@ int dev_time_kernel(DeviceMesh& D, int kernel, int reps, double* avg_ms, std::st
   hipEvent_t e0, e1;
   HIP_OK(hipEventCreate(&e0));
   HIP_OK(hipEventCreate(&e1));
-  hipLaunchKernelGGL(k_ctl_timing, dim3(1), dim3(1), 0, st, D.ctl);
+  hipLaunchKernelGGL(k_ctl_timing, dim3(nblk(D.S)), dim3(BS), 0, st, D.S, D.ctl);
   // one untimed launch to warm caches and code objects
   for (int pass = 0; pass < 2; ++pass) {
     const int n = pass == 0 ? 1 : reps;
     if (pass == 1) HIP_OK(hipEventRecord(e0, st));
     for (int r = 0; r < n; ++r) {
       if (kernel == 0) {
-        launch_elem(D, st, 1, D.X[0], pp.elem, nullptr);
+        launch_elem(D, st, PH_LS, 1, pp.elem, nullptr);
       } else if (kernel == 1) {
-        launch_gather(D, st, 0, 0, D.X[1], D.X[0], D.G[1], D.G[0], pp.gather);
+        launch_gather(D, st, 1, 0, pp.gather);
       } else {
-        launch_solve(D, st, D.q, D.G[1], nullptr);
+        launch_solve(D, st, D.q, D.r, nullptr);
       }
     }
   }
@@ -1094,18 +1218,19 @@ int dev_time_kernel(DeviceMesh& D, int kernel, int reps, double* avg_ms, std::st
   return 0;
 }
 
+// Inverted-input check of the running simulations; inverted[s] receives the
+// flag of simulation s.
 int dev_check_inverted(DeviceMesh& D, const double* x, void* stream, int* inverted,
                        std::string& err) {
   hipStream_t st = (hipStream_t)stream;
-  hipLaunchKernelGGL(k_load_perm, dim3(nblk(D.n)), dim3(BS), 0, st, D.n, D.vperm, x, D.X[1]);
-  hipLaunchKernelGGL(k_ctl_probe, dim3(1), dim3(1), 0, st, D.ctl);
-  hipLaunchKernelGGL(k_check_inverted, dim3(nblk(D.T)), dim3(BS), 0, st, D.T, D.tv, D.Bm, D.tmat,
-                     D.mats, D.X[1], D.ctl);
+  hipLaunchKernelGGL(k_load_perm, dim3(nblk(D.n)), dim3(BS), 0, st, D.n, D.vperm, x, D.y);
+  hipLaunchKernelGGL(k_clear_inverted, dim3(nblk(D.S)), dim3(BS), 0, st, D.S, D.stat);
+  hipLaunchKernelGGL(k_check_inverted, dim3(D.elem_blocks), dim3(BS), 0, st, D.eblk, D.run, D.T,
+                     D.tv, D.Bm, D.tmat, D.mats, D.y, D.stat);
   HIP_OK(hipGetLastError());
-  Ctl tmp;
-  HIP_OK(hipMemcpyAsync(&tmp, D.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+  HIP_OK(hipMemcpyAsync(D.stat_host, D.stat, sizeof(SimStat) * D.S, hipMemcpyDeviceToHost, st));
   HIP_OK(hipStreamSynchronize(st));
-  *inverted = tmp.inverted;
+  for (int s = 0; s < D.S; ++s) inverted[s] = D.stat_host[s].inverted;
   return 0;
 }
 

@@ -217,11 +217,11 @@ __device__ __forceinline__ void fwd_item(const ItemDesc& d, const double* __rest
 __global__ void __launch_bounds__(TS, 4)
 k_solve_fwd(const ItemDesc* __restrict__ items, const double* __restrict__ Bf,
             const int* __restrict__ rel, const double* __restrict__ q, double* __restrict__ z,
-            double* __restrict__ vp, const Ctl* __restrict__ ctl) {
+            double* __restrict__ vp, const int* __restrict__ gate) {
   static_assert(kMaxItemRows == TS, "one staged row per thread");
   __shared__ double s0[TCHUNK], s1[TCHUNK], s2[TCHUNK], sp[3 * kMaxItemRows];
   __shared__ int srel[kMaxItemRows];
-  if (ctl && !(ctl->active && !ctl->need_host)) return;
+  if (gate && *gate <= 0) return;
   const ItemDesc d = items[blockIdx.x];
   fwd_item(d, Bf, rel, q, z, vp, s0, s1, s2, sp, srel);
 }
@@ -331,9 +331,9 @@ __device__ __forceinline__ void bwd_item(const ItemDesc& d, const double* __rest
 __global__ void __launch_bounds__(TS)
 k_solve_bwd(const ItemDesc* __restrict__ items, const double* __restrict__ Bb,
             const int* __restrict__ rows, const double* __restrict__ z, double* __restrict__ w,
-            const Ctl* __restrict__ ctl) {
+            const int* __restrict__ gate) {
   __shared__ double s0[TCHUNK], s1[TCHUNK], s2[TCHUNK];
-  if (ctl && !(ctl->active && !ctl->need_host)) return;
+  if (gate && *gate <= 0) return;
   const ItemDesc d = items[blockIdx.x];
   bwd_item(d, Bb, rows, z, w, s0, s1, s2);
 }
@@ -590,9 +590,9 @@ __global__ void __launch_bounds__(kSubThreads)
 k_solve_fwd_sub(const ItemDesc* __restrict__ items, const int* __restrict__ ptr, int nl,
                 const double* __restrict__ Bf, const int* __restrict__ rel,
                 const double* __restrict__ q, double* __restrict__ z, double* __restrict__ vp,
-                const Ctl* __restrict__ ctl) {
+                const int* __restrict__ gate) {
   __shared__ double stage[kSubWaves][3 * kSubCap];
-  if (ctl && !(ctl->active && !ctl->need_host)) return;
+  if (gate && *gate <= 0) return;
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int* p = ptr + (size_t)blockIdx.x * (nl + 1);
@@ -610,9 +610,9 @@ __global__ void __launch_bounds__(kSubThreads)
 k_solve_bwd_sub(const ItemDesc* __restrict__ items, const int* __restrict__ ptr, int nl,
                 const double* __restrict__ Bb, const int* __restrict__ rows,
                 const double* __restrict__ z, double* __restrict__ w,
-                const Ctl* __restrict__ ctl) {
+                const int* __restrict__ gate) {
   __shared__ double stage[kSubWaves][3 * kSubCap];
-  if (ctl && !(ctl->active && !ctl->need_host)) return;
+  if (gate && *gate <= 0) return;
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int* p = ptr + (size_t)blockIdx.x * (nl + 1);
@@ -629,8 +629,8 @@ k_solve_bwd_sub(const ItemDesc* __restrict__ items, const int* __restrict__ ptr,
 // summed in a fixed order.
 __global__ void __launch_bounds__(TS)
 k_top_assemble(const double* __restrict__ q, const double* __restrict__ slots, int nch,
-               int n3, double* __restrict__ t, const Ctl* __restrict__ ctl) {
-  if (ctl && !(ctl->active && !ctl->need_host)) return;
+               int n3, double* __restrict__ t, const int* __restrict__ gate) {
+  if (gate && *gate <= 0) return;
   const int i = blockIdx.x * TS + threadIdx.x;
   if (i >= n3) return;
   double v = q[i];
@@ -650,10 +650,10 @@ constexpr int kTopU = (kMaxDenseTop / kTopParts + 63) / 64;  // entries per lane
 
 __global__ void __launch_bounds__(kTopThreads)
 k_top_gemv(const double* __restrict__ Sinv, const double* __restrict__ t, int n, int nwg,
-           double* __restrict__ w, const Ctl* __restrict__ ctl) {
+           double* __restrict__ w, const int* __restrict__ gate) {
   __shared__ double ts[3][kMaxDenseTop];
   __shared__ double red[kTopRows][kTopParts][3];
-  if (ctl && !(ctl->active && !ctl->need_host)) return;
+  if (gate && *gate <= 0) return;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int rb = (int)(((long long)blockIdx.x * n) / nwg);
   const int re = (int)(((long long)(blockIdx.x + 1) * n) / nwg);
@@ -712,34 +712,34 @@ k_top_gemv(const double* __restrict__ Sinv, const double* __restrict__ t, int n,
   }
 }
 
-void launch_solve(DeviceMesh& D, hipStream_t st, const double* q, double* r, const Ctl* ctl) {
+void launch_solve(DeviceMesh& D, hipStream_t st, const double* q, double* r, const int* gate) {
   const int L = (int)D.levels.size();
   if (D.sub_tasks > 0)
     hipLaunchKernelGGL(k_solve_fwd_sub, dim3(D.sub_tasks), dim3(kSubThreads), 0, st, D.sub_fw,
-                       D.sub_fw_ptr, D.sub_levels, D.Bf, D.rel, q, D.z, D.vp, ctl);
+                       D.sub_fw_ptr, D.sub_levels, D.Bf, D.rel, q, D.z, D.vp, gate);
   for (int l = D.sub_levels; l < L; ++l) {
     const int n = D.levels[l].fw_end - D.levels[l].fw_begin;
     if (n > 0)
       hipLaunchKernelGGL(k_solve_fwd, dim3(n), dim3(TS), 0, st, D.items + D.levels[l].fw_begin,
-                         D.Bf, D.rel, q, D.z, D.vp, ctl);
+                         D.Bf, D.rel, q, D.z, D.vp, gate);
   }
   if (D.top_n > 0) {
     const int n = D.top_n, n3 = 3 * n;
     hipLaunchKernelGGL(k_top_assemble, dim3((n3 + TS - 1) / TS), dim3(TS), 0, st,
-                       q + 3 * (size_t)D.top_first, D.vp + D.top_vp, D.top_nch, n3, D.top_t, ctl);
+                       q + 3 * (size_t)D.top_first, D.vp + D.top_vp, D.top_nch, n3, D.top_t, gate);
     const int nwg = top_workgroups(n);
     hipLaunchKernelGGL(k_top_gemv, dim3(nwg), dim3(kTopThreads), 0, st, D.Bf + D.top_off,
-                       D.top_t, n, nwg, r + 3 * (size_t)D.top_first, ctl);
+                       D.top_t, n, nwg, r + 3 * (size_t)D.top_first, gate);
   }
   for (int l = L - 1; l >= D.sub_levels; --l) {
     const int n = D.levels[l].bw_end - D.levels[l].bw_begin;
     if (n > 0)
       hipLaunchKernelGGL(k_solve_bwd, dim3(n), dim3(TS), 0, st, D.items + D.levels[l].bw_begin,
-                         D.Bb, D.rows, D.z, r, ctl);
+                         D.Bb, D.rows, D.z, r, gate);
   }
   if (D.sub_tasks > 0)
     hipLaunchKernelGGL(k_solve_bwd_sub, dim3(D.sub_tasks), dim3(kSubThreads), 0, st, D.sub_bw,
-                       D.sub_bw_ptr, D.sub_levels, D.Bb, D.rows, D.z, r, ctl);
+                       D.sub_bw_ptr, D.sub_levels, D.Bb, D.rows, D.z, r, gate);
 }
 
 }  // namespace qn

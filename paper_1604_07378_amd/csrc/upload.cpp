@@ -1,0 +1,593 @@
+// Device upload of one simulation or a batch of independent simulations:
+// the analyzed meshes are concatenated (vertices, tets, materials, factors;
+// A is block diagonal), the supernodal solve schedule is built over the
+// combined supernode forest, and the block tables of the segmented kernels
+// place every block in one simulation, laid out as when it runs alone.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/qnsim.h"
+#include "ctx.hpp"
+
+namespace qn {
+
+namespace {
+
+#define FAIL(code, msg)   \
+  do {                    \
+    err = (msg);          \
+    return (code);        \
+  } while (0)
+
+template <class T>
+int upload(DeviceMesh& D, T** dst, const T* src, size_t count, std::string& err) {
+  hipError_t e = hipMalloc((void**)dst, std::max<size_t>(count * sizeof(T), 8));
+  if (e != hipSuccess) FAIL(QNSIM_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  D.bytes += count * sizeof(T);
+  if (count) {
+    e = hipMemcpy(*dst, src, count * sizeof(T), hipMemcpyHostToDevice);
+    if (e != hipSuccess) FAIL(QNSIM_E_DEVICE, std::string("hipMemcpy: ") + hipGetErrorString(e));
+  }
+  return QNSIM_OK;
+}
+
+#define UP(dst, vec)                                                    \
+  do {                                                                  \
+    int rc_ = upload(D, &(dst), (vec).data(), (vec).size(), err);       \
+    if (rc_) return rc_;                                                \
+  } while (0)
+
+// Supernodes of several factors side by side: column, row-list, block and
+// supernode indices shifted by each factor's offsets.
+void stack_factors(const std::vector<const Factor*>& fs, const std::vector<int>& col0, Factor& F) {
+  F = Factor();
+  F.child_ptr.push_back(0);
+  for (size_t k = 0; k < fs.size(); ++k) {
+    const Factor& f = *fs[k];
+    const int sn0 = (int)F.sn.size();
+    const int64_t rows0 = (int64_t)F.rows.size(), val0 = (int64_t)F.Binv.size();
+    for (Supernode S : f.sn) {
+      S.first += col0[k];
+      if (S.parent >= 0) S.parent += sn0;
+      S.rows_off += rows0;
+      S.val_off += val0;
+      F.sn.push_back(S);
+    }
+    for (int r : f.rows) F.rows.push_back(r + col0[k]);
+    F.rel.insert(F.rel.end(), f.rel.begin(), f.rel.end());
+    const int c0 = (int)F.children.size();
+    for (size_t s = 1; s < f.child_ptr.size(); ++s) F.child_ptr.push_back(c0 + f.child_ptr[s]);
+    for (int ch : f.children) F.children.push_back(ch + sn0);
+    F.Binv.insert(F.Binv.end(), f.Binv.begin(), f.Binv.end());
+    F.n += f.n;
+    F.nlevels = std::max(F.nlevels, f.nlevels);
+    F.max_front = std::max(F.max_front, f.max_front);
+    F.nnz_stored += f.nnz_stored;
+    F.nnz_exact += f.nnz_exact;
+    F.flops += f.flops;
+  }
+  F.top = -1;
+}
+
+}  // namespace
+
+int upload_sims(const std::vector<const qnsim*>& sims, const qnsim_options& opt, double h,
+                DeviceMesh& D, std::string& err) {
+  dev_free(D);
+  const int S = (int)sims.size();
+  if (S < 1) FAIL(QNSIM_E_INVALID, "no simulation to upload");
+  // offsets of each simulation in the concatenated arrays: free vertices
+  // first (every simulation's, in order), then the pinned ones; tets,
+  // materials and caller vertices in simulation order
+  std::vector<int> vf0(S), vp0(S), t0(S), m0(S), cv0(S);
+  int n = 0, nf = 0, T = 0, nmat = 0;
+  for (int s = 0; s < S; ++s) {
+    const qnsim* c = sims[s];
+    if (!c->analyzed || c->h != h) FAIL(QNSIM_E_STATE, "simulation not analyzed for this h");
+    if (S > 1 && c->factor.top >= 0) FAIL(QNSIM_E_INVALID, "batched simulations need dense_top = 0");
+    vf0[s] = nf; t0[s] = T; m0[s] = nmat; cv0[s] = n;
+    nf += c->nf; T += c->T; nmat += (int)c->mats.size(); n += c->n;
+  }
+  {
+    int p = nf;
+    for (int s = 0; s < S; ++s) { vp0[s] = p; p += sims[s]->n - sims[s]->nf; }
+  }
+  // a simulation's internal vertex i -> index in the concatenation
+  auto gv = [&](int s, int i) { return i < sims[s]->nf ? vf0[s] + i : vp0[s] + (i - sims[s]->nf); };
+  D.device = opt.device;
+  D.S = S;
+  D.n = n; D.nf = nf; D.T = T; D.h = h;
+  D.nmat = nmat;
+  D.single_type = sims[0]->single_type;
+  for (int s = 1; s < S; ++s)
+    if (sims[s]->single_type != D.single_type) D.single_type = -1;
+  D.m = opt.history;
+  D.slots = D.m + 1;
+  // element data in internal tet order
+  std::vector<int> tv(4 * (size_t)T), tm(T), tperm(T), vperm(n), vsim(n);
+  std::vector<double> Bm(9 * (size_t)T), vol(T), mass(n);
+  std::vector<DevMat> dm;
+  for (int s = 0; s < S; ++s) {
+    const qnsim* c = sims[s];
+    for (int t = 0; t < c->T; ++t) {
+      const int o = c->tperm[t], g = t0[s] + t;
+      for (int a = 0; a < 4; ++a)
+        tv[4 * (size_t)g + a] = gv(s, c->viperm[c->tets[4 * (size_t)o + a]]);
+      for (int e = 0; e < 9; ++e) Bm[(size_t)e * T + g] = c->Dminv[9 * (size_t)o + e];
+      vol[g] = c->vol[o];
+      tm[g] = m0[s] + c->tet_mat[o];
+      tperm[g] = t0[s] + o;
+    }
+    for (size_t i = 0; i < c->mats.size(); ++i) {
+      const Material& m = c->mats[i];
+      DevMat d;
+      std::memset(&d, 0, sizeof(d));
+      d.type = m.type; d.mu = m.mu; d.lam = m.lam;
+      for (int j = 0; j < 8; ++j) { d.d2[j] = m.d2[j]; d.a0[j] = m.a0[j]; d.a1[j] = m.a1[j]; }
+      dm.push_back(d);
+    }
+    for (int i = 0; i < c->n; ++i) {
+      const int g = gv(s, i);
+      vperm[g] = cv0[s] + c->vperm[i];
+      vsim[g] = s;
+      mass[g] = c->mass[c->vperm[i]];
+    }
+  }
+  // combined factor (a single simulation's is used as it is)
+  Factor stacked;
+  const Factor* Fp = &sims[0]->factor;
+  if (S > 1) {
+    std::vector<const Factor*> fs(S);
+    for (int s = 0; s < S; ++s) fs[s] = &sims[s]->factor;
+    stack_factors(fs, vf0, stacked);
+    Fp = &stacked;
+  }
+  const Factor& F = *Fp;
+  // incidences of free vertices, ordered by (internal tet, slot), in a padded
+  // table of inc_w entries per vertex (-1 after the last)
+  std::vector<int> valence(nf, 0);
+  for (int t = 0; t < T; ++t)
+    for (int a = 0; a < 4; ++a)
+      if (tv[4 * (size_t)t + a] < nf) valence[tv[4 * (size_t)t + a]]++;
+  int inc_w = 4;
+  for (int i = 0; i < nf; ++i) inc_w = std::max(inc_w, (valence[i] + 3) / 4 * 4);
+  std::vector<int> inc_tab((size_t)std::max(nf, 1) * inc_w, -1);
+  {
+    std::vector<int> fill(nf, 0);
+    for (int t = 0; t < T; ++t)
+      for (int a = 0; a < 4; ++a) {
+        const int v = tv[4 * (size_t)t + a];
+        if (v < nf) inc_tab[(size_t)v * inc_w + fill[v]++] = 4 * t + a;
+      }
+  }
+  // supernodal solve: packed blocks (row-major forward copy, column-major
+  // backward copy), work items in topological order, assembly lists
+  const int ns = (int)F.sn.size();
+  auto pow2ceil = [](int v) { int p = 1; while (p < v) p <<= 1; return p; };
+  auto clampi = [](int v, int lo, int hi) { return std::max(lo, std::min(hi, v)); };
+  std::vector<SnInfo> sinfo(ns);
+  // packed offsets: the dense top block (if any) is stored in full in the
+  // forward array only; every other block is packed in both arrays
+  const int top = F.top;
+  std::vector<int64_t> pf(ns + 1, 0), pb(ns + 1, 0);
+  for (int s = 0; s < ns; ++s) {
+    const Supernode& S = F.sn[s];
+    const int64_t packed = (int64_t)S.ncol * (S.ncol + 1) / 2 + (int64_t)S.nbelow * S.ncol;
+    pf[s + 1] = pf[s] + (s == top ? (int64_t)S.ncol * S.ncol : packed);
+    pb[s + 1] = pb[s] + (s == top ? 0 : packed);
+  }
+  std::vector<double> Bf(pf[ns]), Bb(pb[ns]);
+  std::vector<int4> fwl, bwl;
+  std::vector<std::vector<int4>> fw_by_level(F.nlevels), bw_by_level(F.nlevels);
+  // bottom subtrees: the lowest levels whose supernodes all have at most
+  // subtree_cap rows are solved by one workgroup per subtree
+  const int sparse_levels = top >= 0 ? F.sn[top].level : F.nlevels;
+  int Lsub = 0;
+  {
+    std::vector<int> maxm(F.nlevels, 0);
+    for (int s = 0; s < ns; ++s)
+      if (s != top) maxm[F.sn[s].level] = std::max(maxm[F.sn[s].level], F.sn[s].m());
+    const int cap = std::min(opt.subtree_cap, kSubCap);
+    while (Lsub < sparse_levels && maxm[Lsub] <= cap) ++Lsub;
+    if (Lsub < 2) Lsub = 0;
+  }
+  for (int s = 0; s < ns; ++s) {
+    const Supernode& S = F.sn[s];
+    const int nc = S.ncol, m = S.m();
+    const double* blk = F.Binv.data() + S.val_off;
+    SnInfo& I = sinfo[s];
+    I.first = S.first; I.ncol = nc; I.nbelow = S.nbelow; I.parent = S.parent;
+    I.nchild = F.child_ptr[s + 1] - F.child_ptr[s];
+    I.fw_off = pf[s]; I.bw_off = pb[s];
+    I.rows_off = S.rows_off; I.vp_in = 0; I.vp_out = -1;
+    if (s == top) {
+      // symmetric: the column-major block is also its row-major copy
+      std::copy(blk, blk + (size_t)nc * nc, Bf.data() + pf[s]);
+      I.fw_items = I.bw_items = 0;
+      continue;
+    }
+    double* bf = Bf.data() + pf[s];
+    double* bb = Bb.data() + pb[s];
+    for (int r = 0; r < m; ++r) {
+      const int len = r < nc ? r + 1 : nc;
+      const int64_t ro = r < nc ? (int64_t)r * (r + 1) / 2
+                                : (int64_t)nc * (nc + 1) / 2 + (int64_t)(r - nc) * nc;
+      for (int c = 0; c < len; ++c) bf[ro + c] = blk[r + (size_t)c * m];
+    }
+    for (int c = 0; c < nc; ++c) {
+      const int64_t co = (int64_t)c * m - (int64_t)c * (c - 1) / 2;
+      for (int i = c; i < m; ++i) bb[co + (i - c)] = blk[i + (size_t)c * m];
+    }
+    if (S.level < Lsub) {
+      I.fw_items = I.bw_items = 0;  // one-wave items, built per subtree below
+      continue;
+    }
+    // forward items: groups of Lf lanes per row, up to 4 rows per group
+    const int Lf = clampi(pow2ceil((nc + 3) / 4), 4, 64), sf = 4 * (64 / Lf);
+    const int rpg_f = clampi(((16384 + nc - 1) / nc + sf - 1) / sf, 1, 4);
+    const int rows_item = sf * rpg_f;
+    for (int r0 = 0; r0 < m; r0 += rows_item)
+      fw_by_level[S.level].push_back(make_int4(s, r0, std::min(m, r0 + rows_item), Lf));
+    I.fw_items = (m + rows_item - 1) / rows_item;
+    // backward items: groups of Lb lanes per column, up to 4 columns per group
+    const int Lb = clampi(pow2ceil((m + 3) / 4), 4, 64), sb = 4 * (64 / Lb);
+    const int rpg_b = clampi(((16384 + m - 1) / m + sb - 1) / sb, 1, 4);
+    const int cols_item = sb * rpg_b;
+    for (int c0 = 0; c0 < nc; c0 += cols_item)
+      bw_by_level[S.level].push_back(
+          make_int4((int)(0x80000000u | (unsigned)s), c0, std::min(nc, c0 + cols_item), Lb));
+    I.bw_items = (nc + cols_item - 1) / cols_item;
+  }
+  // Update slots: supernode P owns K(P) layers of m(P) x 3 doubles in its own
+  // row space, K(P) = the largest number of children that update one row of
+  // P. The children updating a row take its layers in child order, so every
+  // entry is written by one child at the same place every solve and the
+  // entries nobody writes stay zero; P sums K(P) layers instead of one slot
+  // per child. relL holds each below row's layered position (layer m(P) + row).
+  std::vector<int> relL(F.rel.size(), 0);
+  {
+    std::vector<int> cnt;
+    for (int s = 0; s < ns; ++s) {
+      const int mP = F.sn[s].m();
+      cnt.assign(mP, 0);
+      int K = 0;
+      for (int e = F.child_ptr[s]; e < F.child_ptr[s + 1]; ++e) {
+        const Supernode& C = F.sn[F.children[e]];
+        for (int r = 0; r < C.nbelow; ++r) {
+          const int pos = F.rel[C.rows_off + r];
+          const int layer = cnt[pos]++;
+          K = std::max(K, layer + 1);
+          relL[C.rows_off + r] = layer * mP + pos;
+        }
+      }
+      sinfo[s].nchild = K;
+    }
+  }
+  int64_t vp_total = 0;
+  for (int s = 0; s < ns; ++s) {
+    SnInfo& I = sinfo[s];
+    I.vp_in = vp_total;
+    vp_total += (int64_t)I.nchild * 3 * (I.ncol + I.nbelow);
+  }
+  for (int s = 0; s < ns; ++s)
+    for (int e = F.child_ptr[s]; e < F.child_ptr[s + 1]; ++e)
+      sinfo[F.children[e]].vp_out = sinfo[s].vp_in;
+  for (int s = 0; s < ns; ++s) {
+    SnInfo& I = sinfo[s];
+    I.child_items = 0;
+    for (int e = F.child_ptr[s]; e < F.child_ptr[s + 1]; ++e) I.child_items += sinfo[F.children[e]].fw_items;
+  }
+  // subtree tasks: roots are bottom supernodes whose parent is not a bottom
+  // supernode; a subtree is a contiguous range of the postordered supernodes.
+  // A task (one workgroup) takes one or more whole subtrees.
+  std::vector<int4> sub_fw, sub_bw;
+  std::vector<int> sub_fw_ptr, sub_bw_ptr, task_of(ns, -1);
+  int n_tasks = 0;
+  if (Lsub > 0) {
+    std::vector<int> start(ns);
+    for (int s = 0; s < ns; ++s) {
+      start[s] = s;
+      for (int e = F.child_ptr[s]; e < F.child_ptr[s + 1]; ++e)
+        start[s] = std::min(start[s], start[F.children[e]]);
+    }
+    // subtree roots and sizes (stored block entries)
+    std::vector<int> roots;
+    std::vector<double> size;
+    for (int R = 0; R < ns; ++R) {
+      const Supernode& SR = F.sn[R];
+      if (R == top || SR.level >= Lsub) continue;
+      if (SR.parent >= 0 && SR.parent != top && F.sn[SR.parent].level < Lsub) continue;
+      double e = 0.0;
+      for (int s = start[R]; s <= R; ++s)
+        e += (double)F.sn[s].ncol * (F.sn[s].ncol + 1) / 2 + (double)F.sn[s].ncol * F.sn[s].nbelow;
+      roots.push_back(R);
+      size.push_back(e);
+    }
+    // at most one workgroup per compute unit (the subtree kernels' LDS
+    // allows one per CU): largest subtrees first, each to the lightest group
+    const int ngroups = std::min((int)roots.size(), kSubGroups);
+    std::vector<int> order(roots.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return size[x] > size[y]; });
+    std::vector<std::vector<int>> members(ngroups);
+    std::vector<double> load(ngroups, 0.0);
+    for (int i : order) {
+      const int g = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      members[g].push_back(roots[i]);
+      load[g] += size[i];
+    }
+    for (int g = 0; g < ngroups; ++g) {
+      std::sort(members[g].begin(), members[g].end());
+      std::vector<std::vector<int4>> fw(Lsub), bw(Lsub);
+      for (int R : members[g])
+        for (int s = start[R]; s <= R; ++s) {
+          const Supernode& S = F.sn[s];
+          task_of[s] = n_tasks;
+          const int nc = S.ncol, m = S.m();
+          const int Lf = clampi(pow2ceil((nc + 3) / 4), 4, 64), rf = 4 * (64 / Lf);
+          for (int r0 = 0; r0 < m; r0 += rf)
+            fw[S.level].push_back(make_int4(s, r0, std::min(m, r0 + rf), Lf));
+          const int Lb = clampi(pow2ceil((m + 3) / 4), 4, 64), cb = 4 * (64 / Lb);
+          for (int c0 = 0; c0 < nc; c0 += cb)
+            bw[S.level].push_back(
+                make_int4((int)(0x80000000u | (unsigned)s), c0, std::min(nc, c0 + cb), Lb));
+        }
+      for (int l = 0; l < Lsub; ++l) {
+        sub_fw_ptr.push_back((int)sub_fw.size());
+        sub_fw.insert(sub_fw.end(), fw[l].begin(), fw[l].end());
+        sub_bw_ptr.push_back((int)sub_bw.size());
+        sub_bw.insert(sub_bw.end(), bw[l].begin(), bw[l].end());
+      }
+      sub_fw_ptr.push_back((int)sub_fw.size());
+      sub_bw_ptr.push_back((int)sub_bw.size());
+      ++n_tasks;
+    }
+  }
+  D.levels.assign(F.nlevels, Level{0, 0, 0, 0});
+  for (int l = 0; l < F.nlevels; ++l) {
+    D.levels[l].fw_begin = (int)fwl.size();
+    fwl.insert(fwl.end(), fw_by_level[l].begin(), fw_by_level[l].end());
+    D.levels[l].fw_end = (int)fwl.size();
+  }
+  for (int l = F.nlevels - 1; l >= 0; --l) {
+    D.levels[l].bw_begin = (int)fwl.size();
+    fwl.insert(fwl.end(), bw_by_level[l].begin(), bw_by_level[l].end());
+    D.levels[l].bw_end = (int)fwl.size();
+  }
+  // Self-check of the solve schedule before anything reaches the device:
+  // item ranges inside their supernode and within the 4 rows/columns per lane
+  // group the kernel handles, every row and column covered exactly once,
+  // packed offsets, row lists and assembly indices inside their arrays.
+  {
+    std::vector<int> cover_r(ns, 0), cover_c(ns, 0);
+    for (const int4& it : fwl) {
+      const bool bwd = it.x < 0;
+      const int s = it.x & 0x7fffffff;
+      if (s < 0 || s >= ns) FAIL(QNSIM_E_DEVICE, "schedule: bad supernode");
+      const SnInfo& I = sinfo[s];
+      const int lim = bwd ? I.ncol : I.ncol + I.nbelow;
+      if (it.y < 0 || it.z > lim || it.y >= it.z || it.w < 4 || it.w > 64 || (64 % it.w) != 0 ||
+          it.z - it.y > 4 * 4 * (64 / it.w))
+        FAIL(QNSIM_E_DEVICE, "schedule: bad item range");
+      (bwd ? cover_c : cover_r)[s] += it.z - it.y;
+    }
+    for (int t = 0; t < n_tasks; ++t) {
+      for (int pass = 0; pass < 2; ++pass) {
+        const std::vector<int>& ptr = pass ? sub_bw_ptr : sub_fw_ptr;
+        const std::vector<int4>& its = pass ? sub_bw : sub_fw;
+        for (int l = 0; l < Lsub; ++l) {
+          const int b = ptr[(size_t)t * (Lsub + 1) + l], e = ptr[(size_t)t * (Lsub + 1) + l + 1];
+          if (b > e || e > (int)its.size()) FAIL(QNSIM_E_DEVICE, "schedule: bad subtree offsets");
+          for (int i = b; i < e; ++i) {
+            const int4 it = its[i];
+            const int s = it.x & 0x7fffffff;
+            if ((it.x < 0) != (pass == 1) || s < 0 || s >= ns || task_of[s] != t ||
+                F.sn[s].level != l)
+              FAIL(QNSIM_E_DEVICE, "schedule: subtree item outside its task or level");
+            const SnInfo& I = sinfo[s];
+            const int lim = pass ? I.ncol : I.ncol + I.nbelow;
+            if (I.ncol + I.nbelow > kSubCap || it.y < 0 || it.z > lim || it.y >= it.z ||
+                it.w < 4 || it.w > 64 || (64 % it.w) != 0 || it.z - it.y > 4 * (64 / it.w))
+              FAIL(QNSIM_E_DEVICE, "schedule: bad subtree item range");
+            (pass ? cover_c : cover_r)[s] += it.z - it.y;
+          }
+        }
+      }
+    }
+    for (int s = 0; s < ns; ++s) {
+      if (task_of[s] < 0) continue;
+      const int p = sinfo[s].parent;
+      // the parent is in the same subtree at a higher level, or outside every subtree
+      if (p >= 0 && !((task_of[p] == task_of[s] && F.sn[p].level > F.sn[s].level) ||
+                      (task_of[p] < 0 && (p == top || F.sn[p].level >= Lsub))))
+        FAIL(QNSIM_E_DEVICE, "schedule: subtree parent order");
+    }
+    for (int s = 0; s < ns; ++s) {
+      const SnInfo& I = sinfo[s];
+      const bool is_top = s == top;
+      if (is_top ? (cover_r[s] != 0 || cover_c[s] != 0 || I.nbelow != 0 || I.parent >= 0 ||
+                    s != ns - 1 || I.ncol > kMaxDenseTop || I.first + I.ncol != nf)
+                 : (cover_r[s] != I.ncol + I.nbelow || cover_c[s] != I.ncol))
+        FAIL(QNSIM_E_DEVICE, "schedule: rows or columns not covered once");
+      if (I.fw_off + (is_top ? (int64_t)I.ncol * I.ncol
+                             : (int64_t)I.ncol * (I.ncol + 1) / 2 + (int64_t)I.nbelow * I.ncol) >
+              (int64_t)Bf.size() ||
+          (!is_top && I.bw_off + (int64_t)I.ncol * (I.ncol + 1) / 2 + (int64_t)I.nbelow * I.ncol >
+                          (int64_t)Bb.size()))
+        FAIL(QNSIM_E_DEVICE, "schedule: block offset out of range");
+      if (I.rows_off + I.nbelow > (int64_t)F.rows.size() || I.first < 0 || I.first + I.ncol > nf ||
+          I.vp_in < 0 || I.vp_in + (int64_t)I.nchild * 3 * (I.ncol + I.nbelow) > vp_total ||
+          (I.parent >= 0) != (I.vp_out >= 0) ||
+          I.parent >= ns || (I.parent >= 0 && I.vp_out != sinfo[I.parent].vp_in) ||
+          (I.parent < 0 && I.nbelow != 0))
+        FAIL(QNSIM_E_DEVICE, "schedule: row list or update offset out of range");
+      for (int r = 0; r < I.nbelow; ++r) {
+        int g = F.rows[I.rows_off + r];
+        if (g < I.first + I.ncol || g >= nf) FAIL(QNSIM_E_DEVICE, "schedule: bad row");
+      }
+      if (I.parent >= ns) FAIL(QNSIM_E_DEVICE, "schedule: bad parent");
+      if (I.parent >= 0) {
+        const SnInfo& P = sinfo[I.parent];
+        const int mP = P.ncol + P.nbelow;
+        for (int r = 0; r < I.nbelow; ++r) {
+          const int pos = F.rel[I.rows_off + r];
+          const int lp = relL[I.rows_off + r];
+          if (pos < 0 || pos >= mP || (r > 0 && pos <= F.rel[I.rows_off + r - 1]) ||
+              lp % mP != pos || lp / mP >= P.nchild)
+            FAIL(QNSIM_E_DEVICE, "schedule: bad relative row");
+        }
+      }
+    }
+    // topological order: forward items of a supernode come after those of its
+    // children, backward items after those of its parent and after all forward items
+    std::vector<int> last_fw(ns, -1), first_fw(ns, 1 << 30), first_bw(ns, 1 << 30), last_bw(ns, -1);
+    for (int i = 0; i < (int)fwl.size(); ++i) {
+      const int s = fwl[i].x & 0x7fffffff;
+      if (fwl[i].x < 0) { first_bw[s] = std::min(first_bw[s], i); last_bw[s] = i; }
+      else { first_fw[s] = std::min(first_fw[s], i); last_fw[s] = i; }
+    }
+    // the dense top block runs between the two sweeps: after every forward
+    // item and before every backward item
+    for (int s = 0; s < ns; ++s) {
+      if (s == top) continue;
+      const int p = sinfo[s].parent;
+      if (p == top) continue;
+      if (p >= 0 && !(last_fw[s] < first_fw[p] && last_bw[p] < first_bw[s]))
+        FAIL(QNSIM_E_DEVICE, "schedule: items not in topological order");
+      if (p < 0 && !(last_fw[s] < first_bw[s])) FAIL(QNSIM_E_DEVICE, "schedule: root order");
+    }
+  }
+  // host-side construction done: select the device and upload
+  if (hipSetDevice(D.device) != hipSuccess) FAIL(QNSIM_E_DEVICE, "hipSetDevice failed (no GPU?)");
+  UP(D.tv, tv);
+  UP(D.Bm, Bm);
+  D.mixed = opt.precision == QNSIM_MIXED;
+  UP(D.vol, vol);
+  if (D.nmat > 1) UP(D.tmat, tm);
+  UP(D.mats, dm);
+  UP(D.mass, mass);
+  D.inc_w = inc_w;
+  UP(D.inc_tab, inc_tab);
+  UP(D.vperm, vperm);
+  UP(D.tperm, tperm);
+  UP(D.vsim, vsim);
+  D.nsn = ns;
+  D.n_items = (int)fwl.size();
+  auto to_desc = [&](const std::vector<int4>& in) {
+    std::vector<ItemDesc> out(in.size());
+    for (size_t i = 0; i < in.size(); ++i) {
+      const int4 it = in[i];
+      const bool bwd = it.x < 0;
+      const SnInfo& I = sinfo[it.x & 0x7fffffff];
+      ItemDesc& d = out[i];
+      d.begin = it.y; d.end = it.z; d.L = it.w; d.nchild = I.nchild;
+      d.first = I.first; d.ncol = I.ncol; d.nbelow = I.nbelow; d.pad = 0;
+      d.blk = bwd ? I.bw_off : I.fw_off;
+      d.rows_off = I.rows_off; d.vp_in = I.vp_in; d.vp_out = I.vp_out;
+    }
+    return out;
+  };
+  D.sub_levels = n_tasks > 0 ? Lsub : 0;
+  D.sub_tasks = n_tasks;
+  if (n_tasks > 0) {
+    UP(D.sub_fw, to_desc(sub_fw));
+    UP(D.sub_bw, to_desc(sub_bw));
+    UP(D.sub_fw_ptr, sub_fw_ptr);
+    UP(D.sub_bw_ptr, sub_bw_ptr);
+  }
+  D.top_n = 0;
+  if (top >= 0) {
+    D.top_first = sinfo[top].first;
+    D.top_n = sinfo[top].ncol;
+    D.top_nch = sinfo[top].nchild;
+    D.top_vp = sinfo[top].vp_in;
+    D.top_off = sinfo[top].fw_off;
+  }
+  UP(D.sn, sinfo);
+  UP(D.items, to_desc(fwl));
+  UP(D.Bf, Bf);
+  UP(D.Bb, Bb);
+  UP(D.rows, F.rows);
+  UP(D.rel, relL);
+  {
+    std::vector<double> zv((size_t)vp_total + 3, 0.0);  // zero once: see child slots
+    UP(D.vp, zv);
+  }
+  // block tables of the segmented kernels: each simulation's blocks start
+  // at its own first tet / free vertex / entry, as when it runs alone
+  {
+    std::vector<SimSeg> seg(S);
+    std::vector<BlockSeg> eb, gb, vb, rb;
+    auto mk = [](int sim, int a0, int a1, int b0, int b1) {
+      BlockSeg x;
+      x.sim = sim; x.a0 = a0; x.a1 = a1; x.b0 = b0; x.b1 = b1; x.pad0 = x.pad1 = x.pad2 = 0;
+      return x;
+    };
+    for (int s = 0; s < S; ++s) {
+      const qnsim* c = sims[s];
+      SimSeg& g = seg[s];
+      g.vf0 = vf0[s]; g.nf = c->nf; g.t0 = t0[s]; g.T = c->T;
+      const int ne = std::max((c->T + 255) / 256, (c->nf + 255) / 256);
+      g.eb0 = (int)eb.size();
+      for (int j = 0; j < ne; ++j)
+        eb.push_back(mk(s, std::min(t0[s] + c->T, t0[s] + 256 * j),
+                        std::min(t0[s] + c->T, t0[s] + 256 * (j + 1)),
+                        std::min(vf0[s] + c->nf, vf0[s] + 256 * j),
+                        std::min(vf0[s] + c->nf, vf0[s] + 256 * (j + 1))));
+      g.eb1 = (int)eb.size();
+      g.gb0 = (int)gb.size();
+      for (int v = 0; v < c->nf; v += 64)
+        gb.push_back(mk(s, vf0[s] + v, vf0[s] + std::min(c->nf, v + 64), 0, 0));
+      g.gb1 = (int)gb.size();
+      const int e0 = 3 * vf0[s], ne3 = 3 * c->nf;
+      g.vb0 = (int)vb.size();
+      for (int e = 0; e < ne3; e += 256) vb.push_back(mk(s, e0 + e, e0 + std::min(ne3, e + 256), 0, 0));
+      g.vb1 = (int)vb.size();
+      g.rb0 = (int)rb.size();
+      for (int e = 0; e < ne3; e += 1024) rb.push_back(mk(s, e0 + e, e0 + std::min(ne3, e + 1024), 0, 0));
+      g.rb1 = (int)rb.size();
+    }
+    // self-check: every tet, free vertex and entry in exactly one block of its simulation
+    {
+      std::vector<char> ct(T, 0), cv(nf, 0), cg(nf, 0), ce(3 * (size_t)nf, 0), cr(3 * (size_t)nf, 0);
+      for (const BlockSeg& x : eb) {
+        if (x.a1 - x.a0 > 256 || x.b1 - x.b0 > 256) FAIL(QNSIM_E_DEVICE, "blocks: element block too large");
+        for (int t = x.a0; t < x.a1; ++t) { if (t < t0[x.sim] || t >= t0[x.sim] + sims[x.sim]->T) FAIL(QNSIM_E_DEVICE, "blocks: tet outside its simulation"); ct[t]++; }
+        for (int v = x.b0; v < x.b1; ++v) { if (vsim[v] != x.sim) FAIL(QNSIM_E_DEVICE, "blocks: vertex outside its simulation"); cv[v]++; }
+      }
+      for (const BlockSeg& x : gb) {
+        if (x.a1 - x.a0 > 64) FAIL(QNSIM_E_DEVICE, "blocks: gather block too large");
+        for (int v = x.a0; v < x.a1; ++v) { if (vsim[v] != x.sim) FAIL(QNSIM_E_DEVICE, "blocks: vertex outside its simulation"); cg[v]++; }
+      }
+      for (const BlockSeg& x : vb) {
+        if (x.a1 - x.a0 > 256) FAIL(QNSIM_E_DEVICE, "blocks: vector block too large");
+        for (int e = x.a0; e < x.a1; ++e) { if (vsim[e / 3] != x.sim) FAIL(QNSIM_E_DEVICE, "blocks: entry outside its simulation"); ce[e]++; }
+      }
+      for (const BlockSeg& x : rb) {
+        if (x.a1 - x.a0 > 1024) FAIL(QNSIM_E_DEVICE, "blocks: dot block too large");
+        for (int e = x.a0; e < x.a1; ++e) { if (vsim[e / 3] != x.sim) FAIL(QNSIM_E_DEVICE, "blocks: entry outside its simulation"); cr[e]++; }
+      }
+      for (int t = 0; t < T; ++t) if (ct[t] != 1) FAIL(QNSIM_E_DEVICE, "blocks: tet not covered once");
+      for (int v = 0; v < nf; ++v) if (cv[v] != 1 || cg[v] != 1) FAIL(QNSIM_E_DEVICE, "blocks: vertex not covered once");
+      for (size_t e = 0; e < 3 * (size_t)nf; ++e) if (ce[e] != 1 || cr[e] != 1) FAIL(QNSIM_E_DEVICE, "blocks: entry not covered once");
+    }
+    D.elem_blocks = (int)eb.size();
+    D.gather_blocks = (int)gb.size();
+    D.vec3_blocks = (int)vb.size();
+    D.rdots_blocks = (int)rb.size();
+    D.seg_h = seg;
+    UP(D.seg, seg);
+    UP(D.eblk, eb);
+    UP(D.gblk, gb);
+    UP(D.vblk, vb);
+    UP(D.rblk, rb);
+  }
+  return dev_alloc(D, err);
+}
+
+}  // namespace qn
