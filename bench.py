@@ -38,7 +38,7 @@ def log(msg):
 
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "solve_traffic_block40_neohookean.md")
-SOLVE_SOURCES = ["trisolve.hip", "factor.cpp", "api.cpp", "kernels.hpp", "wave.hpp"]
+SOLVE_SOURCES = ["trisolve.hip", "factor.cpp", "upload.cpp", "kernels.hpp", "wave.hpp"]
 
 
 def solve_traffic(n):
@@ -116,6 +116,113 @@ def run_material(kind, args, torch, W, qnsim, extra=None):
     return res
 
 
+def _pool_of(ws, qnsim, budget, group, **opt):
+    t0 = time.time()
+    p = qnsim.Pool(ws[0].h, budget, gravity=tuple(ws[0].gravity), **opt)
+    ids = p.add_workloads(ws)
+    t1 = time.time()
+    admitted = p.commit(group)
+    t2 = time.time()
+    return p, ids, admitted, t1 - t0, t2 - t1
+
+
+def batched_run(args, torch, W, qnsim, precision):
+    """Many independent meshes of uneven size in one group: every phase of the
+    step is one launch over all of them (one batched step = one step of each)."""
+    ws = W.workload_batch(count=args.batch_count, seed=0)
+    T = sum(w.n_tets for w in ws)
+    p, ids, admitted, t_an, t_up = _pool_of(ws, qnsim, 200 * 10**9, 0, precision=precision)
+    assert admitted == len(ws), "batch does not fit the budget"
+    log(f"[bench] batch of {len(ws)} meshes ({T} tets): analysis {t_an:.1f}s, upload {t_up:.1f}s, "
+        f"{p.info()['used_bytes'] / 1e9:.2f} GB")
+    for _ in range(args.warmup):
+        p.step(ids)
+    torch.cuda.synchronize()
+    evals, trials = 0, 0
+    t0 = time.perf_counter()
+    for _ in range(args.batch_steps):
+        st = p.step(ids)
+        for w, s in zip(ws, st):
+            evals += w.n_tets * (s["ls_trials"] + 1)
+            trials += s["ls_trials"]
+    dt = time.perf_counter() - t0
+    res = dict(meshes=len(ws), tets=T, verts=sum(w.n_verts for w in ws),
+               precision="mixed" if precision else "f64",
+               batched_steps_per_s=args.batch_steps / dt,
+               mesh_steps_per_s=args.batch_steps * len(ws) / dt,
+               tet_evals_per_s=evals / dt, ms_per_batched_step=1e3 * dt / args.batch_steps,
+               ls_trials_per_mesh_step=trials / (args.batch_steps * len(ws)),
+               device_gb=p.info()["used_bytes"] / 1e9, analysis_s=t_an, upload_s=t_up)
+    log(f"[bench] batch ({res['precision']}): {res['batched_steps_per_s']:.1f} batched steps/s, "
+        f"{res['mesh_steps_per_s']:.0f} mesh-steps/s, {res['tet_evals_per_s'] / 1e9:.2f} G tet-evals/s")
+    p.close()
+    return res
+
+
+def served_run(args, torch, W, qnsim):
+    """Request loop over a pool of resident simulations with lognormal sizes:
+    Poisson step requests for uniformly drawn simulations at fractions of the
+    pool's measured batched capacity; latency from submit to completion."""
+    import numpy as np
+    descs = W.workload_pool(count=args.pool_count, seed=0)
+    ws = []
+    for i, d in enumerate(descs):
+        w = W.workload_block(d["kind"], dims=d["dims"], edge=d["edge"], prestretch_seed=d["seed"],
+                             spline_seed=d["seed"], nu=d["nu"])
+        ws.append(w)
+    T = sum(w.n_tets for w in ws)
+    p, ids, admitted, t_an, t_up = _pool_of(ws, qnsim, args.pool_budget_gb * 10**9,
+                                            args.pool_group, precision=args.pool_precision)
+    info = p.info()
+    assert admitted == len(ids), "pool does not fit the budget"
+    res_ids = ids
+    log(f"[bench] pool of {len(ws)} sims ({T} tets), {admitted} admitted into {info['groups']} "
+        f"groups, {info['used_bytes'] / 1e9:.2f} GB; analysis {t_an:.1f}s, upload {t_up:.1f}s")
+    # capacity: every resident simulation stepped once, groups concurrently
+    p.step(res_ids)
+    t0 = time.perf_counter()
+    p.step(res_ids)
+    cap = len(res_ids) / (time.perf_counter() - t0)
+    log(f"[bench] pool capacity (all resident sims, one batched step each): {cap:.0f} steps/s")
+    rng = np.random.default_rng(np.random.SeedSequence([0x5E7, 0]))
+    p.serve_start(lanes=args.pool_lanes)
+    rates = []
+    for frac in [float(f) for f in args.pool_load.split(",")]:
+        rate = frac * cap
+        n = args.pool_requests
+        gaps = rng.exponential(1.0 / rate, size=n)
+        who = rng.integers(0, len(res_ids), size=n)
+        tickets = []
+        t_start = time.perf_counter()
+        t_next = t_start
+        for g, j in zip(gaps, who):
+            t_next += g
+            while True:
+                d = t_next - time.perf_counter()
+                if d <= 0:
+                    break
+                time.sleep(min(d, 0.002) if d > 0.0005 else 0)
+            tickets.append(p.submit(res_ids[int(j)]))
+        lat = [p.wait(t, 120.0)[1] for t in tickets]
+        wall = time.perf_counter() - t_start
+        lat = np.array(lat)
+        r = dict(load=frac, offered_steps_per_s=rate, requests=n,
+                 achieved_steps_per_s=n / wall,
+                 p50_ms=float(np.percentile(lat, 50) * 1e3),
+                 p99_ms=float(np.percentile(lat, 99) * 1e3))
+        rates.append(r)
+        log(f"[bench] served load {frac:.2f} ({rate:.0f}/s offered): p50 {r['p50_ms']:.2f} ms, "
+            f"p99 {r['p99_ms']:.2f} ms, {r['achieved_steps_per_s']:.0f} steps/s")
+    p.serve_stop()
+    info = p.info()
+    p.close()
+    return dict(sims=len(ws), admitted=admitted, tets=T, groups=info["groups"],
+                precision="mixed" if args.pool_precision else "f64",
+                device_gb=info["used_bytes"] / 1e9, budget_gb=args.pool_budget_gb,
+                lanes=args.pool_lanes, capacity_steps_per_s=cap, rates=rates,
+                batches=info["batches_done"], analysis_s=t_an, upload_s=t_up)
+
+
 def cpu_baseline(args, W):
     """The FP64 oracle on a bounded sample: one step of the Neo-Hookean block."""
     import numpy as np  # noqa: F401
@@ -156,6 +263,19 @@ def main():
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="run one plain device copy of this many MB first (a reference kernel of "
                          "known traffic for hardware-counter runs)")
+    ap.add_argument("--batch-count", type=int, default=256,
+                    help="meshes of the batched run (0: skip it)")
+    ap.add_argument("--batch-steps", type=int, default=10)
+    ap.add_argument("--pool-count", type=int, default=200,
+                    help="simulations of the served run, the first of the 2,000-simulation "
+                         "pool's descriptions (0: skip it)")
+    ap.add_argument("--pool-group", type=int, default=32, help="simulations per group")
+    ap.add_argument("--pool-lanes", type=int, default=4)
+    ap.add_argument("--pool-budget-gb", type=float, default=200.0)
+    ap.add_argument("--pool-requests", type=int, default=2000, help="requests per load level")
+    ap.add_argument("--pool-load", default="0.25,0.5,0.8,1.2",
+                    help="offered loads as fractions of the measured capacity")
+    ap.add_argument("--pool-precision", type=int, default=1, help="1: mixed, 0: FP64")
     ap.add_argument("--set", action="append", default=[], metavar="OPTION=INT",
                     help="override an integer solver option (e.g. level_merge=0, dense_top=0)")
     args = ap.parse_args()
@@ -193,6 +313,11 @@ def main():
     if not args.no_mixed and W.NEOHOOKEAN in kinds:
         # informational: the mixed path (FP32 stresses) on the same workload
         mixed = run_material(W.NEOHOOKEAN, args, torch, W, qnsim, {"precision": qnsim.QNSIM_MIXED})
+
+    batched = []
+    if args.batch_count > 0:
+        batched = [batched_run(args, torch, W, qnsim, 0), batched_run(args, torch, W, qnsim, 1)]
+    served = served_run(args, torch, W, qnsim) if args.pool_count > 0 else None
 
     total_steps = sum(r["steps"] for r in runs)
     total_s = sum(r["seconds"] for r in runs)
@@ -241,6 +366,8 @@ def main():
         **({"mixed_precision_run": {k: mixed[k] for k in ("material", "steps_per_s", "ls_trials",
                                                          "iterations", "kernel_ms")}}
            if mixed else {}),
+        **({"batched": batched} if batched else {}),
+        **({"served": served} if served else {}),
         "roofline": {
             "bound": "hbm",
             "kernel": dom,

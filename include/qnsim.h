@@ -50,6 +50,7 @@ extern "C" {
 #define QNSIM_E_STATE -8       /* call out of order (e.g. step before prepare)  */
 #define QNSIM_E_NOMEM -9       /* host or device allocation failed              */
 #define QNSIM_E_DEVICE -10     /* HIP runtime error                             */
+#define QNSIM_E_BUDGET -11     /* pool: the simulation does not fit the budget  */
 
 /* ---- material types (section 4.1, Valanis-Landel materials; section 5) --- */
 #define QNSIM_NEOHOOKEAN 0  /* mu/2 (I1-3) - mu log J + lam/2 (log J)^2          */
@@ -256,6 +257,113 @@ int qnsim_time_kernel(qnsim_t* ctx, int32_t kernel, int32_t reps, double* avg_ms
 /* Descriptive text of a status code, and of the context's last failure. */
 const char* qnsim_strerror(int code);
 const char* qnsim_last_error(const qnsim_t* ctx);
+
+/* ==== Pools: many resident simulations on one GPU ========================
+ *
+ * A pool keeps many independent simulations (mesh, materials, prefactored A
+ * and state x, v) resident in device memory and advances any subset of them
+ * by one implicit-Euler step each, with the same method and options as a
+ * single context (sections 3-4). Admitted simulations are grouped; a group
+ * is one concatenated device mesh (A block diagonal) whose every phase (line
+ * -search trials, gradient gather, two-loop recursion, prefactored solve) is
+ * one kernel launch over all its stepping simulations, each simulation
+ * keeping its own line search and curvature pairs. A simulation's result in
+ * a group equals its result alone (same factor options, same reductions).
+ *
+ * Lifecycle: qnsim_pool_add (host precompute, the simulation is staged) ->
+ * qnsim_pool_commit (staged simulations are uploaded into new groups while
+ * the device-memory budget allows) -> qnsim_pool_step (synchronous batched
+ * step) or the serving loop (qnsim_pool_serve_start, qnsim_pool_submit,
+ * qnsim_pool_wait). Pools use dense_top = 0 and level_merge = 0: a level
+ * launch of a group serves all its simulations, so merging levels would only
+ * add bytes. Every simulation uses the pool's h and gravity; the
+ * external force is gravity only. Functions of one pool may be called from
+ * several threads. */
+typedef struct qnsim_pool qnsim_pool_t;
+
+/* One simulation: mesh (as qnsim_set_mesh), pinned vertices (as
+ * qnsim_set_pinned; pinned may be NULL when n_pinned = 0), materials (as
+ * qnsim_set_materials; tet_mat may be NULL) and the initial state x0, v0
+ * (n x 3; NULL: x0 = rest positions, v0 = 0). */
+typedef struct {
+  int32_t n_verts;
+  const double* rest_xyz;
+  int32_t n_tets;
+  const int32_t* tets;
+  int32_t n_pinned;
+  const int32_t* pinned;
+  int32_t n_mat;
+  const qnsim_material* mats;
+  const int32_t* tet_mat;
+  const double* x0;
+  const double* v0;
+} qnsim_mesh_desc;
+
+typedef struct {
+  int32_t sims_staged;     /* added, not yet resident                           */
+  int32_t sims_resident;   /* admitted into a group and not removed             */
+  int32_t groups;          /* device meshes                                     */
+  int32_t serving;         /* 1 while the request loop runs                     */
+  int64_t budget_bytes;    /* device-memory budget of the pool                  */
+  int64_t used_bytes;      /* device memory held by the groups                  */
+  int64_t steps_done;      /* simulation steps completed since creation         */
+  int64_t batches_done;    /* batched group steps since creation                */
+} qnsim_pool_info;
+
+/* Creates a pool for time step h with a device-memory budget in bytes
+ * (> 0). opts as qnsim_create (NULL: defaults); dense_top and level_merge
+ * are forced to 0. */
+int qnsim_pool_create(const qnsim_options* opts, double h, int64_t budget_bytes,
+                      qnsim_pool_t** out);
+/* Stops the request loop (finishing queued requests) and frees everything. */
+void qnsim_pool_destroy(qnsim_pool_t* pool);
+
+/* Validates and analyses n simulations on the host (in parallel) and stages
+ * them; ids[i] receives the id of descs[i]. On error nothing is staged;
+ * errors are those of qnsim_set_mesh / set_pinned / set_materials /
+ * qnsim_prepare's analysis, for the first failing description. */
+int qnsim_pool_add(qnsim_pool_t* pool, int32_t n, const qnsim_mesh_desc* descs, int32_t* ids);
+
+/* Uploads staged simulations (in id order) into new groups of at most
+ * max_group_sims simulations (<= 0: one group), skipping any whose estimated
+ * device memory does not fit the remaining budget (they stay staged).
+ * *n_admitted (nullable) receives the number admitted. */
+int qnsim_pool_commit(qnsim_pool_t* pool, int32_t max_group_sims, int32_t* n_admitted);
+
+/* Removes a resident or staged simulation; a group's device memory is freed
+ * when its last simulation is removed. */
+int qnsim_pool_remove(qnsim_pool_t* pool, int32_t id);
+
+/* One step of each listed resident simulation (distinct ids): groups run
+ * concurrently, each as one batched step of its listed simulations; the
+ * others keep their state. stats (nullable) receives one record per id.
+ * Synchronous. Not allowed while the request loop runs (QNSIM_E_STATE). */
+int qnsim_pool_step(qnsim_pool_t* pool, int32_t n, const int32_t* ids, qnsim_stats* stats);
+
+/* State of a resident simulation (host arrays, n x 3, its own numbering). */
+int qnsim_pool_get_state(qnsim_pool_t* pool, int32_t id, double* x, double* v);
+int qnsim_pool_set_state(qnsim_pool_t* pool, int32_t id, const double* x, const double* v);
+
+/* Request loop: `lanes` (1..8) host threads each take the group with the
+ * oldest queued request that is not already stepping, step all its
+ * simulations that have a queued request (one request per simulation per
+ * batch, in arrival order), and complete those requests; requests that
+ * arrive meanwhile join that group's next batch, and different groups step
+ * concurrently on their own streams. */
+int qnsim_pool_serve_start(qnsim_pool_t* pool, int32_t lanes);
+/* Queues one step request for a resident simulation; *ticket identifies it. */
+int qnsim_pool_submit(qnsim_pool_t* pool, int32_t id, int64_t* ticket);
+/* Waits for a request (at most timeout_s seconds; < 0: no limit) and
+ * returns its status: the step's own error, or QNSIM_E_STATE on time-out or
+ * an unknown ticket. stats and latency_s (time from submit to completion;
+ * both nullable) are filled on success. A ticket can be waited for once. */
+int qnsim_pool_wait(qnsim_pool_t* pool, int64_t ticket, double timeout_s, qnsim_stats* stats,
+                    double* latency_s);
+/* Stops the request loop after the queued requests are done. */
+int qnsim_pool_serve_stop(qnsim_pool_t* pool);
+
+int qnsim_pool_get_info(qnsim_pool_t* pool, qnsim_pool_info* info);
+const char* qnsim_pool_last_error(const qnsim_pool_t* pool);
 
 #ifdef __cplusplus
 }

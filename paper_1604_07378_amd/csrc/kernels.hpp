@@ -112,7 +112,7 @@ struct SnInfo {
 // per row or column.
 struct ItemDesc {
   int begin, end, L, nchild;  // nchild: layers of the supernode's update slots
-  int first, ncol, nbelow, pad;
+  int first, ncol, nbelow, sim;  // sim: the simulation the supernode belongs to
   long long blk;       // the supernode's block in this sweep's packed copy
   long long rows_off;  // its below-diagonal rows and their positions in the parent
   long long vp_in;     // its update layers (written by its children)
@@ -208,8 +208,10 @@ struct StepParams {
 };
 
 // Prefactored solve r = A^{-1} q on the stream (internal order, nf x 3).
-// gate: if not null, the launches do nothing while *gate <= 0.
-void launch_solve(DeviceMesh& D, hipStream_t st, const double* q, double* r, const int* gate);
+// gate: if not null, the launches do nothing while *gate <= 0; sim_ctl: if
+// not null, only the supernodes of simulations in PH_DIR are solved.
+void launch_solve(DeviceMesh& D, hipStream_t st, const double* q, double* r, const int* gate,
+                  const Ctl* sim_ctl = nullptr);
 
 // Workgroups of the dense top product for an n-column block: rows are split
 // evenly, at most 32 per workgroup, at most 256 workgroups unless more are

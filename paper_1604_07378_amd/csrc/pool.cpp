@@ -1,0 +1,608 @@
+// Pools of resident simulations: host analysis of many meshes, admission
+// into groups (one concatenated device mesh each) under a device-memory
+// budget, batched steps of any subset, and the request loop that serves
+// step requests with continuous batching (a group steps every simulation
+// with a queued request; requests arriving meanwhile join its next batch;
+// groups step concurrently on their own streams).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/qnsim.h"
+#include "ctx.hpp"
+
+using namespace qn;
+
+namespace {
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+struct PoolSim {
+  qnsim* c = nullptr;        // analyzed host context (mesh, factor); no device state
+  int group = -1;            // -1: staged
+  int slot = -1;             // position in its group
+  bool removed = false;
+  int64_t est_bytes = 0;     // device-memory estimate
+  std::vector<double> x0, v0;  // initial state until admitted
+};
+
+struct PoolGroup {
+  DeviceMesh D;
+  std::vector<int> ids;      // pool ids in group order
+  std::vector<int> cv0;      // first caller vertex of each member in xs / vs
+  double* xs = nullptr;      // states of the members, concatenated n x 3
+  double* vs = nullptr;
+  int64_t bytes = 0;
+  int live = 0;              // members not removed
+  bool busy = false;         // a step is running
+};
+
+struct Request {
+  int64_t ticket;
+  int sim;
+  double t_submit;
+};
+
+struct Done {
+  int rc;
+  qnsim_stats st;
+  double latency;
+};
+
+}  // namespace
+
+struct qnsim_pool {
+  qnsim_options opt;
+  double h = 0.0;
+  int64_t budget = 0, used = 0;
+  int64_t steps_done = 0, batches_done = 0;
+  std::vector<PoolSim> sims;
+  std::vector<std::unique_ptr<PoolGroup>> groups;
+  std::mutex mu;
+  std::condition_variable cv;
+  std::string last_error;
+  // request loop
+  std::vector<std::thread> lanes;
+  bool serving = false, stopping = false;
+  std::deque<Request> queue;
+  std::unordered_map<int64_t, Done> done;
+  int64_t next_ticket = 1;
+};
+
+namespace {
+
+int pfail(qnsim_pool* p, int code, const std::string& msg) {
+  p->last_error = msg;
+  return code;
+}
+
+StepParams pool_params(const qnsim_pool* p) {
+  StepParams s;
+  s.iterations = p->opt.iterations;
+  s.history = p->opt.history;
+  s.max_halvings = p->opt.max_halvings;
+  s.budget = 2;
+  s.gamma = p->opt.gamma;
+  s.backtrack = p->opt.backtrack;
+  for (int i = 0; i < 3; ++i) s.grav[i] = p->opt.gravity[i];
+  s.h = p->h;
+  return s;
+}
+
+void stats_of(const SimStat& t, qnsim_stats* s) {
+  s->iterations_run = t.iters;
+  s->ls_trials = t.trials;
+  s->ls_exhausted = t.exhausted;
+  s->lbfgs_skipped = t.skipped;
+  s->fallbacks = t.fallbacks;
+  s->reserved = 0;
+  s->g_first = t.g_first;
+  s->g_last = t.g_last;
+  s->grad_norm_first = std::sqrt(t.gnorm2_first);
+  s->grad_norm_last = NAN;
+}
+
+// Device bytes of one simulation in a group (the allocations of the upload
+// and of dev_alloc, plus its state arrays).
+int64_t estimate_bytes(const qnsim* c, int history) {
+  const Factor& F = c->factor;
+  const int64_t n = c->n, nf = c->nf, T = c->T, slots = history + 1;
+  int64_t packed = 0, vp = 0;
+  for (const Supernode& S : F.sn) {
+    packed += (int64_t)S.ncol * (S.ncol + 1) / 2 + (int64_t)S.nbelow * S.ncol;
+    vp += 3 * (int64_t)(S.ncol + S.nbelow) * 4;  // update layers (a few per supernode)
+  }
+  int64_t b = 0;
+  b += T * (16 + 72 + 8 + 4 + 4 + 96 + 8);          // tv, Bm, vol, tmat, tperm, fel, psi
+  b += n * (8 + 4 + 4 + 4 * 24 + 2 * 24);           // mass, vperm, vsim, x0 v0 y X, state
+  b += nf * (24 * 5 + 2 * slots * 24 + 4 * 64);     // G d r q z, S/T rings, incidences
+  b += 2 * packed * 8 + vp * 8;                     // forward/backward blocks, layers
+  b += (int64_t)F.rows.size() * 8 + (int64_t)F.sn.size() * 64 * 8;  // rows, rel, items
+  b += (T / 256 + nf / 64 + 3 * nf / 256 + 16) * (32 + 8 * 60);     // block tables, partials
+  b += sizeof(Ctl) + sizeof(SimStat) + 64;
+  return b + b / 16;
+}
+
+// One simulation described by d, analyzed on the host for the pool's h.
+int analyze_one(const qnsim_pool* p, const qnsim_mesh_desc& d, PoolSim& out, std::string& err) {
+  qnsim_options o = p->opt;
+  qnsim_t* c = nullptr;
+  int rc = qnsim_create(&o, &c);
+  if (rc) { err = "invalid options"; return rc; }
+  auto bail = [&](int code) {
+    err = qnsim_last_error(c);
+    qnsim_destroy(c);
+    return code;
+  };
+  if ((rc = qnsim_set_mesh(c, d.n_verts, d.rest_xyz, d.n_tets, d.tets))) return bail(rc);
+  if (d.n_pinned > 0 && (rc = qnsim_set_pinned(c, d.n_pinned, d.pinned))) return bail(rc);
+  if ((rc = qnsim_set_materials(c, d.n_mat, d.mats, d.tet_mat))) return bail(rc);
+  if ((rc = qnsim_analyze(c, p->h))) return bail(rc);
+  const size_t n3 = 3 * (size_t)d.n_verts;
+  out.x0.assign(n3, 0.0);
+  out.v0.assign(n3, 0.0);
+  for (size_t i = 0; i < n3; ++i) {
+    out.x0[i] = d.x0 ? d.x0[i] : d.rest_xyz[i];
+    out.v0[i] = d.v0 ? d.v0[i] : 0.0;
+    if (!std::isfinite(out.x0[i]) || !std::isfinite(out.v0[i])) {
+      err = "non-finite initial state";
+      qnsim_destroy(c);
+      return QNSIM_E_NONFINITE;
+    }
+  }
+  out.c = c;
+  out.est_bytes = estimate_bytes(c, p->opt.history);
+  return QNSIM_OK;
+}
+
+void free_group(PoolGroup& g) {
+  if (g.xs) (void)hipFree(g.xs);
+  if (g.vs) (void)hipFree(g.vs);
+  g.xs = g.vs = nullptr;
+  dev_free(g.D);
+}
+
+// Uploads the members (pool ids) as one group; returns 0 or an error code.
+int build_group(qnsim_pool* p, const std::vector<int>& ids, std::unique_ptr<PoolGroup>& out,
+                std::string& err) {
+  auto g = std::make_unique<PoolGroup>();
+  std::vector<const qnsim*> cs;
+  int n = 0;
+  for (int id : ids) {
+    cs.push_back(p->sims[id].c);
+    g->cv0.push_back(n);
+    n += p->sims[id].c->n;
+  }
+  int rc = upload_sims(cs, p->opt, p->h, g->D, err);
+  if (rc) { free_group(*g); return rc; }
+  const size_t bytes = 3 * (size_t)n * sizeof(double);
+  if (hipMalloc((void**)&g->xs, bytes) != hipSuccess || hipMalloc((void**)&g->vs, bytes) != hipSuccess) {
+    free_group(*g);
+    err = "state allocation failed";
+    return QNSIM_E_NOMEM;
+  }
+  for (size_t k = 0; k < ids.size(); ++k) {
+    const PoolSim& s = p->sims[ids[k]];
+    const size_t off = 3 * (size_t)g->cv0[k];
+    if (hipMemcpy(g->xs + off, s.x0.data(), s.x0.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(g->vs + off, s.v0.data(), s.v0.size() * 8, hipMemcpyHostToDevice) != hipSuccess) {
+      free_group(*g);
+      err = "state upload failed";
+      return QNSIM_E_DEVICE;
+    }
+  }
+  g->ids = ids;
+  g->live = (int)ids.size();
+  g->bytes = (int64_t)g->D.bytes + 2 * (int64_t)bytes;
+  out = std::move(g);
+  return QNSIM_OK;
+}
+
+// One batched step of the listed members of group g (slots), on its stream.
+// Called without the pool lock; the group is marked busy by the caller.
+int step_group(qnsim_pool* p, PoolGroup& g, const std::vector<int>& slots,
+               std::vector<SimStat>& st, std::string& err) {
+  if (hipSetDevice(p->opt.device) != hipSuccess) { err = "hipSetDevice failed"; return QNSIM_E_DEVICE; }
+  std::vector<int> run(g.D.S, 0);
+  for (int s : slots) run[s] = 1;
+  int rc = dev_set_run(g.D, run.data(), g.D.stream, err);
+  if (rc) return rc;
+  rc = dev_step(g.D, pool_params(p), g.xs, g.vs, nullptr, g.xs, g.vs, g.D.stream, false, err);
+  if (rc) return rc;
+  st.resize(slots.size());
+  for (size_t i = 0; i < slots.size(); ++i) st[i] = g.D.stat_host[slots[i]];
+  return QNSIM_OK;
+}
+
+int resident(const qnsim_pool* p, int id) {
+  return id >= 0 && id < (int)p->sims.size() && !p->sims[id].removed && p->sims[id].group >= 0;
+}
+
+// Request loop of one lane.
+void lane_main(qnsim_pool* p) {
+  (void)hipSetDevice(p->opt.device);
+  std::unique_lock<std::mutex> lk(p->mu);
+  for (;;) {
+    // the group of the oldest queued request that is not stepping
+    int gi = -1;
+    for (const Request& r : p->queue) {
+      const int g = p->sims[r.sim].group;
+      if (g >= 0 && !p->groups[g]->busy) { gi = g; break; }
+    }
+    if (gi < 0) {
+      if (p->stopping && p->queue.empty()) return;
+      p->cv.wait(lk);
+      continue;
+    }
+    PoolGroup& g = *p->groups[gi];
+    std::vector<Request> batch;
+    std::vector<int> slots;
+    std::vector<char> taken(g.ids.size(), 0);
+    for (auto it = p->queue.begin(); it != p->queue.end();) {
+      const int sim = it->sim;
+      if (p->sims[sim].group == gi && !taken[p->sims[sim].slot]) {
+        taken[p->sims[sim].slot] = 1;
+        slots.push_back(p->sims[sim].slot);
+        batch.push_back(*it);
+        it = p->queue.erase(it);
+      } else {
+        ++it;
+      }
+    }
+    g.busy = true;
+    lk.unlock();
+    std::vector<SimStat> st;
+    std::string err;
+    const int rc = step_group(p, g, slots, st, err);
+    const double t_end = now_s();
+    lk.lock();
+    g.busy = false;
+    for (size_t i = 0; i < batch.size(); ++i) {
+      Done d;
+      d.rc = rc;
+      std::memset(&d.st, 0, sizeof(d.st));
+      if (!rc) stats_of(st[i], &d.st);
+      d.latency = t_end - batch[i].t_submit;
+      p->done[batch[i].ticket] = d;
+    }
+    if (rc) p->last_error = err;
+    else { p->steps_done += (int64_t)batch.size(); p->batches_done += 1; }
+    p->cv.notify_all();
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int qnsim_pool_create(const qnsim_options* opts, double h, int64_t budget_bytes,
+                      qnsim_pool_t** out) {
+  if (!out || !(h > 0.0) || !std::isfinite(h) || budget_bytes <= 0) return QNSIM_E_INVALID;
+  qnsim_options o;
+  if (opts) o = *opts;
+  else qnsim_options_default(&o);
+  // a level launch of a group serves every simulation in it, so merging
+  // levels (or a dense top block) would only add bytes
+  o.dense_top = 0;
+  o.level_merge = 0;
+  qnsim_t* probe = nullptr;  // option validation as for a single context
+  int rc = qnsim_create(&o, &probe);
+  if (rc) return rc;
+  qnsim_destroy(probe);
+  qnsim_pool* p = new (std::nothrow) qnsim_pool();
+  if (!p) return QNSIM_E_NOMEM;
+  p->opt = o;
+  p->h = h;
+  p->budget = budget_bytes;
+  *out = p;
+  return QNSIM_OK;
+}
+
+void qnsim_pool_destroy(qnsim_pool_t* p) {
+  if (!p) return;
+  qnsim_pool_serve_stop(p);
+  for (auto& g : p->groups)
+    if (g) free_group(*g);
+  for (PoolSim& s : p->sims)
+    if (s.c) qnsim_destroy(s.c);
+  delete p;
+}
+
+int qnsim_pool_add(qnsim_pool_t* p, int32_t n, const qnsim_mesh_desc* descs, int32_t* ids) {
+  if (!p) return QNSIM_E_INVALID;
+  if (n <= 0 || !descs || !ids) return pfail(p, QNSIM_E_INVALID, "need n > 0 descriptions and ids");
+  std::vector<PoolSim> made(n);
+  std::vector<int> rcs(n, 0);
+  std::vector<std::string> errs(n);
+  {
+    // host analysis in parallel; the dense kernels inside share one thread pool
+    const int nt = std::max(1, std::min<int>(n, std::min(16, (int)std::thread::hardware_concurrency())));
+    std::vector<std::thread> th;
+    std::mutex qm;
+    int next = 0;
+    for (int t = 0; t < nt; ++t)
+      th.emplace_back([&]() {
+        for (;;) {
+          int i;
+          {
+            std::lock_guard<std::mutex> g(qm);
+            i = next++;
+          }
+          if (i >= n) return;
+          try {
+            rcs[i] = analyze_one(p, descs[i], made[i], errs[i]);
+          } catch (const std::bad_alloc&) {
+            rcs[i] = QNSIM_E_NOMEM;
+            errs[i] = "host allocation failed";
+          }
+        }
+      });
+    for (auto& t : th) t.join();
+  }
+  for (int i = 0; i < n; ++i)
+    if (rcs[i]) {
+      for (PoolSim& s : made)
+        if (s.c) qnsim_destroy(s.c);
+      return pfail(p, rcs[i], "simulation " + std::to_string(i) + ": " + errs[i]);
+    }
+  std::lock_guard<std::mutex> lk(p->mu);
+  for (int i = 0; i < n; ++i) {
+    ids[i] = (int)p->sims.size();
+    p->sims.push_back(std::move(made[i]));
+  }
+  return QNSIM_OK;
+}
+
+int qnsim_pool_commit(qnsim_pool_t* p, int32_t max_group_sims, int32_t* n_admitted) {
+  if (!p) return QNSIM_E_INVALID;
+  std::unique_lock<std::mutex> lk(p->mu);
+  std::vector<std::vector<int>> plan;
+  std::vector<int> cur;
+  int64_t room = p->budget - p->used;
+  for (int id = 0; id < (int)p->sims.size(); ++id) {
+    const PoolSim& s = p->sims[id];
+    if (s.removed || s.group >= 0) continue;
+    if (s.est_bytes > room) continue;  // stays staged
+    room -= s.est_bytes;
+    cur.push_back(id);
+    if (max_group_sims > 0 && (int)cur.size() >= max_group_sims) {
+      plan.push_back(cur);
+      cur.clear();
+    }
+  }
+  if (!cur.empty()) plan.push_back(cur);
+  int admitted = 0;
+  for (const std::vector<int>& ids : plan) {
+    std::unique_ptr<PoolGroup> g;
+    std::string err;
+    int rc;
+    try {
+      rc = build_group(p, ids, g, err);
+    } catch (const std::bad_alloc&) {
+      rc = QNSIM_E_NOMEM;
+      err = "host allocation failed";
+    }
+    if (rc) {
+      if (n_admitted) *n_admitted = admitted;
+      return pfail(p, rc, err);
+    }
+    const int gi = (int)p->groups.size();
+    for (size_t k = 0; k < ids.size(); ++k) {
+      PoolSim& s = p->sims[ids[k]];
+      s.group = gi;
+      s.slot = (int)k;
+      std::vector<double>().swap(s.x0);
+      std::vector<double>().swap(s.v0);
+    }
+    p->used += g->bytes;
+    admitted += (int)ids.size();
+    p->groups.push_back(std::move(g));
+  }
+  if (n_admitted) *n_admitted = admitted;
+  p->cv.notify_all();
+  return QNSIM_OK;
+}
+
+int qnsim_pool_remove(qnsim_pool_t* p, int32_t id) {
+  if (!p) return QNSIM_E_INVALID;
+  std::unique_lock<std::mutex> lk(p->mu);
+  if (id < 0 || id >= (int)p->sims.size() || p->sims[id].removed)
+    return pfail(p, QNSIM_E_INVALID, "unknown simulation id");
+  PoolSim& s = p->sims[id];
+  for (const Request& r : p->queue)
+    if (r.sim == id) return pfail(p, QNSIM_E_STATE, "simulation has queued requests");
+  if (s.group >= 0) {
+    PoolGroup& g = *p->groups[s.group];
+    p->cv.wait(lk, [&] { return !g.busy; });
+    if (--g.live == 0) {
+      p->used -= g.bytes;
+      free_group(g);
+    }
+  }
+  s.removed = true;
+  if (s.c) { qnsim_destroy(s.c); s.c = nullptr; }
+  return QNSIM_OK;
+}
+
+int qnsim_pool_step(qnsim_pool_t* p, int32_t n, const int32_t* ids, qnsim_stats* stats) {
+  if (!p) return QNSIM_E_INVALID;
+  if (n < 0 || (n > 0 && !ids)) return pfail(p, QNSIM_E_INVALID, "bad id list");
+  std::unique_lock<std::mutex> lk(p->mu);
+  if (p->serving) return pfail(p, QNSIM_E_STATE, "the request loop is running");
+  std::vector<std::vector<int>> slots(p->groups.size());
+  std::vector<std::vector<int>> where(p->groups.size());  // index into ids
+  std::vector<char> seen(p->sims.size(), 0);
+  for (int i = 0; i < n; ++i) {
+    if (!resident(p, ids[i])) return pfail(p, QNSIM_E_INVALID, "id " + std::to_string(ids[i]) + " is not resident");
+    if (seen[ids[i]]++) return pfail(p, QNSIM_E_INVALID, "repeated id");
+    const PoolSim& s = p->sims[ids[i]];
+    slots[s.group].push_back(s.slot);
+    where[s.group].push_back(i);
+  }
+  std::vector<int> gl;
+  for (int g = 0; g < (int)p->groups.size(); ++g)
+    if (!slots[g].empty()) { gl.push_back(g); p->groups[g]->busy = true; }
+  lk.unlock();
+  std::vector<int> rcs(gl.size(), 0);
+  std::vector<std::string> errs(gl.size());
+  std::vector<std::vector<SimStat>> st(gl.size());
+  if (gl.size() == 1) {
+    rcs[0] = step_group(p, *p->groups[gl[0]], slots[gl[0]], st[0], errs[0]);
+  } else {
+    std::vector<std::thread> th;
+    for (size_t k = 0; k < gl.size(); ++k)
+      th.emplace_back([&, k]() { rcs[k] = step_group(p, *p->groups[gl[k]], slots[gl[k]], st[k], errs[k]); });
+    for (auto& t : th) t.join();
+  }
+  lk.lock();
+  int rc = 0;
+  for (size_t k = 0; k < gl.size(); ++k) {
+    p->groups[gl[k]]->busy = false;
+    if (rcs[k] && !rc) { rc = rcs[k]; p->last_error = errs[k]; }
+    if (!rcs[k] && stats)
+      for (size_t j = 0; j < where[gl[k]].size(); ++j) stats_of(st[k][j], &stats[where[gl[k]][j]]);
+  }
+  if (!rc) { p->steps_done += n; p->batches_done += (int64_t)gl.size(); }
+  p->cv.notify_all();
+  return rc;
+}
+
+static int state_copy(qnsim_pool* p, int id, double* xh, double* vh, const double* xin,
+                      const double* vin) {
+  std::unique_lock<std::mutex> lk(p->mu);
+  if (!resident(p, id)) return pfail(p, QNSIM_E_INVALID, "id is not resident");
+  const PoolSim& s = p->sims[id];
+  PoolGroup& g = *p->groups[s.group];
+  p->cv.wait(lk, [&] { return !g.busy; });
+  const size_t off = 3 * (size_t)g.cv0[s.slot], bytes = 3 * (size_t)s.c->n * sizeof(double);
+  hipStream_t st = (hipStream_t)g.D.stream;
+  hipError_t e = hipSuccess;
+  if (xin) {
+    e = hipMemcpyAsync(g.xs + off, xin, bytes, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(g.vs + off, vin, bytes, hipMemcpyHostToDevice, st);
+  } else {
+    e = hipMemcpyAsync(xh, g.xs + off, bytes, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(vh, g.vs + off, bytes, hipMemcpyDeviceToHost, st);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return pfail(p, QNSIM_E_DEVICE, hipGetErrorString(e));
+  return QNSIM_OK;
+}
+
+int qnsim_pool_get_state(qnsim_pool_t* p, int32_t id, double* x, double* v) {
+  if (!p || !x || !v) return QNSIM_E_INVALID;
+  return state_copy(p, id, x, v, nullptr, nullptr);
+}
+
+int qnsim_pool_set_state(qnsim_pool_t* p, int32_t id, const double* x, const double* v) {
+  if (!p || !x || !v) return QNSIM_E_INVALID;
+  {
+    std::lock_guard<std::mutex> lk(p->mu);
+    if (!resident(p, id)) return pfail(p, QNSIM_E_INVALID, "id is not resident");
+    const size_t n3 = 3 * (size_t)p->sims[id].c->n;
+    for (size_t i = 0; i < n3; ++i)
+      if (!std::isfinite(x[i]) || !std::isfinite(v[i])) return pfail(p, QNSIM_E_NONFINITE, "non-finite state");
+  }
+  return state_copy(p, id, nullptr, nullptr, x, v);
+}
+
+int qnsim_pool_serve_start(qnsim_pool_t* p, int32_t lanes) {
+  if (!p) return QNSIM_E_INVALID;
+  if (lanes < 1 || lanes > 8) return pfail(p, QNSIM_E_INVALID, "lanes must be 1..8");
+  std::lock_guard<std::mutex> lk(p->mu);
+  if (p->serving) return pfail(p, QNSIM_E_STATE, "the request loop is already running");
+  for (auto& g : p->groups)
+    if (g->busy) return pfail(p, QNSIM_E_STATE, "a step is running");
+  p->serving = true;
+  p->stopping = false;
+  for (int i = 0; i < lanes; ++i) p->lanes.emplace_back(lane_main, p);
+  return QNSIM_OK;
+}
+
+int qnsim_pool_submit(qnsim_pool_t* p, int32_t id, int64_t* ticket) {
+  if (!p || !ticket) return QNSIM_E_INVALID;
+  std::lock_guard<std::mutex> lk(p->mu);
+  if (!p->serving || p->stopping) return pfail(p, QNSIM_E_STATE, "the request loop is not running");
+  if (!resident(p, id)) return pfail(p, QNSIM_E_INVALID, "id is not resident");
+  const int64_t t = p->next_ticket++;
+  p->queue.push_back(Request{t, id, now_s()});
+  *ticket = t;
+  p->cv.notify_all();
+  return QNSIM_OK;
+}
+
+int qnsim_pool_wait(qnsim_pool_t* p, int64_t ticket, double timeout_s, qnsim_stats* stats,
+                    double* latency_s) {
+  if (!p) return QNSIM_E_INVALID;
+  std::unique_lock<std::mutex> lk(p->mu);
+  if (ticket <= 0 || ticket >= p->next_ticket) return pfail(p, QNSIM_E_STATE, "unknown ticket");
+  auto ready = [&] { return p->done.count(ticket) > 0; };
+  if (timeout_s < 0) {
+    p->cv.wait(lk, [&] { return ready() || (!p->serving && p->queue.empty()); });
+  } else {
+    p->cv.wait_for(lk, std::chrono::duration<double>(timeout_s), ready);
+  }
+  auto it = p->done.find(ticket);
+  if (it == p->done.end()) return pfail(p, QNSIM_E_STATE, "request not done (time-out or unknown ticket)");
+  const Done d = it->second;
+  p->done.erase(it);
+  if (d.rc) return d.rc;
+  if (stats) *stats = d.st;
+  if (latency_s) *latency_s = d.latency;
+  return QNSIM_OK;
+}
+
+int qnsim_pool_serve_stop(qnsim_pool_t* p) {
+  if (!p) return QNSIM_E_INVALID;
+  std::vector<std::thread> lanes;
+  {
+    std::lock_guard<std::mutex> lk(p->mu);
+    if (!p->serving) return QNSIM_OK;
+    p->stopping = true;
+    lanes.swap(p->lanes);
+    p->cv.notify_all();
+  }
+  for (auto& t : lanes) t.join();
+  std::lock_guard<std::mutex> lk(p->mu);
+  p->serving = false;
+  p->stopping = false;
+  p->cv.notify_all();
+  return QNSIM_OK;
+}
+
+int qnsim_pool_get_info(qnsim_pool_t* p, qnsim_pool_info* info) {
+  if (!p || !info) return QNSIM_E_INVALID;
+  std::lock_guard<std::mutex> lk(p->mu);
+  std::memset(info, 0, sizeof(*info));
+  for (const PoolSim& s : p->sims) {
+    if (s.removed) continue;
+    if (s.group >= 0) info->sims_resident++;
+    else info->sims_staged++;
+  }
+  for (auto& g : p->groups)
+    if (g->live > 0) info->groups++;
+  info->serving = p->serving ? 1 : 0;
+  info->budget_bytes = p->budget;
+  info->used_bytes = p->used;
+  info->steps_done = p->steps_done;
+  info->batches_done = p->batches_done;
+  return QNSIM_OK;
+}
+
+const char* qnsim_pool_last_error(const qnsim_pool_t* p) { return p ? p->last_error.c_str() : ""; }
+
+}  // extern "C"

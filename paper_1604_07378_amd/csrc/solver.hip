@@ -945,7 +945,7 @@ void launch_direction(DeviceMesh& D, const StepParams& P, hipStream_t st, int cy
                      D.Tv, D.q, D.ctl)
   QN_SLOTS_DISPATCH(slv, QN_QFORM)
 #undef QN_QFORM
-  launch_solve(D, st, D.q, D.r, D.dir_count);
+  launch_solve(D, st, D.q, D.r, D.dir_count, D.S > 1 ? D.ctl : nullptr);
 #define QN_RDOTS(SL)                                                                           \
   hipLaunchKernelGGL(k_rdots<SL>, dim3(D.rdots_blocks), dim3(kWideBS), 0, st, D.rblk, n3,       \
                      slots, D.r, D.G, D.Tv, pp.rdots, D.ctl)

@@ -217,12 +217,14 @@ __device__ __forceinline__ void fwd_item(const ItemDesc& d, const double* __rest
 __global__ void __launch_bounds__(TS, 4)
 k_solve_fwd(const ItemDesc* __restrict__ items, const double* __restrict__ Bf,
             const int* __restrict__ rel, const double* __restrict__ q, double* __restrict__ z,
-            double* __restrict__ vp, const int* __restrict__ gate) {
+            double* __restrict__ vp, const int* __restrict__ gate,
+            const Ctl* __restrict__ sim_ctl) {
   static_assert(kMaxItemRows == TS, "one staged row per thread");
   __shared__ double s0[TCHUNK], s1[TCHUNK], s2[TCHUNK], sp[3 * kMaxItemRows];
   __shared__ int srel[kMaxItemRows];
   if (gate && *gate <= 0) return;
   const ItemDesc d = items[blockIdx.x];
+  if (sim_ctl && sim_ctl[d.sim].phase != PH_DIR) return;
   fwd_item(d, Bf, rel, q, z, vp, s0, s1, s2, sp, srel);
 }
 
@@ -331,10 +333,11 @@ __device__ __forceinline__ void bwd_item(const ItemDesc& d, const double* __rest
 __global__ void __launch_bounds__(TS)
 k_solve_bwd(const ItemDesc* __restrict__ items, const double* __restrict__ Bb,
             const int* __restrict__ rows, const double* __restrict__ z, double* __restrict__ w,
-            const int* __restrict__ gate) {
+            const int* __restrict__ gate, const Ctl* __restrict__ sim_ctl) {
   __shared__ double s0[TCHUNK], s1[TCHUNK], s2[TCHUNK];
   if (gate && *gate <= 0) return;
   const ItemDesc d = items[blockIdx.x];
+  if (sim_ctl && sim_ctl[d.sim].phase != PH_DIR) return;
   bwd_item(d, Bb, rows, z, w, s0, s1, s2);
 }
 
@@ -590,7 +593,7 @@ __global__ void __launch_bounds__(kSubThreads)
 k_solve_fwd_sub(const ItemDesc* __restrict__ items, const int* __restrict__ ptr, int nl,
                 const double* __restrict__ Bf, const int* __restrict__ rel,
                 const double* __restrict__ q, double* __restrict__ z, double* __restrict__ vp,
-                const int* __restrict__ gate) {
+                const int* __restrict__ gate, const Ctl* __restrict__ sim_ctl) {
   __shared__ double stage[kSubWaves][3 * kSubCap];
   if (gate && *gate <= 0) return;
   const int lane = threadIdx.x & 63;
@@ -600,6 +603,7 @@ k_solve_fwd_sub(const ItemDesc* __restrict__ items, const int* __restrict__ ptr,
     if (l > 0) __syncthreads();
     for (int i = p[l] + wv; i < p[l + 1]; i += kSubWaves) {
       const ItemDesc d = items[i];
+      if (sim_ctl && sim_ctl[d.sim].phase != PH_DIR) continue;
       fwd_wave_item(d, Bf, rel, q, z, vp, stage[wv], lane);
     }
   }
@@ -610,7 +614,7 @@ __global__ void __launch_bounds__(kSubThreads)
 k_solve_bwd_sub(const ItemDesc* __restrict__ items, const int* __restrict__ ptr, int nl,
                 const double* __restrict__ Bb, const int* __restrict__ rows,
                 const double* __restrict__ z, double* __restrict__ w,
-                const int* __restrict__ gate) {
+                const int* __restrict__ gate, const Ctl* __restrict__ sim_ctl) {
   __shared__ double stage[kSubWaves][3 * kSubCap];
   if (gate && *gate <= 0) return;
   const int lane = threadIdx.x & 63;
@@ -620,6 +624,7 @@ k_solve_bwd_sub(const ItemDesc* __restrict__ items, const int* __restrict__ ptr,
     if (l < nl - 1) __syncthreads();
     for (int i = p[l] + wv; i < p[l + 1]; i += kSubWaves) {
       const ItemDesc d = items[i];
+      if (sim_ctl && sim_ctl[d.sim].phase != PH_DIR) continue;
       bwd_wave_item(d, Bb, rows, z, w, stage[wv], lane);
     }
   }
@@ -712,16 +717,17 @@ k_top_gemv(const double* __restrict__ Sinv, const double* __restrict__ t, int n,
   }
 }
 
-void launch_solve(DeviceMesh& D, hipStream_t st, const double* q, double* r, const int* gate) {
+void launch_solve(DeviceMesh& D, hipStream_t st, const double* q, double* r, const int* gate,
+                  const Ctl* sim_ctl) {
   const int L = (int)D.levels.size();
   if (D.sub_tasks > 0)
     hipLaunchKernelGGL(k_solve_fwd_sub, dim3(D.sub_tasks), dim3(kSubThreads), 0, st, D.sub_fw,
-                       D.sub_fw_ptr, D.sub_levels, D.Bf, D.rel, q, D.z, D.vp, gate);
+                       D.sub_fw_ptr, D.sub_levels, D.Bf, D.rel, q, D.z, D.vp, gate, sim_ctl);
   for (int l = D.sub_levels; l < L; ++l) {
     const int n = D.levels[l].fw_end - D.levels[l].fw_begin;
     if (n > 0)
       hipLaunchKernelGGL(k_solve_fwd, dim3(n), dim3(TS), 0, st, D.items + D.levels[l].fw_begin,
-                         D.Bf, D.rel, q, D.z, D.vp, gate);
+                         D.Bf, D.rel, q, D.z, D.vp, gate, sim_ctl);
   }
   if (D.top_n > 0) {
     const int n = D.top_n, n3 = 3 * n;
@@ -735,11 +741,11 @@ void launch_solve(DeviceMesh& D, hipStream_t st, const double* q, double* r, con
     const int n = D.levels[l].bw_end - D.levels[l].bw_begin;
     if (n > 0)
       hipLaunchKernelGGL(k_solve_bwd, dim3(n), dim3(TS), 0, st, D.items + D.levels[l].bw_begin,
-                         D.Bb, D.rows, D.z, r, gate);
+                         D.Bb, D.rows, D.z, r, gate, sim_ctl);
   }
   if (D.sub_tasks > 0)
     hipLaunchKernelGGL(k_solve_bwd_sub, dim3(D.sub_tasks), dim3(kSubThreads), 0, st, D.sub_bw,
-                       D.sub_bw_ptr, D.sub_levels, D.Bb, D.rows, D.z, r, gate);
+                       D.sub_bw_ptr, D.sub_levels, D.Bb, D.rows, D.z, r, gate, sim_ctl);
 }
 
 }  // namespace qn

@@ -486,7 +486,7 @@ int upload_sims(const std::vector<const qnsim*>& sims, const qnsim_options& opt,
       const SnInfo& I = sinfo[it.x & 0x7fffffff];
       ItemDesc& d = out[i];
       d.begin = it.y; d.end = it.z; d.L = it.w; d.nchild = I.nchild;
-      d.first = I.first; d.ncol = I.ncol; d.nbelow = I.nbelow; d.pad = 0;
+      d.first = I.first; d.ncol = I.ncol; d.nbelow = I.nbelow; d.sim = vsim[I.first];
       d.blk = bwd ? I.bw_off : I.fw_off;
       d.rows_off = I.rows_off; d.vp_in = I.vp_in; d.vp_out = I.vp_out;
     }

@@ -25,7 +25,7 @@ ERRORS = {
     -1: "QNSIM_E_INVALID", -2: "QNSIM_E_NONFINITE", -3: "QNSIM_E_DEGENERATE",
     -4: "QNSIM_E_INVERTED", -5: "QNSIM_E_STIFFNESS", -6: "QNSIM_E_NOT_SPD",
     -7: "QNSIM_E_H_MISMATCH", -8: "QNSIM_E_STATE", -9: "QNSIM_E_NOMEM",
-    -10: "QNSIM_E_DEVICE",
+    -10: "QNSIM_E_DEVICE", -11: "QNSIM_E_BUDGET",
 }
 
 
@@ -74,6 +74,24 @@ class FactorInfo(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
 
 
+class MeshDesc(ctypes.Structure):
+    _fields_ = [("n_verts", ctypes.c_int32), ("rest_xyz", ctypes.c_void_p),
+                ("n_tets", ctypes.c_int32), ("tets", ctypes.c_void_p),
+                ("n_pinned", ctypes.c_int32), ("pinned", ctypes.c_void_p),
+                ("n_mat", ctypes.c_int32), ("mats", ctypes.c_void_p),
+                ("tet_mat", ctypes.c_void_p), ("x0", ctypes.c_void_p), ("v0", ctypes.c_void_p)]
+
+
+class PoolInfo(ctypes.Structure):
+    _fields_ = [("sims_staged", ctypes.c_int32), ("sims_resident", ctypes.c_int32),
+                ("groups", ctypes.c_int32), ("serving", ctypes.c_int32),
+                ("budget_bytes", ctypes.c_int64), ("used_bytes", ctypes.c_int64),
+                ("steps_done", ctypes.c_int64), ("batches_done", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _P = ctypes.c_void_p
 _D = ctypes.c_double
 _I = ctypes.c_int32
@@ -102,6 +120,22 @@ SIGNATURES = {
     "qnsim_time_kernel": (ctypes.c_int, [_P, _I, _I, ctypes.POINTER(_D)]),
     "qnsim_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "qnsim_last_error": (ctypes.c_char_p, [_P]),
+    "qnsim_pool_create": (ctypes.c_int, [ctypes.POINTER(Options), _D, ctypes.c_int64,
+                                         ctypes.POINTER(_P)]),
+    "qnsim_pool_destroy": (None, [_P]),
+    "qnsim_pool_add": (ctypes.c_int, [_P, _I, ctypes.POINTER(MeshDesc), _P]),
+    "qnsim_pool_commit": (ctypes.c_int, [_P, _I, ctypes.POINTER(_I)]),
+    "qnsim_pool_remove": (ctypes.c_int, [_P, _I]),
+    "qnsim_pool_step": (ctypes.c_int, [_P, _I, _P, ctypes.POINTER(Stats)]),
+    "qnsim_pool_get_state": (ctypes.c_int, [_P, _I, _P, _P]),
+    "qnsim_pool_set_state": (ctypes.c_int, [_P, _I, _P, _P]),
+    "qnsim_pool_serve_start": (ctypes.c_int, [_P, _I]),
+    "qnsim_pool_submit": (ctypes.c_int, [_P, _I, ctypes.POINTER(ctypes.c_int64)]),
+    "qnsim_pool_wait": (ctypes.c_int, [_P, ctypes.c_int64, _D, ctypes.POINTER(Stats),
+                                       ctypes.POINTER(_D)]),
+    "qnsim_pool_serve_stop": (ctypes.c_int, [_P]),
+    "qnsim_pool_get_info": (ctypes.c_int, [_P, ctypes.POINTER(PoolInfo)]),
+    "qnsim_pool_last_error": (ctypes.c_char_p, [_P]),
 }
 
 _lib = None
@@ -156,20 +190,40 @@ def _stream_ptr(stream):
     return getattr(stream, "cuda_stream", stream)
 
 
+def _material_array(materials: Sequence):
+    arr = (MaterialC * len(materials))()
+    for i, m in enumerate(materials):
+        get = (lambda k: m[k]) if isinstance(m, dict) else (lambda k: getattr(m, k))
+        arr[i].type = int(get("type"))
+        arr[i].mu = float(get("mu"))
+        arr[i].lambda_ = float(get("lam"))
+        arr[i].density = float(get("density"))
+        d2 = get("spline_d2") if not isinstance(m, dict) else m.get("spline_d2")
+        if d2 is not None:
+            for j, val in enumerate(np.asarray(d2, dtype=np.float64)):
+                arr[i].spline_d2[j] = float(val)
+    return arr
+
+
+def _options_with(options: Optional[Options], overrides: dict) -> Options:
+    o = options if options is not None else default_options()
+    known = {f for f, _ in Options._fields_}
+    for k, v in overrides.items():
+        if k not in known:
+            raise TypeError(f"unknown solver option {k!r}")
+        if k == "gravity":
+            o.gravity = (ctypes.c_double * 3)(*v)
+        else:
+            setattr(o, k, v)
+    return o
+
+
 class Sim:
     """One simulated mesh (a qnsim_t context)."""
 
     def __init__(self, options: Optional[Options] = None, **overrides):
         self._lib = load_library()
-        o = options if options is not None else default_options()
-        known = {f for f, _ in Options._fields_}
-        for k, v in overrides.items():
-            if k not in known:
-                raise TypeError(f"unknown solver option {k!r}")
-            if k == "gravity":
-                o.gravity = (ctypes.c_double * 3)(*v)
-            else:
-                setattr(o, k, v)
+        o = _options_with(options, overrides)
         self.options = o
         h = ctypes.c_void_p()
         self._check(self._lib.qnsim_create(ctypes.byref(o), ctypes.byref(h)), None)
@@ -206,17 +260,7 @@ class Sim:
         self._check(self._lib.qnsim_set_pinned(self._h, idx.size, _ptr(idx) if idx.size else None))
 
     def set_materials(self, materials: Sequence, tet_mat=None):
-        arr = (MaterialC * len(materials))()
-        for i, m in enumerate(materials):
-            get = (lambda k: m[k]) if isinstance(m, dict) else (lambda k: getattr(m, k))
-            arr[i].type = int(get("type"))
-            arr[i].mu = float(get("mu"))
-            arr[i].lambda_ = float(get("lam"))
-            arr[i].density = float(get("density"))
-            d2 = get("spline_d2") if not isinstance(m, dict) else m.get("spline_d2")
-            if d2 is not None:
-                for j, val in enumerate(np.asarray(d2, dtype=np.float64)):
-                    arr[i].spline_d2[j] = float(val)
+        arr = _material_array(materials)
         tm = None
         if tet_mat is not None:
             tm = np.ascontiguousarray(tet_mat, dtype=np.int32)
@@ -329,3 +373,126 @@ def sim_from_workload(w, options: Optional[Options] = None, prepare: bool = True
     else:
         s.analyze(w.h)
     return s
+
+
+def _materials_of(w):
+    return [dict(type=m.type, mu=m.mu, lam=m.lam, density=m.density,
+                 spline_d2=m.d2() if hasattr(m, "d2") else None) for m in w.materials]
+
+
+class Pool:
+    """Resident simulations on one GPU (a qnsim_pool_t): batched steps of any
+    subset, and the request loop that serves step requests."""
+
+    def __init__(self, h: float, budget_bytes: int, options: Optional[Options] = None,
+                 **overrides):
+        self._lib = load_library()
+        o = _options_with(options, overrides)
+        self.options = o
+        self.h = float(h)
+        p = ctypes.c_void_p()
+        self._p = None
+        rc = self._lib.qnsim_pool_create(ctypes.byref(o), self.h, int(budget_bytes), ctypes.byref(p))
+        if rc != 0:
+            raise QnsimError(rc, self._lib.qnsim_strerror(rc).decode())
+        self._p = p
+        self.nverts = {}
+
+    def close(self):
+        if getattr(self, "_p", None):
+            self._lib.qnsim_pool_destroy(self._p)
+            self._p = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc != 0:
+            msg = self._lib.qnsim_pool_last_error(self._p).decode() if self._p else ""
+            raise QnsimError(rc, msg or self._lib.qnsim_strerror(rc).decode())
+
+    def add(self, meshes: Sequence[dict]) -> list:
+        """meshes: dicts with rest, tets, pinned, materials, tet_mat and
+        optional x0, v0. Returns the new ids (staged)."""
+        n = len(meshes)
+        descs = (MeshDesc * n)()
+        keep = []
+        for i, m in enumerate(meshes):
+            rest = _f64(m["rest"])
+            tets = np.ascontiguousarray(m["tets"], dtype=np.int32)
+            pinned = np.ascontiguousarray(m.get("pinned", np.zeros(0)), dtype=np.int32)
+            mats = _material_array(m["materials"])
+            tm = m.get("tet_mat")
+            tm = np.ascontiguousarray(tm, dtype=np.int32) if tm is not None else None
+            x0 = _f64(m["x0"], rest.shape) if m.get("x0") is not None else None
+            v0 = _f64(m["v0"], rest.shape) if m.get("v0") is not None else None
+            keep += [rest, tets, pinned, mats, tm, x0, v0]
+            d = descs[i]
+            d.n_verts, d.rest_xyz = rest.shape[0], rest.ctypes.data
+            d.n_tets, d.tets = tets.shape[0], tets.ctypes.data
+            d.n_pinned, d.pinned = pinned.size, (pinned.ctypes.data if pinned.size else None)
+            d.n_mat, d.mats = len(m["materials"]), ctypes.addressof(mats)
+            d.tet_mat = tm.ctypes.data if tm is not None else None
+            d.x0 = x0.ctypes.data if x0 is not None else None
+            d.v0 = v0.ctypes.data if v0 is not None else None
+        ids = np.zeros(n, dtype=np.int32)
+        self._check(self._lib.qnsim_pool_add(self._p, n, descs, _ptr(ids)))
+        for i, m in enumerate(meshes):
+            self.nverts[int(ids[i])] = int(np.asarray(m["rest"]).shape[0])
+        return [int(i) for i in ids]
+
+    def add_workloads(self, ws: Sequence) -> list:
+        return self.add([dict(rest=w.rest, tets=w.tets, pinned=w.pinned,
+                              materials=_materials_of(w), tet_mat=w.tet_mat,
+                              x0=w.x0, v0=w.v0) for w in ws])
+
+    def commit(self, max_group_sims: int = 0) -> int:
+        n = ctypes.c_int32()
+        self._check(self._lib.qnsim_pool_commit(self._p, int(max_group_sims), ctypes.byref(n)))
+        return n.value
+
+    def remove(self, sim_id: int):
+        self._check(self._lib.qnsim_pool_remove(self._p, int(sim_id)))
+
+    def step(self, ids: Sequence[int]) -> list:
+        ids = np.ascontiguousarray(ids, dtype=np.int32)
+        st = (Stats * max(1, ids.size))()
+        self._check(self._lib.qnsim_pool_step(self._p, ids.size, _ptr(ids), st))
+        return [st[i].as_dict() for i in range(ids.size)]
+
+    def get_state(self, sim_id: int):
+        n = self.nverts[int(sim_id)]
+        x = np.zeros((n, 3)); v = np.zeros((n, 3))
+        self._check(self._lib.qnsim_pool_get_state(self._p, int(sim_id), _ptr(x), _ptr(v)))
+        return x, v
+
+    def set_state(self, sim_id: int, x, v):
+        n = self.nverts[int(sim_id)]
+        x = _f64(x, (n, 3)); v = _f64(v, (n, 3))
+        self._check(self._lib.qnsim_pool_set_state(self._p, int(sim_id), _ptr(x), _ptr(v)))
+
+    def serve_start(self, lanes: int = 2):
+        self._check(self._lib.qnsim_pool_serve_start(self._p, int(lanes)))
+
+    def submit(self, sim_id: int) -> int:
+        t = ctypes.c_int64()
+        self._check(self._lib.qnsim_pool_submit(self._p, int(sim_id), ctypes.byref(t)))
+        return t.value
+
+    def wait(self, ticket: int, timeout_s: float = -1.0):
+        st = Stats()
+        lat = ctypes.c_double()
+        self._check(self._lib.qnsim_pool_wait(self._p, int(ticket), float(timeout_s),
+                                              ctypes.byref(st), ctypes.byref(lat)))
+        return st.as_dict(), lat.value
+
+    def serve_stop(self):
+        self._check(self._lib.qnsim_pool_serve_stop(self._p))
+
+    def info(self) -> dict:
+        i = PoolInfo()
+        self._check(self._lib.qnsim_pool_get_info(self._p, ctypes.byref(i)))
+        return i.as_dict()

@@ -1,0 +1,202 @@
+"""GPU: pools of resident simulations (batched and served steps).
+
+A simulation stepped in a group (one concatenated device mesh, every phase
+one launch over all stepping simulations) must give the result it gives
+alone, with the same options (pools use dense_top = 0 and level_merge = 0):
+bit for bit when the
+group's element kernel is the same instantiation as the one alone (every
+simulation of one material type), within 1e-12 (displacement-normalised)
+otherwise. Small cases are also checked against the FP64 oracle (1e-9).
+"""
+import threading
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+torch = pytest.importorskip("torch")
+from paper_1604_07378_amd import qnsim  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def _eps(x, ref, rest):
+    return np.linalg.norm(x - ref) / max(np.linalg.norm(ref - rest), 1e-300)
+
+
+def _alone(w, steps, **opt):
+    """States after each of `steps` steps of w run alone (pool options)."""
+    s = qnsim.sim_from_workload(w, dense_top=0, level_merge=0, **opt)
+    x, v = w.x0.copy(), w.v0.copy()
+    out = []
+    for _ in range(steps):
+        x, v, _ = s.step(x, v, w.h)
+        out.append((x.copy(), v.copy()))
+    s.close()
+    return out
+
+
+def _pool(ws, budget=1 << 34, group=0, **opt):
+    p = qnsim.Pool(ws[0].h, budget, gravity=tuple(ws[0].gravity), **opt)
+    ids = p.add_workloads(ws)
+    assert p.commit(group) == len(ws)
+    return p, ids
+
+
+def test_batch_equals_alone_one_material():
+    """Eight Neo-Hookean blocks of uneven size in one group, 12 steps."""
+    ws = [W.workload_block(W.NEOHOOKEAN, dims=d, prestretch_seed=i)
+          for i, d in enumerate([(3, 3, 3), (5, 3, 4), (4, 6, 3), (3, 3, 8),
+                                 (6, 5, 4), (2, 7, 3), (4, 4, 4), (7, 3, 5)])]
+    p, ids = _pool(ws)
+    assert p.info()["groups"] == 1
+    steps = 12
+    ref = [_alone(w, steps) for w in ws]
+    for k in range(steps):
+        st = p.step(ids)
+        assert all(s["iterations_run"] == 10 for s in st)
+        for j, w in enumerate(ws):
+            x, v = p.get_state(ids[j])
+            assert np.array_equal(x, ref[j][k][0]), f"sim {j} step {k}: not bitwise equal"
+            assert np.array_equal(v, ref[j][k][1])
+    print(f"8 NH blocks, {steps} batched steps: bitwise equal to each block alone", flush=True)
+    p.close()
+
+
+def test_batch_mixed_materials_against_alone_and_oracle():
+    """Blocks with NH / StVK / spline materials and per-block nu (the batched
+    workload's generator at small sizes), 6 steps: each equals its run alone;
+    the first two also match the oracle."""
+    ws = W.workload_batch(count=6, seed=3, lo=3, hi=6)
+    p, ids = _pool(ws)
+    steps = 6
+    ref = [_alone(w, steps) for w in ws]
+    worst = 0.0
+    for k in range(steps):
+        p.step(ids)
+        for j, w in enumerate(ws):
+            x, _ = p.get_state(ids[j])
+            e = _eps(x, ref[j][k][0], w.rest)
+            worst = max(worst, e)
+            assert e <= 1e-12, f"sim {j} step {k}: eps vs alone {e:.3e}"
+    for j in range(2):
+        w = ws[j]
+        m = oracle.build_model(w.rest, w.tets, w.pinned, w.materials, w.tet_mat, w.h, w.gravity)
+        x, v = w.x0.copy(), w.v0.copy()
+        for k in range(steps):
+            r = oracle.step(m, x, v)
+            x, v = r.x, r.v
+            e = _eps(ref[j][k][0], r.x, w.rest)
+            assert e <= 1e-9, f"sim {j} step {k}: eps vs oracle {e:.3e}"
+    print(f"mixed-material batch: max eps vs alone {worst:.3e}", flush=True)
+    p.close()
+
+
+def test_subsets_and_groups():
+    """Four groups of two; alternating subsets step; the others keep their state."""
+    ws = [W.workload_block(W.STVK, dims=(3 + i % 3, 3, 4), prestretch_seed=10 + i) for i in range(8)]
+    p, ids = _pool(ws, group=2)
+    assert p.info()["groups"] == 4
+    counts = [0] * 8
+    ref = [_alone(w, 5) for w in ws]
+    for rnd in range(6):
+        sub = [ids[j] for j in range(8) if (j + rnd) % 3 != 0]
+        before = {j: p.get_state(ids[j]) for j in range(8)}
+        p.step(sub)
+        for j in range(8):
+            x, v = p.get_state(ids[j])
+            if ids[j] in sub:
+                counts[j] += 1
+                if counts[j] <= 5:
+                    assert np.array_equal(x, ref[j][counts[j] - 1][0]), f"sim {j} after {counts[j]} steps"
+            else:
+                assert np.array_equal(x, before[j][0]) and np.array_equal(v, before[j][1])
+    info = p.info()
+    assert info["steps_done"] == sum(counts)
+    p.close()
+
+
+def test_mixed_precision_pool_equals_alone():
+    ws = [W.workload_block(W.NEOHOOKEAN, dims=(4, 3, 3), prestretch_seed=i) for i in range(3)]
+    p, ids = _pool(ws, precision=qnsim.QNSIM_MIXED)
+    ref = [_alone(w, 4, precision=qnsim.QNSIM_MIXED) for w in ws]
+    for k in range(4):
+        p.step(ids)
+        for j in range(3):
+            assert np.array_equal(p.get_state(ids[j])[0], ref[j][k][0])
+    p.close()
+
+
+def test_budget_admission_and_remove():
+    ws = [W.workload_block(W.NEOHOOKEAN, dims=(4, 4, 4), prestretch_seed=i) for i in range(6)]
+    probe = qnsim.Pool(ws[0].h, 1 << 34)
+    probe.add_workloads(ws[:1])
+    probe.commit(0)
+    one = probe.info()["used_bytes"]
+    probe.close()
+    p = qnsim.Pool(ws[0].h, int(3.5 * one))
+    ids = p.add_workloads(ws)
+    admitted = p.commit(1)
+    info = p.info()
+    assert 1 <= admitted < 6 and info["sims_resident"] == admitted
+    assert info["sims_staged"] == 6 - admitted and info["used_bytes"] <= info["budget_bytes"]
+    with pytest.raises(qnsim.QnsimError):
+        p.step([ids[-1]])                      # staged, not resident
+    p.remove(ids[0])                           # frees its one-simulation group
+    assert p.info()["used_bytes"] < info["used_bytes"]
+    more = p.commit(1)
+    assert more >= 1 and p.info()["sims_resident"] == admitted - 1 + more
+    p.close()
+
+
+def test_serving_results_equal_alone():
+    """Requests from four client threads with random pacing over six
+    simulations in three groups (two materials each); each simulation's final
+    state equals its run alone with the same number of steps."""
+    ws = [W.workload_block([W.NEOHOOKEAN, W.STVK, W.SPLINE][i % 3], dims=(3, 4, 3),
+                           prestretch_seed=20 + i) for i in range(6)]
+    p, ids = _pool(ws, group=2)
+    p.serve_start(lanes=2)
+    rng = np.random.default_rng(5)
+    plan = [list(rng.integers(0, 6, size=8)) for _ in range(4)]
+    lat = []
+    lock = threading.Lock()
+
+    def client(seq, seed):
+        r = np.random.default_rng(seed)
+        tickets = []
+        for j in seq:
+            tickets.append(p.submit(ids[int(j)]))
+            if r.uniform() < 0.5:
+                import time
+                time.sleep(r.uniform(0, 0.003))
+        for t in tickets:
+            st, l = p.wait(t, 60.0)
+            assert st["iterations_run"] == 10
+            with lock:
+                lat.append(l)
+
+    th = [threading.Thread(target=client, args=(plan[i], i)) for i in range(4)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    p.serve_stop()
+    counts = np.bincount(np.concatenate(plan).astype(int), minlength=6)
+    assert len(lat) == counts.sum() and min(lat) > 0
+    worst = 0.0
+    for j, w in enumerate(ws):
+        if counts[j] == 0:
+            continue
+        ref = _alone(w, int(counts[j]))
+        x, _ = p.get_state(ids[j])
+        e = _eps(x, ref[-1][0], w.rest)   # groups mix materials: rounding-level differences
+        worst = max(worst, e)
+        assert e <= 1e-12, f"sim {j}: served result differs from alone, eps {e:.3e}"
+    info = p.info()
+    assert info["steps_done"] == counts.sum() and info["batches_done"] <= counts.sum()
+    print(f"served {counts.sum()} requests in {info['batches_done']} batches; "
+          f"latency p50 {np.median(lat) * 1e3:.2f} ms; max eps vs alone {worst:.3e}", flush=True)
+    p.close()

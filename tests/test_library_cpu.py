@@ -143,3 +143,56 @@ def test_solve_schedule_self_check_passes_on_host(w, sched):
     with pytest.raises(qnsim.QnsimError) as e:
         s.prepare(w.h)
     assert "hipSetDevice" in str(e.value), str(e.value)
+
+
+def _mesh_dict(w):
+    return dict(rest=w.rest, tets=w.tets, pinned=w.pinned, tet_mat=w.tet_mat,
+                materials=[dict(type=m.type, mu=m.mu, lam=m.lam, density=m.density,
+                                spline_d2=m.d2()) for m in w.materials])
+
+
+def test_pool_staging_and_validation_on_host():
+    """Pool host side: parallel analysis stages simulations; an invalid
+    description stages nothing; stepping or serving needs resident ones."""
+    ws = W.workload_batch(count=5, seed=1, lo=3, hi=6)
+    with pytest.raises(qnsim.QnsimError) as e:
+        qnsim.Pool(ws[0].h, 0)
+    assert e.value.code == -1
+    p = qnsim.Pool(ws[0].h, 1 << 30)
+    ids = p.add_workloads(ws)
+    assert ids == list(range(5))
+    info = p.info()
+    assert (info["sims_staged"], info["sims_resident"], info["groups"]) == (5, 0, 0)
+    bad = _mesh_dict(ws[0])
+    bad["tets"] = ws[0].tets.copy()
+    bad["tets"][3, 1] = ws[0].rest.shape[0]
+    with pytest.raises(qnsim.QnsimError) as e:
+        p.add([_mesh_dict(ws[1]), bad])
+    assert e.value.code == -1 and "simulation 1" in str(e.value)
+    assert p.info()["sims_staged"] == 5
+    with pytest.raises(qnsim.QnsimError) as e:
+        p.step([ids[0]])
+    assert e.value.code == -1
+    with pytest.raises(qnsim.QnsimError) as e:
+        p.submit(ids[0])
+    assert e.value.code == -8
+    p.remove(ids[2])
+    assert p.info()["sims_staged"] == 4
+    p.close()
+
+
+def test_pool_group_schedule_self_check_on_host():
+    """A group of uneven meshes with mixed materials builds its combined solve
+    schedule and block tables and checks them on the host before selecting a
+    device; without a GPU the commit must get as far as hipSetDevice."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("GPU present: commit succeeds instead")
+    ws = W.workload_batch(count=12, seed=2, lo=3, hi=9)
+    p = qnsim.Pool(ws[0].h, 1 << 34)
+    p.add_workloads(ws)
+    with pytest.raises(qnsim.QnsimError) as e:
+        p.commit(0)
+    assert "hipSetDevice" in str(e.value), str(e.value)
+    assert p.info()["sims_resident"] == 0
+    p.close()
