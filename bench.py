@@ -223,6 +223,33 @@ def served_run(args, torch, W, qnsim):
                 batches=info["batches_done"], analysis_s=t_an, upload_s=t_up)
 
 
+def small_runs(args, torch, W, qnsim):
+    """Latency-bound small meshes: the 540-tet cantilever (FP64, with and
+    without the captured step graph) and the mixed-stiffness cantilever in
+    mixed precision; steps/s and the per-step latency."""
+    out = []
+    cases = [("cantilever-neohookean-f64", W.workload_cantilever(0), dict(step_graph=1)),
+             ("cantilever-neohookean-f64-nograph", W.workload_cantilever(0), dict(step_graph=0)),
+             ("cantilever-logE-mixed", W.workload_mixed_cantilever(0),
+              dict(step_graph=1, precision=qnsim.QNSIM_MIXED))]
+    for name, w, opt in cases:
+        sim = qnsim.sim_from_workload(w, **opt)
+        x = torch.from_numpy(w.x0.copy()).cuda()
+        v = torch.from_numpy(w.v0.copy()).cuda()
+        sim.run_device(x, v, w.h, 10)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = sim.run_device(x, v, w.h, args.small_steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out.append(dict(case=name, tets=w.n_tets, steps=args.small_steps,
+                        steps_per_s=args.small_steps / dt, ms_per_step=1e3 * dt / args.small_steps,
+                        ls_trials_per_step=st["ls_trials"] / args.small_steps))
+        log(f"[bench] {name}: {args.small_steps / dt:.0f} steps/s ({1e3 * dt / args.small_steps:.3f} ms/step)")
+        sim.close()
+    return out
+
+
 def cpu_baseline(args, W):
     """The FP64 oracle on a bounded sample: one step of the Neo-Hookean block."""
     import numpy as np  # noqa: F401
@@ -263,6 +290,8 @@ def main():
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="run one plain device copy of this many MB first (a reference kernel of "
                          "known traffic for hardware-counter runs)")
+    ap.add_argument("--small-steps", type=int, default=100,
+                    help="steps of the small-mesh latency runs (0: skip them)")
     ap.add_argument("--batch-count", type=int, default=256,
                     help="meshes of the batched run (0: skip it)")
     ap.add_argument("--batch-steps", type=int, default=10)
@@ -314,6 +343,7 @@ def main():
         # informational: the mixed path (FP32 stresses) on the same workload
         mixed = run_material(W.NEOHOOKEAN, args, torch, W, qnsim, {"precision": qnsim.QNSIM_MIXED})
 
+    small = small_runs(args, torch, W, qnsim) if args.small_steps > 0 else []
     batched = []
     if args.batch_count > 0:
         batched = [batched_run(args, torch, W, qnsim, 0), batched_run(args, torch, W, qnsim, 1)]
@@ -366,6 +396,7 @@ def main():
         **({"mixed_precision_run": {k: mixed[k] for k in ("material", "steps_per_s", "ls_trials",
                                                          "iterations", "kernel_ms")}}
            if mixed else {}),
+        **({"small_meshes": small} if small else {}),
         **({"batched": batched} if batched else {}),
         **({"served": served} if served else {}),
         "roofline": {

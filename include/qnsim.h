@@ -25,7 +25,8 @@
  *    vertex indices (any orientation).
  *  - Host entry points (qnsim_step) synchronise before returning. Device entry
  *    points (qnsim_step_device) take device pointers and a hipStream_t passed
- *    as void*, are stream-ordered and do not synchronise except where stated.
+ *    as void*, are ordered after earlier work on that stream, and state when
+ *    they return (steps return when they are done; probes are stream-ordered).
  *  - Calls on one context must not overlap (a context is not thread-safe);
  *    distinct contexts are independent.
  */
@@ -94,6 +95,12 @@ typedef struct {
   int32_t level_merge;  /* 1: whole levels of the supernode tree may merge
                            into their parents when a latency/bandwidth cost
                            model favours it; 0: off                          */
+  int32_t step_graph;   /* 1: the fixed kernel sequence of a step is captured
+                           once in a HIP graph per set of state buffers and
+                           replayed; 0: kernels launched one by one         */
+  int32_t trials_per_cycle; /* line-search trials enqueued per iteration
+                           (1..8; a longer line search continues in the next
+                           cycle); default 2                                 */
 } qnsim_options;
 
 /* One material. mu, lambda in Pa; density in kg/m^3. For QNSIM_SPLINE,
@@ -186,18 +193,21 @@ int qnsim_step(qnsim_t* ctx, const double* x, const double* v, double h,
                const double* f_ext, double* x_out, double* v_out, qnsim_stats* stats);
 
 /* One time step from device arrays (n x 3 doubles, caller's numbering) on the
- * given stream (hipStream_t as void*; NULL = default stream). x_out / v_out
- * may alias x / v. The inverted-input check of qnsim_step is not made here:
- * an infeasible x shows up as a non-finite g_first. If stats is non-null the
- * call synchronises the stream to fill it; otherwise the step is fully
- * stream-ordered once the line-search budget is not exceeded. */
+ * given stream (hipStream_t as void*; NULL = the null stream: the step then
+ * runs on the context's own stream, after the work already submitted to the
+ * null stream). x_out / v_out may alias x / v. The inverted-input check of
+ * qnsim_step is not made here: an infeasible x shows up as a non-finite
+ * g_first. The step's work is ordered after earlier work on the stream; the
+ * call returns when it is done (the device decides when every iteration has
+ * ended, the host reads a 64-byte status). With options.step_graph the fixed
+ * kernel sequence is captured once per set of buffers and replayed. */
 int qnsim_step_device(qnsim_t* ctx, const double* d_x, const double* d_v, double h,
                       const double* d_fext, double* d_x_out, double* d_v_out,
                       void* stream, qnsim_stats* stats);
 
 /* Run `steps` consecutive time steps on device arrays, advancing (d_x, d_v)
- * in place, and accumulate counters into stats (if non-null). Used to time
- * trajectories without host round trips between steps. */
+ * in place (stream as qnsim_step_device), and accumulate counters into stats
+ * (if non-null). Used to time trajectories; each step reads back one status. */
 int qnsim_run_device(qnsim_t* ctx, double* d_x, double* d_v, double h,
                      const double* d_fext, int32_t steps, void* stream,
                      qnsim_stats* stats);

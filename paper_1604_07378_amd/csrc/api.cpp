@@ -31,9 +31,15 @@ bool finite_all(const double* p, size_t n) {
   return true;
 }
 
+void free_stage(qnsim_t* c) {
+  if (c->stage) (void)hipFree(c->stage);
+  c->stage = nullptr;
+}
+
 void invalidate(qnsim_t* c) {
   c->analyzed = false;
   c->prepared = false;
+  free_stage(c);
   dev_free(c->dev);
 }
 
@@ -238,6 +244,8 @@ int qnsim_options_default(qnsim_options* o) {
   o->dense_top = 6144;
   o->subtree_cap = 384;
   o->level_merge = 1;
+  o->step_graph = 1;
+  o->trials_per_cycle = 2;
   o->gamma = 0.3;
   o->backtrack = 0.5;
   o->fit_lo = 0.5;
@@ -259,6 +267,8 @@ int qnsim_create(const qnsim_options* opts, qnsim_t** out) {
       (o.precision != QNSIM_FP64 && o.precision != QNSIM_MIXED) ||
       o.dense_top < 0 || o.dense_top > kMaxDenseTop || o.subtree_cap < 0 ||
       o.subtree_cap > kSubCap || (o.level_merge != 0 && o.level_merge != 1) ||
+      (o.step_graph != 0 && o.step_graph != 1) || o.trials_per_cycle < 1 ||
+      o.trials_per_cycle > 8 ||
       !finite_all(o.gravity, 3))
     return QNSIM_E_INVALID;
   qnsim_t* c = new (std::nothrow) qnsim();
@@ -270,6 +280,7 @@ int qnsim_create(const qnsim_options* opts, qnsim_t** out) {
 
 void qnsim_destroy(qnsim_t* c) {
   if (!c) return;
+  free_stage(c);
   dev_free(c->dev);
   delete c;
 }
@@ -391,7 +402,8 @@ static StepParams params_of(const qnsim_t* c, double h) {
   p.iterations = c->opt.iterations;
   p.history = c->opt.history;
   p.max_halvings = c->opt.max_halvings;
-  p.budget = 2;
+  p.budget = c->opt.trials_per_cycle;
+  p.graph = c->opt.step_graph;
   p.gamma = c->opt.gamma;
   p.backtrack = c->opt.backtrack;
   for (int i = 0; i < 3; ++i) p.grav[i] = c->opt.gravity[i];
@@ -427,8 +439,8 @@ int qnsim_step_device(qnsim_t* c, const double* d_x, const double* d_v, double h
   int rc = check_step(c, h);
   if (rc) return rc;
   std::string err;
-  rc = dev_step(c->dev, params_of(c, h), d_x, d_v, d_fext, d_xo, d_vo,
-                stream ? stream : c->dev.stream, c->diag_final_gradient != 0, err);
+  rc = dev_step(c->dev, params_of(c, h), d_x, d_v, d_fext, d_xo, d_vo, stream,
+                c->diag_final_gradient != 0, err);
   if (rc) return fail(c, rc, err);
   if (stats) fill_stats(c->dev.stat_host[0], c->diag_final_gradient != 0, stats);
   return QNSIM_OK;
@@ -444,8 +456,8 @@ int qnsim_run_device(qnsim_t* c, double* d_x, double* d_v, double h, const doubl
   std::memset(&acc, 0, sizeof(acc));
   for (int s = 0; s < steps; ++s) {
     std::string err;
-    rc = dev_step(c->dev, params_of(c, h), d_x, d_v, d_fext, d_x, d_v,
-                  stream ? stream : c->dev.stream, c->diag_final_gradient != 0, err);
+    rc = dev_step(c->dev, params_of(c, h), d_x, d_v, d_fext, d_x, d_v, stream,
+                  c->diag_final_gradient != 0, err);
     if (rc) return fail(c, rc, err);
     qnsim_stats one;
     fill_stats(c->dev.stat_host[0], c->diag_final_gradient != 0, &one);
@@ -472,15 +484,16 @@ int qnsim_step(qnsim_t* c, const double* x, const double* v, double h, const dou
   if (!finite_all(x, n3) || !finite_all(v, n3) || (f_ext && !finite_all(f_ext, n3)))
     return fail(c, QNSIM_E_NONFINITE, "non-finite input state");
   hipStream_t st = (hipStream_t)c->dev.stream;
-  double* buf = nullptr;
-  if (hipMalloc(&buf, 5 * n3 * sizeof(double)) != hipSuccess)
+  // staging kept for the context's lifetime (stable buffers: the step's graph is reused)
+  if (!c->stage && hipMalloc(&c->stage, 5 * n3 * sizeof(double)) != hipSuccess) {
+    c->stage = nullptr;
     return fail(c, QNSIM_E_NOMEM, "staging allocation failed");
+  }
+  double* buf = c->stage;
   double *dx = buf, *dv = buf + n3, *df = buf + 2 * n3, *dxo = buf + 3 * n3, *dvo = buf + 4 * n3;
-  auto cleanup = [&]() { (void)hipFree(buf); };
   if (hipMemcpyAsync(dx, x, n3 * 8, hipMemcpyHostToDevice, st) != hipSuccess ||
       hipMemcpyAsync(dv, v, n3 * 8, hipMemcpyHostToDevice, st) != hipSuccess ||
       (f_ext && hipMemcpyAsync(df, f_ext, n3 * 8, hipMemcpyHostToDevice, st) != hipSuccess)) {
-    cleanup();
     return fail(c, QNSIM_E_DEVICE, "host-to-device copy failed");
   }
   std::string err;
@@ -489,20 +502,18 @@ int qnsim_step(qnsim_t* c, const double* x, const double* v, double h, const dou
   if (has_nh) {
     int inv = 0;
     rc = dev_check_inverted(c->dev, dx, st, &inv, err);
-    if (rc) { cleanup(); return fail(c, rc, err); }
-    if (inv) { cleanup(); return fail(c, QNSIM_E_INVERTED, "Neo-Hookean element with J <= 0 at x"); }
+    if (rc) { return fail(c, rc, err); }
+    if (inv) { return fail(c, QNSIM_E_INVERTED, "Neo-Hookean element with J <= 0 at x"); }
   }
   rc = dev_step(c->dev, params_of(c, h), dx, dv, f_ext ? df : nullptr, dxo, dvo, st,
                 c->diag_final_gradient != 0, err);
-  if (rc) { cleanup(); return fail(c, rc, err); }
+  if (rc) { return fail(c, rc, err); }
   const SimStat t = c->dev.stat_host[0];
   if (hipMemcpyAsync(x_out, dxo, n3 * 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
       hipMemcpyAsync(v_out, dvo, n3 * 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
       hipStreamSynchronize(st) != hipSuccess) {
-    cleanup();
     return fail(c, QNSIM_E_DEVICE, "device-to-host copy failed");
   }
-  cleanup();
   if (stats) fill_stats(t, c->diag_final_gradient != 0, stats);
   return QNSIM_OK;
 }

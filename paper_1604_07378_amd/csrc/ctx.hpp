@@ -42,6 +42,7 @@ struct qnsim {
   // ---- device state ----
   bool prepared = false;
   qn::DeviceMesh dev;
+  double* stage = nullptr;        // qnsim_step staging: x, v, f_ext, x', v' (5 n x 3)
 };
 
 namespace qn {

@@ -121,6 +121,13 @@ struct ItemDesc {
 // rows of a forward work item staged in LDS (pass-through sums)
 constexpr int kMaxItemRows = 256;  // == threads of a level-kernel workgroup
 
+// What a captured step depends on besides the device mesh itself.
+struct GraphKey {
+  const void* ptr[5];  // x, v, fext, xo, vo
+  int iterations, history, max_halvings, budget;
+  double gamma, backtrack, grav[3], h;
+};
+
 struct DeviceMesh {
   int device = 0;
   int n = 0, nf = 0, T = 0, nmat = 0, single_type = -1, m = 5, slots = 6;
@@ -196,16 +203,20 @@ struct DeviceMesh {
   SimStat* stat_host = nullptr;  // pinned mirror
   int* run_host = nullptr;    // pinned staging of the participation mask
   void* stream = nullptr;     // internal stream (hipStream_t)
+  void* graph_exec = nullptr; // captured fixed sequence of a step (hipGraphExec_t)
+  GraphKey graph_key = {};
   void* ev[2] = {nullptr, nullptr};
   size_t bytes = 0;
 };
 
 struct StepParams {
-  int iterations, history, max_halvings, budget;
+  int iterations, history, max_halvings, budget;  // budget: line-search trials per cycle
+  int graph;                                      // replay the fixed sequence as a HIP graph
   double gamma, backtrack;
   double grav[3];
   double h;
 };
+
 
 // Prefactored solve r = A^{-1} q on the stream (internal order, nf x 3).
 // gate: if not null, the launches do nothing while *gate <= 0; sim_ctl: if

@@ -95,7 +95,8 @@ StepParams pool_params(const qnsim_pool* p) {
   s.iterations = p->opt.iterations;
   s.history = p->opt.history;
   s.max_halvings = p->opt.max_halvings;
-  s.budget = 2;
+  s.budget = p->opt.trials_per_cycle;
+  s.graph = p->opt.step_graph;
   s.gamma = p->opt.gamma;
   s.backtrack = p->opt.backtrack;
   for (int i = 0; i < 3; ++i) s.grav[i] = p->opt.gravity[i];

@@ -979,6 +979,11 @@ void launch_finalize(DeviceMesh& D, const StepParams& P, hipStream_t st, double*
                      D.vperm, D.x0, D.X, D.d, 1.0 / P.h, D.ctl, xo, vo);
 }
 
+void drop_graph(DeviceMesh& D) {
+  if (D.graph_exec) (void)hipGraphExecDestroy((hipGraphExec_t)D.graph_exec);
+  D.graph_exec = nullptr;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -990,6 +995,7 @@ int dev_sync(DeviceMesh& D, void* stream, std::string& err) {
 }
 
 void dev_free(DeviceMesh& D) {
+  drop_graph(D);
   void* ptrs[] = {D.tv, D.Bm, D.vol, D.tmat, D.mats, D.mass, D.inc_tab, D.vperm,
                   D.sn, D.items, D.Bf, D.Bb, D.rows, D.rel, D.vp, D.x0,
                   D.v0, D.y, D.X, D.G, D.d, D.r, D.q, D.z, D.Sv, D.Tv, D.fel,
@@ -1001,6 +1007,8 @@ void dev_free(DeviceMesh& D) {
   if (D.stat_host) (void)hipHostFree(D.stat_host);
   if (D.run_host) (void)hipHostFree(D.run_host);
   if (D.stream) (void)hipStreamDestroy((hipStream_t)D.stream);
+  for (void* e : D.ev)
+    if (e) (void)hipEventDestroy((hipEvent_t)e);
   D = DeviceMesh();
 }
 
@@ -1040,6 +1048,11 @@ int dev_alloc(DeviceMesh& D, std::string& err) {
   hipStream_t st;
   HIP_OK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
   D.stream = st;
+  for (int i = 0; i < 2; ++i) {
+    hipEvent_t e;
+    HIP_OK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    D.ev[i] = e;
+  }
   HIP_OK(hipMemset(D.X, 0, n3 * 8));
   HIP_OK(hipMemset(D.d, 0, f3 * 8));
   HIP_OK(hipMemset(D.ctl, 0, sizeof(Ctl) * D.S));
@@ -1062,10 +1075,14 @@ int dev_set_run(DeviceMesh& D, const int* run_flags, void* stream, std::string& 
 // ---------------------------------------------------------------------------
 // One time step
 // ---------------------------------------------------------------------------
-int dev_step(DeviceMesh& D, const StepParams& P, const double* x, const double* v,
-             const double* fext, double* xo, double* vo, void* stream, bool final_gradient,
-             std::string& err) {
-  hipStream_t st = (hipStream_t)stream;
+namespace {
+
+// The fixed sequence of a step: set-up, then per iteration k the line search
+// of k and (k + 1 < K) the gather and direction of k + 1 (a simulation whose
+// line search needs more than P.budget trials falls one cycle behind), the
+// final states and the statistics copy. Returns the last cycle tag.
+int enqueue_step(DeviceMesh& D, const StepParams& P, hipStream_t st, const double* x,
+                 const double* v, const double* fext, double* xo, double* vo) {
   Parts pp = parts_of(D);
   const int K = P.iterations;
   hipLaunchKernelGGL(k_step_init, dim3(nblk(D.n)), dim3(BS), 0, st, D.n, D.nf, D.vsim, D.run,
@@ -1074,9 +1091,6 @@ int dev_step(DeviceMesh& D, const StepParams& P, const double* x, const double* 
   launch_elem(D, st, PH_INIT, 0, pp.elem, nullptr);
   hipLaunchKernelGGL(k_init_decide, dim3(D.S), dim3(BS), 0, st, (int)PH_INIT, D.seg, pp.elem,
                      D.ctl, D.stat);
-  // iteration k: line search of k, then (k + 1 < K) the gather and direction
-  // of k + 1; a simulation whose line search needs more than P.budget trials
-  // falls one cycle behind
   int cyc = 0;
   launch_gather_stage(D, P, st);
   launch_direction(D, P, st, cyc);
@@ -1088,8 +1102,74 @@ int dev_step(DeviceMesh& D, const StepParams& P, const double* x, const double* 
     }
   }
   launch_finalize(D, P, st, xo, vo);
+  (void)hipMemcpyAsync(D.stat_host, D.stat, sizeof(SimStat) * D.S, hipMemcpyDeviceToHost, st);
+  return cyc;
+}
+
+GraphKey key_of(const StepParams& P, const double* x, const double* v, const double* fext,
+                const double* xo, const double* vo) {
+  GraphKey k;
+  std::memset(&k, 0, sizeof(k));
+  k.ptr[0] = x; k.ptr[1] = v; k.ptr[2] = fext; k.ptr[3] = xo; k.ptr[4] = vo;
+  k.iterations = P.iterations; k.history = P.history; k.max_halvings = P.max_halvings;
+  k.budget = P.budget; k.gamma = P.gamma; k.backtrack = P.backtrack;
+  for (int i = 0; i < 3; ++i) k.grav[i] = P.grav[i];
+  k.h = P.h;
+  return k;
+}
+
+// Captures the fixed sequence for these buffers (once) and launches it;
+// false if the stream cannot be captured (the caller then launches eagerly).
+bool launch_step_graph(DeviceMesh& D, const StepParams& P, hipStream_t st, const double* x,
+                       const double* v, const double* fext, double* xo, double* vo) {
+  const GraphKey key = key_of(P, x, v, fext, xo, vo);
+  if (!D.graph_exec || std::memcmp(&key, &D.graph_key, sizeof(key)) != 0) {
+    drop_graph(D);
+    if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      (void)hipGetLastError();
+      return false;
+    }
+    enqueue_step(D, P, st, x, v, fext, xo, vo);
+    hipGraph_t g = nullptr;
+    if (hipStreamEndCapture(st, &g) != hipSuccess || !g) {
+      (void)hipGetLastError();
+      return false;
+    }
+    hipGraphExec_t e = nullptr;
+    const hipError_t ie = hipGraphInstantiate(&e, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ie != hipSuccess || !e) {
+      (void)hipGetLastError();
+      return false;
+    }
+    D.graph_exec = e;
+    D.graph_key = key;
+  }
+  return hipGraphLaunch((hipGraphExec_t)D.graph_exec, st) == hipSuccess;
+}
+
+}  // namespace
+
+int dev_step(DeviceMesh& D, const StepParams& P, const double* x, const double* v,
+             const double* fext, double* xo, double* vo, void* stream, bool final_gradient,
+             std::string& err) {
+  hipStream_t st = (hipStream_t)stream;
+  if (!st) {
+    // the null stream cannot be captured: run on the context's stream, after
+    // the work already submitted to the null stream
+    st = (hipStream_t)D.stream;
+    HIP_OK(hipEventRecord((hipEvent_t)D.ev[0], nullptr));
+    HIP_OK(hipStreamWaitEvent(st, (hipEvent_t)D.ev[0], 0));
+  }
+  Parts pp = parts_of(D);
+  const int K = P.iterations;
+  // the cycle tags of a continuation follow the fixed sequence's last one
+  int cyc = K - 1;
+  if (!(P.graph && launch_step_graph(D, P, st, x, v, fext, xo, vo))) {
+    (void)hipGetLastError();
+    cyc = enqueue_step(D, P, st, x, v, fext, xo, vo);
+  }
   HIP_OK(hipGetLastError());
-  HIP_OK(hipMemcpyAsync(D.stat_host, D.stat, sizeof(SimStat) * D.S, hipMemcpyDeviceToHost, st));
   HIP_OK(hipStreamSynchronize(st));
   // Continuation: more cycles for the simulations that are not done.
   const int extra_trials = std::max(P.budget, 4);

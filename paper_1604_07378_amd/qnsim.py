@@ -42,7 +42,8 @@ class Options(ctypes.Structure):
                 ("gamma", ctypes.c_double), ("backtrack", ctypes.c_double),
                 ("fit_lo", ctypes.c_double), ("fit_hi", ctypes.c_double),
                 ("gravity", ctypes.c_double * 3),
-                ("subtree_cap", ctypes.c_int32), ("level_merge", ctypes.c_int32)]
+                ("subtree_cap", ctypes.c_int32), ("level_merge", ctypes.c_int32),
+                ("step_graph", ctypes.c_int32), ("trials_per_cycle", ctypes.c_int32)]
 
 
 class MaterialC(ctypes.Structure):

@@ -337,3 +337,24 @@ def test_mixed_precision_objective_and_gradient():
     grad = grad.cpu().numpy()
     assert abs(g - g_ref) <= 1e-5 * abs(g_ref)
     assert np.abs(grad - grad_ref).max() <= 1e-4 * np.abs(grad_ref).max()
+
+
+def test_step_graph_replays_equal_eager():
+    """The captured step replayed 12 times (with eager probe kernels on the same
+    buffers between replays) equals the step launched kernel by kernel, bit for
+    bit, together with its statistics."""
+    w = W.workload_cantilever(0)
+    sg = qnsim.sim_from_workload(w, step_graph=1)
+    se = qnsim.sim_from_workload(w, step_graph=0)
+    xg, vg = _dev(w.x0), _dev(w.v0)
+    xe, ve = _dev(w.x0), _dev(w.v0)
+    grad = torch.empty(w.n_verts, 3, dtype=torch.float64, device="cuda")
+    for k in range(12):
+        a = sg.step_device(xg, vg, w.h, x_out=xg, v_out=vg)
+        b = se.step_device(xe, ve, w.h, x_out=xe, v_out=ve)
+        torch.cuda.synchronize()
+        assert torch.equal(xg, xe) and torch.equal(vg, ve), f"step {k}"
+        a.pop("grad_norm_last"); b.pop("grad_norm_last")   # not computed (NaN)
+        assert a == b, f"step {k}: stats {a} vs {b}"
+        sg.eval_device(xg, xg, grad)   # eager work on the context's buffers between replays
+        torch.cuda.synchronize()

@@ -200,3 +200,24 @@ def test_serving_results_equal_alone():
     print(f"served {counts.sum()} requests in {info['batches_done']} batches; "
           f"latency p50 {np.median(lat) * 1e3:.2f} ms; max eps vs alone {worst:.3e}", flush=True)
     p.close()
+
+
+def test_pool_graph_replays_equal_eager():
+    """Groups replaying their captured step (run flags changing between
+    replays) equal groups launching kernel by kernel, bit for bit."""
+    ws = W.workload_batch(count=5, seed=4, lo=3, hi=6)
+    pg, ig = _pool(ws, step_graph=1)
+    pe, ie = _pool(ws, step_graph=0)
+    rng = np.random.default_rng(1)
+    for k in range(8):
+        sub = [j for j in range(5) if rng.uniform() < 0.7] or [0]
+        a = pg.step([ig[j] for j in sub])
+        b = pe.step([ie[j] for j in sub])
+        drop = lambda st: [{k2: v for k2, v in d.items() if k2 != "grad_norm_last"} for d in st]
+        assert drop(a) == drop(b), f"round {k}: stats differ"
+        for j in range(5):
+            xg, vg = pg.get_state(ig[j])
+            xe, ve = pe.get_state(ie[j])
+            assert np.array_equal(xg, xe) and np.array_equal(vg, ve), f"round {k}, sim {j}"
+    pg.close()
+    pe.close()
