@@ -146,8 +146,21 @@ def batched_run(args, torch, W, qnsim, precision):
             evals += w.n_tets * (s["ls_trials"] + 1)
             trials += s["ls_trials"]
     dt = time.perf_counter() - t0
-    res = dict(meshes=len(ws), tets=T, verts=sum(w.n_verts for w in ws),
-               precision="mixed" if precision else "f64",
+    info = p.info()
+    kern = {}
+    for name, kid, nbytes in (
+            ("element", qnsim.KERNEL_ELEMENT, element_bytes(T, sum(w.n_verts for w in ws), info["n_free"])),
+            ("gather", qnsim.KERNEL_GATHER, None),
+            ("solve", qnsim.KERNEL_SOLVE, solve_bytes(info["nnz_L"], info["n_free"]))):
+        ms = p.time_kernel(0, kid, 10)
+        kern[name] = {"ms": ms}
+        if nbytes:
+            kern[name].update(bytes=nbytes, GBs=nbytes / (ms * 1e-3) / 1e9,
+                              frac=nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS)
+    log(f"[bench] batch kernels: " + ", ".join(
+        f"{k} {v['ms']:.3f} ms" + (f" ({v['GBs']:.0f} GB/s)" if "GBs" in v else "") for k, v in kern.items()))
+    res = dict(meshes=len(ws), tets=T, verts=sum(w.n_verts for w in ws), nnz_L=info["nnz_L"],
+               kernels=kern, precision="mixed" if precision else "f64",
                batched_steps_per_s=args.batch_steps / dt,
                mesh_steps_per_s=args.batch_steps * len(ws) / dt,
                tet_evals_per_s=evals / dt, ms_per_batched_step=1e3 * dt / args.batch_steps,
@@ -284,7 +297,7 @@ def main():
     ap.add_argument("--n", type=int, default=40, help="cubes per axis of the block")
     ap.add_argument("--materials", default="neohookean,stvk,spline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-steps", type=int, default=1)
+    ap.add_argument("--cpu-sample-steps", type=int, default=3)
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the extra mixed-precision Neo-Hookean run")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,

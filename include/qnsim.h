@@ -318,6 +318,9 @@ typedef struct {
   int64_t used_bytes;      /* device memory held by the groups                  */
   int64_t steps_done;      /* simulation steps completed since creation         */
   int64_t batches_done;    /* batched group steps since creation                */
+  int64_t nnz_L;           /* structural nonzeros of the resident factors       */
+  int64_t n_free;          /* free vertices of the resident simulations         */
+  int64_t n_tets;          /* tetrahedra of the resident simulations            */
 } qnsim_pool_info;
 
 /* Creates a pool for time step h with a device-memory budget in bytes
@@ -373,6 +376,11 @@ int qnsim_pool_wait(qnsim_pool_t* pool, int64_t ticket, double timeout_s, qnsim_
 int qnsim_pool_serve_stop(qnsim_pool_t* pool);
 
 int qnsim_pool_get_info(qnsim_pool_t* pool, qnsim_pool_info* info);
+/* As qnsim_time_kernel, on group `group` (0-based, in admission order) with
+ * every simulation of the group taking part; after at least one step of the
+ * group. Not while the request loop runs. */
+int qnsim_pool_time_kernel(qnsim_pool_t* pool, int32_t group, int32_t kernel, int32_t reps,
+                           double* avg_ms);
 const char* qnsim_pool_last_error(const qnsim_pool_t* pool);
 
 #ifdef __cplusplus

@@ -84,11 +84,16 @@ struct SimSeg {
 
 // Work of one block of a segmented kernel: simulation and index ranges.
 // Element pass: tets [a0, a1) and the inertia terms of free vertices
-// [b0, b1); gather: free vertices [a0, a1); vector passes: entries [a0, a1)
-// of the 3-component free-vertex vectors.
+// [b0, b1), its energy partial written to part[slot]; gather: free vertices
+// [a0, a1); vector passes: entries [a0, a1) of the 3-component free-vertex
+// vectors.
 struct BlockSeg {
-  int sim, a0, a1, b0, b1, pad0, pad1, pad2;
+  int sim, a0, a1, b0, b1, slot, pad1, pad2;
 };
+
+// Material kinds of the element-pass launch lists: the five types, and
+// simulations whose tets mix types (generic evaluation).
+constexpr int kElemKinds = 6;
 
 struct Level {
   int fw_begin, fw_end;  // forward work items of this level
@@ -139,7 +144,11 @@ struct DeviceMesh {
   SimSeg* seg = nullptr;      // S
   int* vsim = nullptr;        // n: simulation of each internal vertex
   int* run = nullptr;         // S: simulation takes part in the current step
-  BlockSeg* eblk = nullptr;   // element-pass blocks
+  BlockSeg* eblk = nullptr;   // element-pass blocks (slot = own index)
+  // element-pass blocks by the material type of their simulation (kind 5:
+  // simulations of several types), one launch each when the batch mixes types
+  BlockSeg* eblk_kind[kElemKinds] = {};
+  int eblk_kind_n[kElemKinds] = {};
   BlockSeg* gblk = nullptr;   // gather blocks (64 vertices each)
   BlockSeg* vblk = nullptr;   // vector-pass blocks (256 entries each)
   BlockSeg* rblk = nullptr;   // r0-dot blocks (1024 entries each)

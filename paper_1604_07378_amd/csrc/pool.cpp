@@ -591,8 +591,14 @@ int qnsim_pool_get_info(qnsim_pool_t* p, qnsim_pool_info* info) {
   std::memset(info, 0, sizeof(*info));
   for (const PoolSim& s : p->sims) {
     if (s.removed) continue;
-    if (s.group >= 0) info->sims_resident++;
-    else info->sims_staged++;
+    if (s.group >= 0) {
+      info->sims_resident++;
+      info->nnz_L += s.c->factor.nnz_exact;
+      info->n_free += s.c->nf;
+      info->n_tets += s.c->T;
+    } else {
+      info->sims_staged++;
+    }
   }
   for (auto& g : p->groups)
     if (g->live > 0) info->groups++;
@@ -602,6 +608,28 @@ int qnsim_pool_get_info(qnsim_pool_t* p, qnsim_pool_info* info) {
   info->steps_done = p->steps_done;
   info->batches_done = p->batches_done;
   return QNSIM_OK;
+}
+
+int qnsim_pool_time_kernel(qnsim_pool_t* p, int32_t group, int32_t kernel, int32_t reps,
+                           double* avg_ms) {
+  if (!p || !avg_ms || reps < 1 || kernel < QNSIM_KERNEL_ELEMENT || kernel > QNSIM_KERNEL_SOLVE)
+    return QNSIM_E_INVALID;
+  std::unique_lock<std::mutex> lk(p->mu);
+  if (p->serving) return pfail(p, QNSIM_E_STATE, "the request loop is running");
+  if (group < 0 || group >= (int)p->groups.size() || p->groups[group]->live == 0)
+    return pfail(p, QNSIM_E_INVALID, "no such group");
+  PoolGroup& g = *p->groups[group];
+  if (g.busy) return pfail(p, QNSIM_E_STATE, "the group is stepping");
+  g.busy = true;
+  lk.unlock();
+  std::string err;
+  std::vector<int> all(g.D.S, 1);
+  int rc = dev_set_run(g.D, all.data(), g.D.stream, err);
+  if (!rc) rc = dev_time_kernel(g.D, kernel, reps, avg_ms, err);
+  lk.lock();
+  g.busy = false;
+  p->cv.notify_all();
+  return rc ? pfail(p, rc, err) : QNSIM_OK;
 }
 
 const char* qnsim_pool_last_error(const qnsim_pool_t* p) { return p ? p->last_error.c_str() : ""; }

@@ -207,6 +207,8 @@ k_elem(int want, int trial, const BlockSeg* __restrict__ blk, int T, int nf,
        const double* __restrict__ y, double inv2h2, const Ctl* __restrict__ ctl,
        R* __restrict__ fel, double* __restrict__ part, double* __restrict__ psi_out) {
   __shared__ double sh[16];
+  // the block's gradient contributions, written out contiguously at the end
+  __shared__ __align__(16) R sfel[BS * 12];
   const BlockSeg sg = blk[blockIdx.x];
   double alpha = 0.0;
   if (want >= 0) {
@@ -269,11 +271,26 @@ k_elem(int want, int trial, const BlockSeg* __restrict__ blk, int T, int nf,
       }
       g[0][i] = -s;
     }
-    R* o = fel + (size_t)t * 12;
+    R* o = sfel + threadIdx.x * 12;
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
       for (int c = 0; c < 3; ++c) o[3 * a + c] = g[a][c];
+  }
+  __syncthreads();
+  {
+    // tets [a0, a1) own fel[12 a0, 12 a1): 16-byte stores, consecutive lanes
+    // on consecutive addresses (12 a0 values start on a 16-byte boundary)
+    const int nval = 12 * max(0, sg.a1 - sg.a0);
+    if constexpr (sizeof(R) == 8) {
+      const double2* src = reinterpret_cast<const double2*>(sfel);
+      double2* dst = reinterpret_cast<double2*>(fel + 12 * (size_t)sg.a0);
+      for (int i = threadIdx.x; i < nval / 2; i += BS) dst[i] = src[i];
+    } else {
+      const float4* src = reinterpret_cast<const float4*>(sfel);
+      float4* dst = reinterpret_cast<float4*>(fel + 12 * (size_t)sg.a0);
+      for (int i = threadIdx.x; i < nval / 4; i += BS) dst[i] = src[i];
+    }
   }
   const int vi = sg.b0 + threadIdx.x;
   if (vi < sg.b1) {
@@ -288,7 +305,7 @@ k_elem(int want, int trial, const BlockSeg* __restrict__ blk, int T, int nf,
     e += mass[vi] * s * inv2h2;
   }
   double b = block_sum(e, sh);
-  if (threadIdx.x == 0 && part) part[blockIdx.x] = b;
+  if (threadIdx.x == 0 && part) part[sg.slot] = b;
 }
 
 // g(x_1) of each simulation in phase `want` (PH_INIT, or PH_RETRY after
@@ -845,31 +862,45 @@ __global__ void __launch_bounds__(BS) k_ctl_timing(int S, Ctl* __restrict__ ctl)
 inline int nblk(int64_t n) { return (int)std::max<int64_t>(1, (n + BS - 1) / BS); }
 
 // want: phase the simulations must be in (-1: all); trial: positions x_k + alpha d.
+// One launch of the element pass per material kind present (a single launch
+// when every tet has the same type), each with its specialised material code.
 void launch_elem(DeviceMesh& D, hipStream_t st, int want, int trial, double* part,
                  double* psi_out) {
   const double inv2h2 = 0.5 / (D.h * D.h);
-  const int grid = D.elem_blocks;
-#define QN_ELEM(TY)                                                                           \
+#define QN_ELEM(TY, BLK, GRID)                                                                \
   do {                                                                                       \
     if (D.mixed)                                                                             \
-      hipLaunchKernelGGL((k_elem<TY, float>), dim3(grid), dim3(BS), 0, st, want, trial,       \
-                         D.eblk, D.T, D.nf, D.tv, D.Bm, D.vol, D.tmat, D.mats, D.mass, D.X,   \
+      hipLaunchKernelGGL((k_elem<TY, float>), dim3(GRID), dim3(BS), 0, st, want, trial,       \
+                         BLK, D.T, D.nf, D.tv, D.Bm, D.vol, D.tmat, D.mats, D.mass, D.X,      \
                          D.d, D.y, inv2h2, D.ctl, reinterpret_cast<float*>(D.fel), part,      \
                          psi_out);                                                           \
     else                                                                                     \
-      hipLaunchKernelGGL((k_elem<TY, double>), dim3(grid), dim3(BS), 0, st, want, trial,      \
-                         D.eblk, D.T, D.nf, D.tv, D.Bm, D.vol, D.tmat, D.mats, D.mass, D.X,   \
+      hipLaunchKernelGGL((k_elem<TY, double>), dim3(GRID), dim3(BS), 0, st, want, trial,      \
+                         BLK, D.T, D.nf, D.tv, D.Bm, D.vol, D.tmat, D.mats, D.mass, D.X,      \
                          D.d, D.y, inv2h2, D.ctl, D.fel, part, psi_out);                      \
   } while (0)
-  switch (D.single_type) {
-    case 0: QN_ELEM(0); break;
-    case 1: QN_ELEM(1); break;
-    case 2: QN_ELEM(2); break;
-    case 3: QN_ELEM(3); break;
-    case 4: QN_ELEM(4); break;
-    default: QN_ELEM(-1); break;
-  }
+  auto one = [&](int type, const BlockSeg* blk, int grid) {
+    switch (type) {
+      case 0: QN_ELEM(0, blk, grid); break;
+      case 1: QN_ELEM(1, blk, grid); break;
+      case 2: QN_ELEM(2, blk, grid); break;
+      case 3: QN_ELEM(3, blk, grid); break;
+      case 4: QN_ELEM(4, blk, grid); break;
+      default: QN_ELEM(-1, blk, grid); break;
+    }
+  };
 #undef QN_ELEM
+  if (D.single_type >= 0) {
+    one(D.single_type, D.eblk, D.elem_blocks);
+    return;
+  }
+  bool any = false;
+  for (int k = 0; k < kElemKinds; ++k)
+    if (D.eblk_kind_n[k] > 0) {
+      one(k < kElemKinds - 1 ? k : -1, D.eblk_kind[k], D.eblk_kind_n[k]);
+      any = true;
+    }
+  if (!any) one(-1, D.eblk, D.elem_blocks);
 }
 
 // Partials layout: gather dots (kGatherDots x gather_blocks), r0 dots
@@ -996,6 +1027,8 @@ int dev_sync(DeviceMesh& D, void* stream, std::string& err) {
 
 void dev_free(DeviceMesh& D) {
   drop_graph(D);
+  for (int k = 0; k < kElemKinds; ++k)
+    if (D.eblk_kind[k]) (void)hipFree(D.eblk_kind[k]);
   void* ptrs[] = {D.tv, D.Bm, D.vol, D.tmat, D.mats, D.mass, D.inc_tab, D.vperm,
                   D.sn, D.items, D.Bf, D.Bb, D.rows, D.rel, D.vp, D.x0,
                   D.v0, D.y, D.X, D.G, D.d, D.r, D.q, D.z, D.Sv, D.Tv, D.fel,

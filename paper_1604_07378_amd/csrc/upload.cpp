@@ -525,7 +525,7 @@ int upload_sims(const std::vector<const qnsim*>& sims, const qnsim_options& opt,
     std::vector<BlockSeg> eb, gb, vb, rb;
     auto mk = [](int sim, int a0, int a1, int b0, int b1) {
       BlockSeg x;
-      x.sim = sim; x.a0 = a0; x.a1 = a1; x.b0 = b0; x.b1 = b1; x.pad0 = x.pad1 = x.pad2 = 0;
+      x.sim = sim; x.a0 = a0; x.a1 = a1; x.b0 = b0; x.b1 = b1; x.slot = x.pad1 = x.pad2 = 0;
       return x;
     };
     for (int s = 0; s < S; ++s) {
@@ -575,6 +575,19 @@ int upload_sims(const std::vector<const qnsim*>& sims, const qnsim_options& opt,
       for (int t = 0; t < T; ++t) if (ct[t] != 1) FAIL(QNSIM_E_DEVICE, "blocks: tet not covered once");
       for (int v = 0; v < nf; ++v) if (cv[v] != 1 || cg[v] != 1) FAIL(QNSIM_E_DEVICE, "blocks: vertex not covered once");
       for (size_t e = 0; e < 3 * (size_t)nf; ++e) if (ce[e] != 1 || cr[e] != 1) FAIL(QNSIM_E_DEVICE, "blocks: entry not covered once");
+    }
+    for (size_t i = 0; i < eb.size(); ++i) eb[i].slot = (int)i;
+    if (D.single_type < 0) {
+      // one launch per material kind, each block keeping its partial slot
+      std::vector<BlockSeg> kind[kElemKinds];
+      for (const BlockSeg& x : eb) {
+        const int t = sims[x.sim]->single_type;
+        kind[t >= 0 && t < kElemKinds - 1 ? t : kElemKinds - 1].push_back(x);
+      }
+      for (int k = 0; k < kElemKinds; ++k) {
+        D.eblk_kind_n[k] = (int)kind[k].size();
+        if (!kind[k].empty()) UP(D.eblk_kind[k], kind[k]);
+      }
     }
     D.elem_blocks = (int)eb.size();
     D.gather_blocks = (int)gb.size();

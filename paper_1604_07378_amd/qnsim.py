@@ -87,7 +87,8 @@ class PoolInfo(ctypes.Structure):
     _fields_ = [("sims_staged", ctypes.c_int32), ("sims_resident", ctypes.c_int32),
                 ("groups", ctypes.c_int32), ("serving", ctypes.c_int32),
                 ("budget_bytes", ctypes.c_int64), ("used_bytes", ctypes.c_int64),
-                ("steps_done", ctypes.c_int64), ("batches_done", ctypes.c_int64)]
+                ("steps_done", ctypes.c_int64), ("batches_done", ctypes.c_int64),
+                ("nnz_L", ctypes.c_int64), ("n_free", ctypes.c_int64), ("n_tets", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -137,6 +138,7 @@ SIGNATURES = {
     "qnsim_pool_serve_stop": (ctypes.c_int, [_P]),
     "qnsim_pool_get_info": (ctypes.c_int, [_P, ctypes.POINTER(PoolInfo)]),
     "qnsim_pool_last_error": (ctypes.c_char_p, [_P]),
+    "qnsim_pool_time_kernel": (ctypes.c_int, [_P, _I, _I, _I, ctypes.POINTER(_D)]),
 }
 
 _lib = None
@@ -492,6 +494,12 @@ class Pool:
 
     def serve_stop(self):
         self._check(self._lib.qnsim_pool_serve_stop(self._p))
+
+    def time_kernel(self, group: int, kernel: int, reps: int) -> float:
+        ms = ctypes.c_double()
+        self._check(self._lib.qnsim_pool_time_kernel(self._p, int(group), int(kernel), int(reps),
+                                                     ctypes.byref(ms)))
+        return ms.value
 
     def info(self) -> dict:
         i = PoolInfo()
