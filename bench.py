@@ -184,8 +184,9 @@ def served_run(args, torch, W, qnsim):
                              spline_seed=d["seed"], nu=d["nu"])
         ws.append(w)
     T = sum(w.n_tets for w in ws)
-    p, ids, admitted, t_an, t_up = _pool_of(ws, qnsim, args.pool_budget_gb * 10**9,
-                                            args.pool_group, precision=args.pool_precision)
+    group = args.pool_group or -(-len(ws) // args.pool_lanes)
+    p, ids, admitted, t_an, t_up = _pool_of(ws, qnsim, int(args.pool_budget_gb * 10**9), group,
+                                            precision=args.pool_precision)
     info = p.info()
     assert admitted == len(ids), "pool does not fit the budget"
     res_ids = ids
@@ -229,7 +230,7 @@ def served_run(args, torch, W, qnsim):
     p.serve_stop()
     info = p.info()
     p.close()
-    return dict(sims=len(ws), admitted=admitted, tets=T, groups=info["groups"],
+    return dict(sims=len(ws), admitted=admitted, tets=T, groups=info["groups"], group_size=group,
                 precision="mixed" if args.pool_precision else "f64",
                 device_gb=info["used_bytes"] / 1e9, budget_gb=args.pool_budget_gb,
                 lanes=args.pool_lanes, capacity_steps_per_s=cap, rates=rates,
@@ -308,13 +309,14 @@ def main():
     ap.add_argument("--batch-count", type=int, default=256,
                     help="meshes of the batched run (0: skip it)")
     ap.add_argument("--batch-steps", type=int, default=10)
-    ap.add_argument("--pool-count", type=int, default=200,
+    ap.add_argument("--pool-count", type=int, default=2000,
                     help="simulations of the served run, the first of the 2,000-simulation "
                          "pool's descriptions (0: skip it)")
-    ap.add_argument("--pool-group", type=int, default=32, help="simulations per group")
+    ap.add_argument("--pool-group", type=int, default=0,
+                    help="simulations per group (0: one group per lane)")
     ap.add_argument("--pool-lanes", type=int, default=4)
     ap.add_argument("--pool-budget-gb", type=float, default=200.0)
-    ap.add_argument("--pool-requests", type=int, default=2000, help="requests per load level")
+    ap.add_argument("--pool-requests", type=int, default=10000, help="requests per load level")
     ap.add_argument("--pool-load", default="0.25,0.5,0.8,1.2",
                     help="offered loads as fractions of the measured capacity")
     ap.add_argument("--pool-precision", type=int, default=1, help="1: mixed, 0: FP64")

@@ -80,13 +80,16 @@ struct SimSeg {
   int gb0, gb1;        // gather blocks
   int rb0, rb1;        // r0-dot blocks
   int vb0, vb1;        // vector blocks
+  int xb0, xb1;        // vertex blocks (step set-up and final states)
+  int pad0, pad1;
 };
 
 // Work of one block of a segmented kernel: simulation and index ranges.
 // Element pass: tets [a0, a1) and the inertia terms of free vertices
-// [b0, b1), its energy partial written to part[slot]; gather: free vertices
-// [a0, a1); vector passes: entries [a0, a1) of the 3-component free-vertex
-// vectors.
+// [b0, b1); gather: free vertices [a0, a1); vector passes: entries [a0, a1)
+// of the 3-component free-vertex vectors; vertex blocks: vertices [a0, a1)
+// (free or pinned). slot: the block's index in its full table, where its
+// partial sums go (a launch may cover only the blocks of some simulations).
 struct BlockSeg {
   int sim, a0, a1, b0, b1, slot, pad1, pad2;
 };
@@ -152,6 +155,24 @@ struct DeviceMesh {
   BlockSeg* gblk = nullptr;   // gather blocks (64 vertices each)
   BlockSeg* vblk = nullptr;   // vector-pass blocks (256 entries each)
   BlockSeg* rblk = nullptr;   // r0-dot blocks (1024 entries each)
+  BlockSeg* xblk = nullptr;   // vertex blocks (256 vertices each)
+  int vtx_blocks = 1;
+  // Partial batches (some simulations not stepping): every launch covers
+  // only the stepping simulations' blocks and solve items. Host copies of the
+  // full tables, the level items of every supernode (bottom levels included)
+  // with each simulation's range per level, and the compacted lists of the
+  // current step (device, filled from pinned staging in one copy).
+  std::vector<BlockSeg> eblk_h, gblk_h, vblk_h, rblk_h, xblk_h;
+  std::vector<int> sim_kind_h;  // element-pass kind of each simulation
+  std::vector<std::vector<ItemDesc>> lv_fw_h, lv_bw_h;  // per level
+  std::vector<std::vector<int>> lv_fw_at, lv_bw_at;     // per level: S + 1 starts
+  int compact = 0;            // the current step uses the compacted lists
+  char* cbuf = nullptr;       // device: compacted block lists, then items
+  char* cstage = nullptr;     // pinned staging of cbuf
+  size_t cbuf_bytes = 0;
+  struct { int off, n; } c_elem[kElemKinds] = {}, c_gat = {}, c_vec = {}, c_rd = {}, c_vtx = {};
+  size_t c_items_off = 0;     // byte offset of the compacted items in cbuf
+  std::vector<Level> c_levels;
   int* dir_count = nullptr;   // simulations whose direction is being formed (solve gate)
   // element data (internal tet order)
   int* tv = nullptr;          // T x 4 internal vertex ids

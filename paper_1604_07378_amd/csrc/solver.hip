@@ -79,10 +79,11 @@ __device__ __forceinline__ double sum_partials(const double* p, int n, double* s
   return r;
 }
 
-// Block sums of N values per thread, written as out[d * nb + blockIdx.x]:
-// wave sums, then the NW wave results added in wave order (sh: NW * N).
+// Block sums of N values per thread, written as out[d * nb + slot]: wave
+// sums, then the NW wave results added in wave order (sh: NW * N).
 template <int N, int NW = BS / 64>
-__device__ __forceinline__ void block_sums_to(double (&v)[N], double* sh, double* out, int nb) {
+__device__ __forceinline__ void block_sums_to(double (&v)[N], double* sh, double* out, int nb,
+                                              int slot) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
   for (int d = 0; d < N; ++d) v[d] = wave_sum(v[d]);
@@ -94,7 +95,7 @@ __device__ __forceinline__ void block_sums_to(double (&v)[N], double* sh, double
   for (int d = threadIdx.x; d < N; d += NW * 64) {
     double t = sh[d];
     for (int k = 1; k < NW; ++k) t += sh[k * N + d];
-    out[(size_t)d * nb + blockIdx.x] = t;
+    out[(size_t)d * nb + slot] = t;
   }
 }
 
@@ -135,17 +136,18 @@ __device__ __forceinline__ int pair_slot(const Ctl* c, int a, int slots) {
 // simulation's first free vertex resets its control block and statistics.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(BS)
-k_step_init(int n, int nf, const int* __restrict__ vsim, const int* __restrict__ run,
+k_step_init(const BlockSeg* __restrict__ blk, int nf, const int* __restrict__ run,
             const SimSeg* __restrict__ seg, const int* __restrict__ vperm,
             const double* __restrict__ mass, const double* __restrict__ x,
             const double* __restrict__ v, const double* __restrict__ fext, double h, double ax,
             double ay, double az, double* __restrict__ x0, double* __restrict__ y,
             double* __restrict__ X, Ctl* __restrict__ ctl, SimStat* __restrict__ stat, int slots,
             int* __restrict__ dir_count) {
-  const int i = blockIdx.x * BS + threadIdx.x;
-  if (i == 0) *dir_count = 0;
-  if (i >= n) return;
-  const int s = vsim[i];
+  const BlockSeg sg = blk[blockIdx.x];
+  const int i = sg.a0 + threadIdx.x;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *dir_count = 0;
+  if (i >= sg.a1) return;
+  const int s = sg.sim;
   const int on = run[s];
   if (i == seg[s].vf0) {
     Ctl* c = ctl + s;
@@ -349,7 +351,7 @@ constexpr int kWideBS = 1024;  // threads per block of the r0 dots
 
 template <int SL, typename FT>
 __global__ void __launch_bounds__(BS)
-k_gather(int probe, const BlockSeg* __restrict__ blk, size_t n3, int slots, int inc_w,
+k_gather(int probe, const BlockSeg* __restrict__ blk, int nb, size_t n3, int slots, int inc_w,
          const int* __restrict__ inc_tab, const FT* __restrict__ fel,
          const double* __restrict__ mass, const double* __restrict__ y, double inv_h2,
          double* __restrict__ X, const double* __restrict__ d, double* __restrict__ Gr,
@@ -444,7 +446,7 @@ k_gather(int probe, const BlockSeg* __restrict__ blk, size_t n3, int slots, int 
       }
     }
   }
-  block_sums_to<ND>(acc, sh, part, gridDim.x);
+  block_sums_to<ND>(acc, sh, part, nb, sg.slot);
 }
 
 // Curvature safeguard, ring bookkeeping and the Gram matrix; then the first
@@ -553,7 +555,8 @@ k_qform(const BlockSeg* __restrict__ blk, size_t n3, int slots, const double* __
 // [j] = t_j . r0, [SL] = grad . r0.
 template <int SL>
 __global__ void __launch_bounds__(kWideBS)
-k_rdots(const BlockSeg* __restrict__ blk, size_t n3, int slots, const double* __restrict__ r0,
+k_rdots(const BlockSeg* __restrict__ blk, int nb, size_t n3, int slots,
+        const double* __restrict__ r0,
         const double* __restrict__ grad, const double* __restrict__ Tall,
         double* __restrict__ part, const Ctl* __restrict__ ctl) {
   constexpr int ND = SL + 1;
@@ -582,7 +585,7 @@ k_rdots(const BlockSeg* __restrict__ blk, size_t n3, int slots, const double* __
     for (int j = 0; j < SL; ++j)
       if (use[j]) acc[j] = Tall[(size_t)j * n3 + i] * r;
   }
-  block_sums_to<ND, kWideBS / 64>(acc, sh, part, gridDim.x);
+  block_sums_to<ND, kWideBS / 64>(acc, sh, part, nb, sg.slot);
 }
 
 // Second loop on scalars, oldest pair first:
@@ -721,13 +724,14 @@ k_ls_decide(int K, int max_halvings, double gamma, double backtrack,
 // End of step: x' = final iterate, v' = (x' - x)/h; pinned: x' = x, v' = 0.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(BS)
-k_finalize(int n, int nf, const int* __restrict__ vsim, const int* __restrict__ run,
+k_finalize(const BlockSeg* __restrict__ blk, int nf, const int* __restrict__ run,
            const int* __restrict__ vperm, const double* __restrict__ x0,
            const double* __restrict__ X, const double* __restrict__ d, double inv_h,
            const Ctl* __restrict__ ctl, double* __restrict__ xo, double* __restrict__ vo) {
-  const int i = blockIdx.x * BS + threadIdx.x;
-  if (i >= n) return;
-  const int s = vsim[i];
+  const BlockSeg sg = blk[blockIdx.x];
+  const int i = sg.a0 + threadIdx.x;
+  if (i >= sg.a1) return;
+  const int s = sg.sim;
   if (!run[s]) return;
   const Ctl* c = ctl + s;
   if (c->phase != PH_DONE) return;
@@ -862,6 +866,45 @@ __global__ void __launch_bounds__(BS) k_ctl_timing(int S, Ctl* __restrict__ ctl)
 inline int nblk(int64_t n) { return (int)std::max<int64_t>(1, (n + BS - 1) / BS); }
 
 // want: phase the simulations must be in (-1: all); trial: positions x_k + alpha d.
+// Launch lists of the current step: the full block tables, or (partial
+// batch) the compacted lists of the stepping simulations.
+struct Lists {
+  const BlockSeg* elem[kElemKinds];
+  int elem_n[kElemKinds];
+  const BlockSeg *gat, *vec, *rd, *vtx;
+  int gat_n, vec_n, rd_n, vtx_n;
+};
+Lists lists_of(const DeviceMesh& D) {
+  Lists L;
+  for (int k = 0; k < kElemKinds; ++k) { L.elem[k] = nullptr; L.elem_n[k] = 0; }
+  if (D.compact) {
+    const BlockSeg* b = reinterpret_cast<const BlockSeg*>(D.cbuf);
+    for (int k = 0; k < kElemKinds; ++k) { L.elem[k] = b + D.c_elem[k].off; L.elem_n[k] = D.c_elem[k].n; }
+    L.gat = b + D.c_gat.off; L.gat_n = D.c_gat.n;
+    L.vec = b + D.c_vec.off; L.vec_n = D.c_vec.n;
+    L.rd = b + D.c_rd.off; L.rd_n = D.c_rd.n;
+    L.vtx = b + D.c_vtx.off; L.vtx_n = D.c_vtx.n;
+    return L;
+  }
+  if (D.single_type >= 0) {
+    L.elem[D.single_type] = D.eblk;
+    L.elem_n[D.single_type] = D.elem_blocks;
+  } else {
+    bool any = false;
+    for (int k = 0; k < kElemKinds; ++k) {
+      L.elem[k] = D.eblk_kind[k];
+      L.elem_n[k] = D.eblk_kind_n[k];
+      any |= D.eblk_kind_n[k] > 0;
+    }
+    if (!any) { L.elem[kElemKinds - 1] = D.eblk; L.elem_n[kElemKinds - 1] = D.elem_blocks; }
+  }
+  L.gat = D.gblk; L.gat_n = D.gather_blocks;
+  L.vec = D.vblk; L.vec_n = D.vec3_blocks;
+  L.rd = D.rblk; L.rd_n = D.rdots_blocks;
+  L.vtx = D.xblk; L.vtx_n = D.vtx_blocks;
+  return L;
+}
+
 // One launch of the element pass per material kind present (a single launch
 // when every tet has the same type), each with its specialised material code.
 void launch_elem(DeviceMesh& D, hipStream_t st, int want, int trial, double* part,
@@ -890,17 +933,9 @@ void launch_elem(DeviceMesh& D, hipStream_t st, int want, int trial, double* par
     }
   };
 #undef QN_ELEM
-  if (D.single_type >= 0) {
-    one(D.single_type, D.eblk, D.elem_blocks);
-    return;
-  }
-  bool any = false;
+  const Lists L = lists_of(D);
   for (int k = 0; k < kElemKinds; ++k)
-    if (D.eblk_kind_n[k] > 0) {
-      one(k < kElemKinds - 1 ? k : -1, D.eblk_kind[k], D.eblk_kind_n[k]);
-      any = true;
-    }
-  if (!any) one(-1, D.eblk, D.elem_blocks);
+    if (L.elem_n[k] > 0) one(k < kElemKinds - 1 ? k : -1, L.elem[k], L.elem_n[k]);
 }
 
 // Partials layout: gather dots (kGatherDots x gather_blocks), r0 dots
@@ -936,16 +971,19 @@ inline int slots_variant(int m) { return m <= 8 ? m + 1 : kSlots; }
 
 void launch_gather(DeviceMesh& D, hipStream_t st, int probe, int m, double* part) {
   const size_t n3 = 3 * (size_t)D.nf;
+  const Lists L = lists_of(D);
+  if (L.gat_n == 0) return;
+  const int nb = D.gather_blocks;
 #define QN_GATHER(SL)                                                                          \
   do {                                                                                        \
     if (D.mixed)                                                                              \
-      hipLaunchKernelGGL((k_gather<SL, float>), dim3(D.gather_blocks), dim3(BS), 0, st, probe, \
-                         D.gblk, n3, m + 1, D.inc_w, D.inc_tab,                                \
+      hipLaunchKernelGGL((k_gather<SL, float>), dim3(L.gat_n), dim3(BS), 0, st, probe, L.gat,  \
+                         nb, n3, m + 1, D.inc_w, D.inc_tab,                                    \
                          reinterpret_cast<const float*>(D.fel), D.mass, D.y,                   \
                          1.0 / (D.h * D.h), D.X, D.d, D.G, D.Sv, D.Tv, D.ctl, part);           \
     else                                                                                      \
-      hipLaunchKernelGGL((k_gather<SL, double>), dim3(D.gather_blocks), dim3(BS), 0, st,       \
-                         probe, D.gblk, n3, m + 1, D.inc_w, D.inc_tab, D.fel, D.mass, D.y,     \
+      hipLaunchKernelGGL((k_gather<SL, double>), dim3(L.gat_n), dim3(BS), 0, st, probe, L.gat, \
+                         nb, n3, m + 1, D.inc_w, D.inc_tab, D.fel, D.mass, D.y,                \
                          1.0 / (D.h * D.h), D.X, D.d, D.G, D.Sv, D.Tv, D.ctl, part);           \
   } while (0)
   QN_SLOTS_DISPATCH(slots_variant(m), QN_GATHER)
@@ -971,15 +1009,17 @@ void launch_direction(DeviceMesh& D, const StepParams& P, hipStream_t st, int cy
   Parts pp = parts_of(D);
   const int m = P.history, slots = m + 1, slv = slots_variant(m);
   const size_t n3 = 3 * (size_t)D.nf;
+  const Lists L = lists_of(D);
+  if (L.vec_n == 0) return;
 #define QN_QFORM(SL)                                                                           \
-  hipLaunchKernelGGL(k_qform<SL>, dim3(D.vec3_blocks), dim3(BS), 0, st, D.vblk, n3, slots, D.G, \
+  hipLaunchKernelGGL(k_qform<SL>, dim3(L.vec_n), dim3(BS), 0, st, L.vec, n3, slots, D.G,       \
                      D.Tv, D.q, D.ctl)
   QN_SLOTS_DISPATCH(slv, QN_QFORM)
 #undef QN_QFORM
   launch_solve(D, st, D.q, D.r, D.dir_count, D.S > 1 ? D.ctl : nullptr);
 #define QN_RDOTS(SL)                                                                           \
-  hipLaunchKernelGGL(k_rdots<SL>, dim3(D.rdots_blocks), dim3(kWideBS), 0, st, D.rblk, n3,       \
-                     slots, D.r, D.G, D.Tv, pp.rdots, D.ctl)
+  hipLaunchKernelGGL(k_rdots<SL>, dim3(L.rd_n), dim3(kWideBS), 0, st, L.rd, D.rdots_blocks,   \
+                     n3, slots, D.r, D.G, D.Tv, pp.rdots, D.ctl)
   QN_SLOTS_DISPATCH(slv, QN_RDOTS)
 #undef QN_RDOTS
 #define QN_COEF(SL)                                                                            \
@@ -988,7 +1028,7 @@ void launch_direction(DeviceMesh& D, const StepParams& P, hipStream_t st, int cy
   QN_SLOTS_DISPATCH(slv, QN_COEF)
 #undef QN_COEF
 #define QN_DFORM(SL)                                                                           \
-  hipLaunchKernelGGL(k_dform<SL>, dim3(D.vec3_blocks), dim3(BS), 0, st, D.vblk, n3, slots, cyc, \
+  hipLaunchKernelGGL(k_dform<SL>, dim3(L.vec_n), dim3(BS), 0, st, L.vec, n3, slots, cyc,       \
                      D.Sv, D.r, D.d, D.ctl)
   QN_SLOTS_DISPATCH(slv, QN_DFORM)
 #undef QN_DFORM
@@ -1006,8 +1046,9 @@ void launch_trials(DeviceMesh& D, const StepParams& P, hipStream_t st, int trial
 
 void launch_finalize(DeviceMesh& D, const StepParams& P, hipStream_t st, double* xo,
                      double* vo) {
-  hipLaunchKernelGGL(k_finalize, dim3(nblk(D.n)), dim3(BS), 0, st, D.n, D.nf, D.vsim, D.run,
-                     D.vperm, D.x0, D.X, D.d, 1.0 / P.h, D.ctl, xo, vo);
+  const Lists L = lists_of(D);
+  hipLaunchKernelGGL(k_finalize, dim3(L.vtx_n), dim3(BS), 0, st, L.vtx, D.nf, D.run, D.vperm,
+                     D.x0, D.X, D.d, 1.0 / P.h, D.ctl, xo, vo);
 }
 
 void drop_graph(DeviceMesh& D) {
@@ -1034,10 +1075,12 @@ void dev_free(DeviceMesh& D) {
                   D.v0, D.y, D.X, D.G, D.d, D.r, D.q, D.z, D.Sv, D.Tv, D.fel,
                   D.part, D.psi, D.ctl, D.stat, D.tperm, D.top_t,
                   D.sub_fw, D.sub_bw, D.sub_fw_ptr, D.sub_bw_ptr,
-                  D.seg, D.vsim, D.run, D.eblk, D.gblk, D.vblk, D.rblk, D.dir_count};
+                  D.seg, D.vsim, D.run, D.eblk, D.gblk, D.vblk, D.rblk, D.xblk, D.dir_count,
+                  D.cbuf};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (D.stat_host) (void)hipHostFree(D.stat_host);
+  if (D.cstage) (void)hipHostFree(D.cstage);
   if (D.run_host) (void)hipHostFree(D.run_host);
   if (D.stream) (void)hipStreamDestroy((hipStream_t)D.stream);
   for (void* e : D.ev)
@@ -1098,10 +1141,65 @@ int dev_alloc(DeviceMesh& D, std::string& err) {
 
 int dev_set_run(DeviceMesh& D, const int* run_flags, void* stream, std::string& err) {
   hipStream_t st = (hipStream_t)(stream ? stream : D.stream);
-  // the previous copy out of run_host must be done before it is rewritten
+  // the previous copies out of the pinned staging must be done before it is rewritten
   HIP_OK(hipStreamSynchronize(st));
-  for (int s = 0; s < D.S; ++s) D.run_host[s] = run_flags[s] ? 1 : 0;
+  int running = 0;
+  for (int s = 0; s < D.S; ++s) running += (D.run_host[s] = run_flags[s] ? 1 : 0);
   HIP_OK(hipMemcpyAsync(D.run, D.run_host, sizeof(int) * D.S, hipMemcpyHostToDevice, st));
+  D.compact = 0;
+  if (!D.cbuf || running == D.S || running == 0) return 0;
+  // partial batch: the stepping simulations' blocks and level items, packed
+  // into the staging buffer in the layout of cbuf
+  char* base = D.cstage;
+  size_t off = 0;
+  auto put = [&](const std::vector<BlockSeg>& full, int SimSeg::*b0, int SimSeg::*b1, int kind)
+      -> decltype(D.c_gat) {
+    decltype(D.c_gat) r;
+    r.off = (int)(off / sizeof(BlockSeg));
+    r.n = 0;
+    for (int s = 0; s < D.S; ++s) {
+      if (!D.run_host[s] || (kind >= 0 && D.sim_kind_h[s] != kind)) continue;
+      const SimSeg& g = D.seg_h[s];
+      const int n = g.*b1 - g.*b0;
+      std::memcpy(base + off, full.data() + g.*b0, n * sizeof(BlockSeg));
+      off += n * sizeof(BlockSeg);
+      r.n += n;
+    }
+    return r;
+  };
+  for (int k = 0; k < kElemKinds; ++k) D.c_elem[k] = put(D.eblk_h, &SimSeg::eb0, &SimSeg::eb1, k);
+  D.c_gat = put(D.gblk_h, &SimSeg::gb0, &SimSeg::gb1, -1);
+  D.c_vec = put(D.vblk_h, &SimSeg::vb0, &SimSeg::vb1, -1);
+  D.c_rd = put(D.rblk_h, &SimSeg::rb0, &SimSeg::rb1, -1);
+  D.c_vtx = put(D.xblk_h, &SimSeg::xb0, &SimSeg::xb1, -1);
+  off = (off + 63) / 64 * 64;
+  D.c_items_off = off;
+  const int L = (int)D.lv_fw_h.size();
+  D.c_levels.assign(L, Level{0, 0, 0, 0});
+  int ni = 0;
+  auto put_items = [&](const std::vector<ItemDesc>& lv, const std::vector<int>& at) {
+    for (int s = 0; s < D.S; ++s) {
+      if (!D.run_host[s]) continue;
+      const int n = at[s + 1] - at[s];
+      std::memcpy(base + off, lv.data() + at[s], n * sizeof(ItemDesc));
+      off += n * sizeof(ItemDesc);
+      ni += n;
+    }
+  };
+  for (int l = 0; l < L; ++l) {
+    D.c_levels[l].fw_begin = ni;
+    put_items(D.lv_fw_h[l], D.lv_fw_at[l]);
+    D.c_levels[l].fw_end = ni;
+    D.c_levels[l].bw_begin = ni;
+    put_items(D.lv_bw_h[l], D.lv_bw_at[l]);
+    D.c_levels[l].bw_end = ni;
+  }
+  if (off > D.cbuf_bytes) {
+    err = "compacted launch lists exceed their buffer";
+    return QNSIM_E_DEVICE;
+  }
+  HIP_OK(hipMemcpyAsync(D.cbuf, D.cstage, off, hipMemcpyHostToDevice, st));
+  D.compact = 1;
   return 0;
 }
 
@@ -1118,8 +1216,9 @@ int enqueue_step(DeviceMesh& D, const StepParams& P, hipStream_t st, const doubl
                  const double* v, const double* fext, double* xo, double* vo) {
   Parts pp = parts_of(D);
   const int K = P.iterations;
-  hipLaunchKernelGGL(k_step_init, dim3(nblk(D.n)), dim3(BS), 0, st, D.n, D.nf, D.vsim, D.run,
-                     D.seg, D.vperm, D.mass, x, v, fext, P.h, P.grav[0], P.grav[1], P.grav[2],
+  const Lists L = lists_of(D);
+  hipLaunchKernelGGL(k_step_init, dim3(L.vtx_n), dim3(BS), 0, st, L.vtx, D.nf, D.run, D.seg,
+                     D.vperm, D.mass, x, v, fext, P.h, P.grav[0], P.grav[1], P.grav[2],
                      D.x0, D.y, D.X, D.ctl, D.stat, D.slots, D.dir_count);
   launch_elem(D, st, PH_INIT, 0, pp.elem, nullptr);
   hipLaunchKernelGGL(k_init_decide, dim3(D.S), dim3(BS), 0, st, (int)PH_INIT, D.seg, pp.elem,
@@ -1198,7 +1297,7 @@ int dev_step(DeviceMesh& D, const StepParams& P, const double* x, const double* 
   const int K = P.iterations;
   // the cycle tags of a continuation follow the fixed sequence's last one
   int cyc = K - 1;
-  if (!(P.graph && launch_step_graph(D, P, st, x, v, fext, xo, vo))) {
+  if (!(P.graph && !D.compact && launch_step_graph(D, P, st, x, v, fext, xo, vo))) {
     (void)hipGetLastError();
     cyc = enqueue_step(D, P, st, x, v, fext, xo, vo);
   }

@@ -251,11 +251,20 @@ __device__ __forceinline__ void bwd_item(const ItemDesc& d, const double* __rest
     cp[k] = Bb + d.blk + bw_col_off(ok ? c : 0, m) - (ok ? c : 0);
     any |= ok;
   }
+  // rows are assigned to lanes by their index modulo L (lane gl takes rows
+  // gl, gl + L, ... in ascending order), so that a column's sum has the same
+  // order in every kernel and every split of the columns into items
+  const int cbase = cst[0] - cst[0] % L;
+  auto first_row = [&](int from) {  // this lane's first row >= from
+    int i = cbase + gl;
+    if (i < from) i += ((from - i + L - 1) / L) * L;
+    return i;
+  };
   // first block iteration of the first chunk
   double b[4][4];
   {
     const int i0 = d.begin, i1 = min(m, i0 + TCHUNK);
-    const int i = max(i0, cst[0]) + gl;
+    const int i = first_row(i0);
 #pragma unroll
     for (int k = 0; k < 4; ++k)
 #pragma unroll
@@ -292,8 +301,9 @@ __device__ __forceinline__ void bwd_item(const ItemDesc& d, const double* __rest
     __syncthreads();
     // the group's (up to) 4 columns advance together: 16 loads in flight per lane
     if (any) {
-      for (int i = max(i0, cst[0]) + gl; i < i1; i += 4 * L) {
-        if (i0 > d.begin || i != max(i0, cst[0]) + gl) {
+      const int istart = first_row(i0);
+      for (int i = istart; i < i1; i += 4 * L) {
+        if (i0 > d.begin || i != istart) {
 #pragma unroll
           for (int k = 0; k < 4; ++k)
 #pragma unroll
@@ -511,12 +521,16 @@ __device__ __forceinline__ void bwd_wave_item(const ItemDesc& d, const double* _
     cst[k] = ok ? c : m;
     cp[k] = Bb + d.blk + bw_col_off(ok ? c : 0, m) - (ok ? c : 0);
   }
+  // rows assigned to lanes by their index modulo L, as in the level kernel
+  const int cbase = cst[0] - cst[0] % L;
+  int istart = cbase + gl;
+  if (istart < d.begin) istart += ((d.begin - istart + L - 1) / L) * L;
   double b[4][4];
 #pragma unroll
   for (int k = 0; k < 4; ++k)
 #pragma unroll
     for (int uu = 0; uu < 4; ++uu) {
-      const int ii = cst[0] + gl + uu * L;
+      const int ii = istart + uu * L;
       b[k][uu] = (ii >= cst[k] && ii < m) ? cp[k][ii] : 0.0;
     }
   int g[KC];
@@ -549,8 +563,8 @@ __device__ __forceinline__ void bwd_wave_item(const ItemDesc& d, const double* _
   double a[4][3];
 #pragma unroll
   for (int k = 0; k < 4; ++k) a[k][0] = a[k][1] = a[k][2] = 0.0;
-  for (int i = cst[0] + gl; i < m; i += 4 * L) {
-    if (i != cst[0] + gl) {
+  for (int i = istart; i < m; i += 4 * L) {
+    if (i != istart) {
 #pragma unroll
       for (int k = 0; k < 4; ++k)
 #pragma unroll
@@ -719,6 +733,24 @@ k_top_gemv(const double* __restrict__ Sinv, const double* __restrict__ t, int n,
 
 void launch_solve(DeviceMesh& D, hipStream_t st, const double* q, double* r, const int* gate,
                   const Ctl* sim_ctl) {
+  if (D.compact) {
+    // partial batch: every level of the stepping simulations, one launch each
+    const ItemDesc* items = reinterpret_cast<const ItemDesc*>(D.cbuf + D.c_items_off);
+    const int L = (int)D.c_levels.size();
+    for (int l = 0; l < L; ++l) {
+      const int n = D.c_levels[l].fw_end - D.c_levels[l].fw_begin;
+      if (n > 0)
+        hipLaunchKernelGGL(k_solve_fwd, dim3(n), dim3(TS), 0, st, items + D.c_levels[l].fw_begin,
+                           D.Bf, D.rel, q, D.z, D.vp, gate, sim_ctl);
+    }
+    for (int l = L - 1; l >= 0; --l) {
+      const int n = D.c_levels[l].bw_end - D.c_levels[l].bw_begin;
+      if (n > 0)
+        hipLaunchKernelGGL(k_solve_bwd, dim3(n), dim3(TS), 0, st, items + D.c_levels[l].bw_begin,
+                           D.Bb, D.rows, D.z, r, gate, sim_ctl);
+    }
+    return;
+  }
   const int L = (int)D.levels.size();
   if (D.sub_tasks > 0)
     hipLaunchKernelGGL(k_solve_fwd_sub, dim3(D.sub_tasks), dim3(kSubThreads), 0, st, D.sub_fw,

@@ -196,6 +196,24 @@ int upload_sims(const std::vector<const qnsim*>& sims, const qnsim_options& opt,
     while (Lsub < sparse_levels && maxm[Lsub] <= cap) ++Lsub;
     if (Lsub < 2) Lsub = 0;
   }
+  // Work items of a supernode for the per-level kernels (appended to fw and
+  // bw; returns the number of forward items). Forward: groups of Lf lanes per
+  // row, up to 4 rows per group; backward: groups of Lb lanes per column, up
+  // to 4 columns per group.
+  auto level_items = [&](int s, std::vector<int4>& fw, std::vector<int4>& bw) {
+    const int nc = F.sn[s].ncol, m = F.sn[s].m();
+    const int Lf = clampi(pow2ceil((nc + 3) / 4), 4, 64), sf = 4 * (64 / Lf);
+    const int rpg_f = clampi(((16384 + nc - 1) / nc + sf - 1) / sf, 1, 4);
+    const int rows_item = sf * rpg_f;
+    for (int r0 = 0; r0 < m; r0 += rows_item)
+      fw.push_back(make_int4(s, r0, std::min(m, r0 + rows_item), Lf));
+    const int Lb = clampi(pow2ceil((m + 3) / 4), 4, 64), sb = 4 * (64 / Lb);
+    const int rpg_b = clampi(((16384 + m - 1) / m + sb - 1) / sb, 1, 4);
+    const int cols_item = sb * rpg_b;
+    for (int c0 = 0; c0 < nc; c0 += cols_item)
+      bw.push_back(make_int4((int)(0x80000000u | (unsigned)s), c0, std::min(nc, c0 + cols_item), Lb));
+    return (m + rows_item - 1) / rows_item;
+  };
   for (int s = 0; s < ns; ++s) {
     const Supernode& S = F.sn[s];
     const int nc = S.ncol, m = S.m();
@@ -227,21 +245,9 @@ int upload_sims(const std::vector<const qnsim*>& sims, const qnsim_options& opt,
       I.fw_items = I.bw_items = 0;  // one-wave items, built per subtree below
       continue;
     }
-    // forward items: groups of Lf lanes per row, up to 4 rows per group
-    const int Lf = clampi(pow2ceil((nc + 3) / 4), 4, 64), sf = 4 * (64 / Lf);
-    const int rpg_f = clampi(((16384 + nc - 1) / nc + sf - 1) / sf, 1, 4);
-    const int rows_item = sf * rpg_f;
-    for (int r0 = 0; r0 < m; r0 += rows_item)
-      fw_by_level[S.level].push_back(make_int4(s, r0, std::min(m, r0 + rows_item), Lf));
-    I.fw_items = (m + rows_item - 1) / rows_item;
-    // backward items: groups of Lb lanes per column, up to 4 columns per group
-    const int Lb = clampi(pow2ceil((m + 3) / 4), 4, 64), sb = 4 * (64 / Lb);
-    const int rpg_b = clampi(((16384 + m - 1) / m + sb - 1) / sb, 1, 4);
-    const int cols_item = sb * rpg_b;
-    for (int c0 = 0; c0 < nc; c0 += cols_item)
-      bw_by_level[S.level].push_back(
-          make_int4((int)(0x80000000u | (unsigned)s), c0, std::min(nc, c0 + cols_item), Lb));
-    I.bw_items = (nc + cols_item - 1) / cols_item;
+    const size_t nb_before = bw_by_level[S.level].size();
+    I.fw_items = level_items(s, fw_by_level[S.level], bw_by_level[S.level]);
+    I.bw_items = (int)(bw_by_level[S.level].size() - nb_before);
   }
   // Update slots: supernode P owns K(P) layers of m(P) x 3 doubles in its own
   // row space, K(P) = the largest number of children that update one row of
@@ -522,7 +528,7 @@ int upload_sims(const std::vector<const qnsim*>& sims, const qnsim_options& opt,
   // at its own first tet / free vertex / entry, as when it runs alone
   {
     std::vector<SimSeg> seg(S);
-    std::vector<BlockSeg> eb, gb, vb, rb;
+    std::vector<BlockSeg> eb, gb, vb, rb, xb;
     auto mk = [](int sim, int a0, int a1, int b0, int b1) {
       BlockSeg x;
       x.sim = sim; x.a0 = a0; x.a1 = a1; x.b0 = b0; x.b1 = b1; x.slot = x.pad1 = x.pad2 = 0;
@@ -551,7 +557,16 @@ int upload_sims(const std::vector<const qnsim*>& sims, const qnsim_options& opt,
       g.rb0 = (int)rb.size();
       for (int e = 0; e < ne3; e += 1024) rb.push_back(mk(s, e0 + e, e0 + std::min(ne3, e + 1024), 0, 0));
       g.rb1 = (int)rb.size();
+      // vertex blocks: the free range, then the pinned range
+      const int np = c->n - c->nf;
+      g.xb0 = (int)xb.size();
+      for (int v = 0; v < c->nf; v += 256) xb.push_back(mk(s, vf0[s] + v, vf0[s] + std::min(c->nf, v + 256), 0, 0));
+      for (int v = 0; v < np; v += 256) xb.push_back(mk(s, vp0[s] + v, vp0[s] + std::min(np, v + 256), 0, 0));
+      g.xb1 = (int)xb.size();
+      g.pad0 = g.pad1 = 0;
     }
+    for (auto* tab : {&eb, &gb, &vb, &rb, &xb})
+      for (size_t i = 0; i < tab->size(); ++i) (*tab)[i].slot = (int)i;
     // self-check: every tet, free vertex and entry in exactly one block of its simulation
     {
       std::vector<char> ct(T, 0), cv(nf, 0), cg(nf, 0), ce(3 * (size_t)nf, 0), cr(3 * (size_t)nf, 0);
@@ -572,11 +587,23 @@ int upload_sims(const std::vector<const qnsim*>& sims, const qnsim_options& opt,
         if (x.a1 - x.a0 > 1024) FAIL(QNSIM_E_DEVICE, "blocks: dot block too large");
         for (int e = x.a0; e < x.a1; ++e) { if (vsim[e / 3] != x.sim) FAIL(QNSIM_E_DEVICE, "blocks: entry outside its simulation"); cr[e]++; }
       }
+      {
+        std::vector<char> cx(n, 0);
+        for (const BlockSeg& x : xb) {
+          if (x.a1 - x.a0 > 256) FAIL(QNSIM_E_DEVICE, "blocks: vertex block too large");
+          for (int v = x.a0; v < x.a1; ++v) { if (vsim[v] != x.sim) FAIL(QNSIM_E_DEVICE, "blocks: vertex outside its simulation"); cx[v]++; }
+        }
+        for (int v = 0; v < n; ++v) if (cx[v] != 1) FAIL(QNSIM_E_DEVICE, "blocks: vertex not covered once");
+      }
       for (int t = 0; t < T; ++t) if (ct[t] != 1) FAIL(QNSIM_E_DEVICE, "blocks: tet not covered once");
       for (int v = 0; v < nf; ++v) if (cv[v] != 1 || cg[v] != 1) FAIL(QNSIM_E_DEVICE, "blocks: vertex not covered once");
       for (size_t e = 0; e < 3 * (size_t)nf; ++e) if (ce[e] != 1 || cr[e] != 1) FAIL(QNSIM_E_DEVICE, "blocks: entry not covered once");
     }
-    for (size_t i = 0; i < eb.size(); ++i) eb[i].slot = (int)i;
+    D.sim_kind_h.assign(S, kElemKinds - 1);
+    for (int s = 0; s < S; ++s) {
+      const int t = D.single_type >= 0 ? D.single_type : sims[s]->single_type;
+      D.sim_kind_h[s] = t >= 0 && t < kElemKinds - 1 ? t : kElemKinds - 1;
+    }
     if (D.single_type < 0) {
       // one launch per material kind, each block keeping its partial slot
       std::vector<BlockSeg> kind[kElemKinds];
@@ -593,12 +620,64 @@ int upload_sims(const std::vector<const qnsim*>& sims, const qnsim_options& opt,
     D.gather_blocks = (int)gb.size();
     D.vec3_blocks = (int)vb.size();
     D.rdots_blocks = (int)rb.size();
+    D.vtx_blocks = (int)xb.size();
     D.seg_h = seg;
     UP(D.seg, seg);
     UP(D.eblk, eb);
     UP(D.gblk, gb);
     UP(D.vblk, vb);
     UP(D.rblk, rb);
+    UP(D.xblk, xb);
+    if (S > 1) {
+      // partial batches: host copies of the tables, and per-level items of
+      // every supernode (the bottom levels too) with each simulation's range
+      D.eblk_h = eb; D.gblk_h = gb; D.vblk_h = vb; D.rblk_h = rb; D.xblk_h = xb;
+      const int L = F.nlevels;
+      std::vector<std::vector<int4>> lf(L), lb(L);
+      std::vector<std::vector<int>> sim_f(L), sim_b(L);
+      for (int sn = 0; sn < ns; ++sn) {
+        const int l = F.sn[sn].level;
+        const size_t f0 = lf[l].size(), b0 = lb[l].size();
+        level_items(sn, lf[l], lb[l]);
+        sim_f[l].resize(lf[l].size(), vsim[F.sn[sn].first]);
+        sim_b[l].resize(lb[l].size(), vsim[F.sn[sn].first]);
+        (void)f0; (void)b0;
+      }
+      D.lv_fw_h.assign(L, {});
+      D.lv_bw_h.assign(L, {});
+      D.lv_fw_at.assign(L, std::vector<int>(S + 1, 0));
+      D.lv_bw_at.assign(L, std::vector<int>(S + 1, 0));
+      size_t items_total = 0;
+      std::vector<int> cov_r(ns, 0), cov_c(ns, 0);
+      for (int l = 0; l < L; ++l) {
+        D.lv_fw_h[l] = to_desc(lf[l]);
+        D.lv_bw_h[l] = to_desc(lb[l]);
+        for (int pass = 0; pass < 2; ++pass) {
+          const std::vector<int>& sims_of = pass ? sim_b[l] : sim_f[l];
+          const std::vector<int4>& its = pass ? lb[l] : lf[l];
+          std::vector<int>& at = pass ? D.lv_bw_at[l] : D.lv_fw_at[l];
+          // items are in supernode order, hence in simulation order
+          for (size_t i = 0; i < sims_of.size(); ++i) {
+            if (i > 0 && sims_of[i] < sims_of[i - 1]) FAIL(QNSIM_E_DEVICE, "schedule: level items out of simulation order");
+            at[sims_of[i] + 1]++;
+            const int sn = its[i].x & 0x7fffffff;
+            (pass ? cov_c : cov_r)[sn] += its[i].z - its[i].y;
+          }
+          for (int s2 = 0; s2 < S; ++s2) at[s2 + 1] += at[s2];
+        }
+        items_total += lf[l].size() + lb[l].size();
+      }
+      for (int sn = 0; sn < ns; ++sn)
+        if (cov_r[sn] != F.sn[sn].m() || cov_c[sn] != F.sn[sn].ncol)
+          FAIL(QNSIM_E_DEVICE, "schedule: level items of a partial batch do not cover a supernode once");
+      D.cbuf_bytes = sizeof(BlockSeg) * (eb.size() + gb.size() + vb.size() + rb.size() + xb.size()) + 64 +
+                     sizeof(ItemDesc) * items_total;
+      hipError_t e = hipMalloc((void**)&D.cbuf, D.cbuf_bytes);
+      if (e != hipSuccess) FAIL(QNSIM_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+      D.bytes += D.cbuf_bytes;
+      e = hipHostMalloc((void**)&D.cstage, D.cbuf_bytes, hipHostMallocDefault);
+      if (e != hipSuccess) FAIL(QNSIM_E_NOMEM, std::string("hipHostMalloc: ") + hipGetErrorString(e));
+    }
   }
   return dev_alloc(D, err);
 }
