@@ -59,6 +59,8 @@ class Model:
     mat_groups: list            # [(kind, tet_ids, mu, lam, d2)]
     mu_t: np.ndarray
     lam_t: np.ndarray
+    kappa_t: np.ndarray         # (T,) fibre stiffness (0: no fibre term)
+    fdir_t: np.ndarray          # (T, 3) unit fibre directions
     h: float
     gravity: np.ndarray
     A: scipy.sparse.csc_matrix  # (n_f, n_f)
@@ -167,6 +169,10 @@ def build_model(rest, tets, pinned, materials, tet_mat=None, h=1.0 / 30.0,
     # per-tet parameters (plain bookkeeping, same arithmetic).
     mu_t = np.array([materials[i].mu for i in tet_mat])
     lam_t = np.array([materials[i].lam for i in tet_mat])
+    # anisotropic fibre term per tet (kappa = 0: none); unit directions
+    kap_m = np.array([float(getattr(m, "fiber_kappa", 0.0) or 0.0) for m in materials])
+    dir_m = np.array([_unit(getattr(m, "fiber_dir", None)) for m in materials])
+    kappa_t, fdir_t = kap_m[tet_mat], dir_m[tet_mat]
     merged = {}
     final = []
     for kind, ids, mu, lam, d2 in groups:
@@ -187,9 +193,16 @@ def build_model(rest, tets, pinned, materials, tet_mat=None, h=1.0 / 30.0,
     A = assemble_A(n, tets, Dm_inv, vol, k, mass, h, free_of)
     return Model(rest=rest, tets=tets, free=free, pinned=pinned, free_of=free_of,
                  Dm_inv=Dm_inv, vol=vol, mass=mass, k=k, mat_groups=final,
-                 mu_t=mu_t, lam_t=lam_t, h=h,
+                 mu_t=mu_t, lam_t=lam_t, kappa_t=kappa_t, fdir_t=fdir_t, h=h,
                  gravity=np.asarray(gravity, dtype=np.float64), A=A,
                  solve=make_solver(A))
+
+
+def _unit(d):
+    if d is None:
+        return np.array([1.0, 0.0, 0.0])
+    d = np.asarray(d, dtype=np.float64)
+    return d / np.linalg.norm(d)
 
 
 def deformation_gradients(model: Model, x: np.ndarray) -> np.ndarray:
@@ -211,6 +224,11 @@ def element_psi_P(model: Model, x: np.ndarray):
         p, P = mat.psi_and_P(kind, F[ids], mu, lam, d2)
         psi[ids] = p
         Pst[ids] = P
+    fib = np.nonzero(model.kappa_t > 0)[0]
+    if len(fib):  # anisotropic fibre term on top of the base material
+        p, P = mat.psi_P_fiber(F[fib], model.kappa_t[fib], model.fdir_t[fib])
+        psi[fib] += p
+        Pst[fib] += P
     return psi, Pst
 
 

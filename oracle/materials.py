@@ -199,6 +199,22 @@ def psi_P_valanis_landel(kind: int, F: np.ndarray, mu, lam, d2=None):
 
 
 # ---------------------------------------------------------------------------
+# Anisotropic fibre term (section 4, "Anisotropy"): added to a base material,
+#   Psi_f = kappa/2 (|F d| - 1)^2,  d the unit rest-pose fibre direction,
+#   P_f = dPsi_f/dF = kappa (|F d| - 1) / |F d| * (F d) d^T.
+# ---------------------------------------------------------------------------
+def psi_P_fiber(F: np.ndarray, kappa, d):
+    kappa = np.asarray(kappa, dtype=np.float64)
+    d = np.asarray(d, dtype=np.float64)
+    f = np.einsum("...ij,...j->...i", F, d)
+    ln = np.sqrt(np.einsum("...i,...i->...", f, f))
+    e = ln - 1.0
+    psi = 0.5 * kappa * e * e
+    P = (kappa * e / ln)[..., None, None] * np.einsum("...i,...j->...ij", f, d)
+    return psi, P
+
+
+# ---------------------------------------------------------------------------
 # Invariant forms (standard definitions; no SVD)
 # ---------------------------------------------------------------------------
 def psi_P_neohookean(F, mu, lam):

@@ -190,3 +190,53 @@ def test_stiffness_positive_for_workload_materials():
     for kind in (W.NEOHOOKEAN, W.STVK, W.SPLINE):
         m = W.make_material(kind, 1e5, 0.4)
         assert mat.stiffness(m.type, m.mu, m.lam, m.d2()) > 0
+
+
+# ---------------------------------------------------------------------------
+# Anisotropic fibre term (section 4, "Anisotropy"): kappa/2 (|F d| - 1)^2
+# ---------------------------------------------------------------------------
+KAPPA = 5.0 * MU
+FDIR = np.array([1.0, 2.0, -0.5]) / np.linalg.norm([1.0, 2.0, -0.5])
+
+
+def test_fiber_stress_is_energy_derivative():
+    F = _random_F(40, 11)
+    psi, P = mat.psi_P_fiber(F, KAPPA, FDIR)
+    eps = 1e-6
+    Pfd = np.zeros_like(P)
+    for i in range(3):
+        for j in range(3):
+            Fp = F.copy(); Fp[:, i, j] += eps
+            Fm = F.copy(); Fm[:, i, j] -= eps
+            Pfd[:, i, j] = (mat.psi_P_fiber(Fp, KAPPA, FDIR)[0] - mat.psi_P_fiber(Fm, KAPPA, FDIR)[0]) / (2 * eps)
+    assert np.abs(Pfd - P).max() / np.abs(P).max() < 1e-7
+
+
+@pytest.mark.parametrize("lam_s", [0.6, 1.0, 1.7])
+def test_fiber_uniaxial_closed_forms(lam_s):
+    """Stretch lam along d: Psi = kappa/2 (lam - 1)^2, P = kappa (lam - 1) d d^T;
+    stretch across d: no fibre energy or stress."""
+    along = np.eye(3) + (lam_s - 1.0) * np.outer(FDIR, FDIR)
+    psi, P = mat.psi_P_fiber(along[None], KAPPA, FDIR)
+    assert psi[0] == pytest.approx(0.5 * KAPPA * (lam_s - 1.0) ** 2, rel=1e-13, abs=1e-9)
+    assert np.abs(P[0] - KAPPA * (lam_s - 1.0) * np.outer(FDIR, FDIR)).max() < 1e-9 * KAPPA
+    e = np.cross(FDIR, [0.0, 0.0, 1.0]); e /= np.linalg.norm(e)
+    across = np.eye(3) + (lam_s - 1.0) * np.outer(e, e)
+    psi, P = mat.psi_P_fiber(across[None], KAPPA, FDIR)
+    assert abs(psi[0]) < 1e-20 * KAPPA and np.abs(P[0]).max() < 1e-12 * KAPPA
+
+
+def test_fiber_invariances():
+    """Frame invariance; invariance under rest rotations about the fibre axis
+    only (the term is transversely isotropic, not isotropic)."""
+    F = _random_F(20, 12)
+    psi, P = mat.psi_P_fiber(F, KAPPA, FDIR)
+    Q = _rot(3)
+    psi_q, P_q = mat.psi_P_fiber(Q @ F, KAPPA, FDIR)
+    assert np.abs(psi_q - psi).max() < 1e-12 * np.abs(psi).max()
+    assert np.abs(P_q - Q @ P).max() < 1e-12 * np.abs(P).max()
+    th = 0.7  # rotation about d (Rodrigues)
+    K = np.array([[0, -FDIR[2], FDIR[1]], [FDIR[2], 0, -FDIR[0]], [-FDIR[1], FDIR[0], 0]])
+    Rd = np.eye(3) + np.sin(th) * K + (1 - np.cos(th)) * K @ K
+    assert np.abs(mat.psi_P_fiber(F @ Rd, KAPPA, FDIR)[0] - psi).max() < 1e-12 * np.abs(psi).max()
+    assert np.abs(mat.psi_P_fiber(F @ _rot(4), KAPPA, FDIR)[0] - psi).max() > 1e-3 * np.abs(psi).max()

@@ -109,12 +109,12 @@ def test_A_is_spd_and_solve_is_exact():
     assert np.abs(lu.solve(q) - r).max() < 1e-12 * np.abs(r).max()
 
 
-@pytest.mark.parametrize("kind", [W.NEOHOOKEAN, W.STVK, W.SPLINE, W.COROTATED, W.POLYNOMIAL])
+@pytest.mark.parametrize("kind", [W.NEOHOOKEAN, W.STVK, W.SPLINE, W.COROTATED, W.POLYNOMIAL, "fiber"])
 def test_gradient_matches_finite_differences(kind):
     """grad g by central differences of g over every free coordinate."""
-    w = _small(kind=kind)
+    w = W.workload_fiber_cantilever(dims=(3, 2, 2)) if kind == "fiber" else _small(kind=kind)
     m = _model(w)
-    rng = np.random.default_rng(kind)
+    rng = np.random.default_rng(7 if kind == "fiber" else kind)
     x = w.rest + 0.01 * rng.normal(size=w.rest.shape)
     y = w.rest + 0.01 * rng.normal(size=w.rest.shape)
     x[m.pinned] = w.rest[m.pinned]
@@ -129,10 +129,10 @@ def test_gradient_matches_finite_differences(kind):
     assert np.abs(fd - g).max() < 1e-6 * np.abs(g).max()
 
 
-@pytest.mark.parametrize("kind", [W.NEOHOOKEAN, W.STVK, W.SPLINE])
+@pytest.mark.parametrize("kind", [W.NEOHOOKEAN, W.STVK, W.SPLINE, "fiber"])
 def test_element_forces_balance(kind):
     """Per tet: sum of vertex forces = 0 and sum of x_j x f_j = 0 (momentum)."""
-    w = _small(kind=kind)
+    w = W.workload_fiber_cantilever(dims=(3, 2, 2)) if kind == "fiber" else _small(kind=kind)
     m = _model(w)
     x = w.rest + 0.02 * np.random.default_rng(3).normal(size=w.rest.shape)
     _, P = fem.element_psi_P(m, x)

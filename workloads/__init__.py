@@ -14,6 +14,7 @@ from .grid import (  # noqa: F401
     workload_cantilever,
     workload_block,
     workload_mixed_cantilever,
+    workload_fiber_cantilever,
     workload_batch,
     workload_pool,
     spline_knots,

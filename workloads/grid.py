@@ -74,6 +74,9 @@ class Material:
     density: float = 1000.0
     # a'' at the 8 knots (absolute values, Pa) for SPLINE; zeros otherwise.
     spline_d2: Optional[np.ndarray] = None
+    # anisotropic fibre term kappa/2 (|F d| - 1)^2 on top (0: none)
+    fiber_kappa: float = 0.0
+    fiber_dir: Optional[np.ndarray] = None
 
     def d2(self) -> np.ndarray:
         if self.spline_d2 is None:
@@ -214,6 +217,21 @@ def workload_mixed_cantilever(E_seed: int = 0, jitter_seed: int = 0,
     w.materials = [make_material(NEOHOOKEAN, float(E), nu) for E in Es]
     w.tet_mat = np.arange(w.n_tets, dtype=np.int32)
     w.name = "cantilever10x3x3-neohookean-logE"
+    return w
+
+
+def workload_fiber_cantilever(jitter_seed: int = 0, kind: int = COROTATED, E: float = 1e5,
+                              nu: float = 0.4, kappa_over_mu: float = 5.0,
+                              direction=(1.0, 0.0, 1.0), dims=(10, 3, 3)) -> Workload:
+    """Cantilever with an anisotropic fibre term kappa/2 (|F d| - 1)^2 on a
+    base material (corotated, as in the paper's anisotropy example; kappa/mu
+    = 5 there); d a fixed unit rest-pose direction."""
+    w = workload_cantilever(jitter_seed=jitter_seed, dims=dims, kind=kind, E=E, nu=nu)
+    m = w.materials[0]
+    m.fiber_kappa = kappa_over_mu * m.mu
+    d = np.asarray(direction, dtype=np.float64)
+    m.fiber_dir = d / np.linalg.norm(d)
+    w.name = w.name + "-fiber"
     return w
 
 
