@@ -115,6 +115,12 @@ typedef struct {
   double lambda;
   double density;
   double spline_d2[8];
+  /* Anisotropic fibre term (section 4, "Anisotropy") added to the base
+   * material: fiber_kappa / 2 (|F d| - 1)^2 with d = fiber_dir / |fiber_dir|
+   * the rest-pose fibre direction. fiber_kappa = 0: none; > 0 needs a
+   * non-zero direction. It does not change the stiffness k of A. */
+  double fiber_kappa;
+  double fiber_dir[3];
 } qnsim_material;
 
 /* Per-step counters (filled by qnsim_step / qnsim_step_device when non-null). */

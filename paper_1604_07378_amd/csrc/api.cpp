@@ -337,8 +337,15 @@ int qnsim_set_materials(qnsim_t* c, int32_t n_mat, const qnsim_material* mats,
     if (q.type < QNSIM_NEOHOOKEAN || q.type > QNSIM_POLYNOMIAL)
       return fail(c, QNSIM_E_INVALID, "unknown material type");
     if (!std::isfinite(q.mu) || !std::isfinite(q.lambda) || !std::isfinite(q.density) ||
-        !finite_all(q.spline_d2, 8))
+        !finite_all(q.spline_d2, 8) || !std::isfinite(q.fiber_kappa) || !finite_all(q.fiber_dir, 3))
       return fail(c, QNSIM_E_NONFINITE, "non-finite material parameter");
+    if (q.fiber_kappa < 0.0) return fail(c, QNSIM_E_INVALID, "fiber_kappa must be >= 0");
+    const double dn = std::sqrt(q.fiber_dir[0] * q.fiber_dir[0] + q.fiber_dir[1] * q.fiber_dir[1] +
+                                q.fiber_dir[2] * q.fiber_dir[2]);
+    if (q.fiber_kappa > 0.0 && !(dn > 0.0))
+      return fail(c, QNSIM_E_INVALID, "fiber_dir must be non-zero when fiber_kappa > 0");
+    ms[i].fiber_kappa = q.fiber_kappa;
+    for (int j = 0; j < 3; ++j) ms[i].fiber_dir[j] = q.fiber_kappa > 0.0 ? q.fiber_dir[j] / dn : (j == 0 ? 1.0 : 0.0);
     if (!(q.density > 0.0)) return fail(c, QNSIM_E_INVALID, "density must be positive");
     ms[i].type = q.type;
     ms[i].mu = q.mu;

@@ -251,6 +251,25 @@ __device__ __forceinline__ bool material_eval(const DevMat& mat, const M3<R>& F,
   }
 }
 
+// Anisotropic fibre term (section 4, "Anisotropy") added to any base
+// material: Psi += kappa/2 (|F d| - 1)^2, P += kappa (|F d| - 1)/|F d| (F d) d^T,
+// formed from F in FP64 (|F d| - 1 is a small difference near rest) and added
+// to P in its precision. An infeasible state (Psi = +inf) is left as it is.
+template <typename R>
+__device__ __forceinline__ void add_fiber(const DevMat& mat, const M3<double>& F, double& psi,
+                                          M3<R>& P) {
+  if (mat.kappa == 0.0 || !(psi < INFINITY)) return;
+  double f[3];
+  for (int i = 0; i < 3; ++i)
+    f[i] = F.a[i][0] * mat.fdir[0] + F.a[i][1] * mat.fdir[1] + F.a[i][2] * mat.fdir[2];
+  const double ln = sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+  const double e = ln - 1.0;
+  psi += 0.5 * mat.kappa * e * e;
+  const double c = ln > 0.0 ? mat.kappa * e / ln : 0.0;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) P.a[i][j] += (R)(c * f[i] * mat.fdir[j]);
+}
+
 template <typename R>
 __device__ __forceinline__ bool material_eval_any(const DevMat& mat, const M3<R>& F, R& psi,
                                                   M3<R>& P) {

@@ -22,6 +22,8 @@ struct Material {
   double a0[8] = {0};   // spline: a at the knots
   double a1[8] = {0};   // spline: a' at the knots
   double k = 0.0;       // stiffness from the least-squares fit
+  double fiber_kappa = 0.0;           // anisotropic fibre term (0: none)
+  double fiber_dir[3] = {1.0, 0.0, 0.0};  // unit rest-pose direction
 };
 
 constexpr int kSplineKnots = 8;

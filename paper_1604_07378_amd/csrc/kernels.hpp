@@ -26,6 +26,8 @@ struct DevMat {
   int pad;
   double mu, lam;
   double d2[8], a0[8], a1[8];
+  double kappa;    // anisotropic fibre term kappa/2 (|F d| - 1)^2 (0: none)
+  double fdir[3];  // its unit rest-pose direction d
 };
 
 // Phase of one simulation within a step (each simulation of a batch moves

@@ -257,6 +257,7 @@ k_elem(int want, int trial, const BlockSeg* __restrict__ blk, int T, int nf,
     } else {
       material_eval_mixed<TYPE>(mt, F, psi, P);  // FP32 stress
     }
+    add_fiber(mt, F, psi, P);
     const double V = vol[t];
     e = V * psi;  // energies and their sum are FP64 in every mode
     if (psi_out) psi_out[t] = psi;
@@ -815,7 +816,9 @@ k_store_stress(int T, const int* __restrict__ tperm, const int* __restrict__ tv,
     }
   double ps;
   M3<double> P;
-  material_eval_any<double>(mats[tmat ? tmat[t] : 0], F, ps, P);
+  const DevMat& mt = mats[tmat ? tmat[t] : 0];
+  material_eval_any<double>(mt, F, ps, P);
+  add_fiber(mt, F, ps, P);
   const int o = tperm[t];
   psi[o] = ps;
   for (int i = 0; i < 3; ++i)

@@ -49,7 +49,8 @@ class Options(ctypes.Structure):
 class MaterialC(ctypes.Structure):
     _fields_ = [("type", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("mu", ctypes.c_double), ("lambda_", ctypes.c_double),
-                ("density", ctypes.c_double), ("spline_d2", ctypes.c_double * 8)]
+                ("density", ctypes.c_double), ("spline_d2", ctypes.c_double * 8),
+                ("fiber_kappa", ctypes.c_double), ("fiber_dir", ctypes.c_double * 3)]
 
 
 class Stats(ctypes.Structure):
@@ -205,6 +206,11 @@ def _material_array(materials: Sequence):
         if d2 is not None:
             for j, val in enumerate(np.asarray(d2, dtype=np.float64)):
                 arr[i].spline_d2[j] = float(val)
+        opt = (lambda k: m.get(k)) if isinstance(m, dict) else (lambda k: getattr(m, k, None))
+        if opt("fiber_kappa"):
+            arr[i].fiber_kappa = float(opt("fiber_kappa"))
+            for j, val in enumerate(np.asarray(opt("fiber_dir"), dtype=np.float64)):
+                arr[i].fiber_dir[j] = float(val)
     return arr
 
 
@@ -366,11 +372,7 @@ def sim_from_workload(w, options: Optional[Options] = None, prepare: bool = True
     s = Sim(options, **overrides)
     s.set_mesh(w.rest, w.tets)
     s.set_pinned(w.pinned)
-    mats = []
-    for m in w.materials:
-        mats.append(dict(type=m.type, mu=m.mu, lam=m.lam, density=m.density,
-                         spline_d2=m.d2() if hasattr(m, "d2") else None))
-    s.set_materials(mats, w.tet_mat)
+    s.set_materials(_materials_of(w), w.tet_mat)
     if prepare:
         s.prepare(w.h)
     else:
@@ -380,7 +382,9 @@ def sim_from_workload(w, options: Optional[Options] = None, prepare: bool = True
 
 def _materials_of(w):
     return [dict(type=m.type, mu=m.mu, lam=m.lam, density=m.density,
-                 spline_d2=m.d2() if hasattr(m, "d2") else None) for m in w.materials]
+                 spline_d2=m.d2() if hasattr(m, "d2") else None,
+                 fiber_kappa=getattr(m, "fiber_kappa", 0.0),
+                 fiber_dir=getattr(m, "fiber_dir", None)) for m in w.materials]
 
 
 class Pool:

@@ -358,3 +358,39 @@ def test_step_graph_replays_equal_eager():
         assert a == b, f"step {k}: stats {a} vs {b}"
         sg.eval_device(xg, xg, grad)   # eager work on the context's buffers between replays
         torch.cuda.synchronize()
+
+
+def test_fiber_element_objective_and_trajectory():
+    """Corotated base + anisotropic fibre term (section 4, Anisotropy): element
+    energies and stresses, g and its gradient, and 30 steps against the oracle."""
+    w = W.workload_fiber_cantilever(0)
+    s = qnsim.sim_from_workload(w)
+    m = _model(w)
+    x = _perturbed(w, 0.1, 5)
+    psi_ref, P_ref = fem.element_psi_P(m, x)
+    psi = torch.empty(w.n_tets, dtype=torch.float64, device="cuda")
+    P = torch.empty(w.n_tets, 9, dtype=torch.float64, device="cuda")
+    s.element_stress_device(_dev(x), psi, P)
+    torch.cuda.synchronize()
+    psi, P = psi.cpu().numpy(), P.cpu().numpy().reshape(-1, 3, 3)
+    assert np.abs(psi - psi_ref).max() <= 1e-11 * np.abs(psi_ref).max()
+    assert np.abs(P - P_ref).max() <= 1e-11 * np.abs(P_ref).max()
+    y = _perturbed(w, 0.1, 6)
+    grad = torch.empty(w.n_verts, 3, dtype=torch.float64, device="cuda")
+    g = s.eval_device(_dev(x), _dev(y), grad)
+    grad_ref = np.zeros_like(x)
+    grad_ref[m.free] = fem.gradient(m, x, y)
+    assert g == pytest.approx(fem.objective(m, x, y), rel=1e-12)
+    assert np.abs(grad.cpu().numpy() - grad_ref).max() <= 1e-11 * np.abs(grad_ref).max()
+    xo, vo = w.x0.copy(), w.v0.copy()
+    xg, vg = w.x0.copy(), w.v0.copy()
+    worst = 0.0
+    for k in range(30):
+        r = oracle.step(m, xo, vo)
+        xo, vo = r.x, r.v
+        xg, vg, st = s.step(xg, vg, w.h)
+        assert st["ls_trials"] == r.ls_trials, f"step {k}: trials {st['ls_trials']} vs {r.ls_trials}"
+        e = _eps(xg, xo, w.rest)
+        worst = max(worst, e)
+        assert e <= 1e-9, f"step {k}: eps {e:.3e}"
+    print(f"fiber cantilever 30 steps: max eps {worst:.3e}", flush=True)

@@ -196,3 +196,19 @@ def test_pool_group_schedule_self_check_on_host():
     assert "hipSetDevice" in str(e.value), str(e.value)
     assert p.info()["sims_resident"] == 0
     p.close()
+
+
+def test_fiber_material_validation():
+    w = W.workload_fiber_cantilever(0, dims=(2, 1, 1))
+    s = qnsim.sim_from_workload(w, prepare=False)
+    mats = [dict(type=W.COROTATED, mu=1e4, lam=4e4, density=1000.0, fiber_kappa=5e4,
+                 fiber_dir=[0.0, 0.0, 0.0])]
+    with pytest.raises(qnsim.QnsimError) as e:
+        s.set_materials(mats)
+    assert e.value.code == -1
+    mats[0]["fiber_dir"] = [0.0, 3.0, 4.0]     # normalised by the library
+    s.set_materials(mats)
+    mats[0]["fiber_kappa"] = -1.0
+    with pytest.raises(qnsim.QnsimError) as e:
+        s.set_materials(mats)
+    assert e.value.code == -1
