@@ -65,6 +65,8 @@ class Model:
     gravity: np.ndarray
     A: scipy.sparse.csc_matrix  # (n_f, n_f)
     solve: object               # q (n_f, 3) -> A^{-1} q
+    planes: np.ndarray = None   # (p, 4) colliders n . x >= c: unit n, c
+    coll_k: float = 0.0         # weight of the collision terms
 
     @property
     def n(self):
@@ -144,7 +146,8 @@ def make_solver(A: scipy.sparse.csc_matrix):
 
 
 def build_model(rest, tets, pinned, materials, tet_mat=None, h=1.0 / 30.0,
-                gravity=(0.0, 0.0, -9.81), fit_lo=0.5, fit_hi=1.5) -> Model:
+                gravity=(0.0, 0.0, -9.81), fit_lo=0.5, fit_hi=1.5, planes=None,
+                coll_k=0.0) -> Model:
     rest = np.asarray(rest, dtype=np.float64)
     tets = np.asarray(tets, dtype=np.int64)
     n = rest.shape[0]
@@ -191,7 +194,12 @@ def build_model(rest, tets, pinned, materials, tet_mat=None, h=1.0 / 30.0,
     free_of = -np.ones(n, dtype=np.int64)
     free_of[free] = np.arange(len(free))
     A = assemble_A(n, tets, Dm_inv, vol, k, mass, h, free_of)
-    return Model(rest=rest, tets=tets, free=free, pinned=pinned, free_of=free_of,
+    if planes is None or len(planes) == 0:
+        planes = np.zeros((0, 4))
+    planes = np.asarray(planes, dtype=np.float64).reshape(-1, 4).copy()
+    planes[:, :3] /= np.linalg.norm(planes[:, :3], axis=1, keepdims=True)
+    return Model(planes=planes, coll_k=float(coll_k),
+                 rest=rest, tets=tets, free=free, pinned=pinned, free_of=free_of,
                  Dm_inv=Dm_inv, vol=vol, mass=mass, k=k, mat_groups=final,
                  mu_t=mu_t, lam_t=lam_t, kappa_t=kappa_t, fdir_t=fdir_t, h=h,
                  gravity=np.asarray(gravity, dtype=np.float64), A=A,
@@ -256,15 +264,63 @@ def inertia_target(model: Model, x, v, f_ext=None):
     return y
 
 
-def objective(model: Model, x: np.ndarray, y: np.ndarray) -> float:
-    """g(x) of Eq. PD restricted to the free vertices (pinned inertia is zero)."""
+# ---------------------------------------------------------------------------
+# Collisions (section 4.3): for each free vertex i in collision with a
+# collider, the energy term ((S x - t)^T n)^2 with t the vertex's projection
+# on the collider surface and n its normal, weighted by coll_k. For a plane
+# n . x >= c this is coll_k (n . x_i - c)^2. The set of terms is chosen once
+# at the start of an iteration and kept through its line search; the terms
+# enter g and grad g but not A.
+# ---------------------------------------------------------------------------
+def contact_set(model: Model, x: np.ndarray, x_start: np.ndarray) -> np.ndarray:
+    """Plane index per free vertex (-1: none): the vertex is in collision or
+    contact (n . x <= c) and not separating (its velocity since the start of
+    the step, (x - x_start)/h, does not point along n); the deepest plane."""
+    f = model.free
+    cset = -np.ones(len(f), dtype=np.int64)
+    if len(model.planes) == 0:
+        return cset
+    n, c = model.planes[:, :3], model.planes[:, 3]
+    depth = x[f] @ n.T - c                           # (n_f, p)
+    moving = (x[f] - x_start[f]) @ n.T               # (n_f, p)
+    ok = (depth <= 0.0) & ~(moving > 0.0)
+    masked = np.where(ok, depth, np.inf)
+    best = np.argmin(masked, axis=1)
+    has = np.isfinite(masked[np.arange(len(f)), best])
+    cset[has] = best[has]
+    return cset
+
+
+def contact_energy(model: Model, x: np.ndarray, cset) -> float:
+    if cset is None or not np.any(cset >= 0):
+        return 0.0
+    idx = np.nonzero(cset >= 0)[0]
+    pl = model.planes[cset[idx]]
+    dep = np.einsum("ij,ij->i", x[model.free[idx]], pl[:, :3]) - pl[:, 3]
+    return float(model.coll_k * np.sum(dep * dep))
+
+
+def contact_gradient(model: Model, x: np.ndarray, cset) -> np.ndarray:
+    g = np.zeros((len(model.free), 3))
+    if cset is None or not np.any(cset >= 0):
+        return g
+    idx = np.nonzero(cset >= 0)[0]
+    pl = model.planes[cset[idx]]
+    dep = np.einsum("ij,ij->i", x[model.free[idx]], pl[:, :3]) - pl[:, 3]
+    g[idx] = (2.0 * model.coll_k * dep)[:, None] * pl[:, :3]
+    return g
+
+
+def objective(model: Model, x: np.ndarray, y: np.ndarray, cset=None) -> float:
+    """g(x) of Eq. PD restricted to the free vertices (pinned inertia is zero),
+    plus the collision terms of cset."""
     f = model.free
     dx = x[f] - y[f]
     inertia = float(np.sum(model.mass[f][:, None] * dx * dx)) / (2.0 * model.h ** 2)
-    return inertia + elastic_energy(model, x)
+    return inertia + elastic_energy(model, x) + contact_energy(model, x, cset)
 
 
-def gradient(model: Model, x: np.ndarray, y: np.ndarray) -> np.ndarray:
+def gradient(model: Model, x: np.ndarray, y: np.ndarray, cset=None) -> np.ndarray:
     """Gradient of g on the free vertices, (n_f, 3)."""
     _, Pst = element_psi_P(model, x)
     fe = element_forces(model, Pst)
@@ -272,7 +328,8 @@ def gradient(model: Model, x: np.ndarray, y: np.ndarray) -> np.ndarray:
     for j in range(4):
         np.add.at(gE, model.tets[:, j], fe[:, j])
     f = model.free
-    return model.mass[f][:, None] * (x[f] - y[f]) / model.h ** 2 + gE[f]
+    return (model.mass[f][:, None] * (x[f] - y[f]) / model.h ** 2 + gE[f]
+            + contact_gradient(model, x, cset))
 
 
 def objective_and_gradient(model: Model, x, y):

@@ -26,6 +26,10 @@ Readings (paper silent):
 * The line search stops after 30 halvings; if no trial passes, the iterate
   stays x_k and the step's remaining iterations are skipped.
 * Pinned vertices keep their input positions; their velocity becomes 0.
+* Collisions (section 4.3): the set of collision terms is chosen at the start
+  of every iteration (before its gradient) at x_k, g(x_k) is re-evaluated
+  with it, and it stays fixed through the iteration's line search; the step
+  starts with no terms.
 """
 from __future__ import annotations
 
@@ -94,8 +98,12 @@ def step(model: "fem.Model", x: np.ndarray, v: np.ndarray, f_ext=None,
 
     pairs: List[tuple] = []
     x_prev = grad_prev = None
+    cset = None
     for k in range(iterations):
-        grad = fem.gradient(model, xk, y)
+        if len(model.planes):
+            cset = fem.contact_set(model, xk, x)
+            gk = fem.objective(model, xk, y, cset)
+        grad = fem.gradient(model, xk, y, cset)
         if k == 0:
             res.grad_norm_first = float(np.linalg.norm(grad))
         if x_prev is not None:
@@ -124,7 +132,7 @@ def step(model: "fem.Model", x: np.ndarray, v: np.ndarray, f_ext=None,
         for _ in range(max_halvings + 1):
             xt = xk.copy()
             xt[f] = xk[f] + alpha * d
-            gt = fem.objective(model, xt, y)
+            gt = fem.objective(model, xt, y, cset)
             res.ls_trials += 1
             bound = gk + gamma * alpha * gtd
             margins.append((alpha, gt, bound))
@@ -145,7 +153,7 @@ def step(model: "fem.Model", x: np.ndarray, v: np.ndarray, f_ext=None,
 
     res.g_last = gk
     if final_gradient:
-        res.grad_norm_last = float(np.linalg.norm(fem.gradient(model, xk, y)))
+        res.grad_norm_last = float(np.linalg.norm(fem.gradient(model, xk, y, cset)))
     xk[model.pinned] = x[model.pinned]
     res.x = xk
     res.v = (xk - x) / model.h

@@ -374,3 +374,105 @@ def test_paper_claims_plausibility():
     e_newton1 = newton.relative_error(g1, g0, g_star)
     assert e5 <= e2 < e0 / 5
     assert e5 < 2.0 * e_newton1
+
+
+# ---------------------------------------------------------------------------
+# Collisions (section 4.3)
+# ---------------------------------------------------------------------------
+COLL_K = 1e5
+
+
+def _coll_model(w, planes):
+    return oracle.build_model(w.rest, w.tets, w.pinned, w.materials, w.tet_mat, w.h, w.gravity,
+                              planes=planes, coll_k=COLL_K)
+
+
+def test_contact_terms_gradient_matches_finite_differences():
+    w = _small()
+    planes = np.array([[0.0, 0.0, 1.0, 0.005], [0.3, 0.0, -1.0, -0.2]])
+    m = _coll_model(w, planes)
+    rng = np.random.default_rng(11)
+    x = w.rest + 0.01 * rng.normal(size=w.rest.shape)
+    x[m.pinned] = w.rest[m.pinned]
+    y = w.rest.copy()
+    cset = fem.contact_set(m, x, x)
+    assert np.any(cset == 0)                              # some vertices below z = 0.005
+    g = fem.gradient(m, x, y, cset)
+    eps = 1e-7
+    fd = np.zeros_like(g)
+    for a, v in enumerate(m.free):
+        for c in range(3):
+            xp = x.copy(); xp[v, c] += eps
+            xm = x.copy(); xm[v, c] -= eps
+            fd[a, c] = (fem.objective(m, xp, y, cset) - fem.objective(m, xm, y, cset)) / (2 * eps)
+    assert np.abs(fd - g).max() < 1e-6 * np.abs(g).max()
+    # the collision energy of one vertex is coll_k times its squared depth
+    i = int(np.nonzero(cset == 0)[0][0])
+    one = -np.ones_like(cset); one[i] = 0
+    dep = x[m.free[i], 2] - 0.005
+    assert fem.contact_energy(m, x, one) == pytest.approx(COLL_K * dep * dep, rel=1e-14)
+
+
+def test_contact_set_rule():
+    """Deepest plane among those the vertex penetrates (or touches), unless its
+    motion since the start of the step points out of that plane."""
+    w = _small()
+    planes = np.array([[0.0, 0.0, 1.0, 0.0], [1.0, 0.0, 0.0, 0.05]])
+    m = _coll_model(w, planes)
+    f0 = m.free[0]
+    x = w.rest.copy()
+    x[f0] = [0.02, 0.0, -0.01]                 # depths: plane 0 -0.01, plane 1 -0.03
+    assert fem.contact_set(m, x, x)[0] == 1
+    start = x.copy(); start[f0] = [0.0, 0.0, -0.01]    # moving +x: separating from plane 1
+    assert fem.contact_set(m, x, start)[0] == 0
+    start[f0] = [0.0, 0.0, -0.05]                       # moving +x and +z: separating from both
+    assert fem.contact_set(m, x, start)[0] == -1
+    x[f0] = [0.1, 0.0, 0.0]                             # on plane 0, outside plane 1: contact
+    assert fem.contact_set(m, x, x)[0] == 0
+
+
+def test_far_collider_changes_nothing():
+    w = _small()
+    m0 = _model(w)
+    m1 = _coll_model(w, np.array([[0.0, 0.0, 1.0, -10.0]]))
+    x0, v0 = w.x0.copy(), w.v0.copy()
+    x1, v1 = w.x0.copy(), w.v0.copy()
+    for _ in range(5):
+        r0 = oracle.step(m0, x0, v0); x0, v0 = r0.x, r0.v
+        r1 = oracle.step(m1, x1, v1); x1, v1 = r1.x, r1.v
+    assert np.array_equal(x0, x1) and r0.ls_trials == r1.ls_trials
+
+
+def test_separating_contact_is_not_held():
+    """No glue: a body touching a plane and moving away from it takes the step
+    it takes without the collider."""
+    w = _small()
+    n_up = np.array([0.0, 0.0, 1.0])
+    m0 = _model(w)
+    m1 = _coll_model(w, np.array([[*n_up, 0.0]]))     # the rest shape touches z = 0
+    v = np.zeros_like(w.rest)
+    v[m0.free] = [0.0, 0.0, 3.0]                          # moving up, out of the plane
+    r0 = oracle.step(m0, w.rest, v)
+    r1 = oracle.step(m1, w.rest, v)
+    assert np.array_equal(r0.x, r1.x)
+
+
+def test_cantilever_comes_to_rest_on_a_plane():
+    """The free end falls onto a tilted ground plane: every accepted iterate
+    decreases g (Armijo), the end stays on the plane within a small depth, and
+    the collision terms cost extra line-search trials (as the paper reports)."""
+    w = W.workload_cantilever(0)
+    planes = W.cantilever_ground_planes()
+    m = _coll_model(w, planes)
+    n, c = planes[0, :3], planes[0, 3]
+    x, v = w.x0.copy(), w.v0.copy()
+    trials = 0
+    for k in range(25):
+        r = oracle.step(m, x, v)
+        x, v = r.x, r.v
+        trials += r.ls_trials
+        for it in r.trace:
+            assert it["alpha"] > 0
+        assert (x[m.free] @ n - c).min() > -0.005 * w.edge * 10   # < 5 mm penetration
+    assert (x[m.free] @ n - c).min() < 0.01                        # the end reached the plane
+    assert trials > 15 * 25

@@ -15,6 +15,7 @@ from .grid import (  # noqa: F401
     workload_block,
     workload_mixed_cantilever,
     workload_fiber_cantilever,
+    cantilever_ground_planes,
     workload_batch,
     workload_pool,
     spline_knots,

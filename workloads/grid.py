@@ -235,6 +235,15 @@ def workload_fiber_cantilever(jitter_seed: int = 0, kind: int = COROTATED, E: fl
     return w
 
 
+def cantilever_ground_planes(depth: float = 0.05, tilt: float = 0.1):
+    """One collider under the cantilever: the plane n . x >= c with
+    n = (tilt, 0, 1)/|.| through (0, 0, -depth) (the free end comes to rest on
+    it under gravity)."""
+    n = np.array([tilt, 0.0, 1.0])
+    n = n / np.linalg.norm(n)
+    return np.array([[n[0], n[1], n[2], float(n @ np.array([0.0, 0.0, -depth]))]])
+
+
 def workload_batch(count: int = 256, seed: int = 0, lo: int = 4, hi: int = 30,
                    edge: float = 0.025) -> List[Workload]:
     """Independent blocks with per-axis sizes ~ U{lo..hi}, random materials."""
