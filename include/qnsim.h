@@ -221,6 +221,19 @@ int qnsim_run_device(qnsim_t* ctx, double* d_x, double* d_v, double h,
 /* Request the extra gradient pass that fills grad_norm_last (0 = off). */
 int qnsim_set_diagnostics(qnsim_t* ctx, int32_t final_gradient);
 
+/* Plane colliders (section 4.3): the half-spaces n . x >= c given as rows
+ * (nx, ny, nz, c) of planes (n_planes x 4; n is normalised, c scaled with it;
+ * at most 16; n_planes = 0 removes them). At the start of every iteration of
+ * a step, each free vertex that penetrates or touches a plane (n . x_k <= c)
+ * and is not separating from it (its motion since the start of the step,
+ * x_k - x_n, does not point along n) gets the energy term
+ * stiffness (n . x - c)^2 of its deepest such plane (the paper's
+ * ((S x - t)^T n)^2, t the projection on the plane, with a weight); the terms
+ * stay fixed through that iteration's line search and enter g and grad g but
+ * not A, so nothing is refactored. May be called before or after prepare.
+ * The probes (qnsim_eval_device) evaluate g without them. */
+int qnsim_set_colliders(qnsim_t* ctx, int32_t n_planes, const double* planes, double stiffness);
+
 /* Per-tet stiffness k (T doubles), available after qnsim_analyze/prepare. */
 int qnsim_get_stiffness(const qnsim_t* ctx, double* k);
 

@@ -197,7 +197,8 @@ def build_model(rest, tets, pinned, materials, tet_mat=None, h=1.0 / 30.0,
     if planes is None or len(planes) == 0:
         planes = np.zeros((0, 4))
     planes = np.asarray(planes, dtype=np.float64).reshape(-1, 4).copy()
-    planes[:, :3] /= np.linalg.norm(planes[:, :3], axis=1, keepdims=True)
+    nn = np.linalg.norm(planes[:, :3], axis=1, keepdims=True)
+    planes /= nn                        # n . x >= c scaled to a unit normal
     return Model(planes=planes, coll_k=float(coll_k),
                  rest=rest, tets=tets, free=free, pinned=pinned, free_of=free_of,
                  Dm_inv=Dm_inv, vol=vol, mass=mass, k=k, mat_groups=final,

@@ -389,6 +389,8 @@ int qnsim_prepare(qnsim_t* c, double h) {
   try {
     std::string err;
     rc = upload_sims({c}, c->opt, c->h, c->dev, err);
+    if (!rc && !c->planes.empty())
+      rc = dev_set_colliders(c->dev, (int)c->planes.size() / 4, c->planes.data(), c->coll_k, err);
     if (rc) fail(c, rc, err);
     else c->prepared = true;
   } catch (const std::bad_alloc&) {
@@ -522,6 +524,32 @@ int qnsim_step(qnsim_t* c, const double* x, const double* v, double h, const dou
     return fail(c, QNSIM_E_DEVICE, "device-to-host copy failed");
   }
   if (stats) fill_stats(t, c->diag_final_gradient != 0, stats);
+  return QNSIM_OK;
+}
+
+int qnsim_set_colliders(qnsim_t* c, int32_t n_planes, const double* planes, double stiffness) {
+  if (!c) return QNSIM_E_INVALID;
+  if (n_planes < 0 || n_planes > kMaxPlanes || (n_planes > 0 && !planes))
+    return fail(c, QNSIM_E_INVALID, "between 0 and 16 planes");
+  if (n_planes > 0 && !(stiffness > 0.0 && std::isfinite(stiffness)))
+    return fail(c, QNSIM_E_INVALID, "collision stiffness must be positive");
+  if (n_planes > 0 && !finite_all(planes, 4 * (size_t)n_planes))
+    return fail(c, QNSIM_E_NONFINITE, "non-finite plane");
+  std::vector<double> p(4 * (size_t)n_planes);
+  for (int i = 0; i < n_planes; ++i) {
+    const double* q = planes + 4 * i;
+    const double nn = std::sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2]);
+    if (!(nn > 0.0)) return fail(c, QNSIM_E_INVALID, "plane normal must be non-zero");
+    for (int j = 0; j < 3; ++j) p[4 * i + j] = q[j] / nn;
+    p[4 * i + 3] = q[3] / nn;
+  }
+  c->planes = p;
+  c->coll_k = n_planes > 0 ? stiffness : 0.0;
+  if (c->prepared) {
+    std::string err;
+    int rc = dev_set_colliders(c->dev, n_planes, p.data(), c->coll_k, err);
+    if (rc) return fail(c, rc, err);
+  }
   return QNSIM_OK;
 }
 

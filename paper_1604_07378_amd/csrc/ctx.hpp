@@ -43,6 +43,8 @@ struct qnsim {
   bool prepared = false;
   qn::DeviceMesh dev;
   double* stage = nullptr;        // qnsim_step staging: x, v, f_ext, x', v' (5 n x 3)
+  std::vector<double> planes;     // colliders: n x 4 (unit normal, offset)
+  double coll_k = 0.0;
 };
 
 namespace qn {

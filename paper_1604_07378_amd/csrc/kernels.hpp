@@ -19,6 +19,8 @@ constexpr int kSubCap = 384;
 // workgroups of the bottom-subtree kernels: one per compute unit of the MI355X
 // (their LDS use allows one per CU)
 constexpr int kSubGroups = 256;
+// plane colliders per simulation context
+constexpr int kMaxPlanes = 16;
 
 // Material parameters as the element kernels read them.
 struct DevMat {
@@ -176,6 +178,12 @@ struct DeviceMesh {
   size_t c_items_off = 0;     // byte offset of the compacted items in cbuf
   std::vector<Level> c_levels;
   int* dir_count = nullptr;   // simulations whose direction is being formed (solve gate)
+  // plane colliders n . x >= c (section 4.3): unit n and c per plane; the
+  // collision term of each free vertex chosen at the start of an iteration
+  int nplanes = 0;
+  double coll_k = 0.0;
+  double* planes = nullptr;   // nplanes x 4
+  int* cset = nullptr;        // nf: plane of the vertex's collision term, or -1
   // element data (internal tet order)
   int* tv = nullptr;          // T x 4 internal vertex ids
   double* Bm = nullptr;       // 9 x T (SoA) entries of Dm^{-1}, row-major per tet
@@ -280,6 +288,8 @@ int dev_step(DeviceMesh& d, const StepParams& p, const double* x, const double* 
              const double* fext, double* xo, double* vo, void* stream, bool final_gradient,
              std::string& err);
 int dev_set_run(DeviceMesh& d, const int* run_flags, void* stream, std::string& err);
+// Plane colliders n . x >= c (n x 4: unit n, c; n <= kMaxPlanes) with weight k.
+int dev_set_colliders(DeviceMesh& d, int n, const double* planes, double k, std::string& err);
 
 // Probes.
 int dev_eval(DeviceMesh& d, const double* x, const double* y, double* g_out, double* grad,

@@ -142,7 +142,7 @@ k_step_init(const BlockSeg* __restrict__ blk, int nf, const int* __restrict__ ru
             const double* __restrict__ v, const double* __restrict__ fext, double h, double ax,
             double ay, double az, double* __restrict__ x0, double* __restrict__ y,
             double* __restrict__ X, Ctl* __restrict__ ctl, SimStat* __restrict__ stat, int slots,
-            int* __restrict__ dir_count) {
+            int* __restrict__ dir_count, int* __restrict__ cset) {
   const BlockSeg sg = blk[blockIdx.x];
   const int i = sg.a0 + threadIdx.x;
   if (blockIdx.x == 0 && threadIdx.x == 0) *dir_count = 0;
@@ -162,6 +162,7 @@ k_step_init(const BlockSeg* __restrict__ blk, int nf, const int* __restrict__ ru
     }
   }
   if (!on) return;
+  if (cset && i < nf) cset[i] = -1;  // the step starts without collision terms
   const int o = vperm[i];
   const double acc[3] = {ax, ay, az};
   for (int c = 0; c < 3; ++c) {
@@ -207,7 +208,8 @@ k_elem(int want, int trial, const BlockSeg* __restrict__ blk, int T, int nf,
        const DevMat* __restrict__ mats, const double* __restrict__ mass,
        const double* __restrict__ X, const double* __restrict__ d,
        const double* __restrict__ y, double inv2h2, const Ctl* __restrict__ ctl,
-       R* __restrict__ fel, double* __restrict__ part, double* __restrict__ psi_out) {
+       R* __restrict__ fel, double* __restrict__ part, double* __restrict__ psi_out,
+       const int* __restrict__ cset, const double* __restrict__ planes, double coll_k) {
   __shared__ double sh[16];
   // the block's gradient contributions, written out contiguously at the end
   __shared__ __align__(16) R sfel[BS * 12];
@@ -297,15 +299,25 @@ k_elem(int want, int trial, const BlockSeg* __restrict__ blk, int T, int nf,
   }
   const int vi = sg.b0 + threadIdx.x;
   if (vi < sg.b1) {
-    double s = 0.0;
+    double s = 0.0, xv3[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       double xv = X[3 * (size_t)vi + c];
       if (trial) xv = __fma_rn(alpha, d[3 * (size_t)vi + c], xv);
+      xv3[c] = xv;
       double dx = xv - y[3 * (size_t)vi + c];
       s += dx * dx;
     }
     e += mass[vi] * s * inv2h2;
+    if (cset) {  // collision term (section 4.3): coll_k (n . x - c)^2
+      const int p = cset[vi];
+      if (p >= 0) {
+        const double* pl = planes + 4 * p;
+        const double dep = __dadd_rn(__dadd_rn(__dmul_rn(xv3[0], pl[0]), __dmul_rn(xv3[1], pl[1])),
+                                     __dmul_rn(xv3[2], pl[2])) - pl[3];
+        e += coll_k * dep * dep;
+      }
+    }
   }
   double b = block_sum(e, sh);
   if (threadIdx.x == 0 && part) part[sg.slot] = b;
@@ -345,8 +357,12 @@ k_init_decide(int want, const SimSeg* __restrict__ seg, const double* __restrict
 // forms every dot product the two-loop recursion needs, so that the
 // recursion runs on scalars (Gram form): dots [0..3] = t.s, s.s, t.t, g.g
 // and, per ring slot j, [4 + 3j] = s_j.g, [5 + 3j] = s.t_j, [6 + 3j] = s_j.t
-// (the candidate's own entries use the new s and t). probe: every
-// simulation, gradient at X (k = 0).
+// (the candidate's own entries use the new s and t). With colliders, the
+// collision terms of iteration k are chosen here at x_k (section 4.3): per
+// free vertex the deepest plane it penetrates or touches and is not
+// separating from, the term's gradient is added, and the last dot is the
+// change of the collision energy at x_k (added to g(x_k)). probe: every
+// simulation, gradient at X (k = 0) with the current collision terms.
 // ---------------------------------------------------------------------------
 constexpr int kWideBS = 1024;  // threads per block of the r0 dots
 
@@ -357,8 +373,9 @@ k_gather(int probe, const BlockSeg* __restrict__ blk, int nb, size_t n3, int slo
          const double* __restrict__ mass, const double* __restrict__ y, double inv_h2,
          double* __restrict__ X, const double* __restrict__ d, double* __restrict__ Gr,
          double* __restrict__ Sall, double* __restrict__ Tall, const Ctl* __restrict__ ctl,
-         double* __restrict__ part) {
-  constexpr int ND = 4 + 3 * SL;
+         double* __restrict__ part, int nplanes, const double* __restrict__ planes,
+         double coll_k, int* __restrict__ cset, const double* __restrict__ xstart) {
+  constexpr int ND = 4 + 3 * SL + 1;
   __shared__ double sh[(BS / 64) * ND];
   const BlockSeg sg = blk[blockIdx.x];
   const Ctl* cs = ctl + sg.sim;
@@ -416,6 +433,30 @@ k_gather(int probe, const BlockSeg* __restrict__ blk, int nb, size_t n3, int slo
   }
 #pragma unroll
   for (int c = 0; c < 3; ++c) f[c] = group_sum(f[c], 4);
+  double cgrad = 0.0;  // this lane's component of the collision term's gradient
+  if (nplanes > 0) {
+    const double xcl = own ? (k > 0 ? __fma_rn(alpha, dd, xp) : xp) : 0.0;
+    const double mvl = own ? xcl - xstart[ic] : 0.0;
+    const int old = live ? cset[i] : -1;
+    int nw = -1;
+    double best = 0.0, dep_old = 0.0;
+    for (int p = 0; p < nplanes; ++p) {
+      const double* pl = planes + 4 * p;
+      const double nc = gl < 3 ? pl[gl] : 0.0;
+      const double dep = group_sum(__dmul_rn(nc, xcl), 4) - pl[3];
+      const double mv = group_sum(__dmul_rn(nc, mvl), 4);
+      if (p == old) dep_old = dep;
+      if (dep <= 0.0 && !(mv > 0.0) && (nw < 0 || dep < best)) { nw = p; best = dep; }
+    }
+    if (probe) { nw = old; best = dep_old; }
+    if (own && nw >= 0) cgrad = 2.0 * coll_k * best * planes[4 * nw + gl];
+    if (live && gl == 0) {
+      const double e_new = nw >= 0 ? coll_k * best * best : 0.0;
+      const double e_old = old >= 0 ? coll_k * dep_old * dep_old : 0.0;
+      acc[ND - 1] += e_new - e_old;
+      if (!probe) cset[i] = nw;
+    }
+  }
   if (own) {
     const double fc = gl == 0 ? f[0] : (gl == 1 ? f[1] : f[2]);
     double xc = xp, sv = 0.0, tv = 0.0;
@@ -426,7 +467,7 @@ k_gather(int probe, const BlockSeg* __restrict__ blk, int nb, size_t n3, int slo
       Sall[(size_t)cand * n3 + ic] = sv;
       acc[1] += sv * sv;
     }
-    const double gr = mi * (xc - yy) + fc;
+    const double gr = mi * (xc - yy) + fc + cgrad;
     Gr[ic] = gr;
     acc[3] += gr * gr;
     if (k > 0) {
@@ -459,7 +500,7 @@ template <int SL>
 __global__ void __launch_bounds__(BS)
 k_pair_decide(int m, const SimSeg* __restrict__ seg, const double* __restrict__ part, int nb,
               Ctl* __restrict__ ctl, SimStat* __restrict__ stat, int* __restrict__ dir_count) {
-  constexpr int ND = 4 + 3 * SL;
+  constexpr int ND = 4 + 3 * SL + 1;
   __shared__ double red[4 * ND], tot[ND];
   __shared__ double sG[SL][SL], srho[SL], szeta[SL];
   const int sim = blockIdx.x;
@@ -476,6 +517,7 @@ k_pair_decide(int m, const SimSeg* __restrict__ seg, const double* __restrict__ 
   if (threadIdx.x != 0) return;
   SimStat* st = stat + sim;
   const double ts = tot[0], ss = tot[1], tt = tot[2], gg = tot[3];
+  ctl_s->g_k += tot[ND - 1];  // the collision terms chosen at x_k (0 without colliders)
   int newest = newest0, np = np0;
   if (k == 0) {
     st->gnorm2_first = gg;
@@ -919,11 +961,12 @@ void launch_elem(DeviceMesh& D, hipStream_t st, int want, int trial, double* par
       hipLaunchKernelGGL((k_elem<TY, float>), dim3(GRID), dim3(BS), 0, st, want, trial,       \
                          BLK, D.T, D.nf, D.tv, D.Bm, D.vol, D.tmat, D.mats, D.mass, D.X,      \
                          D.d, D.y, inv2h2, D.ctl, reinterpret_cast<float*>(D.fel), part,      \
-                         psi_out);                                                           \
+                         psi_out, D.nplanes ? D.cset : nullptr, D.planes, D.coll_k);         \
     else                                                                                     \
       hipLaunchKernelGGL((k_elem<TY, double>), dim3(GRID), dim3(BS), 0, st, want, trial,      \
                          BLK, D.T, D.nf, D.tv, D.Bm, D.vol, D.tmat, D.mats, D.mass, D.X,      \
-                         D.d, D.y, inv2h2, D.ctl, D.fel, part, psi_out);                      \
+                         D.d, D.y, inv2h2, D.ctl, D.fel, part, psi_out,                       \
+                         D.nplanes ? D.cset : nullptr, D.planes, D.coll_k);                   \
   } while (0)
   auto one = [&](int type, const BlockSeg* blk, int grid) {
     switch (type) {
@@ -943,7 +986,7 @@ void launch_elem(DeviceMesh& D, hipStream_t st, int want, int trial, double* par
 
 // Partials layout: gather dots (kGatherDots x gather_blocks), r0 dots
 // (kSlots + 1 x rdots_blocks), element partials (elem_blocks).
-constexpr int kGatherDots = 4 + 3 * kSlots;
+constexpr int kGatherDots = 4 + 3 * kSlots + 1;
 struct Parts {
   double *gather, *rdots, *elem;
 };
@@ -983,11 +1026,13 @@ void launch_gather(DeviceMesh& D, hipStream_t st, int probe, int m, double* part
       hipLaunchKernelGGL((k_gather<SL, float>), dim3(L.gat_n), dim3(BS), 0, st, probe, L.gat,  \
                          nb, n3, m + 1, D.inc_w, D.inc_tab,                                    \
                          reinterpret_cast<const float*>(D.fel), D.mass, D.y,                   \
-                         1.0 / (D.h * D.h), D.X, D.d, D.G, D.Sv, D.Tv, D.ctl, part);           \
+                         1.0 / (D.h * D.h), D.X, D.d, D.G, D.Sv, D.Tv, D.ctl, part,            \
+                         D.nplanes, D.planes, D.coll_k, D.cset, D.x0);                         \
     else                                                                                      \
       hipLaunchKernelGGL((k_gather<SL, double>), dim3(L.gat_n), dim3(BS), 0, st, probe, L.gat, \
                          nb, n3, m + 1, D.inc_w, D.inc_tab, D.fel, D.mass, D.y,                \
-                         1.0 / (D.h * D.h), D.X, D.d, D.G, D.Sv, D.Tv, D.ctl, part);           \
+                         1.0 / (D.h * D.h), D.X, D.d, D.G, D.Sv, D.Tv, D.ctl, part,            \
+                         D.nplanes, D.planes, D.coll_k, D.cset, D.x0);                         \
   } while (0)
   QN_SLOTS_DISPATCH(slots_variant(m), QN_GATHER)
 #undef QN_GATHER
@@ -1079,7 +1124,7 @@ void dev_free(DeviceMesh& D) {
                   D.part, D.psi, D.ctl, D.stat, D.tperm, D.top_t,
                   D.sub_fw, D.sub_bw, D.sub_fw_ptr, D.sub_bw_ptr,
                   D.seg, D.vsim, D.run, D.eblk, D.gblk, D.vblk, D.rblk, D.xblk, D.dir_count,
-                  D.cbuf};
+                  D.cbuf, D.cset, D.planes};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (D.stat_host) (void)hipHostFree(D.stat_host);
@@ -1122,6 +1167,8 @@ int dev_alloc(DeviceMesh& D, std::string& err) {
   HIP_OK(A((void**)&D.stat, sizeof(SimStat) * D.S));
   HIP_OK(A((void**)&D.run, sizeof(int) * D.S));
   HIP_OK(A((void**)&D.dir_count, sizeof(int)));
+  HIP_OK(A((void**)&D.cset, sizeof(int) * std::max(D.nf, 1)));
+  HIP_OK(A((void**)&D.planes, sizeof(double) * 4 * kMaxPlanes));
   HIP_OK(hipHostMalloc((void**)&D.stat_host, sizeof(SimStat) * D.S, hipHostMallocDefault));
   HIP_OK(hipHostMalloc((void**)&D.run_host, sizeof(int) * D.S, hipHostMallocDefault));
   hipStream_t st;
@@ -1139,6 +1186,16 @@ int dev_alloc(DeviceMesh& D, std::string& err) {
   HIP_OK(hipMemset(D.dir_count, 0, sizeof(int)));
   for (int s = 0; s < D.S; ++s) D.run_host[s] = 1;
   HIP_OK(hipMemcpy(D.run, D.run_host, sizeof(int) * D.S, hipMemcpyHostToDevice));
+  return 0;
+}
+
+int dev_set_colliders(DeviceMesh& D, int n, const double* planes, double k, std::string& err) {
+  HIP_OK(hipStreamSynchronize((hipStream_t)D.stream));
+  if (n > 0)
+    HIP_OK(hipMemcpy(D.planes, planes, sizeof(double) * 4 * n, hipMemcpyHostToDevice));
+  D.nplanes = n;
+  D.coll_k = k;
+  drop_graph(D);  // the captured step has the collider count and weight as arguments
   return 0;
 }
 
@@ -1222,7 +1279,8 @@ int enqueue_step(DeviceMesh& D, const StepParams& P, hipStream_t st, const doubl
   const Lists L = lists_of(D);
   hipLaunchKernelGGL(k_step_init, dim3(L.vtx_n), dim3(BS), 0, st, L.vtx, D.nf, D.run, D.seg,
                      D.vperm, D.mass, x, v, fext, P.h, P.grav[0], P.grav[1], P.grav[2],
-                     D.x0, D.y, D.X, D.ctl, D.stat, D.slots, D.dir_count);
+                     D.x0, D.y, D.X, D.ctl, D.stat, D.slots, D.dir_count,
+                     D.nplanes ? D.cset : nullptr);
   launch_elem(D, st, PH_INIT, 0, pp.elem, nullptr);
   hipLaunchKernelGGL(k_init_decide, dim3(D.S), dim3(BS), 0, st, (int)PH_INIT, D.seg, pp.elem,
                      D.ctl, D.stat);
@@ -1366,6 +1424,12 @@ int dev_eval(DeviceMesh& D, const double* x, const double* y, double* g_out, dou
              void* stream, std::string& err) {
   hipStream_t st = (hipStream_t)stream;
   Parts pp = parts_of(D);
+  struct NoPlanes {  // g of Eq. PD only: no collision terms in the probe
+    DeviceMesh& D;
+    int n;
+    ~NoPlanes() { D.nplanes = n; }
+  } keep{D, D.nplanes};
+  D.nplanes = 0;
   hipLaunchKernelGGL(k_load_perm, dim3(nblk(D.n)), dim3(BS), 0, st, D.n, D.vperm, x, D.X);
   hipLaunchKernelGGL(k_load_perm, dim3(nblk(D.n)), dim3(BS), 0, st, D.n, D.vperm, y, D.y);
   launch_elem(D, st, -1, 0, pp.elem, nullptr);

@@ -113,6 +113,7 @@ SIGNATURES = {
     "qnsim_step_device": (ctypes.c_int, [_P, _P, _P, _D, _P, _P, _P, _P, ctypes.POINTER(Stats)]),
     "qnsim_run_device": (ctypes.c_int, [_P, _P, _P, _D, _P, _I, _P, ctypes.POINTER(Stats)]),
     "qnsim_set_diagnostics": (ctypes.c_int, [_P, _I]),
+    "qnsim_set_colliders": (ctypes.c_int, [_P, _I, _P, _D]),
     "qnsim_get_stiffness": (ctypes.c_int, [_P, _P]),
     "qnsim_get_masses": (ctypes.c_int, [_P, _P]),
     "qnsim_get_factor_info": (ctypes.c_int, [_P, ctypes.POINTER(FactorInfo)]),
@@ -281,6 +282,13 @@ class Sim:
 
     def prepare(self, h: float):
         self._check(self._lib.qnsim_prepare(self._h, float(h)))
+
+    def set_colliders(self, planes, stiffness: float):
+        """planes: (p, 4) rows (nx, ny, nz, c) of half-spaces n . x >= c."""
+        planes = _f64(planes).reshape(-1, 4)
+        self._check(self._lib.qnsim_set_colliders(self._h, planes.shape[0],
+                                                  _ptr(planes) if planes.size else None,
+                                                  float(stiffness)))
 
     def set_diagnostics(self, final_gradient: bool):
         self._check(self._lib.qnsim_set_diagnostics(self._h, 1 if final_gradient else 0))
