@@ -26,6 +26,13 @@ Readings (paper silent):
 * The line search stops after 30 halvings; if no trial passes, the iterate
   stays x_k and the step's remaining iterations are skipped.
 * Pinned vertices keep their input positions; their velocity becomes 0.
+* Chebyshev direction (section 5, Algorithm 3, the comparison method):
+  q = -A^{-1} grad g(x_k), x^_{k+1} = x_k + q, omega_{k+1} = 1 for k < S,
+  2/(2 - rho^2) for k = S, 4/(4 - rho^2 omega_k) for k > S, and
+  d = omega_{k+1} (x^_{k+1} - x_{k-1}) + x_{k-1} - x_k; k counts the step's
+  iterations from 0 (so d = q while k < S). Readings: if d is not a descent
+  direction the iteration uses d = q (counted as a fallback) and the omega
+  recursion goes on; it needs history = 0 (no L-BFGS pairs).
 * Collisions (section 4.3): the set of collision terms is chosen at the start
   of every iteration (before its gradient) at x_k, g(x_k) is re-evaluated
   with it, and it stays fixed through the iteration's line search; the step
@@ -70,6 +77,7 @@ class StepResult:
     grad_norm_first: float = 0.0
     grad_norm_last: float = float("nan")
     trace: list = dataclasses.field(default_factory=list)   # per iteration
+    omegas: list = dataclasses.field(default_factory=list)  # Chebyshev weights per iteration
     iterates: list = dataclasses.field(default_factory=list)
 
 
@@ -77,7 +85,8 @@ def step(model: "fem.Model", x: np.ndarray, v: np.ndarray, f_ext=None,
          iterations: int = 10, history: int = 5, gamma: float = 0.3,
          backtrack: float = 0.5, max_halvings: int = 30,
          final_gradient: bool = False, keep_iterates: bool = False,
-         x_init: Optional[np.ndarray] = None) -> StepResult:
+         x_init: Optional[np.ndarray] = None, direction: str = "lbfgs",
+         cheb_delay: int = 10, cheb_rho: float = 0.9) -> StepResult:
     """Advance (x, v) by one step of size model.h; returns the new state."""
     x = np.asarray(x, dtype=np.float64)
     v = np.asarray(v, dtype=np.float64)
@@ -99,6 +108,9 @@ def step(model: "fem.Model", x: np.ndarray, v: np.ndarray, f_ext=None,
     pairs: List[tuple] = []
     x_prev = grad_prev = None
     cset = None
+    omega = 1.0
+    if direction == "chebyshev" and cheb_delay < 1:
+        raise ValueError("the Chebyshev delay S must be at least 1 (x_{k-1} is needed)")
     for k in range(iterations):
         if len(model.planes):
             cset = fem.contact_set(model, xk, x)
@@ -118,13 +130,33 @@ def step(model: "fem.Model", x: np.ndarray, v: np.ndarray, f_ext=None,
                 res.lbfgs_skipped += 1
         if history == 0:
             pairs = []
-        d = two_loop(grad, pairs, model.solve)
-        gtd = float(np.sum(grad * d))
-        if gtd >= 0.0 and np.any(grad != 0.0):
-            pairs = []
-            d = model.solve(-grad)
+        if direction == "chebyshev":
+            q = model.solve(-grad)                       # q := -A^{-1} grad g(x_k)
+            if k < cheb_delay:
+                omega = 1.0
+            elif k == cheb_delay:
+                omega = 2.0 / (2.0 - cheb_rho ** 2)
+            else:
+                omega = 4.0 / (4.0 - cheb_rho ** 2 * omega)
+            res.omegas.append(omega)
+            if omega == 1.0:
+                d = q
+            else:                                        # x_{k-1} exists: k >= S >= 1
+                x_hat = xk[f] + q
+                d = omega * (x_hat - x_prev[f]) + x_prev[f] - xk[f]
             gtd = float(np.sum(grad * d))
-            res.fallbacks += 1
+            if gtd >= 0.0 and np.any(grad != 0.0):
+                d = q
+                gtd = float(np.sum(grad * d))
+                res.fallbacks += 1
+        else:
+            d = two_loop(grad, pairs, model.solve)
+            gtd = float(np.sum(grad * d))
+            if gtd >= 0.0 and np.any(grad != 0.0):
+                pairs = []
+                d = model.solve(-grad)
+                gtd = float(np.sum(grad * d))
+                res.fallbacks += 1
 
         alpha = 1.0
         accepted = False

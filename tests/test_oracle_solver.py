@@ -476,3 +476,64 @@ def test_cantilever_comes_to_rest_on_a_plane():
         assert (x[m.free] @ n - c).min() > -0.005 * w.edge * 10   # < 5 mm penetration
     assert (x[m.free] @ n - c).min() < 0.01                        # the end reached the plane
     assert trials > 15 * 25
+
+
+# ---------------------------------------------------------------------------
+# Chebyshev semi-iterative direction (section 5, Algorithm 3)
+# ---------------------------------------------------------------------------
+def _moving_state(steps=3):
+    w = W.workload_cantilever(0)
+    m = _model(w)
+    x, v = w.x0.copy(), w.v0.copy()
+    for _ in range(steps):
+        r = oracle.step(m, x, v)
+        x, v = r.x, r.v
+    return w, m, x, v
+
+
+def test_chebyshev_within_its_delay_is_the_pd_direction():
+    w, m, x, v = _moving_state(1)
+    a = oracle.step(m, x, v, iterations=12, history=0)
+    b = oracle.step(m, x, v, iterations=12, history=0, direction="chebyshev", cheb_delay=12,
+                    cheb_rho=0.9)
+    assert np.array_equal(a.x, b.x) and a.ls_trials == b.ls_trials
+    assert b.omegas == [1.0] * 12
+
+
+def test_chebyshev_weights():
+    """omega = 1 for k < S, 2/(2 - rho^2) at k = S, then the recursion, whose
+    fixed point is the optimal Chebyshev weight 2/(1 + sqrt(1 - rho^2))."""
+    w, m, x, v = _moving_state(1)
+    rho, S = 0.9, 4
+    r = oracle.step(m, x, v, iterations=60, history=0, direction="chebyshev", cheb_delay=S,
+                    cheb_rho=rho)
+    om = r.omegas
+    assert om[:S] == [1.0] * S
+    assert om[S] == pytest.approx(2.0 / (2.0 - rho ** 2), rel=1e-15)
+    assert om[S + 1] == pytest.approx(4.0 / (4.0 - rho ** 2 * om[S]), rel=1e-15)
+    assert om[-1] == pytest.approx(2.0 / (1.0 + np.sqrt(1.0 - rho ** 2)), rel=1e-9)
+
+
+def test_convergence_order_of_the_directions():
+    """Paper's comparison (section 5): relative error after 40 iterations of one
+    frame: plain PD > Chebyshev (S = 10, rho from a training run of PD) >
+    L-BFGS m = 2 >= m = 5 (plausibility of the paper's printed behaviour)."""
+    w, m, x, v = _moving_state(3)
+    y = fem.inertia_target(m, x, v)
+    ref = oracle.step(m, x, v, iterations=400)
+    gstar = fem.objective(m, ref.x, y)
+
+    def rel(res, k):
+        it = res.iterates[min(k, len(res.iterates) - 1)]
+        return (fem.objective(m, it, y) - gstar) / (fem.objective(m, res.iterates[0], y) - gstar)
+
+    pd = oracle.step(m, x, v, iterations=80, history=0, keep_iterates=True)
+    lens = [np.linalg.norm(pd.iterates[i + 1] - pd.iterates[i]) for i in range(80)]
+    rho = float(np.median([lens[i + 1] / lens[i] for i in range(40, 79)]))   # training estimate
+    assert 0.5 < rho < 1.0
+    ch = oracle.step(m, x, v, iterations=40, history=0, keep_iterates=True, direction="chebyshev",
+                     cheb_delay=10, cheb_rho=rho)
+    l2 = oracle.step(m, x, v, iterations=40, history=2, keep_iterates=True)
+    l5 = oracle.step(m, x, v, iterations=40, history=5, keep_iterates=True)
+    e = [rel(pd, 40), rel(ch, 40), rel(l2, 40), rel(l5, 40)]
+    assert e[0] > 10 * e[1] > 0 and e[1] > 10 * e[2] and e[2] >= e[3] > 0, e
