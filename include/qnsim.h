@@ -101,7 +101,18 @@ typedef struct {
   int32_t trials_per_cycle; /* line-search trials enqueued per iteration
                            (1..8; a longer line search continues in the next
                            cycle); default 2                                 */
+  int32_t direction;    /* QNSIM_DIR_LBFGS (Algorithm 2) or QNSIM_DIR_CHEBYSHEV
+                           (section 5, Algorithm 3: the comparison method;
+                           needs history = 0)                               */
+  int32_t cheb_delay;   /* Chebyshev: iterations S with omega = 1 (>= 1; 10)   */
+  double cheb_rho;      /* Chebyshev: spectral-radius estimate rho in (0, 1)  */
 } qnsim_options;
+
+#define QNSIM_DIR_LBFGS 0
+#define QNSIM_DIR_CHEBYSHEV 1  /* d = omega (x^ - x_{k-1}) + x_{k-1} - x_k, x^ = x_k - A^{-1} grad g,
+                                  omega = 1 (k < S), 2/(2 - rho^2) (k = S),
+                                  4/(4 - rho^2 omega_k) (k > S); an ascent
+                                  direction falls back to d = -A^{-1} grad g */
 
 /* One material. mu, lambda in Pa; density in kg/m^3. For QNSIM_SPLINE,
  * spline_d2[j] is a''(s) at the knot s_j = 0.2 + 0.4 j (j = 0..7); a'' is

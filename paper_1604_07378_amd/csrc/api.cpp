@@ -246,6 +246,9 @@ int qnsim_options_default(qnsim_options* o) {
   o->level_merge = 1;
   o->step_graph = 1;
   o->trials_per_cycle = 2;
+  o->direction = QNSIM_DIR_LBFGS;
+  o->cheb_delay = 10;
+  o->cheb_rho = 0.9;
   o->gamma = 0.3;
   o->backtrack = 0.5;
   o->fit_lo = 0.5;
@@ -269,6 +272,9 @@ int qnsim_create(const qnsim_options* opts, qnsim_t** out) {
       o.subtree_cap > kSubCap || (o.level_merge != 0 && o.level_merge != 1) ||
       (o.step_graph != 0 && o.step_graph != 1) || o.trials_per_cycle < 1 ||
       o.trials_per_cycle > 8 ||
+      (o.direction != QNSIM_DIR_LBFGS && o.direction != QNSIM_DIR_CHEBYSHEV) ||
+      (o.direction == QNSIM_DIR_CHEBYSHEV &&
+       (o.history != 0 || o.cheb_delay < 1 || !(o.cheb_rho > 0.0 && o.cheb_rho < 1.0))) ||
       !finite_all(o.gravity, 3))
     return QNSIM_E_INVALID;
   qnsim_t* c = new (std::nothrow) qnsim();
@@ -413,6 +419,9 @@ static StepParams params_of(const qnsim_t* c, double h) {
   p.max_halvings = c->opt.max_halvings;
   p.budget = c->opt.trials_per_cycle;
   p.graph = c->opt.step_graph;
+  p.direction = c->opt.direction;
+  p.cheb_delay = c->opt.cheb_delay;
+  p.cheb_rho = c->opt.cheb_rho;
   p.gamma = c->opt.gamma;
   p.backtrack = c->opt.backtrack;
   for (int i = 0; i < 3; ++i) p.grav[i] = c->opt.gravity[i];

@@ -59,6 +59,8 @@ struct Ctl {
   double coef[kSlots];       // zeta_i - eta_i (second loop)
   double sg[kSlots];         // s_i . grad g(x_k)
   double G[kSlots][kSlots];  // G[i][j] = s_i . t_j for stored pairs i, j
+  double omega;        // Chebyshev weight of the last iteration (the recursion's state)
+  double omega_used;   // weight of this iteration's d (1 after an ascent fallback)
   int phase;           // Phase
   int k;               // current iteration (0-based)
   int dir_cycle;       // cycle whose direction pass formed d (the d update runs then)
@@ -136,8 +138,8 @@ constexpr int kMaxItemRows = 256;  // == threads of a level-kernel workgroup
 // What a captured step depends on besides the device mesh itself.
 struct GraphKey {
   const void* ptr[5];  // x, v, fext, xo, vo
-  int iterations, history, max_halvings, budget;
-  double gamma, backtrack, grav[3], h;
+  int iterations, history, max_halvings, budget, direction, cheb_delay;
+  double gamma, backtrack, grav[3], h, cheb_rho;
 };
 
 struct DeviceMesh {
@@ -252,6 +254,8 @@ struct DeviceMesh {
 struct StepParams {
   int iterations, history, max_halvings, budget;  // budget: line-search trials per cycle
   int graph;                                      // replay the fixed sequence as a HIP graph
+  int direction, cheb_delay;                      // Algorithm 2, or 3 with delay S
+  double cheb_rho;                                // Chebyshev spectral-radius estimate
   double gamma, backtrack;
   double grav[3];
   double h;

@@ -97,6 +97,9 @@ StepParams pool_params(const qnsim_pool* p) {
   s.max_halvings = p->opt.max_halvings;
   s.budget = p->opt.trials_per_cycle;
   s.graph = p->opt.step_graph;
+  s.direction = p->opt.direction;
+  s.cheb_delay = p->opt.cheb_delay;
+  s.cheb_rho = p->opt.cheb_rho;
   s.gamma = p->opt.gamma;
   s.backtrack = p->opt.backtrack;
   for (int i = 0; i < 3; ++i) s.grav[i] = p->opt.gravity[i];

@@ -154,6 +154,7 @@ k_step_init(const BlockSeg* __restrict__ blk, int nf, const int* __restrict__ ru
     c->phase = on ? PH_INIT : PH_IDLE;
     c->k = 0; c->dir_cycle = -1; c->final_add = 0; c->npairs = 0; c->newest = 0;
     c->cand = slots > 1 ? 1 : 0; c->trials_iter = 0; c->alpha = 0.0; c->gtd = 0.0;
+    c->omega = 1.0; c->omega_used = 1.0;
     if (on) {
       SimStat* t = stat + s;
       t->g_first = 0.0; t->g_last = 0.0; t->gnorm2_first = 0.0; t->gnorm2_last = 0.0;
@@ -638,9 +639,15 @@ k_rdots(const BlockSeg* __restrict__ blk, int nb, size_t n3, int slots,
 // (grad . d < 0 unless grad = 0). A non-descent direction clears the history
 // and the direction is formed again in the next cycle (d = -A^{-1} grad).
 // On success the line search of the iteration starts at alpha = 1.
+//
+// Chebyshev direction (section 5, Algorithm 3; history 0, so r0 = -A^{-1}
+// grad g): d = omega r0 + (omega - 1) s with s = x_k - x_{k-1} (ring slot 0),
+// grad . d = omega grad . r0 + (omega - 1) s . grad; an ascent direction uses
+// d = r0 for this iteration.
 template <int SL>
 __global__ void __launch_bounds__(BS)
-k_coef_decide(int m, int cyc, const SimSeg* __restrict__ seg, const double* __restrict__ part,
+k_coef_decide(int m, int cyc, int cheb, int cheb_delay, double rho2,
+              const SimSeg* __restrict__ seg, const double* __restrict__ part,
               int nb, Ctl* __restrict__ ctl, SimStat* __restrict__ stat,
               int* __restrict__ dir_count) {
   constexpr int ND = SL + 1;
@@ -677,6 +684,23 @@ k_coef_decide(int m, int cyc, const SimSeg* __restrict__ seg, const double* __re
     const int i = (newest - a + slots) % slots;
     gtd += scoef[i] * ssg[i];
   }
+  if (cheb) {
+    const int k = ctl_s->k;
+    const double om = k < cheb_delay ? 1.0
+                      : (k == cheb_delay ? 2.0 / (2.0 - rho2) : 4.0 / (4.0 - rho2 * ctl_s->omega));
+    ctl_s->omega = om;
+    double used = om, gt = gtd;
+    if (om != 1.0) {
+      gt = om * tot[SL] + (om - 1.0) * ssg[0];
+      if (!(gt < 0.0) && gg > 0.0) {  // ascent direction: d = r0 this iteration
+        used = 1.0;
+        gt = gtd;
+        stat[sim].fallbacks += 1;
+      }
+    }
+    ctl_s->omega_used = used;
+    gtd = gt;
+  }
   if (!(gtd < 0.0) && gg > 0.0) {
     ctl_s->npairs = 0;
     ctl_s->dir_cycle = -1;
@@ -694,9 +718,10 @@ k_coef_decide(int m, int cyc, const SimSeg* __restrict__ seg, const double* __re
 
 // d = r0 + sum_i c_i s_i (oldest pair first, the order of the second loop),
 // for the simulations whose direction was formed in this cycle.
+// (Chebyshev: d = omega r0 + (omega - 1) s, s in ring slot 0.)
 template <int SL>
 __global__ void __launch_bounds__(BS)
-k_dform(const BlockSeg* __restrict__ blk, size_t n3, int slots, int cyc,
+k_dform(const BlockSeg* __restrict__ blk, size_t n3, int slots, int cyc, int cheb,
         const double* __restrict__ Sall, const double* __restrict__ r0, double* __restrict__ d,
         const Ctl* __restrict__ ctl) {
   const BlockSeg sg = blk[blockIdx.x];
@@ -720,6 +745,10 @@ k_dform(const BlockSeg* __restrict__ blk, size_t n3, int slots, int cyc,
 #pragma unroll
   for (int a = 0; a < SL; ++a)
     if (a < np) v += sv[a] * cf[a];
+  if (cheb) {
+    const double om = c->omega_used;
+    if (om != 1.0) v = om * v + (om - 1.0) * Sall[i];
+  }
   d[i] = v;
 }
 
@@ -1071,13 +1100,14 @@ void launch_direction(DeviceMesh& D, const StepParams& P, hipStream_t st, int cy
   QN_SLOTS_DISPATCH(slv, QN_RDOTS)
 #undef QN_RDOTS
 #define QN_COEF(SL)                                                                            \
-  hipLaunchKernelGGL(k_coef_decide<SL>, dim3(D.S), dim3(BS), 0, st, m, cyc, D.seg, pp.rdots,    \
-                     D.rdots_blocks, D.ctl, D.stat, D.dir_count)
+  hipLaunchKernelGGL(k_coef_decide<SL>, dim3(D.S), dim3(BS), 0, st, m, cyc, P.direction,      \
+                     P.cheb_delay, P.cheb_rho * P.cheb_rho, D.seg, pp.rdots, D.rdots_blocks,   \
+                     D.ctl, D.stat, D.dir_count)
   QN_SLOTS_DISPATCH(slv, QN_COEF)
 #undef QN_COEF
 #define QN_DFORM(SL)                                                                           \
   hipLaunchKernelGGL(k_dform<SL>, dim3(L.vec_n), dim3(BS), 0, st, L.vec, n3, slots, cyc,       \
-                     D.Sv, D.r, D.d, D.ctl)
+                     P.direction, D.Sv, D.r, D.d, D.ctl)
   QN_SLOTS_DISPATCH(slv, QN_DFORM)
 #undef QN_DFORM
 }
@@ -1306,6 +1336,7 @@ GraphKey key_of(const StepParams& P, const double* x, const double* v, const dou
   k.ptr[0] = x; k.ptr[1] = v; k.ptr[2] = fext; k.ptr[3] = xo; k.ptr[4] = vo;
   k.iterations = P.iterations; k.history = P.history; k.max_halvings = P.max_halvings;
   k.budget = P.budget; k.gamma = P.gamma; k.backtrack = P.backtrack;
+  k.direction = P.direction; k.cheb_delay = P.cheb_delay; k.cheb_rho = P.cheb_rho;
   for (int i = 0; i < 3; ++i) k.grav[i] = P.grav[i];
   k.h = P.h;
   return k;

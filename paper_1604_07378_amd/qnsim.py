@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libqnsim.so")
 KERNEL_ELEMENT, KERNEL_GATHER, KERNEL_SOLVE = 0, 1, 2
 QNSIM_FP64 = 0
 QNSIM_MIXED = 1
+DIR_LBFGS, DIR_CHEBYSHEV = 0, 1
 NEOHOOKEAN, STVK, SPLINE, COROTATED, POLYNOMIAL = 0, 1, 2, 3, 4
 
 ERRORS = {
@@ -43,7 +44,9 @@ class Options(ctypes.Structure):
                 ("fit_lo", ctypes.c_double), ("fit_hi", ctypes.c_double),
                 ("gravity", ctypes.c_double * 3),
                 ("subtree_cap", ctypes.c_int32), ("level_merge", ctypes.c_int32),
-                ("step_graph", ctypes.c_int32), ("trials_per_cycle", ctypes.c_int32)]
+                ("step_graph", ctypes.c_int32), ("trials_per_cycle", ctypes.c_int32),
+                ("direction", ctypes.c_int32), ("cheb_delay", ctypes.c_int32),
+                ("cheb_rho", ctypes.c_double)]
 
 
 class MaterialC(ctypes.Structure):

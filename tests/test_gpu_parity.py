@@ -438,3 +438,27 @@ def test_collisions_with_a_plane_against_oracle():
     r = oracle.step(_model(w), xo, vo)
     x1, _, _ = s.step(xo, vo, w.h)
     assert _eps(x1, r.x, w.rest) <= 1e-9
+
+
+def test_chebyshev_direction_against_oracle():
+    """Chebyshev semi-iterative direction (section 5, Algorithm 3) with 30
+    iterations per step, S = 10, rho = 0.94: 5 steps against the oracle (1e-9,
+    identical line-search trial counts and fallbacks)."""
+    w = W.workload_cantilever(0)
+    m = _model(w)
+    opts = dict(iterations=30, history=0, direction=qnsim.DIR_CHEBYSHEV, cheb_delay=10,
+                cheb_rho=0.94)
+    s = qnsim.sim_from_workload(w, **opts)
+    xo, vo = w.x0.copy(), w.v0.copy()
+    xg, vg = w.x0.copy(), w.v0.copy()
+    worst = 0.0
+    for step in range(5):
+        r = oracle.step(m, xo, vo, iterations=30, history=0, direction="chebyshev",
+                        cheb_delay=10, cheb_rho=0.94)
+        xo, vo = r.x, r.v
+        xg, vg, st = s.step(xg, vg, w.h)
+        assert (st["ls_trials"], st["fallbacks"]) == (r.ls_trials, r.fallbacks), f"step {step}"
+        e = _eps(xg, xo, w.rest)
+        worst = max(worst, e)
+        assert e <= 1e-9, f"step {step}: eps {e:.3e}"
+    print(f"chebyshev 5 steps x 30 iterations: max eps {worst:.3e}", flush=True)
