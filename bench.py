@@ -264,6 +264,46 @@ def small_runs(args, torch, W, qnsim):
     return out
 
 
+def convergence_run(args, torch, W, qnsim):
+    """Relative error (g(x_k) - g*)/(g(x_0) - g*) of one frame of the Neo-Hookean
+    block after K iterations for the plain PD direction (history 0), the
+    Chebyshev direction (S = 10, rho estimated from a plain-PD run on the same
+    frame) and L-BFGS with m = 2 and 5; g* from 200 L-BFGS iterations (section 5,
+    convergence comparison, on the synthetic block)."""
+    import numpy as np
+    w = W.workload_block(W.NEOHOOKEAN, n=args.n)
+    x0 = torch.from_numpy(w.x0.copy()).cuda()
+    v0 = torch.from_numpy(w.v0.copy()).cuda()
+
+    def frame(K, **opt):
+        sim = qnsim.sim_from_workload(w, iterations=K, **opt)
+        x, v = x0.clone(), v0.clone()
+        st = sim.step_device(x, v, w.h)
+        torch.cuda.synchronize()
+        sim.close()
+        return st, x.cpu().numpy()
+
+    ref, _ = frame(200, history=5)
+    gstar = ref["g_last"]
+    pts = [frame(K, history=0)[1] for K in (38, 39, 40)]
+    rho = float(np.linalg.norm(pts[2] - pts[1]) / np.linalg.norm(pts[1] - pts[0]))
+    rho = min(max(rho, 0.05), 0.999)
+    out = {"rho_estimate": rho, "g_star_iterations": 200, "relative_error": {}}
+    methods = {"pd": dict(history=0),
+               "chebyshev": dict(history=0, direction=qnsim.DIR_CHEBYSHEV, cheb_delay=10,
+                                 cheb_rho=rho),
+               "lbfgs_m2": dict(history=2), "lbfgs_m5": dict(history=5)}
+    for name, opt in methods.items():
+        errs = {}
+        for K in (10, 20, 40):
+            st, _ = frame(K, **opt)
+            errs[str(K)] = (st["g_last"] - gstar) / (st["g_first"] - gstar)
+        out["relative_error"][name] = errs
+    log("[bench] convergence (relative error after 10/20/40 iterations): " + "; ".join(
+        f"{k} " + "/".join(f"{v:.1e}" for v in e.values()) for k, e in out["relative_error"].items()))
+    return out
+
+
 def cpu_baseline(args, W):
     """The FP64 oracle on a bounded sample: one step of the Neo-Hookean block."""
     import numpy as np  # noqa: F401
@@ -299,6 +339,8 @@ def main():
     ap.add_argument("--materials", default="neohookean,stvk,spline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=3)
+    ap.add_argument("--no-convergence", action="store_true",
+                    help="skip the convergence comparison of the direction methods")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the extra mixed-precision Neo-Hookean run")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
@@ -359,6 +401,7 @@ def main():
         mixed = run_material(W.NEOHOOKEAN, args, torch, W, qnsim, {"precision": qnsim.QNSIM_MIXED})
 
     small = small_runs(args, torch, W, qnsim) if args.small_steps > 0 else []
+    conv = convergence_run(args, torch, W, qnsim) if not args.no_convergence else None
     batched = []
     if args.batch_count > 0:
         batched = [batched_run(args, torch, W, qnsim, 0), batched_run(args, torch, W, qnsim, 1)]
@@ -412,6 +455,7 @@ def main():
                                                          "iterations", "kernel_ms")}}
            if mixed else {}),
         **({"small_meshes": small} if small else {}),
+        **({"convergence": conv} if conv else {}),
         **({"batched": batched} if batched else {}),
         **({"served": served} if served else {}),
         "roofline": {
