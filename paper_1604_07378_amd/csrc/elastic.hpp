@@ -47,10 +47,14 @@ __device__ __forceinline__ M3<R> cofactor(const M3<R>& F) {
 // gives the signed singular values. Exact Jacobi and Givens angles are used
 // (not the quaternion approximations of the paper cited).
 // ---------------------------------------------------------------------------
+// One Jacobi rotation of the symmetric S in the (p, q) plane, skipped (false)
+// when S_pq is below rounding relevance: S_pq^2 <= eps2 |S_pp S_qq| (a
+// rotation that small changes no entry of S or V in this precision).
 template <typename R>
-__device__ __forceinline__ void jacobi_rotate(R S[3][3], R V[3][3], int p, int q) {
+__device__ __forceinline__ bool jacobi_rotate(R S[3][3], R V[3][3], int p, int q) {
+  const R eps2 = sizeof(R) == 8 ? R(1e-36) : R(1e-15);
   R spq = S[p][q];
-  if (spq == R(0)) return;
+  if (spq * spq <= eps2 * fabs(S[p][p] * S[q][q])) return false;
   R tau = (S[q][q] - S[p][p]) / (R(2) * spq);
   R t = (tau >= R(0) ? R(1) : R(-1)) / (fabs(tau) + sqrt(R(1) + tau * tau));
   R c = R(1) / sqrt(R(1) + t * t);
@@ -71,6 +75,7 @@ __device__ __forceinline__ void jacobi_rotate(R S[3][3], R V[3][3], int p, int q
     V[k][p] = c * vkp - s * vkq;
     V[k][q] = s * vkp + c * vkq;
   }
+  return true;
 }
 
 template <typename R>
@@ -109,11 +114,13 @@ __device__ __forceinline__ void svd3(const M3<R>& F, R U[3][3], R sig[3], R V[3]
       S[i][j] = F.a[0][i] * F.a[0][j] + F.a[1][i] * F.a[1][j] + F.a[2][i] * F.a[2][j];
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j) V[i][j] = (i == j) ? R(1) : R(0);
+  // cyclic sweeps until one rotates nothing (at most 6; quadratic convergence)
   const int sweeps = sizeof(R) == 8 ? 6 : 4;
   for (int sw = 0; sw < sweeps; ++sw) {
-    jacobi_rotate(S, V, 0, 1);
-    jacobi_rotate(S, V, 0, 2);
-    jacobi_rotate(S, V, 1, 2);
+    bool any = jacobi_rotate(S, V, 0, 1);
+    any |= jacobi_rotate(S, V, 0, 2);
+    any |= jacobi_rotate(S, V, 1, 2);
+    if (!any) break;
   }
   R B[3][3];
   for (int i = 0; i < 3; ++i)
