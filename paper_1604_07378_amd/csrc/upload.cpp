@@ -9,6 +9,7 @@
 #include <cstring>
 #include <numeric>
 #include <string>
+#include <memory>
 #include <vector>
 
 #include "../../include/qnsim.h"
@@ -23,6 +24,17 @@ namespace {
     err = (msg);          \
     return (code);        \
   } while (0)
+
+// host array left uninitialised on allocation (for arrays filled in full)
+template <class T>
+struct RawBuf {
+  std::unique_ptr<T[]> p;
+  size_t n = 0;
+  explicit RawBuf(size_t count) : p(new T[std::max<size_t>(count, 1)]), n(count) {}
+  T* data() { return p.get(); }
+  const T* data() const { return p.get(); }
+  size_t size() const { return n; }
+};
 
 template <class T>
 int upload(DeviceMesh& D, T** dst, const T* src, size_t count, std::string& err) {
@@ -44,18 +56,31 @@ int upload(DeviceMesh& D, T** dst, const T* src, size_t count, std::string& err)
 
 // Supernodes of several factors side by side: column, row-list, block and
 // supernode indices shifted by each factor's offsets.
-void stack_factors(const std::vector<const Factor*>& fs, const std::vector<int>& col0, Factor& F) {
+// The structure of several factors side by side (columns of factor k shifted
+// by col0[k]); the values stay where they are: blk[s] points at supernode s's
+// column-major block inside its own factor.
+void stack_factors(const std::vector<const Factor*>& fs, const std::vector<int>& col0, Factor& F,
+                   std::vector<const double*>& blk) {
   F = Factor();
+  size_t nsn = 0, nrows = 0, nch = 0;
+  for (const Factor* f : fs) {
+    nsn += f->sn.size(); nrows += f->rows.size(); nch += f->children.size();
+  }
+  F.sn.reserve(nsn); F.rows.reserve(nrows); F.rel.reserve(nrows);
+  F.child_ptr.reserve(nsn + 1); F.children.reserve(nch);
+  blk.clear();
+  blk.reserve(nsn);
   F.child_ptr.push_back(0);
   for (size_t k = 0; k < fs.size(); ++k) {
     const Factor& f = *fs[k];
     const int sn0 = (int)F.sn.size();
-    const int64_t rows0 = (int64_t)F.rows.size(), val0 = (int64_t)F.Binv.size();
+    const int64_t rows0 = (int64_t)F.rows.size();
     for (Supernode S : f.sn) {
+      blk.push_back(f.Binv.data() + S.val_off);
       S.first += col0[k];
       if (S.parent >= 0) S.parent += sn0;
       S.rows_off += rows0;
-      S.val_off += val0;
+      S.val_off = -1;
       F.sn.push_back(S);
     }
     for (int r : f.rows) F.rows.push_back(r + col0[k]);
@@ -63,7 +88,6 @@ void stack_factors(const std::vector<const Factor*>& fs, const std::vector<int>&
     const int c0 = (int)F.children.size();
     for (size_t s = 1; s < f.child_ptr.size(); ++s) F.child_ptr.push_back(c0 + f.child_ptr[s]);
     for (int ch : f.children) F.children.push_back(ch + sn0);
-    F.Binv.insert(F.Binv.end(), f.Binv.begin(), f.Binv.end());
     F.n += f.n;
     F.nlevels = std::max(F.nlevels, f.nlevels);
     F.max_front = std::max(F.max_front, f.max_front);
@@ -97,8 +121,6 @@ int upload_sims(const std::vector<const qnsim*>& sims, const qnsim_options& opt,
     int p = nf;
     for (int s = 0; s < S; ++s) { vp0[s] = p; p += sims[s]->n - sims[s]->nf; }
   }
-  // a simulation's internal vertex i -> index in the concatenation
-  auto gv = [&](int s, int i) { return i < sims[s]->nf ? vf0[s] + i : vp0[s] + (i - sims[s]->nf); };
   D.device = opt.device;
   D.S = S;
   D.n = n; D.nf = nf; D.T = T; D.h = h;
@@ -111,18 +133,44 @@ int upload_sims(const std::vector<const qnsim*>& sims, const qnsim_options& opt,
   // element data in internal tet order
   std::vector<int> tv(4 * (size_t)T), tm(T), tperm(T), vperm(n), vsim(n);
   std::vector<double> Bm(9 * (size_t)T), vol(T), mass(n);
+  {
+    // each simulation fills its own ranges: in parallel over simulations
+    struct Fill {
+      const std::vector<const qnsim*>* sims;
+      const int *vf0, *vp0, *t0, *m0, *cv0;
+      int T;
+      int *tv, *tm, *tperm, *vperm, *vsim;
+      double *Bm, *vol, *mass;
+    } fl{&sims, vf0.data(), vp0.data(), t0.data(), m0.data(), cv0.data(), T,
+         tv.data(), tm.data(), tperm.data(), vperm.data(), vsim.data(),
+         Bm.data(), vol.data(), mass.data()};
+    parallel_for(S, 1, &fl, [](const void* ctx, int64_t lo, int64_t hi) {
+      const Fill& q = *static_cast<const Fill*>(ctx);
+      for (int64_t s = lo; s < hi; ++s) {
+        const qnsim* c = (*q.sims)[s];
+        // internal vertex i -> index in the concatenation
+        auto gv = [&](int i) { return i < c->nf ? q.vf0[s] + i : q.vp0[s] + (i - c->nf); };
+        for (int t = 0; t < c->T; ++t) {
+          const int o = c->tperm[t], g = q.t0[s] + t;
+          for (int a = 0; a < 4; ++a)
+            q.tv[4 * (size_t)g + a] = gv(c->viperm[c->tets[4 * (size_t)o + a]]);
+          for (int e = 0; e < 9; ++e) q.Bm[(size_t)e * q.T + g] = c->Dminv[9 * (size_t)o + e];
+          q.vol[g] = c->vol[o];
+          q.tm[g] = q.m0[s] + c->tet_mat[o];
+          q.tperm[g] = q.t0[s] + o;
+        }
+        for (int i = 0; i < c->n; ++i) {
+          const int g = gv(i);
+          q.vperm[g] = q.cv0[s] + c->vperm[i];
+          q.vsim[g] = (int)s;
+          q.mass[g] = c->mass[c->vperm[i]];
+        }
+      }
+    });
+  }
   std::vector<DevMat> dm;
   for (int s = 0; s < S; ++s) {
     const qnsim* c = sims[s];
-    for (int t = 0; t < c->T; ++t) {
-      const int o = c->tperm[t], g = t0[s] + t;
-      for (int a = 0; a < 4; ++a)
-        tv[4 * (size_t)g + a] = gv(s, c->viperm[c->tets[4 * (size_t)o + a]]);
-      for (int e = 0; e < 9; ++e) Bm[(size_t)e * T + g] = c->Dminv[9 * (size_t)o + e];
-      vol[g] = c->vol[o];
-      tm[g] = m0[s] + c->tet_mat[o];
-      tperm[g] = t0[s] + o;
-    }
     for (size_t i = 0; i < c->mats.size(); ++i) {
       const Material& m = c->mats[i];
       DevMat d;
@@ -133,21 +181,18 @@ int upload_sims(const std::vector<const qnsim*>& sims, const qnsim_options& opt,
       for (int j = 0; j < 3; ++j) d.fdir[j] = m.fiber_dir[j];
       dm.push_back(d);
     }
-    for (int i = 0; i < c->n; ++i) {
-      const int g = gv(s, i);
-      vperm[g] = cv0[s] + c->vperm[i];
-      vsim[g] = s;
-      mass[g] = c->mass[c->vperm[i]];
-    }
   }
   // combined factor (a single simulation's is used as it is)
   Factor stacked;
   const Factor* Fp = &sims[0]->factor;
+  std::vector<const double*> blk_src;
   if (S > 1) {
     std::vector<const Factor*> fs(S);
     for (int s = 0; s < S; ++s) fs[s] = &sims[s]->factor;
-    stack_factors(fs, vf0, stacked);
+    stack_factors(fs, vf0, stacked, blk_src);
     Fp = &stacked;
+  } else {
+    for (const Supernode& sn : Fp->sn) blk_src.push_back(Fp->Binv.data() + sn.val_off);
   }
   const Factor& F = *Fp;
   // incidences of free vertices, ordered by (internal tet, slot), in a padded
@@ -183,7 +228,7 @@ int upload_sims(const std::vector<const qnsim*>& sims, const qnsim_options& opt,
     pf[s + 1] = pf[s] + (s == top ? (int64_t)S.ncol * S.ncol : packed);
     pb[s + 1] = pb[s] + (s == top ? 0 : packed);
   }
-  std::vector<double> Bf(pf[ns]), Bb(pb[ns]);
+  RawBuf<double> Bf(pf[ns]), Bb(pb[ns]);  // every entry written below
   std::vector<int4> fwl, bwl;
   std::vector<std::vector<int4>> fw_by_level(F.nlevels), bw_by_level(F.nlevels);
   // bottom subtrees: the lowest levels whose supernodes all have at most
@@ -216,32 +261,50 @@ int upload_sims(const std::vector<const qnsim*>& sims, const qnsim_options& opt,
       bw.push_back(make_int4((int)(0x80000000u | (unsigned)s), c0, std::min(nc, c0 + cols_item), Lb));
     return (m + rows_item - 1) / rows_item;
   };
+  // the two packed copies of every block, in parallel over supernodes
+  {
+    struct Pack {
+      const Factor* F; const double* const* blk; const std::vector<int64_t>* pf;
+      const std::vector<int64_t>* pb; double* Bf; double* Bb; int top;
+    } pk{&F, blk_src.data(), &pf, &pb, Bf.data(), Bb.data(), top};
+    parallel_for(ns, 16, &pk, [](const void* ctx, int64_t lo, int64_t hi) {
+      const Pack& q = *static_cast<const Pack*>(ctx);
+      for (int64_t s = lo; s < hi; ++s) {
+        const Supernode& S = q.F->sn[s];
+        const int nc = S.ncol, m = S.m();
+        const double* blk = q.blk[s];
+        if (s == q.top) {
+          // symmetric: the column-major block is also its row-major copy
+          std::copy(blk, blk + (size_t)nc * nc, q.Bf + (*q.pf)[s]);
+          continue;
+        }
+        double* bf = q.Bf + (*q.pf)[s];
+        double* bb = q.Bb + (*q.pb)[s];
+        for (int r = 0; r < m; ++r) {
+          const int len = r < nc ? r + 1 : nc;
+          const int64_t ro = r < nc ? (int64_t)r * (r + 1) / 2
+                                    : (int64_t)nc * (nc + 1) / 2 + (int64_t)(r - nc) * nc;
+          for (int c = 0; c < len; ++c) bf[ro + c] = blk[r + (size_t)c * m];
+        }
+        for (int c = 0; c < nc; ++c) {
+          const int64_t co = (int64_t)c * m - (int64_t)c * (c - 1) / 2;
+          for (int i = c; i < m; ++i) bb[co + (i - c)] = blk[i + (size_t)c * m];
+        }
+      }
+    });
+  }
   for (int s = 0; s < ns; ++s) {
     const Supernode& S = F.sn[s];
     const int nc = S.ncol, m = S.m();
-    const double* blk = F.Binv.data() + S.val_off;
     SnInfo& I = sinfo[s];
     I.first = S.first; I.ncol = nc; I.nbelow = S.nbelow; I.parent = S.parent;
     I.nchild = F.child_ptr[s + 1] - F.child_ptr[s];
     I.fw_off = pf[s]; I.bw_off = pb[s];
     I.rows_off = S.rows_off; I.vp_in = 0; I.vp_out = -1;
+    (void)m;
     if (s == top) {
-      // symmetric: the column-major block is also its row-major copy
-      std::copy(blk, blk + (size_t)nc * nc, Bf.data() + pf[s]);
       I.fw_items = I.bw_items = 0;
       continue;
-    }
-    double* bf = Bf.data() + pf[s];
-    double* bb = Bb.data() + pb[s];
-    for (int r = 0; r < m; ++r) {
-      const int len = r < nc ? r + 1 : nc;
-      const int64_t ro = r < nc ? (int64_t)r * (r + 1) / 2
-                                : (int64_t)nc * (nc + 1) / 2 + (int64_t)(r - nc) * nc;
-      for (int c = 0; c < len; ++c) bf[ro + c] = blk[r + (size_t)c * m];
-    }
-    for (int c = 0; c < nc; ++c) {
-      const int64_t co = (int64_t)c * m - (int64_t)c * (c - 1) / 2;
-      for (int i = c; i < m; ++i) bb[co + (i - c)] = blk[i + (size_t)c * m];
     }
     if (S.level < Lsub) {
       I.fw_items = I.bw_items = 0;  // one-wave items, built per subtree below
