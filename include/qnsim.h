@@ -261,6 +261,24 @@ int qnsim_get_factor_info(const qnsim_t* ctx, qnsim_factor_info* info);
 int qnsim_export_factor(const qnsim_t* ctx, int32_t* perm, int64_t* colptr,
                         int32_t* rowidx, double* values);
 
+/* Numeric refactorisation on the device for a new time step h. A = M/h^2 +
+ * sum_e V_e k_e G_e^T G_e (sections 3.2 and 4.1) depends on h, and the method
+ * prefactors it once per step size. This keeps the ordering and the
+ * supernodal structure of the prepared factor and recomputes its values on
+ * the device: a multifrontal Cholesky factorisation level by level of the
+ * supernode tree, then the solve blocks in place. The first call builds a
+ * device plan (host work linear in the mesh, plus a device workspace of
+ * sum over supernodes of (rows)^2 doubles, kept until the context is
+ * re-prepared or destroyed); later calls do no host work besides launching.
+ * After success, steps and solves use h, and qnsim_export_factor returns
+ * QNSIM_E_STATE (the host copy of the factor belongs to the analysed h) until
+ * the next qnsim_prepare. *device_ms (nullable): device time of the
+ * refactorisation. Errors: QNSIM_E_STATE (not prepared), QNSIM_E_INVALID (h
+ * not positive and finite, or a front wider than 20000 rows),
+ * QNSIM_E_NOT_SPD (a pivot not positive: the previous factor and h stay in
+ * force), QNSIM_E_NOMEM, QNSIM_E_DEVICE. Synchronises. */
+int qnsim_refactor(qnsim_t* ctx, double h, double* device_ms);
+
 /* ---- kernel-level entry points (device arrays, caller's numbering) ------ */
 
 /* Objective and gradient at positions d_x with inertia target d_y (n x 3):

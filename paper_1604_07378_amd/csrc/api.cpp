@@ -376,8 +376,9 @@ int qnsim_set_materials(qnsim_t* c, int32_t n_mat, const qnsim_material* mats,
 
 int qnsim_analyze(qnsim_t* c, double h) {
   if (!c) return QNSIM_E_INVALID;
-  if (c->analyzed && c->h == h) return QNSIM_OK;
+  if (c->analyzed && c->h == h && !c->factor_on_device) return QNSIM_OK;
   invalidate(c);
+  c->factor_on_device = false;
   try {
     return analyze_impl(c, h);
   } catch (const std::bad_alloc&) {
@@ -603,7 +604,7 @@ int qnsim_get_factor_info(const qnsim_t* c, qnsim_factor_info* info) {
 int qnsim_export_factor(const qnsim_t* c, int32_t* perm, int64_t* colptr, int32_t* rowidx,
                         double* values) {
   if (!c) return QNSIM_E_INVALID;
-  if (!c->analyzed) return QNSIM_E_STATE;
+  if (!c->analyzed || c->factor_on_device) return QNSIM_E_STATE;
   if (perm)
     for (int i = 0; i < c->nf; ++i) perm[i] = c->vperm[i];
   if (colptr || rowidx || values) {
@@ -615,6 +616,24 @@ int qnsim_export_factor(const qnsim_t* c, int32_t* perm, int64_t* colptr, int32_
     if (rowidx) std::copy(ri.begin(), ri.end(), rowidx);
     if (values) std::copy(va.begin(), va.end(), values);
   }
+  return QNSIM_OK;
+}
+
+int qnsim_refactor(qnsim_t* c, double h, double* device_ms) {
+  if (!c) return QNSIM_E_INVALID;
+  if (!c->prepared) return fail(c, QNSIM_E_STATE, "qnsim_prepare has not been called");
+  if (!(h > 0.0) || !std::isfinite(h)) return fail(c, QNSIM_E_INVALID, "h must be positive");
+  std::string err;
+  int rc;
+  try {
+    rc = dev_refactor(c, h, device_ms, err);
+  } catch (const std::bad_alloc&) {
+    rc = QNSIM_E_NOMEM;
+    err = "host allocation failed";
+  }
+  if (rc) return fail(c, rc, err);
+  c->h = h;
+  c->factor_on_device = true;
   return QNSIM_OK;
 }
 

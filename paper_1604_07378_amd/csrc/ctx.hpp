@@ -45,6 +45,9 @@ struct qnsim {
   double* stage = nullptr;        // qnsim_step staging: x, v, f_ext, x', v' (5 n x 3)
   std::vector<double> planes;     // colliders: n x 4 (unit normal, offset)
   double coll_k = 0.0;
+  // the device factor was recomputed for h (qnsim_refactor): the host factor
+  // values belong to the analysed step size only
+  bool factor_on_device = false;
 };
 
 namespace qn {
@@ -52,4 +55,7 @@ namespace qn {
 // concatenated; returns 0 or a negative QNSIM_E_* code with err set.
 int upload_sims(const std::vector<const qnsim*>& sims, const qnsim_options& opt, double h,
                 DeviceMesh& D, std::string& err);
+// Numeric refactorisation of A for step size h on the device (single mesh);
+// device_ms (nullable): device time of the factorisation and block writes.
+int dev_refactor(qnsim* c, double h, double* device_ms, std::string& err);
 }  // namespace qn

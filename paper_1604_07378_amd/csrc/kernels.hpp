@@ -142,6 +142,8 @@ struct GraphKey {
   double gamma, backtrack, grav[3], h, cheb_rho;
 };
 
+struct RefactorPlan;  // device refactorisation plan (built on first use)
+
 struct DeviceMesh {
   int device = 0;
   int n = 0, nf = 0, T = 0, nmat = 0, single_type = -1, m = 5, slots = 6;
@@ -248,6 +250,7 @@ struct DeviceMesh {
   void* graph_exec = nullptr; // captured fixed sequence of a step (hipGraphExec_t)
   GraphKey graph_key = {};
   void* ev[2] = {nullptr, nullptr};
+  RefactorPlan* rf = nullptr;
   size_t bytes = 0;
 };
 
@@ -281,6 +284,11 @@ inline int top_workgroups(int n) {
 // All launchers return 0 or a negative QNSIM_E_* code; err receives a message.
 int dev_alloc(DeviceMesh& d, std::string& err);
 void dev_free(DeviceMesh& d);
+// Forget the captured step (its arguments no longer match the mesh).
+void dev_drop_graph(DeviceMesh& d);
+// Device refactorisation plan: release; its device bytes.
+void rf_free(DeviceMesh& d);
+size_t rf_bytes(const DeviceMesh& d);
 int dev_sync(DeviceMesh& d, void* stream, std::string& err);
 
 // One full time step of every simulation whose run flag is set (set_run

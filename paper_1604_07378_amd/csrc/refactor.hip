@@ -1,0 +1,671 @@
+// Numeric refactorisation on the device. The matrix of the global step,
+// A = M/h^2 + sum_e V_e k_e G_e^T G_e (sections 3.2 and 4.1), is constant for
+// a fixed step size and is factored once; when h changes only its values
+// change. This file keeps the ordering and the supernodal structure found by
+// the host analysis and recomputes the values on the device:
+//
+//  1. the fronts: each supernode's m x m front (column-major, lower triangle)
+//     gets its entries of A (K values from the host, M/h^2 on the diagonal);
+//  2. level by level of the supernode tree (multifrontal): the children's
+//     Schur complements are added into the parent's front (one launch per
+//     child rank, so every sum is taken in a fixed order), then the leading
+//     ncol columns are factored right-looking in panels of NB columns
+//     (a panel kernel: Cholesky of the diagonal block, its inverse, and the
+//     rows below; an update kernel: the trailing lower triangle in 64 x 64
+//     tiles); what is left in the last nbelow x nbelow block is the update
+//     for the parent;
+//  3. the solve blocks: L11^{-1} by block columns (each block column of the
+//     inverse is independent; within one, block rows follow in order), then
+//     [L11^{-1}; L21 L11^{-1}] is written into the row-major and the
+//     column-major packed copies, or, for the dense top block, the full
+//     (L11 L11^T)^{-1} = L11^{-T} L11^{-1}.
+//
+// The solve blocks are overwritten only once every pivot has been found
+// positive, so a failed refactorisation leaves the previous factor in force.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "ctx.hpp"
+
+namespace qn {
+
+namespace {
+
+constexpr int NB = 32;  // panel width (columns factored per round)
+constexpr int TL = 64;  // rows and columns of a trailing-update tile
+
+struct RfNode {
+  int ncol, nbelow, nchild, child0;  // child0: first entry in the children list
+  long long front;  // m x m column-major front in the workspace
+  long long xoff;   // ncol x ncol column-major L11^{-1}
+  long long fw, bw; // the supernode's blocks in the forward / backward packed copies
+  long long rel;    // positions of its below rows in the parent's front
+  int top, pad;     // top: stored as the full (L11 L11^T)^{-1} (forward copy only)
+};
+
+struct RfItem {
+  int node, a, b, pad;
+};
+
+}  // namespace
+
+struct RefactorPlan {
+  int ns = 0, nlev = 0;
+  std::vector<RfNode> node_h;
+  std::vector<int> lvl_ptr;      // nlev + 1
+  std::vector<int> lvl_nodes_h;  // by level; ncol descending within a level
+  std::vector<int> children_h;
+  RfNode* node = nullptr;
+  int* lvl_nodes = nullptr;
+  int* children = nullptr;
+  int* rel = nullptr;
+  long long* apos = nullptr;  // positions in the workspace of the entries of A
+  double* aval = nullptr;     // their K values (independent of h)
+  int* adiag = nullptr;       // column of a diagonal entry (mass added), else -1
+  long long nnz = 0;
+  double* ws = nullptr;
+  long long ws_len = 0;
+  double* X = nullptr;
+  long long x_len = 0;
+  RfItem* inv_items = nullptr;
+  int n_inv = 0;
+  RfItem* out_items = nullptr;
+  int n_out = 0;
+  int* flag = nullptr;
+  int* flag_host = nullptr;
+  void* ev[2] = {nullptr, nullptr};
+  size_t bytes = 0;
+};
+
+namespace {
+
+__global__ void k_rf_zero(double* __restrict__ p, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    p[i] = 0.0;
+}
+
+__global__ void k_rf_scatter(const long long* __restrict__ apos, const double* __restrict__ aval,
+                             const int* __restrict__ adiag, long long nnz,
+                             const double* __restrict__ mass, double inv_h2,
+                             double* __restrict__ ws, int* __restrict__ flag) {
+  const long long i0 = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (i0 == 0) *flag = 0;
+  for (long long e = i0; e < nnz; e += (long long)gridDim.x * blockDim.x) {
+    double v = aval[e];
+    const int j = adiag[e];
+    if (j >= 0) v += mass[j] * inv_h2;
+    ws[apos[e]] = v;
+  }
+}
+
+// Adds the Schur complement of each level node's ci-th child into the node's
+// front. blockIdx.x: node of the level; blockIdx.y: chunk of the child's
+// update block.
+__global__ __launch_bounds__(256) void k_rf_extend(const int* __restrict__ lvl_nodes,
+                                                   const RfNode* __restrict__ node,
+                                                   const int* __restrict__ children,
+                                                   const int* __restrict__ rel,
+                                                   double* __restrict__ ws, int ci) {
+  const RfNode p = node[lvl_nodes[blockIdx.x]];
+  if (ci >= p.nchild) return;
+  const RfNode c = node[children[p.child0 + ci]];
+  const int nb = c.nbelow;
+  const int mC = c.ncol + nb, mP = p.ncol + p.nbelow;
+  const int* rl = rel + c.rel;
+  const double* U = ws + c.front + c.ncol + (long long)c.ncol * mC;
+  double* Fp = ws + p.front;
+  const long long tot = (long long)nb * nb;
+  for (long long t = blockIdx.y * 256LL + threadIdx.x; t < tot; t += (long long)gridDim.y * 256) {
+    const int b = (int)(t / nb), a = (int)(t - (long long)b * nb);
+    if (a < b) continue;
+    Fp[rl[a] + (long long)rl[b] * mP] += U[a + (long long)b * mC];
+  }
+}
+
+// Panel j0 of each active node (one workgroup per node): Cholesky of the
+// diagonal block in LDS, its inverse (kept as the diagonal block of
+// L11^{-1}), and the rows below, L_r = F_r L_jj^{-T}.
+__global__ __launch_bounds__(256) void k_rf_panel(const int* __restrict__ lvl_nodes,
+                                                  const RfNode* __restrict__ node,
+                                                  double* __restrict__ ws, double* __restrict__ X,
+                                                  int j0, int* __restrict__ flag) {
+  __shared__ double Dk[NB][NB + 1];
+  __shared__ double Iv[NB][NB + 1];
+  const RfNode nd = node[lvl_nodes[blockIdx.x]];
+  const int nc = nd.ncol, m = nc + nd.nbelow;
+  const int jb = min(NB, nc - j0);
+  double* F = ws + nd.front;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < NB * NB; e += 256) {
+    const int i = e % NB, k = e / NB;
+    Dk[i][k] = (i < jb && k < jb && i >= k) ? F[(j0 + i) + (long long)(j0 + k) * m] : 0.0;
+    Iv[i][k] = 0.0;
+  }
+  __syncthreads();
+  for (int k = 0; k < jb; ++k) {
+    double d = Dk[k][k];
+    if (!(d > 0.0) || !isfinite(d)) {
+      if (tid == 0) *flag = 1;
+      d = 1.0;  // keep the arithmetic finite; the result is discarded
+    }
+    const double l = sqrt(d);
+    __syncthreads();  // every thread has read the pivot
+    if (tid == 0) Dk[k][k] = l;
+    if (tid > k && tid < jb) Dk[tid][k] /= l;
+    __syncthreads();
+    for (int e = tid; e < NB * NB; e += 256) {
+      const int i = e % NB, c = e / NB;
+      if (c > k && i >= c && i < jb) Dk[i][c] -= Dk[i][k] * Dk[c][k];
+    }
+    __syncthreads();
+  }
+  // column c of L_jj^{-1} by forward substitution (zero above the diagonal)
+  if (tid < jb) {
+    const int c = tid;
+    Iv[c][c] = 1.0 / Dk[c][c];
+    for (int i = c + 1; i < jb; ++i) {
+      double s = 0.0;
+      for (int k = c; k < i; ++k) s += Dk[i][k] * Iv[k][c];
+      Iv[i][c] = -s / Dk[i][i];
+    }
+  }
+  __syncthreads();
+  double* Xn = X + nd.xoff;
+  for (int e = tid; e < NB * NB; e += 256) {
+    const int i = e % NB, k = e / NB;
+    if (i < jb && k < jb) {
+      if (i >= k) F[(j0 + i) + (long long)(j0 + k) * m] = Dk[i][k];
+      Xn[(j0 + i) + (long long)(j0 + k) * nc] = Iv[i][k];
+    }
+  }
+  // rows below the diagonal block: L[r][k] = sum_p F[r][p] Iv[k][p]
+  for (int r = j0 + jb + tid; r < m; r += 256) {
+    double f[NB];
+#pragma unroll
+    for (int p = 0; p < NB; ++p) f[p] = p < jb ? F[r + (long long)(j0 + p) * m] : 0.0;
+    for (int k = 0; k < jb; ++k) {
+      double s = 0.0;
+#pragma unroll
+      for (int p = 0; p < NB; ++p) s += f[p] * Iv[k][p];
+      F[r + (long long)(j0 + k) * m] = s;
+    }
+  }
+}
+
+// Trailing update after panel j0: F[i][k] -= sum_p L[i][p] L[k][p] on the
+// lower triangle of rows and columns [j0 + jb, m). blockIdx.x: node;
+// blockIdx.y: 64 x 64 tile of the lower triangle of tiles.
+__global__ __launch_bounds__(256) void k_rf_update(const int* __restrict__ lvl_nodes,
+                                                   const RfNode* __restrict__ node,
+                                                   double* __restrict__ ws, int j0) {
+  __shared__ double Ai[TL][NB + 1];
+  __shared__ double Ak[TL][NB + 1];
+  const RfNode nd = node[lvl_nodes[blockIdx.x]];
+  const int nc = nd.ncol, m = nc + nd.nbelow;
+  const int jb = min(NB, nc - j0);
+  const int s0 = j0 + jb, N = m - s0;
+  if (N <= 0) return;
+  const int Tn = (N + TL - 1) / TL;
+  const int t = blockIdx.y;
+  if (t >= Tn * (Tn + 1) / 2) return;
+  int ti = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+  while (ti * (ti + 1) / 2 > t) --ti;
+  while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+  const int tk = t - ti * (ti + 1) / 2;
+  const int r0 = s0 + ti * TL, c0 = s0 + tk * TL;
+  double* F = ws + nd.front;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < TL * NB; e += 256) {
+    const int r = e % TL, p = e / TL;
+    const bool okp = p < jb;
+    Ai[r][p] = (okp && r0 + r < m) ? F[(r0 + r) + (long long)(j0 + p) * m] : 0.0;
+    Ak[r][p] = (okp && c0 + r < m) ? F[(c0 + r) + (long long)(j0 + p) * m] : 0.0;
+  }
+  __syncthreads();
+  const int tx = tid % 16, ty = tid / 16;
+  double acc[4][4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+#pragma unroll 4
+  for (int p = 0; p < NB; ++p) {
+    double a[4], b[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) a[u] = Ai[tx + 16 * u][p];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) b[v] = Ak[ty + 16 * v][p];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * b[v];
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int col = c0 + ty + 16 * v;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int row = r0 + tx + 16 * u;
+      if (row < m && col < m && row >= col) F[row + (long long)col * m] -= acc[u][v];
+    }
+  }
+}
+
+// Block column J of L11^{-1} (one workgroup per item): for block rows
+// I = J+1, J+2, ...: X[I][J] = -X[I][I] sum_{K=J}^{I-1} L[I][K] X[K][J], the
+// diagonal blocks X[I][I] coming from the panel kernel.
+__global__ __launch_bounds__(256) void k_rf_inv(const RfItem* __restrict__ items,
+                                                const RfNode* __restrict__ node,
+                                                const double* __restrict__ ws,
+                                                double* __restrict__ X) {
+  __shared__ double Lb[NB][NB + 1];
+  __shared__ double Xb[NB][NB + 1];
+  __shared__ double Ac[NB][NB + 1];
+  const RfItem it = items[blockIdx.x];
+  const RfNode nd = node[it.node];
+  const int nc = nd.ncol, m = nc + nd.nbelow, J = it.a;
+  const int nbk = (nc + NB - 1) / NB;
+  const double* F = ws + nd.front;
+  double* Xn = X + nd.xoff;
+  const int tid = threadIdx.x, tx = tid % NB, ty = tid / NB;  // rows tx, columns ty + 8 v
+  const int cJ = J * NB;
+  for (int I = J + 1; I < nbk; ++I) {
+    const int rI = I * NB;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int K = J; K < I; ++K) {
+      const int rK = K * NB;
+      for (int e = tid; e < NB * NB; e += 256) {
+        const int i = e % NB, k = e / NB;
+        Lb[i][k] = (rI + i < nc) ? F[(rI + i) + (long long)(rK + k) * m] : 0.0;
+        Xb[i][k] = (cJ + k < nc) ? Xn[(rK + i) + (long long)(cJ + k) * nc] : 0.0;
+      }
+      __syncthreads();
+#pragma unroll 8
+      for (int p = 0; p < NB; ++p) {
+        const double l = Lb[tx][p];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[v] += l * Xb[p][ty + 8 * v];
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Ac[tx][ty + 8 * v] = acc[v];
+    for (int e = tid; e < NB * NB; e += 256) {
+      const int i = e % NB, k = e / NB;
+      Lb[i][k] = (rI + i < nc && rI + k < nc) ? Xn[(rI + i) + (long long)(rI + k) * nc] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int c = ty + 8 * v;
+      double s = 0.0;
+#pragma unroll 8
+      for (int p = 0; p < NB; ++p) s += Lb[tx][p] * Ac[p][c];
+      if (rI + tx < nc && cJ + c < nc) Xn[(rI + tx) + (long long)(cJ + c) * nc] = -s;
+    }
+    __syncthreads();  // the new block is read by the next block row
+  }
+}
+
+// Solve blocks, one 64-row x 32-column tile per item. Ordinary supernode: the
+// m x ncol block [L11^{-1}; L21 L11^{-1}] into both packed copies. Dense top:
+// the full (L11 L11^T)^{-1}[i][j] = sum_k X[k][i] X[k][j] into the forward copy.
+__global__ __launch_bounds__(256) void k_rf_out(const RfItem* __restrict__ items,
+                                                const RfNode* __restrict__ node,
+                                                const double* __restrict__ ws,
+                                                const double* __restrict__ X,
+                                                double* __restrict__ Bf, double* __restrict__ Bb) {
+  __shared__ double Lt[TL][NB + 1];
+  __shared__ double Xb[NB][NB + 1];
+  const RfItem it = items[blockIdx.x];
+  const RfNode nd = node[it.node];
+  const int nc = nd.ncol, m = nc + nd.nbelow;
+  const int r0 = it.a * TL, cJ = it.b * NB;
+  const double* F = ws + nd.front;
+  const double* Xn = X + nd.xoff;
+  const int tid = threadIdx.x, tx = tid % TL, ty = tid / TL;  // rows tx, columns ty + 4 v
+  double acc[8];
+#pragma unroll
+  for (int v = 0; v < 8; ++v) acc[v] = 0.0;
+  const bool prod = nd.top ? true : (r0 + TL > nc);  // any row of the tile needs a product
+  if (prod) {
+    const int K0 = nd.top ? max(r0, cJ) / NB : it.b;
+    for (int K = K0; K * NB < nc; ++K) {
+      const int rK = K * NB;
+      for (int e = tid; e < TL * NB; e += 256) {
+        if (nd.top) {
+          const int k = e % NB, r = e / NB;  // X[rK + k][r0 + r], read along k
+          Lt[r][k] = (r0 + r < nc && rK + k < nc && rK + k >= r0 + r)
+                         ? Xn[(rK + k) + (long long)(r0 + r) * nc] : 0.0;
+        } else {
+          const int r = e % TL, k = e / TL;  // L21 rows r0 + r >= nc, columns rK + k
+          const int row = r0 + r;
+          Lt[r][k] = (row >= nc && row < m && rK + k < nc) ? F[row + (long long)(rK + k) * m] : 0.0;
+        }
+      }
+      // L11^{-1} is lower triangular: entries above the diagonal read as zero
+      for (int e = tid; e < NB * NB; e += 256) {
+        const int i = e % NB, k = e / NB;
+        Xb[i][k] = (rK + i < nc && cJ + k < nc && rK + i >= cJ + k)
+                       ? Xn[(rK + i) + (long long)(cJ + k) * nc] : 0.0;
+      }
+      __syncthreads();
+#pragma unroll 8
+      for (int p = 0; p < NB; ++p) {
+        const double l = Lt[tx][p];
+#pragma unroll
+        for (int v = 0; v < 8; ++v) acc[v] += l * Xb[p][ty + 4 * v];
+      }
+      __syncthreads();
+    }
+  }
+  const int row = r0 + tx;
+#pragma unroll
+  for (int v = 0; v < 8; ++v) {
+    const int c = cJ + ty + 4 * v;
+    if (c >= nc) continue;
+    if (nd.top) {
+      if (row < nc) Bf[nd.fw + row + (long long)c * nc] = acc[v];
+      continue;
+    }
+    if (row >= m || row < c) continue;
+    const double val = row < nc ? Xn[row + (long long)c * nc] : acc[v];
+    Bb[nd.bw + (long long)c * m - (long long)c * (c - 1) / 2 + (row - c)] = val;
+    const long long fo = row < nc ? (long long)row * (row + 1) / 2 + c
+                                  : (long long)nc * (nc + 1) / 2 + (long long)(row - nc) * nc + c;
+    Bf[nd.fw + fo] = val;
+  }
+}
+
+#define RF_FAIL(code, msg) \
+  do {                     \
+    err = (msg);           \
+    return (code);         \
+  } while (0)
+
+template <class T>
+int rf_upload(RefactorPlan& P, T** dst, const std::vector<T>& src, std::string& err) {
+  const size_t bytes = std::max<size_t>(src.size() * sizeof(T), 8);
+  if (hipMalloc((void**)dst, bytes) != hipSuccess) RF_FAIL(QNSIM_E_NOMEM, "hipMalloc failed (refactor plan)");
+  P.bytes += bytes;
+  if (!src.empty() &&
+      hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess)
+    RF_FAIL(QNSIM_E_DEVICE, "hipMemcpy failed (refactor plan)");
+  return QNSIM_OK;
+}
+
+// The plan: node table, schedules, the entries of K in front positions.
+int build_plan(const qnsim* c, RefactorPlan& P, std::string& err) {
+  const Factor& F = c->factor;
+  const DeviceMesh& D = c->dev;
+  const int ns = (int)F.sn.size();
+  if (D.nsn != ns || D.S != 1) RF_FAIL(QNSIM_E_STATE, "refactor: device mesh does not match the factor");
+  std::vector<SnInfo> si(ns);
+  if (hipMemcpy(si.data(), D.sn, ns * sizeof(SnInfo), hipMemcpyDeviceToHost) != hipSuccess)
+    RF_FAIL(QNSIM_E_DEVICE, "refactor: reading the supernode table failed");
+  P.ns = ns;
+  P.node_h.resize(ns);
+  long long wsl = 0, xl = 0;
+  for (int s = 0; s < ns; ++s) {
+    const Supernode& S = F.sn[s];
+    if (si[s].first != S.first || si[s].ncol != S.ncol || si[s].nbelow != S.nbelow)
+      RF_FAIL(QNSIM_E_STATE, "refactor: supernode table differs from the factor");
+    RfNode& n = P.node_h[s];
+    std::memset(&n, 0, sizeof(n));
+    n.ncol = S.ncol;
+    n.nbelow = S.nbelow;
+    n.nchild = F.child_ptr[s + 1] - F.child_ptr[s];
+    n.child0 = F.child_ptr[s];
+    const long long m = S.m();
+    n.front = wsl;
+    wsl += m * m;
+    n.xoff = xl;
+    xl += (long long)S.ncol * S.ncol;
+    n.fw = si[s].fw_off;
+    n.bw = si[s].bw_off;
+    n.rel = S.rows_off;
+    n.top = s == F.top ? 1 : 0;
+    if (n.top && (S.nbelow != 0 || D.top_n != S.ncol || D.top_off != si[s].fw_off))
+      RF_FAIL(QNSIM_E_STATE, "refactor: dense top block differs from the factor");
+    // trailing-update tiles of one front are a grid dimension (at most 65535)
+    if (m > 20000) RF_FAIL(QNSIM_E_INVALID, "refactor: front too large for the tile grid");
+  }
+  P.ws_len = wsl;
+  P.x_len = xl;
+  // levels (ncol descending within a level)
+  P.nlev = F.nlevels;
+  P.lvl_ptr.assign(P.nlev + 1, 0);
+  for (int s = 0; s < ns; ++s) P.lvl_ptr[F.sn[s].level + 1]++;
+  for (int l = 0; l < P.nlev; ++l) P.lvl_ptr[l + 1] += P.lvl_ptr[l];
+  P.lvl_nodes_h.resize(ns);
+  {
+    std::vector<int> fill(P.lvl_ptr.begin(), P.lvl_ptr.end() - 1);
+    for (int s = 0; s < ns; ++s) P.lvl_nodes_h[fill[F.sn[s].level]++] = s;
+    for (int l = 0; l < P.nlev; ++l)
+      std::stable_sort(P.lvl_nodes_h.begin() + P.lvl_ptr[l], P.lvl_nodes_h.begin() + P.lvl_ptr[l + 1],
+                       [&](int a, int b) { return F.sn[a].ncol > F.sn[b].ncol; });
+  }
+  P.children_h = F.children;
+  for (int s = 0; s < ns; ++s)
+    for (int e = F.child_ptr[s]; e < F.child_ptr[s + 1]; ++e) {
+      const int ch = F.children[e];
+      if (F.sn[ch].parent != s || F.sn[ch].level >= F.sn[s].level)
+        RF_FAIL(QNSIM_E_STATE, "refactor: inconsistent supernode tree");
+      const int mP = F.sn[s].m();
+      for (int r = 0; r < F.sn[ch].nbelow; ++r) {
+        const int pos = F.rel[F.sn[ch].rows_off + r];
+        if (pos < 0 || pos >= mP || (r > 0 && pos <= F.rel[F.sn[ch].rows_off + r - 1]))
+          RF_FAIL(QNSIM_E_STATE, "refactor: bad relative rows");
+      }
+    }
+  // entries of K = sum_e V_e k_e G_e^T G_e (lower triangle), in front positions
+  const int nf = c->nf;
+  std::vector<int> col_sn(nf, -1);
+  for (int s = 0; s < ns; ++s)
+    for (int j = 0; j < F.sn[s].ncol; ++j) col_sn[F.sn[s].first + j] = s;
+  for (int j = 0; j < nf; ++j)
+    if (col_sn[j] < 0) RF_FAIL(QNSIM_E_STATE, "refactor: column outside every supernode");
+  auto front_pos = [&](int row, int col) -> long long {
+    const int s = col_sn[col];
+    const Supernode& S = F.sn[s];
+    int lr;
+    if (row < S.first + S.ncol) {
+      lr = row - S.first;
+    } else {
+      const int* rb = F.rows.data() + S.rows_off;
+      const int* it = std::lower_bound(rb, rb + S.nbelow, row);
+      if (it == rb + S.nbelow || *it != row) return -1;
+      lr = S.ncol + (int)(it - rb);
+    }
+    return P.node_h[s].front + lr + (long long)(col - S.first) * S.m();
+  };
+  struct Ent {
+    long long pos;
+    double v;
+    int diag;
+  };
+  std::vector<Ent> ents;
+  ents.reserve((size_t)c->T * 10 + nf);
+  for (int j = 0; j < nf; ++j) ents.push_back({front_pos(j, j), 0.0, j});
+  for (int t = 0; t < c->T; ++t) {
+    const int* tv = &c->tets[4 * (size_t)t];
+    const double* Mi = &c->Dminv[9 * (size_t)t];
+    double g[4][3];
+    for (int k = 0; k < 3; ++k) {
+      g[1][k] = Mi[0 * 3 + k];
+      g[2][k] = Mi[1 * 3 + k];
+      g[3][k] = Mi[2 * 3 + k];
+      g[0][k] = -(g[1][k] + g[2][k] + g[3][k]);
+    }
+    const double w = c->vol[t] * c->kstiff[t];
+    for (int a = 0; a < 4; ++a) {
+      const int ia = c->viperm[tv[a]];
+      if (ia >= nf) continue;
+      for (int b = 0; b < 4; ++b) {
+        const int ib = c->viperm[tv[b]];
+        if (ib >= nf || ia < ib) continue;
+        const long long pos = front_pos(ia, ib);
+        if (pos < 0) RF_FAIL(QNSIM_E_STATE, "refactor: matrix entry outside the factor structure");
+        ents.push_back({pos, w * (g[a][0] * g[b][0] + g[a][1] * g[b][1] + g[a][2] * g[b][2]),
+                        ia == ib ? ia : -1});
+      }
+    }
+  }
+  std::stable_sort(ents.begin(), ents.end(), [](const Ent& x, const Ent& y) { return x.pos < y.pos; });
+  std::vector<long long> apos;
+  std::vector<double> aval;
+  std::vector<int> adiag;
+  for (size_t e = 0; e < ents.size();) {
+    size_t f = e;
+    double s = 0.0;
+    while (f < ents.size() && ents[f].pos == ents[e].pos) s += ents[f++].v;
+    if (ents[e].pos < 0 || ents[e].pos >= wsl) RF_FAIL(QNSIM_E_STATE, "refactor: entry position out of range");
+    apos.push_back(ents[e].pos);
+    aval.push_back(s);
+    adiag.push_back(ents[e].diag);
+    e = f;
+  }
+  std::vector<Ent>().swap(ents);
+  P.nnz = (long long)apos.size();
+  // work lists of the solve-block kernels (longest block columns first)
+  std::vector<RfItem> inv, out;
+  for (int s = 0; s < ns; ++s) {
+    const int nc = F.sn[s].ncol, m = F.sn[s].m();
+    const int nbk = (nc + NB - 1) / NB;
+    for (int J = 0; J + 1 < nbk; ++J) inv.push_back({s, J, nbk - J, 0});
+    const int rows = s == F.top ? nc : m;
+    for (int a = 0; a * TL < rows; ++a)
+      for (int J = 0; J < nbk; ++J) out.push_back({s, a, J, 0});
+  }
+  std::stable_sort(inv.begin(), inv.end(), [](const RfItem& x, const RfItem& y) { return x.b > y.b; });
+  P.n_inv = (int)inv.size();
+  P.n_out = (int)out.size();
+  int rc;
+  if ((rc = rf_upload(P, &P.node, P.node_h, err))) return rc;
+  if ((rc = rf_upload(P, &P.lvl_nodes, P.lvl_nodes_h, err))) return rc;
+  if ((rc = rf_upload(P, &P.children, P.children_h, err))) return rc;
+  if ((rc = rf_upload(P, &P.rel, F.rel, err))) return rc;
+  if ((rc = rf_upload(P, &P.apos, apos, err))) return rc;
+  if ((rc = rf_upload(P, &P.aval, aval, err))) return rc;
+  if ((rc = rf_upload(P, &P.adiag, adiag, err))) return rc;
+  if ((rc = rf_upload(P, &P.inv_items, inv, err))) return rc;
+  if ((rc = rf_upload(P, &P.out_items, out, err))) return rc;
+  if (hipMalloc((void**)&P.ws, std::max<long long>(wsl, 1) * sizeof(double)) != hipSuccess)
+    RF_FAIL(QNSIM_E_NOMEM, "hipMalloc failed (refactor fronts)");
+  P.bytes += (size_t)std::max<long long>(wsl, 1) * sizeof(double);
+  if (hipMalloc((void**)&P.X, std::max<long long>(xl, 1) * sizeof(double)) != hipSuccess)
+    RF_FAIL(QNSIM_E_NOMEM, "hipMalloc failed (refactor inverse blocks)");
+  P.bytes += (size_t)std::max<long long>(xl, 1) * sizeof(double);
+  if (hipMalloc((void**)&P.flag, sizeof(int)) != hipSuccess) RF_FAIL(QNSIM_E_NOMEM, "hipMalloc failed");
+  if (hipHostMalloc((void**)&P.flag_host, sizeof(int)) != hipSuccess) RF_FAIL(QNSIM_E_NOMEM, "hipHostMalloc failed");
+  for (int k = 0; k < 2; ++k)
+    if (hipEventCreate((hipEvent_t*)&P.ev[k]) != hipSuccess) RF_FAIL(QNSIM_E_DEVICE, "hipEventCreate failed");
+  return QNSIM_OK;
+}
+
+}  // namespace
+
+void rf_free(DeviceMesh& D) {
+  RefactorPlan* P = D.rf;
+  if (!P) return;
+  void* ptrs[] = {P->node, P->lvl_nodes, P->children, P->rel, P->apos, P->aval, P->adiag,
+                  P->ws, P->X, P->inv_items, P->out_items, P->flag};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  if (P->flag_host) (void)hipHostFree(P->flag_host);
+  for (void* e : P->ev)
+    if (e) (void)hipEventDestroy((hipEvent_t)e);
+  delete P;
+  D.rf = nullptr;
+}
+
+size_t rf_bytes(const DeviceMesh& D) { return D.rf ? D.rf->bytes : 0; }
+
+int dev_refactor(qnsim* c, double h, double* device_ms, std::string& err) {
+  DeviceMesh& D = c->dev;
+  if (hipSetDevice(D.device) != hipSuccess) RF_FAIL(QNSIM_E_DEVICE, "hipSetDevice failed");
+  if (!D.rf) {
+    RefactorPlan* P = new RefactorPlan();
+    D.rf = P;
+    int rc;
+    try {
+      rc = build_plan(c, *P, err);
+    } catch (...) {
+      rf_free(D);
+      throw;
+    }
+    if (rc) {
+      rf_free(D);
+      return rc;
+    }
+  }
+  RefactorPlan& P = *D.rf;
+  hipStream_t st = (hipStream_t)D.stream;
+  const double inv_h2 = 1.0 / (h * h);
+  (void)hipEventRecord((hipEvent_t)P.ev[0], st);
+  k_rf_zero<<<2048, 256, 0, st>>>(P.ws, P.ws_len);
+  {
+    const long long blocks = std::min<long long>((P.nnz + 255) / 256, 4096);
+    k_rf_scatter<<<(unsigned)std::max<long long>(blocks, 1), 256, 0, st>>>(
+        P.apos, P.aval, P.adiag, P.nnz, D.mass, inv_h2, P.ws, P.flag);
+  }
+  for (int l = 0; l < P.nlev; ++l) {
+    const int l0 = P.lvl_ptr[l], l1 = P.lvl_ptr[l + 1], cnt = l1 - l0;
+    if (cnt == 0) continue;
+    const int* ln = P.lvl_nodes + l0;
+    int maxch = 0;
+    for (int i = l0; i < l1; ++i) maxch = std::max(maxch, P.node_h[P.lvl_nodes_h[i]].nchild);
+    for (int ci = 0; ci < maxch; ++ci) {
+      long long tot = 0;
+      for (int i = l0; i < l1; ++i) {
+        const RfNode& n = P.node_h[P.lvl_nodes_h[i]];
+        if (ci < n.nchild) {
+          const long long nb = P.node_h[P.children_h[n.child0 + ci]].nbelow;
+          tot = std::max(tot, nb * nb);
+        }
+      }
+      if (tot == 0) continue;
+      const int chunks = (int)std::min<long long>((tot + 255) / 256, 1024);
+      k_rf_extend<<<dim3(cnt, chunks), 256, 0, st>>>(ln, P.node, P.children, P.rel, P.ws, ci);
+    }
+    const int maxnc = P.node_h[P.lvl_nodes_h[l0]].ncol;
+    int act = cnt;
+    for (int j0 = 0; j0 < maxnc; j0 += NB) {
+      while (act > 0 && P.node_h[P.lvl_nodes_h[l0 + act - 1]].ncol <= j0) --act;
+      k_rf_panel<<<act, 256, 0, st>>>(ln, P.node, P.ws, P.X, j0, P.flag);
+      long long tiles = 0;
+      for (int i = l0; i < l0 + act; ++i) {
+        const RfNode& n = P.node_h[P.lvl_nodes_h[i]];
+        const long long N = (long long)n.ncol + n.nbelow - j0 - std::min(NB, n.ncol - j0);
+        const long long Tn = (N + TL - 1) / TL;
+        tiles = std::max(tiles, Tn * (Tn + 1) / 2);
+      }
+      if (tiles > 0) k_rf_update<<<dim3(act, (unsigned)tiles), 256, 0, st>>>(ln, P.node, P.ws, j0);
+    }
+  }
+  (void)hipMemcpyAsync(P.flag_host, P.flag, sizeof(int), hipMemcpyDeviceToHost, st);
+  if (hipStreamSynchronize(st) != hipSuccess) RF_FAIL(QNSIM_E_DEVICE, "refactor: device error");
+  if (*P.flag_host) RF_FAIL(QNSIM_E_NOT_SPD, "refactor: matrix is not positive definite");
+  if (P.n_inv) k_rf_inv<<<P.n_inv, 256, 0, st>>>(P.inv_items, P.node, P.ws, P.X);
+  if (P.n_out) k_rf_out<<<P.n_out, 256, 0, st>>>(P.out_items, P.node, P.ws, P.X, D.Bf, D.Bb);
+  (void)hipEventRecord((hipEvent_t)P.ev[1], st);
+  if (hipStreamSynchronize(st) != hipSuccess || hipGetLastError() != hipSuccess)
+    RF_FAIL(QNSIM_E_DEVICE, "refactor: device error");
+  if (device_ms) {
+    float ms = 0.0f;
+    (void)hipEventElapsedTime(&ms, (hipEvent_t)P.ev[0], (hipEvent_t)P.ev[1]);
+    *device_ms = ms;
+  }
+  D.h = h;
+  dev_drop_graph(D);  // a captured step holds 1/h^2 among its arguments
+  return QNSIM_OK;
+}
+
+}  // namespace qn

@@ -1144,8 +1144,11 @@ int dev_sync(DeviceMesh& D, void* stream, std::string& err) {
   return 0;
 }
 
+void dev_drop_graph(DeviceMesh& D) { drop_graph(D); }
+
 void dev_free(DeviceMesh& D) {
   drop_graph(D);
+  rf_free(D);
   for (int k = 0; k < kElemKinds; ++k)
     if (D.eblk_kind[k]) (void)hipFree(D.eblk_kind[k]);
   void* ptrs[] = {D.tv, D.Bm, D.vol, D.tmat, D.mats, D.mass, D.inc_tab, D.vperm,

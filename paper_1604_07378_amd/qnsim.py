@@ -124,6 +124,7 @@ SIGNATURES = {
     "qnsim_eval_device": (ctypes.c_int, [_P, _P, _P, ctypes.POINTER(_D), _P, _P]),
     "qnsim_element_stress_device": (ctypes.c_int, [_P, _P, _P, _P, _P]),
     "qnsim_solve_device": (ctypes.c_int, [_P, _P, _P, _P]),
+    "qnsim_refactor": (ctypes.c_int, [_P, _D, ctypes.POINTER(_D)]),
     "qnsim_time_kernel": (ctypes.c_int, [_P, _I, _I, ctypes.POINTER(_D)]),
     "qnsim_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "qnsim_last_error": (ctypes.c_char_p, [_P]),
@@ -374,6 +375,12 @@ class Sim:
     def solve_device(self, q, r_out, stream=None):
         self._check(self._lib.qnsim_solve_device(self._h, _tptr(q), _tptr(r_out),
                                                  _stream_ptr(stream)))
+
+    def refactor(self, h: float) -> float:
+        """Refactor A for step size h on the device; returns the device time in ms."""
+        ms = _D(0.0)
+        self._check(self._lib.qnsim_refactor(self._h, float(h), ctypes.byref(ms)))
+        return ms.value
 
 
 def sim_from_workload(w, options: Optional[Options] = None, prepare: bool = True, **overrides):

@@ -122,6 +122,9 @@ def test_errors_are_reported_not_raised_across_the_abi():
     s.set_pinned([0])
     s.analyze(1 / 30)
     assert s.factor_info()["n_free"] == 3
+    with pytest.raises(qnsim.QnsimError) as e:
+        s.refactor(1 / 60)                        # analysed, not prepared on a device
+    assert e.value.code == -8                     # QNSIM_E_STATE
 
 
 @pytest.mark.parametrize("sched", [dict(dense_top=0, subtree_cap=0, level_merge=0),
