@@ -9,16 +9,18 @@
 //  2. level by level of the supernode tree (multifrontal): the children's
 //     Schur complements are added into the parent's front (one launch per
 //     child rank, so every sum is taken in a fixed order), then the leading
-//     ncol columns are factored right-looking in panels of NB columns
-//     (a panel kernel: Cholesky of the diagonal block, its inverse, and the
-//     rows below; an update kernel: the trailing lower triangle in 64 x 64
-//     tiles); what is left in the last nbelow x nbelow block is the update
-//     for the parent;
-//  3. the solve blocks: L11^{-1} by block columns (each block column of the
-//     inverse is independent; within one, block rows follow in order), then
-//     [L11^{-1}; L21 L11^{-1}] is written into the row-major and the
-//     column-major packed copies, or, for the dense top block, the full
-//     (L11 L11^T)^{-1} = L11^{-T} L11^{-1}.
+//     ncol columns are factored right-looking in panels of NB columns, three
+//     launches per panel: the diagonal block (Cholesky and inverse), the
+//     rows below it, and the trailing lower triangle in 64 x 64 tiles. What
+//     is left in the last nbelow x nbelow block is the update for the parent.
+//     The same rounds build Z = [L11^{-1}; -L21 L11^{-1}], the first ncol
+//     columns of the inverse of [L11 0; L21 I]: that matrix is the product
+//     of one block-column factor per panel, so Z is the identity's columns
+//     with the inverses of those factors applied in panel order (row block J
+//     times L_JJ^{-1}, then the rows below minus L_IJ times row block J);
+//  3. the solve blocks: [Z11; -Z21] = [L11^{-1}; L21 L11^{-1}] into the
+//     row-major and the column-major packed copies, or, for the dense top
+//     block, the full (L11 L11^T)^{-1} = Z11^T Z11.
 //
 // The solve blocks are overwritten only once every pivot has been found
 // positive, so a failed refactorisation leaves the previous factor in force.
@@ -43,7 +45,7 @@ constexpr int TL = 64;  // rows and columns of a trailing-update tile
 struct RfNode {
   int ncol, nbelow, nchild, child0;  // child0: first entry in the children list
   long long front;  // m x m column-major front in the workspace
-  long long xoff;   // ncol x ncol column-major L11^{-1}
+  long long zoff;   // m x ncol column-major [L11^{-1}; -L21 L11^{-1}] (leading dim m)
   long long fw, bw; // the supernode's blocks in the forward / backward packed copies
   long long rel;    // positions of its below rows in the parent's front
   int top, pad;     // top: stored as the full (L11 L11^T)^{-1} (forward copy only)
@@ -71,10 +73,8 @@ struct RefactorPlan {
   long long nnz = 0;
   double* ws = nullptr;
   long long ws_len = 0;
-  double* X = nullptr;
-  long long x_len = 0;
-  RfItem* inv_items = nullptr;
-  int n_inv = 0;
+  double* Z = nullptr;
+  long long z_len = 0;
   RfItem* out_items = nullptr;
   int n_out = 0;
   int* flag = nullptr;
@@ -129,198 +129,233 @@ __global__ __launch_bounds__(256) void k_rf_extend(const int* __restrict__ lvl_n
   }
 }
 
-// Panel j0 of each active node (one workgroup per node): Cholesky of the
-// diagonal block in LDS, its inverse (kept as the diagonal block of
-// L11^{-1}), and the rows below, L_r = F_r L_jj^{-T}.
-__global__ __launch_bounds__(256) void k_rf_panel(const int* __restrict__ lvl_nodes,
-                                                  const RfNode* __restrict__ node,
-                                                  double* __restrict__ ws, double* __restrict__ X,
-                                                  int j0, int* __restrict__ flag) {
-  __shared__ double Dk[NB][NB + 1];
-  __shared__ double Iv[NB][NB + 1];
+// Node loop of the per-level kernels: blockIdx.y strides over the active
+// nodes of the level (more nodes than a grid dimension holds are fine).
+#define RF_NODES(ni, act) for (int ni = blockIdx.y; ni < (act); ni += gridDim.y)
+
+// Round j0, step 1 (one wave per node): Cholesky of the diagonal block and
+// its inverse, L_jj^{-1}, which is also the diagonal block of
+// Z = [L11^{-1}; -L21 L11^{-1}] (Z starts at zero; the identity's diagonal
+// blocks enter here). Lane i holds row i of the block in registers, padded
+// with the identity past the last column of the supernode; every loop is
+// unrolled so that the rows stay in registers.
+__global__ __launch_bounds__(64) void k_rf_diag(const int* __restrict__ lvl_nodes,
+                                                const RfNode* __restrict__ node,
+                                                double* __restrict__ ws, double* __restrict__ Z,
+                                                int j0, int* __restrict__ flag) {
+  __shared__ double col[NB];
+  __shared__ double Lm[NB][NB + 1];
+  __shared__ double dinv[NB];
   const RfNode nd = node[lvl_nodes[blockIdx.x]];
   const int nc = nd.ncol, m = nc + nd.nbelow;
   const int jb = min(NB, nc - j0);
   double* F = ws + nd.front;
-  const int tid = threadIdx.x;
-  for (int e = tid; e < NB * NB; e += 256) {
-    const int i = e % NB, k = e / NB;
-    Dk[i][k] = (i < jb && k < jb && i >= k) ? F[(j0 + i) + (long long)(j0 + k) * m] : 0.0;
-    Iv[i][k] = 0.0;
+  const int i = threadIdx.x;
+  const bool lane = i < NB;
+  double a[NB];
+#pragma unroll
+  for (int c = 0; c < NB; ++c) {
+    a[c] = i == c ? 1.0 : 0.0;
+    if (lane && i < jb && c < jb && c <= i) a[c] = F[(j0 + i) + (long long)(j0 + c) * m];
   }
-  __syncthreads();
-  for (int k = 0; k < jb; ++k) {
-    double d = Dk[k][k];
+  // left-looking: step k forms column k from the finished columns left of
+  // it, L(i,k) = (A(i,k) - sum_{j<k} L(i,j) L(k,j)) / L(k,k); row k of L is
+  // read from LDS
+#pragma unroll
+  for (int k = 0; k < NB; ++k) {
+    double s = a[k];
+#pragma unroll
+    for (int j = 0; j < k; ++j) s -= a[j] * Lm[k][j];
+    if (i == k) col[0] = s;
+    __syncthreads();
+    double d = col[0];
     if (!(d > 0.0) || !isfinite(d)) {
-      if (tid == 0) *flag = 1;
+      if (i == 0) *flag = 1;
       d = 1.0;  // keep the arithmetic finite; the result is discarded
     }
     const double l = sqrt(d);
-    __syncthreads();  // every thread has read the pivot
-    if (tid == 0) Dk[k][k] = l;
-    if (tid > k && tid < jb) Dk[tid][k] /= l;
-    __syncthreads();
-    for (int e = tid; e < NB * NB; e += 256) {
-      const int i = e % NB, c = e / NB;
-      if (c > k && i >= c && i < jb) Dk[i][c] -= Dk[i][k] * Dk[c][k];
-    }
+    const double lik = i == k ? l : s / l;
+    if (i >= k) a[k] = lik;
+    if (lane) Lm[i][k] = i >= k ? lik : 0.0;
     __syncthreads();
   }
-  // column c of L_jj^{-1} by forward substitution (zero above the diagonal)
-  if (tid < jb) {
-    const int c = tid;
-    Iv[c][c] = 1.0 / Dk[c][c];
-    for (int i = c + 1; i < jb; ++i) {
-      double s = 0.0;
-      for (int k = c; k < i; ++k) s += Dk[i][k] * Iv[k][c];
-      Iv[i][c] = -s / Dk[i][i];
-    }
+  if (lane && i < jb) {
+#pragma unroll
+    for (int c = 0; c < NB; ++c)
+      if (c < jb && c <= i) F[(j0 + i) + (long long)(j0 + c) * m] = a[c];
+  }
+  if (lane) dinv[i] = 1.0 / Lm[i][i];
+  __syncthreads();
+  // lane i: column i of L_jj^{-1} by forward substitution
+  double x[NB];
+#pragma unroll
+  for (int r = 0; r < NB; ++r) {
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < r; ++k) s += Lm[r][k] * x[k];
+    x[r] = r == i ? dinv[r] : (r > i ? -dinv[r] * s : 0.0);
+  }
+  __syncthreads();  // Lm has been read
+  if (lane) {
+#pragma unroll
+    for (int r = 0; r < NB; ++r) Lm[r][i] = x[r];
   }
   __syncthreads();
-  double* Xn = X + nd.xoff;
-  for (int e = tid; e < NB * NB; e += 256) {
-    const int i = e % NB, k = e / NB;
-    if (i < jb && k < jb) {
-      if (i >= k) F[(j0 + i) + (long long)(j0 + k) * m] = Dk[i][k];
-      Xn[(j0 + i) + (long long)(j0 + k) * nc] = Iv[i][k];
-    }
+  double* Zn = Z + nd.zoff;
+  if (lane && i < jb) {
+#pragma unroll
+    for (int c = 0; c < NB; ++c)
+      if (c < jb) Zn[(j0 + i) + (long long)(j0 + c) * m] = Lm[i][c];
   }
-  // rows below the diagonal block: L[r][k] = sum_p F[r][p] Iv[k][p]
-  for (int r = j0 + jb + tid; r < m; r += 256) {
-    double f[NB];
+}
+
+// Round j0, step 2. Tiles y < nT: the panel rows below the diagonal block,
+// L_r = F_r L_jj^{-T} (64 rows per tile). Tiles y >= nT: row block J of Z left
+// of the diagonal block, Z_J <- L_jj^{-1} Z_J (64 columns per tile).
+__global__ __launch_bounds__(256) void k_rf_rows(const int* __restrict__ lvl_nodes,
+                                                 const RfNode* __restrict__ node, int act,
+                                                 double* __restrict__ ws, double* __restrict__ Z,
+                                                 int j0) {
+  __shared__ double Iv[NB][NB + 1];
+  __shared__ double St[TL][NB + 1];
+  const int tid = threadIdx.x;
+  RF_NODES(ni, act) {
+    const RfNode nd = node[lvl_nodes[ni]];
+    const int nc = nd.ncol, m = nc + nd.nbelow;
+    const int jb = min(NB, nc - j0), s0 = j0 + jb;
+    const int nT = (m - s0 + TL - 1) / TL, nZ = (j0 + TL - 1) / TL;
+    const int t = blockIdx.x;
+    if (t >= nT + nZ) continue;
+    double* F = ws + nd.front;
+    double* Zn = Z + nd.zoff;
+    __syncthreads();  // LDS of the previous node is free
+    for (int e = tid; e < NB * NB; e += 256) {
+      const int i = e % NB, k = e / NB;
+      Iv[i][k] = (i < jb && k < jb) ? Zn[(j0 + i) + (long long)(j0 + k) * m] : 0.0;
+    }
+    if (t < nT) {
+      const int r0 = s0 + t * TL;
+      for (int e = tid; e < TL * NB; e += 256) {
+        const int r = e % TL, p = e / TL;
+        St[r][p] = (p < jb && r0 + r < m) ? F[(r0 + r) + (long long)(j0 + p) * m] : 0.0;
+      }
+      __syncthreads();
+      const int r = tid % TL, kg = tid / TL;
 #pragma unroll
-    for (int p = 0; p < NB; ++p) f[p] = p < jb ? F[r + (long long)(j0 + p) * m] : 0.0;
-    for (int k = 0; k < jb; ++k) {
-      double s = 0.0;
+      for (int v = 0; v < NB / 4; ++v) {
+        const int k = kg + 4 * v;
+        double s = 0.0;
+#pragma unroll 8
+        for (int p = 0; p < NB; ++p) s += St[r][p] * Iv[k][p];
+        if (k < jb && r0 + r < m) F[(r0 + r) + (long long)(j0 + k) * m] = s;
+      }
+    } else {
+      const int c0 = (t - nT) * TL;
+      for (int e = tid; e < TL * NB; e += 256) {
+        const int p = e % NB, c = e / NB;  // St[c][p] = Z[j0 + p][c0 + c]
+        St[c][p] = (p < jb && c0 + c < j0) ? Zn[(j0 + p) + (long long)(c0 + c) * m] : 0.0;
+      }
+      __syncthreads();
+      const int c = tid % TL, ig = tid / TL;
 #pragma unroll
-      for (int p = 0; p < NB; ++p) s += f[p] * Iv[k][p];
-      F[r + (long long)(j0 + k) * m] = s;
+      for (int v = 0; v < NB / 4; ++v) {
+        const int i = ig + 4 * v;
+        double s = 0.0;
+#pragma unroll 8
+        for (int p = 0; p < NB; ++p) s += Iv[i][p] * St[c][p];
+        if (i < jb && c0 + c < j0) Zn[(j0 + i) + (long long)(c0 + c) * m] = s;
+      }
     }
   }
 }
 
-// Trailing update after panel j0: F[i][k] -= sum_p L[i][p] L[k][p] on the
-// lower triangle of rows and columns [j0 + jb, m). blockIdx.x: node;
-// blockIdx.y: 64 x 64 tile of the lower triangle of tiles.
+// Round j0, step 3. Tiles y < nF: the trailing lower triangle of the front,
+// F[i][k] -= sum_p L[i][p] L[k][p] over rows and columns [s0, m) (64 x 64
+// tiles). Tiles y >= nF: the rows of Z below row block J,
+// Z[i][c] -= sum_p L[i][p] Z_J[p][c] for columns c < s0.
 __global__ __launch_bounds__(256) void k_rf_update(const int* __restrict__ lvl_nodes,
-                                                   const RfNode* __restrict__ node,
-                                                   double* __restrict__ ws, int j0) {
+                                                   const RfNode* __restrict__ node, int act,
+                                                   double* __restrict__ ws, double* __restrict__ Z,
+                                                   int j0) {
   __shared__ double Ai[TL][NB + 1];
-  __shared__ double Ak[TL][NB + 1];
-  const RfNode nd = node[lvl_nodes[blockIdx.x]];
-  const int nc = nd.ncol, m = nc + nd.nbelow;
-  const int jb = min(NB, nc - j0);
-  const int s0 = j0 + jb, N = m - s0;
-  if (N <= 0) return;
-  const int Tn = (N + TL - 1) / TL;
-  const int t = blockIdx.y;
-  if (t >= Tn * (Tn + 1) / 2) return;
-  int ti = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
-  while (ti * (ti + 1) / 2 > t) --ti;
-  while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
-  const int tk = t - ti * (ti + 1) / 2;
-  const int r0 = s0 + ti * TL, c0 = s0 + tk * TL;
-  double* F = ws + nd.front;
-  const int tid = threadIdx.x;
-  for (int e = tid; e < TL * NB; e += 256) {
-    const int r = e % TL, p = e / TL;
-    const bool okp = p < jb;
-    Ai[r][p] = (okp && r0 + r < m) ? F[(r0 + r) + (long long)(j0 + p) * m] : 0.0;
-    Ak[r][p] = (okp && c0 + r < m) ? F[(c0 + r) + (long long)(j0 + p) * m] : 0.0;
-  }
-  __syncthreads();
-  const int tx = tid % 16, ty = tid / 16;
-  double acc[4][4];
-#pragma unroll
-  for (int u = 0; u < 4; ++u)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
-#pragma unroll 4
-  for (int p = 0; p < NB; ++p) {
-    double a[4], b[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) a[u] = Ai[tx + 16 * u][p];
-#pragma unroll
-    for (int v = 0; v < 4; ++v) b[v] = Ak[ty + 16 * v][p];
+  __shared__ double Bk[TL][NB + 1];
+  const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
+  RF_NODES(ni, act) {
+    const RfNode nd = node[lvl_nodes[ni]];
+    const int nc = nd.ncol, m = nc + nd.nbelow;
+    const int jb = min(NB, nc - j0);
+    const int s0 = j0 + jb, N = m - s0;
+    const int Tn = (N + TL - 1) / TL;
+    const int nF = Tn * (Tn + 1) / 2, nZc = (s0 + TL - 1) / TL;
+    const int t = blockIdx.x;
+    if (N <= 0 || t >= nF + Tn * nZc) continue;
+    double* F = ws + nd.front;
+    double* Zn = Z + nd.zoff;
+    const bool ztile = t >= nF;
+    int r0, c0;
+    if (!ztile) {
+      int ti = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+      while (ti * (ti + 1) / 2 > t) --ti;
+      while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+      const int tk = t - ti * (ti + 1) / 2;
+      r0 = s0 + ti * TL;
+      c0 = s0 + tk * TL;
+    } else {
+      const int tz = t - nF;
+      r0 = s0 + (tz / nZc) * TL;
+      c0 = (tz % nZc) * TL;
+    }
+    __syncthreads();  // LDS of the previous node is free
+    for (int e = tid; e < TL * NB; e += 256) {
+      const int r = e % TL, p = e / TL;
+      Ai[r][p] = (p < jb && r0 + r < m) ? F[(r0 + r) + (long long)(j0 + p) * m] : 0.0;
+      if (!ztile) Bk[r][p] = (p < jb && c0 + r < m) ? F[(c0 + r) + (long long)(j0 + p) * m] : 0.0;
+    }
+    if (ztile)
+      for (int e = tid; e < TL * NB; e += 256) {
+        const int p = e % NB, c = e / NB;  // Bk[c][p] = Z_J[p][c0 + c]
+        Bk[c][p] = (p < jb && c0 + c < s0) ? Zn[(j0 + p) + (long long)(c0 + c) * m] : 0.0;
+      }
+    __syncthreads();
+    double acc[4][4];
 #pragma unroll
     for (int u = 0; u < 4; ++u)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * b[v];
-  }
+      for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+#pragma unroll 4
+    for (int p = 0; p < NB; ++p) {
+      double a[4], b[4];
 #pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const int col = c0 + ty + 16 * v;
+      for (int u = 0; u < 4; ++u) a[u] = Ai[tx + 16 * u][p];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int row = r0 + tx + 16 * u;
-      if (row < m && col < m && row >= col) F[row + (long long)col * m] -= acc[u][v];
+      for (int v = 0; v < 4; ++v) b[v] = Bk[ty + 16 * v][p];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * b[v];
     }
-  }
-}
-
-// Block column J of L11^{-1} (one workgroup per item): for block rows
-// I = J+1, J+2, ...: X[I][J] = -X[I][I] sum_{K=J}^{I-1} L[I][K] X[K][J], the
-// diagonal blocks X[I][I] coming from the panel kernel.
-__global__ __launch_bounds__(256) void k_rf_inv(const RfItem* __restrict__ items,
-                                                const RfNode* __restrict__ node,
-                                                const double* __restrict__ ws,
-                                                double* __restrict__ X) {
-  __shared__ double Lb[NB][NB + 1];
-  __shared__ double Xb[NB][NB + 1];
-  __shared__ double Ac[NB][NB + 1];
-  const RfItem it = items[blockIdx.x];
-  const RfNode nd = node[it.node];
-  const int nc = nd.ncol, m = nc + nd.nbelow, J = it.a;
-  const int nbk = (nc + NB - 1) / NB;
-  const double* F = ws + nd.front;
-  double* Xn = X + nd.xoff;
-  const int tid = threadIdx.x, tx = tid % NB, ty = tid / NB;  // rows tx, columns ty + 8 v
-  const int cJ = J * NB;
-  for (int I = J + 1; I < nbk; ++I) {
-    const int rI = I * NB;
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int K = J; K < I; ++K) {
-      const int rK = K * NB;
-      for (int e = tid; e < NB * NB; e += 256) {
-        const int i = e % NB, k = e / NB;
-        Lb[i][k] = (rI + i < nc) ? F[(rI + i) + (long long)(rK + k) * m] : 0.0;
-        Xb[i][k] = (cJ + k < nc) ? Xn[(rK + i) + (long long)(cJ + k) * nc] : 0.0;
-      }
-      __syncthreads();
-#pragma unroll 8
-      for (int p = 0; p < NB; ++p) {
-        const double l = Lb[tx][p];
-#pragma unroll
-        for (int v = 0; v < 4; ++v) acc[v] += l * Xb[p][ty + 8 * v];
-      }
-      __syncthreads();
-    }
-#pragma unroll
-    for (int v = 0; v < 4; ++v) Ac[tx][ty + 8 * v] = acc[v];
-    for (int e = tid; e < NB * NB; e += 256) {
-      const int i = e % NB, k = e / NB;
-      Lb[i][k] = (rI + i < nc && rI + k < nc) ? Xn[(rI + i) + (long long)(rI + k) * nc] : 0.0;
-    }
-    __syncthreads();
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int c = ty + 8 * v;
-      double s = 0.0;
-#pragma unroll 8
-      for (int p = 0; p < NB; ++p) s += Lb[tx][p] * Ac[p][c];
-      if (rI + tx < nc && cJ + c < nc) Xn[(rI + tx) + (long long)(cJ + c) * nc] = -s;
+      const int col = c0 + ty + 16 * v;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int row = r0 + tx + 16 * u;
+        if (!ztile) {
+          if (row < m && col < m && row >= col) F[row + (long long)col * m] -= acc[u][v];
+        } else if (row < m && col < s0) {
+          Zn[row + (long long)col * m] -= acc[u][v];
+        }
+      }
     }
-    __syncthreads();  // the new block is read by the next block row
   }
 }
 
-// Solve blocks, one 64-row x 32-column tile per item. Ordinary supernode: the
-// m x ncol block [L11^{-1}; L21 L11^{-1}] into both packed copies. Dense top:
-// the full (L11 L11^T)^{-1}[i][j] = sum_k X[k][i] X[k][j] into the forward copy.
+// Solve blocks, one 64-row x 32-column tile per item. Ordinary supernode:
+// [L11^{-1}; L21 L11^{-1}] = [Z11; -Z21] into both packed copies. Dense top:
+// the full (L11 L11^T)^{-1}[i][j] = sum_k Z[k][i] Z[k][j] into the forward copy.
 __global__ __launch_bounds__(256) void k_rf_out(const RfItem* __restrict__ items,
                                                 const RfNode* __restrict__ node,
-                                                const double* __restrict__ ws,
-                                                const double* __restrict__ X,
+                                                const double* __restrict__ Z,
                                                 double* __restrict__ Bf, double* __restrict__ Bb) {
   __shared__ double Lt[TL][NB + 1];
   __shared__ double Xb[NB][NB + 1];
@@ -328,59 +363,53 @@ __global__ __launch_bounds__(256) void k_rf_out(const RfItem* __restrict__ items
   const RfNode nd = node[it.node];
   const int nc = nd.ncol, m = nc + nd.nbelow;
   const int r0 = it.a * TL, cJ = it.b * NB;
-  const double* F = ws + nd.front;
-  const double* Xn = X + nd.xoff;
+  const double* Zn = Z + nd.zoff;
   const int tid = threadIdx.x, tx = tid % TL, ty = tid / TL;  // rows tx, columns ty + 4 v
+  if (!nd.top) {
+    const int row = r0 + tx;
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+      const int c = cJ + ty + 4 * v;
+      if (c >= nc || row >= m || row < c) continue;
+      const double z = Zn[row + (long long)c * m];
+      const double val = row < nc ? z : -z;
+      Bb[nd.bw + (long long)c * m - (long long)c * (c - 1) / 2 + (row - c)] = val;
+      const long long fo = row < nc ? (long long)row * (row + 1) / 2 + c
+                                    : (long long)nc * (nc + 1) / 2 + (long long)(row - nc) * nc + c;
+      Bf[nd.fw + fo] = val;
+    }
+    return;
+  }
   double acc[8];
 #pragma unroll
   for (int v = 0; v < 8; ++v) acc[v] = 0.0;
-  const bool prod = nd.top ? true : (r0 + TL > nc);  // any row of the tile needs a product
-  if (prod) {
-    const int K0 = nd.top ? max(r0, cJ) / NB : it.b;
-    for (int K = K0; K * NB < nc; ++K) {
-      const int rK = K * NB;
-      for (int e = tid; e < TL * NB; e += 256) {
-        if (nd.top) {
-          const int k = e % NB, r = e / NB;  // X[rK + k][r0 + r], read along k
-          Lt[r][k] = (r0 + r < nc && rK + k < nc && rK + k >= r0 + r)
-                         ? Xn[(rK + k) + (long long)(r0 + r) * nc] : 0.0;
-        } else {
-          const int r = e % TL, k = e / TL;  // L21 rows r0 + r >= nc, columns rK + k
-          const int row = r0 + r;
-          Lt[r][k] = (row >= nc && row < m && rK + k < nc) ? F[row + (long long)(rK + k) * m] : 0.0;
-        }
-      }
-      // L11^{-1} is lower triangular: entries above the diagonal read as zero
-      for (int e = tid; e < NB * NB; e += 256) {
-        const int i = e % NB, k = e / NB;
-        Xb[i][k] = (rK + i < nc && cJ + k < nc && rK + i >= cJ + k)
-                       ? Xn[(rK + i) + (long long)(cJ + k) * nc] : 0.0;
-      }
-      __syncthreads();
-#pragma unroll 8
-      for (int p = 0; p < NB; ++p) {
-        const double l = Lt[tx][p];
-#pragma unroll
-        for (int v = 0; v < 8; ++v) acc[v] += l * Xb[p][ty + 4 * v];
-      }
-      __syncthreads();
+  // Z11 = L11^{-1} is lower triangular: entries above the diagonal read as zero
+  for (int K = max(r0, cJ) / NB; K * NB < nc; ++K) {
+    const int rK = K * NB;
+    for (int e = tid; e < TL * NB; e += 256) {
+      const int k = e % NB, r = e / NB;  // Z[rK + k][r0 + r], read along k
+      Lt[r][k] = (r0 + r < nc && rK + k < nc && rK + k >= r0 + r)
+                     ? Zn[(rK + k) + (long long)(r0 + r) * m] : 0.0;
     }
+    for (int e = tid; e < NB * NB; e += 256) {
+      const int i = e % NB, k = e / NB;
+      Xb[i][k] = (rK + i < nc && cJ + k < nc && rK + i >= cJ + k)
+                     ? Zn[(rK + i) + (long long)(cJ + k) * m] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int p = 0; p < NB; ++p) {
+      const double l = Lt[tx][p];
+#pragma unroll
+      for (int v = 0; v < 8; ++v) acc[v] += l * Xb[p][ty + 4 * v];
+    }
+    __syncthreads();
   }
   const int row = r0 + tx;
 #pragma unroll
   for (int v = 0; v < 8; ++v) {
     const int c = cJ + ty + 4 * v;
-    if (c >= nc) continue;
-    if (nd.top) {
-      if (row < nc) Bf[nd.fw + row + (long long)c * nc] = acc[v];
-      continue;
-    }
-    if (row >= m || row < c) continue;
-    const double val = row < nc ? Xn[row + (long long)c * nc] : acc[v];
-    Bb[nd.bw + (long long)c * m - (long long)c * (c - 1) / 2 + (row - c)] = val;
-    const long long fo = row < nc ? (long long)row * (row + 1) / 2 + c
-                                  : (long long)nc * (nc + 1) / 2 + (long long)(row - nc) * nc + c;
-    Bf[nd.fw + fo] = val;
+    if (c < nc && row < nc) Bf[nd.fw + row + (long long)c * nc] = acc[v];
   }
 }
 
@@ -412,7 +441,7 @@ int build_plan(const qnsim* c, RefactorPlan& P, std::string& err) {
     RF_FAIL(QNSIM_E_DEVICE, "refactor: reading the supernode table failed");
   P.ns = ns;
   P.node_h.resize(ns);
-  long long wsl = 0, xl = 0;
+  long long wsl = 0, zl = 0;
   for (int s = 0; s < ns; ++s) {
     const Supernode& S = F.sn[s];
     if (si[s].first != S.first || si[s].ncol != S.ncol || si[s].nbelow != S.nbelow)
@@ -426,8 +455,8 @@ int build_plan(const qnsim* c, RefactorPlan& P, std::string& err) {
     const long long m = S.m();
     n.front = wsl;
     wsl += m * m;
-    n.xoff = xl;
-    xl += (long long)S.ncol * S.ncol;
+    n.zoff = zl;
+    zl += m * S.ncol;
     n.fw = si[s].fw_off;
     n.bw = si[s].bw_off;
     n.rel = S.rows_off;
@@ -438,7 +467,7 @@ int build_plan(const qnsim* c, RefactorPlan& P, std::string& err) {
     if (m > 20000) RF_FAIL(QNSIM_E_INVALID, "refactor: front too large for the tile grid");
   }
   P.ws_len = wsl;
-  P.x_len = xl;
+  P.z_len = zl;
   // levels (ncol descending within a level)
   P.nlev = F.nlevels;
   P.lvl_ptr.assign(P.nlev + 1, 0);
@@ -534,18 +563,14 @@ int build_plan(const qnsim* c, RefactorPlan& P, std::string& err) {
   }
   std::vector<Ent>().swap(ents);
   P.nnz = (long long)apos.size();
-  // work lists of the solve-block kernels (longest block columns first)
-  std::vector<RfItem> inv, out;
+  // work list of the solve-block kernel: (supernode, 64-row tile, 32-column block)
+  std::vector<RfItem> out;
   for (int s = 0; s < ns; ++s) {
     const int nc = F.sn[s].ncol, m = F.sn[s].m();
     const int nbk = (nc + NB - 1) / NB;
-    for (int J = 0; J + 1 < nbk; ++J) inv.push_back({s, J, nbk - J, 0});
-    const int rows = s == F.top ? nc : m;
-    for (int a = 0; a * TL < rows; ++a)
+    for (int a = 0; a * TL < m; ++a)
       for (int J = 0; J < nbk; ++J) out.push_back({s, a, J, 0});
   }
-  std::stable_sort(inv.begin(), inv.end(), [](const RfItem& x, const RfItem& y) { return x.b > y.b; });
-  P.n_inv = (int)inv.size();
   P.n_out = (int)out.size();
   int rc;
   if ((rc = rf_upload(P, &P.node, P.node_h, err))) return rc;
@@ -555,14 +580,13 @@ int build_plan(const qnsim* c, RefactorPlan& P, std::string& err) {
   if ((rc = rf_upload(P, &P.apos, apos, err))) return rc;
   if ((rc = rf_upload(P, &P.aval, aval, err))) return rc;
   if ((rc = rf_upload(P, &P.adiag, adiag, err))) return rc;
-  if ((rc = rf_upload(P, &P.inv_items, inv, err))) return rc;
   if ((rc = rf_upload(P, &P.out_items, out, err))) return rc;
   if (hipMalloc((void**)&P.ws, std::max<long long>(wsl, 1) * sizeof(double)) != hipSuccess)
     RF_FAIL(QNSIM_E_NOMEM, "hipMalloc failed (refactor fronts)");
   P.bytes += (size_t)std::max<long long>(wsl, 1) * sizeof(double);
-  if (hipMalloc((void**)&P.X, std::max<long long>(xl, 1) * sizeof(double)) != hipSuccess)
+  if (hipMalloc((void**)&P.Z, std::max<long long>(zl, 1) * sizeof(double)) != hipSuccess)
     RF_FAIL(QNSIM_E_NOMEM, "hipMalloc failed (refactor inverse blocks)");
-  P.bytes += (size_t)std::max<long long>(xl, 1) * sizeof(double);
+  P.bytes += (size_t)std::max<long long>(zl, 1) * sizeof(double);
   if (hipMalloc((void**)&P.flag, sizeof(int)) != hipSuccess) RF_FAIL(QNSIM_E_NOMEM, "hipMalloc failed");
   if (hipHostMalloc((void**)&P.flag_host, sizeof(int)) != hipSuccess) RF_FAIL(QNSIM_E_NOMEM, "hipHostMalloc failed");
   for (int k = 0; k < 2; ++k)
@@ -576,7 +600,7 @@ void rf_free(DeviceMesh& D) {
   RefactorPlan* P = D.rf;
   if (!P) return;
   void* ptrs[] = {P->node, P->lvl_nodes, P->children, P->rel, P->apos, P->aval, P->adiag,
-                  P->ws, P->X, P->inv_items, P->out_items, P->flag};
+                  P->ws, P->Z, P->out_items, P->flag};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (P->flag_host) (void)hipHostFree(P->flag_host);
@@ -611,6 +635,7 @@ int dev_refactor(qnsim* c, double h, double* device_ms, std::string& err) {
   const double inv_h2 = 1.0 / (h * h);
   (void)hipEventRecord((hipEvent_t)P.ev[0], st);
   k_rf_zero<<<2048, 256, 0, st>>>(P.ws, P.ws_len);
+  k_rf_zero<<<1024, 256, 0, st>>>(P.Z, P.z_len);
   {
     const long long blocks = std::min<long long>((P.nnz + 255) / 256, 4096);
     k_rf_scatter<<<(unsigned)std::max<long long>(blocks, 1), 256, 0, st>>>(
@@ -639,22 +664,25 @@ int dev_refactor(qnsim* c, double h, double* device_ms, std::string& err) {
     int act = cnt;
     for (int j0 = 0; j0 < maxnc; j0 += NB) {
       while (act > 0 && P.node_h[P.lvl_nodes_h[l0 + act - 1]].ncol <= j0) --act;
-      k_rf_panel<<<act, 256, 0, st>>>(ln, P.node, P.ws, P.X, j0, P.flag);
-      long long tiles = 0;
+      const unsigned gy = (unsigned)std::min(act, 32768);
+      long long rows_t = 0, upd_t = 0;
       for (int i = l0; i < l0 + act; ++i) {
         const RfNode& n = P.node_h[P.lvl_nodes_h[i]];
-        const long long N = (long long)n.ncol + n.nbelow - j0 - std::min(NB, n.ncol - j0);
-        const long long Tn = (N + TL - 1) / TL;
-        tiles = std::max(tiles, Tn * (Tn + 1) / 2);
+        const long long m = (long long)n.ncol + n.nbelow;
+        const long long s0 = j0 + std::min(NB, n.ncol - j0);
+        const long long Tn = (m - s0 + TL - 1) / TL, nZc = (s0 + TL - 1) / TL;
+        rows_t = std::max(rows_t, Tn + (j0 + TL - 1) / TL);
+        upd_t = std::max(upd_t, Tn * (Tn + 1) / 2 + Tn * nZc);
       }
-      if (tiles > 0) k_rf_update<<<dim3(act, (unsigned)tiles), 256, 0, st>>>(ln, P.node, P.ws, j0);
+      k_rf_diag<<<act, 64, 0, st>>>(ln, P.node, P.ws, P.Z, j0, P.flag);
+      if (rows_t > 0) k_rf_rows<<<dim3((unsigned)rows_t, gy), 256, 0, st>>>(ln, P.node, act, P.ws, P.Z, j0);
+      if (upd_t > 0) k_rf_update<<<dim3((unsigned)upd_t, gy), 256, 0, st>>>(ln, P.node, act, P.ws, P.Z, j0);
     }
   }
   (void)hipMemcpyAsync(P.flag_host, P.flag, sizeof(int), hipMemcpyDeviceToHost, st);
   if (hipStreamSynchronize(st) != hipSuccess) RF_FAIL(QNSIM_E_DEVICE, "refactor: device error");
   if (*P.flag_host) RF_FAIL(QNSIM_E_NOT_SPD, "refactor: matrix is not positive definite");
-  if (P.n_inv) k_rf_inv<<<P.n_inv, 256, 0, st>>>(P.inv_items, P.node, P.ws, P.X);
-  if (P.n_out) k_rf_out<<<P.n_out, 256, 0, st>>>(P.out_items, P.node, P.ws, P.X, D.Bf, D.Bb);
+  if (P.n_out) k_rf_out<<<P.n_out, 256, 0, st>>>(P.out_items, P.node, P.Z, D.Bf, D.Bb);
   (void)hipEventRecord((hipEvent_t)P.ev[1], st);
   if (hipStreamSynchronize(st) != hipSuccess || hipGetLastError() != hipSuccess)
     RF_FAIL(QNSIM_E_DEVICE, "refactor: device error");
