@@ -30,6 +30,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector (and FP64 matrix) peak
 METRIC = "timesteps/s and tet-evals/s at fixed L-BFGS residual; served p50/p99 step latency"
 
 
@@ -304,6 +305,35 @@ def convergence_run(args, torch, W, qnsim):
     return out
 
 
+def refactor_run(args, torch, W, qnsim):
+    """Numeric refactorisation of A = M/h^2 + sum V k G^T G for a new time step
+    on the device (the Neo-Hookean block, default solve schedule): device time
+    per refactorisation once the plan exists, against the host's analysis and
+    factorisation of the same matrix at prepare."""
+    import time
+    w = W.workload_block(W.NEOHOOKEAN, n=args.n)
+    s = qnsim.sim_from_workload(w)
+    info = s.factor_info()
+    t0 = time.perf_counter()
+    s.refactor(w.h / 2)
+    first_wall = time.perf_counter() - t0
+    ms = [s.refactor(w.h if k % 2 == 0 else w.h / 2) for k in range(6)]
+    s.refactor(w.h)
+    s.close()
+    avg = sum(ms) / len(ms)
+    flops = info["factor_flops"]
+    out = {"workload": f"block {args.n}^3 Neo-Hookean, h = 1/30 <-> 1/60 s, default schedule "
+                       f"(dense top {info['dense_top_cols']} columns)",
+           "device_ms": avg, "first_call_wall_s": first_wall,
+           "host_prepare_s": info["prepare_seconds"], "factor_flops_host_count": flops,
+           "achieved_tflops": flops / (avg * 1e-3) / 1e12, "bound": "fp64 valu",
+           "peak_tflops": FP64_PEAK_TFLOPS,
+           "frac": flops / (avg * 1e-3) / 1e12 / FP64_PEAK_TFLOPS}
+    log(f"[bench] refactor on the device: {avg:.2f} ms ({out['achieved_tflops']:.2f} TFLOP/s); "
+        f"host prepare {info['prepare_seconds']:.2f} s")
+    return out
+
+
 def cpu_baseline(args, W):
     """The FP64 oracle on a bounded sample: one step of the Neo-Hookean block."""
     import numpy as np  # noqa: F401
@@ -341,6 +371,8 @@ def main():
     ap.add_argument("--cpu-sample-steps", type=int, default=3)
     ap.add_argument("--no-convergence", action="store_true",
                     help="skip the convergence comparison of the direction methods")
+    ap.add_argument("--no-refactor", action="store_true",
+                    help="skip the device refactorisation measurement")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the extra mixed-precision Neo-Hookean run")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
@@ -406,6 +438,7 @@ def main():
     if args.batch_count > 0:
         batched = [batched_run(args, torch, W, qnsim, 0), batched_run(args, torch, W, qnsim, 1)]
     served = served_run(args, torch, W, qnsim) if args.pool_count > 0 else None
+    refac = refactor_run(args, torch, W, qnsim) if not args.no_refactor else None
 
     total_steps = sum(r["steps"] for r in runs)
     total_s = sum(r["seconds"] for r in runs)
@@ -458,6 +491,7 @@ def main():
         **({"convergence": conv} if conv else {}),
         **({"batched": batched} if batched else {}),
         **({"served": served} if served else {}),
+        **({"refactor": refac} if refac else {}),
         "roofline": {
             "bound": "hbm",
             "kernel": dom,
