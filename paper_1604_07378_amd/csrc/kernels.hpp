@@ -96,8 +96,11 @@ struct SimSeg {
 // of the 3-component free-vertex vectors; vertex blocks: vertices [a0, a1)
 // (free or pinned). slot: the block's index in its full table, where its
 // partial sums go (a launch may cover only the blocks of some simulations).
+// One block of a segmented kernel: its simulation, index ranges and partial
+// slot. Element blocks also name their force partials: p0 = the first, np =
+// how many (one per distinct free vertex of the block's tets).
 struct BlockSeg {
-  int sim, a0, a1, b0, b1, slot, pad1, pad2;
+  int sim, a0, a1, b0, b1, slot, p0, np;
 };
 
 // Material kinds of the element-pass launch lists: the five types, and
@@ -197,8 +200,14 @@ struct DeviceMesh {
   DevMat* mats = nullptr;     // nmat
   // vertices (internal order: free in factor order, then pinned)
   double* mass = nullptr;     // n
-  int inc_w = 4;              // incidence-table width: largest valence, rounded up to 4
-  int* inc_tab = nullptr;     // nf x inc_w: (tet * 4 + slot) per incidence, -1 padding
+  // element-pass force partials: an element block sums its tets' gradient
+  // contributions per distinct free vertex, in (tet, slot) order, into one
+  // partial; the gather adds a vertex's partials in block order
+  long long n_part = 0;       // partials of all element blocks
+  int bp_w = 4;               // bp_tab width: most blocks touching one vertex, rounded up to 4
+  int* bp_tab = nullptr;      // nf x bp_w: partials of each free vertex, -1 padding
+  int* lc_ptr = nullptr;      // n_part + 1: each partial's contributions (CSR)
+  unsigned short* lc_idx = nullptr;  // per contribution: 4 (tet - block's first tet) + slot
   int* vperm = nullptr;       // n: internal -> caller vertex
   int* tperm = nullptr;       // T: internal -> caller tet
   // supernodal solve (one launch per tree level and sweep)
@@ -235,7 +244,7 @@ struct DeviceMesh {
   double* z = nullptr;        // nf x 3 forward-solve intermediate
   double* Sv = nullptr;       // slots x nf x 3
   double* Tv = nullptr;       // slots x nf x 3
-  double* fel = nullptr;      // T x 4 x 3 element gradient contributions (FP32 in mixed mode)
+  double* bpart = nullptr;    // n_part x 3 force partials (FP64 in every mode)
   double* part = nullptr;     // reduction partials
   double* psi = nullptr;      // T per-element energies (probe entry point)
   int gather_blocks = 1;      // blocks of the gradient gather (four lanes per vertex)

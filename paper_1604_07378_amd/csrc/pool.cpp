@@ -131,9 +131,9 @@ int64_t estimate_bytes(const qnsim* c, int history) {
     vp += 3 * (int64_t)(S.ncol + S.nbelow) * 4;  // update layers (a few per supernode)
   }
   int64_t b = 0;
-  b += T * (16 + 72 + 8 + 4 + 4 + 96 + 8);          // tv, Bm, vol, tmat, tperm, fel, psi
+  b += T * (16 + 72 + 8 + 4 + 4 + 8 + 8);           // tv, Bm, vol, tmat, tperm, psi, lc_idx
   b += n * (8 + 4 + 4 + 4 * 24 + 2 * 24);           // mass, vperm, vsim, x0 v0 y X, state
-  b += nf * (24 * 5 + 2 * slots * 24 + 4 * 64);     // G d r q z, S/T rings, incidences
+  b += nf * (24 * 5 + 2 * slots * 24 + 4 * 8 + 3 * 28);  // G d r q z, S/T rings, partials
   b += 2 * packed * 8 + vp * 8;                     // forward/backward blocks, layers
   b += (int64_t)F.rows.size() * 8 + (int64_t)F.sn.size() * 64 * 8;  // rows, rel, items
   b += (T / 256 + nf / 64 + 3 * nf / 256 + 16) * (32 + 8 * 60);     // block tables, partials

@@ -126,6 +126,16 @@ __device__ __forceinline__ void totals_of(const double* __restrict__ part, int s
 }
 
 // Ring slot of the a-th newest stored pair.
+// Workgroups are handed to the eight XCDs in turn (workgroup b to XCD b mod
+// 8). This returns the list position for workgroup b such that each XCD, with
+// its own L2, takes one contiguous range of positions: neighbouring element
+// and gather blocks share vertices.
+__device__ __forceinline__ int xcd_block() {
+  const int N = gridDim.x, b = blockIdx.x;
+  const int q = N / 8, r = N % 8, x = b % 8;
+  return x * q + min(x, r) + b / 8;
+}
+
 __device__ __forceinline__ int pair_slot(const Ctl* c, int a, int slots) {
   return (c->newest - a + slots) % slots;
 }
@@ -209,12 +219,13 @@ k_elem(int want, int trial, const BlockSeg* __restrict__ blk, int T, int nf,
        const DevMat* __restrict__ mats, const double* __restrict__ mass,
        const double* __restrict__ X, const double* __restrict__ d,
        const double* __restrict__ y, double inv2h2, const Ctl* __restrict__ ctl,
-       R* __restrict__ fel, double* __restrict__ part, double* __restrict__ psi_out,
+       const int* __restrict__ lc_ptr, const unsigned short* __restrict__ lc_idx,
+       double* __restrict__ bpart, double* __restrict__ part, double* __restrict__ psi_out,
        const int* __restrict__ cset, const double* __restrict__ planes, double coll_k) {
   __shared__ double sh[16];
-  // the block's gradient contributions, written out contiguously at the end
+  // the block's gradient contributions, summed per vertex at the end
   __shared__ __align__(16) R sfel[BS * 12];
-  const BlockSeg sg = blk[blockIdx.x];
+  const BlockSeg sg = blk[xcd_block()];
   double alpha = 0.0;
   if (want >= 0) {
     const Ctl* c = ctl + sg.sim;
@@ -284,19 +295,21 @@ k_elem(int want, int trial, const BlockSeg* __restrict__ blk, int T, int nf,
       for (int c = 0; c < 3; ++c) o[3 * a + c] = g[a][c];
   }
   __syncthreads();
-  {
-    // tets [a0, a1) own fel[12 a0, 12 a1): 16-byte stores, consecutive lanes
-    // on consecutive addresses (12 a0 values start on a 16-byte boundary)
-    const int nval = 12 * max(0, sg.a1 - sg.a0);
-    if constexpr (sizeof(R) == 8) {
-      const double2* src = reinterpret_cast<const double2*>(sfel);
-      double2* dst = reinterpret_cast<double2*>(fel + 12 * (size_t)sg.a0);
-      for (int i = threadIdx.x; i < nval / 2; i += BS) dst[i] = src[i];
-    } else {
-      const float4* src = reinterpret_cast<const float4*>(sfel);
-      float4* dst = reinterpret_cast<float4*>(fel + 12 * (size_t)sg.a0);
-      for (int i = threadIdx.x; i < nval / 4; i += BS) dst[i] = src[i];
+  // one partial per distinct free vertex of the block: its contributions in
+  // (tet, slot) order, summed in FP64 in every mode
+  for (int j = threadIdx.x; j < sg.np; j += BS) {
+    const int g = sg.p0 + j;
+    const int k0 = lc_ptr[g], k1 = lc_ptr[g + 1];
+    double f0 = 0.0, f1 = 0.0, f2 = 0.0;
+    for (int k = k0; k < k1; ++k) {
+      const R* src = sfel + 3 * (int)lc_idx[k];
+      f0 += (double)src[0];
+      f1 += (double)src[1];
+      f2 += (double)src[2];
     }
+    bpart[3 * (size_t)g] = f0;
+    bpart[3 * (size_t)g + 1] = f1;
+    bpart[3 * (size_t)g + 2] = f2;
   }
   const int vi = sg.b0 + threadIdx.x;
   if (vi < sg.b1) {
@@ -367,10 +380,10 @@ k_init_decide(int want, const SimSeg* __restrict__ seg, const double* __restrict
 // ---------------------------------------------------------------------------
 constexpr int kWideBS = 1024;  // threads per block of the r0 dots
 
-template <int SL, typename FT>
+template <int SL>
 __global__ void __launch_bounds__(BS)
-k_gather(int probe, const BlockSeg* __restrict__ blk, int nb, size_t n3, int slots, int inc_w,
-         const int* __restrict__ inc_tab, const FT* __restrict__ fel,
+k_gather(int probe, const BlockSeg* __restrict__ blk, int nb, size_t n3, int slots, int bp_w,
+         const int* __restrict__ bp_tab, const double* __restrict__ bpart,
          const double* __restrict__ mass, const double* __restrict__ y, double inv_h2,
          double* __restrict__ X, const double* __restrict__ d, double* __restrict__ Gr,
          double* __restrict__ Sall, double* __restrict__ Tall, const Ctl* __restrict__ ctl,
@@ -378,7 +391,7 @@ k_gather(int probe, const BlockSeg* __restrict__ blk, int nb, size_t n3, int slo
          double coll_k, int* __restrict__ cset, const double* __restrict__ xstart) {
   constexpr int ND = 4 + 3 * SL + 1;
   __shared__ double sh[(BS / 64) * ND];
-  const BlockSeg sg = blk[blockIdx.x];
+  const BlockSeg sg = blk[xcd_block()];
   const Ctl* cs = ctl + sg.sim;
   if (!probe && cs->phase != PH_GATHER) return;
   const int k = probe ? 0 : cs->k;
@@ -387,7 +400,7 @@ k_gather(int probe, const BlockSeg* __restrict__ blk, int nb, size_t n3, int slo
   double acc[ND];
 #pragma unroll
   for (int j = 0; j < ND; ++j) acc[j] = 0.0;
-  // four lanes per vertex: lane gl sums incidence-table entries gl + 4u,
+  // four lanes per vertex: lane gl sums the vertex's partials gl + 4u,
   // a butterfly gives all four lanes the same total, and lane gl < 3 then
   // handles component gl
   const int i = sg.a0 + (threadIdx.x >> 2), gl = threadIdx.x & 3;
@@ -415,21 +428,21 @@ k_gather(int probe, const BlockSeg* __restrict__ blk, int nb, size_t n3, int slo
   }
   double f[3] = {0.0, 0.0, 0.0};
   if (live) {
-    const int* __restrict__ row = inc_tab + (size_t)i * inc_w;
-    for (int u0 = gl; u0 < inc_w; u0 += 32) {
-      int ix[8];
+    const int* __restrict__ row = bp_tab + (size_t)i * bp_w;
+    for (int u0 = gl; u0 < bp_w; u0 += 8) {
+      int ix[2];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) ix[u] = u0 + 4 * u < inc_w ? row[u0 + 4 * u] : -1;
-      double fv[8][3];
+      for (int u = 0; u < 2; ++u) ix[u] = u0 + 4 * u < bp_w ? row[u0 + 4 * u] : -1;
+      double fv[2][3];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const FT* fp = fel + 3 * (size_t)(ix[u] >= 0 ? ix[u] : 0);
-        fv[u][0] = ix[u] >= 0 ? (double)fp[0] : 0.0;  // summed in FP64 in every mode
-        fv[u][1] = ix[u] >= 0 ? (double)fp[1] : 0.0;
-        fv[u][2] = ix[u] >= 0 ? (double)fp[2] : 0.0;
+      for (int u = 0; u < 2; ++u) {
+        const double* fp = bpart + 3 * (size_t)(ix[u] >= 0 ? ix[u] : 0);
+        fv[u][0] = ix[u] >= 0 ? fp[0] : 0.0;
+        fv[u][1] = ix[u] >= 0 ? fp[1] : 0.0;
+        fv[u][2] = ix[u] >= 0 ? fp[2] : 0.0;
       }
 #pragma unroll
-      for (int u = 0; u < 8; ++u) { f[0] += fv[u][0]; f[1] += fv[u][1]; f[2] += fv[u][2]; }
+      for (int u = 0; u < 2; ++u) { f[0] += fv[u][0]; f[1] += fv[u][1]; f[2] += fv[u][2]; }
     }
   }
 #pragma unroll
@@ -989,13 +1002,13 @@ void launch_elem(DeviceMesh& D, hipStream_t st, int want, int trial, double* par
     if (D.mixed)                                                                             \
       hipLaunchKernelGGL((k_elem<TY, float>), dim3(GRID), dim3(BS), 0, st, want, trial,       \
                          BLK, D.T, D.nf, D.tv, D.Bm, D.vol, D.tmat, D.mats, D.mass, D.X,      \
-                         D.d, D.y, inv2h2, D.ctl, reinterpret_cast<float*>(D.fel), part,      \
+                         D.d, D.y, inv2h2, D.ctl, D.lc_ptr, D.lc_idx, D.bpart, part,          \
                          psi_out, D.nplanes ? D.cset : nullptr, D.planes, D.coll_k);         \
     else                                                                                     \
       hipLaunchKernelGGL((k_elem<TY, double>), dim3(GRID), dim3(BS), 0, st, want, trial,      \
                          BLK, D.T, D.nf, D.tv, D.Bm, D.vol, D.tmat, D.mats, D.mass, D.X,      \
-                         D.d, D.y, inv2h2, D.ctl, D.fel, part, psi_out,                       \
-                         D.nplanes ? D.cset : nullptr, D.planes, D.coll_k);                   \
+                         D.d, D.y, inv2h2, D.ctl, D.lc_ptr, D.lc_idx, D.bpart, part,          \
+                         psi_out, D.nplanes ? D.cset : nullptr, D.planes, D.coll_k);         \
   } while (0)
   auto one = [&](int type, const BlockSeg* blk, int grid) {
     switch (type) {
@@ -1050,19 +1063,10 @@ void launch_gather(DeviceMesh& D, hipStream_t st, int probe, int m, double* part
   if (L.gat_n == 0) return;
   const int nb = D.gather_blocks;
 #define QN_GATHER(SL)                                                                          \
-  do {                                                                                        \
-    if (D.mixed)                                                                              \
-      hipLaunchKernelGGL((k_gather<SL, float>), dim3(L.gat_n), dim3(BS), 0, st, probe, L.gat,  \
-                         nb, n3, m + 1, D.inc_w, D.inc_tab,                                    \
-                         reinterpret_cast<const float*>(D.fel), D.mass, D.y,                   \
-                         1.0 / (D.h * D.h), D.X, D.d, D.G, D.Sv, D.Tv, D.ctl, part,            \
-                         D.nplanes, D.planes, D.coll_k, D.cset, D.x0);                         \
-    else                                                                                      \
-      hipLaunchKernelGGL((k_gather<SL, double>), dim3(L.gat_n), dim3(BS), 0, st, probe, L.gat, \
-                         nb, n3, m + 1, D.inc_w, D.inc_tab, D.fel, D.mass, D.y,                \
-                         1.0 / (D.h * D.h), D.X, D.d, D.G, D.Sv, D.Tv, D.ctl, part,            \
-                         D.nplanes, D.planes, D.coll_k, D.cset, D.x0);                         \
-  } while (0)
+  hipLaunchKernelGGL((k_gather<SL>), dim3(L.gat_n), dim3(BS), 0, st, probe, L.gat, nb, n3,    \
+                     m + 1, D.bp_w, D.bp_tab, D.bpart, D.mass, D.y, 1.0 / (D.h * D.h), D.X,    \
+                     D.d, D.G, D.Sv, D.Tv, D.ctl, part, D.nplanes, D.planes, D.coll_k, D.cset, \
+                     D.x0)
   QN_SLOTS_DISPATCH(slots_variant(m), QN_GATHER)
 #undef QN_GATHER
 }
@@ -1151,9 +1155,9 @@ void dev_free(DeviceMesh& D) {
   rf_free(D);
   for (int k = 0; k < kElemKinds; ++k)
     if (D.eblk_kind[k]) (void)hipFree(D.eblk_kind[k]);
-  void* ptrs[] = {D.tv, D.Bm, D.vol, D.tmat, D.mats, D.mass, D.inc_tab, D.vperm,
+  void* ptrs[] = {D.tv, D.Bm, D.vol, D.tmat, D.mats, D.mass, D.bp_tab, D.lc_ptr, D.lc_idx, D.vperm,
                   D.sn, D.items, D.Bf, D.Bb, D.rows, D.rel, D.vp, D.x0,
-                  D.v0, D.y, D.X, D.G, D.d, D.r, D.q, D.z, D.Sv, D.Tv, D.fel,
+                  D.v0, D.y, D.X, D.G, D.d, D.r, D.q, D.z, D.Sv, D.Tv, D.bpart,
                   D.part, D.psi, D.ctl, D.stat, D.tperm, D.top_t,
                   D.sub_fw, D.sub_bw, D.sub_fw_ptr, D.sub_bw_ptr,
                   D.seg, D.vsim, D.run, D.eblk, D.gblk, D.vblk, D.rblk, D.xblk, D.dir_count,
@@ -1191,7 +1195,7 @@ int dev_alloc(DeviceMesh& D, std::string& err) {
   HIP_OK(A((void**)&D.top_t, 3 * (size_t)std::max(D.top_n, 1) * 8));
   HIP_OK(A((void**)&D.Sv, f3 * 8 * D.slots));
   HIP_OK(A((void**)&D.Tv, f3 * 8 * D.slots));
-  HIP_OK(A((void**)&D.fel, (size_t)D.T * 12 * 8));
+  HIP_OK(A((void**)&D.bpart, 3 * (size_t)std::max<long long>(D.n_part, 1) * 8));
   HIP_OK(A((void**)&D.psi, (size_t)D.T * 8));
   HIP_OK(A((void**)&D.part,
            ((size_t)kGatherDots * D.gather_blocks + (size_t)(kSlots + 1) * D.rdots_blocks +
