@@ -163,9 +163,15 @@ __global__ __launch_bounds__(64) void k_rf_diag(const int* __restrict__ lvl_node
   // read from LDS
 #pragma unroll
   for (int k = 0; k < NB; ++k) {
-    double s = a[k];
+    // two partial sums halve the dependent chain
+    double s0 = a[k], s1 = 0.0;
 #pragma unroll
-    for (int j = 0; j < k; ++j) s -= a[j] * Lm[k][j];
+    for (int j = 0; j + 1 < k; j += 2) {
+      s0 -= a[j] * Lm[k][j];
+      s1 -= a[j + 1] * Lm[k][j + 1];
+    }
+    if (k & 1) s0 -= a[k - 1] * Lm[k][k - 1];
+    const double s = s0 + s1;
     if (i == k) col[0] = s;
     __syncthreads();
     double d = col[0];
@@ -173,8 +179,12 @@ __global__ __launch_bounds__(64) void k_rf_diag(const int* __restrict__ lvl_node
       if (i == 0) *flag = 1;
       d = 1.0;  // keep the arithmetic finite; the result is discarded
     }
-    const double l = sqrt(d);
-    const double lik = i == k ? l : s / l;
+    // 1/sqrt(d): the hardware estimate and two Newton steps
+    // r <- r + r (1 - d r^2) / 2, each doubling the correct bits
+    double r = __builtin_amdgcn_rsq(d);
+#pragma unroll
+    for (int it = 0; it < 2; ++it) r = fma(0.5 * r, fma(-d * r, r, 1.0), r);
+    const double lik = i == k ? d * r : s * r;
     if (i >= k) a[k] = lik;
     if (lane) Lm[i][k] = i >= k ? lik : 0.0;
     __syncthreads();
@@ -190,9 +200,14 @@ __global__ __launch_bounds__(64) void k_rf_diag(const int* __restrict__ lvl_node
   double x[NB];
 #pragma unroll
   for (int r = 0; r < NB; ++r) {
-    double s = 0.0;
+    double s0 = 0.0, s1 = 0.0;
 #pragma unroll
-    for (int k = 0; k < r; ++k) s += Lm[r][k] * x[k];
+    for (int k = 0; k + 1 < r; k += 2) {
+      s0 += Lm[r][k] * x[k];
+      s1 += Lm[r][k + 1] * x[k + 1];
+    }
+    if (r & 1) s0 += Lm[r][r - 1] * x[r - 1];
+    const double s = s0 + s1;
     x[r] = r == i ? dinv[r] : (r > i ? -dinv[r] * s : 0.0);
   }
   __syncthreads();  // Lm has been read

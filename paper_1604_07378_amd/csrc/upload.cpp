@@ -14,6 +14,7 @@
 
 #include "../../include/qnsim.h"
 #include "ctx.hpp"
+#include "partials.hpp"
 
 namespace qn {
 
@@ -195,12 +196,9 @@ int upload_sims(const std::vector<const qnsim*>& sims, const qnsim_options& opt,
     for (const Supernode& sn : Fp->sn) blk_src.push_back(Fp->Binv.data() + sn.val_off);
   }
   const Factor& F = *Fp;
-  // element-pass force partials. Element blocks (256 tets, per simulation
-  // from its first tet, as laid out below) each get one partial per distinct
-  // free vertex of their tets (ascending vertex), with the block's
-  // contributions to it listed in (tet, slot) order; a free vertex's partials
-  // are listed in block order.
-  std::vector<int> eb_t0, eb_t1, eb_p0;  // element blocks in table order
+  // element-pass force partials of the element blocks (256 tets, per
+  // simulation from its first tet, as laid out in the block tables below)
+  std::vector<int> eb_t0, eb_t1;
   for (int s = 0; s < S; ++s) {
     const int ne = std::max((sims[s]->T + 255) / 256, (sims[s]->nf + 255) / 256);
     for (int j = 0; j < ne; ++j) {
@@ -209,85 +207,13 @@ int upload_sims(const std::vector<const qnsim*>& sims, const qnsim_options& opt,
     }
   }
   const int nblk = (int)eb_t0.size();
-  std::vector<std::vector<int>> blk_verts(nblk);
+  Partials parts;
   {
-    struct Pv { const int* tv; const int *b0, *b1; int nf; std::vector<std::vector<int>>* out; } pv{
-        tv.data(), eb_t0.data(), eb_t1.data(), nf, &blk_verts};
-    parallel_for(nblk, 64, &pv, [](const void* ctx, int64_t lo, int64_t hi) {
-      const Pv& q = *static_cast<const Pv*>(ctx);
-      for (int64_t b = lo; b < hi; ++b) {
-        std::vector<int>& l = (*q.out)[b];
-        for (int t = q.b0[b]; t < q.b1[b]; ++t)
-          for (int a = 0; a < 4; ++a)
-            if (q.tv[4 * (size_t)t + a] < q.nf) l.push_back(q.tv[4 * (size_t)t + a]);
-        std::sort(l.begin(), l.end());
-        l.erase(std::unique(l.begin(), l.end()), l.end());
-      }
-    });
+    const int rc = build_partials(tv, T, nf, eb_t0, eb_t1, parts, err);
+    if (rc) return rc;
   }
-  eb_p0.assign(nblk + 1, 0);
-  for (int b = 0; b < nblk; ++b) eb_p0[b + 1] = eb_p0[b] + (int)blk_verts[b].size();
+  const std::vector<int>& eb_p0 = parts.p0;
   const int n_part = eb_p0[nblk];
-  std::vector<int> lc_ptr((size_t)n_part + 1, 0);
-  std::vector<unsigned short> lc_idx;
-  {
-    // contributions per partial, then their lists in (tet, slot) order
-    std::vector<int> lc_cnt((size_t)n_part, 0);
-    for (int b = 0; b < nblk; ++b) {
-      const std::vector<int>& l = blk_verts[b];
-      for (int t = eb_t0[b]; t < eb_t1[b]; ++t)
-        for (int a = 0; a < 4; ++a) {
-          const int v = tv[4 * (size_t)t + a];
-          if (v >= nf) continue;
-          const int j = (int)(std::lower_bound(l.begin(), l.end(), v) - l.begin());
-          lc_cnt[eb_p0[b] + j]++;
-        }
-    }
-    for (int g = 0; g < n_part; ++g) lc_ptr[g + 1] = lc_ptr[g] + lc_cnt[g];
-    lc_idx.assign((size_t)lc_ptr[n_part], 0);
-    std::vector<int> fill(lc_ptr.begin(), lc_ptr.end() - 1);
-    for (int b = 0; b < nblk; ++b) {
-      const std::vector<int>& l = blk_verts[b];
-      for (int t = eb_t0[b]; t < eb_t1[b]; ++t)
-        for (int a = 0; a < 4; ++a) {
-          const int v = tv[4 * (size_t)t + a];
-          if (v >= nf) continue;
-          const int j = (int)(std::lower_bound(l.begin(), l.end(), v) - l.begin());
-          lc_idx[fill[eb_p0[b] + j]++] = (unsigned short)(4 * (t - eb_t0[b]) + a);
-        }
-    }
-  }
-  // the partials of each free vertex, in block order
-  std::vector<int> nbp(nf, 0);
-  for (int b = 0; b < nblk; ++b)
-    for (int v : blk_verts[b]) nbp[v]++;
-  int bp_w = 4;
-  for (int i = 0; i < nf; ++i) bp_w = std::max(bp_w, (nbp[i] + 3) / 4 * 4);
-  std::vector<int> bp_tab((size_t)std::max(nf, 1) * bp_w, -1);
-  {
-    std::vector<int> fill(nf, 0);
-    for (int b = 0; b < nblk; ++b)
-      for (size_t j = 0; j < blk_verts[b].size(); ++j) {
-        const int v = blk_verts[b][j];
-        bp_tab[(size_t)v * bp_w + fill[v]++] = eb_p0[b] + (int)j;
-      }
-    // self-check: every free vertex has a partial (it belongs to a tet), every
-    // contribution of a free vertex is listed once, within its block
-    int64_t nc = 0;
-    for (int t = 0; t < T; ++t)
-      for (int a = 0; a < 4; ++a) nc += tv[4 * (size_t)t + a] < nf;
-    if (nc != (int64_t)lc_idx.size()) FAIL(QNSIM_E_DEVICE, "partials: contributions not listed once");
-    for (int i = 0; i < nf; ++i)
-      if (nbp[i] < 1) FAIL(QNSIM_E_DEVICE, "partials: free vertex without a partial");
-    for (int b = 0; b < nblk; ++b)
-      for (int g = eb_p0[b]; g < eb_p0[b + 1]; ++g)
-        for (int k = lc_ptr[g]; k < lc_ptr[g + 1]; ++k) {
-          const int q = lc_idx[k], t = eb_t0[b] + q / 4;
-          if (t >= eb_t1[b] || tv[4 * (size_t)t + q % 4] != blk_verts[b][g - eb_p0[b]])
-            FAIL(QNSIM_E_DEVICE, "partials: contribution outside its block or vertex");
-        }
-  }
-  std::vector<std::vector<int>>().swap(blk_verts);
   // supernodal solve: packed blocks (row-major forward copy, column-major
   // backward copy), work items in topological order, assembly lists
   const int ns = (int)F.sn.size();
@@ -619,10 +545,10 @@ int upload_sims(const std::vector<const qnsim*>& sims, const qnsim_options& opt,
   UP(D.mats, dm);
   UP(D.mass, mass);
   D.n_part = n_part;
-  D.bp_w = bp_w;
-  UP(D.bp_tab, bp_tab);
-  UP(D.lc_ptr, lc_ptr);
-  UP(D.lc_idx, lc_idx);
+  D.bp_w = parts.bp_w;
+  UP(D.bp_tab, parts.bp_tab);
+  UP(D.lc_ptr, parts.lc_ptr);
+  UP(D.lc_idx, parts.lc_idx);
   UP(D.vperm, vperm);
   UP(D.tperm, tperm);
   UP(D.vsim, vsim);

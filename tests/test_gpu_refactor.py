@@ -60,6 +60,27 @@ def test_refactor_solve_against_oracle(dims, sched):
     s.close()
 
 
+@pytest.mark.parametrize("mk", [lambda: W.workload_mixed_cantilever(0),
+                                lambda: W.workload_block(W.SPLINE, dims=(6, 5, 4), prestretch_seed=1)],
+                         ids=["logE-cantilever", "spline-block"])
+def test_refactor_per_element_stiffness(mk):
+    """Stiffness varying over three decades per element (log-uniform E), and
+    the spline material's fitted k: the refactored solve at h = 1/120 against
+    the oracle's."""
+    w = mk()
+    s = qnsim.sim_from_workload(w, dense_top=0, level_merge=0)
+    q = np.random.default_rng(9).normal(size=(w.n_verts, 3))
+    h = 1.0 / 120.0
+    s.refactor(h)
+    m = _model(w, h)
+    r_ref = np.zeros_like(q)
+    r_ref[m.free] = m.solve(q[m.free])
+    r = _solve(s, q)
+    err = np.abs(r - r_ref).max() / np.abs(r_ref).max()
+    assert err <= 1e-11, f"rel err {err:.3e}"
+    s.close()
+
+
 @pytest.mark.parametrize("sched", ["levels", "default"])
 def test_refactor_round_trip_and_steps(sched):
     """Refactor to h = 1/60, run five steps against the oracle at that h; a
