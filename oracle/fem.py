@@ -77,6 +77,14 @@ class Model:
         return self.free.shape[0]
 
 
+def _extra(m):
+    """The material's parameter beyond mu and lam: the spline's knot values
+    a'' (SPLINE) or the second shear modulus mu2 (MOONEY_RIVLIN)."""
+    if m.type == mat.MOONEY_RIVLIN:
+        return float(getattr(m, "mu2", 0.0) or 0.0)
+    return m.d2()
+
+
 def element_rest_data(rest: np.ndarray, tets: np.ndarray):
     """Dm = [X1 - X0, X2 - X0, X3 - X0] (columns), V = |det Dm| / 6, Dm^{-1}."""
     X = rest[tets]                                   # (T, 4, 3)
@@ -160,14 +168,14 @@ def build_model(rest, tets, pinned, materials, tet_mat=None, h=1.0 / 30.0,
     mass = lumped_mass(n, tets, vol, rho)
 
     # Stiffness per material (section 4.1, Eq. stiffness).
-    kmat = np.array([mat.stiffness(m.type, m.mu, m.lam, m.d2(), fit_lo, fit_hi)
+    kmat = np.array([mat.stiffness(m.type, m.mu, m.lam, _extra(m), fit_lo, fit_hi)
                      for m in materials])
     k = kmat[tet_mat]
     groups = []
     for mi, m in enumerate(materials):
         ids = np.nonzero(tet_mat == mi)[0]
         if len(ids):
-            groups.append((m.type, ids, m.mu, m.lam, m.d2()))
+            groups.append((m.type, ids, m.mu, m.lam, _extra(m)))
     # Merge groups of identical non-spline kind into one vectorised group with
     # per-tet parameters (plain bookkeeping, same arithmetic).
     mu_t = np.array([materials[i].mu for i in tet_mat])
@@ -179,7 +187,7 @@ def build_model(rest, tets, pinned, materials, tet_mat=None, h=1.0 / 30.0,
     merged = {}
     final = []
     for kind, ids, mu, lam, d2 in groups:
-        if kind == mat.SPLINE:
+        if kind in (mat.SPLINE, mat.MOONEY_RIVLIN):
             final.append((kind, ids, mu, lam, d2))
         else:
             merged.setdefault(kind, []).append(ids)

@@ -14,12 +14,18 @@ Paper passages followed:
 * Section 5: Neo-Hookean, St. Venant-Kirchhoff, corotated and spline-based
   materials; the polynomial material a(x) = mu (x - 1)^4, b = c = 0 of the
   squirrel-head example (section 4, figure caption; section 4.1).
+* Section 4.1 names Mooney-Rivlin among the materials with a Valanis-Landel
+  form (no formula or parameters are given).
 
 Readings where the paper is silent:
 * Material formulas (not written in the paper) are the standard ones:
     Neo-Hookean   Psi = mu/2 (I1 - 3) - mu log J + lam/2 (log J)^2, +inf for J <= 0
     StVK          Psi = mu tr(E^2) + lam/2 tr(E)^2,  E = (F^T F - I)/2
     corotated     Psi = mu |F - R|^2 + lam/2 tr(R^T F - I)^2
+    Mooney-Rivlin Psi = mu/2 (I1 - 3) + mu2/2 (I2 - 3) - (mu + 2 mu2) log J
+                        + lam/2 (log J)^2,  I2 = ((tr C)^2 - tr C^2)/2, C = F^T F,
+                  +inf for J <= 0 (compressible form; the log J coefficient
+                  makes the rest state stress-free; mu2 = 0 is Neo-Hookean)
   Their Valanis-Landel forms (derived by expanding in the stretches):
     Neo-Hookean   a(x) = mu/2 (x^2 - 1),                         b = 0,
                   c(J) = -mu log J + lam/2 (log J)^2
@@ -27,6 +33,8 @@ Readings where the paper is silent:
                   b(y) = lam/4 (y^2 - 1),                         c = 0
     corotated     a(x) = (mu + lam/2)(x - 1)^2 - 2 lam (x - 1),
                   b(y) = lam (y - 1),                             c = 0
+    Mooney-Rivlin a(x) = mu/2 (x^2 - 1),  b(y) = mu2/2 (y^2 - 1),
+                  c(J) = -(mu + 2 mu2) log J + lam/2 (log J)^2
 * Spline material (the paper's spline curves are not given): a'' is the
   piecewise-linear interpolant of 8 values d2_j at knots 0.2 + 0.4 j
   (j = 0..7), constant beyond the end knots; a'(1) = a(1) = 0, so a is a
@@ -42,7 +50,7 @@ from __future__ import annotations
 
 import numpy as np
 
-NEOHOOKEAN, STVK, SPLINE, COROTATED, POLYNOMIAL = 0, 1, 2, 3, 4
+NEOHOOKEAN, STVK, SPLINE, COROTATED, POLYNOMIAL, MOONEY_RIVLIN = 0, 1, 2, 3, 4, 5
 
 SPLINE_KNOTS = 0.2 + 0.4 * np.arange(8, dtype=np.float64)
 
@@ -139,7 +147,10 @@ class StretchSpline:
 # Valanis-Landel terms a, b, c and their derivatives (Eq. valanis-landel)
 # ---------------------------------------------------------------------------
 def vl_terms(kind: int, mu, lam, d2=None):
-    """Return functions (a, da, b, db, c, dc) of the Valanis-Landel form."""
+    """Return functions (a, da, b, db, c, dc) of the Valanis-Landel form.
+
+    d2: the knot values a'' (SPLINE) or the second shear modulus mu2
+    (MOONEY_RIVLIN); unused otherwise."""
     mu = np.asarray(mu, dtype=np.float64)
     lam = np.asarray(lam, dtype=np.float64)
     zero = lambda x: np.zeros_like(np.asarray(x, dtype=np.float64))  # noqa: E731
@@ -170,6 +181,20 @@ def vl_terms(kind: int, mu, lam, d2=None):
     if kind == POLYNOMIAL:
         return (lambda x: mu * (x - 1.0) ** 4, lambda x: 4.0 * mu * (x - 1.0) ** 3,
                 zero, zero, zero, zero)
+    if kind == MOONEY_RIVLIN:
+        mu2 = np.asarray(d2, dtype=np.float64)
+        mue = mu + 2.0 * mu2
+
+        def c(J):
+            with np.errstate(divide="ignore", invalid="ignore"):
+                lj = np.log(J)
+                return np.where(J > 0, -mue * lj + 0.5 * lam * lj * lj, np.inf)
+
+        def dc(J):
+            with np.errstate(divide="ignore", invalid="ignore"):
+                return np.where(J > 0, (-mue + lam * np.log(J)) / J, np.nan)
+        return (lambda x: 0.5 * mu * (x * x - 1.0), lambda x: mu * x,
+                lambda y: 0.5 * mu2 * (y * y - 1.0), lambda y: mu2 * y, c, dc)
     if kind == SPLINE:
         sp = StretchSpline(d2)
         return (lambda x: sp.eval(x)[0], lambda x: sp.eval(x)[1],
@@ -234,6 +259,29 @@ def psi_P_neohookean(F, mu, lam):
     return psi, P
 
 
+def psi_P_mooney_rivlin(F, mu, lam, mu2):
+    """Invariant form: P = mu F + mu2 (I1 F - F C) + (lam log J - mu - 2 mu2) F^{-T}."""
+    mu = np.asarray(mu, dtype=np.float64)
+    lam = np.asarray(lam, dtype=np.float64)
+    mu2 = np.asarray(mu2, dtype=np.float64)
+    J = np.linalg.det(F)
+    ok = J > 0
+    Fs = np.where(ok[..., None, None], F, np.eye(3))
+    Finv_T = np.swapaxes(np.linalg.inv(Fs), -1, -2)
+    C = np.einsum("...ki,...kj->...ij", F, F)
+    I1 = np.trace(C, axis1=-2, axis2=-1)
+    I2 = 0.5 * (I1 * I1 - np.einsum("...ij,...ji->...", C, C))
+    with np.errstate(divide="ignore", invalid="ignore"):
+        logJ = np.log(np.where(ok, J, 1.0))
+    mue = mu + 2.0 * mu2
+    psi = 0.5 * mu * (I1 - 3.0) + 0.5 * mu2 * (I2 - 3.0) - mue * logJ + 0.5 * lam * logJ * logJ
+    psi = np.where(ok, psi, np.inf)
+    P = (mu[..., None, None] * F + mu2[..., None, None] * (I1[..., None, None] * F - F @ C)
+         + (lam * logJ - mue)[..., None, None] * Finv_T)
+    P = np.where(ok[..., None, None], P, np.nan)
+    return psi, P
+
+
 def psi_P_stvk(F, mu, lam):
     mu = np.asarray(mu, dtype=np.float64)
     lam = np.asarray(lam, dtype=np.float64)
@@ -265,6 +313,8 @@ def psi_and_P(kind: int, F: np.ndarray, mu, lam, d2=None):
         return psi_P_stvk(F, mu, lam)
     if kind == COROTATED:
         return psi_P_corotated(F, mu, lam)
+    if kind == MOONEY_RIVLIN:
+        return psi_P_mooney_rivlin(F, mu, lam, d2)
     if kind in (SPLINE, POLYNOMIAL):
         return psi_P_valanis_landel(kind, F, mu, lam, d2)
     raise ValueError(f"unknown material type {kind}")

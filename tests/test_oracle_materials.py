@@ -12,13 +12,20 @@ import pytest
 
 from oracle import materials as mat
 
-KINDS = [mat.NEOHOOKEAN, mat.STVK, mat.SPLINE, mat.COROTATED, mat.POLYNOMIAL]
+KINDS = [mat.NEOHOOKEAN, mat.STVK, mat.SPLINE, mat.COROTATED, mat.POLYNOMIAL,
+         mat.MOONEY_RIVLIN]
 MU, LAM = 35714.28571428572, 142857.1428571429
+MU2 = 0.4 * MU  # Mooney-Rivlin: shear modulus of the I2 term
 
 
 def _d2(seed=0):
     rng = np.random.default_rng(seed)
     return MU * rng.uniform(0.5, 2.0, size=8)
+
+
+def _extra(kind, seed=0):
+    """The parameter beyond mu and lam: spline knot values, or mu2."""
+    return MU2 if kind == mat.MOONEY_RIVLIN else _d2(seed)
 
 
 def _random_F(n, seed, amp=0.3):
@@ -41,7 +48,7 @@ def _rot(seed):
 def test_stress_is_energy_derivative(kind):
     """P = dPsi/dF by central differences (rel. err < 1e-7)."""
     F = _random_F(40, kind)
-    d2 = _d2()
+    d2 = _extra(kind)
     psi, P = mat.psi_and_P(kind, F, MU, LAM, d2)
     eps = 1e-6
     Pfd = np.zeros_like(P)
@@ -57,7 +64,7 @@ def test_stress_is_energy_derivative(kind):
 
 @pytest.mark.parametrize("kind", KINDS)
 def test_rest_state_is_stress_free(kind):
-    psi, P = mat.psi_and_P(kind, np.eye(3)[None], MU, LAM, _d2())
+    psi, P = mat.psi_and_P(kind, np.eye(3)[None], MU, LAM, _extra(kind))
     assert abs(psi[0]) < 1e-12 * MU
     assert np.abs(P).max() < 1e-12 * MU
 
@@ -66,7 +73,7 @@ def test_rest_state_is_stress_free(kind):
 def test_rotation_invariance(kind):
     """Psi(QF) = Psi(F), P(QF) = Q P(F) (world frame); Psi(FQ) = Psi(F) (isotropy)."""
     F = _random_F(30, 10 + kind)
-    d2 = _d2()
+    d2 = _extra(kind)
     psi, P = mat.psi_and_P(kind, F, MU, LAM, d2)
     for s in range(3):
         Q = _rot(100 + s)
@@ -78,12 +85,12 @@ def test_rotation_invariance(kind):
         assert np.abs(P_l - Q @ P).max() < 1e-10 * np.abs(P).max()
 
 
-@pytest.mark.parametrize("kind", [mat.NEOHOOKEAN, mat.STVK, mat.COROTATED])
+@pytest.mark.parametrize("kind", [mat.NEOHOOKEAN, mat.STVK, mat.COROTATED, mat.MOONEY_RIVLIN])
 def test_invariant_form_equals_valanis_landel_form(kind):
     """The closed invariant formula and the Valanis-Landel stretch form agree."""
     F = _random_F(50, 20 + kind)
-    psi_a, P_a = mat.psi_and_P(kind, F, MU, LAM)
-    psi_b, P_b = mat.psi_P_valanis_landel(kind, F, MU, LAM)
+    psi_a, P_a = mat.psi_and_P(kind, F, MU, LAM, MU2)
+    psi_b, P_b = mat.psi_P_valanis_landel(kind, F, MU, LAM, MU2)
     assert np.abs(psi_a - psi_b).max() < 1e-10 * np.abs(psi_a).max()
     assert np.abs(P_a - P_b).max() < 1e-10 * np.abs(P_a).max()
 
@@ -92,6 +99,32 @@ def test_neohookean_inverted_is_infinite():
     F = np.diag([1.0, 1.0, -0.5])[None]
     psi, _ = mat.psi_and_P(mat.NEOHOOKEAN, F, MU, LAM)
     assert np.isinf(psi[0])
+    psi, _ = mat.psi_and_P(mat.MOONEY_RIVLIN, F, MU, LAM, MU2)
+    assert np.isinf(psi[0])
+
+
+def test_mooney_rivlin_without_i2_term_is_neohookean():
+    """mu2 = 0 leaves exactly the Neo-Hookean energy and stress."""
+    F = _random_F(40, 31)
+    psi_a, P_a = mat.psi_and_P(mat.MOONEY_RIVLIN, F, MU, LAM, 0.0)
+    psi_b, P_b = mat.psi_and_P(mat.NEOHOOKEAN, F, MU, LAM)
+    assert np.abs(psi_a - psi_b).max() <= 1e-12 * np.abs(psi_b).max()
+    assert np.abs(P_a - P_b).max() <= 1e-12 * np.abs(P_b).max()
+
+
+def test_mooney_rivlin_second_invariant_and_uniaxial_stress():
+    """Uniaxial stretch F = diag(s, 1, 1), worked by hand: I1 = s^2 + 2,
+    I2 = ((tr C)^2 - tr C^2)/2 = 2 s^2 + 1, J = s, so Psi(s) and its
+    derivative P_11 = mu s + 2 mu2 s - (mu + 2 mu2)/s + lam log(s)/s."""
+    for sv in (0.6, 0.9, 1.0, 1.3, 1.8):
+        F = np.diag([sv, 1.0, 1.0])[None]
+        psi, P = mat.psi_and_P(mat.MOONEY_RIVLIN, F, MU, LAM, MU2)
+        ls = math.log(sv)
+        p11 = MU * sv + 2 * MU2 * sv - (MU + 2 * MU2) / sv + LAM * ls / sv
+        e = (0.5 * MU * (sv * sv - 1) + 0.5 * MU2 * (2 * sv * sv - 2)
+             - (MU + 2 * MU2) * ls + 0.5 * LAM * ls * ls)
+        assert P[0, 0, 0] == pytest.approx(p11, rel=1e-12, abs=1e-9 * MU)
+        assert psi[0] == pytest.approx(e, rel=1e-12, abs=1e-9 * MU)
 
 
 def test_signed_svd():
@@ -176,7 +209,7 @@ def test_stiffness_matches_discrete_least_squares(kind):
     Equal-weight samples at cell midpoints make the discrete least-squares sums
     midpoint-rule quadratures of the continuous ones (error O(N^-2)).
     """
-    d2 = _d2(7)
+    d2 = _extra(kind, 7)
     N = 200000
     s = 0.5 + (np.arange(N) + 0.5) / N
     f = mat.stress_profile(kind, MU, LAM, d2)(s)
@@ -185,11 +218,23 @@ def test_stiffness_matches_discrete_least_squares(kind):
     assert k == pytest.approx(slope, rel=1e-8)
 
 
+def test_stiffness_mooney_rivlin_is_neohookean_with_summed_shear():
+    """f(s) = (mu + 2 mu2)(s - 1/s) + lam log(s)/s is the Neo-Hookean profile
+    with shear modulus mu + 2 mu2, so k follows the same closed form."""
+    ln = math.log
+    mu_coef = 1.0 + 12.0 * (ln(3.0) - 1.0)
+    F = lambda s: s * ln(s) - s - 0.5 * ln(s) ** 2
+    lam_coef = 12.0 * (F(1.5) - F(0.5))
+    k = mat.stiffness(mat.MOONEY_RIVLIN, MU, LAM, MU2)
+    assert k == pytest.approx(mu_coef * (MU + 2 * MU2) + lam_coef * LAM, rel=1e-13)
+
+
 def test_stiffness_positive_for_workload_materials():
     import workloads as W
-    for kind in (W.NEOHOOKEAN, W.STVK, W.SPLINE):
+    for kind in (W.NEOHOOKEAN, W.STVK, W.SPLINE, W.MOONEY_RIVLIN):
         m = W.make_material(kind, 1e5, 0.4)
-        assert mat.stiffness(m.type, m.mu, m.lam, m.d2()) > 0
+        extra = m.mu2 if kind == W.MOONEY_RIVLIN else m.d2()
+        assert mat.stiffness(m.type, m.mu, m.lam, extra) > 0
 
 
 # ---------------------------------------------------------------------------

@@ -27,5 +27,6 @@ from .grid import (  # noqa: F401
     SPLINE,
     COROTATED,
     POLYNOMIAL,
+    MOONEY_RIVLIN,
     MATERIAL_NAMES,
 )

@@ -31,12 +31,14 @@ STVK = 1
 SPLINE = 2
 COROTATED = 3
 POLYNOMIAL = 4
+MOONEY_RIVLIN = 5
 MATERIAL_NAMES = {
     NEOHOOKEAN: "neohookean",
     STVK: "stvk",
     SPLINE: "spline",
     COROTATED: "corotated",
     POLYNOMIAL: "polynomial",
+    MOONEY_RIVLIN: "mooneyrivlin",
 }
 
 # Uniform body acceleration (m/s^2); the external force is M times this field.
@@ -77,6 +79,8 @@ class Material:
     # anisotropic fibre term kappa/2 (|F d| - 1)^2 on top (0: none)
     fiber_kappa: float = 0.0
     fiber_dir: Optional[np.ndarray] = None
+    # second shear modulus of MOONEY_RIVLIN (the I2 term); 0 otherwise
+    mu2: float = 0.0
 
     def d2(self) -> np.ndarray:
         if self.spline_d2 is None:
@@ -86,10 +90,15 @@ class Material:
 
 def make_material(kind: int, E: float, nu: float, density: float = 1000.0,
                   spline_seed: int = 0) -> Material:
+    """Material of the given type from Young's modulus and Poisson's ratio.
+    Mooney-Rivlin splits the shear modulus mu into 0.7 mu on the I1 term and
+    0.3 mu on the I2 term (their sum is the small-strain shear modulus)."""
     mu, lam = lame_from_young(E, nu)
     d2 = None
     if kind == SPLINE:
         d2 = mu * spline_d2_multipliers(spline_seed)
+    if kind == MOONEY_RIVLIN:
+        return Material(kind, 0.7 * mu, lam, density, None, mu2=0.3 * mu)
     return Material(kind, mu, lam, density, d2)
 
 
