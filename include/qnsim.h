@@ -59,6 +59,9 @@ extern "C" {
 #define QNSIM_SPLINE 2      /* sum a(s_i) + lam/2 (J-1)^2, a'' piecewise linear  */
 #define QNSIM_COROTATED 3   /* mu |F-R|^2 + lam/2 tr(R^T F - I)^2                */
 #define QNSIM_POLYNOMIAL 4  /* sum mu (s_i - 1)^4                                */
+#define QNSIM_MOONEY_RIVLIN 5 /* mu/2 (I1-3) + mu2/2 (I2-3) - (mu + 2 mu2) log J
+                                 + lam/2 (log J)^2, I2 = ((tr C)^2 - tr C^2)/2,
+                                 C = F^T F (compressible; mu2 = 0 is Neo-Hookean) */
 
 /* ---- precision modes ---------------------------------------------------- */
 #define QNSIM_FP64 0   /* every kernel in FP64                                   */
@@ -132,6 +135,11 @@ typedef struct {
    * non-zero direction. It does not change the stiffness k of A. */
   double fiber_kappa;
   double fiber_dir[3];
+  /* QNSIM_MOONEY_RIVLIN: shear modulus of the I2 term (>= 0, Pa); ignored
+   * for other types. Its stiffness k is the Neo-Hookean rule's with shear
+   * modulus mu + 2 mu2 (the stress profile of the stiffness rule is the same
+   * function of the stretch). */
+  double mu2;
 } qnsim_material;
 
 /* Per-step counters (filled by qnsim_step / qnsim_step_device when non-null). */

@@ -340,12 +340,15 @@ int qnsim_set_materials(qnsim_t* c, int32_t n_mat, const qnsim_material* mats,
   std::vector<Material> ms(n_mat);
   for (int i = 0; i < n_mat; ++i) {
     const qnsim_material& q = mats[i];
-    if (q.type < QNSIM_NEOHOOKEAN || q.type > QNSIM_POLYNOMIAL)
+    if (q.type < QNSIM_NEOHOOKEAN || q.type > QNSIM_MOONEY_RIVLIN)
       return fail(c, QNSIM_E_INVALID, "unknown material type");
     if (!std::isfinite(q.mu) || !std::isfinite(q.lambda) || !std::isfinite(q.density) ||
-        !finite_all(q.spline_d2, 8) || !std::isfinite(q.fiber_kappa) || !finite_all(q.fiber_dir, 3))
+        !finite_all(q.spline_d2, 8) || !std::isfinite(q.fiber_kappa) || !finite_all(q.fiber_dir, 3) ||
+        (q.type == QNSIM_MOONEY_RIVLIN && !std::isfinite(q.mu2)))
       return fail(c, QNSIM_E_NONFINITE, "non-finite material parameter");
     if (q.fiber_kappa < 0.0) return fail(c, QNSIM_E_INVALID, "fiber_kappa must be >= 0");
+    if (q.type == QNSIM_MOONEY_RIVLIN && q.mu2 < 0.0) return fail(c, QNSIM_E_INVALID, "mu2 must be >= 0");
+    ms[i].mu2 = q.type == QNSIM_MOONEY_RIVLIN ? q.mu2 : 0.0;
     const double dn = std::sqrt(q.fiber_dir[0] * q.fiber_dir[0] + q.fiber_dir[1] * q.fiber_dir[1] +
                                 q.fiber_dir[2] * q.fiber_dir[2]);
     if (q.fiber_kappa > 0.0 && !(dn > 0.0))
@@ -517,12 +520,12 @@ int qnsim_step(qnsim_t* c, const double* x, const double* v, double h, const dou
   }
   std::string err;
   bool has_nh = false;
-  for (const Material& m : c->mats) has_nh |= (m.type == NEOHOOKEAN);
+  for (const Material& m : c->mats) has_nh |= (m.type == NEOHOOKEAN || m.type == MOONEY_RIVLIN);
   if (has_nh) {
     int inv = 0;
     rc = dev_check_inverted(c->dev, dx, st, &inv, err);
     if (rc) { return fail(c, rc, err); }
-    if (inv) { return fail(c, QNSIM_E_INVERTED, "Neo-Hookean element with J <= 0 at x"); }
+    if (inv) { return fail(c, QNSIM_E_INVERTED, "Neo-Hookean or Mooney-Rivlin element with J <= 0 at x"); }
   }
   rc = dev_step(c->dev, params_of(c, h), dx, dv, f_ext ? df : nullptr, dxo, dvo, st,
                 c->diag_final_gradient != 0, err);

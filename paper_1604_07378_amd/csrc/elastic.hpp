@@ -217,6 +217,35 @@ __device__ __forceinline__ bool material_eval(const DevMat& mat, const M3<R>& F,
       for (int j = 0; j < 3; ++j)
         P.a[i][j] = F.a[i][0] * Sst[0][j] + F.a[i][1] * Sst[1][j] + F.a[i][2] * Sst[2][j];
     return true;
+  } else if (TYPE == 5) {  // Mooney-Rivlin
+    R J = det3(F);
+    if (!(J > R(0))) {
+      psi = R(INFINITY);
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) P.a[i][j] = R(0);
+      return false;
+    }
+    const R mu2 = R(mat.mu2), mue = mu + R(2) * mu2;
+    R C[3][3];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j)
+        C[i][j] = F.a[0][i] * F.a[0][j] + F.a[1][i] * F.a[1][j] + F.a[2][i] * F.a[2][j];
+    const R I1 = C[0][0] + C[1][1] + C[2][2];
+    R trC2 = R(0);
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) trC2 += C[i][j] * C[i][j];
+    const R I2 = R(0.5) * (I1 * I1 - trC2);
+    M3<R> Cf = cofactor(F);
+    const R lj = log(J);
+    psi = R(0.5) * mu * (I1 - R(3)) + R(0.5) * mu2 * (I2 - R(3)) - mue * lj + R(0.5) * lam * lj * lj;
+    // P = mu F + mu2 (I1 F - F C) + (lam log J - mu - 2 mu2) F^{-T}
+    const R cf = (lam * lj - mue) / J;
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        const R fc = F.a[i][0] * C[0][j] + F.a[i][1] * C[1][j] + F.a[i][2] * C[2][j];
+        P.a[i][j] = mu * F.a[i][j] + mu2 * (I1 * F.a[i][j] - fc) + cf * Cf.a[i][j];
+      }
+    return true;
   } else {  // stretch-based: spline (2), corotated (3), polynomial (4)
     R U[3][3], V[3][3], s[3];
     svd3(F, U, s, V);
@@ -285,6 +314,7 @@ __device__ __forceinline__ bool material_eval_any(const DevMat& mat, const M3<R>
     case 1: return material_eval<R, 1>(mat, F, psi, P);
     case 2: return material_eval<R, 2>(mat, F, psi, P);
     case 3: return material_eval<R, 3>(mat, F, psi, P);
+    case 5: return material_eval<R, 5>(mat, F, psi, P);
     default: return material_eval<R, 4>(mat, F, psi, P);
   }
 }

@@ -13,11 +13,13 @@ namespace qn {
 // ---------------------------------------------------------------------------
 // Materials (section 4.1, Valanis-Landel form; section 5 material list)
 // ---------------------------------------------------------------------------
-enum MatType { NEOHOOKEAN = 0, STVK = 1, SPLINE = 2, COROTATED = 3, POLYNOMIAL = 4 };
+enum MatType { NEOHOOKEAN = 0, STVK = 1, SPLINE = 2, COROTATED = 3, POLYNOMIAL = 4,
+               MOONEY_RIVLIN = 5 };
 
 struct Material {
   int type = NEOHOOKEAN;
   double mu = 0.0, lam = 0.0, rho = 0.0;
+  double mu2 = 0.0;     // Mooney-Rivlin: shear modulus of the I2 term
   double d2[8] = {0};   // spline: a'' at the knots 0.2 + 0.4 j
   double a0[8] = {0};   // spline: a at the knots
   double a1[8] = {0};   // spline: a' at the knots

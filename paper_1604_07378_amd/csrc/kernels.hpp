@@ -30,6 +30,7 @@ struct DevMat {
   double d2[8], a0[8], a1[8];
   double kappa;    // anisotropic fibre term kappa/2 (|F d| - 1)^2 (0: none)
   double fdir[3];  // its unit rest-pose direction d
+  double mu2;      // Mooney-Rivlin: shear modulus of the I2 term
 };
 
 // Phase of one simulation within a step (each simulation of a batch moves
@@ -105,7 +106,7 @@ struct BlockSeg {
 
 // Material kinds of the element-pass launch lists: the five types, and
 // simulations whose tets mix types (generic evaluation).
-constexpr int kElemKinds = 6;
+constexpr int kElemKinds = 7;
 
 struct Level {
   int fw_begin, fw_end;  // forward work items of this level

@@ -52,9 +52,12 @@ double anti_lin(double s, double mid) {           // g(s) = s - 1
 double stiffness_fit(const Material& m, double lo, double hi) {
   const double L = hi - lo, mid = 0.5 * (lo + hi);
   const double scale = 12.0 / (L * L * L);
-  const double mu = m.mu, lam = m.lam;
+  // Mooney-Rivlin's stress profile is the Neo-Hookean one with shear
+  // modulus mu + 2 mu2: f(s) = (mu + 2 mu2)(s - 1/s) + lam log(s) / s
+  const double mu = m.type == MOONEY_RIVLIN ? m.mu + 2.0 * m.mu2 : m.mu, lam = m.lam;
   switch (m.type) {
-    case NEOHOOKEAN: {
+    case NEOHOOKEAN:
+    case MOONEY_RIVLIN: {
       // f(s) = mu s - mu / s + lam log(s) / s
       auto F = [&](double s) {
         const double ls = std::log(s);

@@ -914,8 +914,8 @@ __global__ void __launch_bounds__(BS) k_clear_inverted(int S, SimStat* __restric
   if (s < S) stat[s].inverted = 0;
 }
 
-// Neo-Hookean inverted-input check: flags each simulation with a Neo-Hookean
-// tet of J <= 0 at X (running simulations only).
+// Inverted-input check: flags each simulation with a Neo-Hookean or
+// Mooney-Rivlin tet of J <= 0 at X (running simulations only).
 __global__ void __launch_bounds__(BS)
 k_check_inverted(const BlockSeg* __restrict__ blk, const int* __restrict__ run, int T,
                  const int* __restrict__ tv, const double* __restrict__ Bm,
@@ -925,7 +925,8 @@ k_check_inverted(const BlockSeg* __restrict__ blk, const int* __restrict__ run, 
   if (!run[sg.sim]) return;
   const int t = sg.a0 + threadIdx.x;
   if (t >= sg.a1) return;
-  if (mats[tmat ? tmat[t] : 0].type != 0) return;
+  const int ty = mats[tmat ? tmat[t] : 0].type;
+  if (ty != 0 && ty != 5) return;  // log J terms: Neo-Hookean, Mooney-Rivlin
   const int4 iv = reinterpret_cast<const int4*>(tv)[t];
   const int vid[4] = {iv.x, iv.y, iv.z, iv.w};
   M3<double> F;
@@ -1017,6 +1018,7 @@ void launch_elem(DeviceMesh& D, hipStream_t st, int want, int trial, double* par
       case 2: QN_ELEM(2, blk, grid); break;
       case 3: QN_ELEM(3, blk, grid); break;
       case 4: QN_ELEM(4, blk, grid); break;
+      case 5: QN_ELEM(5, blk, grid); break;
       default: QN_ELEM(-1, blk, grid); break;
     }
   };

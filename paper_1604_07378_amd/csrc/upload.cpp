@@ -179,6 +179,7 @@ int upload_sims(const std::vector<const qnsim*>& sims, const qnsim_options& opt,
       d.type = m.type; d.mu = m.mu; d.lam = m.lam;
       for (int j = 0; j < 8; ++j) { d.d2[j] = m.d2[j]; d.a0[j] = m.a0[j]; d.a1[j] = m.a1[j]; }
       d.kappa = m.fiber_kappa;
+      d.mu2 = m.mu2;
       for (int j = 0; j < 3; ++j) d.fdir[j] = m.fiber_dir[j];
       dm.push_back(d);
     }

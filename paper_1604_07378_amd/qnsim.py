@@ -20,7 +20,7 @@ KERNEL_ELEMENT, KERNEL_GATHER, KERNEL_SOLVE = 0, 1, 2
 QNSIM_FP64 = 0
 QNSIM_MIXED = 1
 DIR_LBFGS, DIR_CHEBYSHEV = 0, 1
-NEOHOOKEAN, STVK, SPLINE, COROTATED, POLYNOMIAL = 0, 1, 2, 3, 4
+NEOHOOKEAN, STVK, SPLINE, COROTATED, POLYNOMIAL, MOONEY_RIVLIN = 0, 1, 2, 3, 4, 5
 
 ERRORS = {
     -1: "QNSIM_E_INVALID", -2: "QNSIM_E_NONFINITE", -3: "QNSIM_E_DEGENERATE",
@@ -53,7 +53,8 @@ class MaterialC(ctypes.Structure):
     _fields_ = [("type", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("mu", ctypes.c_double), ("lambda_", ctypes.c_double),
                 ("density", ctypes.c_double), ("spline_d2", ctypes.c_double * 8),
-                ("fiber_kappa", ctypes.c_double), ("fiber_dir", ctypes.c_double * 3)]
+                ("fiber_kappa", ctypes.c_double), ("fiber_dir", ctypes.c_double * 3),
+                ("mu2", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):
@@ -216,6 +217,8 @@ def _material_array(materials: Sequence):
             arr[i].fiber_kappa = float(opt("fiber_kappa"))
             for j, val in enumerate(np.asarray(opt("fiber_dir"), dtype=np.float64)):
                 arr[i].fiber_dir[j] = float(val)
+        if opt("mu2"):
+            arr[i].mu2 = float(opt("mu2"))
     return arr
 
 
@@ -402,7 +405,8 @@ def _materials_of(w):
     return [dict(type=m.type, mu=m.mu, lam=m.lam, density=m.density,
                  spline_d2=m.d2() if hasattr(m, "d2") else None,
                  fiber_kappa=getattr(m, "fiber_kappa", 0.0),
-                 fiber_dir=getattr(m, "fiber_dir", None)) for m in w.materials]
+                 fiber_dir=getattr(m, "fiber_dir", None),
+                 mu2=getattr(m, "mu2", 0.0)) for m in w.materials]
 
 
 class Pool:

@@ -20,7 +20,7 @@ from paper_1604_07378_amd import qnsim  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
-KINDS = [W.NEOHOOKEAN, W.STVK, W.SPLINE, W.COROTATED, W.POLYNOMIAL]
+KINDS = [W.NEOHOOKEAN, W.STVK, W.SPLINE, W.COROTATED, W.POLYNOMIAL, W.MOONEY_RIVLIN]
 
 
 def _dev(a):
@@ -142,7 +142,7 @@ def test_cantilever_other_jitter_seeds(seed):
     _trajectory_parity(W.workload_cantilever(seed), 30)
 
 
-@pytest.mark.parametrize("kind", [W.STVK, W.SPLINE, W.COROTATED, W.POLYNOMIAL])
+@pytest.mark.parametrize("kind", [W.STVK, W.SPLINE, W.COROTATED, W.POLYNOMIAL, W.MOONEY_RIVLIN])
 def test_cantilever_materials(kind):
     _trajectory_parity(W.workload_cantilever(0, kind=kind), 30)
 
@@ -250,7 +250,7 @@ def test_block_solve_full_size(sched):
     assert err <= 1e-12
 
 
-@pytest.mark.parametrize("kind", [W.NEOHOOKEAN, W.STVK, W.SPLINE])
+@pytest.mark.parametrize("kind", [W.NEOHOOKEAN, W.STVK, W.SPLINE, W.MOONEY_RIVLIN])
 def test_block_first_step_full_size(kind):
     """The 40^3 block (384,000 tets) at full size, in the benchmark's launch
     configuration: one time step against the oracle (banded LAPACK solve)."""

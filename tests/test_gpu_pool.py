@@ -90,6 +90,31 @@ def test_batch_mixed_materials_against_alone_and_oracle():
     p.close()
 
 
+def test_batch_with_mooney_rivlin_equals_alone():
+    """Neo-Hookean, Mooney-Rivlin and spline blocks in one group (one element
+    launch per material type), 5 steps: each equals its run alone, bit for
+    bit, and the Mooney-Rivlin block matches the oracle."""
+    kinds = [W.NEOHOOKEAN, W.MOONEY_RIVLIN, W.SPLINE, W.MOONEY_RIVLIN]
+    ws = [W.workload_block(k, dims=(4 + i, 3, 4), prestretch_seed=30 + i) for i, k in enumerate(kinds)]
+    p, ids = _pool(ws)
+    steps = 5
+    ref = [_alone(w, steps) for w in ws]
+    for k in range(steps):
+        p.step(ids)
+        for j in range(len(ws)):
+            x, v = p.get_state(ids[j])
+            assert np.array_equal(x, ref[j][k][0]) and np.array_equal(v, ref[j][k][1]), \
+                f"sim {j} step {k}"
+    w = ws[1]
+    m = oracle.build_model(w.rest, w.tets, w.pinned, w.materials, w.tet_mat, w.h, w.gravity)
+    x, v = w.x0.copy(), w.v0.copy()
+    for k in range(steps):
+        r = oracle.step(m, x, v)
+        x, v = r.x, r.v
+        assert _eps(ref[1][k][0], r.x, w.rest) <= 1e-9, f"step {k}"
+    p.close()
+
+
 def test_subsets_and_groups():
     """Four groups of two; alternating subsets step; the others keep their state."""
     ws = [W.workload_block(W.STVK, dims=(3 + i % 3, 3, 4), prestretch_seed=10 + i) for i in range(8)]

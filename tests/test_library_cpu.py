@@ -44,7 +44,8 @@ def _model(w):
     return oracle.build_model(w.rest, w.tets, w.pinned, w.materials, w.tet_mat, w.h, w.gravity)
 
 
-@pytest.mark.parametrize("kind", [W.NEOHOOKEAN, W.STVK, W.SPLINE, W.COROTATED, W.POLYNOMIAL])
+@pytest.mark.parametrize("kind", [W.NEOHOOKEAN, W.STVK, W.SPLINE, W.COROTATED, W.POLYNOMIAL,
+                                  W.MOONEY_RIVLIN])
 def test_host_stiffness_and_masses_match_oracle(kind):
     w = W.workload_cantilever(0, kind=kind)
     s = qnsim.sim_from_workload(w, prepare=False)
