@@ -109,6 +109,13 @@ typedef struct {
                            needs history = 0)                               */
   int32_t cheb_delay;   /* Chebyshev: iterations S with omega = 1 (>= 1; 10)   */
   double cheb_rho;      /* Chebyshev: spectral-radius estimate rho in (0, 1)  */
+  int32_t device_factor; /* 1: qnsim_prepare runs the ordering and symbolic
+                           analysis on the host and the numeric factorisation
+                           of A on the device (as qnsim_refactor); the host
+                           holds no factor values (qnsim_export_factor returns
+                           QNSIM_E_STATE). 0 (default): both on the host.
+                           Pools use 0.                                      */
+  int32_t reserved_opt;
 } qnsim_options;
 
 #define QNSIM_DIR_LBFGS 0

@@ -194,7 +194,7 @@ int analyze_impl(qnsim_t* c, double h) {
   for (int j = 0; j < nf; ++j) colptr[j + 1] += colptr[j];
   std::string err;
   int rc = factorize(nf, colptr, rowidx, val, c->factor, err, c->opt.dense_top,
-                     c->opt.level_merge != 0);
+                     c->opt.level_merge != 0, c->opt.device_factor == 0);
   if (rc == -1) return fail(c, QNSIM_E_NOT_SPD, err);
   if (rc != 0) return fail(c, QNSIM_E_DEVICE, err);
   // internal vertex order: free unknowns in factor order, then pinned vertices
@@ -275,7 +275,7 @@ int qnsim_create(const qnsim_options* opts, qnsim_t** out) {
       (o.direction != QNSIM_DIR_LBFGS && o.direction != QNSIM_DIR_CHEBYSHEV) ||
       (o.direction == QNSIM_DIR_CHEBYSHEV &&
        (o.history != 0 || o.cheb_delay < 1 || !(o.cheb_rho > 0.0 && o.cheb_rho < 1.0))) ||
-      !finite_all(o.gravity, 3))
+      !finite_all(o.gravity, 3) || (o.device_factor != 0 && o.device_factor != 1))
     return QNSIM_E_INVALID;
   qnsim_t* c = new (std::nothrow) qnsim();
   if (!c) return QNSIM_E_NOMEM;
@@ -379,7 +379,9 @@ int qnsim_set_materials(qnsim_t* c, int32_t n_mat, const qnsim_material* mats,
 
 int qnsim_analyze(qnsim_t* c, double h) {
   if (!c) return QNSIM_E_INVALID;
-  if (c->analyzed && c->h == h && !c->factor_on_device) return QNSIM_OK;
+  // the host analysis stands while h is unchanged and the host factor's values
+  // (if it holds any) belong to h
+  if (c->analyzed && c->h == h && (!c->factor_on_device || c->opt.device_factor)) return QNSIM_OK;
   invalidate(c);
   c->factor_on_device = false;
   try {
@@ -399,6 +401,10 @@ int qnsim_prepare(qnsim_t* c, double h) {
   try {
     std::string err;
     rc = upload_sims({c}, c->opt, c->h, c->dev, err);
+    if (!rc && c->opt.device_factor) {
+      rc = dev_refactor(c, c->h, nullptr, err);  // the numeric factorisation
+      if (!rc) c->factor_on_device = true;
+    }
     if (!rc && !c->planes.empty())
       rc = dev_set_colliders(c->dev, (int)c->planes.size() / 4, c->planes.data(), c->coll_k, err);
     if (rc) fail(c, rc, err);
@@ -598,7 +604,9 @@ int qnsim_get_factor_info(const qnsim_t* c, qnsim_factor_info* info) {
   info->subtree_levels = c->prepared ? c->dev.sub_levels : 0;
   info->nnz_L = F.nnz_stored;
   info->nnz_L_exact = F.nnz_exact;
-  info->factor_bytes = (int64_t)F.Binv.size() * 8;
+  int64_t blk = 0;  // the partitioned-inverse blocks (host layout; with or without values)
+  for (const Supernode& S : F.sn) blk += (int64_t)S.m() * S.ncol;
+  info->factor_bytes = blk * 8;
   info->factor_flops = F.flops;
   info->prepare_seconds = c->analyze_seconds;
   return QNSIM_OK;
@@ -607,7 +615,7 @@ int qnsim_get_factor_info(const qnsim_t* c, qnsim_factor_info* info) {
 int qnsim_export_factor(const qnsim_t* c, int32_t* perm, int64_t* colptr, int32_t* rowidx,
                         double* values) {
   if (!c) return QNSIM_E_INVALID;
-  if (!c->analyzed || c->factor_on_device) return QNSIM_E_STATE;
+  if (!c->analyzed || c->factor_on_device || (c->factor.L.empty() && c->nf > 0)) return QNSIM_E_STATE;
   if (perm)
     for (int i = 0; i < c->nf; ++i) perm[i] = c->vperm[i];
   if (colptr || rowidx || values) {

@@ -90,7 +90,8 @@ void inv_cols(const void* vctx, int64_t lo, int64_t hi) {
 }  // namespace
 
 int factorize(int n, const std::vector<int64_t>& colptr, const std::vector<int>& rowidx,
-              const std::vector<double>& val, Factor& f, std::string& err, int dense_top_max, bool level_merge) {
+              const std::vector<double>& val, Factor& f, std::string& err, int dense_top_max,
+              bool level_merge, bool numeric) {
   f = Factor();
   f.n = n;
   if (n == 0) return 0;
@@ -511,6 +512,18 @@ int factorize(int n, const std::vector<int64_t>& colptr, const std::vector<int>&
   f.nnz_stored = 0;
   for (int k = 0; k < ns; ++k) f.nnz_stored += (int64_t)block_entries(f.sn[k].ncol, f.sn[k].nbelow);
 
+  if (!numeric) {
+    // operation count of the factorisation and its partitioned inverse
+    double flops = 0.0;
+    for (int k = 0; k < ns; ++k) {
+      const double nc = f.sn[k].ncol, nb = f.sn[k].nbelow;
+      flops += nc * nc * nc / 3.0 + nc * nc * nb + nc * nb * nb + nc * nc * nc / 3.0;
+      if (k == f.top) flops += nc * nc * nc / 3.0;
+      else if (nb > 0) flops += 2.0 * nb * nc * nc;
+    }
+    f.flops = flops;
+    return 0;
+  }
   // ---- numeric multifrontal factorisation ----------------------------------
   f.L.assign(voff, 0.0);
   f.Binv.assign(voff, 0.0);

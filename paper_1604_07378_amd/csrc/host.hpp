@@ -107,9 +107,11 @@ struct Factor {
 // parents; the top levels may be merged into one dense root block of at most
 // dense_top_max columns (0 disables), see Factor::top. Both follow a cost
 // model of the level-scheduled triangular solves.
+// numeric = false: the ordering and the symbolic structure only (no L, no
+// partitioned inverse; the values are factored on the device).
 int factorize(int n, const std::vector<int64_t>& colptr, const std::vector<int>& rowidx,
               const std::vector<double>& val, Factor& f, std::string& err, int dense_top_max,
-              bool level_merge);
+              bool level_merge, bool numeric = true);
 
 // Exact CSC of L (for export and tests): column j's nonzeros.
 void factor_to_csc(const Factor& f, std::vector<int64_t>& colptr, std::vector<int>& rowidx,

@@ -303,6 +303,7 @@ int qnsim_pool_create(const qnsim_options* opts, double h, int64_t budget_bytes,
   // levels (or a dense top block) would only add bytes
   o.dense_top = 0;
   o.level_merge = 0;
+  o.device_factor = 0;
   qnsim_t* probe = nullptr;  // option validation as for a single context
   int rc = qnsim_create(&o, &probe);
   if (rc) return rc;

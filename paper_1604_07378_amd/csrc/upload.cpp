@@ -188,12 +188,18 @@ int upload_sims(const std::vector<const qnsim*>& sims, const qnsim_options& opt,
   Factor stacked;
   const Factor* Fp = &sims[0]->factor;
   std::vector<const double*> blk_src;
+  // a factor analysed without values (numeric factorisation on the device)
+  // gets zero blocks here
+  bool values = true;
+  for (int s = 0; s < S; ++s)
+    if (sims[s]->factor.Binv.empty() && sims[s]->nf > 0) values = false;
+  if (!values && S > 1) FAIL(QNSIM_E_INVALID, "batched simulations need host factor values");
   if (S > 1) {
     std::vector<const Factor*> fs(S);
     for (int s = 0; s < S; ++s) fs[s] = &sims[s]->factor;
     stack_factors(fs, vf0, stacked, blk_src);
     Fp = &stacked;
-  } else {
+  } else if (values) {
     for (const Supernode& sn : Fp->sn) blk_src.push_back(Fp->Binv.data() + sn.val_off);
   }
   const Factor& F = *Fp;
@@ -270,31 +276,36 @@ int upload_sims(const std::vector<const qnsim*>& sims, const qnsim_options& opt,
       const Factor* F; const double* const* blk; const std::vector<int64_t>* pf;
       const std::vector<int64_t>* pb; double* Bf; double* Bb; int top;
     } pk{&F, blk_src.data(), &pf, &pb, Bf.data(), Bb.data(), top};
-    parallel_for(ns, 16, &pk, [](const void* ctx, int64_t lo, int64_t hi) {
-      const Pack& q = *static_cast<const Pack*>(ctx);
-      for (int64_t s = lo; s < hi; ++s) {
-        const Supernode& S = q.F->sn[s];
-        const int nc = S.ncol, m = S.m();
-        const double* blk = q.blk[s];
-        if (s == q.top) {
-          // symmetric: the column-major block is also its row-major copy
-          std::copy(blk, blk + (size_t)nc * nc, q.Bf + (*q.pf)[s]);
-          continue;
+    if (!values) {
+      std::fill(Bf.data(), Bf.data() + Bf.size(), 0.0);
+      std::fill(Bb.data(), Bb.data() + Bb.size(), 0.0);
+    } else {
+      parallel_for(ns, 16, &pk, [](const void* ctx, int64_t lo, int64_t hi) {
+        const Pack& q = *static_cast<const Pack*>(ctx);
+        for (int64_t s = lo; s < hi; ++s) {
+          const Supernode& S = q.F->sn[s];
+          const int nc = S.ncol, m = S.m();
+          const double* blk = q.blk[s];
+          if (s == q.top) {
+            // symmetric: the column-major block is also its row-major copy
+            std::copy(blk, blk + (size_t)nc * nc, q.Bf + (*q.pf)[s]);
+            continue;
+          }
+          double* bf = q.Bf + (*q.pf)[s];
+          double* bb = q.Bb + (*q.pb)[s];
+          for (int r = 0; r < m; ++r) {
+            const int len = r < nc ? r + 1 : nc;
+            const int64_t ro = r < nc ? (int64_t)r * (r + 1) / 2
+                                      : (int64_t)nc * (nc + 1) / 2 + (int64_t)(r - nc) * nc;
+            for (int c = 0; c < len; ++c) bf[ro + c] = blk[r + (size_t)c * m];
+          }
+          for (int c = 0; c < nc; ++c) {
+            const int64_t co = (int64_t)c * m - (int64_t)c * (c - 1) / 2;
+            for (int i = c; i < m; ++i) bb[co + (i - c)] = blk[i + (size_t)c * m];
+          }
         }
-        double* bf = q.Bf + (*q.pf)[s];
-        double* bb = q.Bb + (*q.pb)[s];
-        for (int r = 0; r < m; ++r) {
-          const int len = r < nc ? r + 1 : nc;
-          const int64_t ro = r < nc ? (int64_t)r * (r + 1) / 2
-                                    : (int64_t)nc * (nc + 1) / 2 + (int64_t)(r - nc) * nc;
-          for (int c = 0; c < len; ++c) bf[ro + c] = blk[r + (size_t)c * m];
-        }
-        for (int c = 0; c < nc; ++c) {
-          const int64_t co = (int64_t)c * m - (int64_t)c * (c - 1) / 2;
-          for (int i = c; i < m; ++i) bb[co + (i - c)] = blk[i + (size_t)c * m];
-        }
-      }
-    });
+      });
+    }
   }
   for (int s = 0; s < ns; ++s) {
     const Supernode& S = F.sn[s];

@@ -46,7 +46,8 @@ class Options(ctypes.Structure):
                 ("subtree_cap", ctypes.c_int32), ("level_merge", ctypes.c_int32),
                 ("step_graph", ctypes.c_int32), ("trials_per_cycle", ctypes.c_int32),
                 ("direction", ctypes.c_int32), ("cheb_delay", ctypes.c_int32),
-                ("cheb_rho", ctypes.c_double)]
+                ("cheb_rho", ctypes.c_double), ("device_factor", ctypes.c_int32),
+                ("reserved_opt", ctypes.c_int32)]
 
 
 class MaterialC(ctypes.Structure):

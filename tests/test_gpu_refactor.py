@@ -156,3 +156,34 @@ def test_refactor_full_size(sched):
           f"solve rel err vs oracle {err:.3e}; round trip {back:.3e}", flush=True)
     assert err <= 1e-11 and back <= 1e-12
     s.close()
+
+
+@pytest.mark.parametrize("sched", ["levels", "subtrees+top", "default"])
+def test_device_factor_at_prepare(sched):
+    """device_factor = 1: the host orders and analyses, the device computes
+    the numeric factor at prepare. Trajectory against the oracle (1e-9, same
+    line-search counts) and against the host-factored context (1e-11)."""
+    w = W.workload_block(W.STVK, dims=(8, 6, 5), prestretch_seed=4)
+    s = qnsim.sim_from_workload(w, device_factor=1, **SCHEDULES[sched])
+    ref = qnsim.sim_from_workload(w, **SCHEDULES[sched])
+    with pytest.raises(qnsim.QnsimError):
+        s.export_factor()                    # no host factor values
+    assert s.factor_info()["factor_bytes"] == ref.factor_info()["factor_bytes"]
+    m = _model(w, w.h)
+    x_o, v_o = w.x0.copy(), w.v0.copy()
+    x_g, v_g = w.x0.copy(), w.v0.copy()
+    x_r, v_r = w.x0.copy(), w.v0.copy()
+    for k in range(6):
+        r = oracle.step(m, x_o, v_o)
+        x_o, v_o = r.x, r.v
+        x_g, v_g, st = s.step(x_g, v_g, w.h)
+        x_r, v_r, _ = ref.step(x_r, v_r, w.h)
+        assert _eps(x_g, x_o, w.rest) <= 1e-9, f"step {k}"
+        assert st["ls_trials"] == r.ls_trials
+        assert _eps(x_g, x_r, w.rest) <= 1e-11, f"step {k} vs host factor"
+    s.prepare(w.h)                           # again: analysis kept, factor rebuilt
+    x2, _, _ = s.step(w.x0, w.v0, w.h)
+    x1, _, _ = ref.step(w.x0, w.v0, w.h)
+    assert _eps(x2, x1, w.rest) <= 1e-11
+    s.close()
+    ref.close()
