@@ -439,6 +439,17 @@ int qnsim_pool_wait(qnsim_pool_t* pool, int64_t ticket, double timeout_s, qnsim_
 int qnsim_pool_serve_stop(qnsim_pool_t* pool);
 
 int qnsim_pool_get_info(qnsim_pool_t* pool, qnsim_pool_info* info);
+
+/* Change the pool's time step to h (sections 3.2 and 4.1: A = M/h^2 + L
+ * depends on h). Every resident group's A is refactored on the device (as
+ * qnsim_refactor; the first call per group builds its refactorisation plan,
+ * whose device memory is outside the pool's budget); staged simulations are
+ * analysed again on the host for h. Later steps use h. Needs the request loop
+ * stopped (QNSIM_E_STATE) and waits for running steps. On a failure the
+ * groups already refactored return to the previous h and the error is
+ * returned (QNSIM_E_NOT_SPD, QNSIM_E_NOMEM, QNSIM_E_DEVICE). *device_ms
+ * (nullable): the device time of the refactorisations. */
+int qnsim_pool_set_h(qnsim_pool_t* pool, double h, double* device_ms);
 /* As qnsim_time_kernel, on group `group` (0-based, in admission order) with
  * every simulation of the group taking part; after at least one step of the
  * group. Not while the request loop runs. */

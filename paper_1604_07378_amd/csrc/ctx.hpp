@@ -55,7 +55,15 @@ namespace qn {
 // concatenated; returns 0 or a negative QNSIM_E_* code with err set.
 int upload_sims(const std::vector<const qnsim*>& sims, const qnsim_options& opt, double h,
                 DeviceMesh& D, std::string& err);
-// Numeric refactorisation of A for step size h on the device (single mesh);
-// device_ms (nullable): device time of the factorisation and block writes.
+// The structure of several factors side by side (columns of factor k shifted
+// by col0[k]); blk[s]: supernode s's column-major block in its own factor.
+void stack_factors(const std::vector<const Factor*>& fs, const std::vector<int>& col0, Factor& F,
+                   std::vector<const double*>& blk);
+// Numeric refactorisation of A for step size h on the device mesh D of the
+// simulations sims (their concatenation, as uploaded); device_ms (nullable):
+// device time of the factorisation and block writes.
+int dev_refactor_mesh(const std::vector<const qnsim*>& sims, DeviceMesh& D, double h,
+                      double* device_ms, std::string& err);
+// The same for a single context's own device mesh.
 int dev_refactor(qnsim* c, double h, double* device_ms, std::string& err);
 }  // namespace qn

@@ -430,15 +430,22 @@ int qnsim_pool_remove(qnsim_pool_t* p, int32_t id) {
   PoolSim& s = p->sims[id];
   for (const Request& r : p->queue)
     if (r.sim == id) return pfail(p, QNSIM_E_STATE, "simulation has queued requests");
+  s.removed = true;
   if (s.group >= 0) {
     PoolGroup& g = *p->groups[s.group];
     p->cv.wait(lk, [&] { return !g.busy; });
     if (--g.live == 0) {
       p->used -= g.bytes;
       free_group(g);
+      // the members' host data served the group's refactorisation
+      for (int id2 : g.ids)
+        if (p->sims[id2].removed && p->sims[id2].c) {
+          qnsim_destroy(p->sims[id2].c);
+          p->sims[id2].c = nullptr;
+        }
     }
+    return QNSIM_OK;  // a member's host data stays while its group is resident
   }
-  s.removed = true;
   if (s.c) { qnsim_destroy(s.c); s.c = nullptr; }
   return QNSIM_OK;
 }
@@ -611,6 +618,58 @@ int qnsim_pool_get_info(qnsim_pool_t* p, qnsim_pool_info* info) {
   info->used_bytes = p->used;
   info->steps_done = p->steps_done;
   info->batches_done = p->batches_done;
+  return QNSIM_OK;
+}
+
+int qnsim_pool_set_h(qnsim_pool_t* p, double h, double* device_ms) {
+  if (!p) return QNSIM_E_INVALID;
+  if (!(h > 0.0) || !std::isfinite(h)) return pfail(p, QNSIM_E_INVALID, "h must be positive");
+  std::unique_lock<std::mutex> lk(p->mu);
+  if (p->serving) return pfail(p, QNSIM_E_STATE, "the request loop is running");
+  p->cv.wait(lk, [&] {
+    for (auto& g : p->groups)
+      if (g && g->busy) return false;
+    return true;
+  });
+  const double h_old = p->h;
+  double total = 0.0;
+  std::string err;
+  // resident groups: A refactored on the device, group by group; on a
+  // failure the groups already done go back to the previous h
+  std::vector<int> done;
+  for (int gi = 0; gi < (int)p->groups.size(); ++gi) {
+    PoolGroup& g = *p->groups[gi];
+    if (g.live == 0) continue;
+    std::vector<const qnsim*> members;
+    for (int id : g.ids) members.push_back(p->sims[id].c);
+    double ms = 0.0;
+    int rc = dev_refactor_mesh(members, g.D, h, &ms, err);
+    if (rc) {
+      for (int gj : done) {
+        PoolGroup& g2 = *p->groups[gj];
+        std::vector<const qnsim*> m2;
+        for (int id : g2.ids) m2.push_back(p->sims[id].c);
+        std::string e2;
+        (void)dev_refactor_mesh(m2, g2.D, h_old, nullptr, e2);
+      }
+      return pfail(p, rc, err);
+    }
+    total += ms;
+    done.push_back(gi);
+  }
+  // staged simulations: host analysis for the new h
+  for (PoolSim& s : p->sims)
+    if (!s.removed && s.group < 0 && s.c) {
+      int rc = qnsim_analyze(s.c, h);
+      if (rc) return pfail(p, rc, std::string("staged simulation: ") + qnsim_last_error(s.c));
+    }
+  for (PoolSim& s : p->sims)
+    if (s.c && s.group >= 0) {
+      s.c->h = h;
+      s.c->factor_on_device = true;  // the host factor values belong to the old h
+    }
+  p->h = h;
+  if (device_ms) *device_ms = total;
   return QNSIM_OK;
 }
 

@@ -446,11 +446,27 @@ int rf_upload(RefactorPlan& P, T** dst, const std::vector<T>& src, std::string& 
 }
 
 // The plan: node table, schedules, the entries of K in front positions.
-int build_plan(const qnsim* c, RefactorPlan& P, std::string& err) {
-  const Factor& F = c->factor;
-  const DeviceMesh& D = c->dev;
+int build_plan(const std::vector<const qnsim*>& sims, const DeviceMesh& D, RefactorPlan& P,
+               std::string& err) {
+  const int nsim = (int)sims.size();
+  if (nsim < 1 || D.S != nsim || (int)D.seg_h.size() != nsim)
+    RF_FAIL(QNSIM_E_STATE, "refactor: device mesh does not match the simulations");
+  Factor stacked;
+  const Factor* Fp = &sims[0]->factor;
+  if (nsim > 1) {
+    std::vector<const Factor*> fs(nsim);
+    std::vector<int> col0(nsim);
+    for (int s = 0; s < nsim; ++s) {
+      fs[s] = &sims[s]->factor;
+      col0[s] = D.seg_h[s].vf0;
+    }
+    std::vector<const double*> unused;
+    stack_factors(fs, col0, stacked, unused);
+    Fp = &stacked;
+  }
+  const Factor& F = *Fp;
   const int ns = (int)F.sn.size();
-  if (D.nsn != ns || D.S != 1) RF_FAIL(QNSIM_E_STATE, "refactor: device mesh does not match the factor");
+  if (D.nsn != ns) RF_FAIL(QNSIM_E_STATE, "refactor: device mesh does not match the factor");
   std::vector<SnInfo> si(ns);
   if (hipMemcpy(si.data(), D.sn, ns * sizeof(SnInfo), hipMemcpyDeviceToHost) != hipSuccess)
     RF_FAIL(QNSIM_E_DEVICE, "refactor: reading the supernode table failed");
@@ -510,7 +526,7 @@ int build_plan(const qnsim* c, RefactorPlan& P, std::string& err) {
       }
     }
   // entries of K = sum_e V_e k_e G_e^T G_e (lower triangle), in front positions
-  const int nf = c->nf;
+  const int nf = D.nf;
   std::vector<int> col_sn(nf, -1);
   for (int s = 0; s < ns; ++s)
     for (int j = 0; j < F.sn[s].ncol; ++j) col_sn[F.sn[s].first + j] = s;
@@ -536,29 +552,34 @@ int build_plan(const qnsim* c, RefactorPlan& P, std::string& err) {
     int diag;
   };
   std::vector<Ent> ents;
-  ents.reserve((size_t)c->T * 10 + nf);
+  ents.reserve((size_t)D.T * 10 + nf);
   for (int j = 0; j < nf; ++j) ents.push_back({front_pos(j, j), 0.0, j});
-  for (int t = 0; t < c->T; ++t) {
-    const int* tv = &c->tets[4 * (size_t)t];
-    const double* Mi = &c->Dminv[9 * (size_t)t];
-    double g[4][3];
-    for (int k = 0; k < 3; ++k) {
-      g[1][k] = Mi[0 * 3 + k];
-      g[2][k] = Mi[1 * 3 + k];
-      g[3][k] = Mi[2 * 3 + k];
-      g[0][k] = -(g[1][k] + g[2][k] + g[3][k]);
-    }
-    const double w = c->vol[t] * c->kstiff[t];
-    for (int a = 0; a < 4; ++a) {
-      const int ia = c->viperm[tv[a]];
-      if (ia >= nf) continue;
-      for (int b = 0; b < 4; ++b) {
-        const int ib = c->viperm[tv[b]];
-        if (ib >= nf || ia < ib) continue;
-        const long long pos = front_pos(ia, ib);
-        if (pos < 0) RF_FAIL(QNSIM_E_STATE, "refactor: matrix entry outside the factor structure");
-        ents.push_back({pos, w * (g[a][0] * g[b][0] + g[a][1] * g[b][1] + g[a][2] * g[b][2]),
-                        ia == ib ? ia : -1});
+  for (int sm = 0; sm < nsim; ++sm) {
+    // a simulation's free unknowns start at its own first column
+    const qnsim* c = sims[sm];
+    const int cf = c->nf, off = D.seg_h[sm].vf0;
+    for (int t = 0; t < c->T; ++t) {
+      const int* tv = &c->tets[4 * (size_t)t];
+      const double* Mi = &c->Dminv[9 * (size_t)t];
+      double g[4][3];
+      for (int k = 0; k < 3; ++k) {
+        g[1][k] = Mi[0 * 3 + k];
+        g[2][k] = Mi[1 * 3 + k];
+        g[3][k] = Mi[2 * 3 + k];
+        g[0][k] = -(g[1][k] + g[2][k] + g[3][k]);
+      }
+      const double w = c->vol[t] * c->kstiff[t];
+      for (int a = 0; a < 4; ++a) {
+        const int ia = c->viperm[tv[a]];
+        if (ia >= cf) continue;
+        for (int b = 0; b < 4; ++b) {
+          const int ib = c->viperm[tv[b]];
+          if (ib >= cf || ia < ib) continue;
+          const long long pos = front_pos(off + ia, off + ib);
+          if (pos < 0) RF_FAIL(QNSIM_E_STATE, "refactor: matrix entry outside the factor structure");
+          ents.push_back({pos, w * (g[a][0] * g[b][0] + g[a][1] * g[b][1] + g[a][2] * g[b][2]),
+                          ia == ib ? off + ia : -1});
+        }
       }
     }
   }
@@ -628,14 +649,18 @@ void rf_free(DeviceMesh& D) {
 size_t rf_bytes(const DeviceMesh& D) { return D.rf ? D.rf->bytes : 0; }
 
 int dev_refactor(qnsim* c, double h, double* device_ms, std::string& err) {
-  DeviceMesh& D = c->dev;
+  return dev_refactor_mesh({c}, c->dev, h, device_ms, err);
+}
+
+int dev_refactor_mesh(const std::vector<const qnsim*>& sims, DeviceMesh& D, double h,
+                      double* device_ms, std::string& err) {
   if (hipSetDevice(D.device) != hipSuccess) RF_FAIL(QNSIM_E_DEVICE, "hipSetDevice failed");
   if (!D.rf) {
     RefactorPlan* P = new RefactorPlan();
     D.rf = P;
     int rc;
     try {
-      rc = build_plan(c, *P, err);
+      rc = build_plan(sims, D, *P, err);
     } catch (...) {
       rf_free(D);
       throw;

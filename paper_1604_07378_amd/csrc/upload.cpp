@@ -55,6 +55,8 @@ int upload(DeviceMesh& D, T** dst, const T* src, size_t count, std::string& err)
     if (rc_) return rc_;                                                \
   } while (0)
 
+}  // namespace
+
 // Supernodes of several factors side by side: column, row-list, block and
 // supernode indices shifted by each factor's offsets.
 // The structure of several factors side by side (columns of factor k shifted
@@ -99,7 +101,6 @@ void stack_factors(const std::vector<const Factor*>& fs, const std::vector<int>&
   F.top = -1;
 }
 
-}  // namespace
 
 int upload_sims(const std::vector<const qnsim*>& sims, const qnsim_options& opt, double h,
                 DeviceMesh& D, std::string& err) {

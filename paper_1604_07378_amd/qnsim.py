@@ -147,6 +147,7 @@ SIGNATURES = {
     "qnsim_pool_get_info": (ctypes.c_int, [_P, ctypes.POINTER(PoolInfo)]),
     "qnsim_pool_last_error": (ctypes.c_char_p, [_P]),
     "qnsim_pool_time_kernel": (ctypes.c_int, [_P, _I, _I, _I, ctypes.POINTER(_D)]),
+    "qnsim_pool_set_h": (ctypes.c_int, [_P, _D, ctypes.POINTER(_D)]),
 }
 
 _lib = None
@@ -526,6 +527,13 @@ class Pool:
         ms = ctypes.c_double()
         self._check(self._lib.qnsim_pool_time_kernel(self._p, int(group), int(kernel), int(reps),
                                                      ctypes.byref(ms)))
+        return ms.value
+
+    def set_h(self, h: float) -> float:
+        """New time step for every simulation (A refactored on the device);
+        returns the device milliseconds."""
+        ms = ctypes.c_double()
+        self._check(self._lib.qnsim_pool_set_h(self._p, float(h), ctypes.byref(ms)))
         return ms.value
 
     def info(self) -> dict:

@@ -240,3 +240,46 @@ def test_pool_graph_replays_equal_eager():
             assert np.array_equal(xg, xe) and np.array_equal(vg, ve), f"round {k}, sim {j}"
     pg.close()
     pe.close()
+
+
+def test_pool_time_step_change():
+    """qnsim_pool_set_h: four mixed-material simulations in two groups (one
+    member removed from its group first) go to h = 1/60 with A refactored on
+    the device; their steps match the oracle at 1/60 and a fresh pool built
+    for 1/60 to rounding; a staged simulation is analysed again for 1/60."""
+    ws = [W.workload_block([W.NEOHOOKEAN, W.STVK, W.MOONEY_RIVLIN, W.SPLINE][i], dims=(4, 3 + i, 4),
+                           prestretch_seed=40 + i) for i in range(4)]
+    extra = W.workload_block(W.STVK, dims=(5, 4, 3), prestretch_seed=50)
+    p, ids = _pool(ws + [W.workload_block(W.NEOHOOKEAN, dims=(3, 3, 3))], group=3)
+    p.remove(ids[4])                               # its group keeps the member's data
+    sid = p.add_workloads([extra])[0]              # staged, analysed for 1/30
+    h2 = 1.0 / 60.0
+    ms = p.set_h(h2)
+    assert ms > 0.0
+    fresh = qnsim.Pool(h2, 1 << 34, gravity=tuple(ws[0].gravity))
+    fids = fresh.add_workloads(ws)
+    fresh.commit(3)
+    for k in range(4):
+        p.step(ids[:4])
+        fresh.step(fids)
+        for j in range(4):
+            x, _ = p.get_state(ids[j])
+            xf, _ = fresh.get_state(fids[j])
+            assert _eps(x, xf, ws[j].rest) <= 1e-11, f"sim {j} step {k} vs fresh pool"
+    w = ws[2]                                      # the Mooney-Rivlin member against the oracle
+    m = oracle.build_model(w.rest, w.tets, w.pinned, w.materials, w.tet_mat, h2, w.gravity)
+    x, v = w.x0.copy(), w.v0.copy()
+    for k in range(4):
+        r = oracle.step(m, x, v)
+        x, v = r.x, r.v
+    xg, _ = p.get_state(ids[2])
+    assert _eps(xg, x, w.rest) <= 1e-9
+    assert p.commit(0) == 1                        # the staged one, analysed for 1/60
+    p.step([sid])
+    s = qnsim.sim_from_workload(extra, dense_top=0, level_merge=0, prepare=False)
+    s.prepare(h2)
+    xs, _, _ = s.step(extra.x0, extra.v0, h2)
+    assert np.array_equal(p.get_state(sid)[0], xs)
+    s.close()
+    p.close()
+    fresh.close()
