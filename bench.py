@@ -230,12 +230,21 @@ def served_run(args, torch, W, qnsim):
             f"p99 {r['p99_ms']:.2f} ms, {r['achieved_steps_per_s']:.0f} steps/s")
     p.serve_stop()
     info = p.info()
+    # a time-step change of the whole served pool: A refactored on the device,
+    # group by group (the first change also builds each group's plan)
+    t0 = time.perf_counter()
+    p.set_h(ws[0].h / 2)
+    h_first_s = time.perf_counter() - t0
+    h_ms = p.set_h(ws[0].h)
+    log(f"[bench] pool time-step change: {h_ms:.1f} ms on the device for {info['groups']} groups "
+        f"(first change {h_first_s:.1f} s with the plans)")
     p.close()
     return dict(sims=len(ws), admitted=admitted, tets=T, groups=info["groups"], group_size=group,
                 precision="mixed" if args.pool_precision else "f64",
                 device_gb=info["used_bytes"] / 1e9, budget_gb=args.pool_budget_gb,
                 lanes=args.pool_lanes, capacity_steps_per_s=cap, rates=rates,
-                batches=info["batches_done"], analysis_s=t_an, upload_s=t_up)
+                batches=info["batches_done"], analysis_s=t_an, upload_s=t_up,
+                set_h_device_ms=h_ms, set_h_first_s=h_first_s)
 
 
 def small_runs(args, torch, W, qnsim):
