@@ -445,6 +445,90 @@ int rf_upload(RefactorPlan& P, T** dst, const std::vector<T>& src, std::string& 
   return QNSIM_OK;
 }
 
+// Entries of K = sum_e V_e k_e G_e^T G_e (lower triangle) of the
+// simulations [lo, hi) in front positions, per simulation: the diagonal of
+// every free column first (mass added on the device), then the tets' terms,
+// summed per position in tet order.
+struct KCtx {
+  const std::vector<const qnsim*>* sims;
+  const DeviceMesh* D;
+  const Factor* F;
+  const std::vector<int>* col_sn;
+  const std::vector<RfNode>* node;
+  std::vector<std::vector<long long>> apos;
+  std::vector<std::vector<double>> aval;
+  std::vector<std::vector<int>> adiag;
+  std::vector<int> bad;
+};
+
+long long k_front_pos(const KCtx& q, int row, int col) {
+  const int s = (*q.col_sn)[col];
+  const Supernode& S = q.F->sn[s];
+  int lr;
+  if (row < S.first + S.ncol) {
+    lr = row - S.first;
+  } else {
+    const int* rb = q.F->rows.data() + S.rows_off;
+    const int* it = std::lower_bound(rb, rb + S.nbelow, row);
+    if (it == rb + S.nbelow || *it != row) return -1;
+    lr = S.ncol + (int)(it - rb);
+  }
+  return (*q.node)[s].front + lr + (long long)(col - S.first) * S.m();
+}
+
+void k_entries(const void* ctx, int64_t lo, int64_t hi) {
+  KCtx& q = *const_cast<KCtx*>(static_cast<const KCtx*>(ctx));
+  struct Ent {
+    long long pos;
+    double v;
+    int diag;
+  };
+  for (int64_t sm = lo; sm < hi; ++sm) {
+    const qnsim* c = (*q.sims)[sm];
+    const int cf = c->nf, off = q.D->seg_h[sm].vf0;
+    std::vector<Ent> ents;
+    ents.reserve((size_t)c->T * 10 + cf);
+    for (int j = 0; j < cf; ++j) ents.push_back({k_front_pos(q, off + j, off + j), 0.0, off + j});
+    for (int t = 0; t < c->T; ++t) {
+      const int* tv = &c->tets[4 * (size_t)t];
+      const double* Mi = &c->Dminv[9 * (size_t)t];
+      double g[4][3];
+      for (int k = 0; k < 3; ++k) {
+        g[1][k] = Mi[0 * 3 + k];
+        g[2][k] = Mi[1 * 3 + k];
+        g[3][k] = Mi[2 * 3 + k];
+        g[0][k] = -(g[1][k] + g[2][k] + g[3][k]);
+      }
+      const double w = c->vol[t] * c->kstiff[t];
+      for (int a = 0; a < 4; ++a) {
+        const int ia = c->viperm[tv[a]];
+        if (ia >= cf) continue;
+        for (int b = 0; b < 4; ++b) {
+          const int ib = c->viperm[tv[b]];
+          if (ib >= cf || ia < ib) continue;
+          const long long pos = k_front_pos(q, off + ia, off + ib);
+          if (pos < 0) q.bad[sm] = 1;
+          ents.push_back({pos, w * (g[a][0] * g[b][0] + g[a][1] * g[b][1] + g[a][2] * g[b][2]),
+                          ia == ib ? off + ia : -1});
+        }
+      }
+    }
+    std::stable_sort(ents.begin(), ents.end(), [](const Ent& x, const Ent& y) { return x.pos < y.pos; });
+    std::vector<long long>& ap = q.apos[sm];
+    std::vector<double>& av = q.aval[sm];
+    std::vector<int>& ad = q.adiag[sm];
+    for (size_t e = 0; e < ents.size();) {
+      size_t f = e;
+      double sum = 0.0;
+      while (f < ents.size() && ents[f].pos == ents[e].pos) sum += ents[f++].v;
+      ap.push_back(ents[e].pos);
+      av.push_back(sum);
+      ad.push_back(ents[e].diag);
+      e = f;
+    }
+  }
+}
+
 // The plan: node table, schedules, the entries of K in front positions.
 int build_plan(const std::vector<const qnsim*>& sims, const DeviceMesh& D, RefactorPlan& P,
                std::string& err) {
@@ -532,72 +616,31 @@ int build_plan(const std::vector<const qnsim*>& sims, const DeviceMesh& D, Refac
     for (int j = 0; j < F.sn[s].ncol; ++j) col_sn[F.sn[s].first + j] = s;
   for (int j = 0; j < nf; ++j)
     if (col_sn[j] < 0) RF_FAIL(QNSIM_E_STATE, "refactor: column outside every supernode");
-  auto front_pos = [&](int row, int col) -> long long {
-    const int s = col_sn[col];
-    const Supernode& S = F.sn[s];
-    int lr;
-    if (row < S.first + S.ncol) {
-      lr = row - S.first;
-    } else {
-      const int* rb = F.rows.data() + S.rows_off;
-      const int* it = std::lower_bound(rb, rb + S.nbelow, row);
-      if (it == rb + S.nbelow || *it != row) return -1;
-      lr = S.ncol + (int)(it - rb);
-    }
-    return P.node_h[s].front + lr + (long long)(col - S.first) * S.m();
-  };
-  struct Ent {
-    long long pos;
-    double v;
-    int diag;
-  };
-  std::vector<Ent> ents;
-  ents.reserve((size_t)D.T * 10 + nf);
-  for (int j = 0; j < nf; ++j) ents.push_back({front_pos(j, j), 0.0, j});
-  for (int sm = 0; sm < nsim; ++sm) {
-    // a simulation's free unknowns start at its own first column
-    const qnsim* c = sims[sm];
-    const int cf = c->nf, off = D.seg_h[sm].vf0;
-    for (int t = 0; t < c->T; ++t) {
-      const int* tv = &c->tets[4 * (size_t)t];
-      const double* Mi = &c->Dminv[9 * (size_t)t];
-      double g[4][3];
-      for (int k = 0; k < 3; ++k) {
-        g[1][k] = Mi[0 * 3 + k];
-        g[2][k] = Mi[1 * 3 + k];
-        g[3][k] = Mi[2 * 3 + k];
-        g[0][k] = -(g[1][k] + g[2][k] + g[3][k]);
-      }
-      const double w = c->vol[t] * c->kstiff[t];
-      for (int a = 0; a < 4; ++a) {
-        const int ia = c->viperm[tv[a]];
-        if (ia >= cf) continue;
-        for (int b = 0; b < 4; ++b) {
-          const int ib = c->viperm[tv[b]];
-          if (ib >= cf || ia < ib) continue;
-          const long long pos = front_pos(off + ia, off + ib);
-          if (pos < 0) RF_FAIL(QNSIM_E_STATE, "refactor: matrix entry outside the factor structure");
-          ents.push_back({pos, w * (g[a][0] * g[b][0] + g[a][1] * g[b][1] + g[a][2] * g[b][2]),
-                          ia == ib ? off + ia : -1});
-        }
-      }
-    }
-  }
-  std::stable_sort(ents.begin(), ents.end(), [](const Ent& x, const Ent& y) { return x.pos < y.pos; });
+  // entries of each simulation (its unknowns from its own first column; its
+  // supernodes, hence its front positions, after the previous one's), built
+  // in parallel and concatenated in simulation order
+  KCtx kc{&sims, &D, &F, &col_sn, &P.node_h, {}, {}, {}, {}};
+  kc.apos.resize(nsim);
+  kc.aval.resize(nsim);
+  kc.adiag.resize(nsim);
+  kc.bad.assign(nsim, 0);
+  parallel_for(nsim, 1, &kc, k_entries);
   std::vector<long long> apos;
   std::vector<double> aval;
   std::vector<int> adiag;
-  for (size_t e = 0; e < ents.size();) {
-    size_t f = e;
-    double s = 0.0;
-    while (f < ents.size() && ents[f].pos == ents[e].pos) s += ents[f++].v;
-    if (ents[e].pos < 0 || ents[e].pos >= wsl) RF_FAIL(QNSIM_E_STATE, "refactor: entry position out of range");
-    apos.push_back(ents[e].pos);
-    aval.push_back(s);
-    adiag.push_back(ents[e].diag);
-    e = f;
+  for (int sm = 0; sm < nsim; ++sm) {
+    if (kc.bad[sm]) RF_FAIL(QNSIM_E_STATE, "refactor: matrix entry outside the factor structure");
+    if (!kc.apos[sm].empty() &&
+        (kc.apos[sm].front() < 0 || kc.apos[sm].back() >= wsl ||
+         (!apos.empty() && kc.apos[sm].front() <= apos.back())))
+      RF_FAIL(QNSIM_E_STATE, "refactor: entry position out of range");
+    apos.insert(apos.end(), kc.apos[sm].begin(), kc.apos[sm].end());
+    aval.insert(aval.end(), kc.aval[sm].begin(), kc.aval[sm].end());
+    adiag.insert(adiag.end(), kc.adiag[sm].begin(), kc.adiag[sm].end());
+    std::vector<long long>().swap(kc.apos[sm]);
+    std::vector<double>().swap(kc.aval[sm]);
+    std::vector<int>().swap(kc.adiag[sm]);
   }
-  std::vector<Ent>().swap(ents);
   P.nnz = (long long)apos.size();
   // work list of the solve-block kernel: (supernode, 64-row tile, 32-column block)
   std::vector<RfItem> out;
