@@ -366,7 +366,7 @@ k_init_decide(int want, const SimSeg* __restrict__ seg, const double* __restrict
 // ---------------------------------------------------------------------------
 // Gradient gather of iteration k (section 4, Eq. PDgrad2): x_k = x_{k-1} +
 // alpha d (in place), s = x_k - x_{k-1}, grad = M/h^2 (x_k - y) + sum of
-// element contributions (incidence lists, fixed order), t = grad -
+// element-block partials (block order, fixed), t = grad -
 // grad_{k-1} (in place); s and t go to the candidate ring slot. The same pass
 // forms every dot product the two-loop recursion needs, so that the
 // recursion runs on scalars (Gram form): dots [0..3] = t.s, s.s, t.t, g.g
@@ -406,7 +406,7 @@ k_gather(int probe, const BlockSeg* __restrict__ blk, int nb, size_t n3, int slo
   const int i = sg.a0 + (threadIdx.x >> 2), gl = threadIdx.x & 3;
   const bool live = i < sg.a1, own = live && gl < 3;
   const size_t ic = 3 * (size_t)(live ? i : sg.a0) + (gl < 3 ? gl : 0);
-  // loads that do not depend on the incidence sums go first
+  // loads that do not depend on the partial sums go first
   double mi = 0.0, yy = 0.0, xp = 0.0, dd = 0.0, gp = 0.0;
   double sj[SL], tj[SL];
 #pragma unroll

@@ -187,3 +187,36 @@ def test_device_factor_at_prepare(sched):
     assert _eps(x2, x1, w.rest) <= 1e-11
     s.close()
     ref.close()
+
+
+def test_refactor_with_colliders_and_mixed_precision():
+    """The cantilever falling onto a tilted plane (section 4.3: the contact
+    terms are not in A) after A is refactored for h = 1/45: each of 15 steps,
+    from the oracle's state, against the oracle's step at that h (FP64:
+    1e-9 with identical trial counts; the mixed path prepared with the device
+    factorisation: 1e-4)."""
+    w = W.workload_cantilever(0)
+    planes = W.cantilever_ground_planes()
+    k = 1e5
+    h2 = 1.0 / 45.0
+    m = oracle.build_model(w.rest, w.tets, w.pinned, w.materials, w.tet_mat, h2, w.gravity,
+                           planes=planes, coll_k=k)
+    s = qnsim.sim_from_workload(w)
+    s.set_colliders(planes, k)
+    s.refactor(h2)
+    sm = qnsim.sim_from_workload(w, precision=qnsim.QNSIM_MIXED, device_factor=1, prepare=False)
+    sm.prepare(h2)
+    sm.set_colliders(planes, k)
+    xo, vo = w.x0.copy(), w.v0.copy()
+    for step in range(15):
+        r = oracle.step(m, xo, vo)
+        x1, _, st = s.step(xo, vo, h2)
+        assert st["ls_trials"] == r.ls_trials, f"step {step}"
+        assert _eps(x1, r.x, w.rest) <= 1e-9, f"step {step}"
+        x2, _, _ = sm.step(xo, vo, h2)
+        assert _eps(x2, r.x, w.rest) <= 1e-4, f"mixed step {step}"
+        xo, vo = r.x, r.v
+    n, c = planes[0, :3], planes[0, 3]
+    assert (xo[m.free] @ n - c).min() < 0.001  # the bar is on the plane
+    s.close()
+    sm.close()
