@@ -350,6 +350,17 @@ def refactor_run(args, torch, W, qnsim):
     return out
 
 
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(args, W):
     """The FP64 oracle on a bounded sample: one step of the Neo-Hookean block."""
     import numpy as np  # noqa: F401
@@ -370,10 +381,22 @@ def cpu_baseline(args, W):
         r = oracle.step(m, x, v)
         x, v = r.x, r.v
     dt = time.perf_counter() - t0
-    log(f"[bench] oracle: build {build:.1f}s, {steps} step(s) in {dt:.1f}s")
+    # the same oracle on one thread (BLAS/LAPACK pools limited to 1), one step
+    one = None
+    try:
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            oracle.step(m, w.x0, w.v0)
+            one = 1.0 / (time.perf_counter() - t0)
+    except Exception:
+        one = None
+    log(f"[bench] oracle: build {build:.1f}s, {steps} step(s) in {dt:.1f}s"
+        + (f"; one thread {1.0 / one:.1f}s per step" if one else ""))
     return {"value": steps / dt, "unit": "timesteps/s", "cores": int(cores), "kind": "oracle",
             "sample": f"{steps} step(s) of the Neo-Hookean 40^3 block (384,000 tets) after an "
-                      f"untimed {build:.1f}s model build and banded Cholesky factorisation"}
+                      f"untimed {build:.1f}s model build and banded Cholesky factorisation",
+            "value_one_thread": one, "cpu": _cpu_model()}
 
 
 def main():
