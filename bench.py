@@ -394,7 +394,7 @@ def cpu_baseline(args, W):
     log(f"[bench] oracle: build {build:.1f}s, {steps} step(s) in {dt:.1f}s"
         + (f"; one thread {1.0 / one:.1f}s per step" if one else ""))
     return {"value": steps / dt, "unit": "timesteps/s", "cores": int(cores), "kind": "oracle",
-            "sample": f"{steps} step(s) of the Neo-Hookean 40^3 block (384,000 tets) after an "
+            "sample": f"{steps} step(s) of the Neo-Hookean {args.n}^3 block ({w.n_tets:,} tets) after an "
                       f"untimed {build:.1f}s model build and banded Cholesky factorisation",
             "value_one_thread": one, "cpu": _cpu_model()}
 
