@@ -138,6 +138,15 @@ def batched_run(args, torch, W, qnsim, precision):
         f"{p.info()['used_bytes'] / 1e9:.2f} GB")
     for _ in range(args.warmup):
         p.step(ids)
+    tune = None
+    if not args.no_tune:
+        t_tu = time.perf_counter()
+        tiles, tms = p.tune(reps=3)
+        tune = dict(elem_tile=tiles[0], step_ms={t: m for t, m in zip((128, 256, 512), tms[0])},
+                    seconds=time.perf_counter() - t_tu)
+        log(f"[bench] element-tile tune: {tiles[0]} (ms per batched step "
+            + ", ".join(f"{t}: {m:.2f}" for t, m in tune["step_ms"].items()) + f"; {tune['seconds']:.1f}s)")
+        p.step(ids)
     torch.cuda.synchronize()
     evals, trials = 0, 0
     t0 = time.perf_counter()
@@ -161,7 +170,7 @@ def batched_run(args, torch, W, qnsim, precision):
     log(f"[bench] batch kernels: " + ", ".join(
         f"{k} {v['ms']:.3f} ms" + (f" ({v['GBs']:.0f} GB/s)" if "GBs" in v else "") for k, v in kern.items()))
     res = dict(meshes=len(ws), tets=T, verts=sum(w.n_verts for w in ws), nnz_L=info["nnz_L"],
-               kernels=kern, precision="mixed" if precision else "f64",
+               kernels=kern, precision="mixed" if precision else "f64", tune=tune,
                batched_steps_per_s=args.batch_steps / dt,
                mesh_steps_per_s=args.batch_steps * len(ws) / dt,
                tet_evals_per_s=evals / dt, ms_per_batched_step=1e3 * dt / args.batch_steps,
@@ -412,6 +421,8 @@ def main():
                     help="skip the convergence comparison of the direction methods")
     ap.add_argument("--no-refactor", action="store_true",
                     help="skip the device refactorisation measurement")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the default element tile in the batched run")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the extra mixed-precision Neo-Hookean run")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,

@@ -249,6 +249,7 @@ int qnsim_options_default(qnsim_options* o) {
   o->direction = QNSIM_DIR_LBFGS;
   o->cheb_delay = 10;
   o->cheb_rho = 0.9;
+  o->elem_tile = 256;
   o->gamma = 0.3;
   o->backtrack = 0.5;
   o->fit_lo = 0.5;
@@ -275,7 +276,8 @@ int qnsim_create(const qnsim_options* opts, qnsim_t** out) {
       (o.direction != QNSIM_DIR_LBFGS && o.direction != QNSIM_DIR_CHEBYSHEV) ||
       (o.direction == QNSIM_DIR_CHEBYSHEV &&
        (o.history != 0 || o.cheb_delay < 1 || !(o.cheb_rho > 0.0 && o.cheb_rho < 1.0))) ||
-      !finite_all(o.gravity, 3) || (o.device_factor != 0 && o.device_factor != 1))
+      !finite_all(o.gravity, 3) || (o.device_factor != 0 && o.device_factor != 1) ||
+      (o.elem_tile != 0 && o.elem_tile != 128 && o.elem_tile != 256 && o.elem_tile != 512))
     return QNSIM_E_INVALID;
   qnsim_t* c = new (std::nothrow) qnsim();
   if (!c) return QNSIM_E_NOMEM;

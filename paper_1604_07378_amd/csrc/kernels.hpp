@@ -108,6 +108,11 @@ struct BlockSeg {
 // simulations whose tets mix types (generic evaluation).
 constexpr int kElemKinds = 7;
 
+// Element-pass tiles (tets, and free vertices of the inertia term, per
+// block); the kernel is compiled for each.
+constexpr int kElemTiles[3] = {128, 256, 512};
+constexpr int kMaxElemTile = 512;
+
 struct Level {
   int fw_begin, fw_end;  // forward work items of this level
   int bw_begin, bw_end;  // backward work items of this level
@@ -160,6 +165,7 @@ struct DeviceMesh {
   int* vsim = nullptr;        // n: simulation of each internal vertex
   int* run = nullptr;         // S: simulation takes part in the current step
   BlockSeg* eblk = nullptr;   // element-pass blocks (slot = own index)
+  int elem_tile = 256;        // tets per element-pass block
   // element-pass blocks by the material type of their simulation (kind 5:
   // simulations of several types), one launch each when the batch mixes types
   BlockSeg* eblk_kind[kElemKinds] = {};

@@ -10,6 +10,7 @@
 
 #include "../../include/qnsim.h"
 #include "host.hpp"
+#include "kernels.hpp"
 #include "partials.hpp"
 
 namespace qn {
@@ -89,14 +90,14 @@ int build_partials(const std::vector<int>& tv, int T, int nf, const std::vector<
   std::vector<std::vector<int>> verts(nblk);
   Ctx q{tv.data(), nf, blk_t0.data(), blk_t1.data(), &verts, nullptr, nullptr, nullptr, nullptr};
   for (int b = 0; b < nblk; ++b)
-    if (blk_t1[b] - blk_t0[b] > 256 || blk_t0[b] < 0 || blk_t1[b] > T) {
+    if (blk_t1[b] - blk_t0[b] > kMaxElemTile || blk_t0[b] < 0 || blk_t1[b] > T) {
       err = "partials: bad element block";
       return QNSIM_E_DEVICE;
     }
   parallel_for(nblk, 16, &q, blk_vertices);
   P.p0.assign(nblk + 1, 0);
   for (int b = 0; b < nblk; ++b) {
-    if (verts[b].size() > 1024) {
+    if (verts[b].size() > 4 * (size_t)kMaxElemTile) {
       err = "partials: too many in one block";
       return QNSIM_E_DEVICE;
     }

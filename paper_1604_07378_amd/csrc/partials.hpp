@@ -15,7 +15,8 @@ struct Partials {
 };
 
 // Tables for element blocks [blk_t0[b], blk_t1[b]) of the internal tets tv
-// (T x 4, free vertices < nf first); 0 or a negative QNSIM_E_* code with err.
+// (T x 4, free vertices < nf first), at most 512 tets each; 0 or a negative
+// QNSIM_E_* code with err.
 int build_partials(const std::vector<int>& tv, int T, int nf, const std::vector<int>& blk_t0,
                    const std::vector<int>& blk_t1, Partials& P, std::string& err);
 

@@ -613,6 +613,7 @@ int qnsim_pool_get_info(qnsim_pool_t* p, qnsim_pool_info* info) {
   }
   for (auto& g : p->groups)
     if (g->live > 0) info->groups++;
+  info->groups_made = (int32_t)p->groups.size();
   info->serving = p->serving ? 1 : 0;
   info->budget_bytes = p->budget;
   info->used_bytes = p->used;
@@ -670,6 +671,104 @@ int qnsim_pool_set_h(qnsim_pool_t* p, double h, double* device_ms) {
     }
   p->h = h;
   if (device_ms) *device_ms = total;
+  return QNSIM_OK;
+}
+
+int qnsim_pool_tune(qnsim_pool_t* p, int32_t candidates, int32_t reps, int32_t n_groups,
+                    int32_t* tiles, double* step_ms) {
+  if (!p) return QNSIM_E_INVALID;
+  if (candidates == 0) candidates = 7;
+  if (candidates < 0 || candidates > 7)
+    return pfail(p, QNSIM_E_INVALID, "candidates: a mask of bits 1 (128), 2 (256), 4 (512)");
+  if (reps < 1 || reps > 1000 || n_groups < 0 || (n_groups > 0 && !tiles))
+    return pfail(p, QNSIM_E_INVALID, "reps must be 1..1000 and tiles given for n_groups > 0");
+  std::unique_lock<std::mutex> lk(p->mu);
+  if (p->serving) return pfail(p, QNSIM_E_STATE, "the request loop is running");
+  p->cv.wait(lk, [&] {
+    for (auto& g : p->groups)
+      if (g && g->busy) return false;
+    return true;
+  });
+  if (hipSetDevice(p->opt.device) != hipSuccess) return pfail(p, QNSIM_E_DEVICE, "hipSetDevice failed");
+  for (int gi = 0; gi < n_groups; ++gi) {
+    tiles[gi] = 0;
+    if (step_ms)
+      for (int k = 0; k < 3; ++k) step_ms[3 * gi + k] = NAN;
+  }
+  const StepParams prm = pool_params(p);
+  std::string err;
+  for (int gi = 0; gi < (int)p->groups.size(); ++gi) {
+    PoolGroup& g = *p->groups[gi];
+    if (g.live == 0) continue;
+    std::vector<const qnsim*> members;
+    bool refactored = false;
+    for (int id : g.ids) {
+      members.push_back(p->sims[id].c);
+      refactored = refactored || p->sims[id].c->factor_on_device;
+    }
+    // the steps being timed run on a copy of the members' states
+    const size_t bytes = 3 * (size_t)g.D.n * sizeof(double);
+    double *tx = nullptr, *tvl = nullptr;
+    if (hipMalloc((void**)&tx, bytes) != hipSuccess || hipMalloc((void**)&tvl, bytes) != hipSuccess) {
+      if (tx) (void)hipFree(tx);
+      return pfail(p, QNSIM_E_NOMEM, "tuning state allocation failed");
+    }
+    DeviceMesh spare, cand;  // the fastest rebuilt mesh so far, the one being timed
+    int best_tile = g.D.elem_tile;
+    double best_ms = INFINITY;
+    int rc = QNSIM_OK;
+    for (int k = 0; k < 3 && !rc; ++k) {
+      if (!(candidates & (1 << k))) continue;
+      const int tile = kElemTiles[k];
+      DeviceMesh* D = &g.D;
+      if (tile != g.D.elem_tile) {
+        qnsim_options o = p->opt;
+        o.elem_tile = tile;
+        rc = upload_sims(members, o, p->h, cand, err);
+        // host factor values belong to an earlier h after a time-step change
+        if (!rc && refactored) rc = dev_refactor_mesh(members, cand, p->h, nullptr, err);
+        if (rc) break;
+        D = &cand;
+      }
+      hipStream_t st = (hipStream_t)D->stream;
+      std::vector<int> all(D->S, 1);
+      rc = dev_set_run(*D, all.data(), D->stream, err);
+      if (!rc && (hipMemcpyAsync(tx, g.xs, bytes, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+                  hipMemcpyAsync(tvl, g.vs, bytes, hipMemcpyDeviceToDevice, st) != hipSuccess)) {
+        err = "tuning state copy failed";
+        rc = QNSIM_E_DEVICE;
+      }
+      // one untimed step (graph capture), then reps timed steps
+      if (!rc) rc = dev_step(*D, prm, tx, tvl, nullptr, tx, tvl, D->stream, false, err);
+      const double t0 = now_s();
+      for (int r = 0; r < reps && !rc; ++r)
+        rc = dev_step(*D, prm, tx, tvl, nullptr, tx, tvl, D->stream, false, err);
+      if (rc) break;
+      const double ms = (now_s() - t0) * 1e3 / reps;
+      if (step_ms && gi < n_groups) step_ms[3 * gi + k] = ms;
+      if (ms < best_ms) {
+        best_ms = ms;
+        best_tile = tile;
+        if (D == &cand) std::swap(spare, cand);
+      }
+      dev_free(cand);
+    }
+    (void)hipFree(tx);
+    (void)hipFree(tvl);
+    if (rc) {
+      dev_free(cand);
+      dev_free(spare);
+      return pfail(p, rc, err);
+    }
+    if (best_tile != g.D.elem_tile) {
+      const int64_t old = (int64_t)g.D.bytes;
+      std::swap(g.D, spare);
+      p->used += (int64_t)g.D.bytes - old;
+      g.bytes += (int64_t)g.D.bytes - old;
+    }
+    dev_free(spare);
+    if (gi < n_groups) tiles[gi] = g.D.elem_tile;
+  }
   return QNSIM_OK;
 }
 

@@ -66,6 +66,24 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return r;
 }
 
+// Block sum over NW waves in a fixed order (NW = 4: as block_sum); result in
+// thread 0.
+template <int NW>
+__device__ __forceinline__ double block_sum_t(double v, double* sh) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0) {
+    if (NW == 2) r = sh[0] + sh[1];
+    else if (NW == 4) r = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+    else r = ((sh[0] + sh[1]) + (sh[2] + sh[3])) + ((sh[4] + sh[5]) + (sh[6] + sh[7]));
+  }
+  return r;
+}
+
 // Sum of n partials in a fixed order; result valid in every thread.
 __device__ __forceinline__ double sum_partials(const double* p, int n, double* sh) {
   double v = 0.0;
@@ -211,8 +229,8 @@ k_copy_retry(int nf, const int* __restrict__ vsim, const Ctl* __restrict__ ctl,
 // otherwise. want: the phase the block's simulation must be in (-1: always;
 // probes).
 // ---------------------------------------------------------------------------
-template <int TYPE, typename R>
-__global__ void __launch_bounds__(BS)
+template <int TYPE, typename R, int NT>
+__global__ void __launch_bounds__(NT)
 k_elem(int want, int trial, const BlockSeg* __restrict__ blk, int T, int nf,
        const int* __restrict__ tv, const double* __restrict__ Bm,
        const double* __restrict__ vol, const int* __restrict__ tmat,
@@ -224,7 +242,7 @@ k_elem(int want, int trial, const BlockSeg* __restrict__ blk, int T, int nf,
        const int* __restrict__ cset, const double* __restrict__ planes, double coll_k) {
   __shared__ double sh[16];
   // the block's gradient contributions, summed per vertex at the end
-  __shared__ __align__(16) R sfel[BS * 12];
+  __shared__ __align__(16) R sfel[NT * 12];
   const BlockSeg sg = blk[xcd_block()];
   double alpha = 0.0;
   if (want >= 0) {
@@ -297,7 +315,7 @@ k_elem(int want, int trial, const BlockSeg* __restrict__ blk, int T, int nf,
   __syncthreads();
   // one partial per distinct free vertex of the block: its contributions in
   // (tet, slot) order, summed in FP64 in every mode
-  for (int j = threadIdx.x; j < sg.np; j += BS) {
+  for (int j = threadIdx.x; j < sg.np; j += NT) {
     const int g = sg.p0 + j;
     const int k0 = lc_ptr[g], k1 = lc_ptr[g + 1];
     double f0 = 0.0, f1 = 0.0, f2 = 0.0;
@@ -333,7 +351,7 @@ k_elem(int want, int trial, const BlockSeg* __restrict__ blk, int T, int nf,
       }
     }
   }
-  double b = block_sum(e, sh);
+  double b = block_sum_t<NT / 64>(e, sh);
   if (threadIdx.x == 0 && part) part[sg.slot] = b;
 }
 
@@ -923,21 +941,21 @@ k_check_inverted(const BlockSeg* __restrict__ blk, const int* __restrict__ run, 
                  const double* __restrict__ X, SimStat* __restrict__ stat) {
   const BlockSeg sg = blk[blockIdx.x];
   if (!run[sg.sim]) return;
-  const int t = sg.a0 + threadIdx.x;
-  if (t >= sg.a1) return;
-  const int ty = mats[tmat ? tmat[t] : 0].type;
-  if (ty != 0 && ty != 5) return;  // log J terms: Neo-Hookean, Mooney-Rivlin
-  const int4 iv = reinterpret_cast<const int4*>(tv)[t];
-  const int vid[4] = {iv.x, iv.y, iv.z, iv.w};
-  M3<double> F;
-  for (int i = 0; i < 3; ++i)
-    for (int k = 0; k < 3; ++k) {
-      double s = 0.0;
-      for (int j = 0; j < 3; ++j)
-        s += (X[3 * (size_t)vid[j + 1] + i] - X[3 * (size_t)vid[0] + i]) * Bm[(size_t)(3 * j + k) * T + t];
-      F.a[i][k] = s;
-    }
-  if (!(det3(F) > 0.0)) stat[sg.sim].inverted = 1;  // every writer stores the same value
+  for (int t = sg.a0 + threadIdx.x; t < sg.a1; t += BS) {  // element blocks hold up to 512 tets
+    const int ty = mats[tmat ? tmat[t] : 0].type;
+    if (ty != 0 && ty != 5) continue;  // log J terms: Neo-Hookean, Mooney-Rivlin
+    const int4 iv = reinterpret_cast<const int4*>(tv)[t];
+    const int vid[4] = {iv.x, iv.y, iv.z, iv.w};
+    M3<double> F;
+    for (int i = 0; i < 3; ++i)
+      for (int k = 0; k < 3; ++k) {
+        double s = 0.0;
+        for (int j = 0; j < 3; ++j)
+          s += (X[3 * (size_t)vid[j + 1] + i] - X[3 * (size_t)vid[0] + i]) * Bm[(size_t)(3 * j + k) * T + t];
+        F.a[i][k] = s;
+      }
+    if (!(det3(F) > 0.0)) stat[sg.sim].inverted = 1;  // every writer stores the same value
+  }
 }
 
 // Control state for timing the kernels in isolation: every simulation in a
@@ -998,18 +1016,24 @@ Lists lists_of(const DeviceMesh& D) {
 void launch_elem(DeviceMesh& D, hipStream_t st, int want, int trial, double* part,
                  double* psi_out) {
   const double inv2h2 = 0.5 / (D.h * D.h);
-#define QN_ELEM(TY, BLK, GRID)                                                                \
+#define QN_ELEM_NT(TY, NT, BLK, GRID)                                                         \
   do {                                                                                       \
     if (D.mixed)                                                                             \
-      hipLaunchKernelGGL((k_elem<TY, float>), dim3(GRID), dim3(BS), 0, st, want, trial,       \
+      hipLaunchKernelGGL((k_elem<TY, float, NT>), dim3(GRID), dim3(NT), 0, st, want, trial,   \
                          BLK, D.T, D.nf, D.tv, D.Bm, D.vol, D.tmat, D.mats, D.mass, D.X,      \
                          D.d, D.y, inv2h2, D.ctl, D.lc_ptr, D.lc_idx, D.bpart, part,          \
                          psi_out, D.nplanes ? D.cset : nullptr, D.planes, D.coll_k);         \
     else                                                                                     \
-      hipLaunchKernelGGL((k_elem<TY, double>), dim3(GRID), dim3(BS), 0, st, want, trial,      \
+      hipLaunchKernelGGL((k_elem<TY, double, NT>), dim3(GRID), dim3(NT), 0, st, want, trial,  \
                          BLK, D.T, D.nf, D.tv, D.Bm, D.vol, D.tmat, D.mats, D.mass, D.X,      \
                          D.d, D.y, inv2h2, D.ctl, D.lc_ptr, D.lc_idx, D.bpart, part,          \
                          psi_out, D.nplanes ? D.cset : nullptr, D.planes, D.coll_k);         \
+  } while (0)
+#define QN_ELEM(TY, BLK, GRID)                                                                \
+  do {                                                                                       \
+    if (D.elem_tile == 128) QN_ELEM_NT(TY, 128, BLK, GRID);                                  \
+    else if (D.elem_tile == 512) QN_ELEM_NT(TY, 512, BLK, GRID);                             \
+    else QN_ELEM_NT(TY, 256, BLK, GRID);                                                     \
   } while (0)
   auto one = [&](int type, const BlockSeg* blk, int grid) {
     switch (type) {
@@ -1023,6 +1047,7 @@ void launch_elem(DeviceMesh& D, hipStream_t st, int want, int trial, double* par
     }
   };
 #undef QN_ELEM
+#undef QN_ELEM_NT
   const Lists L = lists_of(D);
   for (int k = 0; k < kElemKinds; ++k)
     if (L.elem_n[k] > 0) one(k < kElemKinds - 1 ? k : -1, L.elem[k], L.elem_n[k]);

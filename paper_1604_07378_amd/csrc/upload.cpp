@@ -204,14 +204,16 @@ int upload_sims(const std::vector<const qnsim*>& sims, const qnsim_options& opt,
     for (const Supernode& sn : Fp->sn) blk_src.push_back(Fp->Binv.data() + sn.val_off);
   }
   const Factor& F = *Fp;
-  // element-pass force partials of the element blocks (256 tets, per
+  // element-pass force partials of the element blocks (ET tets, per
   // simulation from its first tet, as laid out in the block tables below)
+  const int ET = opt.elem_tile > 0 ? opt.elem_tile : 256;
+  if (ET != 128 && ET != 256 && ET != 512) FAIL(QNSIM_E_INVALID, "element tile must be 128, 256 or 512");
   std::vector<int> eb_t0, eb_t1;
   for (int s = 0; s < S; ++s) {
-    const int ne = std::max((sims[s]->T + 255) / 256, (sims[s]->nf + 255) / 256);
+    const int ne = std::max((sims[s]->T + ET - 1) / ET, (sims[s]->nf + ET - 1) / ET);
     for (int j = 0; j < ne; ++j) {
-      eb_t0.push_back(std::min(t0[s] + sims[s]->T, t0[s] + 256 * j));
-      eb_t1.push_back(std::min(t0[s] + sims[s]->T, t0[s] + 256 * (j + 1)));
+      eb_t0.push_back(std::min(t0[s] + sims[s]->T, t0[s] + ET * j));
+      eb_t1.push_back(std::min(t0[s] + sims[s]->T, t0[s] + ET * (j + 1)));
     }
   }
   const int nblk = (int)eb_t0.size();
@@ -558,6 +560,7 @@ int upload_sims(const std::vector<const qnsim*>& sims, const qnsim_options& opt,
   UP(D.mats, dm);
   UP(D.mass, mass);
   D.n_part = n_part;
+  D.elem_tile = ET;
   D.bp_w = parts.bp_w;
   UP(D.bp_tab, parts.bp_tab);
   UP(D.lc_ptr, parts.lc_ptr);
@@ -621,13 +624,13 @@ int upload_sims(const std::vector<const qnsim*>& sims, const qnsim_options& opt,
       const qnsim* c = sims[s];
       SimSeg& g = seg[s];
       g.vf0 = vf0[s]; g.nf = c->nf; g.t0 = t0[s]; g.T = c->T;
-      const int ne = std::max((c->T + 255) / 256, (c->nf + 255) / 256);
+      const int ne = std::max((c->T + ET - 1) / ET, (c->nf + ET - 1) / ET);
       g.eb0 = (int)eb.size();
       for (int j = 0; j < ne; ++j)
-        eb.push_back(mk(s, std::min(t0[s] + c->T, t0[s] + 256 * j),
-                        std::min(t0[s] + c->T, t0[s] + 256 * (j + 1)),
-                        std::min(vf0[s] + c->nf, vf0[s] + 256 * j),
-                        std::min(vf0[s] + c->nf, vf0[s] + 256 * (j + 1))));
+        eb.push_back(mk(s, std::min(t0[s] + c->T, t0[s] + ET * j),
+                        std::min(t0[s] + c->T, t0[s] + ET * (j + 1)),
+                        std::min(vf0[s] + c->nf, vf0[s] + ET * j),
+                        std::min(vf0[s] + c->nf, vf0[s] + ET * (j + 1))));
       g.eb1 = (int)eb.size();
       g.gb0 = (int)gb.size();
       for (int v = 0; v < c->nf; v += 64)
@@ -655,13 +658,13 @@ int upload_sims(const std::vector<const qnsim*>& sims, const qnsim_options& opt,
       if (eb[b].a0 != eb_t0[b] || eb[b].a1 != eb_t1[b]) FAIL(QNSIM_E_DEVICE, "partials: element blocks differ");
       eb[b].p0 = eb_p0[b];
       eb[b].np = eb_p0[b + 1] - eb_p0[b];
-      if (eb[b].np > 4 * 256) FAIL(QNSIM_E_DEVICE, "partials: too many in one block");
+      if (eb[b].np > 4 * ET) FAIL(QNSIM_E_DEVICE, "partials: too many in one block");
     }
     // self-check: every tet, free vertex and entry in exactly one block of its simulation
     {
       std::vector<char> ct(T, 0), cv(nf, 0), cg(nf, 0), ce(3 * (size_t)nf, 0), cr(3 * (size_t)nf, 0);
       for (const BlockSeg& x : eb) {
-        if (x.a1 - x.a0 > 256 || x.b1 - x.b0 > 256) FAIL(QNSIM_E_DEVICE, "blocks: element block too large");
+        if (x.a1 - x.a0 > ET || x.b1 - x.b0 > ET) FAIL(QNSIM_E_DEVICE, "blocks: element block too large");
         for (int t = x.a0; t < x.a1; ++t) { if (t < t0[x.sim] || t >= t0[x.sim] + sims[x.sim]->T) FAIL(QNSIM_E_DEVICE, "blocks: tet outside its simulation"); ct[t]++; }
         for (int v = x.b0; v < x.b1; ++v) { if (vsim[v] != x.sim) FAIL(QNSIM_E_DEVICE, "blocks: vertex outside its simulation"); cv[v]++; }
       }

@@ -47,7 +47,7 @@ class Options(ctypes.Structure):
                 ("step_graph", ctypes.c_int32), ("trials_per_cycle", ctypes.c_int32),
                 ("direction", ctypes.c_int32), ("cheb_delay", ctypes.c_int32),
                 ("cheb_rho", ctypes.c_double), ("device_factor", ctypes.c_int32),
-                ("reserved_opt", ctypes.c_int32)]
+                ("elem_tile", ctypes.c_int32)]
 
 
 class MaterialC(ctypes.Structure):
@@ -94,7 +94,8 @@ class PoolInfo(ctypes.Structure):
                 ("groups", ctypes.c_int32), ("serving", ctypes.c_int32),
                 ("budget_bytes", ctypes.c_int64), ("used_bytes", ctypes.c_int64),
                 ("steps_done", ctypes.c_int64), ("batches_done", ctypes.c_int64),
-                ("nnz_L", ctypes.c_int64), ("n_free", ctypes.c_int64), ("n_tets", ctypes.c_int64)]
+                ("nnz_L", ctypes.c_int64), ("n_free", ctypes.c_int64), ("n_tets", ctypes.c_int64),
+                ("groups_made", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -148,6 +149,7 @@ SIGNATURES = {
     "qnsim_pool_last_error": (ctypes.c_char_p, [_P]),
     "qnsim_pool_time_kernel": (ctypes.c_int, [_P, _I, _I, _I, ctypes.POINTER(_D)]),
     "qnsim_pool_set_h": (ctypes.c_int, [_P, _D, ctypes.POINTER(_D)]),
+    "qnsim_pool_tune": (ctypes.c_int, [_P, _I, _I, _I, ctypes.POINTER(_I), ctypes.POINTER(_D)]),
 }
 
 _lib = None
@@ -535,6 +537,19 @@ class Pool:
         ms = ctypes.c_double()
         self._check(self._lib.qnsim_pool_set_h(self._p, float(h), ctypes.byref(ms)))
         return ms.value
+
+    def tune(self, reps: int = 3, candidates=(128, 256, 512)):
+        """Element-tile autotuning of every resident group among the candidate
+        tiles: returns the chosen tile per group (admission order, 0 for a
+        group with no resident member) and the measured milliseconds per
+        batched step for the tiles 128, 256, 512 (groups x 3, NaN where not
+        measured)."""
+        mask = sum({128: 1, 256: 2, 512: 4}[int(t)] for t in set(candidates))
+        n = self.info()["groups_made"]
+        tiles = (_I * max(n, 1))()
+        ms = (_D * (3 * max(n, 1)))()
+        self._check(self._lib.qnsim_pool_tune(self._p, mask, int(reps), n, tiles, ms))
+        return [int(tiles[i]) for i in range(n)], [[float(ms[3 * i + k]) for k in range(3)] for i in range(n)]
 
     def info(self) -> dict:
         i = PoolInfo()

@@ -107,9 +107,9 @@ def test_prefactored_solve(dims, sched):
     assert np.abs(r - r_ref).max() <= 1e-12 * np.abs(r_ref).max()
 
 
-def _trajectory_parity(w, steps, tol=1e-9, history=5, check_stats=True, sched="default"):
+def _trajectory_parity(w, steps, tol=1e-9, history=5, check_stats=True, sched="default", **opt):
     m = _model(w)
-    s = qnsim.sim_from_workload(w, history=history, **SCHEDULES[sched])
+    s = qnsim.sim_from_workload(w, history=history, **SCHEDULES[sched], **opt)
     x_o, v_o = w.x0.copy(), w.v0.copy()
     x_g, v_g = w.x0.copy(), w.v0.copy()
     worst = 0.0
@@ -145,6 +145,15 @@ def test_cantilever_other_jitter_seeds(seed):
 @pytest.mark.parametrize("kind", [W.STVK, W.SPLINE, W.COROTATED, W.POLYNOMIAL, W.MOONEY_RIVLIN])
 def test_cantilever_materials(kind):
     _trajectory_parity(W.workload_cantilever(0, kind=kind), 30)
+
+
+@pytest.mark.parametrize("tile", [128, 512])
+@pytest.mark.parametrize("kind", [W.NEOHOOKEAN, W.STVK, W.MOONEY_RIVLIN])
+def test_element_tiles(kind, tile):
+    """Element-pass blocks of 128 and 512 tets: the 540-tet cantilever spans
+    five blocks with a ragged tail, or one full block and a partial one."""
+    _trajectory_parity(W.workload_cantilever(0, kind=kind), 20, elem_tile=tile)
+    _trajectory_parity(W.workload_mixed_cantilever(0), 5, elem_tile=tile)
 
 
 @pytest.mark.parametrize("history", [0, 1, 2, 8])

@@ -283,3 +283,70 @@ def test_pool_time_step_change():
     s.close()
     p.close()
     fresh.close()
+
+
+def _alone_from(w, x, v, steps, h=None, **opt):
+    """States after each of `steps` steps of w alone from (x, v)."""
+    h = w.h if h is None else h
+    s = qnsim.sim_from_workload(w, dense_top=0, level_merge=0, prepare=False, **opt)
+    s.prepare(h)
+    out = []
+    for _ in range(steps):
+        x, v, _ = s.step(x, v, h)
+        out.append((x.copy(), v.copy()))
+    s.close()
+    return out
+
+
+def test_pool_tune_element_tiles():
+    """qnsim_pool_tune on six mixed-material simulations in two groups.
+    Restricted to 512, both groups are rebuilt, the members' states stay as
+    they were, and later steps equal each simulation alone with elem_tile 512
+    bit for bit; a full tune picks a tile per group, again equal to alone
+    with that tile; after a time-step change (A refactored on the device) a
+    rebuild to 128 steps as the simulation alone at the new h, to rounding."""
+    kinds = [W.NEOHOOKEAN, W.STVK, W.MOONEY_RIVLIN, W.SPLINE, W.COROTATED, W.NEOHOOKEAN]
+    ws = [W.workload_block(kinds[i], dims=(4 + i % 3, 3 + i, 4), prestretch_seed=60 + i)
+          for i in range(6)]
+    p, ids = _pool(ws, group=3)
+    p.step(ids)
+    before = [p.get_state(i) for i in ids]
+    tiles, ms = p.tune(reps=2, candidates=(512,))
+    assert tiles == [512, 512]
+    for g in range(2):
+        assert np.isnan(ms[g][0]) and np.isnan(ms[g][1]) and ms[g][2] > 0.0
+    for j, i in enumerate(ids):
+        x, v = p.get_state(i)
+        assert np.array_equal(x, before[j][0]) and np.array_equal(v, before[j][1])
+    ref = [_alone_from(w, *before[j], 3, elem_tile=512) for j, w in enumerate(ws)]
+    for k in range(3):
+        p.step(ids)
+        for j in range(6):
+            x, v = p.get_state(ids[j])
+            assert np.array_equal(x, ref[j][k][0]), f"tile 512, sim {j} step {k}"
+            assert np.array_equal(v, ref[j][k][1])
+    start = [p.get_state(i) for i in ids]
+    tiles, ms = p.tune(reps=2)
+    print(f"tune: tiles {tiles}, ms per step {ms}", flush=True)
+    assert all(t in (128, 256, 512) for t in tiles)
+    assert all(np.isfinite(m).all() and min(m) > 0.0 for m in ms)
+    for j, i in enumerate(ids):
+        assert np.array_equal(p.get_state(i)[0], start[j][0])
+    ref = [_alone_from(w, *start[j], 2, elem_tile=tiles[j // 3]) for j, w in enumerate(ws)]
+    for k in range(2):
+        p.step(ids)
+        for j in range(6):
+            x, _ = p.get_state(ids[j])
+            assert np.array_equal(x, ref[j][k][0]), f"tile {tiles[j // 3]}, sim {j} step {k}"
+    h2 = 1.0 / 60.0
+    p.set_h(h2)
+    start = [p.get_state(i) for i in ids]
+    tiles, _ = p.tune(reps=1, candidates=(128,))
+    assert tiles == [128, 128]
+    ref = [_alone_from(w, *start[j], 2, h=h2, elem_tile=128) for j, w in enumerate(ws)]
+    for k in range(2):
+        p.step(ids)
+        for j in range(6):
+            x, _ = p.get_state(ids[j])
+            assert _eps(x, ref[j][k][0], ws[j].rest) <= 1e-11, f"h 1/60, sim {j} step {k}"
+    p.close()
