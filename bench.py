@@ -359,6 +359,29 @@ def refactor_run(args, torch, W, qnsim):
     return out
 
 
+def tune_run(args, torch, W, qnsim):
+    """qnsim_tune on the Neo-Hookean block: the four solve schedules, then the
+    three element tiles with the fastest schedule (informational: the headline
+    runs keep the default options)."""
+    w = W.workload_block(W.NEOHOOKEAN, n=args.n)
+    s = qnsim.sim_from_workload(w, **args.overrides)
+    import numpy as np
+    x = torch.from_numpy(np.ascontiguousarray(w.x0, dtype=np.float64)).cuda()
+    v = torch.from_numpy(np.ascontiguousarray(w.v0, dtype=np.float64)).cuda()
+    t0 = time.perf_counter()
+    info = s.tune(x, v, w.h, reps=5)
+    info["seconds"] = time.perf_counter() - t0
+    s.close()
+    names = ["levels", "subtrees", "merged", "merged+top"]
+    log(f"[bench] tune block {args.n}^3: schedules " + ", ".join(
+        f"{n} {m:.3f}" for n, m in zip(names, info["schedule_ms"])) + " ms/step; tiles " + ", ".join(
+        f"{t} {m:.3f}" for t, m in zip((128, 256, 512), info["tile_ms"])) +
+        f" ms/step; kept dense_top {info['dense_top']}, subtree_cap {info['subtree_cap']}, "
+        f"level_merge {info['level_merge']}, elem_tile {info['elem_tile']} ({info['seconds']:.1f}s)")
+    info["schedules"] = names
+    return info
+
+
 def _cpu_model():
     try:
         with open("/proc/cpuinfo") as f:
@@ -422,7 +445,7 @@ def main():
     ap.add_argument("--no-refactor", action="store_true",
                     help="skip the device refactorisation measurement")
     ap.add_argument("--no-tune", action="store_true",
-                    help="keep the default element tile in the batched run")
+                    help="skip the autotuners (batched run: default element tile)")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the extra mixed-precision Neo-Hookean run")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
@@ -489,6 +512,7 @@ def main():
         batched = [batched_run(args, torch, W, qnsim, 0), batched_run(args, torch, W, qnsim, 1)]
     served = served_run(args, torch, W, qnsim) if args.pool_count > 0 else None
     refac = refactor_run(args, torch, W, qnsim) if not args.no_refactor else None
+    tuned = tune_run(args, torch, W, qnsim) if not args.no_tune else None
 
     total_steps = sum(r["steps"] for r in runs)
     total_s = sum(r["seconds"] for r in runs)
@@ -542,6 +566,7 @@ def main():
         **({"batched": batched} if batched else {}),
         **({"served": served} if served else {}),
         **({"refactor": refac} if refac else {}),
+        **({"tune": tuned} if tuned else {}),
         "roofline": {
             "bound": "hbm",
             "kernel": dom,

@@ -239,6 +239,33 @@ int qnsim_step_device(qnsim_t* ctx, const double* d_x, const double* d_v, double
                       const double* d_fext, double* d_x_out, double* d_v_out,
                       void* stream, qnsim_stats* stats);
 
+/* Autotuning of a prepared context (prepared for h) on its own workload:
+ * times reps steps (after one untimed step) from the device state (d_x,
+ * d_v), n x 3 float64 in caller order, which is not modified. what = 1: the
+ * solve schedule among four (levels only; bottom subtrees per workgroup;
+ * plus level merging; plus the dense top block: dense_top / subtree_cap /
+ * level_merge = 0/0/0, 0/384/0, 0/384/1, 6144/384/1), each a new host
+ * analysis and factorisation for h (section 3: the prefactored A); what =
+ * 2: the element tile among 128, 256, 512 (the per-element gradient of
+ * section 4.1); what = 0 or 3: the schedule, then the tile with that
+ * schedule. The context keeps the fastest options and stays prepared for
+ * h; the options are reported in *info with the measured milliseconds per
+ * step (NaN: not timed). Results with different options agree to rounding.
+ * Errors: QNSIM_E_INVALID, QNSIM_E_STATE / QNSIM_E_H_MISMATCH (not prepared
+ * for h), QNSIM_E_NOMEM, QNSIM_E_DEVICE, QNSIM_E_NOT_SPD; on an error the
+ * options return to their values before the call and the context is left
+ * unprepared. Synchronous; the context must not be stepping. */
+typedef struct {
+  int32_t dense_top;     /* options kept */
+  int32_t subtree_cap;
+  int32_t level_merge;
+  int32_t elem_tile;
+  double schedule_ms[4]; /* ms per step for the four schedules, in the order above */
+  double tile_ms[3];     /* ms per step with the kept schedule, tiles 128, 256, 512 */
+} qnsim_tune_info;
+int qnsim_tune(qnsim_t* ctx, double h, const double* d_x, const double* d_v, int32_t reps,
+               int32_t what, qnsim_tune_info* info);
+
 /* Run `steps` consecutive time steps on device arrays, advancing (d_x, d_v)
  * in place (stream as qnsim_step_device), and accumulate counters into stats
  * (if non-null). Used to time trajectories; each step reads back one status. */

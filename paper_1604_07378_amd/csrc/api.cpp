@@ -395,6 +395,19 @@ int qnsim_analyze(qnsim_t* c, double h) {
   }
 }
 
+// Device mesh of an analysed context: the upload, the numeric factorisation
+// on the device when the host holds no values for c->h, the colliders.
+static int upload_ctx(qnsim_t* c, std::string& err) {
+  int rc = upload_sims({c}, c->opt, c->h, c->dev, err);
+  if (!rc && (c->opt.device_factor || c->factor_on_device)) {
+    rc = dev_refactor(c, c->h, nullptr, err);
+    if (!rc) c->factor_on_device = true;
+  }
+  if (!rc && !c->planes.empty())
+    rc = dev_set_colliders(c->dev, (int)c->planes.size() / 4, c->planes.data(), c->coll_k, err);
+  return rc;
+}
+
 int qnsim_prepare(qnsim_t* c, double h) {
   if (!c) return QNSIM_E_INVALID;
   auto t0 = std::chrono::steady_clock::now();
@@ -402,13 +415,7 @@ int qnsim_prepare(qnsim_t* c, double h) {
   if (rc) return rc;
   try {
     std::string err;
-    rc = upload_sims({c}, c->opt, c->h, c->dev, err);
-    if (!rc && c->opt.device_factor) {
-      rc = dev_refactor(c, c->h, nullptr, err);  // the numeric factorisation
-      if (!rc) c->factor_on_device = true;
-    }
-    if (!rc && !c->planes.empty())
-      rc = dev_set_colliders(c->dev, (int)c->planes.size() / 4, c->planes.data(), c->coll_k, err);
+    rc = upload_ctx(c, err);
     if (rc) fail(c, rc, err);
     else c->prepared = true;
   } catch (const std::bad_alloc&) {
@@ -473,6 +480,98 @@ int qnsim_step_device(qnsim_t* c, const double* d_x, const double* d_v, double h
                 c->diag_final_gradient != 0, err);
   if (rc) return fail(c, rc, err);
   if (stats) fill_stats(c->dev.stat_host[0], c->diag_final_gradient != 0, stats);
+  return QNSIM_OK;
+}
+
+int qnsim_tune(qnsim_t* c, double h, const double* d_x, const double* d_v, int32_t reps,
+               int32_t what, qnsim_tune_info* info) {
+  if (!c) return QNSIM_E_INVALID;
+  if (!d_x || !d_v || !info) return fail(c, QNSIM_E_INVALID, "null pointer");
+  if (reps < 1 || reps > 1000 || what < 0 || what > 3)
+    return fail(c, QNSIM_E_INVALID, "reps must be 1..1000 and what 0..3");
+  int rc = check_step(c, h);
+  if (rc) return rc;
+  if (what == 0) what = 3;
+  for (double& t : info->schedule_ms) t = NAN;
+  for (double& t : info->tile_ms) t = NAN;
+  const size_t bytes = 3 * (size_t)c->n * sizeof(double);
+  double *tx = nullptr, *tv = nullptr;
+  if (hipSetDevice(c->opt.device) != hipSuccess) return fail(c, QNSIM_E_DEVICE, "hipSetDevice failed");
+  if (hipMalloc((void**)&tx, bytes) != hipSuccess || hipMalloc((void**)&tv, bytes) != hipSuccess) {
+    if (tx) (void)hipFree(tx);
+    return fail(c, QNSIM_E_NOMEM, "tuning state allocation failed");
+  }
+  std::string err;
+  // ms per step from (d_x, d_v): one untimed step (graph capture), then reps
+  auto time_steps = [&](double* ms) -> int {
+    hipStream_t st = (hipStream_t)c->dev.stream;
+    if (hipMemcpyAsync(tx, d_x, bytes, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(tv, d_v, bytes, hipMemcpyDeviceToDevice, st) != hipSuccess) {
+      err = "tuning state copy failed";
+      return QNSIM_E_DEVICE;
+    }
+    const StepParams P = params_of(c, h);
+    int r = dev_step(c->dev, P, tx, tv, nullptr, tx, tv, c->dev.stream, false, err);
+    const auto t0 = std::chrono::steady_clock::now();
+    for (int k = 0; k < reps && !r; ++k) r = dev_step(c->dev, P, tx, tv, nullptr, tx, tv, c->dev.stream, false, err);
+    *ms = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count() * 1e3 / reps;
+    return r;
+  };
+  // solve schedules: levels only; bottom subtrees; + level merging; + dense top block
+  static const int32_t kSched[4][3] = {{0, 0, 0}, {0, 384, 0}, {0, 384, 1}, {6144, 384, 1}};
+  auto set_sched = [&](int k) {
+    c->opt.dense_top = kSched[k][0];
+    c->opt.subtree_cap = kSched[k][1];
+    c->opt.level_merge = kSched[k][2];
+  };
+  auto reprepare = [&]() -> int {
+    c->analyzed = false;  // the factor's structure depends on the schedule
+    const int r = qnsim_prepare(c, h);
+    if (r) err = c->last_error;
+    return r;
+  };
+  const qnsim_options keep = c->opt;
+  double best = INFINITY;
+  if (what & 1) {
+    int kbest = -1;
+    for (int k = 0; k < 4 && !rc; ++k) {
+      set_sched(k);
+      rc = reprepare();
+      if (!rc) rc = time_steps(&info->schedule_ms[k]);
+      if (!rc && info->schedule_ms[k] < best) { best = info->schedule_ms[k]; kbest = k; }
+    }
+    if (!rc && kbest != 3) {
+      set_sched(kbest);
+      rc = reprepare();
+    }
+  }
+  if (!rc && (what & 2)) {
+    int tbest = c->opt.elem_tile > 0 ? c->opt.elem_tile : 256;
+    best = INFINITY;
+    for (int k = 0; k < 3 && !rc; ++k) {
+      c->opt.elem_tile = kElemTiles[k];
+      dev_free(c->dev);
+      rc = upload_ctx(c, err);
+      if (!rc) rc = time_steps(&info->tile_ms[k]);
+      if (!rc && info->tile_ms[k] < best) { best = info->tile_ms[k]; tbest = kElemTiles[k]; }
+    }
+    if (!rc && tbest != kElemTiles[2]) {
+      c->opt.elem_tile = tbest;
+      dev_free(c->dev);
+      rc = upload_ctx(c, err);
+    }
+  }
+  (void)hipFree(tx);
+  (void)hipFree(tv);
+  if (rc) {
+    c->opt = keep;
+    invalidate(c);
+    return fail(c, rc, err);
+  }
+  info->dense_top = c->opt.dense_top;
+  info->subtree_cap = c->opt.subtree_cap;
+  info->level_merge = c->opt.level_merge;
+  info->elem_tile = c->opt.elem_tile > 0 ? c->opt.elem_tile : 256;
   return QNSIM_OK;
 }
 

@@ -69,6 +69,17 @@ class Stats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
 
 
+class TuneInfo(ctypes.Structure):
+    _fields_ = [("dense_top", ctypes.c_int32), ("subtree_cap", ctypes.c_int32),
+                ("level_merge", ctypes.c_int32), ("elem_tile", ctypes.c_int32),
+                ("schedule_ms", ctypes.c_double * 4), ("tile_ms", ctypes.c_double * 3)]
+
+    def as_dict(self):
+        return dict(dense_top=self.dense_top, subtree_cap=self.subtree_cap,
+                    level_merge=self.level_merge, elem_tile=self.elem_tile,
+                    schedule_ms=list(self.schedule_ms), tile_ms=list(self.tile_ms))
+
+
 class FactorInfo(ctypes.Structure):
     _fields_ = [("n_free", ctypes.c_int32), ("n_supernodes", ctypes.c_int32),
                 ("n_levels", ctypes.c_int32), ("max_front", ctypes.c_int32),
@@ -149,6 +160,7 @@ SIGNATURES = {
     "qnsim_pool_last_error": (ctypes.c_char_p, [_P]),
     "qnsim_pool_time_kernel": (ctypes.c_int, [_P, _I, _I, _I, ctypes.POINTER(_D)]),
     "qnsim_pool_set_h": (ctypes.c_int, [_P, _D, ctypes.POINTER(_D)]),
+    "qnsim_tune": (ctypes.c_int, [_P, _D, _P, _P, _I, _I, ctypes.POINTER(TuneInfo)]),
     "qnsim_pool_tune": (ctypes.c_int, [_P, _I, _I, _I, ctypes.POINTER(_I), ctypes.POINTER(_D)]),
 }
 
@@ -361,6 +373,17 @@ class Sim:
                                                _tptr(f_ext), int(steps), _stream_ptr(stream),
                                                ctypes.byref(st)))
         return st.as_dict()
+
+    def tune(self, x, v, h: float, reps: int = 3, schedule: bool = True, tile: bool = True) -> dict:
+        """Keep the fastest solve schedule and element tile for steps from the
+        device state (x, v) (torch n x 3 float64 tensors, not modified)."""
+        info = TuneInfo()
+        what = (1 if schedule else 0) | (2 if tile else 0)
+        if what == 0:
+            raise ValueError("nothing to tune")
+        self._check(self._lib.qnsim_tune(self._h, float(h), _tptr(x), _tptr(v), int(reps), what,
+                                         ctypes.byref(info)))
+        return info.as_dict()
 
     def time_kernel(self, kernel: int, reps: int) -> float:
         """Mean milliseconds per launch of one step kernel (HIP events)."""

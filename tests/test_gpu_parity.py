@@ -471,3 +471,58 @@ def test_chebyshev_direction_against_oracle():
         worst = max(worst, e)
         assert e <= 1e-9, f"step {step}: eps {e:.3e}"
     print(f"chebyshev 5 steps x 30 iterations: max eps {worst:.3e}", flush=True)
+
+
+def test_tune_single_context():
+    """qnsim_tune on the 540-tet cantilever from a perturbed state: the state
+    tensors stay as they were, every schedule and tile is timed, the tuned
+    context steps as a fresh context created with the kept options (bit for
+    bit) and as the oracle (1e-9); with the device factorisation and after a
+    time-step change (A refactored on the device) the tile-only and the full
+    tune keep oracle parity at the new h."""
+    w = W.workload_cantilever(0)
+    x0 = _perturbed(w, 0.05, 7)
+    x, v = _dev(x0), _dev(w.v0)
+    xc, vc = x.clone(), v.clone()
+    s = qnsim.sim_from_workload(w)
+    info = s.tune(x, v, w.h, reps=2)
+    print(f"tune: {info}", flush=True)
+    assert torch.equal(x, xc) and torch.equal(v, vc)
+    assert np.isfinite(info["schedule_ms"]).all() and np.isfinite(info["tile_ms"]).all()
+    kept = dict(dense_top=info["dense_top"], subtree_cap=info["subtree_cap"],
+                level_merge=info["level_merge"], elem_tile=info["elem_tile"])
+    assert (kept["dense_top"], kept["subtree_cap"], kept["level_merge"]) in [
+        (0, 0, 0), (0, 384, 0), (0, 384, 1), (6144, 384, 1)]
+    assert kept["elem_tile"] in (128, 256, 512)
+    fresh = qnsim.sim_from_workload(w, **kept)
+    m = _model(w)
+    xo, vo = x0.copy(), w.v0.copy()
+    xa, va = x0.copy(), w.v0.copy()
+    xb, vb = x0.copy(), w.v0.copy()
+    for k in range(10):
+        r = oracle.step(m, xo, vo)
+        xo, vo = r.x, r.v
+        xa, va, _ = s.step(xa, va, w.h)
+        xb, vb, _ = fresh.step(xb, vb, w.h)
+        assert np.array_equal(xa, xb) and np.array_equal(va, vb), f"step {k}"
+        assert _eps(xa, xo, w.rest) <= 1e-9, f"step {k}"
+    fresh.close()
+    s.close()
+    h2 = 1.0 / 60.0
+    w2 = W.workload_cantilever(0)
+    w2.h = h2
+    m2 = _model(w2)
+    for opts in (dict(device_factor=1), dict()):
+        s = qnsim.sim_from_workload(w, **opts)
+        s.refactor(h2)
+        for sched in (False, True):
+            info = s.tune(x, v, h2, reps=1, schedule=sched)
+            assert np.isnan(info["schedule_ms"]).all() != sched
+            xo, vo = x0.copy(), w.v0.copy()
+            xa, va = x0.copy(), w.v0.copy()
+            for k in range(5):
+                r = oracle.step(m2, xo, vo)
+                xo, vo = r.x, r.v
+                xa, va, _ = s.step(xa, va, h2)
+                assert _eps(xa, xo, w.rest) <= 1e-9, f"{opts} schedule {sched} step {k}"
+        s.close()
