@@ -448,6 +448,16 @@ int qnsim_pool_remove(qnsim_pool_t* pool, int32_t id);
 int qnsim_pool_step(qnsim_pool_t* pool, int32_t n, const int32_t* ids, qnsim_stats* stats);
 
 /* State of a resident simulation (host arrays, n x 3, its own numbering). */
+/* External force of a resident simulation (section 3: f_ext in the inertial
+ * target y = x + h v + h^2 M^{-1} f_ext): n x 3 float64 in newtons, caller
+ * order, copied; NULL removes it. It acts, with the pool's gravity, in every
+ * later step of the simulation (batched or served) until changed: a step
+ * uses the force set before it starts. The first force set in a group
+ * allocates one n x 3 array for the whole group (counted in the pool's used
+ * bytes, outside the admission budget). Waits for a running step of the
+ * group. Errors: QNSIM_E_INVALID (not resident), QNSIM_E_NONFINITE,
+ * QNSIM_E_NOMEM, QNSIM_E_DEVICE. */
+int qnsim_pool_set_force(qnsim_pool_t* pool, int32_t id, const double* f_ext);
 int qnsim_pool_get_state(qnsim_pool_t* pool, int32_t id, double* x, double* v);
 int qnsim_pool_set_state(qnsim_pool_t* pool, int32_t id, const double* x, const double* v);
 

@@ -36,6 +36,7 @@ struct PoolSim {
   int group = -1;            // -1: staged
   int slot = -1;             // position in its group
   bool removed = false;
+  bool has_force = false;    // its slice of the group's force array is set
   int64_t est_bytes = 0;     // device-memory estimate
   std::vector<double> x0, v0;  // initial state until admitted
 };
@@ -46,6 +47,7 @@ struct PoolGroup {
   std::vector<int> cv0;      // first caller vertex of each member in xs / vs
   double* xs = nullptr;      // states of the members, concatenated n x 3
   double* vs = nullptr;
+  double* fx = nullptr;      // external forces, as xs (allocated on the first force set)
   int64_t bytes = 0;
   int live = 0;              // members not removed
   bool busy = false;         // a step is running
@@ -176,7 +178,8 @@ int analyze_one(const qnsim_pool* p, const qnsim_mesh_desc& d, PoolSim& out, std
 void free_group(PoolGroup& g) {
   if (g.xs) (void)hipFree(g.xs);
   if (g.vs) (void)hipFree(g.vs);
-  g.xs = g.vs = nullptr;
+  if (g.fx) (void)hipFree(g.fx);
+  g.xs = g.vs = g.fx = nullptr;
   dev_free(g.D);
 }
 
@@ -225,7 +228,7 @@ int step_group(qnsim_pool* p, PoolGroup& g, const std::vector<int>& slots,
   for (int s : slots) run[s] = 1;
   int rc = dev_set_run(g.D, run.data(), g.D.stream, err);
   if (rc) return rc;
-  rc = dev_step(g.D, pool_params(p), g.xs, g.vs, nullptr, g.xs, g.vs, g.D.stream, false, err);
+  rc = dev_step(g.D, pool_params(p), g.xs, g.vs, g.fx, g.xs, g.vs, g.D.stream, false, err);
   if (rc) return rc;
   st.resize(slots.size());
   for (size_t i = 0; i < slots.size(); ++i) st[i] = g.D.stat_host[slots[i]];
@@ -530,6 +533,39 @@ int qnsim_pool_set_state(qnsim_pool_t* p, int32_t id, const double* x, const dou
       if (!std::isfinite(x[i]) || !std::isfinite(v[i])) return pfail(p, QNSIM_E_NONFINITE, "non-finite state");
   }
   return state_copy(p, id, nullptr, nullptr, x, v);
+}
+
+int qnsim_pool_set_force(qnsim_pool_t* p, int32_t id, const double* f_ext) {
+  if (!p) return QNSIM_E_INVALID;
+  std::unique_lock<std::mutex> lk(p->mu);
+  if (!resident(p, id)) return pfail(p, QNSIM_E_INVALID, "id is not resident");
+  PoolSim& s = p->sims[id];
+  const size_t n3 = 3 * (size_t)s.c->n;
+  if (f_ext)
+    for (size_t i = 0; i < n3; ++i)
+      if (!std::isfinite(f_ext[i])) return pfail(p, QNSIM_E_NONFINITE, "non-finite force");
+  PoolGroup& g = *p->groups[s.group];
+  p->cv.wait(lk, [&] { return !g.busy; });
+  if (!f_ext && !s.has_force) return QNSIM_OK;
+  if (hipSetDevice(p->opt.device) != hipSuccess) return pfail(p, QNSIM_E_DEVICE, "hipSetDevice failed");
+  hipStream_t st = (hipStream_t)g.D.stream;
+  const size_t all = 3 * (size_t)g.D.n * sizeof(double);
+  if (!g.fx) {
+    if (hipMalloc((void**)&g.fx, all) != hipSuccess) {
+      g.fx = nullptr;
+      return pfail(p, QNSIM_E_NOMEM, "force allocation failed");
+    }
+    if (hipMemsetAsync(g.fx, 0, all, st) != hipSuccess) return pfail(p, QNSIM_E_DEVICE, "force clear failed");
+    g.bytes += (int64_t)all;
+    p->used += (int64_t)all;
+  }
+  double* dst = g.fx + 3 * (size_t)g.cv0[s.slot];
+  hipError_t e = f_ext ? hipMemcpyAsync(dst, f_ext, n3 * sizeof(double), hipMemcpyHostToDevice, st)
+                       : hipMemsetAsync(dst, 0, n3 * sizeof(double), st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return pfail(p, QNSIM_E_DEVICE, hipGetErrorString(e));
+  s.has_force = f_ext != nullptr;
+  return QNSIM_OK;
 }
 
 int qnsim_pool_serve_start(qnsim_pool_t* p, int32_t lanes) {

@@ -160,6 +160,7 @@ SIGNATURES = {
     "qnsim_pool_last_error": (ctypes.c_char_p, [_P]),
     "qnsim_pool_time_kernel": (ctypes.c_int, [_P, _I, _I, _I, ctypes.POINTER(_D)]),
     "qnsim_pool_set_h": (ctypes.c_int, [_P, _D, ctypes.POINTER(_D)]),
+    "qnsim_pool_set_force": (ctypes.c_int, [_P, _I, _P]),
     "qnsim_tune": (ctypes.c_int, [_P, _D, _P, _P, _I, _I, ctypes.POINTER(TuneInfo)]),
     "qnsim_pool_tune": (ctypes.c_int, [_P, _I, _I, _I, ctypes.POINTER(_I), ctypes.POINTER(_D)]),
 }
@@ -518,6 +519,14 @@ class Pool:
         st = (Stats * max(1, ids.size))()
         self._check(self._lib.qnsim_pool_step(self._p, ids.size, _ptr(ids), st))
         return [st[i].as_dict() for i in range(ids.size)]
+
+    def set_force(self, sim_id: int, f_ext=None):
+        """External force (n x 3, N) of a resident simulation for its later
+        steps; None removes it."""
+        n = self.nverts[int(sim_id)]
+        f = _f64(f_ext, (n, 3)) if f_ext is not None else None
+        self._check(self._lib.qnsim_pool_set_force(self._p, int(sim_id),
+                                                   _ptr(f) if f is not None else None))
 
     def get_state(self, sim_id: int):
         n = self.nverts[int(sim_id)]

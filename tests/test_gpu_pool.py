@@ -350,3 +350,53 @@ def test_pool_tune_element_tiles():
             x, _ = p.get_state(ids[j])
             assert _eps(x, ref[j][k][0], ws[j].rest) <= 1e-11, f"h 1/60, sim {j} step {k}"
     p.close()
+
+
+def test_pool_external_force():
+    """qnsim_pool_set_force: a force on one member of a group of four gives,
+    bit for bit, that simulation's steps alone with the same f_ext (full and
+    partial batches, a served request); the other members equal their steps
+    alone without one; removing the force returns to gravity only."""
+    ws = [W.workload_block(W.NEOHOOKEAN if i % 2 == 0 else W.STVK, dims=(3 + i, 4, 3),
+                           prestretch_seed=70 + i) for i in range(4)]
+    p, ids = _pool(ws)
+    alone = [qnsim.sim_from_workload(w, dense_top=0, level_merge=0) for w in ws]
+    rng = np.random.default_rng(5)
+    m = alone[1].masses()
+    f = m[:, None] * rng.normal(scale=4.0, size=(ws[1].n_verts, 3))  # about 4 m/s^2 per vertex
+    p.set_force(ids[1], f)
+    state = [(w.x0.copy(), w.v0.copy()) for w in ws]
+
+    def advance(j, force):
+        x, v, _ = alone[j].step(*state[j], ws[j].h, f_ext=force)
+        state[j] = (x, v)
+
+    def check(js, tag):
+        for j in js:
+            x, v = p.get_state(ids[j])
+            assert np.array_equal(x, state[j][0]) and np.array_equal(v, state[j][1]), f"{tag}: sim {j}"
+
+    for k in range(2):
+        p.step(ids)
+        for j in range(4):
+            advance(j, f if j == 1 else None)
+        check(range(4), f"batched step {k}")
+    p.step([ids[1], ids[2]])
+    advance(1, f)
+    advance(2, None)
+    check(range(4), "partial batch")
+    p.serve_start(1)
+    p.wait(p.submit(ids[1]))
+    p.serve_stop()
+    advance(1, f)
+    check([1], "served request")
+    p.set_force(ids[1], None)
+    p.step(ids)
+    for j in range(4):
+        advance(j, None)
+    check(range(4), "force removed")
+    moved = np.linalg.norm(state[1][0] - ws[1].rest)
+    assert moved > 0.0
+    for s in alone:
+        s.close()
+    p.close()
