@@ -526,3 +526,26 @@ def test_tune_single_context():
                 xa, va, _ = s.step(xa, va, h2)
                 assert _eps(xa, xo, w.rest) <= 1e-9, f"{opts} schedule {sched} step {k}"
         s.close()
+
+
+def test_resume_from_saved_state():
+    """The method keeps no state across steps (the L-BFGS window starts empty
+    every step), so (x, v) is the whole checkpoint: 10 steps in one context
+    equal 5 steps, a new context, and 5 more from the saved state, bit for bit."""
+    w = W.workload_cantilever(0)
+    s = qnsim.sim_from_workload(w)
+    x, v = w.x0.copy(), w.v0.copy()
+    traj = []
+    for _ in range(10):
+        x, v, _ = s.step(x, v, w.h)
+        traj.append((x, v))
+    s.close()
+    s = qnsim.sim_from_workload(w)
+    x, v = traj[4]
+    s.close()
+    s = qnsim.sim_from_workload(w)
+    x, v = x.copy(), v.copy()
+    for k in range(5, 10):
+        x, v, _ = s.step(x, v, w.h)
+        assert np.array_equal(x, traj[k][0]) and np.array_equal(v, traj[k][1]), f"step {k}"
+    s.close()
