@@ -725,7 +725,6 @@ int qnsim_pool_tune(qnsim_pool_t* p, int32_t candidates, int32_t reps, int32_t n
       if (g && g->busy) return false;
     return true;
   });
-  if (hipSetDevice(p->opt.device) != hipSuccess) return pfail(p, QNSIM_E_DEVICE, "hipSetDevice failed");
   for (int gi = 0; gi < n_groups; ++gi) {
     tiles[gi] = 0;
     if (step_ms)
@@ -736,6 +735,7 @@ int qnsim_pool_tune(qnsim_pool_t* p, int32_t candidates, int32_t reps, int32_t n
   for (int gi = 0; gi < (int)p->groups.size(); ++gi) {
     PoolGroup& g = *p->groups[gi];
     if (g.live == 0) continue;
+    if (hipSetDevice(p->opt.device) != hipSuccess) return pfail(p, QNSIM_E_DEVICE, "hipSetDevice failed");
     std::vector<const qnsim*> members;
     bool refactored = false;
     for (int id : g.ids) {

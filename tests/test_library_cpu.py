@@ -126,6 +126,15 @@ def test_errors_are_reported_not_raised_across_the_abi():
     with pytest.raises(qnsim.QnsimError) as e:
         s.refactor(1 / 60)                        # analysed, not prepared on a device
     assert e.value.code == -8                     # QNSIM_E_STATE
+    # qnsim_tune checks its arguments and the prepared state before touching
+    # the (never dereferenced) state pointers
+    import ctypes
+    info = qnsim.TuneInfo()
+    fake = ctypes.c_void_p(64)
+    assert s._lib.qnsim_tune(s._h, 1 / 30, fake, fake, 0, 0, ctypes.byref(info)) == -1
+    assert s._lib.qnsim_tune(s._h, 1 / 30, fake, fake, 2, 4, ctypes.byref(info)) == -1
+    assert s._lib.qnsim_tune(s._h, 1 / 30, None, fake, 2, 0, ctypes.byref(info)) == -1
+    assert s._lib.qnsim_tune(s._h, 1 / 30, fake, fake, 2, 0, ctypes.byref(info)) == -8
 
 
 @pytest.mark.parametrize("sched", [dict(dense_top=0, subtree_cap=0, level_merge=0),
@@ -180,6 +189,14 @@ def test_pool_staging_and_validation_on_host():
     with pytest.raises(qnsim.QnsimError) as e:
         p.submit(ids[0])
     assert e.value.code == -8
+    with pytest.raises(qnsim.QnsimError) as e:
+        p.set_force(ids[0], np.zeros((ws[0].n_verts, 3)))   # staged, not resident
+    assert e.value.code == -1
+    assert p.tune() == ([], [])                   # no group yet: nothing to time
+    import ctypes
+    tiles = (ctypes.c_int32 * 1)()
+    assert p._lib.qnsim_pool_tune(p._p, 8, 1, 1, tiles, None) == -1   # bad candidate mask
+    assert p._lib.qnsim_pool_tune(p._p, 0, 0, 1, tiles, None) == -1   # reps < 1
     p.remove(ids[2])
     assert p.info()["sims_staged"] == 4
     p.close()
