@@ -283,6 +283,43 @@ def small_runs(args, torch, W, qnsim):
     return out
 
 
+def mixed_error_run(args, torch, W, qnsim, steps=300):
+    """Mixed precision on the mixed-stiffness cantilever (E log-uniform in
+    [1e4, 1e7] Pa): per-step position error of the mixed path against the
+    FP64 GPU path (which the parity tests hold to the FP64 oracle at 1e-9),
+    both stepping from the FP64 trajectory's state, over `steps` steps; and the
+    free-running separation of the two trajectories."""
+    import numpy as np
+    w = W.workload_mixed_cantilever(0)
+    f64 = qnsim.sim_from_workload(w)
+    mix = qnsim.sim_from_workload(w, precision=qnsim.QNSIM_MIXED)
+    rest = torch.from_numpy(np.ascontiguousarray(w.rest, dtype=np.float64)).cuda()
+    x = torch.from_numpy(w.x0.copy()).cuda()
+    v = torch.from_numpy(w.v0.copy()).cuda()
+    xf, vf = x.clone(), v.clone()          # free-running mixed trajectory
+    xm, vm = torch.empty_like(x), torch.empty_like(v)
+    per_step, free = [], {}
+    for k in range(steps):
+        mix.step_device(x, v, w.h, x_out=xm, v_out=vm, stats=False)
+        f64.step_device(x, v, w.h, stats=False)           # in place: the FP64 trajectory
+        mix.step_device(xf, vf, w.h, stats=False)
+        den = max(float(torch.linalg.norm(x - rest)), 1e-300)
+        per_step.append(float(torch.linalg.norm(xm - x)) / den)
+        if k + 1 in (10, 60, steps):
+            free[k + 1] = float(torch.linalg.norm(xf - x)) / den
+    f64.close()
+    mix.close()
+    e = np.array(per_step)
+    out = dict(workload="cantilever 10x3x3 cubes (540 tets), Neo-Hookean, E log-uniform in [1e4, 1e7] Pa",
+               steps=steps, reference="FP64 GPU path from the same state",
+               per_step_error_max=float(e.max()), per_step_error_median=float(np.median(e)),
+               free_running_error={str(k): v for k, v in free.items()}, tolerance=1e-4)
+    log(f"[bench] mixed precision error over {steps} steps (vs FP64 GPU path, same state): "
+        f"max {e.max():.2e}, median {np.median(e):.2e}; free-running "
+        + ", ".join(f"step {k} {v:.1e}" for k, v in free.items()))
+    return out
+
+
 def convergence_run(args, torch, W, qnsim):
     """Relative error (g(x_k) - g*)/(g(x_0) - g*) of one frame of the Neo-Hookean
     block after K iterations for the plain PD direction (history 0), the
@@ -506,6 +543,7 @@ def main():
         mixed = run_material(W.NEOHOOKEAN, args, torch, W, qnsim, {"precision": qnsim.QNSIM_MIXED})
 
     small = small_runs(args, torch, W, qnsim) if args.small_steps > 0 else []
+    mixed_err = mixed_error_run(args, torch, W, qnsim) if not args.no_mixed else None
     conv = convergence_run(args, torch, W, qnsim) if not args.no_convergence else None
     batched = []
     if args.batch_count > 0:
@@ -562,6 +600,7 @@ def main():
                                                          "iterations", "kernel_ms")}}
            if mixed else {}),
         **({"small_meshes": small} if small else {}),
+        **({"mixed_precision_error": mixed_err} if mixed_err else {}),
         **({"convergence": conv} if conv else {}),
         **({"batched": batched} if batched else {}),
         **({"served": served} if served else {}),
