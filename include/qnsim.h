@@ -470,6 +470,12 @@ int qnsim_pool_set_state(qnsim_pool_t* pool, int32_t id, const double* x, const 
 int qnsim_pool_serve_start(qnsim_pool_t* pool, int32_t lanes);
 /* Queues one step request for a resident simulation; *ticket identifies it. */
 int qnsim_pool_submit(qnsim_pool_t* pool, int32_t id, int64_t* ticket);
+/* As qnsim_pool_submit, with an external force for this step only (section
+ * 3: f_ext in y; n x 3 float64 in newtons, caller order, copied at submit;
+ * NULL: as qnsim_pool_submit): the step that serves the request uses it in
+ * place of the simulation's own force (qnsim_pool_set_force), which later
+ * steps use again. Errors as qnsim_pool_submit, and QNSIM_E_NONFINITE. */
+int qnsim_pool_submit_force(qnsim_pool_t* pool, int32_t id, const double* f_ext, int64_t* ticket);
 /* Waits for a request (at most timeout_s seconds; < 0: no limit) and
  * returns its status: the step's own error, or QNSIM_E_STATE on time-out or
  * an unknown ticket. stats and latency_s (time from submit to completion;

@@ -37,6 +37,7 @@ struct PoolSim {
   int slot = -1;             // position in its group
   bool removed = false;
   bool has_force = false;    // its slice of the group's force array is set
+  std::vector<double> force; // host copy of that force (n x 3, caller order)
   int64_t est_bytes = 0;     // device-memory estimate
   std::vector<double> x0, v0;  // initial state until admitted
 };
@@ -57,6 +58,7 @@ struct Request {
   int64_t ticket;
   int sim;
   double t_submit;
+  std::shared_ptr<const std::vector<double>> force;  // this step's own f_ext, or null
 };
 
 struct Done {
@@ -219,6 +221,36 @@ int build_group(qnsim_pool* p, const std::vector<int>& ids, std::unique_ptr<Pool
   return QNSIM_OK;
 }
 
+// The group's force array (zeroed) on first use; called with the pool lock held.
+int ensure_force_array(qnsim_pool* p, PoolGroup& g, std::string& err) {
+  if (g.fx) return QNSIM_OK;
+  const size_t all = 3 * (size_t)g.D.n * sizeof(double);
+  if (hipMalloc((void**)&g.fx, all) != hipSuccess) {
+    g.fx = nullptr;
+    err = "force allocation failed";
+    return QNSIM_E_NOMEM;
+  }
+  if (hipMemsetAsync(g.fx, 0, all, (hipStream_t)g.D.stream) != hipSuccess) {
+    err = "force clear failed";
+    return QNSIM_E_DEVICE;
+  }
+  g.bytes += (int64_t)all;
+  p->used += (int64_t)all;
+  return QNSIM_OK;
+}
+
+// Writes the force of member `slot` (caller order; null: zero) into the
+// group's force array, on the group's stream.
+int write_force(PoolGroup& g, int slot, int n, const double* f, std::string& err) {
+  double* dst = g.fx + 3 * (size_t)g.cv0[slot];
+  const size_t bytes = 3 * (size_t)n * sizeof(double);
+  hipStream_t st = (hipStream_t)g.D.stream;
+  const hipError_t e = f ? hipMemcpyAsync(dst, f, bytes, hipMemcpyHostToDevice, st)
+                         : hipMemsetAsync(dst, 0, bytes, st);
+  if (e != hipSuccess) { err = hipGetErrorString(e); return QNSIM_E_DEVICE; }
+  return QNSIM_OK;
+}
+
 // One batched step of the listed members of group g (slots), on its stream.
 // Called without the pool lock; the group is marked busy by the caller.
 int step_group(qnsim_pool* p, PoolGroup& g, const std::vector<int>& slots,
@@ -270,11 +302,38 @@ void lane_main(qnsim_pool* p) {
         ++it;
       }
     }
+    // requests with their own force: the group's force array takes it for
+    // this step, and the simulation's own force (or zero) afterwards
+    // (copied under the lock: the pool's tables may grow while it steps)
+    struct OwnForce {
+      int slot, n;
+      std::shared_ptr<const std::vector<double>> req;
+      std::vector<double> keep;  // the simulation's own force; empty: none
+    };
+    std::vector<OwnForce> own;
+    for (const Request& r : batch)
+      if (r.force) {
+        const PoolSim& s = p->sims[r.sim];
+        own.push_back(OwnForce{s.slot, s.c->n, r.force, s.has_force ? s.force : std::vector<double>()});
+      }
+    std::string err;
+    int rc = own.empty() ? QNSIM_OK : ensure_force_array(p, g, err);
     g.busy = true;
     lk.unlock();
     std::vector<SimStat> st;
-    std::string err;
-    const int rc = step_group(p, g, slots, st, err);
+    for (size_t k = 0; k < own.size() && !rc; ++k)
+      rc = write_force(g, own[k].slot, own[k].n, own[k].req->data(), err);
+    if (!rc) rc = step_group(p, g, slots, st, err);
+    for (size_t k = 0; k < own.size() && g.fx; ++k) {
+      std::string e2;
+      const int r2 = write_force(g, own[k].slot, own[k].n,
+                                 own[k].keep.empty() ? nullptr : own[k].keep.data(), e2);
+      if (r2 && !rc) { rc = r2; err = e2; }
+    }
+    if (!own.empty() && g.fx && hipStreamSynchronize((hipStream_t)g.D.stream) != hipSuccess && !rc) {
+      rc = QNSIM_E_DEVICE;
+      err = "force restore failed";
+    }
     const double t_end = now_s();
     lk.lock();
     g.busy = false;
@@ -548,23 +607,17 @@ int qnsim_pool_set_force(qnsim_pool_t* p, int32_t id, const double* f_ext) {
   p->cv.wait(lk, [&] { return !g.busy; });
   if (!f_ext && !s.has_force) return QNSIM_OK;
   if (hipSetDevice(p->opt.device) != hipSuccess) return pfail(p, QNSIM_E_DEVICE, "hipSetDevice failed");
-  hipStream_t st = (hipStream_t)g.D.stream;
-  const size_t all = 3 * (size_t)g.D.n * sizeof(double);
-  if (!g.fx) {
-    if (hipMalloc((void**)&g.fx, all) != hipSuccess) {
-      g.fx = nullptr;
-      return pfail(p, QNSIM_E_NOMEM, "force allocation failed");
-    }
-    if (hipMemsetAsync(g.fx, 0, all, st) != hipSuccess) return pfail(p, QNSIM_E_DEVICE, "force clear failed");
-    g.bytes += (int64_t)all;
-    p->used += (int64_t)all;
+  std::string err;
+  int rc = ensure_force_array(p, g, err);
+  if (!rc) rc = write_force(g, s.slot, s.c->n, f_ext, err);
+  if (!rc && hipStreamSynchronize((hipStream_t)g.D.stream) != hipSuccess) {
+    rc = QNSIM_E_DEVICE;
+    err = "force copy failed";
   }
-  double* dst = g.fx + 3 * (size_t)g.cv0[s.slot];
-  hipError_t e = f_ext ? hipMemcpyAsync(dst, f_ext, n3 * sizeof(double), hipMemcpyHostToDevice, st)
-                       : hipMemsetAsync(dst, 0, n3 * sizeof(double), st);
-  if (e == hipSuccess) e = hipStreamSynchronize(st);
-  if (e != hipSuccess) return pfail(p, QNSIM_E_DEVICE, hipGetErrorString(e));
+  if (rc) return pfail(p, rc, err);
   s.has_force = f_ext != nullptr;
+  if (f_ext) s.force.assign(f_ext, f_ext + n3);
+  else std::vector<double>().swap(s.force);
   return QNSIM_OK;
 }
 
@@ -587,7 +640,30 @@ int qnsim_pool_submit(qnsim_pool_t* p, int32_t id, int64_t* ticket) {
   if (!p->serving || p->stopping) return pfail(p, QNSIM_E_STATE, "the request loop is not running");
   if (!resident(p, id)) return pfail(p, QNSIM_E_INVALID, "id is not resident");
   const int64_t t = p->next_ticket++;
-  p->queue.push_back(Request{t, id, now_s()});
+  p->queue.push_back(Request{t, id, now_s(), nullptr});
+  *ticket = t;
+  p->cv.notify_all();
+  return QNSIM_OK;
+}
+
+int qnsim_pool_submit_force(qnsim_pool_t* p, int32_t id, const double* f_ext, int64_t* ticket) {
+  if (!p || !ticket) return QNSIM_E_INVALID;
+  std::shared_ptr<std::vector<double>> f;
+  {
+    std::lock_guard<std::mutex> lk(p->mu);
+    if (!resident(p, id)) return pfail(p, QNSIM_E_INVALID, "id is not resident");
+    if (f_ext) {
+      const size_t n3 = 3 * (size_t)p->sims[id].c->n;
+      for (size_t i = 0; i < n3; ++i)
+        if (!std::isfinite(f_ext[i])) return pfail(p, QNSIM_E_NONFINITE, "non-finite force");
+      f = std::make_shared<std::vector<double>>(f_ext, f_ext + n3);
+    }
+  }
+  std::lock_guard<std::mutex> lk(p->mu);
+  if (!p->serving || p->stopping) return pfail(p, QNSIM_E_STATE, "the request loop is not running");
+  if (!resident(p, id)) return pfail(p, QNSIM_E_INVALID, "id is not resident");
+  const int64_t t = p->next_ticket++;
+  p->queue.push_back(Request{t, id, now_s(), f});
   *ticket = t;
   p->cv.notify_all();
   return QNSIM_OK;

@@ -161,6 +161,7 @@ SIGNATURES = {
     "qnsim_pool_time_kernel": (ctypes.c_int, [_P, _I, _I, _I, ctypes.POINTER(_D)]),
     "qnsim_pool_set_h": (ctypes.c_int, [_P, _D, ctypes.POINTER(_D)]),
     "qnsim_pool_set_force": (ctypes.c_int, [_P, _I, _P]),
+    "qnsim_pool_submit_force": (ctypes.c_int, [_P, _I, _P, ctypes.POINTER(ctypes.c_int64)]),
     "qnsim_tune": (ctypes.c_int, [_P, _D, _P, _P, _I, _I, ctypes.POINTER(TuneInfo)]),
     "qnsim_pool_tune": (ctypes.c_int, [_P, _I, _I, _I, ctypes.POINTER(_I), ctypes.POINTER(_D)]),
 }
@@ -545,6 +546,15 @@ class Pool:
     def submit(self, sim_id: int) -> int:
         t = ctypes.c_int64()
         self._check(self._lib.qnsim_pool_submit(self._p, int(sim_id), ctypes.byref(t)))
+        return t.value
+
+    def submit_force(self, sim_id: int, f_ext) -> int:
+        """Step request whose step uses f_ext (n x 3, N) in place of the
+        simulation's own force."""
+        n = self.nverts[int(sim_id)]
+        f = _f64(f_ext, (n, 3))
+        t = ctypes.c_int64()
+        self._check(self._lib.qnsim_pool_submit_force(self._p, int(sim_id), _ptr(f), ctypes.byref(t)))
         return t.value
 
     def wait(self, ticket: int, timeout_s: float = -1.0):

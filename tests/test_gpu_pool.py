@@ -356,7 +356,9 @@ def test_pool_external_force():
     """qnsim_pool_set_force: a force on one member of a group of four gives,
     bit for bit, that simulation's steps alone with the same f_ext (full and
     partial batches, a served request); the other members equal their steps
-    alone without one; removing the force returns to gravity only."""
+    alone without one; removing the force returns to gravity only.
+    qnsim_pool_submit_force: the served step uses the request's force, and
+    the next one the simulation's own force (or none) again."""
     ws = [W.workload_block(W.NEOHOOKEAN if i % 2 == 0 else W.STVK, dims=(3 + i, 4, 3),
                            prestretch_seed=70 + i) for i in range(4)]
     p, ids = _pool(ws)
@@ -397,6 +399,24 @@ def test_pool_external_force():
     check(range(4), "force removed")
     moved = np.linalg.norm(state[1][0] - ws[1].rest)
     assert moved > 0.0
+    # a force for one served step only: in place of the simulation's own
+    # force (sim 1), or of none (sim 2); later steps use their own again
+    p.set_force(ids[1], f)
+    f2 = -2.0 * f
+    m2 = alone[2].masses()
+    f3 = m2[:, None] * rng.normal(scale=4.0, size=(ws[2].n_verts, 3))
+    p.serve_start(2)
+    p.wait(p.submit_force(ids[1], f2))
+    advance(1, f2)
+    p.wait(p.submit_force(ids[2], f3))
+    advance(2, f3)
+    check([1, 2], "served step with its own force")
+    p.wait(p.submit(ids[1]))
+    p.wait(p.submit(ids[2]))
+    p.serve_stop()
+    advance(1, f)
+    advance(2, None)
+    check([1, 2], "served step after the request's force")
     for s in alone:
         s.close()
     p.close()
