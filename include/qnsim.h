@@ -378,9 +378,11 @@ const char* qnsim_last_error(const qnsim_t* ctx);
  * step) or the serving loop (qnsim_pool_serve_start, qnsim_pool_submit,
  * qnsim_pool_wait). Pools use dense_top = 0 and level_merge = 0: a level
  * launch of a group serves all its simulations, so merging levels would only
- * add bytes. Every simulation uses the pool's h and gravity; the
- * external force is gravity only. Functions of one pool may be called from
- * several threads. */
+ * add bytes. Every simulation uses the pool's h (qnsim_pool_set_h changes
+ * it) and gravity, plus its own external force if one is set
+ * (qnsim_pool_set_force) or the request's (qnsim_pool_submit_force).
+ * qnsim_pool_tune picks each group's element tile. Functions of one pool may
+ * be called from several threads. */
 typedef struct qnsim_pool qnsim_pool_t;
 
 /* One simulation: mesh (as qnsim_set_mesh), pinned vertices (as
