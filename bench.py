@@ -398,8 +398,8 @@ def refactor_run(args, torch, W, qnsim):
 
 def tune_run(args, torch, W, qnsim):
     """qnsim_tune on the Neo-Hookean block: the four solve schedules, then the
-    three element tiles with the fastest schedule (informational: the headline
-    runs keep the default options)."""
+    three element tiles with the fastest schedule, then 1-3 line-search trials
+    per cycle (informational: the headline runs keep the default options)."""
     w = W.workload_block(W.NEOHOOKEAN, n=args.n)
     s = qnsim.sim_from_workload(w, **args.overrides)
     import numpy as np
@@ -413,8 +413,11 @@ def tune_run(args, torch, W, qnsim):
     log(f"[bench] tune block {args.n}^3: schedules " + ", ".join(
         f"{n} {m:.3f}" for n, m in zip(names, info["schedule_ms"])) + " ms/step; tiles " + ", ".join(
         f"{t} {m:.3f}" for t, m in zip((128, 256, 512), info["tile_ms"])) +
+        f" ms/step; trials per cycle " + ", ".join(
+        f"{t} {m:.3f}" for t, m in zip((1, 2, 3), info["trials_ms"])) +
         f" ms/step; kept dense_top {info['dense_top']}, subtree_cap {info['subtree_cap']}, "
-        f"level_merge {info['level_merge']}, elem_tile {info['elem_tile']} ({info['seconds']:.1f}s)")
+        f"level_merge {info['level_merge']}, elem_tile {info['elem_tile']}, "
+        f"trials_per_cycle {info['trials_per_cycle']} ({info['seconds']:.1f}s)")
     info["schedules"] = names
     return info
 

@@ -247,10 +247,14 @@ int qnsim_step_device(qnsim_t* ctx, const double* d_x, const double* d_v, double
  * level_merge = 0/0/0, 0/384/0, 0/384/1, 6144/384/1), each a new host
  * analysis and factorisation for h (section 3: the prefactored A); what =
  * 2: the element tile among 128, 256, 512 (the per-element gradient of
- * section 4.1); what = 0 or 3: the schedule, then the tile with that
- * schedule. The context keeps the fastest options and stays prepared for
- * h; the options are reported in *info with the measured milliseconds per
- * step (NaN: not timed). Results with different options agree to rounding.
+ * section 4.1); what = 4: line-search trials enqueued per iteration
+ * (trials_per_cycle 1, 2 or 3: the step's fixed launch sequence, with
+ * Algorithm 1's line search unchanged); bits combine, 0 = 7: the schedule,
+ * then the tile, then the trials. The context keeps the fastest options
+ * and stays prepared for h; the options are reported in *info with the
+ * measured milliseconds per step (NaN: not timed). Results with different
+ * schedules or tiles agree to rounding; the trials per cycle change no
+ * result.
  * Errors: QNSIM_E_INVALID, QNSIM_E_STATE / QNSIM_E_H_MISMATCH (not prepared
  * for h), QNSIM_E_NOMEM, QNSIM_E_DEVICE, QNSIM_E_NOT_SPD; on an error the
  * options return to their values before the call and the context is left
@@ -260,8 +264,11 @@ typedef struct {
   int32_t subtree_cap;
   int32_t level_merge;
   int32_t elem_tile;
+  int32_t trials_per_cycle;
+  int32_t reserved;
   double schedule_ms[4]; /* ms per step for the four schedules, in the order above */
   double tile_ms[3];     /* ms per step with the kept schedule, tiles 128, 256, 512 */
+  double trials_ms[3];   /* ms per step with the kept schedule and tile, 1, 2, 3 trials per cycle */
 } qnsim_tune_info;
 int qnsim_tune(qnsim_t* ctx, double h, const double* d_x, const double* d_v, int32_t reps,
                int32_t what, qnsim_tune_info* info);

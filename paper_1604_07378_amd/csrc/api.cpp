@@ -487,13 +487,14 @@ int qnsim_tune(qnsim_t* c, double h, const double* d_x, const double* d_v, int32
                int32_t what, qnsim_tune_info* info) {
   if (!c) return QNSIM_E_INVALID;
   if (!d_x || !d_v || !info) return fail(c, QNSIM_E_INVALID, "null pointer");
-  if (reps < 1 || reps > 1000 || what < 0 || what > 3)
-    return fail(c, QNSIM_E_INVALID, "reps must be 1..1000 and what 0..3");
+  if (reps < 1 || reps > 1000 || what < 0 || what > 7)
+    return fail(c, QNSIM_E_INVALID, "reps must be 1..1000 and what 0..7");
   int rc = check_step(c, h);
   if (rc) return rc;
-  if (what == 0) what = 3;
+  if (what == 0) what = 7;
   for (double& t : info->schedule_ms) t = NAN;
   for (double& t : info->tile_ms) t = NAN;
+  for (double& t : info->trials_ms) t = NAN;
   const size_t bytes = 3 * (size_t)c->n * sizeof(double);
   double *tx = nullptr, *tv = nullptr;
   if (hipSetDevice(c->opt.device) != hipSuccess) return fail(c, QNSIM_E_DEVICE, "hipSetDevice failed");
@@ -561,6 +562,17 @@ int qnsim_tune(qnsim_t* c, double h, const double* d_x, const double* d_v, int32
       rc = upload_ctx(c, err);
     }
   }
+  if (!rc && (what & 4)) {
+    // a step parameter: no rebuild, the step graph is captured again
+    int bbest = c->opt.trials_per_cycle;
+    best = INFINITY;
+    for (int b = 1; b <= 3 && !rc; ++b) {
+      c->opt.trials_per_cycle = b;
+      rc = time_steps(&info->trials_ms[b - 1]);
+      if (!rc && info->trials_ms[b - 1] < best) { best = info->trials_ms[b - 1]; bbest = b; }
+    }
+    c->opt.trials_per_cycle = bbest;
+  }
   (void)hipFree(tx);
   (void)hipFree(tv);
   if (rc) {
@@ -572,6 +584,8 @@ int qnsim_tune(qnsim_t* c, double h, const double* d_x, const double* d_v, int32
   info->subtree_cap = c->opt.subtree_cap;
   info->level_merge = c->opt.level_merge;
   info->elem_tile = c->opt.elem_tile > 0 ? c->opt.elem_tile : 256;
+  info->trials_per_cycle = c->opt.trials_per_cycle;
+  info->reserved = 0;
   return QNSIM_OK;
 }
 

@@ -72,12 +72,16 @@ class Stats(ctypes.Structure):
 class TuneInfo(ctypes.Structure):
     _fields_ = [("dense_top", ctypes.c_int32), ("subtree_cap", ctypes.c_int32),
                 ("level_merge", ctypes.c_int32), ("elem_tile", ctypes.c_int32),
-                ("schedule_ms", ctypes.c_double * 4), ("tile_ms", ctypes.c_double * 3)]
+                ("trials_per_cycle", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("schedule_ms", ctypes.c_double * 4), ("tile_ms", ctypes.c_double * 3),
+                ("trials_ms", ctypes.c_double * 3)]
 
     def as_dict(self):
         return dict(dense_top=self.dense_top, subtree_cap=self.subtree_cap,
                     level_merge=self.level_merge, elem_tile=self.elem_tile,
-                    schedule_ms=list(self.schedule_ms), tile_ms=list(self.tile_ms))
+                    trials_per_cycle=self.trials_per_cycle,
+                    schedule_ms=list(self.schedule_ms), tile_ms=list(self.tile_ms),
+                    trials_ms=list(self.trials_ms))
 
 
 class FactorInfo(ctypes.Structure):
@@ -376,11 +380,13 @@ class Sim:
                                                ctypes.byref(st)))
         return st.as_dict()
 
-    def tune(self, x, v, h: float, reps: int = 3, schedule: bool = True, tile: bool = True) -> dict:
-        """Keep the fastest solve schedule and element tile for steps from the
-        device state (x, v) (torch n x 3 float64 tensors, not modified)."""
+    def tune(self, x, v, h: float, reps: int = 3, schedule: bool = True, tile: bool = True,
+             trials: bool = True) -> dict:
+        """Keep the fastest solve schedule, element tile and line-search trials
+        per cycle for steps from the device state (x, v) (torch n x 3 float64
+        tensors, not modified)."""
         info = TuneInfo()
-        what = (1 if schedule else 0) | (2 if tile else 0)
+        what = (1 if schedule else 0) | (2 if tile else 0) | (4 if trials else 0)
         if what == 0:
             raise ValueError("nothing to tune")
         self._check(self._lib.qnsim_tune(self._h, float(h), _tptr(x), _tptr(v), int(reps), what,

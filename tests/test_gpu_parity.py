@@ -489,8 +489,10 @@ def test_tune_single_context():
     print(f"tune: {info}", flush=True)
     assert torch.equal(x, xc) and torch.equal(v, vc)
     assert np.isfinite(info["schedule_ms"]).all() and np.isfinite(info["tile_ms"]).all()
+    assert np.isfinite(info["trials_ms"]).all() and info["trials_per_cycle"] in (1, 2, 3)
     kept = dict(dense_top=info["dense_top"], subtree_cap=info["subtree_cap"],
-                level_merge=info["level_merge"], elem_tile=info["elem_tile"])
+                level_merge=info["level_merge"], elem_tile=info["elem_tile"],
+                trials_per_cycle=info["trials_per_cycle"])
     assert (kept["dense_top"], kept["subtree_cap"], kept["level_merge"]) in [
         (0, 0, 0), (0, 384, 0), (0, 384, 1), (6144, 384, 1)]
     assert kept["elem_tile"] in (128, 256, 512)

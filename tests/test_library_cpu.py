@@ -132,7 +132,7 @@ def test_errors_are_reported_not_raised_across_the_abi():
     info = qnsim.TuneInfo()
     fake = ctypes.c_void_p(64)
     assert s._lib.qnsim_tune(s._h, 1 / 30, fake, fake, 0, 0, ctypes.byref(info)) == -1
-    assert s._lib.qnsim_tune(s._h, 1 / 30, fake, fake, 2, 4, ctypes.byref(info)) == -1
+    assert s._lib.qnsim_tune(s._h, 1 / 30, fake, fake, 2, 8, ctypes.byref(info)) == -1
     assert s._lib.qnsim_tune(s._h, 1 / 30, None, fake, 2, 0, ctypes.byref(info)) == -1
     assert s._lib.qnsim_tune(s._h, 1 / 30, fake, fake, 2, 0, ctypes.byref(info)) == -8
 
