@@ -141,11 +141,16 @@ def batched_run(args, torch, W, qnsim, precision):
     tune = None
     if not args.no_tune:
         t_tu = time.perf_counter()
-        tiles, tms = p.tune(reps=3)
+        tiles, tms, trials, trms = p.tune(reps=3, trials=True)
         tune = dict(elem_tile=tiles[0], step_ms={t: m for t, m in zip((128, 256, 512), tms[0])},
+                    trials_per_cycle=trials[0],
+                    trials_ms={t: m for t, m in zip((1, 2, 3), trms[0])},
                     seconds=time.perf_counter() - t_tu)
-        log(f"[bench] element-tile tune: {tiles[0]} (ms per batched step "
-            + ", ".join(f"{t}: {m:.2f}" for t, m in tune["step_ms"].items()) + f"; {tune['seconds']:.1f}s)")
+        log(f"[bench] tune: element tile {tiles[0]} (ms per batched step "
+            + ", ".join(f"{t}: {m:.2f}" for t, m in tune["step_ms"].items())
+            + f"), trials per cycle {trials[0]} ("
+            + ", ".join(f"{t}: {m:.2f}" for t, m in tune["trials_ms"].items())
+            + f"); {tune['seconds']:.1f}s")
         p.step(ids)
     torch.cuda.synchronize()
     evals, trials = 0, 0

@@ -518,13 +518,17 @@ int qnsim_pool_set_h(qnsim_pool_t* pool, double h, double* device_ms);
  * elem_tile set to its group's tile. tiles: n_groups entries, the chosen tile
  * of each group in admission order (0: group with no resident member);
  * step_ms (nullable): n_groups x 3 measured milliseconds per step for the
- * tiles 128, 256, 512 (NaN: not a candidate). Needs the request loop
+ * tiles 128, 256, 512 (NaN: not a candidate). trials (nullable): with the
+ * kept tile, also time 1, 2 and 3 line-search trials enqueued per iteration
+ * (trials_per_cycle; no result changes) and keep the fastest for the group;
+ * n_groups entries, the kept value (0: group with no resident member);
+ * trials_ms (nullable): n_groups x 3 milliseconds per step. Needs the request loop
  * stopped (QNSIM_E_STATE); waits for running steps; other pool calls wait
  * until it returns. Errors: QNSIM_E_INVALID (bad mask, reps outside
  * 1..1000), QNSIM_E_NOMEM / QNSIM_E_DEVICE (the rebuild failed: the group
  * keeps its mesh). */
 int qnsim_pool_tune(qnsim_pool_t* pool, int32_t candidates, int32_t reps, int32_t n_groups,
-                    int32_t* tiles, double* step_ms);
+                    int32_t* tiles, double* step_ms, int32_t* trials, double* trials_ms);
 /* As qnsim_time_kernel, on group `group` (0-based, in admission order) with
  * every simulation of the group taking part; after at least one step of the
  * group. Not while the request loop runs. */

@@ -52,6 +52,7 @@ struct PoolGroup {
   int64_t bytes = 0;
   int live = 0;              // members not removed
   bool busy = false;         // a step is running
+  int trials = 0;            // line-search trials per cycle from the tuner (0: the pool's)
 };
 
 struct Request {
@@ -260,7 +261,9 @@ int step_group(qnsim_pool* p, PoolGroup& g, const std::vector<int>& slots,
   for (int s : slots) run[s] = 1;
   int rc = dev_set_run(g.D, run.data(), g.D.stream, err);
   if (rc) return rc;
-  rc = dev_step(g.D, pool_params(p), g.xs, g.vs, g.fx, g.xs, g.vs, g.D.stream, false, err);
+  StepParams prm = pool_params(p);
+  if (g.trials > 0) prm.budget = g.trials;
+  rc = dev_step(g.D, prm, g.xs, g.vs, g.fx, g.xs, g.vs, g.D.stream, false, err);
   if (rc) return rc;
   st.resize(slots.size());
   for (size_t i = 0; i < slots.size(); ++i) st[i] = g.D.stat_host[slots[i]];
@@ -787,7 +790,7 @@ int qnsim_pool_set_h(qnsim_pool_t* p, double h, double* device_ms) {
 }
 
 int qnsim_pool_tune(qnsim_pool_t* p, int32_t candidates, int32_t reps, int32_t n_groups,
-                    int32_t* tiles, double* step_ms) {
+                    int32_t* tiles, double* step_ms, int32_t* trials, double* trials_ms) {
   if (!p) return QNSIM_E_INVALID;
   if (candidates == 0) candidates = 7;
   if (candidates < 0 || candidates > 7)
@@ -803,10 +806,12 @@ int qnsim_pool_tune(qnsim_pool_t* p, int32_t candidates, int32_t reps, int32_t n
   });
   for (int gi = 0; gi < n_groups; ++gi) {
     tiles[gi] = 0;
-    if (step_ms)
-      for (int k = 0; k < 3; ++k) step_ms[3 * gi + k] = NAN;
+    if (trials) trials[gi] = 0;
+    for (int k = 0; k < 3; ++k) {
+      if (step_ms) step_ms[3 * gi + k] = NAN;
+      if (trials_ms) trials_ms[3 * gi + k] = NAN;
+    }
   }
-  const StepParams prm = pool_params(p);
   std::string err;
   for (int gi = 0; gi < (int)p->groups.size(); ++gi) {
     PoolGroup& g = *p->groups[gi];
@@ -825,6 +830,26 @@ int qnsim_pool_tune(qnsim_pool_t* p, int32_t candidates, int32_t reps, int32_t n
       if (tx) (void)hipFree(tx);
       return pfail(p, QNSIM_E_NOMEM, "tuning state allocation failed");
     }
+    StepParams prm = pool_params(p);
+    if (g.trials > 0) prm.budget = g.trials;
+    // ms per batched step of all members on mesh D from the members' states
+    auto timed = [&](DeviceMesh& D, const StepParams& P, double* ms) -> int {
+      hipStream_t st = (hipStream_t)D.stream;
+      std::vector<int> all(D.S, 1);
+      int r = dev_set_run(D, all.data(), D.stream, err);
+      if (!r && (hipMemcpyAsync(tx, g.xs, bytes, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+                 hipMemcpyAsync(tvl, g.vs, bytes, hipMemcpyDeviceToDevice, st) != hipSuccess)) {
+        err = "tuning state copy failed";
+        r = QNSIM_E_DEVICE;
+      }
+      // one untimed step (graph capture), then reps timed steps
+      if (!r) r = dev_step(D, P, tx, tvl, nullptr, tx, tvl, D.stream, false, err);
+      const double t0 = now_s();
+      for (int k = 0; k < reps && !r; ++k)
+        r = dev_step(D, P, tx, tvl, nullptr, tx, tvl, D.stream, false, err);
+      *ms = (now_s() - t0) * 1e3 / reps;
+      return r;
+    };
     DeviceMesh spare, cand;  // the fastest rebuilt mesh so far, the one being timed
     int best_tile = g.D.elem_tile;
     double best_ms = INFINITY;
@@ -842,21 +867,9 @@ int qnsim_pool_tune(qnsim_pool_t* p, int32_t candidates, int32_t reps, int32_t n
         if (rc) break;
         D = &cand;
       }
-      hipStream_t st = (hipStream_t)D->stream;
-      std::vector<int> all(D->S, 1);
-      rc = dev_set_run(*D, all.data(), D->stream, err);
-      if (!rc && (hipMemcpyAsync(tx, g.xs, bytes, hipMemcpyDeviceToDevice, st) != hipSuccess ||
-                  hipMemcpyAsync(tvl, g.vs, bytes, hipMemcpyDeviceToDevice, st) != hipSuccess)) {
-        err = "tuning state copy failed";
-        rc = QNSIM_E_DEVICE;
-      }
-      // one untimed step (graph capture), then reps timed steps
-      if (!rc) rc = dev_step(*D, prm, tx, tvl, nullptr, tx, tvl, D->stream, false, err);
-      const double t0 = now_s();
-      for (int r = 0; r < reps && !rc; ++r)
-        rc = dev_step(*D, prm, tx, tvl, nullptr, tx, tvl, D->stream, false, err);
+      double ms = 0.0;
+      rc = timed(*D, prm, &ms);
       if (rc) break;
-      const double ms = (now_s() - t0) * 1e3 / reps;
       if (step_ms && gi < n_groups) step_ms[3 * gi + k] = ms;
       if (ms < best_ms) {
         best_ms = ms;
@@ -865,21 +878,35 @@ int qnsim_pool_tune(qnsim_pool_t* p, int32_t candidates, int32_t reps, int32_t n
       }
       dev_free(cand);
     }
-    (void)hipFree(tx);
-    (void)hipFree(tvl);
-    if (rc) {
-      dev_free(cand);
-      dev_free(spare);
-      return pfail(p, rc, err);
-    }
-    if (best_tile != g.D.elem_tile) {
+    if (!rc && best_tile != g.D.elem_tile) {
       const int64_t old = (int64_t)g.D.bytes;
       std::swap(g.D, spare);
       p->used += (int64_t)g.D.bytes - old;
       g.bytes += (int64_t)g.D.bytes - old;
     }
+    dev_free(cand);
     dev_free(spare);
-    if (gi < n_groups) tiles[gi] = g.D.elem_tile;
+    // then the line-search trials per cycle with the kept tile
+    if (!rc && trials) {
+      int best_b = prm.budget;
+      best_ms = INFINITY;
+      for (int b = 1; b <= 3 && !rc; ++b) {
+        StepParams pb = prm;
+        pb.budget = b;
+        double ms = 0.0;
+        rc = timed(g.D, pb, &ms);
+        if (!rc && trials_ms && gi < n_groups) trials_ms[3 * gi + b - 1] = ms;
+        if (!rc && ms < best_ms) { best_ms = ms; best_b = b; }
+      }
+      if (!rc) g.trials = best_b;
+    }
+    (void)hipFree(tx);
+    (void)hipFree(tvl);
+    if (rc) return pfail(p, rc, err);
+    if (gi < n_groups) {
+      tiles[gi] = g.D.elem_tile;
+      if (trials) trials[gi] = g.trials > 0 ? g.trials : p->opt.trials_per_cycle;
+    }
   }
   return QNSIM_OK;
 }

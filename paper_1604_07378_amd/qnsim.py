@@ -167,7 +167,8 @@ SIGNATURES = {
     "qnsim_pool_set_force": (ctypes.c_int, [_P, _I, _P]),
     "qnsim_pool_submit_force": (ctypes.c_int, [_P, _I, _P, ctypes.POINTER(ctypes.c_int64)]),
     "qnsim_tune": (ctypes.c_int, [_P, _D, _P, _P, _I, _I, ctypes.POINTER(TuneInfo)]),
-    "qnsim_pool_tune": (ctypes.c_int, [_P, _I, _I, _I, ctypes.POINTER(_I), ctypes.POINTER(_D)]),
+    "qnsim_pool_tune": (ctypes.c_int, [_P, _I, _I, _I, ctypes.POINTER(_I), ctypes.POINTER(_D),
+                                       ctypes.POINTER(_I), ctypes.POINTER(_D)]),
 }
 
 _lib = None
@@ -586,18 +587,25 @@ class Pool:
         self._check(self._lib.qnsim_pool_set_h(self._p, float(h), ctypes.byref(ms)))
         return ms.value
 
-    def tune(self, reps: int = 3, candidates=(128, 256, 512)):
+    def tune(self, reps: int = 3, candidates=(128, 256, 512), trials: bool = False):
         """Element-tile autotuning of every resident group among the candidate
         tiles: returns the chosen tile per group (admission order, 0 for a
         group with no resident member) and the measured milliseconds per
         batched step for the tiles 128, 256, 512 (groups x 3, NaN where not
-        measured)."""
+        measured). With trials, also the kept line-search trials per cycle per
+        group and their milliseconds per step (for 1, 2, 3), as two more lists."""
         mask = sum({128: 1, 256: 2, 512: 4}[int(t)] for t in set(candidates))
         n = self.info()["groups_made"]
         tiles = (_I * max(n, 1))()
         ms = (_D * (3 * max(n, 1)))()
-        self._check(self._lib.qnsim_pool_tune(self._p, mask, int(reps), n, tiles, ms))
-        return [int(tiles[i]) for i in range(n)], [[float(ms[3 * i + k]) for k in range(3)] for i in range(n)]
+        tr = (_I * max(n, 1))()
+        tms = (_D * (3 * max(n, 1)))()
+        self._check(self._lib.qnsim_pool_tune(self._p, mask, int(reps), n, tiles, ms,
+                                              tr if trials else None, tms if trials else None))
+        out = ([int(tiles[i]) for i in range(n)], [[float(ms[3 * i + k]) for k in range(3)] for i in range(n)])
+        if trials:
+            out += ([int(tr[i]) for i in range(n)], [[float(tms[3 * i + k]) for k in range(3)] for i in range(n)])
+        return out
 
     def info(self) -> dict:
         i = PoolInfo()

@@ -326,10 +326,12 @@ def test_pool_tune_element_tiles():
             assert np.array_equal(x, ref[j][k][0]), f"tile 512, sim {j} step {k}"
             assert np.array_equal(v, ref[j][k][1])
     start = [p.get_state(i) for i in ids]
-    tiles, ms = p.tune(reps=2)
-    print(f"tune: tiles {tiles}, ms per step {ms}", flush=True)
+    tiles, ms, trials, tms = p.tune(reps=2, trials=True)
+    print(f"tune: tiles {tiles}, ms per step {ms}; trials per cycle {trials}, ms {tms}", flush=True)
     assert all(t in (128, 256, 512) for t in tiles)
     assert all(np.isfinite(m).all() and min(m) > 0.0 for m in ms)
+    assert all(t in (1, 2, 3) for t in trials)
+    assert all(np.isfinite(m).all() and min(m) > 0.0 for m in tms)
     for j, i in enumerate(ids):
         assert np.array_equal(p.get_state(i)[0], start[j][0])
     ref = [_alone_from(w, *start[j], 2, elem_tile=tiles[j // 3]) for j, w in enumerate(ws)]

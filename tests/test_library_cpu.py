@@ -195,8 +195,8 @@ def test_pool_staging_and_validation_on_host():
     assert p.tune() == ([], [])                   # no group yet: nothing to time
     import ctypes
     tiles = (ctypes.c_int32 * 1)()
-    assert p._lib.qnsim_pool_tune(p._p, 8, 1, 1, tiles, None) == -1   # bad candidate mask
-    assert p._lib.qnsim_pool_tune(p._p, 0, 0, 1, tiles, None) == -1   # reps < 1
+    assert p._lib.qnsim_pool_tune(p._p, 8, 1, 1, tiles, None, None, None) == -1   # bad candidate mask
+    assert p._lib.qnsim_pool_tune(p._p, 0, 0, 1, tiles, None, None, None) == -1   # reps < 1
     p.remove(ids[2])
     assert p.info()["sims_staged"] == 4
     p.close()
