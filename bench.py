@@ -521,7 +521,7 @@ def main():
         args.overrides[key.strip()] = int(val)
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
+        print("bench.py measures one GPU: the library has no multi-GPU path "
               "(independent simulations would be sharded by simulation, one process per GPU); "
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
