@@ -209,6 +209,17 @@ def served_run(args, torch, W, qnsim):
         f"groups, {info['used_bytes'] / 1e9:.2f} GB; analysis {t_an:.1f}s, upload {t_up:.1f}s")
     # capacity: every resident simulation stepped once, groups concurrently
     p.step(res_ids)
+    tune = None
+    if not args.no_tune:
+        # line-search trials per cycle per group (the element tile stays at
+        # 256: rebuilding groups of 500 simulations is not worth its time here)
+        t_tu = time.perf_counter()
+        _, _, trials, trms = p.tune(reps=2, candidates=(256,), trials=True)
+        tune = dict(trials_per_cycle=trials, trials_ms=trms, seconds=time.perf_counter() - t_tu)
+        log(f"[bench] pool tune: trials per cycle per group {trials} "
+            f"({tune['seconds']:.1f}s; ms per group step for 1/2/3: "
+            + "; ".join("/".join(f"{m:.0f}" for m in g) for g in trms) + ")")
+        p.step(res_ids)
     t0 = time.perf_counter()
     p.step(res_ids)
     cap = len(res_ids) / (time.perf_counter() - t0)
@@ -256,7 +267,7 @@ def served_run(args, torch, W, qnsim):
     return dict(sims=len(ws), admitted=admitted, tets=T, groups=info["groups"], group_size=group,
                 precision="mixed" if args.pool_precision else "f64",
                 device_gb=info["used_bytes"] / 1e9, budget_gb=args.pool_budget_gb,
-                lanes=args.pool_lanes, capacity_steps_per_s=cap, rates=rates,
+                lanes=args.pool_lanes, capacity_steps_per_s=cap, tune=tune, rates=rates,
                 batches=info["batches_done"], analysis_s=t_an, upload_s=t_up,
                 set_h_device_ms=h_ms, set_h_first_s=h_first_s)
 
