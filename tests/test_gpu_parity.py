@@ -551,3 +551,30 @@ def test_resume_from_saved_state():
         x, v, _ = s.step(x, v, w.h)
         assert np.array_equal(x, traj[k][0]) and np.array_equal(v, traj[k][1]), f"step {k}"
     s.close()
+
+
+@pytest.mark.parametrize("max_halvings", [0, 1, 4])
+def test_line_search_exhaustion(max_halvings):
+    """A StVK cantilever thrown with random 5 m/s vertex velocities: with at
+    most 0, 1 or 4 halvings the first iteration's line search fails (up to 5
+    trials, more than one cycle's budget of 2); the iterate stays where the
+    iteration started and the step's remaining iterations are skipped. GPU
+    and oracle agree on the statistics exactly and on the positions to 1e-9."""
+    w = W.workload_cantilever(0, kind=W.STVK)
+    m = _model(w)
+    rng = np.random.default_rng(4)
+    v0 = 5.0 * rng.normal(size=w.rest.shape)
+    v0[w.pinned] = 0.0
+    s = qnsim.sim_from_workload(w, max_halvings=max_halvings)
+    x_o, v_o = w.rest.copy(), v0.copy()
+    x_g, v_g = w.rest.copy(), v0.copy()
+    for k in range(3):
+        r = oracle.step(m, x_o, v_o, max_halvings=max_halvings)
+        x_o, v_o = r.x, r.v
+        x_g, v_g, st = s.step(x_g, v_g, w.h)
+        assert r.ls_exhausted == 1, "the case must exhaust its line search"
+        assert (st["ls_exhausted"], st["iterations_run"], st["ls_trials"]) == \
+            (r.ls_exhausted, r.iterations_run, r.ls_trials), f"step {k}"
+        assert _eps(x_g, x_o, w.rest) <= 1e-9, f"step {k}"
+        assert np.abs(v_g - v_o).max() <= 1e-9 * max(np.abs(v_o).max(), 1.0)
+    s.close()
