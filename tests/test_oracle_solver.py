@@ -376,6 +376,34 @@ def test_paper_claims_plausibility():
     assert e5 < 2.0 * e_newton1
 
 
+@pytest.mark.parametrize("kind", [W.NEOHOOKEAN, W.STVK])
+def test_results_insensitive_to_the_fit_interval(kind):
+    """Section 5 (stiffness fit): the interval [x_start, x_end] of the linear
+    fit that sets k changes the convergence little. One step of the cantilever
+    (from a perturbed state) with the intervals [0.5, 1.5], [0.3, 1.7] and
+    [0.7, 1.3]: k changes, and the relative error after 10 iterations stays
+    below 1e-3 and within a factor of 5 of the default interval's (Neo-Hookean:
+    7.3e-5, 2.5e-4, 4.2e-5, so "little" is read as the same order)."""
+    w = W.workload_cantilever(0, kind=kind)
+    rng = np.random.default_rng(11)
+    x = w.rest + 0.05 * w.edge * rng.uniform(-1, 1, size=w.rest.shape)
+    x[w.pinned] = w.rest[w.pinned]
+    v = w.v0
+    errs, ks = [], []
+    for lo, hi in [(0.5, 1.5), (0.3, 1.7), (0.7, 1.3)]:
+        m = oracle.build_model(w.rest, w.tets, w.pinned, w.materials, w.tet_mat, w.h, w.gravity,
+                               fit_lo=lo, fit_hi=hi)
+        y = fem.inertia_target(m, x, v)
+        x_star, g_star = newton.newton_minimise(m, y, y, tol=1e-9)
+        g0 = fem.objective(m, y, y)
+        r = solver.step(m, x, v)
+        errs.append(newton.relative_error(r.g_last, g0, g_star))
+        ks.append(m.k.copy())
+    assert not np.allclose(ks[0], ks[1]) and not np.allclose(ks[0], ks[2])
+    assert all(e < 1e-3 for e in errs), errs
+    assert max(errs) <= 5.0 * errs[0] and min(errs) >= errs[0] / 5.0, errs
+
+
 # ---------------------------------------------------------------------------
 # Collisions (section 4.3)
 # ---------------------------------------------------------------------------
