@@ -506,27 +506,28 @@ int qnsim_pool_get_info(qnsim_pool_t* pool, qnsim_pool_info* info);
  * returned (QNSIM_E_NOT_SPD, QNSIM_E_NOMEM, QNSIM_E_DEVICE). *device_ms
  * (nullable): the device time of the refactorisations. */
 int qnsim_pool_set_h(qnsim_pool_t* pool, double h, double* device_ms);
-/* Element-tile autotuning of the pool's element pass (the per-element gradient
- * of E, section 4.1). For each resident group, times reps
- * batched steps of all its members (after one untimed step) with each
- * candidate element tile (candidates: a mask of 1 = 128, 2 = 256, 4 = 512
- * tets per block; 0: all three), on a copy of the members' states, and
- * keeps the fastest candidate: the group's device mesh is rebuilt with that
- * tile (for a tile other than the current one, a second copy of the group's
- * device mesh exists during the call). Members' states are unchanged. Later
- * steps of a simulation equal, bit for bit, its steps alone with
- * elem_tile set to its group's tile. tiles: n_groups entries, the chosen tile
- * of each group in admission order (0: group with no resident member);
- * step_ms (nullable): n_groups x 3 measured milliseconds per step for the
- * tiles 128, 256, 512 (NaN: not a candidate). trials (nullable): with the
- * kept tile, also time 1, 2 and 3 line-search trials enqueued per iteration
- * (trials_per_cycle; no result changes) and keep the fastest for the group;
- * n_groups entries, the kept value (0: group with no resident member);
- * trials_ms (nullable): n_groups x 3 milliseconds per step. Needs the request loop
- * stopped (QNSIM_E_STATE); waits for running steps; other pool calls wait
- * until it returns. Errors: QNSIM_E_INVALID (bad mask, reps outside
- * 1..1000), QNSIM_E_NOMEM / QNSIM_E_DEVICE (the rebuild failed: the group
- * keeps its mesh). */
+/* Autotuning of a pool's groups: the element tile of the element pass (the
+ * per-element gradient of E, section 4.1) and, optionally, the line-search
+ * trials enqueued per iteration. For each resident group, times reps batched
+ * steps of all its members (after one untimed step) with each candidate
+ * element tile (candidates: a mask of 1 = 128, 2 = 256, 4 = 512 tets per
+ * block; 0: all three), on a copy of the members' states, and keeps the
+ * fastest candidate: the group's device mesh is rebuilt with that tile (for
+ * a tile other than the current one, a second copy of the group's device
+ * mesh exists during the call). Members' states are unchanged. Later steps
+ * of a simulation equal, bit for bit, its steps alone with elem_tile set to
+ * its group's tile. tiles: n_groups entries, the chosen tile of each group
+ * in admission order (0: group with no resident member); step_ms (nullable):
+ * n_groups x 3 measured milliseconds per step for the tiles 128, 256, 512
+ * (NaN: not a candidate). trials (nullable): with the kept tile, also time
+ * 1, 2 and 3 line-search trials enqueued per iteration (trials_per_cycle; no
+ * result changes) and keep the fastest for the group; n_groups entries, the
+ * kept value (0: group with no resident member); trials_ms (nullable):
+ * n_groups x 3 milliseconds per step. Needs the request loop stopped
+ * (QNSIM_E_STATE); waits for running steps; other pool calls wait until it
+ * returns. Errors: QNSIM_E_INVALID (bad mask, reps outside 1..1000),
+ * QNSIM_E_NOMEM / QNSIM_E_DEVICE (the rebuild failed: the group keeps its
+ * mesh). */
 int qnsim_pool_tune(qnsim_pool_t* pool, int32_t candidates, int32_t reps, int32_t n_groups,
                     int32_t* tiles, double* step_ms, int32_t* trials, double* trials_ms);
 /* As qnsim_time_kernel, on group `group` (0-based, in admission order) with
