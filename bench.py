@@ -113,8 +113,27 @@ def run_material(kind, args, torch, W, qnsim, extra=None):
     res["kernel_ms"] = dict(element=el_ms, gather=ga_ms, solve=so_ms)
     res["element_bytes"] = element_bytes(w.n_tets, w.n_verts, info["n_free"])
     res["solve_bytes"] = solve_bytes(info["nnz_L_exact"], info["n_free"])
+    res["residual"] = gradient_reduction(sim, x, v, w.h, args.residual_steps)
     sim.close()
     return res
+
+
+def gradient_reduction(sim, x, v, h, steps):
+    """The "fixed L-BFGS residual" of the timed schedule: |grad g(x_final)| /
+    |grad g(x_1)| per step (one extra gradient pass per step, untimed), over
+    `steps` further steps from the state the timed run left."""
+    import numpy as np
+    if steps <= 0:
+        return None
+    sim.set_diagnostics(True)
+    red = []
+    for _ in range(steps):
+        st = sim.step_device(x, v, h)
+        red.append(st["grad_norm_last"] / st["grad_norm_first"])
+    sim.set_diagnostics(False)
+    r = np.array(red)
+    return {"steps": steps, "grad_reduction_median": float(np.median(r)),
+            "grad_reduction_max": float(r.max())}
 
 
 def _pool_of(ws, qnsim, budget, group, **opt):
@@ -299,6 +318,45 @@ def small_runs(args, torch, W, qnsim):
     return out
 
 
+def relative_error_run(args, torch, W, qnsim, steps=100, k_star=300):
+    """Eq. RelativeError (section 5) on the 540-tet Neo-Hookean cantilever:
+    per step, (g(x_K) - g*) / (g(x_1) - g*) after the K = 10 iterations of the
+    timed schedule, with g* from k_star iterations of the same method from the
+    same state (converged: the relative gradient falls below 1e-9), plus the
+    per-step gradient reduction |grad g(x_K)| / |grad g(x_1)|. Steps follow the
+    10-iteration trajectory from rest."""
+    import numpy as np
+    w = W.workload_cantilever(0)
+    run = qnsim.sim_from_workload(w)
+    ref = qnsim.sim_from_workload(w, iterations=k_star)
+    run.set_diagnostics(True)
+    ref.set_diagnostics(True)
+    x = torch.from_numpy(w.x0.copy()).cuda()
+    v = torch.from_numpy(w.v0.copy()).cuda()
+    xs, vs = torch.empty_like(x), torch.empty_like(v)
+    rel, red, red_star = [], [], []
+    for _ in range(steps):
+        st_ref = ref.step_device(x, v, w.h, x_out=xs, v_out=vs)
+        st = run.step_device(x, v, w.h)                # in place: the trajectory
+        g_star = st_ref["g_last"]
+        den = st["g_first"] - g_star
+        rel.append((st["g_last"] - g_star) / den if den > 0 else 0.0)
+        red.append(st["grad_norm_last"] / st["grad_norm_first"])
+        red_star.append(st_ref["grad_norm_last"] / st_ref["grad_norm_first"])
+    run.close()
+    ref.close()
+    rel, red = np.array(rel), np.array(red)
+    out = {"workload": "cantilever 10x3x3 cubes (540 tets), Neo-Hookean, FP64, 100 steps from rest",
+           "iterations": 10, "g_star_iterations": k_star,
+           "relative_error_median": float(np.median(rel)), "relative_error_max": float(rel.max()),
+           "grad_reduction_median": float(np.median(red)), "grad_reduction_max": float(red.max()),
+           "g_star_grad_reduction_max": float(max(red_star))}
+    log(f"[bench] relative error (Eq. RelativeError) on the cantilever: median "
+        f"{out['relative_error_median']:.2e}, max {out['relative_error_max']:.2e}; gradient "
+        f"reduction median {out['grad_reduction_median']:.2e}")
+    return out
+
+
 def mixed_error_run(args, torch, W, qnsim, steps=300):
     """Mixed precision on the mixed-stiffness cantilever (E log-uniform in
     [1e4, 1e7] Pa): per-step position error of the mixed path against the
@@ -449,15 +507,28 @@ def _cpu_model():
     return None
 
 
-def cpu_baseline(args, W):
-    """The FP64 oracle on a bounded sample: one step of the Neo-Hookean block."""
-    import numpy as np  # noqa: F401
-    import oracle
+def _thread_pools():
+    """The BLAS / OpenMP thread pools NumPy and SciPy run on, and the
+    environment variables that size them."""
+    pools = []
     try:
         from threadpoolctl import threadpool_info
-        cores = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+        for p in threadpool_info():
+            pools.append({"api": p.get("user_api"), "library": p.get("internal_api"),
+                          "threads": p.get("num_threads")})
     except Exception:
-        cores = os.cpu_count() or 1
+        pass
+    env = {k: os.environ[k] for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS",
+                                      "MKL_NUM_THREADS", "BLIS_NUM_THREADS") if k in os.environ}
+    return pools, env
+
+
+def cpu_baseline(args, W):
+    """The FP64 oracle on a bounded sample: a few steps of the Neo-Hookean block."""
+    import numpy as np  # noqa: F401
+    import oracle
+    pools, env = _thread_pools()
+    cores = max([p["threads"] or 1 for p in pools] + [1]) if pools else (os.cpu_count() or 1)
     w = W.workload_block(W.NEOHOOKEAN, n=args.n)
     t0 = time.time()
     m = oracle.build_model(w.rest, w.tets, w.pinned, w.materials, w.tet_mat, w.h, w.gravity)
@@ -484,7 +555,8 @@ def cpu_baseline(args, W):
     return {"value": steps / dt, "unit": "timesteps/s", "cores": int(cores), "kind": "oracle",
             "sample": f"{steps} step(s) of the Neo-Hookean {args.n}^3 block ({w.n_tets:,} tets) after an "
                       f"untimed {build:.1f}s model build and banded Cholesky factorisation",
-            "value_one_thread": one, "cpu": _cpu_model()}
+            "seconds": dt, "value_one_thread": one, "cpu": _cpu_model(),
+            "os_cpu_count": os.cpu_count(), "thread_pools": pools, "thread_env": env}
 
 
 def main():
@@ -495,7 +567,10 @@ def main():
     ap.add_argument("--n", type=int, default=40, help="cubes per axis of the block")
     ap.add_argument("--materials", default="neohookean,stvk,spline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-steps", type=int, default=3)
+    ap.add_argument("--cpu-sample-steps", type=int, default=5,
+                    help="oracle steps of the CPU baseline (about 5-6 s each on 16 cores)")
+    ap.add_argument("--residual-steps", type=int, default=3,
+                    help="untimed steps per block run that report the gradient reduction")
     ap.add_argument("--no-convergence", action="store_true",
                     help="skip the convergence comparison of the direction methods")
     ap.add_argument("--no-refactor", action="store_true",
@@ -562,6 +637,7 @@ def main():
         mixed = run_material(W.NEOHOOKEAN, args, torch, W, qnsim, {"precision": qnsim.QNSIM_MIXED})
 
     small = small_runs(args, torch, W, qnsim) if args.small_steps > 0 else []
+    relerr = relative_error_run(args, torch, W, qnsim) if args.small_steps > 0 else None
     mixed_err = mixed_error_run(args, torch, W, qnsim) if not args.no_mixed else None
     conv = convergence_run(args, torch, W, qnsim) if not args.no_convergence else None
     batched = []
@@ -612,13 +688,15 @@ def main():
         },
         "tet_evals_per_s": tet_evals / total_s,
         "runs": [{k: r[k] for k in ("material", "steps_per_s", "ls_trials", "iterations",
-                                    "exhausted", "kernel_ms", "nnz_L", "levels", "prepare_s")}
+                                    "exhausted", "kernel_ms", "nnz_L", "levels", "prepare_s",
+                                    "residual")}
                  for r in runs],
         "step_time_share_ms": per_step,
         **({"mixed_precision_run": {k: mixed[k] for k in ("material", "steps_per_s", "ls_trials",
                                                          "iterations", "kernel_ms")}}
            if mixed else {}),
         **({"small_meshes": small} if small else {}),
+        **({"relative_error": relerr} if relerr else {}),
         **({"mixed_precision_error": mixed_err} if mixed_err else {}),
         **({"convergence": conv} if conv else {}),
         **({"batched": batched} if batched else {}),

@@ -199,11 +199,19 @@ int qnsim_set_mesh(qnsim_t* ctx, int32_t n_verts, const double* rest_xyz,
 
 /* Pinned (Dirichlet) vertices: they keep their input positions, enter the
  * element deformation gradients, and are eliminated from A and the solver
- * vectors. n_pinned = 0 clears the set. Invalidates a previous prepare. */
+ * vectors. n_pinned = 0 clears the set. Invalidates a previous prepare.
+ * (The paper states no boundary conditions; its scenes hold vertices fixed,
+ * section 5. Elimination keeps A = M/h^2 + L of section 3, Eq. PDsolution,
+ * symmetric positive definite on the free vertices.) */
 int qnsim_set_pinned(qnsim_t* ctx, int32_t n_pinned, const int32_t* idx);
 
 /* Materials: n_mat entries; tet_mat[T] gives each tet's material index, or
- * NULL to use material 0 everywhere. Invalidates a previous prepare. */
+ * NULL to use material 0 everywhere. Invalidates a previous prepare. Each
+ * material is an energy density Psi(F) of the deformation gradient of a
+ * tetrahedron (section 4.1: isotropic Valanis-Landel energies written in the
+ * principal stretches, Neo-Hookean and StVK among them; spline-based
+ * materials; section 4, "Anisotropy" for the fibre term); its stiffness k
+ * for A comes from Eq. stiffness (section 4.1). */
 int qnsim_set_materials(qnsim_t* ctx, int32_t n_mat, const qnsim_material* mats,
                         const int32_t* tet_mat);
 
@@ -220,14 +228,19 @@ int qnsim_prepare(qnsim_t* ctx, double h);
 int qnsim_analyze(qnsim_t* ctx, double h);
 
 /* One time step from host arrays (n x 3): x, v in; x_out, v_out out (may alias
- * x and v). f_ext may be NULL (gravity only). h must equal the prepared h.
+ * x and v). The step minimises g of Eq. PD (section 3) with
+ * y = x + h v + h^2 M^{-1} f_ext by Algorithm 1 (section 4.1) with the
+ * direction of Algorithm 2 (section 4.2), and returns x' = x_{K+1},
+ * v' = (x' - x)/h. f_ext may be NULL (gravity only). h must equal the
+ * prepared h.
  * Returns QNSIM_E_INVERTED if a Neo-Hookean element has J <= 0 at x.
  * Synchronises. stats may be NULL. */
 int qnsim_step(qnsim_t* ctx, const double* x, const double* v, double h,
                const double* f_ext, double* x_out, double* v_out, qnsim_stats* stats);
 
-/* One time step from device arrays (n x 3 doubles, caller's numbering) on the
- * given stream (hipStream_t as void*; NULL = the null stream: the step then
+/* One time step from device arrays (n x 3 doubles, caller's numbering): the
+ * same step as qnsim_step (Eq. PD, section 3; Algorithms 1 and 2, sections
+ * 4.1 and 4.2), on the given stream (hipStream_t as void*; NULL = the null stream: the step then
  * runs on the context's own stream, after the work already submitted to the
  * null stream). x_out / v_out may alias x / v. The inverted-input check of
  * qnsim_step is not made here: an infeasible x shows up as a non-finite
@@ -296,7 +309,9 @@ int qnsim_set_diagnostics(qnsim_t* ctx, int32_t final_gradient);
  * The probes (qnsim_eval_device) evaluate g without them. */
 int qnsim_set_colliders(qnsim_t* ctx, int32_t n_planes, const double* planes, double stiffness);
 
-/* Per-tet stiffness k (T doubles), available after qnsim_analyze/prepare. */
+/* Per-tet stiffness k (T doubles), available after qnsim_analyze/prepare:
+ * the slope of the least-squares line through the material's stress-stretch
+ * profile over [fit_lo, fit_hi] (section 4.1, Eq. stiffness). */
 int qnsim_get_stiffness(const qnsim_t* ctx, double* k);
 
 /* Lumped vertex masses (n doubles), available after qnsim_analyze/prepare. */
@@ -313,7 +328,8 @@ int qnsim_export_factor(const qnsim_t* ctx, int32_t* perm, int64_t* colptr,
                         int32_t* rowidx, double* values);
 
 /* Numeric refactorisation on the device for a new time step h. A = M/h^2 +
- * sum_e V_e k_e G_e^T G_e (sections 3.2 and 4.1) depends on h, and the method
+ * sum_e V_e k_e G_e^T G_e (section 3, Eq. PDsolution; section 4.1,
+ * Eq. stiffness for k_e) depends on h, and the method
  * prefactors it once per step size. This keeps the ordering and the
  * supernodal structure of the prepared factor and recomputes its values on
  * the device: a multifrontal Cholesky factorisation level by level of the
@@ -496,7 +512,7 @@ int qnsim_pool_serve_stop(qnsim_pool_t* pool);
 
 int qnsim_pool_get_info(qnsim_pool_t* pool, qnsim_pool_info* info);
 
-/* Change the pool's time step to h (sections 3.2 and 4.1: A = M/h^2 + L
+/* Change the pool's time step to h (section 3, Eq. PDsolution: A = M/h^2 + L
  * depends on h). Every resident group's A is refactored on the device (as
  * qnsim_refactor; the first call per group builds its refactorisation plan,
  * whose device memory is outside the pool's budget); staged simulations are

@@ -530,25 +530,32 @@ int qnsim_pool_step(qnsim_pool_t* p, int32_t n, const int32_t* ids, qnsim_stats*
     slots[s.group].push_back(s.slot);
     where[s.group].push_back(i);
   }
+  // The groups are taken by pointer while the lock is held: a concurrent
+  // commit may grow p->groups (moving its elements, not the groups).
   std::vector<int> gl;
+  std::vector<PoolGroup*> gp;
   for (int g = 0; g < (int)p->groups.size(); ++g)
-    if (!slots[g].empty()) { gl.push_back(g); p->groups[g]->busy = true; }
+    if (!slots[g].empty()) {
+      gl.push_back(g);
+      gp.push_back(p->groups[g].get());
+      gp.back()->busy = true;
+    }
   lk.unlock();
   std::vector<int> rcs(gl.size(), 0);
   std::vector<std::string> errs(gl.size());
   std::vector<std::vector<SimStat>> st(gl.size());
   if (gl.size() == 1) {
-    rcs[0] = step_group(p, *p->groups[gl[0]], slots[gl[0]], st[0], errs[0]);
+    rcs[0] = step_group(p, *gp[0], slots[gl[0]], st[0], errs[0]);
   } else {
     std::vector<std::thread> th;
     for (size_t k = 0; k < gl.size(); ++k)
-      th.emplace_back([&, k]() { rcs[k] = step_group(p, *p->groups[gl[k]], slots[gl[k]], st[k], errs[k]); });
+      th.emplace_back([&, k]() { rcs[k] = step_group(p, *gp[k], slots[gl[k]], st[k], errs[k]); });
     for (auto& t : th) t.join();
   }
   lk.lock();
   int rc = 0;
   for (size_t k = 0; k < gl.size(); ++k) {
-    p->groups[gl[k]]->busy = false;
+    gp[k]->busy = false;
     if (rcs[k] && !rc) { rc = rcs[k]; p->last_error = errs[k]; }
     if (!rcs[k] && stats)
       for (size_t j = 0; j < where[gl[k]].size(); ++j) stats_of(st[k][j], &stats[where[gl[k]][j]]);

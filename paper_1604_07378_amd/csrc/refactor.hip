@@ -1,5 +1,6 @@
 // Numeric refactorisation on the device. The matrix of the global step,
-// A = M/h^2 + sum_e V_e k_e G_e^T G_e (sections 3.2 and 4.1), is constant for
+// A = M/h^2 + sum_e V_e k_e G_e^T G_e (section 3, Eq. PDsolution; section
+// 4.1, Eq. stiffness for k_e), is constant for
 // a fixed step size and is factored once; when h changes only its values
 // change. This file keeps the ordering and the supernodal structure found by
 // the host analysis and recomputes the values on the device:

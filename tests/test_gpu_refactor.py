@@ -1,6 +1,6 @@
 """GPU: numeric refactorisation of A = M/h^2 + sum V k G^T G on the device
 for a new time step (the matrix is constant for a fixed h and prefactored,
-sections 3.2 and 4.1).
+section 3, Eq. PDsolution; section 4.1, Eq. stiffness).
 
 The refactored solve is checked against the oracle's solve with A assembled
 for the new h, the steps that follow against the oracle's steps at that h, and

@@ -109,6 +109,30 @@ def test_A_is_spd_and_solve_is_exact():
     assert np.abs(lu.solve(q) - r).max() < 1e-12 * np.abs(r).max()
 
 
+def test_banded_solve_is_exact_on_a_large_block():
+    """The large-system branch of the solve (reverse Cuthill-McKee band and a
+    banded Cholesky factor, used above 4000 free vertices, so at every block
+    size the parity tests run) against the definition r = A^{-1} q (section 3,
+    Eq. PDsolution): the residual of A r = q at rounding level, and the same
+    r from an unrelated sparse LU factorisation. A permutation applied the
+    wrong way round, a dropped band diagonal or a transposed band fails both."""
+    import scipy.sparse.linalg as spla
+    w = W.workload_block(n=20)
+    m = _model(w)
+    assert m.n_free == 8820 and m.n_free > 4000       # the banded branch
+    rng = np.random.default_rng(11)
+    q = rng.normal(size=(m.n_free, 3))
+    r = m.solve(q)
+    A = m.A.tocsr()
+    normA = abs(A).sum(axis=1).max()                  # infinity norm of A
+    assert np.abs(A @ r - q).max() <= 1e-13 * normA * np.abs(r).max()
+    lu = spla.splu(m.A.tocsc(), permc_spec="COLAMD")
+    assert np.abs(lu.solve(q) - r).max() <= 1e-12 * np.abs(r).max()
+    # a right-hand side that is A times a known vector gives that vector back
+    x_true = rng.normal(size=(m.n_free, 3))
+    assert np.abs(m.solve(A @ x_true) - x_true).max() <= 1e-10 * np.abs(x_true).max()
+
+
 @pytest.mark.parametrize("kind", [W.NEOHOOKEAN, W.STVK, W.SPLINE, W.COROTATED, W.POLYNOMIAL, "fiber"])
 def test_gradient_matches_finite_differences(kind):
     """grad g by central differences of g over every free coordinate."""
