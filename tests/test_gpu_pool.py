@@ -90,6 +90,51 @@ def test_batch_mixed_materials_against_alone_and_oracle():
     p.close()
 
 
+@pytest.mark.timeout(600)
+def test_batch_with_a_large_mesh_equals_alone_and_oracle():
+    """A 22 x 20 x 21 block (55,440 tets: the per-level solve items and
+    element blocks of the pool options at scale) among five small blocks of
+    mixed materials, in one group. Steps alternate between the whole batch
+    and partial batches (compacted launch lists) that include or leave out
+    the large block; every simulation equals its run alone with as many
+    steps, bit for bit, and the large block's first two steps match the
+    oracle at 1e-9 (section 4.1, Algorithm 1)."""
+    big = W.workload_block(W.NEOHOOKEAN, dims=(22, 20, 21), prestretch_seed=7)
+    small = W.workload_batch(count=5, seed=11, lo=3, hi=6)
+    ws = [small[0], small[1], big, small[2], small[3], small[4]]
+    p, ids = _pool(ws)
+    assert p.info()["groups"] == 1
+    plan = [list(range(6)), [2, 0], list(range(6)), [1, 3, 4], [2, 5]]
+    counts = [0] * 6
+    for sub in plan:
+        for j in sub:
+            counts[j] += 1
+    ref = [_alone(w, max(counts[j], 1)) for j, w in enumerate(ws)]
+    done = [0] * 6
+    for k, sub in enumerate(plan):
+        p.step([ids[j] for j in sub])
+        for j in sub:
+            done[j] += 1
+        for j in range(6):
+            if done[j] == 0:
+                continue
+            x, v = p.get_state(ids[j])
+            xr, vr = ref[j][done[j] - 1]
+            assert np.array_equal(x, xr) and np.array_equal(v, vr), \
+                f"batch step {k}, sim {j} ({ws[j].n_tets} tets) after {done[j]} steps: " \
+                f"eps vs alone {_eps(x, xr, ws[j].rest):.3e}"
+    m = oracle.build_model(big.rest, big.tets, big.pinned, big.materials, big.tet_mat, big.h,
+                           big.gravity)
+    x, v = big.x0.copy(), big.v0.copy()
+    for k in range(2):
+        r = oracle.step(m, x, v)
+        x, v = r.x, r.v
+        e = _eps(ref[2][k][0], r.x, big.rest)
+        assert e <= 1e-9, f"large block step {k}: eps vs oracle {e:.3e}"
+    print(f"large block in a batch of 6: bitwise equal alone over {plan}", flush=True)
+    p.close()
+
+
 def test_batch_with_mooney_rivlin_equals_alone():
     """Neo-Hookean, Mooney-Rivlin and spline blocks in one group (one element
     launch per material type), 5 steps: each equals its run alone, bit for
