@@ -364,6 +364,22 @@ int qnsim_element_stress_device(qnsim_t* ctx, const double* d_x, double* d_psi,
  * in q and set to zero in r. Stream-ordered. */
 int qnsim_solve_device(qnsim_t* ctx, const double* d_q, double* d_r, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the solve
+ * of qnsim_solve_device, with the same arguments, kernels and results (bit
+ * for bit), whose working memory (permuted right-hand side and solution,
+ * forward intermediate, update layers, dense top block right-hand side) lives
+ * in a fixed 16 MiB device array of the library instead of the context's
+ * buffers; it calls no allocation routine. Each GPU holds its own copy of the
+ * array until the process ends, and every call on a GPU shares it: calls that
+ * overlap on one GPU (other streams or threads) race and must be serialised
+ * by the caller. The array keeps the last call's contents; the call clears
+ * what must start at zero. Returns QNSIM_E_INVALID when the mesh needs more
+ * working memory than the array holds (about 9 n_free + the update layers
+ * doubles: the 40^3 block fits), QNSIM_E_STATE before qnsim_prepare,
+ * QNSIM_E_DEVICE on a HIP error. Stream-ordered, like qnsim_solve_device. */
+int qnsim_solve_device_noalloc(qnsim_t* ctx, const double* d_q, double* d_r, void* stream);
+
 /* ---- measurement -------------------------------------------------------- */
 
 /* Kernels that qnsim_time_kernel can time in isolation. */

@@ -789,6 +789,14 @@ int qnsim_solve_device(qnsim_t* c, const double* d_q, double* d_r, void* stream)
   return rc ? fail(c, rc, err) : QNSIM_OK;
 }
 
+int qnsim_solve_device_noalloc(qnsim_t* c, const double* d_q, double* d_r, void* stream) {
+  if (!c || !d_q || !d_r) return QNSIM_E_INVALID;
+  if (!c->prepared) return fail(c, QNSIM_E_STATE, "qnsim_prepare has not been called");
+  std::string err;
+  int rc = dev_solve_noalloc(c->dev, d_q, d_r, stream ? stream : c->dev.stream, err);
+  return rc ? fail(c, rc, err) : QNSIM_OK;
+}
+
 int qnsim_time_kernel(qnsim_t* c, int32_t kernel, int32_t reps, double* avg_ms) {
   if (!c || !avg_ms || reps < 1 || kernel < QNSIM_KERNEL_ELEMENT || kernel > QNSIM_KERNEL_SOLVE)
     return QNSIM_E_INVALID;

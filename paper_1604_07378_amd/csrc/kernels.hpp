@@ -226,6 +226,7 @@ struct DeviceMesh {
   int* rows = nullptr;        // below-diagonal rows of each supernode
   int* rel = nullptr;         // layered position of each below row in the parent's layers
   double* vp = nullptr;       // update layers of every supernode (children's updates)
+  long long vp_len = 0;       // doubles of vp
   std::vector<Level> levels;  // item ranges per tree level (levels >= sub_levels)
   // bottom subtrees: levels < sub_levels, one workgroup per subtree
   int sub_levels = 0, sub_tasks = 0;
@@ -281,11 +282,28 @@ struct StepParams {
 };
 
 
+// Working memory of one solve besides its input and output: the forward
+// intermediate z (nf x 3), the children's update layers (vp_len doubles,
+// zero wherever no child writes) and the dense top block's right-hand side
+// (top_n x 3).
+struct SolveScratch {
+  double* z;
+  double* vp;
+  double* top_t;
+};
+
 // Prefactored solve r = A^{-1} q on the stream (internal order, nf x 3).
 // gate: if not null, the launches do nothing while *gate <= 0; sim_ctl: if
-// not null, only the supernodes of simulations in PH_DIR are solved.
+// not null, only the supernodes of simulations in PH_DIR are solved; scr: if
+// not null, the solve's working memory (else the mesh's own buffers).
 void launch_solve(DeviceMesh& D, hipStream_t st, const double* q, double* r, const int* gate,
-                  const Ctl* sim_ctl = nullptr);
+                  const Ctl* sim_ctl = nullptr, const SolveScratch* scr = nullptr);
+
+// dst[i] = src[vperm[i]] (rows of 3 doubles, i < n); and its inverse
+// dst[vperm[i]] = i < nf ? src[i] : 0 for i < n.
+void launch_load_perm(hipStream_t st, int n, const int* vperm, const double* src, double* dst);
+void launch_store_perm(hipStream_t st, int n, int nf, const int* vperm, const double* src,
+                       double* dst);
 
 // Workgroups of the dense top product for an n-column block: rows are split
 // evenly, at most 32 per workgroup, at most 256 workgroups unless more are
@@ -325,6 +343,9 @@ int dev_eval(DeviceMesh& d, const double* x, const double* y, double* g_out, dou
 int dev_element_stress(DeviceMesh& d, const double* x, double* psi, double* P, void* stream,
                        std::string& err);
 int dev_solve(DeviceMesh& d, const double* q, double* r, void* stream, std::string& err);
+// The same solve with its working memory in the library's fixed device
+// scratch array instead of the mesh's buffers; allocates nothing.
+int dev_solve_noalloc(DeviceMesh& d, const double* q, double* r, void* stream, std::string& err);
 int dev_time_kernel(DeviceMesh& d, int kernel, int reps, double* avg_ms, std::string& err);
 int dev_check_inverted(DeviceMesh& d, const double* x, void* stream, int* inverted,
                        std::string& err);

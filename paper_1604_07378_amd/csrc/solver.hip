@@ -1522,6 +1522,15 @@ int dev_element_stress(DeviceMesh& D, const double* x, double* psi, double* P, v
   return 0;
 }
 
+void launch_load_perm(hipStream_t st, int n, const int* vperm, const double* src, double* dst) {
+  hipLaunchKernelGGL(k_load_perm, dim3(nblk(n)), dim3(BS), 0, st, n, vperm, src, dst);
+}
+
+void launch_store_perm(hipStream_t st, int n, int nf, const int* vperm, const double* src,
+                       double* dst) {
+  hipLaunchKernelGGL(k_store_perm, dim3(nblk(n)), dim3(BS), 0, st, n, nf, vperm, src, dst);
+}
+
 int dev_solve(DeviceMesh& D, const double* q, double* r, void* stream, std::string& err) {
   hipStream_t st = (hipStream_t)stream;
   hipLaunchKernelGGL(k_load_perm, dim3(nblk(D.nf)), dim3(BS), 0, st, D.nf, D.vperm, q, D.q);

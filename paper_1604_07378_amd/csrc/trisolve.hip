@@ -732,7 +732,10 @@ k_top_gemv(const double* __restrict__ Sinv, const double* __restrict__ t, int n,
 }
 
 void launch_solve(DeviceMesh& D, hipStream_t st, const double* q, double* r, const int* gate,
-                  const Ctl* sim_ctl) {
+                  const Ctl* sim_ctl, const SolveScratch* scr) {
+  double* const zb = scr ? scr->z : D.z;
+  double* const vp = scr ? scr->vp : D.vp;
+  double* const top_t = scr ? scr->top_t : D.top_t;
   if (D.compact) {
     // partial batch: every level of the stepping simulations, one launch each
     const ItemDesc* items = reinterpret_cast<const ItemDesc*>(D.cbuf + D.c_items_off);
@@ -741,43 +744,43 @@ void launch_solve(DeviceMesh& D, hipStream_t st, const double* q, double* r, con
       const int n = D.c_levels[l].fw_end - D.c_levels[l].fw_begin;
       if (n > 0)
         hipLaunchKernelGGL(k_solve_fwd, dim3(n), dim3(TS), 0, st, items + D.c_levels[l].fw_begin,
-                           D.Bf, D.rel, q, D.z, D.vp, gate, sim_ctl);
+                           D.Bf, D.rel, q, zb, vp, gate, sim_ctl);
     }
     for (int l = L - 1; l >= 0; --l) {
       const int n = D.c_levels[l].bw_end - D.c_levels[l].bw_begin;
       if (n > 0)
         hipLaunchKernelGGL(k_solve_bwd, dim3(n), dim3(TS), 0, st, items + D.c_levels[l].bw_begin,
-                           D.Bb, D.rows, D.z, r, gate, sim_ctl);
+                           D.Bb, D.rows, zb, r, gate, sim_ctl);
     }
     return;
   }
   const int L = (int)D.levels.size();
   if (D.sub_tasks > 0)
     hipLaunchKernelGGL(k_solve_fwd_sub, dim3(D.sub_tasks), dim3(kSubThreads), 0, st, D.sub_fw,
-                       D.sub_fw_ptr, D.sub_levels, D.Bf, D.rel, q, D.z, D.vp, gate, sim_ctl);
+                       D.sub_fw_ptr, D.sub_levels, D.Bf, D.rel, q, zb, vp, gate, sim_ctl);
   for (int l = D.sub_levels; l < L; ++l) {
     const int n = D.levels[l].fw_end - D.levels[l].fw_begin;
     if (n > 0)
       hipLaunchKernelGGL(k_solve_fwd, dim3(n), dim3(TS), 0, st, D.items + D.levels[l].fw_begin,
-                         D.Bf, D.rel, q, D.z, D.vp, gate, sim_ctl);
+                         D.Bf, D.rel, q, zb, vp, gate, sim_ctl);
   }
   if (D.top_n > 0) {
     const int n = D.top_n, n3 = 3 * n;
     hipLaunchKernelGGL(k_top_assemble, dim3((n3 + TS - 1) / TS), dim3(TS), 0, st,
-                       q + 3 * (size_t)D.top_first, D.vp + D.top_vp, D.top_nch, n3, D.top_t, gate);
+                       q + 3 * (size_t)D.top_first, vp + D.top_vp, D.top_nch, n3, top_t, gate);
     const int nwg = top_workgroups(n);
     hipLaunchKernelGGL(k_top_gemv, dim3(nwg), dim3(kTopThreads), 0, st, D.Bf + D.top_off,
-                       D.top_t, n, nwg, r + 3 * (size_t)D.top_first, gate);
+                       top_t, n, nwg, r + 3 * (size_t)D.top_first, gate);
   }
   for (int l = L - 1; l >= D.sub_levels; --l) {
     const int n = D.levels[l].bw_end - D.levels[l].bw_begin;
     if (n > 0)
       hipLaunchKernelGGL(k_solve_bwd, dim3(n), dim3(TS), 0, st, D.items + D.levels[l].bw_begin,
-                         D.Bb, D.rows, D.z, r, gate, sim_ctl);
+                         D.Bb, D.rows, zb, r, gate, sim_ctl);
   }
   if (D.sub_tasks > 0)
     hipLaunchKernelGGL(k_solve_bwd_sub, dim3(D.sub_tasks), dim3(kSubThreads), 0, st, D.sub_bw,
-                       D.sub_bw_ptr, D.sub_levels, D.Bb, D.rows, D.z, r, gate, sim_ctl);
+                       D.sub_bw_ptr, D.sub_levels, D.Bb, D.rows, zb, r, gate, sim_ctl);
 }
 
 }  // namespace qn

@@ -609,6 +609,7 @@ int upload_sims(const std::vector<const qnsim*>& sims, const qnsim_options& opt,
   {
     std::vector<double> zv((size_t)vp_total + 3, 0.0);  // zero once: see child slots
     UP(D.vp, zv);
+    D.vp_len = vp_total + 3;
   }
   // block tables of the segmented kernels: each simulation's blocks start
   // at its own first tet / free vertex / entry, as when it runs alone

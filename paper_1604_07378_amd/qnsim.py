@@ -142,6 +142,7 @@ SIGNATURES = {
     "qnsim_eval_device": (ctypes.c_int, [_P, _P, _P, ctypes.POINTER(_D), _P, _P]),
     "qnsim_element_stress_device": (ctypes.c_int, [_P, _P, _P, _P, _P]),
     "qnsim_solve_device": (ctypes.c_int, [_P, _P, _P, _P]),
+    "qnsim_solve_device_noalloc": (ctypes.c_int, [_P, _P, _P, _P]),
     "qnsim_refactor": (ctypes.c_int, [_P, _D, ctypes.POINTER(_D)]),
     "qnsim_time_kernel": (ctypes.c_int, [_P, _I, _I, ctypes.POINTER(_D)]),
     "qnsim_strerror": (ctypes.c_char_p, [ctypes.c_int]),
@@ -414,6 +415,12 @@ class Sim:
     def solve_device(self, q, r_out, stream=None):
         self._check(self._lib.qnsim_solve_device(self._h, _tptr(q), _tptr(r_out),
                                                  _stream_ptr(stream)))
+
+    def solve_device_noalloc(self, q, r_out, stream=None):
+        """As solve_device, with the working memory in the library's fixed
+        device array (no allocation); stream-ordered."""
+        self._check(self._lib.qnsim_solve_device_noalloc(self._h, _tptr(q), _tptr(r_out),
+                                                         _stream_ptr(stream)))
 
     def refactor(self, h: float) -> float:
         """Refactor A for step size h on the device; returns the device time in ms."""
