@@ -291,6 +291,107 @@ def served_run(args, torch, W, qnsim):
                 set_h_device_ms=h_ms, set_h_first_s=h_first_s)
 
 
+def admission_run(args, torch, W, qnsim, windows=6, per_window=1500, retire_frac=0.12):
+    """Admission under a binding budget while serving: the 2,000 pool
+    descriptions against a 20 GB budget, so that only part of them is
+    resident. Poisson requests for the resident simulations run throughout;
+    in each window a client thread retires the oldest resident simulations
+    (waits for their requests, removes them) and commits, admitting staged
+    simulations as the budget frees (groups whose removed members hold half
+    of their memory are rebuilt first), while the main thread keeps
+    submitting. Reports per window: resident count, device GB, admitted,
+    commit seconds, requests completed during the commit, p50/p99."""
+    import threading
+    import numpy as np
+    descs = W.workload_pool(count=args.pool_count, seed=0)
+    ws = [W.workload_block(d["kind"], dims=d["dims"], edge=d["edge"], prestretch_seed=d["seed"],
+                           spline_seed=d["seed"], nu=d["nu"]) for d in descs]
+    budget = int(args.admission_budget_gb * 10**9)
+    p, ids, admitted, t_an, t_up = _pool_of(ws, qnsim, budget, args.admission_group,
+                                            precision=args.pool_precision)
+    resident = [i for i in ids if p.status(i)[0] == "resident"]
+    log(f"[bench] admission: budget {args.admission_budget_gb:.0f} GB, {admitted} of {len(ids)} "
+        f"admitted ({p.info()['used_bytes'] / 1e9:.2f} GB; analysis {t_an:.1f}s, upload {t_up:.1f}s)")
+    p.step(resident)
+    t0 = time.perf_counter()
+    p.step(resident)
+    cap = len(resident) / (time.perf_counter() - t0)
+    rate = args.admission_load * cap
+    rng = np.random.default_rng(np.random.SeedSequence([0xAD1, 0]))
+    p.serve_start(lanes=args.pool_lanes)
+    outstanding = {}                      # sim -> tickets not yet waited for
+    lock = threading.Lock()
+    out = []
+    t_run = time.perf_counter()
+    for wnd in range(windows):
+        active = list(resident)
+        n_ret = max(1, int(retire_frac * len(active)))
+        retire, keep = active[:n_ret], active[n_ret:]
+        box = {}
+
+        def churn(retire=retire, box=box):
+            with lock:
+                pend = [t for sid in retire for t in outstanding.pop(sid, [])]
+            lats = [p.wait(t, 120.0)[1] for t in pend]
+            for sid in retire:
+                p.remove(sid)
+            done0 = p.info()["steps_done"]
+            c0 = time.perf_counter()
+            box["admitted"] = p.commit(args.admission_group)
+            box["commit_s"] = time.perf_counter() - c0
+            box["during"] = p.info()["steps_done"] - done0
+            box["lat"] = lats
+
+        th = threading.Thread(target=churn)
+        started = False
+        tickets = []
+        t_start = time.perf_counter()
+        t_next = t_start
+        who = rng.integers(0, len(keep), size=per_window)
+        for k, g in enumerate(rng.exponential(1.0 / rate, size=per_window)):
+            if k == per_window // 4 and not started:
+                th.start()
+                started = True
+            t_next += g
+            while True:
+                d = t_next - time.perf_counter()
+                if d <= 0:
+                    break
+                time.sleep(min(d, 0.002) if d > 0.0005 else 0)
+            sid = keep[int(who[k])]
+            t = p.submit(sid)
+            with lock:
+                outstanding.setdefault(sid, []).append(t)
+            tickets.append((sid, t))
+        th.join()
+        lat = list(box["lat"])
+        for sid, t in tickets:
+            with lock:
+                mine = t in outstanding.get(sid, [])
+                if mine:
+                    outstanding[sid].remove(t)
+            if mine:
+                lat.append(p.wait(t, 120.0)[1])
+        lat = np.array(lat)
+        resident = [i for i in ids if p.status(i)[0] == "resident"]
+        info = p.info()
+        r = dict(window=wnd, t_s=time.perf_counter() - t_run, resident=len(resident),
+                 staged=info["sims_staged"], device_gb=info["used_bytes"] / 1e9,
+                 retired=len(retire), admitted=box["admitted"], commit_s=box["commit_s"],
+                 steps_during_commit=box["during"], requests=int(lat.size),
+                 p50_ms=float(np.percentile(lat, 50) * 1e3), p99_ms=float(np.percentile(lat, 99) * 1e3))
+        out.append(r)
+        log(f"[bench] admission window {wnd}: resident {r['resident']} ({r['device_gb']:.2f} GB), "
+            f"retired {r['retired']}, admitted {r['admitted']} in {r['commit_s']:.2f}s "
+            f"({r['steps_during_commit']} steps served meanwhile), p50 {r['p50_ms']:.1f} ms, "
+            f"p99 {r['p99_ms']:.1f} ms")
+    p.serve_stop()
+    p.close()
+    return dict(sims=len(ws), budget_gb=args.admission_budget_gb, initial_admitted=admitted,
+                group_size=args.admission_group, offered_steps_per_s=rate,
+                capacity_steps_per_s=cap, windows=out)
+
+
 def small_runs(args, torch, W, qnsim):
     """Latency-bound small meshes: the 540-tet cantilever (FP64, with and
     without the captured step graph) and the mixed-stiffness cantilever in
@@ -373,9 +474,11 @@ def mixed_error_run(args, torch, W, qnsim, steps=300):
     xf, vf = x.clone(), v.clone()          # free-running mixed trajectory
     xm, vm = torch.empty_like(x), torch.empty_like(v)
     per_step, free = [], {}
+    flips = 0          # steps whose line searches took other decisions than FP64's
     for k in range(steps):
-        mix.step_device(x, v, w.h, x_out=xm, v_out=vm, stats=False)
-        f64.step_device(x, v, w.h, stats=False)           # in place: the FP64 trajectory
+        sm = mix.step_device(x, v, w.h, x_out=xm, v_out=vm)
+        sf = f64.step_device(x, v, w.h)                   # in place: the FP64 trajectory
+        flips += int(sm["ls_trials"] != sf["ls_trials"] or sm["iterations_run"] != sf["iterations_run"])
         mix.step_device(xf, vf, w.h, stats=False)
         den = max(float(torch.linalg.norm(x - rest)), 1e-300)
         per_step.append(float(torch.linalg.norm(xm - x)) / den)
@@ -387,9 +490,11 @@ def mixed_error_run(args, torch, W, qnsim, steps=300):
     out = dict(workload="cantilever 10x3x3 cubes (540 tets), Neo-Hookean, E log-uniform in [1e4, 1e7] Pa",
                steps=steps, reference="FP64 GPU path from the same state",
                per_step_error_max=float(e.max()), per_step_error_median=float(np.median(e)),
-               free_running_error={str(k): v for k, v in free.items()}, tolerance=1e-4)
+               free_running_error={str(k): v for k, v in free.items()}, tolerance=1e-4,
+               steps_with_other_line_search=flips)
     log(f"[bench] mixed precision error over {steps} steps (vs FP64 GPU path, same state): "
-        f"max {e.max():.2e}, median {np.median(e):.2e}; free-running "
+        f"max {e.max():.2e}, median {np.median(e):.2e}; {flips} steps with other line-search "
+        f"decisions; free-running "
         + ", ".join(f"step {k} {v:.1e}" for k, v in free.items()))
     return out
 
@@ -598,6 +703,12 @@ def main():
     ap.add_argument("--pool-load", default="0.25,0.5,0.8,1.2",
                     help="offered loads as fractions of the measured capacity")
     ap.add_argument("--pool-precision", type=int, default=1, help="1: mixed, 0: FP64")
+    ap.add_argument("--admission-budget-gb", type=float, default=20.0,
+                    help="budget of the admission run (0: skip it)")
+    ap.add_argument("--admission-group", type=int, default=64,
+                    help="simulations per group in the admission run")
+    ap.add_argument("--admission-load", type=float, default=0.5,
+                    help="offered load of the admission run, fraction of its capacity")
     ap.add_argument("--set", action="append", default=[], metavar="OPTION=INT",
                     help="override an integer solver option (e.g. level_merge=0, dense_top=0)")
     args = ap.parse_args()
@@ -644,6 +755,8 @@ def main():
     if args.batch_count > 0:
         batched = [batched_run(args, torch, W, qnsim, 0), batched_run(args, torch, W, qnsim, 1)]
     served = served_run(args, torch, W, qnsim) if args.pool_count > 0 else None
+    admission = (admission_run(args, torch, W, qnsim)
+                 if args.pool_count > 0 and args.admission_budget_gb > 0 else None)
     refac = refactor_run(args, torch, W, qnsim) if not args.no_refactor else None
     tuned = tune_run(args, torch, W, qnsim) if not args.no_tune else None
 
@@ -701,6 +814,7 @@ def main():
         **({"convergence": conv} if conv else {}),
         **({"batched": batched} if batched else {}),
         **({"served": served} if served else {}),
+        **({"admission": admission} if admission else {}),
         **({"refactor": refac} if refac else {}),
         **({"tune": tuned} if tuned else {}),
         "roofline": {

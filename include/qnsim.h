@@ -355,7 +355,9 @@ int qnsim_eval_device(qnsim_t* ctx, const double* d_x, const double* d_y,
                       double* g_out, double* d_grad, void* stream);
 
 /* Per-element energy density Psi (T doubles) and first Piola stress P
- * (T x 9, row-major 3x3 per tet) at positions d_x. Synchronises. */
+ * (T x 9, row-major 3x3 per tet) at positions d_x, evaluated as the element
+ * pass does in the context's precision mode (QNSIM_MIXED: FP32 from the
+ * displacement gradient, returned widened to FP64). Synchronises. */
 int qnsim_element_stress_device(qnsim_t* ctx, const double* d_x, double* d_psi,
                                 double* d_P, void* stream);
 
@@ -475,11 +477,22 @@ int qnsim_pool_add(qnsim_pool_t* pool, int32_t n, const qnsim_mesh_desc* descs, 
 /* Uploads staged simulations (in id order) into new groups of at most
  * max_group_sims simulations (<= 0: one group), skipping any whose estimated
  * device memory does not fit the remaining budget (they stay staged).
- * *n_admitted (nullable) receives the number admitted. */
+ * *n_admitted (nullable) receives the number admitted. Allowed while the
+ * request loop runs: the admission is planned under the pool's lock, the
+ * groups are built and uploaded without it (resident groups keep stepping on
+ * their own streams), and the new simulations become resident, able to take
+ * requests, when their group is published. A group whose removed members
+ * hold at least half of its estimated memory is first rebuilt with its live
+ * members (states and forces copied on the device; its requests wait
+ * meanwhile), and the memory it frees counts for the admission. One commit
+ * runs at a time (later ones wait); on a failure the simulations of the
+ * failed group and of the groups after it stay staged and the first error
+ * is returned. */
 int qnsim_pool_commit(qnsim_pool_t* pool, int32_t max_group_sims, int32_t* n_admitted);
 
 /* Removes a resident or staged simulation; a group's device memory is freed
- * when its last simulation is removed. */
+ * when its last simulation is removed, or returned by the next commit's
+ * rebuild when removed members hold half of it. */
 int qnsim_pool_remove(qnsim_pool_t* pool, int32_t id);
 
 /* One step of each listed resident simulation (distinct ids): groups run
@@ -527,6 +540,14 @@ int qnsim_pool_wait(qnsim_pool_t* pool, int64_t ticket, double timeout_s, qnsim_
 int qnsim_pool_serve_stop(qnsim_pool_t* pool);
 
 int qnsim_pool_get_info(qnsim_pool_t* pool, qnsim_pool_info* info);
+
+/* Where simulation id is: QNSIM_SIM_STAGED (added, not admitted, or being
+ * admitted by a running commit), QNSIM_SIM_RESIDENT (in a group; *group, if
+ * non-null, receives its index) or QNSIM_SIM_REMOVED (*group = -1). */
+#define QNSIM_SIM_STAGED 0
+#define QNSIM_SIM_RESIDENT 1
+#define QNSIM_SIM_REMOVED 2
+int qnsim_pool_status(qnsim_pool_t* pool, int32_t id, int32_t* status, int32_t* group);
 
 /* Change the pool's time step to h (section 3, Eq. PDsolution: A = M/h^2 + L
  * depends on h). Every resident group's A is refactored on the device (as

@@ -106,12 +106,17 @@ __device__ __forceinline__ void givens_qr(R B[3][3], R U[3][3], int i, int j, in
   }
 }
 
+// The signed SVD of F with V taken from the Jacobi eigenvectors of S, a
+// symmetric matrix with the eigenvectors of F^T F: F^T F itself, or (mixed
+// precision) the Green strain E = (F^T F - I)/2 formed accurately from the
+// displacement gradient, whose eigenvectors are not blurred by the rounding
+// of the 1 on the diagonal when the stretches are close together.
 template <typename R>
-__device__ __forceinline__ void svd3(const M3<R>& F, R U[3][3], R sig[3], R V[3][3]) {
+__device__ __forceinline__ void svd3_basis(const M3<R>& F, const R S0[3][3], R U[3][3], R sig[3],
+                                           R V[3][3]) {
   R S[3][3];
   for (int i = 0; i < 3; ++i)
-    for (int j = 0; j < 3; ++j)
-      S[i][j] = F.a[0][i] * F.a[0][j] + F.a[1][i] * F.a[1][j] + F.a[2][i] * F.a[2][j];
+    for (int j = 0; j < 3; ++j) S[i][j] = S0[i][j];
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j) V[i][j] = (i == j) ? R(1) : R(0);
   // cyclic sweeps until one rotates nothing (at most 6; quadratic convergence)
@@ -149,6 +154,15 @@ __device__ __forceinline__ void svd3(const M3<R>& F, R U[3][3], R sig[3], R V[3]
   }
 }
 
+template <typename R>
+__device__ __forceinline__ void svd3(const M3<R>& F, R U[3][3], R sig[3], R V[3][3]) {
+  R S[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j)
+      S[i][j] = F.a[0][i] * F.a[0][j] + F.a[1][i] * F.a[1][j] + F.a[2][i] * F.a[2][j];
+  svd3_basis(F, S, U, sig, V);
+}
+
 // Spline stretch term: a(s), a'(s) from the knot tables (knots 0.2 + 0.4 j).
 template <typename R>
 __device__ __forceinline__ void spline_eval(const DevMat& m, R s, R& a, R& da) {
@@ -173,6 +187,36 @@ __device__ __forceinline__ void spline_eval(const DevMat& m, R s, R& a, R& da) {
   R c0 = R(m.d2[j]), slope = (R(m.d2[j + 1]) - c0) / dk;
   a = R(m.a0[j]) + R(m.a1[j]) * x + c0 * x * x * R(0.5) + slope * x * x * x * (R(1) / R(6));
   da = R(m.a1[j]) + c0 * x + slope * x * x * R(0.5);
+}
+
+// The same spline in FP32 as a function of x1 = s - 1 (given accurately).
+// The segment is found from s = 1 + x1; its cubic is expanded about its
+// nearer end knot k (the same cubic: a'' is linear on the segment, a''' its
+// constant slope), a(s) = a(k) + a'(k) x + a''(k) x^2/2 + a''' x^3/6 with
+// x = s - k = x1 + (1 - k). Near rest the nearer knot is k = 1 itself, where
+// x = x1 exactly and a(1) = a'(1) = 0, so a and a' keep their relative
+// accuracy at small strain instead of cancelling O(1) terms of the segment.
+__device__ __forceinline__ void spline_eval_m1(const DevMat& m, float x1, float& a, float& da) {
+  const float s = 1.0f + x1;
+  if (s < 0.2f || s > 3.0f) {
+    const int j = s < 0.2f ? 0 : 7;
+    const float x = s < 0.2f ? s - 0.2f : s - 3.0f;
+    a = (float)m.a0[j] + (float)m.a1[j] * x + (float)m.d2[j] * x * x * 0.5f;
+    da = (float)m.a1[j] + (float)m.d2[j] * x;
+    return;
+  }
+  int j = (int)((s - 0.2f) / 0.4f);
+  j = j < 0 ? 0 : (j > 6 ? 6 : j);
+  const float slope = ((float)m.d2[j + 1] - (float)m.d2[j]) / 0.4f;  // a''' on the segment
+  float x = x1 + (float)(0.8 - 0.4 * j);  // s - (0.2 + 0.4 j), from the left knot
+  int k = j;
+  if (x > 0.2f) {  // nearer to the right knot 0.2 + 0.4 (j + 1)
+    k = j + 1;
+    x = x1 + (float)(0.4 - 0.4 * j);
+  }
+  const float c0 = (float)m.d2[k];
+  a = (float)m.a0[k] + (float)m.a1[k] * x + c0 * x * x * 0.5f + slope * x * x * x * (1.0f / 6.0f);
+  da = (float)m.a1[k] + c0 * x + slope * x * x * 0.5f;
 }
 
 // Psi (energy per unit rest volume) and P for one material. Returns false if
@@ -319,83 +363,143 @@ __device__ __forceinline__ bool material_eval_any(const DevMat& mat, const M3<R>
   }
 }
 
-// Mixed precision (FP32 stresses) without losing the small strains: near
-// rest, F - F^{-T} cancels at leading order, so a stress evaluated in FP32 on
-// F would carry a relative error of about 1e-7 / strain. Here F, J and the
-// Green strain E = (F^T F - I) / 2 = (H + H^T + H^T H) / 2 (H = F - I) are
-// formed in FP64 and the first Piola stress is evaluated in FP32 from terms
-// that are each accurate relative to themselves:
-//   Neo-Hookean  P = F S,  S = C^{-1} (2 mu E + lam log J I),  C = I + 2E,
-//   StVK         P = F (2 mu E + lam tr E I).
-// The energy density is formed in FP64 from the same invariants (a handful of
-// flops): FP32 energies put noise of ~1e-7 g into the Armijo test, which flips
-// line-search decisions and moves the trajectory by more than the mixed
-// path's tolerance. The stretch-based materials (SVD) are evaluated in FP64 in
-// this mode.
+// Mixed precision: the element energy density and first Piola stress in
+// FP32, from the displacement gradient H = F - I. F = Ds Dm^{-1} is formed in
+// FP64 (the current and rest geometry are FP64) and H is rounded to FP32 once;
+// every quantity after that is written as a sum of terms that are small when H
+// is small, so each is accurate relative to itself and not to the O(1) parts
+// of F that cancel near rest (an FP32 evaluation on F itself would carry a
+// relative stress error of about 1e-7 / strain). With
+//   j = J - 1 = tr H + m2(H) + det H   (m2: sum of the principal 2x2 minors),
+//   cof F = (1 + tr H) I - H^T + cof H,
+//   J I - cof F = (m2 + det H) I + H^T - cof H,
+//   phi(j) = j - log(1 + j)   (a series for |j| < 1/8),
+// the materials read
+//   Neo-Hookean   Psi = mu (|H|^2 / 2 - m2 - det H + phi(j)) + lam/2 log1p(j)^2,
+//                 P   = mu H + (mu (J I - cof F) + lam log1p(j) cof F) / J,
+//   StVK          E = (H + H^T + H^T H) / 2, Psi = mu |E|^2 + lam/2 (tr E)^2,
+//                 P = (I + H) (2 mu E + lam tr E I),
+//   spline        the signed SVD of F in FP32 (the stretch terms a(s), a'(s)
+//                 from FP32 knot tables), Psi_vol = lam/2 j^2,
+//                 P_vol = lam j cof F.
+// The caller adds the element energies in FP64 (per block, then per
+// simulation: the line-search sums), and the gradient contributions are
+// summed per vertex in FP64. The Mooney-Rivlin, corotated and polynomial
+// materials are evaluated in FP64 in this mode.
+__device__ __forceinline__ float phi_log1p(float j) {
+  // j - log(1 + j): for small j the difference of two nearly equal numbers,
+  // so the alternating series j^2/2 - j^3/3 + ... is summed there instead
+  if (fabsf(j) < 0.125f) {
+    float t = 0.0f;
+    for (int k = 12; k >= 2; --k) t = 1.0f / (float)k - j * t;
+    return j * j * t;
+  }
+  return j - log1pf(j);
+}
+
 template <int TYPE>
 __device__ __forceinline__ void material_eval_mixed(const DevMat& mat, const M3<double>& F,
                                                     double& psi, M3<float>& P) {
   const int ty = TYPE >= 0 ? TYPE : mat.type;
-  if (ty == 0 || ty == 1) {
-    double Ed[3][3];
-    for (int i = 0; i < 3; ++i)
-      for (int j = 0; j < 3; ++j) {
-        const double hij = F.a[i][j] - (i == j ? 1.0 : 0.0);
-        const double hji = F.a[j][i] - (i == j ? 1.0 : 0.0);
-        double hth = 0.0;
-        for (int k = 0; k < 3; ++k)
-          hth += (F.a[k][i] - (k == i ? 1.0 : 0.0)) * (F.a[k][j] - (k == j ? 1.0 : 0.0));
-        Ed[i][j] = 0.5 * (hij + hji + hth);
-      }
-    M3<float> Ff, E;
-    for (int i = 0; i < 3; ++i)
-      for (int j = 0; j < 3; ++j) {
-        Ff.a[i][j] = (float)F.a[i][j];
-        E.a[i][j] = (float)Ed[i][j];
-      }
-    const double trEd = Ed[0][0] + Ed[1][1] + Ed[2][2];
-    const float mu = (float)mat.mu, lam = (float)mat.lam;
-    float S[3][3];
-    if (ty == 0) {
-      const double J = det3(F);
-      if (!(J > 0.0)) {
-        psi = INFINITY;
-        for (int i = 0; i < 3; ++i)
-          for (int j = 0; j < 3; ++j) P.a[i][j] = 0.0f;
-        return;
-      }
-      const double ljd = log(J);
-      const float lj = (float)ljd;
-      psi = mat.mu * (trEd - ljd) + 0.5 * mat.lam * ljd * ljd;
-      M3<float> C;
-      for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) C.a[i][j] = (i == j ? 1.0f : 0.0f) + 2.0f * E.a[i][j];
-      const M3<float> Cc = cofactor(C);  // C symmetric: cofactor = adjugate
-      const float invC = (float)(1.0 / (J * J));
-      float T[3][3];
-      for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) T[i][j] = 2.0f * mu * E.a[i][j] + (i == j ? lam * lj : 0.0f);
-      for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j)
-          S[i][j] = invC * (Cc.a[i][0] * T[0][j] + Cc.a[i][1] * T[1][j] + Cc.a[i][2] * T[2][j]);
-    } else {
-      const float tr = (float)trEd;
-      double ee = 0.0;
-      for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) ee += Ed[i][j] * Ed[i][j];
-      psi = mat.mu * ee + 0.5 * mat.lam * trEd * trEd;
-      for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) S[i][j] = 2.0f * mu * E.a[i][j] + (i == j ? lam * tr : 0.0f);
-    }
-    for (int i = 0; i < 3; ++i)
-      for (int j = 0; j < 3; ++j)
-        P.a[i][j] = Ff.a[i][0] * S[0][j] + Ff.a[i][1] * S[1][j] + Ff.a[i][2] * S[2][j];
-  } else {
+  if (ty != 0 && ty != 1 && ty != 2) {
     M3<double> Pd;
     material_eval_any<double>(mat, F, psi, Pd);
     for (int i = 0; i < 3; ++i)
       for (int j = 0; j < 3; ++j) P.a[i][j] = (float)Pd.a[i][j];
+    return;
   }
+  M3<float> H;
+  for (int i = 0; i < 3; ++i)
+    for (int k = 0; k < 3; ++k) H.a[i][k] = (float)(F.a[i][k] - (i == k ? 1.0 : 0.0));
+  const float mu = (float)mat.mu, lam = (float)mat.lam;
+  const float trH = H.a[0][0] + H.a[1][1] + H.a[2][2];
+  const float m2 = (H.a[0][0] * H.a[1][1] - H.a[0][1] * H.a[1][0]) +
+                   (H.a[0][0] * H.a[2][2] - H.a[0][2] * H.a[2][0]) +
+                   (H.a[1][1] * H.a[2][2] - H.a[1][2] * H.a[2][1]);
+  const float dH = det3(H);
+  const float jm = trH + (m2 + dH);  // J - 1
+  if (ty == 1) {  // St. Venant-Kirchhoff
+    float E[3][3];
+    for (int i = 0; i < 3; ++i)
+      for (int k = 0; k < 3; ++k) {
+        const float hth = H.a[0][i] * H.a[0][k] + H.a[1][i] * H.a[1][k] + H.a[2][i] * H.a[2][k];
+        E[i][k] = 0.5f * ((H.a[i][k] + H.a[k][i]) + hth);
+      }
+    const float tr = E[0][0] + E[1][1] + E[2][2];
+    float ee = 0.0f;
+    for (int i = 0; i < 3; ++i)
+      for (int k = 0; k < 3; ++k) ee += E[i][k] * E[i][k];
+    psi = (double)(mu * ee + 0.5f * lam * tr * tr);
+    float S[3][3];
+    for (int i = 0; i < 3; ++i)
+      for (int k = 0; k < 3; ++k) S[i][k] = 2.0f * mu * E[i][k] + (i == k ? lam * tr : 0.0f);
+    for (int i = 0; i < 3; ++i)
+      for (int k = 0; k < 3; ++k)
+        P.a[i][k] = S[i][k] + (H.a[i][0] * S[0][k] + H.a[i][1] * S[1][k] + H.a[i][2] * S[2][k]);
+    return;
+  }
+  const M3<float> cH = cofactor(H);
+  // cof F = (1 + tr H) I - H^T + cof H
+  M3<float> cF;
+  for (int i = 0; i < 3; ++i)
+    for (int k = 0; k < 3; ++k)
+      cF.a[i][k] = (i == k ? 1.0f + trH : 0.0f) - H.a[k][i] + cH.a[i][k];
+  if (ty == 0) {  // Neo-Hookean
+    if (!(jm > -1.0f)) {  // J <= 0: infeasible
+      psi = INFINITY;
+      for (int i = 0; i < 3; ++i)
+        for (int k = 0; k < 3; ++k) P.a[i][k] = 0.0f;
+      return;
+    }
+    float hh = 0.0f;
+    for (int i = 0; i < 3; ++i)
+      for (int k = 0; k < 3; ++k) hh += H.a[i][k] * H.a[i][k];
+    const float lj = log1pf(jm);
+    psi = (double)(mu * ((0.5f * hh - m2 - dH) + phi_log1p(jm)) + 0.5f * lam * lj * lj);
+    const float invJ = 1.0f / (1.0f + jm);
+    for (int i = 0; i < 3; ++i)
+      for (int k = 0; k < 3; ++k) {
+        const float d = (i == k ? m2 + dH : 0.0f) + H.a[k][i] - cH.a[i][k];  // (J I - cof F)_ik
+        P.a[i][k] = mu * H.a[i][k] + (mu * d + lam * lj * cF.a[i][k]) * invJ;
+      }
+    return;
+  }
+  // spline (TYPE 2): stretch terms from the FP32 signed SVD of F, its right
+  // basis V from the Jacobi eigenvectors of the Green strain E (accurate at
+  // small strain, unlike F^T F rounded in FP32). The stretches near 1 are not
+  // taken from the SVD's diagonal (absolute error ~1e-7, so s - 1 would lose
+  // digits at small strain) but from E in that basis: s_i^2 = 1 + 2 e_i with
+  // e_i = v_i^T E v_i, so s_i - 1 = 2 e_i / (1 + sqrt(1 + 2 e_i)) for a
+  // positive stretch (the SVD supplies the sign and U).
+  M3<float> Ff;
+  for (int i = 0; i < 3; ++i)
+    for (int k = 0; k < 3; ++k) Ff.a[i][k] = (i == k ? 1.0f : 0.0f) + H.a[i][k];
+  float E[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int k = 0; k < 3; ++k) {
+      const float hth = H.a[0][i] * H.a[0][k] + H.a[1][i] * H.a[1][k] + H.a[2][i] * H.a[2][k];
+      E[i][k] = 0.5f * ((H.a[i][k] + H.a[k][i]) + hth);
+    }
+  float U[3][3], V[3][3], sg[3], g[3];
+  svd3_basis(Ff, E, U, sg, V);
+  float ps = 0.5f * lam * jm * jm;
+  for (int i = 0; i < 3; ++i) {
+    float e = 0.0f;
+    for (int p = 0; p < 3; ++p)
+      e += V[p][i] * (E[p][0] * V[0][i] + E[p][1] * V[1][i] + E[p][2] * V[2][i]);
+    const float r = sqrtf(fmaxf(1.0f + 2.0f * e, 0.0f));
+    const float sm1 = sg[i] >= 0.0f ? 2.0f * e / (1.0f + r) : -(1.0f + r);
+    float a, da;
+    spline_eval_m1(mat, sm1, a, da);
+    ps += a;
+    g[i] = da;
+  }
+  psi = (double)ps;
+  const float cf = lam * jm;
+  for (int i = 0; i < 3; ++i)
+    for (int k = 0; k < 3; ++k)
+      P.a[i][k] = U[i][0] * g[0] * V[k][0] + U[i][1] * g[1] * V[k][1] + U[i][2] * g[2] * V[k][2] +
+                  cf * cF.a[i][k];
 }
 
 }  // namespace qn

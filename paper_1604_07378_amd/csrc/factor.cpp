@@ -348,7 +348,7 @@ int factorize(int n, const std::vector<int64_t>& colptr, const std::vector<int>&
         ncT += cols_at[c];
         if (ncT > dense_top_max) break;
         sparse += 2.0 * kPhaseUs + 2.0 * ent_at[c] * kEntryUs;
-        const double gain = sparse - (kTopUs + ncT * ncT * kEntryUs);
+        const double gain = sparse - (kTopUs + 0.5 * ncT * ncT * kEntryUs);  // one triangle read
         if (gain > best_gain) { best_gain = gain; cut = c; }
       }
       if (cut >= 0) {

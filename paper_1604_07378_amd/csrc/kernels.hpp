@@ -235,11 +235,12 @@ struct DeviceMesh {
   int* sub_fw_ptr = nullptr;  // sub_tasks x (sub_levels + 1) item offsets
   int* sub_bw_ptr = nullptr;
   // dense top block (root supernode of the merged top levels), if top_n > 0:
-  // columns [top_first, top_first + top_n), full n x n inverse of its Schur
-  // complement at Bf + top_off, top_nch children's update slots at vp + top_vp
+  // columns [top_first, top_first + top_n); the lower block triangle of the
+  // (symmetric) inverse of its Schur complement in kTopTile^2 tiles at
+  // Bf + top_off (top_tile_off), top_nch children's update slots at vp + top_vp
   int top_first = 0, top_n = 0, top_nch = 0;
   long long top_vp = 0, top_off = 0;
-  double* top_t = nullptr;    // top_n x 3 assembled right-hand side
+  double* top_t = nullptr;    // top_part_doubles(top_n): partial products per tile
   // solver vectors (internal order, 3 doubles per vertex)
   double* x0 = nullptr;       // n x 3 input positions
   double* v0 = nullptr;       // n x 3 input velocities
@@ -284,8 +285,8 @@ struct StepParams {
 
 // Working memory of one solve besides its input and output: the forward
 // intermediate z (nf x 3), the children's update layers (vp_len doubles,
-// zero wherever no child writes) and the dense top block's right-hand side
-// (top_n x 3).
+// zero wherever no child writes) and the dense top block's partial products
+// (top_part_doubles(top_n)).
 struct SolveScratch {
   double* z;
   double* vp;
@@ -305,14 +306,27 @@ void launch_load_perm(hipStream_t st, int n, const int* vperm, const double* src
 void launch_store_perm(hipStream_t st, int n, int nf, const int* vperm, const double* src,
                        double* dst);
 
-// Workgroups of the dense top product for an n-column block: rows are split
-// evenly, at most 32 per workgroup, at most 256 workgroups unless more are
-// needed for the row limit.
-inline int top_workgroups(int n) {
-  int g = n / 8 < 1 ? 1 : n / 8;
-  if (g > 256) g = 256;
-  while ((n + g - 1) / g > 32) ++g;
-  return g;
+// The dense top block S^{-1} (n x n, symmetric) is stored as the tiles (I, J),
+// J <= I, of its lower block triangle, kTopTile x kTopTile each, row-major
+// inside a tile, tile (I, J) at index I (I + 1) / 2 + J; a diagonal tile holds
+// its full square, tiles past the last row or column are zero-padded.
+constexpr int kTopTile = 64;
+__host__ __device__ inline int top_blocks(int n) { return (n + kTopTile - 1) / kTopTile; }
+__host__ __device__ inline long long top_tile_entries(int n) {
+  const long long nb = top_blocks(n);
+  return nb * (nb + 1) / 2 * kTopTile * kTopTile;
+}
+// Offset of S^{-1}[row][col] in the tile array, or -1 above the block diagonal.
+__host__ __device__ inline long long top_tile_off(int row, int col) {
+  const long long I = row / kTopTile, J = col / kTopTile;
+  if (I < J) return -1;
+  return (I * (I + 1) / 2 + J) * kTopTile * kTopTile + (long long)(row % kTopTile) * kTopTile +
+         col % kTopTile;
+}
+// Doubles of the per-tile partial products (block rows x slots x kTopTile x 3).
+inline size_t top_part_doubles(int n) {
+  const size_t nb = (size_t)top_blocks(n);
+  return nb * nb * kTopTile * 3;
 }
 
 // All launchers return 0 or a negative QNSIM_E_* code; err receives a message.

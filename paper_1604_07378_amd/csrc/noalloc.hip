@@ -3,7 +3,7 @@
 // serving loops, harnesses that forbid hipMalloc). The solve and its kernels
 // are the ones of qnsim_solve_device; only the buffers differ: the permuted
 // right-hand side, the forward intermediate, the children's update layers,
-// the dense top block's right-hand side and the permuted solution are carved
+// the dense top block's partial products and the permuted solution are carved
 // out of `scratch`, a file-scope device array of kNoAllocBytes that every
 // device the library runs on holds until the process ends.
 //
@@ -51,8 +51,8 @@ int dev_solve_noalloc(DeviceMesh& D, const double* q, double* r, void* stream, s
   }
   const size_t v3 = lines(3 * (size_t)D.nf);
   const size_t vp = lines((size_t)D.vp_len);
-  const size_t tt = lines(3 * (size_t)D.top_n);
-  const size_t need = 3 * v3 + vp + tt;  // q, z, r; update layers; top right-hand side
+  const size_t tt = lines(D.top_n > 0 ? top_part_doubles(D.top_n) : 0);
+  const size_t need = 3 * v3 + vp + tt;  // q, z, r; update layers; top partial products
   if (need > kNoAllocDoubles) {
     err = "the solve needs " + std::to_string(need * sizeof(double)) +
           " bytes of working memory; the fixed scratch array holds " +

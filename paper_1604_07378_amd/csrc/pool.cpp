@@ -36,6 +36,7 @@ struct PoolSim {
   int group = -1;            // -1: staged
   int slot = -1;             // position in its group
   bool removed = false;
+  bool admitting = false;    // staged, its group is being built by a commit
   bool has_force = false;    // its slice of the group's force array is set
   std::vector<double> force; // host copy of that force (n x 3, caller order)
   int64_t est_bytes = 0;     // device-memory estimate
@@ -77,6 +78,9 @@ struct qnsim_pool {
   int64_t steps_done = 0, batches_done = 0;
   std::vector<PoolSim> sims;
   std::vector<std::unique_ptr<PoolGroup>> groups;
+  // a commit is building groups outside the lock; commits, time-step
+  // changes and tuning wait for it (one administrative change at a time)
+  bool admin_busy = false;
   std::mutex mu;
   std::condition_variable cv;
   std::string last_error;
@@ -186,39 +190,116 @@ void free_group(PoolGroup& g) {
   dev_free(g.D);
 }
 
-// Uploads the members (pool ids) as one group; returns 0 or an error code.
-int build_group(qnsim_pool* p, const std::vector<int>& ids, std::unique_ptr<PoolGroup>& out,
-                std::string& err) {
-  auto g = std::make_unique<PoolGroup>();
+// What a commit needs to build one group, taken from the pool's tables under
+// the lock so that the build itself runs without it: the members' pool ids,
+// their analysed host contexts (which stay put while the pool grows) and
+// their initial states (moved out of the staged records, moved back on a
+// failure).
+struct GroupBuild {
+  std::vector<int> ids;
   std::vector<const qnsim*> cs;
+  std::vector<std::vector<double>> x0, v0;
+  std::unique_ptr<PoolGroup> g;
+  int rc = QNSIM_OK;
+  std::string err;
+};
+
+// Uploads the members of b as one group (factored for h); returns 0 or an
+// error code. Touches no pool table: runs without the pool lock, while other
+// groups step on their own (non-blocking) streams.
+int build_group(const qnsim_options& opt, double h, GroupBuild& b) {
+  auto g = std::make_unique<PoolGroup>();
   int n = 0;
-  for (int id : ids) {
-    cs.push_back(p->sims[id].c);
+  for (const qnsim* c : b.cs) {
     g->cv0.push_back(n);
-    n += p->sims[id].c->n;
+    n += c->n;
   }
-  int rc = upload_sims(cs, p->opt, p->h, g->D, err);
+  if (hipSetDevice(opt.device) != hipSuccess) {
+    b.err = "hipSetDevice failed";
+    return QNSIM_E_DEVICE;
+  }
+  int rc = upload_sims(b.cs, opt, h, g->D, b.err);
   if (rc) { free_group(*g); return rc; }
   const size_t bytes = 3 * (size_t)n * sizeof(double);
   if (hipMalloc((void**)&g->xs, bytes) != hipSuccess || hipMalloc((void**)&g->vs, bytes) != hipSuccess) {
     free_group(*g);
-    err = "state allocation failed";
+    b.err = "state allocation failed";
     return QNSIM_E_NOMEM;
   }
-  for (size_t k = 0; k < ids.size(); ++k) {
-    const PoolSim& s = p->sims[ids[k]];
+  for (size_t k = 0; k < b.cs.size(); ++k) {
     const size_t off = 3 * (size_t)g->cv0[k];
-    if (hipMemcpy(g->xs + off, s.x0.data(), s.x0.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(g->vs + off, s.v0.data(), s.v0.size() * 8, hipMemcpyHostToDevice) != hipSuccess) {
+    if (hipMemcpy(g->xs + off, b.x0[k].data(), b.x0[k].size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(g->vs + off, b.v0[k].data(), b.v0[k].size() * 8, hipMemcpyHostToDevice) != hipSuccess) {
       free_group(*g);
-      err = "state upload failed";
+      b.err = "state upload failed";
       return QNSIM_E_DEVICE;
     }
   }
-  g->ids = ids;
-  g->live = (int)ids.size();
+  g->ids = b.ids;
+  g->live = (int)b.ids.size();
   g->bytes = (int64_t)g->D.bytes + 2 * (int64_t)bytes;
-  out = std::move(g);
+  b.g = std::move(g);
+  return QNSIM_OK;
+}
+
+// A group rebuilt without its removed members (their device memory is
+// returned to the budget): the live members' host contexts and their slots
+// in the old group, whose states (and forces) are copied over on the device.
+struct Repack {
+  int gi = -1;
+  PoolGroup* old = nullptr;
+  std::vector<int> ids, old_slots;
+  std::vector<const qnsim*> cs;
+  bool refactored = false;   // the pool's h differs from the analysed one
+  std::unique_ptr<PoolGroup> g;
+  int rc = QNSIM_OK;
+  std::string err;
+};
+
+// Builds r.g from r's live members; the old group is marked busy by the
+// caller, so nothing else reads or steps it meanwhile. Runs without the lock.
+int build_repack(const qnsim_options& opt, double h, Repack& r) {
+  auto g = std::make_unique<PoolGroup>();
+  int n = 0;
+  for (const qnsim* c : r.cs) {
+    g->cv0.push_back(n);
+    n += c->n;
+  }
+  if (hipSetDevice(opt.device) != hipSuccess) { r.err = "hipSetDevice failed"; return QNSIM_E_DEVICE; }
+  qnsim_options o = opt;
+  o.elem_tile = r.old->D.elem_tile;
+  int rc = upload_sims(r.cs, o, h, g->D, r.err);
+  // host factor values belong to an earlier h after a time-step change
+  if (!rc && r.refactored) rc = dev_refactor_mesh(r.cs, g->D, h, nullptr, r.err);
+  if (rc) { free_group(*g); return rc; }
+  const size_t bytes = 3 * (size_t)n * sizeof(double);
+  if (hipMalloc((void**)&g->xs, bytes) != hipSuccess || hipMalloc((void**)&g->vs, bytes) != hipSuccess ||
+      (r.old->fx && hipMalloc((void**)&g->fx, bytes) != hipSuccess)) {
+    free_group(*g);
+    r.err = "state allocation failed";
+    return QNSIM_E_NOMEM;
+  }
+  hipStream_t st = (hipStream_t)r.old->D.stream;
+  hipError_t e = hipSuccess;
+  for (size_t k = 0; k < r.cs.size() && e == hipSuccess; ++k) {
+    const size_t dst = 3 * (size_t)g->cv0[k], src = 3 * (size_t)r.old->cv0[r.old_slots[k]];
+    const size_t nb = 3 * (size_t)r.cs[k]->n * sizeof(double);
+    e = hipMemcpyAsync(g->xs + dst, r.old->xs + src, nb, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(g->vs + dst, r.old->vs + src, nb, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess && g->fx)
+      e = hipMemcpyAsync(g->fx + dst, r.old->fx + src, nb, hipMemcpyDeviceToDevice, st);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) {
+    free_group(*g);
+    r.err = std::string("state copy failed: ") + hipGetErrorString(e);
+    return QNSIM_E_DEVICE;
+  }
+  g->ids = r.ids;
+  g->live = (int)r.ids.size();
+  g->trials = r.old->trials;
+  g->bytes = (int64_t)g->D.bytes + (g->fx ? 3 : 2) * (int64_t)bytes;
+  r.g = std::move(g);
   return QNSIM_OK;
 }
 
@@ -439,13 +520,46 @@ int qnsim_pool_add(qnsim_pool_t* p, int32_t n, const qnsim_mesh_desc* descs, int
 
 int qnsim_pool_commit(qnsim_pool_t* p, int32_t max_group_sims, int32_t* n_admitted) {
   if (!p) return QNSIM_E_INVALID;
+  if (n_admitted) *n_admitted = 0;
   std::unique_lock<std::mutex> lk(p->mu);
+  p->cv.wait(lk, [&] { return !p->admin_busy; });
+  // 1. plan under the lock. Groups whose removed members hold at least half
+  //    of their memory are repacked (rebuilt with the live members, marked
+  //    busy meanwhile: their requests wait); the memory that frees counts
+  //    for the admission. Then staged simulations in id order while the
+  //    budget allows, max_group_sims per group.
+  std::vector<Repack> repacks;
+  int64_t freed = 0;
+  for (int gi = 0; gi < (int)p->groups.size(); ++gi) {
+    PoolGroup& g = *p->groups[gi];
+    if (g.live == 0 || g.live == (int)g.ids.size() || g.busy) continue;
+    int64_t dead = 0, all = 0;
+    for (int id : g.ids) {
+      all += p->sims[id].est_bytes;
+      if (p->sims[id].removed) dead += p->sims[id].est_bytes;
+    }
+    if (2 * dead < all) continue;
+    Repack r;
+    r.gi = gi;
+    r.old = &g;
+    for (size_t k = 0; k < g.ids.size(); ++k) {
+      const PoolSim& m = p->sims[g.ids[k]];
+      if (m.removed) continue;
+      r.ids.push_back(g.ids[k]);
+      r.old_slots.push_back((int)k);
+      r.cs.push_back(m.c);
+      r.refactored = r.refactored || m.c->factor_on_device;
+    }
+    g.busy = true;
+    freed += dead;
+    repacks.push_back(std::move(r));
+  }
   std::vector<std::vector<int>> plan;
   std::vector<int> cur;
-  int64_t room = p->budget - p->used;
+  int64_t room = p->budget - p->used + freed;
   for (int id = 0; id < (int)p->sims.size(); ++id) {
     const PoolSim& s = p->sims[id];
-    if (s.removed || s.group >= 0) continue;
+    if (s.removed || s.group >= 0 || s.admitting) continue;
     if (s.est_bytes > room) continue;  // stays staged
     room -= s.est_bytes;
     cur.push_back(id);
@@ -455,36 +569,104 @@ int qnsim_pool_commit(qnsim_pool_t* p, int32_t max_group_sims, int32_t* n_admitt
     }
   }
   if (!cur.empty()) plan.push_back(cur);
-  int admitted = 0;
-  for (const std::vector<int>& ids : plan) {
-    std::unique_ptr<PoolGroup> g;
-    std::string err;
-    int rc;
-    try {
-      rc = build_group(p, ids, g, err);
-    } catch (const std::bad_alloc&) {
-      rc = QNSIM_E_NOMEM;
-      err = "host allocation failed";
+  if (plan.empty() && repacks.empty()) return QNSIM_OK;
+  std::vector<GroupBuild> builds(plan.size());
+  for (size_t b = 0; b < plan.size(); ++b) {
+    builds[b].ids = plan[b];
+    for (int id : plan[b]) {
+      PoolSim& s = p->sims[id];
+      s.admitting = true;
+      builds[b].cs.push_back(s.c);
+      builds[b].x0.push_back(std::move(s.x0));
+      builds[b].v0.push_back(std::move(s.v0));
     }
-    if (rc) {
-      if (n_admitted) *n_admitted = admitted;
-      return pfail(p, rc, err);
+  }
+  p->admin_busy = true;
+  const qnsim_options opt = p->opt;
+  const double h = p->h;
+  lk.unlock();
+  // 2. build and upload outside the lock: serving lanes keep picking and
+  //    stepping resident groups meanwhile; repacks first (their memory is
+  //    freed before the new groups allocate); a failed group and the ones
+  //    after it are not built
+  for (Repack& r : repacks) {
+    try {
+      r.rc = build_repack(opt, h, r);
+    } catch (const std::bad_alloc&) {
+      r.rc = QNSIM_E_NOMEM;
+      r.err = "host allocation failed";
+    }
+    if (!r.rc) free_group(*r.old);  // busy: nothing else touches it
+  }
+  bool failed = false;
+  for (GroupBuild& b : builds) {
+    if (failed) { b.rc = QNSIM_E_STATE; continue; }
+    try {
+      b.rc = build_group(opt, h, b);
+    } catch (const std::bad_alloc&) {
+      b.rc = QNSIM_E_NOMEM;
+      b.err = "host allocation failed";
+    }
+    failed = b.rc != QNSIM_OK;
+  }
+  // 3. publish under the lock
+  lk.lock();
+  int admitted = 0, rc = QNSIM_OK;
+  std::string err;
+  for (Repack& r : repacks) {
+    PoolGroup& old = *p->groups[r.gi];
+    if (r.rc) {  // the old group stays as it was
+      old.busy = false;
+      if (!rc) { rc = r.rc; err = "repack: " + r.err; }
+      continue;
+    }
+    p->used += r.g->bytes - old.bytes;
+    std::vector<char> kept(p->sims.size(), 0);
+    for (int id : r.ids) kept[id] = 1;
+    for (int id : old.ids) {  // members removed before the repack leave for good
+      PoolSim& m = p->sims[id];
+      if (!kept[id] && m.c) { qnsim_destroy(m.c); m.c = nullptr; }
+    }
+    for (size_t k = 0; k < r.ids.size(); ++k) p->sims[r.ids[k]].slot = (int)k;
+    // a member removed while the repack ran is counted out by its
+    // qnsim_pool_remove, which waits for the group and finds the new one
+    p->groups[r.gi] = std::move(r.g);
+  }
+  for (GroupBuild& b : builds) {
+    if (b.rc) {
+      // not admitted: the simulations stay staged with their initial state
+      for (size_t k = 0; k < b.ids.size(); ++k) {
+        PoolSim& s = p->sims[b.ids[k]];
+        s.admitting = false;
+        s.x0 = std::move(b.x0[k]);
+        s.v0 = std::move(b.v0[k]);
+        if (s.removed && s.c) { qnsim_destroy(s.c); s.c = nullptr; }
+      }
+      if (!rc && b.rc != QNSIM_E_STATE) { rc = b.rc; err = b.err; }
+      continue;
     }
     const int gi = (int)p->groups.size();
-    for (size_t k = 0; k < ids.size(); ++k) {
-      PoolSim& s = p->sims[ids[k]];
+    for (size_t k = 0; k < b.ids.size(); ++k) {
+      PoolSim& s = p->sims[b.ids[k]];
+      s.admitting = false;
       s.group = gi;
       s.slot = (int)k;
-      std::vector<double>().swap(s.x0);
-      std::vector<double>().swap(s.v0);
+      if (s.removed) b.g->live--;  // removed while its group was built
     }
-    p->used += g->bytes;
-    admitted += (int)ids.size();
-    p->groups.push_back(std::move(g));
+    p->used += b.g->bytes;
+    admitted += b.g->live;
+    p->groups.push_back(std::move(b.g));
+    if (p->groups.back()->live == 0) {  // every member removed meanwhile
+      p->used -= p->groups.back()->bytes;
+      free_group(*p->groups.back());
+      for (int id : b.ids)
+        if (p->sims[id].c) { qnsim_destroy(p->sims[id].c); p->sims[id].c = nullptr; }
+    }
   }
+  p->admin_busy = false;
   if (n_admitted) *n_admitted = admitted;
   p->cv.notify_all();
-  return QNSIM_OK;
+  return rc ? pfail(p, rc, err) : QNSIM_OK;
 }
 
 int qnsim_pool_remove(qnsim_pool_t* p, int32_t id) {
@@ -496,9 +678,12 @@ int qnsim_pool_remove(qnsim_pool_t* p, int32_t id) {
   for (const Request& r : p->queue)
     if (r.sim == id) return pfail(p, QNSIM_E_STATE, "simulation has queued requests");
   s.removed = true;
+  if (s.admitting) return QNSIM_OK;  // the commit building its group drops it
   if (s.group >= 0) {
-    PoolGroup& g = *p->groups[s.group];
-    p->cv.wait(lk, [&] { return !g.busy; });
+    // the group is looked up again after the wait: a repack may replace it
+    // and a concurrent add may move the simulation records
+    p->cv.wait(lk, [&] { return !p->groups[p->sims[id].group]->busy; });
+    PoolGroup& g = *p->groups[p->sims[id].group];
     if (--g.live == 0) {
       p->used -= g.bytes;
       free_group(g);
@@ -520,6 +705,12 @@ int qnsim_pool_step(qnsim_pool_t* p, int32_t n, const int32_t* ids, qnsim_stats*
   if (n < 0 || (n > 0 && !ids)) return pfail(p, QNSIM_E_INVALID, "bad id list");
   std::unique_lock<std::mutex> lk(p->mu);
   if (p->serving) return pfail(p, QNSIM_E_STATE, "the request loop is running");
+  // wait until no listed simulation's group is stepping or being repacked
+  p->cv.wait(lk, [&] {
+    for (int i = 0; i < n; ++i)
+      if (resident(p, ids[i]) && p->groups[p->sims[ids[i]].group]->busy) return false;
+    return true;
+  });
   std::vector<std::vector<int>> slots(p->groups.size());
   std::vector<std::vector<int>> where(p->groups.size());  // index into ids
   std::vector<char> seen(p->sims.size(), 0);
@@ -569,9 +760,10 @@ static int state_copy(qnsim_pool* p, int id, double* xh, double* vh, const doubl
                       const double* vin) {
   std::unique_lock<std::mutex> lk(p->mu);
   if (!resident(p, id)) return pfail(p, QNSIM_E_INVALID, "id is not resident");
+  p->cv.wait(lk, [&] { return !resident(p, id) || !p->groups[p->sims[id].group]->busy; });
+  if (!resident(p, id)) return pfail(p, QNSIM_E_INVALID, "id was removed");
   const PoolSim& s = p->sims[id];
   PoolGroup& g = *p->groups[s.group];
-  p->cv.wait(lk, [&] { return !g.busy; });
   const size_t off = 3 * (size_t)g.cv0[s.slot], bytes = 3 * (size_t)s.c->n * sizeof(double);
   hipStream_t st = (hipStream_t)g.D.stream;
   hipError_t e = hipSuccess;
@@ -613,21 +805,23 @@ int qnsim_pool_set_force(qnsim_pool_t* p, int32_t id, const double* f_ext) {
   if (f_ext)
     for (size_t i = 0; i < n3; ++i)
       if (!std::isfinite(f_ext[i])) return pfail(p, QNSIM_E_NONFINITE, "non-finite force");
-  PoolGroup& g = *p->groups[s.group];
-  p->cv.wait(lk, [&] { return !g.busy; });
-  if (!f_ext && !s.has_force) return QNSIM_OK;
+  p->cv.wait(lk, [&] { return !resident(p, id) || !p->groups[p->sims[id].group]->busy; });
+  if (!resident(p, id)) return pfail(p, QNSIM_E_INVALID, "id was removed");
+  PoolSim& s2 = p->sims[id];  // records may have moved during the wait
+  PoolGroup& g = *p->groups[s2.group];
+  if (!f_ext && !s2.has_force) return QNSIM_OK;
   if (hipSetDevice(p->opt.device) != hipSuccess) return pfail(p, QNSIM_E_DEVICE, "hipSetDevice failed");
   std::string err;
   int rc = ensure_force_array(p, g, err);
-  if (!rc) rc = write_force(g, s.slot, s.c->n, f_ext, err);
+  if (!rc) rc = write_force(g, s2.slot, s2.c->n, f_ext, err);
   if (!rc && hipStreamSynchronize((hipStream_t)g.D.stream) != hipSuccess) {
     rc = QNSIM_E_DEVICE;
     err = "force copy failed";
   }
   if (rc) return pfail(p, rc, err);
-  s.has_force = f_ext != nullptr;
-  if (f_ext) s.force.assign(f_ext, f_ext + n3);
-  else std::vector<double>().swap(s.force);
+  s2.has_force = f_ext != nullptr;
+  if (f_ext) s2.force.assign(f_ext, f_ext + n3);
+  else std::vector<double>().swap(s2.force);
   return QNSIM_OK;
 }
 
@@ -718,6 +912,16 @@ int qnsim_pool_serve_stop(qnsim_pool_t* p) {
   return QNSIM_OK;
 }
 
+int qnsim_pool_status(qnsim_pool_t* p, int32_t id, int32_t* status, int32_t* group) {
+  if (!p || !status) return QNSIM_E_INVALID;
+  std::lock_guard<std::mutex> lk(p->mu);
+  if (id < 0 || id >= (int)p->sims.size()) return pfail(p, QNSIM_E_INVALID, "unknown simulation id");
+  const PoolSim& s = p->sims[id];
+  *status = s.removed ? QNSIM_SIM_REMOVED : s.group >= 0 ? QNSIM_SIM_RESIDENT : QNSIM_SIM_STAGED;
+  if (group) *group = s.removed ? -1 : s.group;
+  return QNSIM_OK;
+}
+
 int qnsim_pool_get_info(qnsim_pool_t* p, qnsim_pool_info* info) {
   if (!p || !info) return QNSIM_E_INVALID;
   std::lock_guard<std::mutex> lk(p->mu);
@@ -750,6 +954,7 @@ int qnsim_pool_set_h(qnsim_pool_t* p, double h, double* device_ms) {
   std::unique_lock<std::mutex> lk(p->mu);
   if (p->serving) return pfail(p, QNSIM_E_STATE, "the request loop is running");
   p->cv.wait(lk, [&] {
+    if (p->admin_busy) return false;
     for (auto& g : p->groups)
       if (g && g->busy) return false;
     return true;
@@ -807,6 +1012,7 @@ int qnsim_pool_tune(qnsim_pool_t* p, int32_t candidates, int32_t reps, int32_t n
   std::unique_lock<std::mutex> lk(p->mu);
   if (p->serving) return pfail(p, QNSIM_E_STATE, "the request loop is running");
   p->cv.wait(lk, [&] {
+    if (p->admin_busy) return false;
     for (auto& g : p->groups)
       if (g && g->busy) return false;
     return true;

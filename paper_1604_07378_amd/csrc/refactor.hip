@@ -21,7 +21,7 @@
 //     times L_JJ^{-1}, then the rows below minus L_IJ times row block J);
 //  3. the solve blocks: [Z11; -Z21] = [L11^{-1}; L21 L11^{-1}] into the
 //     row-major and the column-major packed copies, or, for the dense top
-//     block, the full (L11 L11^T)^{-1} = Z11^T Z11.
+//     block, (L11 L11^T)^{-1} = Z11^T Z11 in tiles of its lower block triangle.
 //
 // The solve blocks are overwritten only once every pivot has been found
 // positive, so a failed refactorisation leaves the previous factor in force.
@@ -49,7 +49,7 @@ struct RfNode {
   long long zoff;   // m x ncol column-major [L11^{-1}; -L21 L11^{-1}] (leading dim m)
   long long fw, bw; // the supernode's blocks in the forward / backward packed copies
   long long rel;    // positions of its below rows in the parent's front
-  int top, pad;     // top: stored as the full (L11 L11^T)^{-1} (forward copy only)
+  int top, pad;     // top: (L11 L11^T)^{-1} in tiles of its lower block triangle (forward copy only)
 };
 
 struct RfItem {
@@ -368,7 +368,8 @@ __global__ __launch_bounds__(256) void k_rf_update(const int* __restrict__ lvl_n
 
 // Solve blocks, one 64-row x 32-column tile per item. Ordinary supernode:
 // [L11^{-1}; L21 L11^{-1}] = [Z11; -Z21] into both packed copies. Dense top:
-// the full (L11 L11^T)^{-1}[i][j] = sum_k Z[k][i] Z[k][j] into the forward copy.
+// (L11 L11^T)^{-1}[i][j] = sum_k Z[k][i] Z[k][j] into the forward copy's tiles
+// of the lower block triangle (padding stays as the upload wrote it: zero).
 __global__ __launch_bounds__(256) void k_rf_out(const RfItem* __restrict__ items,
                                                 const RfNode* __restrict__ node,
                                                 const double* __restrict__ Z,
@@ -425,7 +426,8 @@ __global__ __launch_bounds__(256) void k_rf_out(const RfItem* __restrict__ items
 #pragma unroll
   for (int v = 0; v < 8; ++v) {
     const int c = cJ + ty + 4 * v;
-    if (c < nc && row < nc) Bf[nd.fw + row + (long long)c * nc] = acc[v];
+    const long long o = top_tile_off(row, c);  // lower block triangle only
+    if (c < nc && row < nc && o >= 0) Bf[nd.fw + o] = acc[v];
   }
 }
 

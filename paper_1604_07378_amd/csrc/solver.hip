@@ -901,7 +901,7 @@ __global__ void __launch_bounds__(BS)
 k_store_stress(int T, const int* __restrict__ tperm, const int* __restrict__ tv,
                const double* __restrict__ Bm, const int* __restrict__ tmat,
                const DevMat* __restrict__ mats, const double* __restrict__ X,
-               double* __restrict__ psi, double* __restrict__ Pout) {
+               double* __restrict__ psi, double* __restrict__ Pout, int mixed) {
   const int t = blockIdx.x * BS + threadIdx.x;
   if (t >= T) return;
   const int4 iv = reinterpret_cast<const int4*>(tv)[t];
@@ -919,8 +919,16 @@ k_store_stress(int T, const int* __restrict__ tperm, const int* __restrict__ tv,
   double ps;
   M3<double> P;
   const DevMat& mt = mats[tmat ? tmat[t] : 0];
-  material_eval_any<double>(mt, F, ps, P);
-  add_fiber(mt, F, ps, P);
+  if (mixed) {  // the element pass's evaluation in mixed precision
+    M3<float> Pf;
+    material_eval_mixed<-1>(mt, F, ps, Pf);
+    add_fiber(mt, F, ps, Pf);
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) P.a[i][j] = (double)Pf.a[i][j];
+  } else {
+    material_eval_any<double>(mt, F, ps, P);
+    add_fiber(mt, F, ps, P);
+  }
   const int o = tperm[t];
   psi[o] = ps;
   for (int i = 0; i < 3; ++i)
@@ -1219,7 +1227,7 @@ int dev_alloc(DeviceMesh& D, std::string& err) {
   HIP_OK(A((void**)&D.r, f3 * 8));
   HIP_OK(A((void**)&D.q, f3 * 8));
   HIP_OK(A((void**)&D.z, f3 * 8));
-  HIP_OK(A((void**)&D.top_t, 3 * (size_t)std::max(D.top_n, 1) * 8));
+  HIP_OK(A((void**)&D.top_t, std::max<size_t>(top_part_doubles(D.top_n), 3) * 8));
   HIP_OK(A((void**)&D.Sv, f3 * 8 * D.slots));
   HIP_OK(A((void**)&D.Tv, f3 * 8 * D.slots));
   HIP_OK(A((void**)&D.bpart, 3 * (size_t)std::max<long long>(D.n_part, 1) * 8));
@@ -1516,7 +1524,7 @@ int dev_element_stress(DeviceMesh& D, const double* x, double* psi, double* P, v
   hipStream_t st = (hipStream_t)stream;
   hipLaunchKernelGGL(k_load_perm, dim3(nblk(D.n)), dim3(BS), 0, st, D.n, D.vperm, x, D.X);
   hipLaunchKernelGGL(k_store_stress, dim3(nblk(D.T)), dim3(BS), 0, st, D.T, D.tperm, D.tv, D.Bm,
-                     D.tmat, D.mats, D.X, psi, P);
+                     D.tmat, D.mats, D.X, psi, P, D.mixed);
   HIP_OK(hipGetLastError());
   HIP_OK(hipStreamSynchronize(st));
   return 0;

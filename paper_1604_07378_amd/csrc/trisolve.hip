@@ -644,91 +644,102 @@ k_solve_bwd_sub(const ItemDesc* __restrict__ items, const int* __restrict__ ptr,
   }
 }
 
-// Dense top block, step 1: its right-hand side t_T = q_T - (its update layers),
-// summed in a fixed order.
-__global__ void __launch_bounds__(TS)
-k_top_assemble(const double* __restrict__ q, const double* __restrict__ slots, int nch,
-               int n3, double* __restrict__ t, const int* __restrict__ gate) {
+// Dense top block: w_T = S^{-1} t_T with t_T = q_T - (its update layers) and
+// S^{-1} symmetric, of which only the tiles of the lower block triangle are
+// stored (each entry read once). Step 1, one workgroup per tile (I, J):
+// assemble t for the tile's block rows I and J (fixed order over the layers),
+// then T_IJ t_J is the tile's contribution to w's block I and, for I != J,
+// T_IJ^T t_I its contribution to block J; each goes to its own slot of the
+// partial array (block I, slot J and block J, slot I), so every (block, slot)
+// is written by exactly one tile. A thread holds two adjacent columns of
+// eight rows: the row sums are reduced over the 32 lanes of a half wave, the
+// column sums over the two half waves and then the four waves in LDS.
+__global__ void __launch_bounds__(256)
+k_top_sym(const double* __restrict__ tiles, const double* __restrict__ q,
+          const double* __restrict__ slots, int nch, int n, int nb, double* __restrict__ part,
+          const int* __restrict__ gate) {
+  constexpr int TT = kTopTile;
+  __shared__ double tI[TT][3], tJ[TT][3];
+  __shared__ double red[4][TT][3];
   if (gate && *gate <= 0) return;
-  const int i = blockIdx.x * TS + threadIdx.x;
-  if (i >= n3) return;
-  double v = q[i];
-  for (int j = 0; j < nch; ++j) v -= slots[(size_t)j * n3 + i];
-  t[i] = v;
+  const int b = blockIdx.x;
+  int I = (int)((sqrt(8.0 * b + 1.0) - 1.0) * 0.5);
+  while ((I + 1) * (I + 2) / 2 <= b) ++I;
+  while (I * (I + 1) / 2 > b) --I;
+  const int J = b - I * (I + 1) / 2;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int cp = tid & 31, rg = tid >> 5;  // column pair, group of eight rows
+  const double* T = tiles + (size_t)b * TT * TT;
+  double2 e[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+    e[i] = *reinterpret_cast<const double2*>(T + (rg * 8 + i) * TT + 2 * cp);
+  const size_t n3 = 3 * (size_t)n;
+  for (int k = tid; k < 2 * TT * 3; k += 256) {
+    const int which = k / (TT * 3), rem = k % (TT * 3), r = rem / 3, comp = rem % 3;
+    const int row = (which ? J : I) * TT + r;
+    double v = 0.0;
+    if (row < n) {
+      v = q[3 * (size_t)row + comp];
+      for (int j = 0; j < nch; ++j) v -= slots[(size_t)j * n3 + 3 * (size_t)row + comp];
+    }
+    if (which) tJ[r][comp] = v;
+    else tI[r][comp] = v;
+  }
+  __syncthreads();
+  const int c0 = 2 * cp;
+  double ra[8][3], ca[2][3];
+#pragma unroll
+  for (int comp = 0; comp < 3; ++comp) ca[0][comp] = ca[1][comp] = 0.0;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int r = rg * 8 + i;
+#pragma unroll
+    for (int comp = 0; comp < 3; ++comp) {
+      ra[i][comp] = e[i].x * tJ[c0][comp] + e[i].y * tJ[c0 + 1][comp];
+      ca[0][comp] += e[i].x * tI[r][comp];
+      ca[1][comp] += e[i].y * tI[r][comp];
+    }
+  }
+  // T_IJ t_J: this half wave's eight rows
+  double* pr = part + ((size_t)I * nb + J) * TT * 3 + (size_t)rg * 8 * 3;
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+#pragma unroll
+    for (int comp = 0; comp < 3; ++comp) {
+      const double v = group_sum(ra[i][comp], 32);
+      if (cp == 0) pr[3 * i + comp] = v;
+    }
+  if (I == J) return;  // the diagonal tile's full square gave the whole product
+  // T_IJ^T t_I: column sums over the eight row groups
+#pragma unroll
+  for (int k = 0; k < 2; ++k)
+#pragma unroll
+    for (int comp = 0; comp < 3; ++comp) {
+      const double hi = __shfl_xor(ca[k][comp], 32);  // the odd row group's sum
+      if (lane < 32) red[wv][c0 + k][comp] = ca[k][comp] + hi;
+    }
+  __syncthreads();
+  if (tid < TT * 3) {
+    const int c = tid / 3, comp = tid % 3;
+    part[((size_t)J * nb + I) * TT * 3 + tid] =
+        ((red[0][c][comp] + red[1][c][comp]) + red[2][c][comp]) + red[3][c][comp];
+  }
 }
 
-// Dense top block, step 2: w_T = S^{-1} t_T with S^{-1} symmetric, n x n,
-// row-major. A workgroup owns a contiguous range of at most kTopRows rows and
-// stages t_T in LDS. Its tasks are (row, one of kTopParts column ranges);
-// wave wv takes tasks wv, wv + 16, ... A lane loads up to kTopU entries of
-// the task (all in flight at once), the next task's loads are issued before
-// the current task's sums are reduced over the wave, and the parts of a row
-// are added in LDS in a fixed order.
-constexpr int kTopThreads = 1024, kTopWaves = kTopThreads / 64, kTopRows = 32, kTopParts = 8;
-constexpr int kTopU = (kMaxDenseTop / kTopParts + 63) / 64;  // entries per lane and task
-
-__global__ void __launch_bounds__(kTopThreads)
-k_top_gemv(const double* __restrict__ Sinv, const double* __restrict__ t, int n, int nwg,
-           double* __restrict__ w, const int* __restrict__ gate) {
-  __shared__ double ts[3][kMaxDenseTop];
-  __shared__ double red[kTopRows][kTopParts][3];
+// Dense top block, step 2: w_T, entry by entry, as the sum of its block's
+// slots in slot order.
+__global__ void __launch_bounds__(256)
+k_top_sum(const double* __restrict__ part, int n, int nb, double* __restrict__ w,
+          const int* __restrict__ gate) {
   if (gate && *gate <= 0) return;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int rb = (int)(((long long)blockIdx.x * n) / nwg);
-  const int re = (int)(((long long)(blockIdx.x + 1) * n) / nwg);
-  const int ntask = kTopParts * (re - rb);
-  const int qw = (n + kTopParts - 1) / kTopParts;  // columns per part
-  const int U = (qw + 63) / 64;            // entries per lane and task (uniform)
-  double b[kTopU];
-  auto load_task = [&](int task) {
-    const int r = rb + task / kTopParts, q = task % kTopParts;
-    const int c0 = q * qw, c1 = min(n, c0 + qw);
-    const double* rowp = Sinv + (size_t)r * n;
-#pragma unroll
-    for (int u = 0; u < kTopU; ++u) {
-      const int c = c0 + lane + 64 * u;
-      b[u] = (u < U && c < c1) ? rowp[c] : 0.0;
-    }
-  };
-  int task = wv;
-  if (task < ntask) load_task(task);
-  for (int i = threadIdx.x; i < n; i += kTopThreads) {
-    ts[0][i] = t[3 * (size_t)i + 0];
-    ts[1][i] = t[3 * (size_t)i + 1];
-    ts[2][i] = t[3 * (size_t)i + 2];
-  }
-  __syncthreads();
-  for (; task < ntask; task += kTopWaves) {
-    const int q = task % kTopParts, c0 = q * qw, c1 = min(n, c0 + qw);
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-#pragma unroll
-    for (int u = 0; u < kTopU; ++u) {
-      const int c = c0 + lane + 64 * u;
-      if (u < U && c < c1) {
-        a0 += b[u] * ts[0][c];
-        a1 += b[u] * ts[1][c];
-        a2 += b[u] * ts[2][c];
-      }
-    }
-    if (task + kTopWaves < ntask) load_task(task + kTopWaves);
-    a0 = group_sum(a0, 64);
-    a1 = group_sum(a1, 64);
-    a2 = group_sum(a2, 64);
-    if (lane == 0) {
-      red[task / kTopParts][q][0] = a0;
-      red[task / kTopParts][q][1] = a1;
-      red[task / kTopParts][q][2] = a2;
-    }
-  }
-  __syncthreads();
-  const int i = threadIdx.x;
-  if (i < 3 * (re - rb)) {
-    const int r = i / 3, comp = i % 3;
-    double v = 0.0;
-#pragma unroll
-    for (int k = 0; k < kTopParts; ++k) v += red[r][k][comp];
-    w[3 * (size_t)rb + i] = v;
-  }
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= 3 * n) return;
+  const int row = i / 3, comp = i % 3, I = row / kTopTile;
+  const double* p = part + (size_t)I * nb * kTopTile * 3 + (size_t)(row % kTopTile) * 3 + comp;
+  double s = 0.0;
+  for (int k = 0; k < nb; ++k) s += p[(size_t)k * kTopTile * 3];
+  w[i] = s;
 }
 
 void launch_solve(DeviceMesh& D, hipStream_t st, const double* q, double* r, const int* gate,
@@ -765,12 +776,11 @@ void launch_solve(DeviceMesh& D, hipStream_t st, const double* q, double* r, con
                          D.Bf, D.rel, q, zb, vp, gate, sim_ctl);
   }
   if (D.top_n > 0) {
-    const int n = D.top_n, n3 = 3 * n;
-    hipLaunchKernelGGL(k_top_assemble, dim3((n3 + TS - 1) / TS), dim3(TS), 0, st,
-                       q + 3 * (size_t)D.top_first, vp + D.top_vp, D.top_nch, n3, top_t, gate);
-    const int nwg = top_workgroups(n);
-    hipLaunchKernelGGL(k_top_gemv, dim3(nwg), dim3(kTopThreads), 0, st, D.Bf + D.top_off,
-                       top_t, n, nwg, r + 3 * (size_t)D.top_first, gate);
+    const int n = D.top_n, nb = top_blocks(n);
+    hipLaunchKernelGGL(k_top_sym, dim3(nb * (nb + 1) / 2), dim3(256), 0, st, D.Bf + D.top_off,
+                       q + 3 * (size_t)D.top_first, vp + D.top_vp, D.top_nch, n, nb, top_t, gate);
+    hipLaunchKernelGGL(k_top_sum, dim3((3 * n + 255) / 256), dim3(256), 0, st, top_t, n, nb,
+                       r + 3 * (size_t)D.top_first, gate);
   }
   for (int l = L - 1; l >= D.sub_levels; --l) {
     const int n = D.levels[l].bw_end - D.levels[l].bw_begin;

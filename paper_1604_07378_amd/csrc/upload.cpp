@@ -237,8 +237,9 @@ int upload_sims(const std::vector<const qnsim*>& sims, const qnsim_options& opt,
   for (int s = 0; s < ns; ++s) {
     const Supernode& S = F.sn[s];
     const int64_t packed = (int64_t)S.ncol * (S.ncol + 1) / 2 + (int64_t)S.nbelow * S.ncol;
-    pf[s + 1] = pf[s] + (s == top ? (int64_t)S.ncol * S.ncol : packed);
+    pf[s + 1] = pf[s] + (s == top ? (int64_t)top_tile_entries(S.ncol) : packed);
     pb[s + 1] = pb[s] + (s == top ? 0 : packed);
+    if (s + 1 == top) pf[s + 1] = (pf[s + 1] + 31) / 32 * 32;  // tiles on 256-byte lines
   }
   RawBuf<double> Bf(pf[ns]), Bb(pb[ns]);  // every entry written below
   std::vector<int4> fwl, bwl;
@@ -290,8 +291,19 @@ int upload_sims(const std::vector<const qnsim*>& sims, const qnsim_options& opt,
           const int nc = S.ncol, m = S.m();
           const double* blk = q.blk[s];
           if (s == q.top) {
-            // symmetric: the column-major block is also its row-major copy
-            std::copy(blk, blk + (size_t)nc * nc, q.Bf + (*q.pf)[s]);
+            // the lower block triangle of the symmetric inverse in tiles
+            double* bt = q.Bf + (*q.pf)[s];
+            const int nb = top_blocks(nc);
+            for (int I = 0; I < nb; ++I)
+              for (int J = 0; J <= I; ++J) {
+                double* tile = bt + top_tile_off(I * kTopTile, J * kTopTile);
+                for (int r = 0; r < kTopTile; ++r)
+                  for (int c = 0; c < kTopTile; ++c) {
+                    const int row = I * kTopTile + r, col = J * kTopTile + c;
+                    tile[r * kTopTile + c] =
+                        row < nc && col < nc ? blk[(size_t)col * nc + row] : 0.0;
+                  }
+              }
             continue;
           }
           double* bf = q.Bf + (*q.pf)[s];
@@ -502,9 +514,10 @@ int upload_sims(const std::vector<const qnsim*>& sims, const qnsim_options& opt,
                     s != ns - 1 || I.ncol > kMaxDenseTop || I.first + I.ncol != nf)
                  : (cover_r[s] != I.ncol + I.nbelow || cover_c[s] != I.ncol))
         FAIL(QNSIM_E_DEVICE, "schedule: rows or columns not covered once");
-      if (I.fw_off + (is_top ? (int64_t)I.ncol * I.ncol
+      if (I.fw_off + (is_top ? (int64_t)top_tile_entries(I.ncol)
                              : (int64_t)I.ncol * (I.ncol + 1) / 2 + (int64_t)I.nbelow * I.ncol) >
               (int64_t)Bf.size() ||
+          (is_top && I.fw_off % 32 != 0) ||
           (!is_top && I.bw_off + (int64_t)I.ncol * (I.ncol + 1) / 2 + (int64_t)I.nbelow * I.ncol >
                           (int64_t)Bb.size()))
         FAIL(QNSIM_E_DEVICE, "schedule: block offset out of range");

@@ -161,6 +161,7 @@ SIGNATURES = {
     "qnsim_pool_wait": (ctypes.c_int, [_P, ctypes.c_int64, _D, ctypes.POINTER(Stats),
                                        ctypes.POINTER(_D)]),
     "qnsim_pool_serve_stop": (ctypes.c_int, [_P]),
+    "qnsim_pool_status": (ctypes.c_int, [_P, _I, ctypes.POINTER(_I), ctypes.POINTER(_I)]),
     "qnsim_pool_get_info": (ctypes.c_int, [_P, ctypes.POINTER(PoolInfo)]),
     "qnsim_pool_last_error": (ctypes.c_char_p, [_P]),
     "qnsim_pool_time_kernel": (ctypes.c_int, [_P, _I, _I, _I, ctypes.POINTER(_D)]),
@@ -613,6 +614,13 @@ class Pool:
         if trials:
             out += ([int(tr[i]) for i in range(n)], [[float(tms[3 * i + k]) for k in range(3)] for i in range(n)])
         return out
+
+    def status(self, sim_id: int):
+        """('staged' | 'resident' | 'removed', group index or -1)."""
+        st, g = ctypes.c_int32(), ctypes.c_int32()
+        self._check(self._lib.qnsim_pool_status(self._p, int(sim_id), ctypes.byref(st),
+                                                ctypes.byref(g)))
+        return ("staged", "resident", "removed")[st.value], g.value
 
     def info(self) -> dict:
         i = PoolInfo()

@@ -433,6 +433,32 @@ def test_mixed_precision_block_first_step(kind):
           flush=True)
 
 
+@pytest.mark.parametrize("amp", [0.15, 1e-4])
+@pytest.mark.parametrize("kind", [W.NEOHOOKEAN, W.STVK, W.SPLINE])
+def test_mixed_element_energy_and_stress(kind, amp):
+    """The mixed path's FP32 element evaluation (from the displacement
+    gradient H = F - I) against the FP64 oracle, at moderate strain and at
+    strains of about 1e-4: the errors stay at FP32 level relative to the
+    largest |Psi| and |P| of the mesh at either strain (1e-5). An FP32
+    evaluation on F itself would lose about three digits at the small strain
+    (relative error ~6e-8 / strain)."""
+    w = W.workload_cantilever(0, kind=kind)
+    s = qnsim.sim_from_workload(w, precision=qnsim.QNSIM_MIXED)
+    m = _model(w)
+    x = _perturbed(w, amp, 11)
+    psi_ref, P_ref = fem.element_psi_P(m, x)
+    psi = torch.empty(w.n_tets, dtype=torch.float64, device="cuda")
+    P = torch.empty(w.n_tets, 9, dtype=torch.float64, device="cuda")
+    s.element_stress_device(_dev(x), psi, P)
+    torch.cuda.synchronize()
+    psi, P = psi.cpu().numpy(), P.cpu().numpy().reshape(-1, 3, 3)
+    ep = np.abs(psi - psi_ref).max() / np.abs(psi_ref).max()
+    eP = np.abs(P - P_ref).max() / np.abs(P_ref).max()
+    print(f"mixed {W.MATERIAL_NAMES[kind]} at amplitude {amp}: Psi {ep:.2e}, P {eP:.2e}", flush=True)
+    assert ep <= 1e-5 and eP <= 1e-5
+    s.close()
+
+
 def test_mixed_precision_objective_and_gradient():
     """The mixed evaluation of g and its gradient against the FP64 oracle at a
     perturbed state (FP32 element terms: relative error ~1e-6 expected)."""

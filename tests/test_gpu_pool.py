@@ -266,6 +266,98 @@ def test_serving_results_equal_alone():
     p.close()
 
 
+def test_commit_while_serving_results_equal_alone():
+    """Live admission: while two lanes serve a steady stream of requests for
+    four resident simulations, three new ones are added and committed (built
+    and uploaded outside the pool's lock); requests for them follow as soon
+    as they are resident. Every simulation's final state equals its run
+    alone with the same number of steps, bit for bit."""
+    import time
+    old = [W.workload_block([W.NEOHOOKEAN, W.STVK][i % 2], dims=(3, 3 + i, 4),
+                            prestretch_seed=60 + i) for i in range(4)]
+    new = [W.workload_block([W.SPLINE, W.NEOHOOKEAN, W.STVK][i], dims=(4, 3, 3 + i),
+                            prestretch_seed=70 + i) for i in range(3)]
+    p, ids = _pool(old, group=2)
+    p.serve_start(lanes=2)
+    counts = {}
+    stop = threading.Event()
+    errors = []
+
+    def client():
+        try:
+            k = 0
+            while not stop.is_set() or k < 24:
+                j = k % 4
+                t = p.submit(ids[j])
+                st, _ = p.wait(t, 60.0)
+                assert st["iterations_run"] == 10
+                counts[ids[j]] = counts.get(ids[j], 0) + 1
+                k += 1
+        except Exception as e:  # noqa: BLE001
+            errors.append(e)
+
+    th = threading.Thread(target=client)
+    th.start()
+    time.sleep(0.05)
+    before = p.info()["steps_done"]
+    nids = p.add_workloads(new)
+    admitted = p.commit(0)
+    during = p.info()["steps_done"] - before
+    assert admitted == 3
+    tickets = [(nid, p.submit(nid)) for nid in nids for _ in range(2)]
+    for nid, t in tickets:
+        st, _ = p.wait(t, 60.0)
+        assert st["iterations_run"] == 10
+        counts[nid] = counts.get(nid, 0) + 1
+    stop.set()
+    th.join()
+    p.serve_stop()
+    assert not errors, errors
+    for j, w in enumerate(old + new):
+        sid = (ids + nids)[j]
+        ref = _alone(w, counts[sid])
+        x, v = p.get_state(sid)
+        assert np.array_equal(x, ref[-1][0]) and np.array_equal(v, ref[-1][1]), \
+            f"sim {j} after {counts[sid]} served steps: eps vs alone {_eps(x, ref[-1][0], w.rest):.3e}"
+    print(f"live admission: {during} requests completed while the commit ran; "
+          f"{sum(counts.values())} served in all, each bitwise equal to alone", flush=True)
+    p.close()
+
+
+def test_commit_repacks_a_group_with_removed_members():
+    """Two of four members of a group (holding more than half of its memory)
+    are removed; the next commit rebuilds the group with the two live members
+    (states copied on the device), returning memory to the budget; their
+    later steps equal their runs alone bit for bit, and a force set before
+    the rebuild still acts after it."""
+    ws = [W.workload_block(W.NEOHOOKEAN, dims=d, prestretch_seed=80 + i)
+          for i, d in enumerate([(3, 3, 3), (6, 5, 4), (3, 4, 3), (5, 6, 4)])]
+    p, ids = _pool(ws)
+    f = np.zeros((ws[2].n_verts, 3))
+    f[:, 0] = 0.5
+    p.set_force(ids[2], f)
+    p.step(ids)
+    p.step(ids)
+    p.remove(ids[1])
+    p.remove(ids[3])
+    used = p.info()["used_bytes"]
+    assert p.commit(0) == 0
+    assert p.info()["used_bytes"] < used
+    for _ in range(2):
+        p.step([ids[0], ids[2]])
+    ref0 = _alone(ws[0], 4)
+    x, v = p.get_state(ids[0])
+    assert np.array_equal(x, ref0[-1][0]) and np.array_equal(v, ref0[-1][1])
+    s = qnsim.sim_from_workload(ws[2], dense_top=0, level_merge=0)
+    x2, v2 = ws[2].x0.copy(), ws[2].v0.copy()
+    for _ in range(4):
+        x2, v2, _ = s.step(x2, v2, ws[2].h, f_ext=f)
+    x, v = p.get_state(ids[2])
+    assert np.array_equal(x, x2) and np.array_equal(v, v2)
+    s.close()
+    p.close()
+
+
 def test_pool_graph_replays_equal_eager():
     """Groups replaying their captured step (run flags changing between
     replays) equal groups launching kernel by kernel, bit for bit."""
