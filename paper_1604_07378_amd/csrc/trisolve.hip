@@ -688,28 +688,22 @@ k_top_sym(const double* __restrict__ tiles, const double* __restrict__ q,
   }
   __syncthreads();
   const int c0 = 2 * cp;
-  double ra[8][3], ca[2][3];
+  double ca[2][3];
 #pragma unroll
   for (int comp = 0; comp < 3; ++comp) ca[0][comp] = ca[1][comp] = 0.0;
+  // T_IJ t_J: this half wave's eight rows, each reduced as soon as formed
+  double* pr = part + ((size_t)I * nb + J) * TT * 3 + (size_t)rg * 8 * 3;
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
     const int r = rg * 8 + i;
 #pragma unroll
     for (int comp = 0; comp < 3; ++comp) {
-      ra[i][comp] = e[i].x * tJ[c0][comp] + e[i].y * tJ[c0 + 1][comp];
+      const double v = group_sum(e[i].x * tJ[c0][comp] + e[i].y * tJ[c0 + 1][comp], 32);
+      if (cp == 0) pr[3 * i + comp] = v;
       ca[0][comp] += e[i].x * tI[r][comp];
       ca[1][comp] += e[i].y * tI[r][comp];
     }
   }
-  // T_IJ t_J: this half wave's eight rows
-  double* pr = part + ((size_t)I * nb + J) * TT * 3 + (size_t)rg * 8 * 3;
-#pragma unroll
-  for (int i = 0; i < 8; ++i)
-#pragma unroll
-    for (int comp = 0; comp < 3; ++comp) {
-      const double v = group_sum(ra[i][comp], 32);
-      if (cp == 0) pr[3 * i + comp] = v;
-    }
   if (I == J) return;  // the diagonal tile's full square gave the whole product
   // T_IJ^T t_I: column sums over the eight row groups
 #pragma unroll
@@ -727,19 +721,40 @@ k_top_sym(const double* __restrict__ tiles, const double* __restrict__ q,
   }
 }
 
-// Dense top block, step 2: w_T, entry by entry, as the sum of its block's
-// slots in slot order.
-__global__ void __launch_bounds__(256)
+// Dense top block, step 2: w_T as the sum of each block row's slots. One
+// workgroup per block row; each of its 192 outputs (64 rows x 3) is summed
+// by 4 threads over the slots k = g, g + 4, ... (their loads in flight
+// together), and the 4 partial sums are added in g order.
+constexpr int kTopSumGroups = 4;
+__global__ void __launch_bounds__(kTopTile * 3 * kTopSumGroups)
 k_top_sum(const double* __restrict__ part, int n, int nb, double* __restrict__ w,
           const int* __restrict__ gate) {
+  constexpr int NO = kTopTile * 3;  // outputs of a block row
+  __shared__ double red[kTopSumGroups][NO];
   if (gate && *gate <= 0) return;
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= 3 * n) return;
-  const int row = i / 3, comp = i % 3, I = row / kTopTile;
-  const double* p = part + (size_t)I * nb * kTopTile * 3 + (size_t)(row % kTopTile) * 3 + comp;
+  const int I = blockIdx.x, o = threadIdx.x % NO, g = threadIdx.x / NO;
+  const double* p = part + (size_t)I * nb * NO + o;
+  constexpr int U = 8;
   double s = 0.0;
-  for (int k = 0; k < nb; ++k) s += p[(size_t)k * kTopTile * 3];
-  w[i] = s;
+  for (int k0 = g; k0 < nb; k0 += U * kTopSumGroups) {
+    double v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int k = k0 + u * kTopSumGroups;
+      v[u] = k < nb ? p[(size_t)k * NO] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) s += v[u];
+  }
+  red[g][o] = s;
+  __syncthreads();
+  if (g == 0) {
+    const int row = I * kTopTile + o / 3;
+    double t = red[0][o];
+#pragma unroll
+    for (int k = 1; k < kTopSumGroups; ++k) t += red[k][o];
+    if (row < n) w[3 * (size_t)row + o % 3] = t;
+  }
 }
 
 void launch_solve(DeviceMesh& D, hipStream_t st, const double* q, double* r, const int* gate,
@@ -779,8 +794,8 @@ void launch_solve(DeviceMesh& D, hipStream_t st, const double* q, double* r, con
     const int n = D.top_n, nb = top_blocks(n);
     hipLaunchKernelGGL(k_top_sym, dim3(nb * (nb + 1) / 2), dim3(256), 0, st, D.Bf + D.top_off,
                        q + 3 * (size_t)D.top_first, vp + D.top_vp, D.top_nch, n, nb, top_t, gate);
-    hipLaunchKernelGGL(k_top_sum, dim3((3 * n + 255) / 256), dim3(256), 0, st, top_t, n, nb,
-                       r + 3 * (size_t)D.top_first, gate);
+    hipLaunchKernelGGL(k_top_sum, dim3(nb), dim3(kTopTile * 3 * kTopSumGroups), 0, st, top_t,
+                       n, nb, r + 3 * (size_t)D.top_first, gate);
   }
   for (int l = L - 1; l >= D.sub_levels; --l) {
     const int n = D.levels[l].bw_end - D.levels[l].bw_begin;

@@ -448,6 +448,41 @@ int upload_sims(const std::vector<const qnsim*>& sims, const qnsim_options& opt,
       ++n_tasks;
     }
   }
+  // Within a level the items are independent; they are launched largest
+  // first (entries streamed plus the staged right-hand side), so that the
+  // hardware's in-order dispatch of workgroups to free slots is a longest-
+  // processing-time-first schedule and a level with slightly more items
+  // than resident workgroups ends with small items, not large ones.
+  {
+    auto fw_cost = [&](const int4& it) {
+      const int s2 = it.x, nc = F.sn[s2].ncol;
+      int64_t e = 0;
+      for (int r = it.y; r < it.z; ++r) e += r < nc ? r + 1 : nc;
+      return e + 2 * (int64_t)nc;
+    };
+    auto bw_cost = [&](const int4& it) {
+      const int s2 = it.x & 0x7fffffff, m = F.sn[s2].m();
+      int64_t e = 0;
+      for (int c = it.y; c < it.z; ++c) e += m - c;
+      return e + 2 * (int64_t)(m - it.y);
+    };
+    for (int l = 0; l < F.nlevels; ++l) {
+      std::vector<int4>& fv = fw_by_level[l];
+      std::vector<int4>& bv = bw_by_level[l];
+      std::vector<std::pair<int64_t, int>> key(fv.size());
+      for (size_t i = 0; i < fv.size(); ++i) key[i] = {-fw_cost(fv[i]), (int)i};
+      std::stable_sort(key.begin(), key.end());
+      std::vector<int4> sorted(fv.size());
+      for (size_t i = 0; i < fv.size(); ++i) sorted[i] = fv[key[i].second];
+      fv.swap(sorted);
+      key.assign(bv.size(), {0, 0});
+      for (size_t i = 0; i < bv.size(); ++i) key[i] = {-bw_cost(bv[i]), (int)i};
+      std::stable_sort(key.begin(), key.end());
+      sorted.assign(bv.size(), int4{});
+      for (size_t i = 0; i < bv.size(); ++i) sorted[i] = bv[key[i].second];
+      bv.swap(sorted);
+    }
+  }
   D.levels.assign(F.nlevels, Level{0, 0, 0, 0});
   for (int l = 0; l < F.nlevels; ++l) {
     D.levels[l].fw_begin = (int)fwl.size();
