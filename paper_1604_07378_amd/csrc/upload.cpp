@@ -260,15 +260,31 @@ int upload_sims(const std::vector<const qnsim*>& sims, const qnsim_options& opt,
   // bw; returns the number of forward items). Forward: groups of Lf lanes per
   // row, up to 4 rows per group; backward: groups of Lb lanes per column, up
   // to 4 columns per group.
+  // The entries an item aims at, per level: a level's factor entries spread
+  // over about kLevelItems items (a round of resident workgroups), at least
+  // kItemMin and at most kItemMax entries each; an item's rows (columns)
+  // come in whole rounds of the lane groups, so the aim is approximate.
+  constexpr int64_t kLevelItems = 768, kItemMin = 4096, kItemMax = 32768;
+  std::vector<int64_t> level_aim(F.nlevels, 16384);
+  {
+    std::vector<int64_t> ent(F.nlevels, 0);
+    for (int s = 0; s < ns; ++s)
+      if (s != top)
+        ent[F.sn[s].level] += (int64_t)F.sn[s].ncol * (F.sn[s].ncol + 1) / 2 +
+                              (int64_t)F.sn[s].nbelow * F.sn[s].ncol;
+    for (int l = 0; l < F.nlevels; ++l)
+      level_aim[l] = std::max(kItemMin, std::min(kItemMax, ent[l] / kLevelItems));
+  }
   auto level_items = [&](int s, std::vector<int4>& fw, std::vector<int4>& bw) {
     const int nc = F.sn[s].ncol, m = F.sn[s].m();
+    const int64_t aim = level_aim[F.sn[s].level];
     const int Lf = clampi(pow2ceil((nc + 3) / 4), 4, 64), sf = 4 * (64 / Lf);
-    const int rpg_f = clampi(((16384 + nc - 1) / nc + sf - 1) / sf, 1, 4);
+    const int rpg_f = clampi((int)(((aim + nc - 1) / nc + sf - 1) / sf), 1, 4);
     const int rows_item = sf * rpg_f;
     for (int r0 = 0; r0 < m; r0 += rows_item)
       fw.push_back(make_int4(s, r0, std::min(m, r0 + rows_item), Lf));
     const int Lb = clampi(pow2ceil((m + 3) / 4), 4, 64), sb = 4 * (64 / Lb);
-    const int rpg_b = clampi(((16384 + m - 1) / m + sb - 1) / sb, 1, 4);
+    const int rpg_b = clampi((int)(((aim + m - 1) / m + sb - 1) / sb), 1, 4);
     const int cols_item = sb * rpg_b;
     for (int c0 = 0; c0 < nc; c0 += cols_item)
       bw.push_back(make_int4((int)(0x80000000u | (unsigned)s), c0, std::min(nc, c0 + cols_item), Lb));
