@@ -483,8 +483,10 @@ int qnsim_pool_add(qnsim_pool_t* pool, int32_t n, const qnsim_mesh_desc* descs, 
  * their own streams), and the new simulations become resident, able to take
  * requests, when their group is published. A group whose removed members
  * hold at least half of its estimated memory is first rebuilt with its live
- * members (states and forces copied on the device; its requests wait
- * meanwhile), and the memory it frees counts for the admission. One commit
+ * members while the old group keeps serving them; once the old group is not
+ * stepping, their states and forces are copied to the new group on the
+ * device (under the pool's lock) and it replaces the old one, before the new
+ * groups are built; the memory it frees counts for the admission. One commit
  * runs at a time (later ones wait); on a failure the simulations of the
  * failed group and of the groups after it stay staged and the first error
  * is returned. */

@@ -53,6 +53,8 @@ struct PoolGroup {
   int64_t bytes = 0;
   int live = 0;              // members not removed
   bool busy = false;         // a step is running
+  bool repacking = false;    // a commit is rebuilding it without its removed members (it
+                             // keeps serving; the members' host data stays meanwhile)
   int trials = 0;            // line-search trials per cycle from the tuner (0: the pool's)
 };
 
@@ -244,10 +246,11 @@ int build_group(const qnsim_options& opt, double h, GroupBuild& b) {
 
 // A group rebuilt without its removed members (their device memory is
 // returned to the budget): the live members' host contexts and their slots
-// in the old group, whose states (and forces) are copied over on the device.
+// in the old group. The old group keeps serving while the new one is built;
+// their states (and forces) are copied over on the device when it replaces
+// the old one.
 struct Repack {
   int gi = -1;
-  PoolGroup* old = nullptr;
   std::vector<int> ids, old_slots;
   std::vector<const qnsim*> cs;
   bool refactored = false;   // the pool's h differs from the analysed one
@@ -256,9 +259,10 @@ struct Repack {
   std::string err;
 };
 
-// Builds r.g from r's live members; the old group is marked busy by the
-// caller, so nothing else reads or steps it meanwhile. Runs without the lock.
-int build_repack(const qnsim_options& opt, double h, Repack& r) {
+// Builds r.g from r's live members (mesh, factor, empty state arrays); reads
+// only their host contexts, which stay while the old group is marked
+// repacking. Runs without the lock.
+int build_repack(const qnsim_options& opt, double h, int elem_tile, Repack& r) {
   auto g = std::make_unique<PoolGroup>();
   int n = 0;
   for (const qnsim* c : r.cs) {
@@ -267,39 +271,53 @@ int build_repack(const qnsim_options& opt, double h, Repack& r) {
   }
   if (hipSetDevice(opt.device) != hipSuccess) { r.err = "hipSetDevice failed"; return QNSIM_E_DEVICE; }
   qnsim_options o = opt;
-  o.elem_tile = r.old->D.elem_tile;
+  o.elem_tile = elem_tile;
   int rc = upload_sims(r.cs, o, h, g->D, r.err);
   // host factor values belong to an earlier h after a time-step change
   if (!rc && r.refactored) rc = dev_refactor_mesh(r.cs, g->D, h, nullptr, r.err);
   if (rc) { free_group(*g); return rc; }
   const size_t bytes = 3 * (size_t)n * sizeof(double);
-  if (hipMalloc((void**)&g->xs, bytes) != hipSuccess || hipMalloc((void**)&g->vs, bytes) != hipSuccess ||
-      (r.old->fx && hipMalloc((void**)&g->fx, bytes) != hipSuccess)) {
+  if (hipMalloc((void**)&g->xs, bytes) != hipSuccess || hipMalloc((void**)&g->vs, bytes) != hipSuccess) {
     free_group(*g);
     r.err = "state allocation failed";
     return QNSIM_E_NOMEM;
   }
-  hipStream_t st = (hipStream_t)r.old->D.stream;
+  g->ids = r.ids;
+  g->bytes = (int64_t)g->D.bytes + 2 * (int64_t)bytes;
+  r.g = std::move(g);
+  return QNSIM_OK;
+}
+
+// Moves the members' states (and forces) from the old group into the
+// rebuilt one on the device; the old group is not stepping (the caller
+// holds the lock and waited for it).
+int repack_states(const PoolGroup& old, PoolGroup& g, const Repack& r, std::string& err) {
+  size_t n = 0;
+  for (const qnsim* c : r.cs) n += (size_t)c->n;
+  const size_t bytes = 3 * n * sizeof(double);
+  if (old.fx && !g.fx) {  // the first force was set while the group was rebuilt
+    if (hipMalloc((void**)&g.fx, bytes) != hipSuccess) {
+      g.fx = nullptr;
+      err = "force allocation failed";
+      return QNSIM_E_NOMEM;
+    }
+    g.bytes += (int64_t)bytes;
+  }
+  hipStream_t st = (hipStream_t)g.D.stream;
   hipError_t e = hipSuccess;
   for (size_t k = 0; k < r.cs.size() && e == hipSuccess; ++k) {
-    const size_t dst = 3 * (size_t)g->cv0[k], src = 3 * (size_t)r.old->cv0[r.old_slots[k]];
+    const size_t dst = 3 * (size_t)g.cv0[k], src = 3 * (size_t)old.cv0[r.old_slots[k]];
     const size_t nb = 3 * (size_t)r.cs[k]->n * sizeof(double);
-    e = hipMemcpyAsync(g->xs + dst, r.old->xs + src, nb, hipMemcpyDeviceToDevice, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(g->vs + dst, r.old->vs + src, nb, hipMemcpyDeviceToDevice, st);
-    if (e == hipSuccess && g->fx)
-      e = hipMemcpyAsync(g->fx + dst, r.old->fx + src, nb, hipMemcpyDeviceToDevice, st);
+    e = hipMemcpyAsync(g.xs + dst, old.xs + src, nb, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(g.vs + dst, old.vs + src, nb, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess && g.fx)
+      e = hipMemcpyAsync(g.fx + dst, old.fx + src, nb, hipMemcpyDeviceToDevice, st);
   }
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) {
-    free_group(*g);
-    r.err = std::string("state copy failed: ") + hipGetErrorString(e);
+    err = std::string("state copy failed: ") + hipGetErrorString(e);
     return QNSIM_E_DEVICE;
   }
-  g->ids = r.ids;
-  g->live = (int)r.ids.size();
-  g->trials = r.old->trials;
-  g->bytes = (int64_t)g->D.bytes + (g->fx ? 3 : 2) * (int64_t)bytes;
-  r.g = std::move(g);
   return QNSIM_OK;
 }
 
@@ -524,15 +542,16 @@ int qnsim_pool_commit(qnsim_pool_t* p, int32_t max_group_sims, int32_t* n_admitt
   std::unique_lock<std::mutex> lk(p->mu);
   p->cv.wait(lk, [&] { return !p->admin_busy; });
   // 1. plan under the lock. Groups whose removed members hold at least half
-  //    of their memory are repacked (rebuilt with the live members, marked
-  //    busy meanwhile: their requests wait); the memory that frees counts
-  //    for the admission. Then staged simulations in id order while the
-  //    budget allows, max_group_sims per group.
+  //    of their memory are repacked (rebuilt with the live members while
+  //    the old group keeps serving them); the memory that frees counts for
+  //    the admission. Then staged simulations in id order while the budget
+  //    allows, max_group_sims per group.
   std::vector<Repack> repacks;
+  std::vector<int> repack_tile;
   int64_t freed = 0;
   for (int gi = 0; gi < (int)p->groups.size(); ++gi) {
     PoolGroup& g = *p->groups[gi];
-    if (g.live == 0 || g.live == (int)g.ids.size() || g.busy) continue;
+    if (g.live == 0 || g.live == (int)g.ids.size() || g.repacking) continue;
     int64_t dead = 0, all = 0;
     for (int id : g.ids) {
       all += p->sims[id].est_bytes;
@@ -541,7 +560,6 @@ int qnsim_pool_commit(qnsim_pool_t* p, int32_t max_group_sims, int32_t* n_admitt
     if (2 * dead < all) continue;
     Repack r;
     r.gi = gi;
-    r.old = &g;
     for (size_t k = 0; k < g.ids.size(); ++k) {
       const PoolSim& m = p->sims[g.ids[k]];
       if (m.removed) continue;
@@ -550,8 +568,9 @@ int qnsim_pool_commit(qnsim_pool_t* p, int32_t max_group_sims, int32_t* n_admitt
       r.cs.push_back(m.c);
       r.refactored = r.refactored || m.c->factor_on_device;
     }
-    g.busy = true;
+    g.repacking = true;
     freed += dead;
+    repack_tile.push_back(g.D.elem_tile);
     repacks.push_back(std::move(r));
   }
   std::vector<std::vector<int>> plan;
@@ -586,17 +605,57 @@ int qnsim_pool_commit(qnsim_pool_t* p, int32_t max_group_sims, int32_t* n_admitt
   const double h = p->h;
   lk.unlock();
   // 2. build and upload outside the lock: serving lanes keep picking and
-  //    stepping resident groups meanwhile; repacks first (their memory is
-  //    freed before the new groups allocate); a failed group and the ones
-  //    after it are not built
-  for (Repack& r : repacks) {
+  //    stepping resident groups (those being repacked included) meanwhile;
+  //    repacks first, and they replace their old groups (whose memory is
+  //    freed) before the new groups allocate
+  int rc = QNSIM_OK;
+  std::string err;
+  for (size_t k = 0; k < repacks.size(); ++k) {
+    Repack& r = repacks[k];
     try {
-      r.rc = build_repack(opt, h, r);
+      r.rc = build_repack(opt, h, repack_tile[k], r);
     } catch (const std::bad_alloc&) {
       r.rc = QNSIM_E_NOMEM;
       r.err = "host allocation failed";
     }
-    if (!r.rc) free_group(*r.old);  // busy: nothing else touches it
+  }
+  if (!repacks.empty()) {
+    std::vector<std::unique_ptr<PoolGroup>> dead;
+    lk.lock();
+    for (Repack& r : repacks) {
+      p->cv.wait(lk, [&] { return !p->groups[r.gi]->busy; });
+      PoolGroup& old = *p->groups[r.gi];
+      old.repacking = false;
+      if (!r.rc && old.live > 0) r.rc = repack_states(old, *r.g, r, r.err);
+      if (r.rc || old.live == 0) {
+        if (r.g) free_group(*r.g);
+        if (r.rc) {  // the old group stays as it was
+          if (!rc) { rc = r.rc; err = "repack: " + r.err; }
+          continue;
+        }
+        // every member was removed while the group was rebuilt
+        p->used -= old.bytes;
+        free_group(old);
+        for (int id : old.ids)
+          if (p->sims[id].c) { qnsim_destroy(p->sims[id].c); p->sims[id].c = nullptr; }
+        continue;
+      }
+      r.g->live = old.live;
+      r.g->trials = old.trials;
+      p->used += r.g->bytes - old.bytes;
+      std::vector<char> kept(p->sims.size(), 0);
+      for (int id : r.ids) kept[id] = 1;
+      for (int id : old.ids) {  // members removed before the repack leave for good
+        PoolSim& m = p->sims[id];
+        if (!kept[id] && m.c) { qnsim_destroy(m.c); m.c = nullptr; }
+      }
+      for (size_t k = 0; k < r.ids.size(); ++k) p->sims[r.ids[k]].slot = (int)k;
+      dead.push_back(std::move(p->groups[r.gi]));
+      p->groups[r.gi] = std::move(r.g);
+    }
+    p->cv.notify_all();
+    lk.unlock();
+    for (auto& g : dead) free_group(*g);  // no lane holds a replaced group
   }
   bool failed = false;
   for (GroupBuild& b : builds) {
@@ -609,29 +668,9 @@ int qnsim_pool_commit(qnsim_pool_t* p, int32_t max_group_sims, int32_t* n_admitt
     }
     failed = b.rc != QNSIM_OK;
   }
-  // 3. publish under the lock
+  // 3. publish the new groups under the lock
   lk.lock();
-  int admitted = 0, rc = QNSIM_OK;
-  std::string err;
-  for (Repack& r : repacks) {
-    PoolGroup& old = *p->groups[r.gi];
-    if (r.rc) {  // the old group stays as it was
-      old.busy = false;
-      if (!rc) { rc = r.rc; err = "repack: " + r.err; }
-      continue;
-    }
-    p->used += r.g->bytes - old.bytes;
-    std::vector<char> kept(p->sims.size(), 0);
-    for (int id : r.ids) kept[id] = 1;
-    for (int id : old.ids) {  // members removed before the repack leave for good
-      PoolSim& m = p->sims[id];
-      if (!kept[id] && m.c) { qnsim_destroy(m.c); m.c = nullptr; }
-    }
-    for (size_t k = 0; k < r.ids.size(); ++k) p->sims[r.ids[k]].slot = (int)k;
-    // a member removed while the repack ran is counted out by its
-    // qnsim_pool_remove, which waits for the group and finds the new one
-    p->groups[r.gi] = std::move(r.g);
-  }
+  int admitted = 0;
   for (GroupBuild& b : builds) {
     if (b.rc) {
       // not admitted: the simulations stay staged with their initial state
@@ -684,7 +723,9 @@ int qnsim_pool_remove(qnsim_pool_t* p, int32_t id) {
     // and a concurrent add may move the simulation records
     p->cv.wait(lk, [&] { return !p->groups[p->sims[id].group]->busy; });
     PoolGroup& g = *p->groups[p->sims[id].group];
-    if (--g.live == 0) {
+    // a group being repacked is freed by the commit once its build is done
+    // (the build reads the members' host data)
+    if (--g.live == 0 && !g.repacking) {
       p->used -= g.bytes;
       free_group(g);
       // the members' host data served the group's refactorisation

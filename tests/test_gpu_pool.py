@@ -358,6 +358,65 @@ def test_commit_repacks_a_group_with_removed_members():
     p.close()
 
 
+def test_repack_while_serving_results_equal_alone():
+    """A group is rebuilt without its two removed members while two lanes
+    keep serving its two live members (the old group steps them until the
+    new one, with their states copied over, replaces it); a third
+    simulation in another group is served throughout. Every final state
+    equals the simulation's run alone with the same number of steps, bit for
+    bit, and the removed members' memory returns to the budget."""
+    import time
+    ws = [W.workload_block(W.NEOHOOKEAN, dims=d, prestretch_seed=90 + i)
+          for i, d in enumerate([(4, 3, 3), (7, 6, 5), (3, 4, 4), (6, 7, 5)])]
+    other = W.workload_block(W.STVK, dims=(4, 4, 3), prestretch_seed=95)
+    p, ids = _pool(ws + [other], group=4)
+    p.step(ids)
+    p.remove(ids[1])
+    p.remove(ids[3])
+    used = p.info()["used_bytes"]
+    p.serve_start(lanes=2)
+    live = [ids[0], ids[2], ids[4]]
+    counts = {sid: 1 for sid in live}  # the step before the removals
+    stop = threading.Event()
+    errors = []
+
+    def client():
+        try:
+            k = 0
+            while not stop.is_set() or k < 12:
+                sid = live[k % 3]
+                st, _ = p.wait(p.submit(sid), 60.0)
+                assert st["iterations_run"] == 10
+                counts[sid] += 1
+                k += 1
+        except Exception as e:  # noqa: BLE001
+            errors.append(e)
+
+    th = threading.Thread(target=client)
+    th.start()
+    time.sleep(0.05)
+    before = p.info()["steps_done"]
+    assert p.commit(0) == 0
+    during = p.info()["steps_done"] - before
+    time.sleep(0.05)
+    stop.set()
+    th.join()
+    p.serve_stop()
+    assert not errors, errors
+    assert p.info()["used_bytes"] < used
+    for j, sid in [(0, ids[0]), (2, ids[2])]:
+        ref = _alone(ws[j], counts[sid])
+        x, v = p.get_state(sid)
+        assert np.array_equal(x, ref[-1][0]) and np.array_equal(v, ref[-1][1]), \
+            f"member {j} after {counts[sid]} steps: eps vs alone {_eps(x, ref[-1][0], ws[j].rest):.3e}"
+    ref = _alone(other, counts[ids[4]])
+    x, v = p.get_state(ids[4])
+    assert np.array_equal(x, ref[-1][0]) and np.array_equal(v, ref[-1][1])
+    print(f"repack while serving: {during} requests completed while the commit ran; "
+          f"steps {counts}", flush=True)
+    p.close()
+
+
 def test_pool_graph_replays_equal_eager():
     """Groups replaying their captured step (run flags changing between
     replays) equal groups launching kernel by kernel, bit for bit."""
