@@ -11,8 +11,9 @@
 // Backward (root to leaves):
 //     w_S = (L11^{-1})^T z_S - (L21 L11^{-1})^T w_{rows below S}
 // Work items are a supernode and a block of its rows (forward) or columns
-// (backward); a lane group of 4..64 lanes computes one row or column, so a
-// large separator spreads over hundreds of workgroups. Levels of the tree are
+// (backward); a lane group of 4..64 lanes (about one per 16 entries of the
+// row or column) computes one row or column, so a large separator spreads
+// over hundreds of workgroups. Levels of the tree are
 // ordered by kernel boundaries (one launch per level and sweep), except for
 // the lowest levels, where one workgroup walks a whole subtree, and the
 // highest levels, merged into one dense block (see the dense top block
