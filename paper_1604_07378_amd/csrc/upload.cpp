@@ -270,10 +270,12 @@ int upload_sims(const std::vector<const qnsim*>& sims, const qnsim_options& opt,
   // row, up to 4 rows per group; backward: groups of Lb lanes per column, up
   // to 4 columns per group.
   // The entries an item aims at, per level: a level's factor entries spread
-  // over about kLevelItems items (a round of resident workgroups), at least
-  // kItemMin and at most kItemMax entries each; an item's rows (columns)
-  // come in whole rounds of the lane groups, so the aim is approximate.
-  constexpr int64_t kLevelItems = 768, kItemMin = 4096, kItemMax = 32768;
+  // over about kLevelItems items (fewer than the 1,024 workgroups the level
+  // kernels keep resident, since an item's rows come in whole rounds of its
+  // lane groups and the counts overshoot; at 40^3 an aim of 640 items gave
+  // 0.195 ms per solve, 768 0.202 ms, 1,024 0.210 ms, 320 0.198 ms), at
+  // least kItemMin and at most kItemMax entries each.
+  constexpr int64_t kLevelItems = 640, kItemMin = 4096, kItemMax = 32768;
   std::vector<int64_t> level_aim(F.nlevels, 16384);
   {
     std::vector<int64_t> ent(F.nlevels, 0);
