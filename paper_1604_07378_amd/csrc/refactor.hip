@@ -134,20 +134,19 @@ __global__ __launch_bounds__(256) void k_rf_extend(const int* __restrict__ lvl_n
 // nodes of the level (more nodes than a grid dimension holds are fine).
 #define RF_NODES(ni, act) for (int ni = blockIdx.y; ni < (act); ni += gridDim.y)
 
-// Round j0, step 1 (one wave per node): Cholesky of the diagonal block and
-// its inverse, L_jj^{-1}, which is also the diagonal block of
-// Z = [L11^{-1}; -L21 L11^{-1}] (Z starts at zero; the identity's diagonal
-// blocks enter here). Lane i holds row i of the block in registers, padded
-// with the identity past the last column of the supernode; every loop is
-// unrolled so that the rows stay in registers.
-__global__ __launch_bounds__(64) void k_rf_diag(const int* __restrict__ lvl_nodes,
-                                                const RfNode* __restrict__ node,
-                                                double* __restrict__ ws, double* __restrict__ Z,
-                                                int j0, int* __restrict__ flag) {
-  __shared__ double col[NB];
-  __shared__ double Lm[NB][NB + 1];
-  __shared__ double dinv[NB];
-  const RfNode nd = node[lvl_nodes[blockIdx.x]];
+// Round j0, step 1: Cholesky of the diagonal block and its inverse,
+// L_jj^{-1}, which is also the diagonal block of Z = [L11^{-1}; -L21 L11^{-1}]
+// (Z starts at zero; the identity's diagonal blocks enter here). The first
+// wave of the block does the arithmetic and every thread of the block must
+// call this (it holds block barriers). Lane i holds row i of the block in
+// registers, padded with the identity past the last column of the supernode;
+// every loop is unrolled so that the rows stay in registers. L_jj goes to the
+// front, L_jj^{-1} to Iv (row-major) and to Z. LDS: Lm and Iv (NB x (NB + 1)
+// each), col and dinv (NB each).
+__device__ __forceinline__ void rf_diag_block(const RfNode& nd, double* __restrict__ ws,
+                                              double* __restrict__ Z, int j0,
+                                              int* __restrict__ flag, double (*Lm)[NB + 1],
+                                              double* col, double* dinv, double (*Iv)[NB + 1]) {
   const int nc = nd.ncol, m = nc + nd.nbelow;
   const int jb = min(NB, nc - j0);
   double* F = ws + nd.front;
@@ -211,23 +210,34 @@ __global__ __launch_bounds__(64) void k_rf_diag(const int* __restrict__ lvl_node
     const double s = s0 + s1;
     x[r] = r == i ? dinv[r] : (r > i ? -dinv[r] * s : 0.0);
   }
-  __syncthreads();  // Lm has been read
   if (lane) {
 #pragma unroll
-    for (int r = 0; r < NB; ++r) Lm[r][i] = x[r];
+    for (int r = 0; r < NB; ++r) Iv[r][i] = x[r];
   }
   __syncthreads();
   double* Zn = Z + nd.zoff;
   if (lane && i < jb) {
 #pragma unroll
     for (int c = 0; c < NB; ++c)
-      if (c < jb) Zn[(j0 + i) + (long long)(j0 + c) * m] = Lm[i][c];
+      if (c < jb) Zn[(j0 + i) + (long long)(j0 + c) * m] = Iv[i][c];
   }
 }
 
+// Round j0, step 1: one wave per node.
+__global__ __launch_bounds__(64) void k_rf_diag(const int* __restrict__ lvl_nodes,
+                                                const RfNode* __restrict__ node,
+                                                double* __restrict__ ws, double* __restrict__ Z,
+                                                int j0, int* __restrict__ flag) {
+  __shared__ double Lm[NB][NB + 1], Iv[NB][NB + 1];
+  __shared__ double col[NB], dinv[NB];
+  const RfNode nd = node[lvl_nodes[blockIdx.x]];
+  rf_diag_block(nd, ws, Z, j0, flag, Lm, col, dinv, Iv);
+}
+
 // Round j0, step 2. Tiles y < nT: the panel rows below the diagonal block,
-// L_r = F_r L_jj^{-T} (64 rows per tile). Tiles y >= nT: row block J of Z left
-// of the diagonal block, Z_J <- L_jj^{-1} Z_J (64 columns per tile).
+// L_r = F_r L_jj^{-T} (64 rows per tile). Tiles y >= nT: row block J of Z
+// left of the diagonal block, Z_J <- L_jj^{-1} Z_J (64 columns per tile),
+// staged in LDS; L_jj^{-1} is read from Z (written by step 1).
 __global__ __launch_bounds__(256) void k_rf_rows(const int* __restrict__ lvl_nodes,
                                                  const RfNode* __restrict__ node, int act,
                                                  double* __restrict__ ws, double* __restrict__ Z,
@@ -245,17 +255,26 @@ __global__ __launch_bounds__(256) void k_rf_rows(const int* __restrict__ lvl_nod
     double* F = ws + nd.front;
     double* Zn = Z + nd.zoff;
     __syncthreads();  // LDS of the previous node is free
-    for (int e = tid; e < NB * NB; e += 256) {
-      const int i = e % NB, k = e / NB;
-      Iv[i][k] = (i < jb && k < jb) ? Zn[(j0 + i) + (long long)(j0 + k) * m] : 0.0;
-    }
     if (t < nT) {
       const int r0 = s0 + t * TL;
       for (int e = tid; e < TL * NB; e += 256) {
         const int r = e % TL, p = e / TL;
         St[r][p] = (p < jb && r0 + r < m) ? F[(r0 + r) + (long long)(j0 + p) * m] : 0.0;
       }
-      __syncthreads();
+    } else {
+      const int c0 = (t - nT) * TL;
+      for (int e = tid; e < TL * NB; e += 256) {
+        const int p = e % NB, c = e / NB;  // St[c][p] = Z[j0 + p][c0 + c]
+        St[c][p] = (p < jb && c0 + c < j0) ? Zn[(j0 + p) + (long long)(c0 + c) * m] : 0.0;
+      }
+    }
+    for (int e = tid; e < NB * NB; e += 256) {
+      const int i = e % NB, k = e / NB;
+      Iv[i][k] = (i < jb && k < jb) ? Zn[(j0 + i) + (long long)(j0 + k) * m] : 0.0;
+    }
+    __syncthreads();
+    if (t < nT) {
+      const int r0 = s0 + t * TL;
       const int r = tid % TL, kg = tid / TL;
 #pragma unroll
       for (int v = 0; v < NB / 4; ++v) {
@@ -267,11 +286,6 @@ __global__ __launch_bounds__(256) void k_rf_rows(const int* __restrict__ lvl_nod
       }
     } else {
       const int c0 = (t - nT) * TL;
-      for (int e = tid; e < TL * NB; e += 256) {
-        const int p = e % NB, c = e / NB;  // St[c][p] = Z[j0 + p][c0 + c]
-        St[c][p] = (p < jb && c0 + c < j0) ? Zn[(j0 + p) + (long long)(c0 + c) * m] : 0.0;
-      }
-      __syncthreads();
       const int c = tid % TL, ig = tid / TL;
 #pragma unroll
       for (int v = 0; v < NB / 4; ++v) {
@@ -350,32 +364,45 @@ __global__ __launch_bounds__(256) void k_rf_update(const int* __restrict__ lvl_n
 #pragma unroll
         for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * b[v];
     }
+    // the tile's 16 entries of this thread are all loaded before any is
+    // stored back (one round trip, not one per entry)
+    double* const dst = ztile ? Zn : F;
+    const int cl = ztile ? s0 : m;  // columns of the destination
+    double cur[4][4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int col = c0 + ty + 16 * v;
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int row = r0 + tx + 16 * u;
-        if (!ztile) {
-          if (row < m && col < m && row >= col) F[row + (long long)col * m] -= acc[u][v];
-        } else if (row < m && col < s0) {
-          Zn[row + (long long)col * m] -= acc[u][v];
-        }
+        const bool in = row < m && col < cl && (ztile || row >= col);
+        cur[u][v] = in ? dst[row + (long long)col * m] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int col = c0 + ty + 16 * v;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int row = r0 + tx + 16 * u;
+        const bool in = row < m && col < cl && (ztile || row >= col);
+        if (in) dst[row + (long long)col * m] = cur[u][v] - acc[u][v];
       }
     }
   }
 }
 
-// Solve blocks, one 64-row x 32-column tile per item. Ordinary supernode:
-// [L11^{-1}; L21 L11^{-1}] = [Z11; -Z21] into both packed copies. Dense top:
+// Solve blocks. Ordinary supernode, one 64-row x 32-column tile per item:
+// [L11^{-1}; L21 L11^{-1}] = [Z11; -Z21] into both packed copies. Dense top,
+// one 64 x 64 tile of the lower block triangle per item:
 // (L11 L11^T)^{-1}[i][j] = sum_k Z[k][i] Z[k][j] into the forward copy's tiles
-// of the lower block triangle (padding stays as the upload wrote it: zero).
+// (padding stays as the upload wrote it: zero).
 __global__ __launch_bounds__(256) void k_rf_out(const RfItem* __restrict__ items,
                                                 const RfNode* __restrict__ node,
                                                 const double* __restrict__ Z,
                                                 double* __restrict__ Bf, double* __restrict__ Bb) {
   __shared__ double Lt[TL][NB + 1];
-  __shared__ double Xb[NB][NB + 1];
+  __shared__ double Xb[NB][TL + 1];
   const RfItem it = items[blockIdx.x];
   const RfNode nd = node[it.node];
   const int nc = nd.ncol, m = nc + nd.nbelow;
@@ -397,35 +424,37 @@ __global__ __launch_bounds__(256) void k_rf_out(const RfItem* __restrict__ items
     }
     return;
   }
-  double acc[8];
+  // the item's tile: rows r0.., columns cB.. (cB <= r0)
+  const int cB = it.b * TL;
+  double acc[16];
 #pragma unroll
-  for (int v = 0; v < 8; ++v) acc[v] = 0.0;
+  for (int v = 0; v < 16; ++v) acc[v] = 0.0;
   // Z11 = L11^{-1} is lower triangular: entries above the diagonal read as zero
-  for (int K = max(r0, cJ) / NB; K * NB < nc; ++K) {
+  for (int K = max(r0, cB) / NB; K * NB < nc; ++K) {
     const int rK = K * NB;
     for (int e = tid; e < TL * NB; e += 256) {
       const int k = e % NB, r = e / NB;  // Z[rK + k][r0 + r], read along k
       Lt[r][k] = (r0 + r < nc && rK + k < nc && rK + k >= r0 + r)
                      ? Zn[(rK + k) + (long long)(r0 + r) * m] : 0.0;
     }
-    for (int e = tid; e < NB * NB; e += 256) {
+    for (int e = tid; e < NB * TL; e += 256) {
       const int i = e % NB, k = e / NB;
-      Xb[i][k] = (rK + i < nc && cJ + k < nc && rK + i >= cJ + k)
-                     ? Zn[(rK + i) + (long long)(cJ + k) * m] : 0.0;
+      Xb[i][k] = (rK + i < nc && cB + k < nc && rK + i >= cB + k)
+                     ? Zn[(rK + i) + (long long)(cB + k) * m] : 0.0;
     }
     __syncthreads();
 #pragma unroll 8
     for (int p = 0; p < NB; ++p) {
       const double l = Lt[tx][p];
 #pragma unroll
-      for (int v = 0; v < 8; ++v) acc[v] += l * Xb[p][ty + 4 * v];
+      for (int v = 0; v < 16; ++v) acc[v] += l * Xb[p][ty + 4 * v];
     }
     __syncthreads();
   }
   const int row = r0 + tx;
 #pragma unroll
-  for (int v = 0; v < 8; ++v) {
-    const int c = cJ + ty + 4 * v;
+  for (int v = 0; v < 16; ++v) {
+    const int c = cB + ty + 4 * v;
     const long long o = top_tile_off(row, c);  // lower block triangle only
     if (c < nc && row < nc && o >= 0) Bf[nd.fw + o] = acc[v];
   }
@@ -645,10 +674,17 @@ int build_plan(const std::vector<const qnsim*>& sims, const DeviceMesh& D, Refac
     std::vector<int>().swap(kc.adiag[sm]);
   }
   P.nnz = (long long)apos.size();
-  // work list of the solve-block kernel: (supernode, 64-row tile, 32-column block)
+  // work list of the solve-block kernel: (supernode, 64-row tile, 32-column
+  // block), or for the dense top (supernode, 64-row tile, 64-column tile) of
+  // its lower block triangle
   std::vector<RfItem> out;
   for (int s = 0; s < ns; ++s) {
     const int nc = F.sn[s].ncol, m = F.sn[s].m();
+    if (s == F.top) {
+      for (int a = 0; a * TL < nc; ++a)
+        for (int b = 0; b <= a; ++b) out.push_back({s, a, b, 0});
+      continue;
+    }
     const int nbk = (nc + NB - 1) / NB;
     for (int a = 0; a * TL < m; ++a)
       for (int J = 0; J < nbk; ++J) out.push_back({s, a, J, 0});
@@ -761,7 +797,8 @@ int dev_refactor_mesh(const std::vector<const qnsim*>& sims, DeviceMesh& D, doub
         upd_t = std::max(upd_t, Tn * (Tn + 1) / 2 + Tn * nZc);
       }
       k_rf_diag<<<act, 64, 0, st>>>(ln, P.node, P.ws, P.Z, j0, P.flag);
-      if (rows_t > 0) k_rf_rows<<<dim3((unsigned)rows_t, gy), 256, 0, st>>>(ln, P.node, act, P.ws, P.Z, j0);
+      if (rows_t > 0)
+        k_rf_rows<<<dim3((unsigned)rows_t, gy), 256, 0, st>>>(ln, P.node, act, P.ws, P.Z, j0);
       if (upd_t > 0) k_rf_update<<<dim3((unsigned)upd_t, gy), 256, 0, st>>>(ln, P.node, act, P.ws, P.Z, j0);
     }
   }
