@@ -46,6 +46,18 @@ __device__ __forceinline__ long long bw_col_off(int c, int m) {
   return (long long)c * m - (long long)c * (c - 1) / 2;
 }
 
+// Masked load for the staging of right-hand sides and update layers: the
+// load is issued from an address the caller keeps in bounds, whatever `ok`,
+// and the value is selected after. Written as `ok ? p[i] : 0` the load can
+// become a branch on the lane mask, and the compiler then waits for each
+// such load before the next, one memory round trip per load instead of one
+// for the batch. (The factor's own loads stay conditional: masked lanes skip
+// them, which measured faster than clamped addresses and selects.)
+__device__ __forceinline__ double ld_or0(const double* p, bool ok) {
+  const double x = *p;
+  return ok ? x : 0.0;
+}
+
 }  // namespace
 
 // Forward sweep, one tree level: one work item per workgroup. A lane group
@@ -85,34 +97,43 @@ __device__ __forceinline__ void fwd_item(const ItemDesc& d, const double* __rest
   {
     const int c1 = min(nc, TCHUNK);
 #pragma unroll
-    for (int k = 0; k < 4; ++k)
+    for (int k = 0; k < 4; ++k) {
+      const int lim = min(cend[k], c1);
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int cc = gl + u * L;
-        b[k][u] = (cc < min(cend[k], c1)) ? rp[k][cc] : 0.0;
+        b[k][u] = cc < lim ? rp[k][cc] : 0.0;
       }
+    }
   }
   // output positions and pass-through sums of the item's rows below the
   // columns, staged in LDS (one row per thread)
   const int nrows = d.end - d.begin;
-  if (tid < nrows) {  // nrows <= kMaxItemRows == TS
-    const int r = d.begin + tid;
-    srel[tid] = r >= nc ? rel[d.rows_off + (r - nc)] : 0;
+  if (d.end > nc) {  // uniform: the item has rows below the columns (so nbelow > 0)
+    // every thread loads (rows past the item's end repeat its last row), so
+    // that no load sits under a lane condition; threads below nrows store
+    const int r = d.begin + min(tid, nrows - 1);  // nrows <= kMaxItemRows == TS
+    const bool below = r >= nc;
+    // (a row above the block reads some valid entry; its slot is never used)
+    const int ri = rel[d.rows_off + min(max(r - nc, 0), d.nbelow - 1)];
     double p0 = 0.0, p1 = 0.0, p2 = 0.0;
-    for (int j0 = 0; r >= nc && j0 < nch; j0 += 2) {
+    for (int j0 = 0; j0 < nch; j0 += 2) {
       double u[2][3];
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
-        const bool ok = j0 + j < nch;
-        const double* up = vin + (ok ? j0 + j : 0) * ss + 3 * (size_t)r;
-        u[j][0] = ok ? up[0] : 0.0;
-        u[j][1] = ok ? up[1] : 0.0;
-        u[j][2] = ok ? up[2] : 0.0;
+        const bool ok = below && j0 + j < nch;
+        const double* up = vin + (size_t)min(j0 + j, nch - 1) * ss + 3 * (size_t)r;
+        u[j][0] = ld_or0(up + 0, ok);
+        u[j][1] = ld_or0(up + 1, ok);
+        u[j][2] = ld_or0(up + 2, ok);
       }
       p0 += u[0][0]; p1 += u[0][1]; p2 += u[0][2];
       p0 += u[1][0]; p1 += u[1][1]; p2 += u[1][2];
     }
-    sp[3 * tid + 0] = p0; sp[3 * tid + 1] = p1; sp[3 * tid + 2] = p2;
+    if (tid < nrows) {
+      srel[tid] = ri;
+      sp[3 * tid + 0] = p0; sp[3 * tid + 1] = p1; sp[3 * tid + 2] = p2;
+    }
   }
   double a[4][3];
 #pragma unroll
@@ -141,10 +162,11 @@ __device__ __forceinline__ void fwd_item(const ItemDesc& d, const double* __rest
 #pragma unroll
           for (int j = 0; j < 2; ++j) {
             const bool ok = (j0 + j < nch) && c < c1;
-            const double* up = vin + (j0 + j) * ss + 3 * (size_t)(ok ? c : 0);
-            u[jj][j][0] = ok ? up[0] : 0.0;
-            u[jj][j][1] = ok ? up[1] : 0.0;
-            u[jj][j][2] = ok ? up[2] : 0.0;
+            const double* up =
+                vin + (size_t)min(j0 + j, nch - 1) * ss + 3 * (size_t)(c < c1 ? c : c0);
+            u[jj][j][0] = ld_or0(up + 0, ok);
+            u[jj][j][1] = ld_or0(up + 1, ok);
+            u[jj][j][2] = ld_or0(up + 2, ok);
           }
         }
 #pragma unroll
@@ -170,6 +192,9 @@ __device__ __forceinline__ void fwd_item(const ItemDesc& d, const double* __rest
     // the group's (up to) 4 rows advance together: 4 rows x 4 unrolled
     // columns = 16 independent loads in flight per lane
     const int cm = min(cmax, c1);
+    int lim[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) lim[k] = min(cend[k], c1);
     for (int c = c0 + gl; c < cm; c += 4 * L) {
       if (c0 > 0 || c != gl) {
 #pragma unroll
@@ -177,7 +202,7 @@ __device__ __forceinline__ void fwd_item(const ItemDesc& d, const double* __rest
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
             const int cc = c + u * L;
-            b[k][u] = (cc < min(cend[k], c1)) ? rp[k][cc] : 0.0;
+            b[k][u] = cc < lim[k] ? rp[k][cc] : 0.0;
           }
       }
 #pragma unroll
@@ -280,24 +305,32 @@ __device__ __forceinline__ void bwd_item(const ItemDesc& d, const double* __rest
   for (int i0 = d.begin; i0 < m; i0 += TCHUNK) {  // rows above the item's columns never contribute
     const int i1 = min(m, i0 + TCHUNK);
     if (i0 > d.begin) __syncthreads();
+    // all index loads, then all value loads, then the LDS writes (an index
+    // for a row that is not below the columns, or past the chunk, is some
+    // valid row of the supernode: its value is never used)
     int g[TCHUNK / TS];
 #pragma unroll
-    for (int j = 0; j < TCHUNK / TS; ++j) {
-      const int i = i0 + tid + j * TS;
-      g[j] = (i < i1 && i >= nc) ? rw[i - nc] : -1;
+    for (int j = 0; j < TCHUNK / TS; ++j) g[j] = 0;
+    if (d.nbelow > 0) {  // uniform
+#pragma unroll
+      for (int j = 0; j < TCHUNK / TS; ++j)
+        g[j] = rw[min(max(i0 + tid + j * TS - nc, 0), d.nbelow - 1)];
     }
+    double v[TCHUNK / TS][3];
 #pragma unroll
     for (int j = 0; j < TCHUNK / TS; ++j) {
       const int i = i0 + tid + j * TS;
-      if (i < i1) {
-        if (i < nc) {
-          const double* p = z + 3 * (size_t)(first + i);
-          s0[i - i0] = p[0]; s1[i - i0] = p[1]; s2[i - i0] = p[2];
-        } else {
-          const double* p = w + 3 * (size_t)g[j];
-          s0[i - i0] = -p[0]; s1[i - i0] = -p[1]; s2[i - i0] = -p[2];
-        }
-      }
+      const double* p = i < nc ? z + 3 * (size_t)(first + i) : w + 3 * (size_t)g[j];
+      v[j][0] = p[0]; v[j][1] = p[1]; v[j][2] = p[2];
+    }
+    // stored for every i < i0 + TCHUNK (entries past i1 are never read): a
+    // store under `i < i1` would let the compiler sink the loads into that
+    // branch, one round trip each
+#pragma unroll
+    for (int j = 0; j < TCHUNK / TS; ++j) {
+      const int i = i0 + tid + j * TS;
+      const double sg = i < nc ? 1.0 : -1.0;
+      s0[i - i0] = sg * v[j][0]; s1[i - i0] = sg * v[j][1]; s2[i - i0] = sg * v[j][2];
     }
     __syncthreads();
     // the group's (up to) 4 columns advance together: 16 loads in flight per lane
@@ -403,11 +436,15 @@ __device__ __forceinline__ void fwd_wave_item(const ItemDesc& d, const double* _
       const int cc = gl + uu * L;
       b[k][uu] = (cc < cend[k]) ? rp[k][cc] : 0.0;
     }
-  int relr[4];
+  // output positions of the rows below the columns, loaded together (rows
+  // that are not below read some valid entry, never used)
+  int relr[4] = {0, 0, 0, 0};
+  if (d.end > nc) {  // uniform: rows below exist, so nbelow > 0
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const int r = d.begin + grp + k * G;
-    relr[k] = (gl == 0 && r < d.end && r >= nc) ? rel[d.rows_off + (r - nc)] : 0;
+    for (int k = 0; k < 4; ++k) {
+      const int r = d.begin + grp + k * G;
+      relr[k] = rel[d.rows_off + min(max(r - nc, 0), d.nbelow - 1)];
+    }
   }
   for (int i0 = 0; i0 < m; i0 += 128) {
     double v[2][3];
@@ -534,31 +571,32 @@ __device__ __forceinline__ void bwd_wave_item(const ItemDesc& d, const double* _
       const int ii = istart + uu * L;
       b[k][uu] = (ii >= cst[k] && ii < m) ? cp[k][ii] : 0.0;
     }
+  // all index loads, then all value loads, then the LDS writes, each for
+  // every i < begin + kSubCap (an index for a row that is not below the
+  // columns, or past m, is some valid row of the supernode, and the staged
+  // entries past m are never read)
   int g[KC];
 #pragma unroll
-  for (int k = 0; k < KC; ++k) {
-    const int i = d.begin + lane + 64 * k;
-    g[k] = (i < m && i >= nc) ? rw[i - nc] : -1;
+  for (int k = 0; k < KC; ++k) g[k] = 0;
+  if (d.nbelow > 0) {  // uniform
+#pragma unroll
+    for (int k = 0; k < KC; ++k)
+      g[k] = rw[min(max(d.begin + lane + 64 * k - nc, 0), d.nbelow - 1)];
   }
   double v[KC][3];
 #pragma unroll
   for (int k = 0; k < KC; ++k) {
     const int i = d.begin + lane + 64 * k;
-    const double* p = (i < nc) ? z + 3 * (size_t)(first + i) : w + 3 * (size_t)(g[k] >= 0 ? g[k] : 0);
-    const bool ok = i < m;
-    const double sg = (i < nc) ? 1.0 : -1.0;
-    v[k][0] = ok ? sg * p[0] : 0.0;
-    v[k][1] = ok ? sg * p[1] : 0.0;
-    v[k][2] = ok ? sg * p[2] : 0.0;
+    const double* p = (i < nc) ? z + 3 * (size_t)(first + i) : w + 3 * (size_t)g[k];
+    v[k][0] = p[0]; v[k][1] = p[1]; v[k][2] = p[2];
   }
 #pragma unroll
   for (int k = 0; k < KC; ++k) {
     const int i = d.begin + lane + 64 * k;
-    if (i < m) {
-      us[i - d.begin] = v[k][0];
-      us[kSubCap + i - d.begin] = v[k][1];
-      us[2 * kSubCap + i - d.begin] = v[k][2];
-    }
+    const double sg = (i < nc) ? 1.0 : -1.0;
+    us[i - d.begin] = sg * v[k][0];
+    us[kSubCap + i - d.begin] = sg * v[k][1];
+    us[2 * kSubCap + i - d.begin] = sg * v[k][2];
   }
   wave_sync_lds();
   double a[4][3];
