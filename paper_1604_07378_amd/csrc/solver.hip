@@ -154,8 +154,11 @@ __device__ __forceinline__ int xcd_block() {
   return x * q + min(x, r) + b / 8;
 }
 
-__device__ __forceinline__ int pair_slot(const Ctl* c, int a, int slots) {
-  return (c->newest - a + slots) % slots;
+// Ring slot a places before `newest` (any integer a: for a >= slots, or
+// a < 0, it wraps), so that it can be formed for every a of an unrolled loop.
+__device__ __forceinline__ int ring_slot(int newest, int a, int slots) {
+  const int j = (newest - a) % slots;
+  return j < 0 ? j + slots : j;
 }
 
 // ---------------------------------------------------------------------------
@@ -230,7 +233,7 @@ k_copy_retry(int nf, const int* __restrict__ vsim, const Ctl* __restrict__ ctl,
 // probes).
 // ---------------------------------------------------------------------------
 template <int TYPE, typename R, int NT>
-__global__ void __launch_bounds__(NT)
+__global__ void __launch_bounds__(NT, TYPE == 2 ? 4 : (TYPE == 0 || TYPE == 1 ? 6 : 1))
 k_elem(int want, int trial, const BlockSeg* __restrict__ blk, int T, int nf,
        const int* __restrict__ tv, const double* __restrict__ Bm,
        const double* __restrict__ vol, const int* __restrict__ tmat,
@@ -255,22 +258,45 @@ k_elem(int want, int trial, const BlockSeg* __restrict__ blk, int T, int nf,
   if (t < sg.a1) {
     const int4 iv = reinterpret_cast<const int4*>(tv)[t];
     const int vid[4] = {iv.x, iv.y, iv.z, iv.w};
+    // the tet's own data (Dm^{-1}, volume, material): loaded together with
+    // its vertex ids where registers allow (Neo-Hookean, StVK; the SVD
+    // materials would lose a wave per SIMD), else after the positions
+    constexpr bool kEarly = TYPE == 0 || TYPE == 1;
+    double B[3][3], V;
+    int mi;
+    auto load_tet = [&] {
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) B[r][c] = Bm[(size_t)(3 * r + c) * T + t];
+      V = vol[t];
+      mi = tmat ? tmat[t] : 0;
+    };
+    if constexpr (kEarly) load_tet();
+    // every position load, and in a trial every direction load (from vertex 0
+    // for a pinned vertex, whose value is not used), is issued before any is
+    // used: a load under a lane condition compiles to a branch that waits for
+    // it, one memory round trip per vertex component
     double p[4][3];
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      const int v = vid[a];
+    for (int a = 0; a < 4; ++a)
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        double xv = X[3 * (size_t)v + c];
-        if (trial && v < nf) xv = __fma_rn(alpha, d[3 * (size_t)v + c], xv);
-        p[a][c] = xv;
-      }
+      for (int c = 0; c < 3; ++c) p[a][c] = X[3 * (size_t)vid[a] + c];
+    if (trial) {  // uniform; a trial has free vertices (nf > 0)
+      double dv[4][3];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) dv[a][c] = d[3 * (size_t)(vid[a] < nf ? vid[a] : 0) + c];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const double xt = __fma_rn(alpha, dv[a][c], p[a][c]);
+          p[a][c] = vid[a] < nf ? xt : p[a][c];
+        }
     }
-    double B[3][3];
-#pragma unroll
-    for (int r = 0; r < 3; ++r)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) B[r][c] = Bm[(size_t)(3 * r + c) * T + t];
+    if constexpr (!kEarly) load_tet();
     M3<double> F;
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
@@ -278,7 +304,7 @@ k_elem(int want, int trial, const BlockSeg* __restrict__ blk, int T, int nf,
 #pragma unroll
       for (int k = 0; k < 3; ++k) F.a[i][k] = ds0 * B[0][k] + ds1 * B[1][k] + ds2 * B[2][k];
     }
-    const DevMat& mt = mats[tmat ? tmat[t] : 0];
+    const DevMat& mt = mats[mi];
     double psi;
     M3<R> P;
     if constexpr (sizeof(R) == 8) {
@@ -290,7 +316,6 @@ k_elem(int want, int trial, const BlockSeg* __restrict__ blk, int T, int nf,
       material_eval_mixed<TYPE>(mt, F, psi, P);  // FP32 stress
     }
     add_fiber(mt, F, psi, P);
-    const double V = vol[t];
     e = V * psi;  // energies and their sum are FP64 in every mode
     if (psi_out) psi_out[t] = psi;
     const R VR = (R)V;
@@ -605,14 +630,17 @@ k_qform(const BlockSeg* __restrict__ blk, size_t n3, int slots, const double* __
         const double* __restrict__ Tall, double* __restrict__ q, const Ctl* __restrict__ ctl) {
   const BlockSeg sg = blk[blockIdx.x];
   const Ctl* c = ctl + sg.sim;
-  if (c->phase != PH_DIR) return;
-  const int np = c->npairs;
+  // control fields read together, then every pair's coefficient together
+  // (read behind `a < np` each would cost a round trip)
+  const int phase = c->phase, np = c->npairs, newest = c->newest;
+  if (phase != PH_DIR) return;
   int sl[SL];
   double ze[SL];
 #pragma unroll
   for (int a = 0; a < SL; ++a) {
-    sl[a] = a < np ? pair_slot(c, a, slots) : 0;
-    ze[a] = a < np ? c->zeta[sl[a]] : 0.0;
+    sl[a] = ring_slot(newest, a, slots);
+    const double z = c->zeta[sl[a]];
+    ze[a] = a < np ? z : 0.0;
   }
   const size_t i = (size_t)sg.a0 + threadIdx.x;  // one entry per thread
   if (i >= (size_t)sg.a1) return;
@@ -638,27 +666,27 @@ k_rdots(const BlockSeg* __restrict__ blk, int nb, size_t n3, int slots,
   __shared__ double sh[(kWideBS / 64) * ND];
   const BlockSeg sg = blk[blockIdx.x];
   const Ctl* c = ctl + sg.sim;
-  if (c->phase != PH_DIR) return;
-  const int np = c->npairs;
+  const int phase = c->phase, np = c->npairs, newest = c->newest;
+  if (phase != PH_DIR) return;
+  // slot j holds one of the np newest pairs when its age (newest - j mod
+  // slots) is below np
   bool use[SL];
 #pragma unroll
-  for (int j = 0; j < SL; ++j) use[j] = false;
-  for (int a = 0; a < np; ++a) {
-    const int j = pair_slot(c, a, slots);
-#pragma unroll
-    for (int jj = 0; jj < SL; ++jj)
-      if (jj == j) use[jj] = true;
-  }
+  for (int j = 0; j < SL; ++j) use[j] = j < slots && ring_slot(newest, j, slots) < np;
   double acc[ND];
 #pragma unroll
   for (int j = 0; j < ND; ++j) acc[j] = 0.0;
   const size_t i = (size_t)sg.a0 + threadIdx.x;  // one entry per thread
   if (i < (size_t)sg.a1) {
+    // every stored t_j is loaded before any is used (each load behind its
+    // own test and product would cost a round trip)
+    double tj[SL];
+#pragma unroll
+    for (int j = 0; j < SL; ++j) tj[j] = use[j] ? Tall[(size_t)j * n3 + i] : 0.0;
     const double r = r0[i];
     acc[SL] = grad[i] * r;
 #pragma unroll
-    for (int j = 0; j < SL; ++j)
-      if (use[j]) acc[j] = Tall[(size_t)j * n3 + i] * r;
+    for (int j = 0; j < SL; ++j) acc[j] = use[j] ? tj[j] * r : 0.0;
   }
   block_sums_to<ND, kWideBS / 64>(acc, sh, part, nb, sg.slot);
 }
@@ -757,15 +785,18 @@ k_dform(const BlockSeg* __restrict__ blk, size_t n3, int slots, int cyc, int che
         const Ctl* __restrict__ ctl) {
   const BlockSeg sg = blk[blockIdx.x];
   const Ctl* c = ctl + sg.sim;
-  if (c->phase != PH_LS || c->dir_cycle != cyc) return;
-  const int np = c->npairs;
+  // control fields read together, then every pair's coefficient together
+  const int phase = c->phase, dcyc = c->dir_cycle, np = c->npairs, newest = c->newest;
+  const double om = c->omega_used;
+  if (phase != PH_LS || dcyc != cyc) return;
   int sl[SL];
   double cf[SL];
 #pragma unroll
   for (int a = 0; a < SL; ++a) {
     const int b = np - 1 - a;  // oldest first
-    sl[a] = b >= 0 ? pair_slot(c, b, slots) : 0;
-    cf[a] = b >= 0 ? c->coef[sl[a]] : 0.0;
+    sl[a] = ring_slot(newest, b, slots);
+    const double cv = c->coef[sl[a]];
+    cf[a] = b >= 0 ? cv : 0.0;
   }
   const size_t i = (size_t)sg.a0 + threadIdx.x;  // one entry per thread
   if (i >= (size_t)sg.a1) return;
@@ -776,10 +807,7 @@ k_dform(const BlockSeg* __restrict__ blk, size_t n3, int slots, int cyc, int che
 #pragma unroll
   for (int a = 0; a < SL; ++a)
     if (a < np) v += sv[a] * cf[a];
-  if (cheb) {
-    const double om = c->omega_used;
-    if (om != 1.0) v = om * v + (om - 1.0) * Sall[i];
-  }
+  if (cheb && om != 1.0) v = om * v + (om - 1.0) * Sall[i];
   d[i] = v;
 }
 
