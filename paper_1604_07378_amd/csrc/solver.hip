@@ -85,9 +85,27 @@ __device__ __forceinline__ double block_sum_t(double v, double* sh) {
 }
 
 // Sum of n partials in a fixed order; result valid in every thread.
+// Masked load: issued from an address the caller keeps in bounds whatever
+// `ok`, value selected after (written as `ok ? p[i] : 0` the load can become
+// a branch at which the compiler waits for it alone).
+__device__ __forceinline__ double ld_or0(const double* p, bool ok) {
+  const double x = *p;
+  return ok ? x : 0.0;
+}
+
 __device__ __forceinline__ double sum_partials(const double* p, int n, double* sh) {
   double v = 0.0;
-  for (int i = threadIdx.x; i < n; i += BS) v += p[i];
+  // eight rounds in flight at once, then added in the same order as one at a
+  // time (a round past n reloads this thread's first entry and is skipped)
+  constexpr int R = 8;
+  for (int i0 = threadIdx.x; i0 < n; i0 += R * BS) {
+    double x[R];
+#pragma unroll
+    for (int u = 0; u < R; ++u) x[u] = p[i0 + u * BS < n ? i0 + u * BS : i0];
+#pragma unroll
+    for (int u = 0; u < R; ++u)
+      if (i0 + u * BS < n) v += x[u];
+  }
   v = block_sum(v, sh);
   __syncthreads();
   if (threadIdx.x == 0) sh[8] = v;
@@ -127,9 +145,23 @@ __device__ __forceinline__ void totals_of(const double* __restrict__ part, int s
   double v[N];
 #pragma unroll
   for (int d = 0; d < N; ++d) v[d] = 0.0;
-  for (int b = threadIdx.x; b < nb; b += BS) {
+  // two rounds of the N partial arrays in flight at once, then the sums (in
+  // the same order as one round at a time)
+  for (int b = threadIdx.x; b < nb; b += 2 * BS) {
+    const bool two = b + BS < nb;
+    double x[2][N];
 #pragma unroll
-    for (int d = 0; d < N; ++d) v[d] += part[(size_t)d * stride + b];
+    for (int d = 0; d < N; ++d) {
+      x[0][d] = part[(size_t)d * stride + b];
+      const double y = part[(size_t)d * stride + (two ? b + BS : b)];
+      x[1][d] = two ? y : 0.0;
+    }
+#pragma unroll
+    for (int d = 0; d < N; ++d) v[d] += x[0][d];
+    if (two) {
+#pragma unroll
+      for (int d = 0; d < N; ++d) v[d] += x[1][d];
+    }
   }
 #pragma unroll
   for (int d = 0; d < N; ++d) v[d] = wave_sum(v[d]);
@@ -382,7 +414,7 @@ k_elem(int want, int trial, const BlockSeg* __restrict__ blk, int T, int nf,
 
 // g(x_1) of each simulation in phase `want` (PH_INIT, or PH_RETRY after
 // x_1 := x): one block per simulation.
-__global__ void __launch_bounds__(BS)
+__global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(1, 1)))
 k_init_decide(int want, const SimSeg* __restrict__ seg, const double* __restrict__ part,
               Ctl* __restrict__ ctl, SimStat* __restrict__ stat) {
   __shared__ double sh[16];
@@ -448,31 +480,48 @@ k_gather(int probe, const BlockSeg* __restrict__ blk, int nb, size_t n3, int slo
   // handles component gl
   const int i = sg.a0 + (threadIdx.x >> 2), gl = threadIdx.x & 3;
   const bool live = i < sg.a1, own = live && gl < 3;
-  const size_t ic = 3 * (size_t)(live ? i : sg.a0) + (gl < 3 ? gl : 0);
-  // loads that do not depend on the partial sums go first
-  double mi = 0.0, yy = 0.0, xp = 0.0, dd = 0.0, gp = 0.0;
+  const int iv = live ? i : sg.a0;  // a dead lane reads its block's first vertex
+  const size_t ic = 3 * (size_t)iv + (gl < 3 ? gl : 0);
+  // Load order: the first round of the vertex's partial indices, the loads
+  // that do not depend on the partials, then the first round of partials and
+  // the stored pairs. Every load is unconditional per lane (values of lanes
+  // that do not own a component are unused): a load under a lane condition
+  // compiles to a branch at which the compiler waits for it alone.
+  const int* __restrict__ row = bp_tab + (size_t)iv * bp_w;
+  int ix[2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {  // bp_w >= 4, so gl < bp_w
+    const int x = row[gl + 4 * u < bp_w ? gl + 4 * u : gl];
+    ix[u] = (live & (gl + 4 * u < bp_w)) ? x : -1;  // `&`: no short-circuit branch
+  }
+  const double mi = mass[iv] * inv_h2, yy = y[ic], xp = X[ic];
+  const double dd = d[ic], gp = Gr[ic];  // used only when k > 0
+  double f[3] = {0.0, 0.0, 0.0};
+  {
+    double fv[2][3];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const double* fp = bpart + 3 * (size_t)(ix[u] >= 0 ? ix[u] : 0);
+      fv[u][0] = ld_or0(fp + 0, ix[u] >= 0);
+      fv[u][1] = ld_or0(fp + 1, ix[u] >= 0);
+      fv[u][2] = ld_or0(fp + 2, ix[u] >= 0);
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) { f[0] += fv[u][0]; f[1] += fv[u][1]; f[2] += fv[u][2]; }
+  }
   double sj[SL], tj[SL];
 #pragma unroll
   for (int j = 0; j < SL; ++j) sj[j] = tj[j] = 0.0;
-  if (own) {
-    mi = mass[i] * inv_h2;
-    yy = y[ic];
-    xp = X[ic];
-    if (k > 0) {
-      dd = d[ic];
-      gp = Gr[ic];
+  if (k > 0) {
 #pragma unroll
-      for (int j = 0; j < SL; ++j)
-        if (j < slots && j != cand) {  // ring slots beyond m + 1 are not allocated
-          sj[j] = Sall[(size_t)j * n3 + ic];
-          tj[j] = Tall[(size_t)j * n3 + ic];
-        }
-    }
+    for (int j = 0; j < SL; ++j)
+      if (j < slots && j != cand) {  // ring slots beyond m + 1 are not allocated
+        sj[j] = Sall[(size_t)j * n3 + ic];
+        tj[j] = Tall[(size_t)j * n3 + ic];
+      }
   }
-  double f[3] = {0.0, 0.0, 0.0};
-  if (live) {
-    const int* __restrict__ row = bp_tab + (size_t)i * bp_w;
-    for (int u0 = gl; u0 < bp_w; u0 += 8) {
+  if (live) {  // further rounds of partials (vertices in more than 8 element blocks)
+    for (int u0 = gl + 8; u0 < bp_w; u0 += 8) {
       int ix[2];
 #pragma unroll
       for (int u = 0; u < 2; ++u) ix[u] = u0 + 4 * u < bp_w ? row[u0 + 4 * u] : -1;
@@ -554,7 +603,7 @@ k_gather(int probe, const BlockSeg* __restrict__ blk, int nb, size_t n3, int slo
 //   s_i . q_i = -s_i . grad - sum_{j newer} zeta_j G[i][j].
 // One block per simulation.
 template <int SL>
-__global__ void __launch_bounds__(BS)
+__global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(1, 1)))
 k_pair_decide(int m, const SimSeg* __restrict__ seg, const double* __restrict__ part, int nb,
               Ctl* __restrict__ ctl, SimStat* __restrict__ stat, int* __restrict__ dir_count) {
   constexpr int ND = 4 + 3 * SL + 1;
@@ -704,7 +753,7 @@ k_rdots(const BlockSeg* __restrict__ blk, int nb, size_t n3, int slots,
 // grad . d = omega grad . r0 + (omega - 1) s . grad; an ascent direction uses
 // d = r0 for this iteration.
 template <int SL>
-__global__ void __launch_bounds__(BS)
+__global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(1, 1)))
 k_coef_decide(int m, int cyc, int cheb, int cheb_delay, double rho2,
               const SimSeg* __restrict__ seg, const double* __restrict__ part,
               int nb, Ctl* __restrict__ ctl, SimStat* __restrict__ stat,
@@ -814,7 +863,7 @@ k_dform(const BlockSeg* __restrict__ blk, size_t n3, int slots, int cyc, int che
 // Armijo test of one line-search trial (section 4.1, Algorithm 1), one block
 // per simulation. Accepting the trial of the last iteration ends the step
 // (x' = x_k + alpha d); otherwise the next iteration's gather forms x_{k+1}.
-__global__ void __launch_bounds__(BS)
+__global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(1, 1)))
 k_ls_decide(int K, int max_halvings, double gamma, double backtrack,
             const SimSeg* __restrict__ seg, const double* __restrict__ part,
             Ctl* __restrict__ ctl, SimStat* __restrict__ stat) {
