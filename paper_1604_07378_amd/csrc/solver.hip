@@ -265,7 +265,7 @@ k_copy_retry(int nf, const int* __restrict__ vsim, const Ctl* __restrict__ ctl,
 // probes).
 // ---------------------------------------------------------------------------
 template <int TYPE, typename R, int NT>
-__global__ void __launch_bounds__(NT, TYPE == 2 ? 4 : (TYPE == 0 || TYPE == 1 ? 6 : 1))
+__global__ void __launch_bounds__(NT, TYPE == 2 ? 4 : 1)
 k_elem(int want, int trial, const BlockSeg* __restrict__ blk, int T, int nf,
        const int* __restrict__ tv, const double* __restrict__ Bm,
        const double* __restrict__ vol, const int* __restrict__ tmat,
@@ -291,20 +291,20 @@ k_elem(int want, int trial, const BlockSeg* __restrict__ blk, int T, int nf,
     const int4 iv = reinterpret_cast<const int4*>(tv)[t];
     const int vid[4] = {iv.x, iv.y, iv.z, iv.w};
     // the tet's own data (Dm^{-1}, volume, material): loaded together with
-    // its vertex ids where registers allow (Neo-Hookean, StVK; the SVD
-    // materials would lose a wave per SIMD), else after the positions
-    constexpr bool kEarly = TYPE == 0 || TYPE == 1;
-    double B[3][3], V;
-    int mi;
-    auto load_tet = [&] {
+    // its vertex ids where registers allow (StVK; Neo-Hookean would spill at
+    // six waves per SIMD and the SVD materials lose a wave), else after the
+    // positions
+    constexpr bool kEarly = TYPE == 1;
+    double B[3][3], V = 0.0;
+    int mi = 0;
+    if constexpr (kEarly) {
 #pragma unroll
       for (int r = 0; r < 3; ++r)
 #pragma unroll
         for (int c = 0; c < 3; ++c) B[r][c] = Bm[(size_t)(3 * r + c) * T + t];
       V = vol[t];
       mi = tmat ? tmat[t] : 0;
-    };
-    if constexpr (kEarly) load_tet();
+    }
     // every position load, and in a trial every direction load (from vertex 0
     // for a pinned vertex, whose value is not used), is issued before any is
     // used: a load under a lane condition compiles to a branch that waits for
@@ -328,7 +328,13 @@ k_elem(int want, int trial, const BlockSeg* __restrict__ blk, int T, int nf,
           p[a][c] = vid[a] < nf ? xt : p[a][c];
         }
     }
-    if constexpr (!kEarly) load_tet();
+    if constexpr (!kEarly) {
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) B[r][c] = Bm[(size_t)(3 * r + c) * T + t];
+      mi = tmat ? tmat[t] : 0;
+    }
     M3<double> F;
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
@@ -348,6 +354,7 @@ k_elem(int want, int trial, const BlockSeg* __restrict__ blk, int T, int nf,
       material_eval_mixed<TYPE>(mt, F, psi, P);  // FP32 stress
     }
     add_fiber(mt, F, psi, P);
+    if constexpr (!kEarly) V = vol[t];
     e = V * psi;  // energies and their sum are FP64 in every mode
     if (psi_out) psi_out[t] = psi;
     const R VR = (R)V;
