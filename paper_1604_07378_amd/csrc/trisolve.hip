@@ -178,14 +178,16 @@ __device__ __forceinline__ void fwd_item(const ItemDesc& d, const double* __rest
             v[jj][2] -= u[jj][j][2];
           }
       }
+      // stored for every c < c0 + TCHUNK (entries past c1 are never read),
+      // so that every loaded value is used: a load whose value is dropped on
+      // some lanes stays outstanding, and the compiler then waits for it
+      // when its register is next written (inside the block loop below)
 #pragma unroll
       for (int jj = 0; jj < 2; ++jj) {
         const int c = c0 + tid + (jh + jj) * TS;
-        if (c < c1) {
-          s0[c - c0] = v[jj][0];
-          s1[c - c0] = v[jj][1];
-          s2[c - c0] = v[jj][2];
-        }
+        s0[c - c0] = v[jj][0];
+        s1[c - c0] = v[jj][1];
+        s2[c - c0] = v[jj][2];
       }
     }
     __syncthreads();
