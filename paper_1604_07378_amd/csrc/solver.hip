@@ -383,11 +383,23 @@ k_elem(int want, int trial, const BlockSeg* __restrict__ blk, int T, int nf,
     const int g = sg.p0 + j;
     const int k0 = lc_ptr[g], k1 = lc_ptr[g + 1];
     double f0 = 0.0, f1 = 0.0, f2 = 0.0;
-    for (int k = k0; k < k1; ++k) {
-      const R* src = sfel + 3 * (int)lc_idx[k];
-      f0 += (double)src[0];
-      f1 += (double)src[1];
-      f2 += (double)src[2];
+    // the vertex's entries in rounds of eight, each round's indices loaded
+    // together (one index load per entry, each waited for before its LDS
+    // read, made this loop a chain of up to 24 round trips)
+    constexpr int KR = 8;
+    for (int kk = k0; kk < k1; kk += KR) {
+      int ix[KR];
+#pragma unroll
+      for (int u = 0; u < KR; ++u) ix[u] = lc_idx[kk + u < k1 ? kk + u : k1 - 1];
+#pragma unroll
+      for (int u = 0; u < KR; ++u) {
+        if (kk + u < k1) {
+          const R* src = sfel + 3 * ix[u];
+          f0 += (double)src[0];
+          f1 += (double)src[1];
+          f2 += (double)src[2];
+        }
+      }
     }
     bpart[3 * (size_t)g] = f0;
     bpart[3 * (size_t)g + 1] = f1;
@@ -395,16 +407,26 @@ k_elem(int want, int trial, const BlockSeg* __restrict__ blk, int T, int nf,
   }
   const int vi = sg.b0 + threadIdx.x;
   if (vi < sg.b1) {
-    double s = 0.0, xv3[3];
+    // all of the vertex's loads first (in a trial each direction component
+    // loaded and used in turn cost a round trip apiece)
+    double s = 0.0, xv3[3], yv[3], dv[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      double xv = X[3 * (size_t)vi + c];
-      if (trial) xv = __fma_rn(alpha, d[3 * (size_t)vi + c], xv);
-      xv3[c] = xv;
-      double dx = xv - y[3 * (size_t)vi + c];
+      xv3[c] = X[3 * (size_t)vi + c];
+      yv[c] = y[3 * (size_t)vi + c];
+    }
+    if (trial) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) dv[c] = d[3 * (size_t)vi + c];
+    }
+    const double mv = mass[vi];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      if (trial) xv3[c] = __fma_rn(alpha, dv[c], xv3[c]);
+      const double dx = xv3[c] - yv[c];
       s += dx * dx;
     }
-    e += mass[vi] * s * inv2h2;
+    e += mv * s * inv2h2;
     if (cset) {  // collision term (section 4.3): coll_k (n . x - c)^2
       const int p = cset[vi];
       if (p >= 0) {
