@@ -715,17 +715,46 @@ k_top_sym(const double* __restrict__ tiles, const double* __restrict__ q,
 #pragma unroll
   for (int i = 0; i < 8; ++i)
     e[i] = *reinterpret_cast<const double2*>(T + (rg * 8 + i) * TT + 2 * cp);
+  // the right-hand side of block rows I and J (t = q minus the update
+  // layers, layers in order): a thread's two entries and four layers at a
+  // time are loaded together, from clamped rows (a row past n is zero);
+  // loaded under `row < n` and used at once, each load was waited for alone
+  static_assert(2 * TT * 3 <= 2 * 256, "two entries per thread");
+  constexpr int KL = 4;
   const size_t n3 = 3 * (size_t)n;
-  for (int k = tid; k < 2 * TT * 3; k += 256) {
+  size_t ix[2];
+  bool ok[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int k = min(tid + 256 * h, 2 * TT * 3 - 1);
     const int which = k / (TT * 3), rem = k % (TT * 3), r = rem / 3, comp = rem % 3;
     const int row = (which ? J : I) * TT + r;
-    double v = 0.0;
-    if (row < n) {
-      v = q[3 * (size_t)row + comp];
-      for (int j = 0; j < nch; ++j) v -= slots[(size_t)j * n3 + 3 * (size_t)row + comp];
+    ok[h] = row < n;
+    ix[h] = 3 * (size_t)(row < n ? row : n - 1) + comp;
+  }
+  double v[2] = {q[ix[0]], q[ix[1]]};
+  for (int j0 = 0; j0 < nch; j0 += KL) {
+    double u[2][KL];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int uu = 0; uu < KL; ++uu)
+        u[h][uu] = slots[(size_t)min(j0 + uu, nch - 1) * n3 + ix[h]];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int uu = 0; uu < KL; ++uu)
+        if (j0 + uu < nch) v[h] -= u[h][uu];
+  }
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int k = tid + 256 * h;
+    if (k < 2 * TT * 3) {
+      const int which = k / (TT * 3), rem = k % (TT * 3), r = rem / 3, comp = rem % 3;
+      const double t = ok[h] ? v[h] : 0.0;
+      if (which) tJ[r][comp] = t;
+      else tI[r][comp] = t;
     }
-    if (which) tJ[r][comp] = v;
-    else tI[r][comp] = v;
   }
   __syncthreads();
   const int c0 = 2 * cp;
