@@ -135,14 +135,14 @@ __device__ __forceinline__ void block_sums_to(double (&v)[N], double* sh, double
   }
 }
 
-// Totals of N partial arrays (part[d * stride + b], b in [0, nb)) into
-// tot[0..N), valid in every thread: thread t takes entries t, t + 256, ... of
-// every array (all loads independent), then the block tree of block_sums_to.
+// Totals of N partial arrays (part[d * stride + b], b in [0, nb)): thread t
+// sums entries t, t + 256, ... of every array into v (all loads independent);
+// partials_total then gives tot[0..N), valid in every thread, by the block
+// tree of block_sums_to. Split so that a kernel can issue its other loads
+// between the two.
 template <int N>
-__device__ __forceinline__ void totals_of(const double* __restrict__ part, int stride, int nb,
-                                          double* sh, double* tot) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  double v[N];
+__device__ __forceinline__ void partials_load(const double* __restrict__ part, int stride, int nb,
+                                              double (&v)[N]) {
 #pragma unroll
   for (int d = 0; d < N; ++d) v[d] = 0.0;
   // two rounds of the N partial arrays in flight at once, then the sums (in
@@ -163,6 +163,13 @@ __device__ __forceinline__ void totals_of(const double* __restrict__ part, int s
       for (int d = 0; d < N; ++d) v[d] += x[1][d];
     }
   }
+}
+
+// Block totals of N per-thread sums (wave sums, then the four wave results in
+// wave order): tot[d] for every thread after the second barrier.
+template <int N>
+__device__ __forceinline__ void partials_total(double (&v)[N], double* sh, double* tot) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
   for (int d = 0; d < N; ++d) v[d] = wave_sum(v[d]);
   if (lane == 0) {
@@ -184,6 +191,20 @@ __device__ __forceinline__ int xcd_block() {
   const int N = gridDim.x, b = blockIdx.x;
   const int q = N / 8, r = N % 8, x = b % 8;
   return x * q + min(x, r) + b / 8;
+}
+
+// The control block's eight int fields (phase .. trials_iter), read in one
+// load: read field by field, the compiler issues some of them only after the
+// phase test, one more scalar round trip each time.
+struct CtlInts {
+  int phase, k, dir_cycle, final_add, npairs, newest, cand, trials_iter;
+};
+static_assert(offsetof(Ctl, trials_iter) - offsetof(Ctl, phase) == 7 * sizeof(int),
+              "the control block's int fields are contiguous");
+__device__ __forceinline__ CtlInts ctl_ints(const Ctl* c) {
+  CtlInts r;
+  __builtin_memcpy(&r, &c->phase, sizeof r);
+  return r;
 }
 
 // Ring slot a places before `newest` (any integer a: for a >= slots, or
@@ -640,15 +661,23 @@ k_pair_decide(int m, const SimSeg* __restrict__ seg, const double* __restrict__ 
   __shared__ double sG[SL][SL], srho[SL], szeta[SL];
   const int sim = blockIdx.x;
   Ctl* ctl_s = ctl + sim;
-  if (ctl_s->phase != PH_GATHER) return;
-  const int slots = m + 1;  // <= SL
-  // the control state the recursion reads, staged in LDS in parallel
-  for (int t = threadIdx.x; t < slots * slots; t += BS)
-    sG[t / slots][t % slots] = ctl_s->G[t / slots][t % slots];
-  if (threadIdx.x < slots) srho[threadIdx.x] = ctl_s->rho[threadIdx.x];
-  const int k = ctl_s->k, cand = ctl_s->cand, newest0 = ctl_s->newest, np0 = ctl_s->npairs;
   const SimSeg sg = seg[sim];
-  totals_of<ND>(part + sg.gb0, nb, sg.gb1 - sg.gb0, red, tot);  // barrier after the staging
+  const CtlInts ci = ctl_ints(ctl_s);
+  if (ci.phase != PH_GATHER) return;
+  const int slots = m + 1;  // <= SL
+  const int k = ci.k, cand = ci.cand, newest0 = ci.newest, np0 = ci.npairs;
+  // the control state the recursion reads (two G entries per thread, from
+  // clamped indices) goes out with the partials and is staged in LDS after
+  static_assert(kSlots * kSlots <= 2 * BS, "two G entries per thread");
+  const int g0 = min((int)threadIdx.x, slots * slots - 1), g1 = min((int)threadIdx.x + BS, slots * slots - 1);
+  const double gv0 = ctl_s->G[g0 / slots][g0 % slots], gv1 = ctl_s->G[g1 / slots][g1 % slots];
+  const double rv = ctl_s->rho[min((int)threadIdx.x, slots - 1)];
+  double v[ND];
+  partials_load<ND>(part + sg.gb0, nb, sg.gb1 - sg.gb0, v);
+  if ((int)threadIdx.x < slots * slots) sG[g0 / slots][g0 % slots] = gv0;
+  if ((int)threadIdx.x + BS < slots * slots) sG[g1 / slots][g1 % slots] = gv1;
+  if ((int)threadIdx.x < slots) srho[threadIdx.x] = rv;
+  partials_total<ND>(v, red, tot);  // barrier after the staging
   if (threadIdx.x != 0) return;
   SimStat* st = stat + sim;
   const double ts = tot[0], ss = tot[1], tt = tot[2], gg = tot[3];
@@ -792,19 +821,29 @@ k_coef_decide(int m, int cyc, int cheb, int cheb_delay, double rho2,
   __shared__ double sG[SL][SL], srho[SL], szeta[SL], ssg[SL], scoef[SL];
   const int sim = blockIdx.x;
   Ctl* ctl_s = ctl + sim;
-  if (ctl_s->phase != PH_DIR) return;
-  const int slots = m + 1;  // <= SL
-  for (int t = threadIdx.x; t < slots * slots; t += BS)
-    sG[t / slots][t % slots] = ctl_s->G[t / slots][t % slots];
-  if (threadIdx.x < slots) {
-    srho[threadIdx.x] = ctl_s->rho[threadIdx.x];
-    szeta[threadIdx.x] = ctl_s->zeta[threadIdx.x];
-    ssg[threadIdx.x] = ctl_s->sg[threadIdx.x];
-  }
-  const int np = ctl_s->npairs, newest = ctl_s->newest;
-  const double gg = ctl_s->gnorm2_cur;
   const SimSeg sg = seg[sim];
-  totals_of<ND>(part + sg.rb0, nb, sg.rb1 - sg.rb0, red, tot);  // barrier after the staging
+  const CtlInts ci = ctl_ints(ctl_s);
+  const double gg = ctl_s->gnorm2_cur;
+  if (ci.phase != PH_DIR) return;
+  const int slots = m + 1;  // <= SL
+  const int np = ci.npairs, newest = ci.newest;
+  // the recursion's control state goes out with the partials (clamped
+  // indices, two G entries per thread) and is staged in LDS after
+  static_assert(kSlots * kSlots <= 2 * BS, "two G entries per thread");
+  const int g0 = min((int)threadIdx.x, slots * slots - 1), g1 = min((int)threadIdx.x + BS, slots * slots - 1);
+  const int ts = min((int)threadIdx.x, slots - 1);
+  const double gv0 = ctl_s->G[g0 / slots][g0 % slots], gv1 = ctl_s->G[g1 / slots][g1 % slots];
+  const double rv = ctl_s->rho[ts], zv = ctl_s->zeta[ts], sv = ctl_s->sg[ts];
+  double v[ND];
+  partials_load<ND>(part + sg.rb0, nb, sg.rb1 - sg.rb0, v);
+  if ((int)threadIdx.x < slots * slots) sG[g0 / slots][g0 % slots] = gv0;
+  if ((int)threadIdx.x + BS < slots * slots) sG[g1 / slots][g1 % slots] = gv1;
+  if ((int)threadIdx.x < slots) {
+    srho[threadIdx.x] = rv;
+    szeta[threadIdx.x] = zv;
+    ssg[threadIdx.x] = sv;
+  }
+  partials_total<ND>(v, red, tot);  // barrier after the staging
   if (threadIdx.x != 0) return;
   double gtd = tot[SL];
   for (int a = np - 1; a >= 0; --a) {
