@@ -22,6 +22,10 @@ ARCH = "gfx950"
 COMMON = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # kernel arguments preloaded into SGPRs at dispatch (the kernels keep a
+    # fallback that loads them when the firmware does not preload): saves the
+    # argument load each launch starts with, ~2 % of a 40^3 step
+    "-mllvm", "-amdgpu-kernarg-preload-count=16",
     "-Xarch_host", "-mavx2", "-Xarch_host", "-mfma",
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
     "-I", os.path.join(HERE, "..", "include"),
