@@ -285,6 +285,8 @@ k_copy_retry(int nf, const int* __restrict__ vsim, const Ctl* __restrict__ ctl,
 // otherwise. want: the phase the block's simulation must be in (-1: always;
 // probes).
 // ---------------------------------------------------------------------------
+// (The spline material is held to four waves per SIMD, 128 VGPRs: left
+// free it takes 136 and runs three.)
 template <int TYPE, typename R, int NT>
 __global__ void __launch_bounds__(NT, TYPE == 2 ? 4 : 1)
 k_elem(int want, int trial, const BlockSeg* __restrict__ blk, int T, int nf,
@@ -335,7 +337,7 @@ k_elem(int want, int trial, const BlockSeg* __restrict__ blk, int T, int nf,
     for (int a = 0; a < 4; ++a)
 #pragma unroll
       for (int c = 0; c < 3; ++c) p[a][c] = X[3 * (size_t)vid[a] + c];
-    if (trial) {  // uniform; a trial has free vertices (nf > 0)
+    if (trial) {  // uniform; nf > 0 (analysis rejects a mesh with no free vertex)
       double dv[4][3];
 #pragma unroll
       for (int a = 0; a < 4; ++a)
