@@ -222,11 +222,14 @@ __device__ __forceinline__ void fwd_item(const ItemDesc& d, const double* __rest
       }
     }
   }
+  double o[12];  // the 12 sums reduced together
+#pragma unroll
+  for (int k = 0; k < 4; ++k) o[3 * k] = a[k][0], o[3 * k + 1] = a[k][1], o[3 * k + 2] = a[k][2];
+  group_sum_n(o, L);
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const int r = d.begin + slot0 + k * stride;
-    const double o0 = group_sum(a[k][0], L), o1 = group_sum(a[k][1], L),
-                 o2 = group_sum(a[k][2], L);
+    const double o0 = o[3 * k], o1 = o[3 * k + 1], o2 = o[3 * k + 2];
     if (gl == 0 && r < d.end) {
       if (r < nc) {
         double* o = z + 3 * (size_t)(first + r);
@@ -364,11 +367,14 @@ __device__ __forceinline__ void bwd_item(const ItemDesc& d, const double* __rest
       }
     }
   }
+  double o[12];  // the 12 sums reduced together
+#pragma unroll
+  for (int k = 0; k < 4; ++k) o[3 * k] = a[k][0], o[3 * k + 1] = a[k][1], o[3 * k + 2] = a[k][2];
+  group_sum_n(o, L);
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const int c = d.begin + slot0 + k * stride;
-    const double o0 = group_sum(a[k][0], L), o1 = group_sum(a[k][1], L),
-                 o2 = group_sum(a[k][2], L);
+    const double o0 = o[3 * k], o1 = o[3 * k + 1], o2 = o[3 * k + 2];
     if (gl == 0 && c < d.end) {
       double* o = w + 3 * (size_t)(first + c);
       o[0] = o0; o[1] = o1; o[2] = o2;
@@ -520,11 +526,14 @@ __device__ __forceinline__ void fwd_wave_item(const ItemDesc& d, const double* _
       }
     }
   }
+  double o[12];  // the 12 sums reduced together
+#pragma unroll
+  for (int k = 0; k < 4; ++k) o[3 * k] = a[k][0], o[3 * k + 1] = a[k][1], o[3 * k + 2] = a[k][2];
+  group_sum_n(o, L);
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const int r = d.begin + grp + k * G;
-    const double o0 = group_sum(a[k][0], L), o1 = group_sum(a[k][1], L),
-                 o2 = group_sum(a[k][2], L);
+    const double o0 = o[3 * k], o1 = o[3 * k + 1], o2 = o[3 * k + 2];
     if (gl == 0 && r < d.end) {
       if (r < nc) {
         double* o = z + 3 * (size_t)(first + r);
@@ -629,11 +638,14 @@ __device__ __forceinline__ void bwd_wave_item(const ItemDesc& d, const double* _
       }
     }
   }
+  double o[12];  // the 12 sums reduced together
+#pragma unroll
+  for (int k = 0; k < 4; ++k) o[3 * k] = a[k][0], o[3 * k + 1] = a[k][1], o[3 * k + 2] = a[k][2];
+  group_sum_n(o, L);
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const int c = d.begin + grp + k * G;
-    const double o0 = group_sum(a[k][0], L), o1 = group_sum(a[k][1], L),
-                 o2 = group_sum(a[k][2], L);
+    const double o0 = o[3 * k], o1 = o[3 * k + 1], o2 = o[3 * k + 2];
     if (gl == 0 && c < d.end) {
       double* o = w + 3 * (size_t)(first + c);
       o[0] = o0; o[1] = o1; o[2] = o2;

@@ -46,6 +46,43 @@ __device__ __forceinline__ double group_sum(double v, int L) {
   return v;
 }
 
+// group_sum of N values together: the same steps in the same order for each
+// value (so the same bits as N calls of group_sum), but step by step over all
+// N, so that the N independent chains interleave instead of running one after
+// another behind the tests of L.
+template <int N>
+__device__ __forceinline__ void group_sum_n(double (&v)[N], int L) {
+  if (L >= 2) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] += dpp_d<kDppXor1>(v[i]);
+  }
+  if (L >= 4) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] += dpp_d<kDppXor2>(v[i]);
+  }
+  if (L >= 8) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] += dpp_d<kDppHalfMirror>(v[i]);
+  }
+  if (L >= 16) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] += dpp_d<kDppMirror>(v[i]);
+  }
+  if (L == 32) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      const double lo = readlane_d(v[i], 0) + readlane_d(v[i], 16);
+      const double hi = readlane_d(v[i], 32) + readlane_d(v[i], 48);
+      v[i] = (threadIdx.x & 32) ? hi : lo;
+    }
+  } else if (L == 64) {
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+      v[i] = (readlane_d(v[i], 0) + readlane_d(v[i], 16)) +
+             (readlane_d(v[i], 32) + readlane_d(v[i], 48));
+  }
+}
+
 // Sum over the whole wave (every lane receives it).
 __device__ __forceinline__ double wave_total(double v) { return group_sum(v, 64); }
 
