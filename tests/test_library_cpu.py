@@ -233,3 +233,14 @@ def test_fiber_material_validation():
     with pytest.raises(qnsim.QnsimError) as e:
         s.set_materials(mats)
     assert e.value.code == -1
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The bench measures one GPU: asked for more it exits with status 2 and a
+    message, before touching torch or the library."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120, cwd=ROOT)
+    assert r.returncode == 2, r.stderr
+    assert "measures one GPU" in r.stderr and r.stdout == ""
