@@ -244,3 +244,29 @@ def test_bench_refuses_more_than_one_gpu():
                        capture_output=True, text=True, timeout=120, cwd=ROOT)
     assert r.returncode == 2, r.stderr
     assert "measures one GPU" in r.stderr and r.stdout == ""
+
+
+def test_bench_byte_accounting_and_traffic_gate(tmp_path, monkeypatch):
+    """The bench's algorithmic bytes at 40^3 (the figures the profiles divide
+    by), and the measured traffic is used only while the hash of the solve's
+    sources matches the one recorded with it."""
+    import importlib
+    import sys
+    sys.path.insert(0, ROOT)
+    bench = importlib.import_module("bench")
+    # exact factor of the 40^3 block: 25,061,779 entries; 67,240 free vertices
+    assert bench.solve_bytes(25061779, 67240) == 404215984
+    # 384,000 tets, 68,921 vertices, 67,240 free
+    assert bench.element_bytes(384000, 68921, 67240) == 42283544
+    fake = tmp_path / "traffic.md"
+    fake.write_text("traffic_bytes_per_solve: 123\nsolve_source_sha256_16: 0000000000000000\n")
+    monkeypatch.setattr(bench, "TRAFFIC_PROFILE", str(fake))
+    assert bench.solve_traffic(40) is None          # sources do not match
+    import hashlib
+    h = hashlib.sha256()
+    for f in bench.SOLVE_SOURCES:
+        with open(os.path.join(ROOT, "paper_1604_07378_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    fake.write_text(f"traffic_bytes_per_solve: 123\nsolve_source_sha256_16: {h.hexdigest()[:16]}\n")
+    assert bench.solve_traffic(40) == 123
+    assert bench.solve_traffic(30) is None          # another workload
