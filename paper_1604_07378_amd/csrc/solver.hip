@@ -52,14 +52,38 @@ constexpr int BS = 256;          // threads per block of every kernel
 // ---------------------------------------------------------------------------
 // Deterministic reductions
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double wave_sum(double v) { return wave_total(v); }
+// v of the lane that the row broadcast CTRL selects, in the rows of ROWS;
+// 0 in the other rows.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_rows_d(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWS, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWS, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Total over the wave, valid in lane 63 (the lane that writes it): the row
+// sums r0..r3 by the DPP steps of group_sum, then row_bcast:15 (into rows 1
+// and 3) and row_bcast:31 (into rows 2 and 3). Lane 63 gets
+// (r3 + r2) + (r1 + r0), the same bits as group_sum's (r0 + r1) + (r2 + r3)
+// read back through four readlanes (IEEE addition is commutative), with no
+// VALU-to-SGPR round trips.
+constexpr int kLastLane = 63;
+__device__ __forceinline__ double wave_sum(double v) {
+  v += dpp_d<kDppXor1>(v);
+  v += dpp_d<kDppXor2>(v);
+  v += dpp_d<kDppHalfMirror>(v);
+  v += dpp_d<kDppMirror>(v);
+  v += dpp_rows_d<0x142, 0xA>(v);  // row_bcast:15
+  v += dpp_rows_d<0x143, 0xC>(v);  // row_bcast:31
+  return v;
+}
 
 // Sum over the 256 threads of a block; result valid in thread 0.
 __device__ __forceinline__ double block_sum(double v, double* sh) {
   v = wave_sum(v);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   __syncthreads();
-  if (lane == 0) sh[w] = v;
+  if (lane == kLastLane) sh[w] = v;
   __syncthreads();
   double r = 0.0;
   if (threadIdx.x == 0) r = (sh[0] + sh[1]) + (sh[2] + sh[3]);
@@ -73,7 +97,7 @@ __device__ __forceinline__ double block_sum_t(double v, double* sh) {
   v = wave_sum(v);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   __syncthreads();
-  if (lane == 0) sh[w] = v;
+  if (lane == kLastLane) sh[w] = v;
   __syncthreads();
   double r = 0.0;
   if (threadIdx.x == 0) {
@@ -123,7 +147,7 @@ __device__ __forceinline__ void block_sums_to(double (&v)[N], double* sh, double
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
   for (int d = 0; d < N; ++d) v[d] = wave_sum(v[d]);
-  if (lane == 0) {
+  if (lane == kLastLane) {
 #pragma unroll
     for (int d = 0; d < N; ++d) sh[w * N + d] = v[d];
   }
@@ -172,7 +196,7 @@ __device__ __forceinline__ void partials_total(double (&v)[N], double* sh, doubl
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
   for (int d = 0; d < N; ++d) v[d] = wave_sum(v[d]);
-  if (lane == 0) {
+  if (lane == kLastLane) {
 #pragma unroll
     for (int d = 0; d < N; ++d) sh[w * N + d] = v[d];
   }
